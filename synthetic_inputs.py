@@ -1,0 +1,77 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the GPU path.
+
+This module holds problem descriptions (plain numbers) and seeded random
+generators only.  It contains none of the method's arithmetic: no mesh, no
+finite elements, no chaos matrices, no tensor-train algebra.  Both sides of the
+parity tests draw their inputs from here and nowhere else.
+
+Problem family (Elman & Su, sec. 6.1, Table 6.1): flow over a symmetric step,
+inlet [-1,0]x[-1/2,1/2], channel [0,L]x[-1,1], uniform squares of size h,
+Q2-Q1 elements, backward Euler with n_t steps of size tau, viscosity
+nu(xi) = nu0 * (1 + nu_coef * sum_k xi_k / k^2) with xi_k iid U[-1,1],
+Legendre chaos of total degree <= p in m variables.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Grid labels such as "16x48" and "64x192" read as (4/h) x (12/h), i.e. the
+# Q2 node lattice across the channel height by the element count along the
+# channel: h = 1/4 and h = 1/16 respectively (pinned by the paper's dof counts
+# n_u = 2992, n_p = 461 at h = 1/4).
+CONFIGS = {
+    # smallest sizes: the dense all-at-once matrix is formed and solved directly
+    "tiny": dict(h=0.5, L=2.0, m=2, p=1, nt=3, tau=0.1, nu0=1.0 / 50, nu_coef=0.1,
+                 ramp=10.0),
+    "tiny2": dict(h=0.25, L=2.0, m=2, p=2, nt=4, tau=0.1, nu0=1.0 / 50, nu_coef=0.1,
+                  ramp=10.0),
+    # 16x48 grid (h=1/4), m=2, p=2 (6 chaos terms), nt=10, tau=0.1: Stokes system
+    "C1": dict(h=0.25, L=12.0, m=2, p=2, nt=10, tau=0.1, nu0=1.0 / 50, nu_coef=0.1,
+               ramp=10.0),
+    # 64x192 grid (h=1/16), m=4, p=3 (35 chaos terms), nt=128, tau=0.05
+    "C2": dict(h=1.0 / 16, L=12.0, m=4, p=3, nt=128, tau=0.05, nu0=1.0 / 50,
+               nu_coef=0.1, ramp=10.0),
+    # intermediate size used by parity tests at a shape between C1 and C2
+    "C1b": dict(h=0.125, L=12.0, m=3, p=2, nt=32, tau=0.05, nu0=1.0 / 50,
+                nu_coef=0.1, ramp=10.0),
+}
+
+# Solver defaults (readings of the paper):
+SOLVER_DEFAULTS = dict(
+    tol=1e-8,            # exact relative residual target of one Picard-step solve
+    eps_krylov=1e-6,     # TT truncation of Krylov / preconditioned vectors
+    tol_cycle=1e-4,      # relative tolerance of one flexible-GMRES cycle
+    restart=30,          # iterations per cycle
+    max_cycles=8,
+    inner_tol=1e-1,      # mean-matrix inner solve (paper: 1e-1 suffices)
+    inner_eps=1e-3,      # truncation inside the inner solve
+    inner_maxit=20,
+    eps_conv=1e-3,       # truncation of the convection field (Table 6.2)
+)
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(seed)
+
+
+def random_tt_cores(n1: int, n2: int, n3: int, r1: int, r2: int, seed: int,
+                    decay: float = 0.0):
+    """Random TT cores (paper convention): G1 (n1 x r1), G2 (r1 x n2 x r2),
+    G3 (r2 x n3), entries N(0,1).  With decay>0 the rank columns are scaled by
+    exp(-decay*index) so that the tensor has a decaying spectrum."""
+    g = rng(seed)
+    G1 = g.standard_normal((n1, r1))
+    G2 = g.standard_normal((r1, n2, r2))
+    G3 = g.standard_normal((r2, n3))
+    if decay > 0.0:
+        G1 = G1 * np.exp(-decay * np.arange(r1))[None, :]
+        G3 = G3 * np.exp(-decay * np.arange(r2))[:, None]
+    return G1, G2, G3
+
+
+def random_tt_pair(nt: int, nxi: int, nu: int, np_: int, ranks_u, ranks_p,
+                   seed: int, decay: float = 0.0):
+    """A (velocity, pressure) pair of random TTs with the given ranks."""
+    u = random_tt_cores(nt, nxi, nu, ranks_u[0], ranks_u[1], seed, decay)
+    p = random_tt_cores(nt, nxi, np_, ranks_p[0], ranks_p[1], seed + 7919, decay)
+    return u, p

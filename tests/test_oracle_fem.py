@@ -1,0 +1,88 @@
+"""Pins of the oracle's mesh and Q2-Q1 assembly against facts the paper and
+the mathematics fix (not against the oracle itself)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mesh as fem
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_numbers.json")))
+
+
+def test_dof_counts_printed_in_paper():
+    # sec. 6.1: h = 2^-2 gives n_u = 2992, n_p = 461
+    m = fem.build_mesh(0.25, 12.0)
+    assert m.n_u == GOLD["dofs_h_quarter"]["n_u"]
+    assert m.n_p == GOLD["dofs_h_quarter"]["n_p"]
+
+
+def test_all_at_once_size_printed_in_paper():
+    from math import comb
+    g = GOLD["all_at_once_size"]
+    m = fem.build_mesh(0.25, 12.0)
+    n_xi = comb(g["m"] + g["d_psi"], g["d_psi"])
+    assert n_xi == g["n_xi"]
+    assert g["n_t"] * n_xi * (m.n_u + m.n_p) == g["unknowns"]
+
+
+@pytest.mark.parametrize("h,L,nu,npp", [(0.5, 2.0, 136, 31), (0.25, 2.0, 592, 101),
+                                        (1.0 / 16, 12.0, 50368, 6641)])
+def test_lattice_counts(h, L, nu, npp):
+    # counts from enumerating the Q2 / Q1 node lattice by hand:
+    # h=1/2,L=2: 20 elements; h=1/16: 64x192 grid
+    m = fem.build_mesh(h, L)
+    assert (m.n_u, m.n_p) == (nu, npp)
+
+
+def test_mass_integrates_area():
+    m = fem.build_mesh(0.25, 12.0)
+    M, A, B1, B2, Mp = fem.assemble(m)
+    one = np.ones(m.n_all)
+    # |inlet| + |channel| = 1 * 1 + 12 * 2 = 25
+    assert abs(one @ (M @ one) - 25.0) < 1e-12
+    assert abs(np.ones(m.n_p) @ (Mp @ np.ones(m.n_p)) - 25.0) < 1e-12
+
+
+def test_stiffness_kills_constants_and_divergence_of_fields():
+    m = fem.build_mesh(0.25, 12.0)
+    M, A, B1, B2, Mp = fem.assemble(m)
+    one = np.ones(m.n_all)
+    assert np.abs(A @ one).max() < 1e-13
+    # div of a constant field is 0; div of (x1, 0) is 1, so B1 x1 = -(psi_i, 1)
+    assert np.abs(B1 @ one).max() < 1e-14 and np.abs(B2 @ one).max() < 1e-14
+    rowsum = Mp @ np.ones(m.n_p)
+    assert np.abs(B1 @ m.coords[:, 0] + rowsum).max() < 1e-13
+    assert np.abs(B2 @ m.coords[:, 1] + rowsum).max() < 1e-13
+    # Laplacian of x1^2 is 2: (grad x1^2, grad phi_i) = -(2, phi_i) + boundary;
+    # check on interior nodes only (natural boundary terms vanish there)
+    x = m.coords[:, 0]
+    interior = np.ones(m.n_all, bool)
+    interior[m.dirichlet] = False
+    interior &= (np.abs(m.coords[:, 0] - 12.0) > 1e-12) & (np.abs(m.coords[:, 0] + 1.0) > 1e-12)
+    lhs = A @ (x * x)
+    rhs = -2.0 * (M @ one)
+    assert np.abs((lhs - rhs)[interior]).max() < 1e-12
+
+
+def test_convection_skew_up_to_boundary():
+    # (w.grad phi_j, phi_i) + (w.grad phi_i, phi_j) = boundary integral of
+    # (w.n) phi_i phi_j for a constant (divergence-free) w: zero whenever one of
+    # the two nodes is off the boundary.
+    m = fem.build_mesh(0.5, 2.0)
+    w1 = np.full(m.n_all, 1.0)
+    w2 = np.full(m.n_all, 0.3)
+    N = fem.convection(m, w1, w2).toarray()
+    S = N + N.T
+    x1, x2 = m.coords[:, 0], m.coords[:, 1]
+    on_bd = np.zeros(m.n_all, bool)
+    on_bd[m.dirichlet] = True
+    on_bd |= np.abs(x1 - 2.0) < 1e-12
+    off = ~on_bd
+    assert np.abs(S[off, :]).max() < 1e-14
+    assert np.abs(S[:, off]).max() < 1e-14
+    # outflow boundary x1 = L: w.n = 1 -> S restricted to outflow nodes = Q2
+    # boundary mass on that edge, whose total is the edge length 2
+    out = np.abs(x1 - 2.0) < 1e-12
+    assert abs(S[np.ix_(out, out)].sum() - 2.0) < 1e-12

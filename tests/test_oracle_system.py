@@ -1,0 +1,243 @@
+"""Pins of the oracle's all-at-once operator, right-hand side and solvers:
+explicit Kronecker matrices, dense direct solves, physics invariants, the
+ideal preconditioner of eq. 5.3 and the full-tensor limit of the low-rank
+solver."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import tt
+from oracle.solver import lowrank_fgmres, FullOps, solve_tt, solve_full
+from oracle.system import Problem
+from synthetic_inputs import CONFIGS, random_tt_pair
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return Problem(CONFIGS["tiny"])
+
+
+def _prior(P, seed=3):
+    # a smooth-ish prior velocity/pressure iterate (low rank, small amplitude)
+    u, p = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 2), (1, 1), seed)
+    return tt.scale(u, 0.3 / tt.tt_norm(u)), tt.scale(p, 0.1 / tt.tt_norm(p))
+
+
+def test_apply_matches_explicit_kron(tiny):
+    P = tiny
+    x = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 3), (2, 2), 0)
+    K = P.explicit()
+    ref = K @ tt.pair_full(x)
+    assert np.abs(tt.pair_full(P.apply(x)) - ref).max() <= 1e-13 * np.abs(ref).max()
+    yu, yp = P.apply_full(tt.full(x[0]), tt.full(x[1]))
+    assert np.abs(np.concatenate([yu.ravel(), yp.ravel()]) - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_apply_with_convection_matches_explicit(tiny):
+    P = tiny
+    conv = P.convection(_prior(P), 1e-3)
+    x = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 3), (2, 2), 1)
+    K = P.explicit(conv)
+    ref = K @ tt.pair_full(x)
+    got = tt.pair_full(P.apply(x, conv))
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    yu, yp = P.apply_full(tt.full(x[0]), tt.full(x[1]), conv)
+    assert np.abs(np.concatenate([yu.ravel(), yp.ravel()]) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_time_stepping_equals_dense_solve(tiny):
+    P = tiny
+    b = P.rhs()
+    K = P.explicit()
+    zd = spla.spsolve(K, tt.pair_full(b))
+    u, p = P.solve_direct(tt.full(b[0]), tt.full(b[1]))
+    z = np.concatenate([u.ravel(), p.ravel()])
+    assert np.linalg.norm(z - zd) <= 1e-12 * np.linalg.norm(zd)
+    conv = P.convection(_prior(P), 1e-3)
+    b2 = P.rhs(_prior(P))
+    K2 = P.explicit(conv)
+    zd2 = spla.spsolve(K2, tt.pair_full(b2))
+    u2, p2 = P.solve_direct(tt.full(b2[0]), tt.full(b2[1]), conv)
+    assert np.linalg.norm(np.concatenate([u2.ravel(), p2.ravel()]) - zd2) <= 1e-11 * np.linalg.norm(zd2)
+
+
+def test_rhs_is_lifted_dirichlet_data(tiny):
+    # f = -L_{free,Dirichlet} g a(t): check against the all-node operator applied
+    # to the lift vector, assembled independently with scipy.sparse.kron.
+    P = tiny
+    b = P.rhs()
+    assert tt.ranks(b[0]) == (2, 2) and tt.ranks(b[1]) == (1, 1)
+    nt, nx = P.nt, P.n_xi
+    e1 = np.zeros(nx)
+    e1[0] = 1.0
+    lift = np.kron(np.kron(P.ramp, e1), P.g_all)
+    Kfa = sp.kron(sp.kron((P.It - P.Ct) / P.tau, sp.identity(nx)), P.Mb_fall) \
+        + sp.kron(sp.kron(P.It, sp.csr_matrix(P.Gnu)), P.Ab_fall)
+    Kpa = sp.kron(sp.identity(nt * nx), P.B_all)
+    ref = -np.concatenate([Kfa @ lift, Kpa @ lift])
+    assert np.abs(tt.pair_full(b) - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_physics_divergence_free_and_outflow_flux():
+    # With zero initial data the exact discrete solution is discretely
+    # divergence-free (B u_full = 0 for each (t_k, psi_r)), and since q = 1 is in
+    # the pressure space the net boundary flux is zero: outflow flux at x1 = L
+    # equals the inflow flux (2/3)(1 - e^{-10 t_k}) in the psi_1 mode, 0 otherwise.
+    cfg = dict(CONFIGS["tiny2"])
+    P = Problem(cfg)
+    b = P.rhs()
+    u, p = P.solve_direct(tt.full(b[0]), tt.full(b[1]))
+    nall = P.n_all
+    f = P.mesh.free
+    ufull = np.zeros((P.nt, P.n_xi, 2 * nall))
+    ufull[:, :, f] = u[:, :, :P.n_s]
+    ufull[:, :, nall + f] = u[:, :, P.n_s:]
+    gall = P.g_all
+    ufull += P.ramp[:, None, None] * np.eye(P.n_xi)[0][None, :, None] * gall[None, None, :]
+    div = np.einsum("px,tkx->tkp", P.B_all.toarray(), ufull)
+    assert np.abs(div).max() < 1e-10
+    # flux through x1 = L: integrate u1 along the outflow edge with the Q2 trace
+    x1, x2 = P.mesh.coords[:, 0], P.mesh.coords[:, 1]
+    out = np.nonzero(np.abs(x1 - cfg["L"]) < 1e-12)[0]
+    out = out[np.argsort(x2[out])]
+    hh = cfg["h"]
+    wts = np.zeros(out.size)      # Simpson weights per element edge (exact for Q2)
+    for e in range(0, out.size - 1, 2):
+        wts[e:e + 3] += np.array([1, 4, 1]) * hh / 6
+    flux = np.einsum("tkx,x->tk", ufull[:, :, out], wts)
+    assert np.abs(flux[:, 0] - (2.0 / 3.0) * P.ramp).max() < 1e-10
+    assert np.abs(flux[:, 1:]).max() < 1e-10
+
+
+def test_deterministic_limit():
+    # nu_coef = 0: G_nu = nu0 I, so only the psi_1 mode is driven (G_0 = I).
+    cfg = dict(CONFIGS["tiny"], nu_coef=0.0)
+    P = Problem(cfg)
+    b = P.rhs()
+    u, p = P.solve_direct(tt.full(b[0]), tt.full(b[1]))
+    assert np.abs(u[:, 1:]).max() < 1e-14 and np.abs(p[:, 1:]).max() < 1e-14
+    assert np.abs(u[:, 0]).max() > 1e-2
+
+
+def test_time_inverse_is_prefix_sum():
+    P = Problem(CONFIGS["tiny"])
+    IC = (P.It - P.Ct).toarray()
+    assert np.allclose(np.linalg.inv(IC), np.tril(np.ones((P.nt, P.nt))))
+
+
+def test_commutator_identity_eq_5_15(tiny):
+    # M_p^-1 B M^-1 C - M_p^-1 C_p M_p^-1 B = 0 exactly (eq. 5.15)
+    P = tiny
+    nx = P.n_xi
+    Mi = sp.kron(sp.kron(P.It, sp.identity(nx)), sp.linalg.inv(P.Mb.tocsc()))
+    Mpi = sp.kron(sp.kron(P.It, sp.identity(nx)), sp.linalg.inv(P.Mp.tocsc()))
+    Bb = sp.kron(sp.identity(P.nt * nx), P.B)
+    Cb = -sp.kron(sp.kron(P.Ct, sp.identity(nx)), P.Mb) / P.tau
+    Cp = -sp.kron(sp.kron(P.Ct, sp.identity(nx)), P.Mp) / P.tau
+    D = Mpi @ Bb @ Mi @ Cb - Mpi @ Cp @ Mpi @ Bb
+    assert abs(D).max() < 1e-10
+
+
+def test_ideal_preconditioner_two_iterations(tiny):
+    # eq. 5.2-5.3: with exact (F+C)^-1 and exact Schur complement, right
+    # preconditioned GMRES converges in two iterations.
+    P = tiny
+    K = P.explicit().toarray()
+    nu_tot = P.nt * P.n_xi * P.n_u
+    F = K[:nu_tot, :nu_tot]
+    Bt = K[:nu_tot, nu_tot:]
+    Bm = K[nu_tot:, :nu_tot]
+    Finv = np.linalg.inv(F)
+    S = Bm @ Finv @ Bt
+    Sinv = np.linalg.inv(S)
+
+    def prec(y):
+        ph = -Sinv @ y[nu_tot:]
+        return np.concatenate([Finv @ (y[:nu_tot] - Bt @ ph), ph])
+
+    ops = FullOps(P)
+    b = tt.pair_full(P.rhs())
+    z, k, res, bn = lowrank_fgmres(ops, lambda x: K @ x, prec, b, 1e-10, 0.0, 10)
+    assert k == 2
+    assert np.linalg.norm(K @ z - b) <= 1e-10 * bn
+
+
+def test_tt_limit_reproduces_full_tensor_fgmres(tiny):
+    # eps -> 0: the TT iterates reproduce the full-tensor flexible GMRES
+    # (same Hessenberg entries, same iteration count).
+    P = tiny
+    b = P.rhs()
+    rec_full, rec_tt = [], []
+    solve_full(P, tt.full(b[0]), tt.full(b[1]), tol=1e-6, record=rec_full)
+    from oracle.solver import TTOps, MeanLSC
+    ops = TTOps(P)
+    prec = MeanLSC(P, None, "tt", 1e-1, 1e-14, 20, 1e-14)
+    lowrank_fgmres(ops, ops.apply, prec.apply_tt, b, 1e-6, 1e-14, 60, rec_tt)
+    assert len(rec_full) == len(rec_tt)
+    Hf, Ht = rec_full[-1]["H"], rec_tt[-1]["H"]
+    assert np.abs(Hf - Ht).max() <= 1e-9 * np.abs(Hf).max()
+
+
+def test_lowrank_solve_reaches_target_and_exact_solution(tiny):
+    P = tiny
+    b = P.rhs()
+    z, st = solve_tt(P, b)
+    assert st["rel"][-1] <= 1e-8
+    u, p = P.solve_direct(tt.full(b[0]), tt.full(b[1]))
+    zd = np.concatenate([u.ravel(), p.ravel()])
+    assert np.linalg.norm(tt.pair_full(z) - zd) <= 1e-7 * np.linalg.norm(zd)
+
+
+def test_lowrank_solve_with_convection(tiny):
+    P = tiny
+    prior = _prior(P)
+    conv = P.convection(prior, 1e-3)
+    b = P.rhs(prior)
+    z, st = solve_tt(P, b, conv)
+    assert st["rel"][-1] <= 1e-8
+    u, p = P.solve_direct(tt.full(b[0]), tt.full(b[1]), conv)
+    zd = np.concatenate([u.ravel(), p.ravel()])
+    assert np.linalg.norm(tt.pair_full(z) - zd) <= 1e-7 * np.linalg.norm(zd)
+
+
+def _steady_stokes(P, nu):
+    """Steady Stokes with viscosity nu on the same mesh: nu A u + B^T p = -nu
+    A_fD g, B u = -B_D g (the time-independent problem, built here directly)."""
+    Kuu = nu * P.Ab
+    K = sp.bmat([[Kuu, P.Bt], [P.B, None]]).tocsc()
+    rhs = -np.concatenate([nu * (P.Ab_fall @ P.g_all), P.B_all @ P.g_all])
+    sol = spla.spsolve(K, rhs)
+    return sol[:P.n_u], sol[P.n_u:]
+
+
+def test_long_time_limit_is_steady_stokes():
+    # Backward Euler with a constant inflow converges to the steady problem:
+    # pins the sign and scaling of the time shift C and of tau^-1 M.
+    cfg = dict(CONFIGS["tiny"], nu0=1.0, nu_coef=0.0, ramp=1e9, tau=0.5, nt=60)
+    P = Problem(cfg)
+    b = P.rhs()
+    u, p = P.solve_direct(tt.full(b[0]), tt.full(b[1]))
+    us, ps = _steady_stokes(P, 1.0)
+    assert np.linalg.norm(u[-1, 0] - us) <= 1e-10 * np.linalg.norm(us)
+    assert np.linalg.norm(p[-1, 0] - ps) <= 1e-9 * np.linalg.norm(ps)
+
+
+def test_stochastic_galerkin_mean_matches_quadrature():
+    # One random variable, high chaos degree: the Galerkin mean of the final
+    # time step equals the U[-1,1] expectation of deterministic solves with
+    # nu(xi) = nu0 (1 + c xi), evaluated by Gauss-Legendre quadrature.
+    from scipy.special import roots_legendre
+    nu0, c = 0.5, 0.4
+    cfg = dict(CONFIGS["tiny"], m=1, p=10, nu0=nu0, nu_coef=c, nt=3, tau=0.2)
+    P = Problem(cfg)
+    b = P.rhs()
+    u, p = P.solve_direct(tt.full(b[0]), tt.full(b[1]))
+    xq, wq = roots_legendre(16)
+    mean = np.zeros(P.n_u)
+    for x, w in zip(xq, wq):
+        Pd = Problem(dict(cfg, m=1, p=0, nu0=nu0 * (1 + c * x), nu_coef=0.0))
+        bd = Pd.rhs()
+        ud, _ = Pd.solve_direct(tt.full(bd[0]), tt.full(bd[1]))
+        mean += 0.5 * w * ud[-1, 0]
+    assert np.linalg.norm(u[-1, 0] - mean) <= 1e-9 * np.linalg.norm(mean)
