@@ -1,0 +1,195 @@
+/*
+ * sgtt: low-rank (tensor-train) solver for one Picard step of the stochastic
+ * Galerkin, all-at-once discretization of the unsteady Navier-Stokes
+ * equations (Elman & Su, "A low-rank solver for the stochastic unsteady
+ * Navier-Stokes problem"), on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes; no C++ or framework types cross it.
+ * Every function returns an int status: 0 = OK, > 0 = warning, < 0 = error
+ * (see SGTT_* codes).  No exception crosses the ABI.  After an error,
+ * sgtt_last_error() on the context describes it.
+ *
+ * Vectors of the all-at-once system are pairs (u, p) of 3-way tensor trains
+ * over (time, chaos, space) (sec. 4.1, eq. 4.1-4.2):
+ *   z(i1,i2,i3) = sum_{a,b} core1[i1,a] core2[a,i2,b] core3'[b,i3]
+ * with the memory layout of sgtt_tt below.  Velocity space dofs are
+ * [x1-component on free nodes; x2-component on free nodes] (sec. 3.2), free
+ * velocity nodes and pressure nodes sorted by (x1, x2).
+ *
+ * Threading / streams: calls on one context are ordered on the context's HIP
+ * stream; calls are not thread-safe on one context.  Device buffers passed
+ * in are owned by the caller and must stay valid for the call.
+ */
+#ifndef SGTT_H
+#define SGTT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+#define SGTT_OK 0
+#define SGTT_W_NOT_CONVERGED 1    /* solve stopped at max cycles; x = best iterate */
+#define SGTT_E_INVALID -1         /* bad argument (null pointer, size mismatch)    */
+#define SGTT_E_HIP -2             /* HIP runtime error                             */
+#define SGTT_E_OOM -3             /* device allocation failed                      */
+#define SGTT_E_RANK_CAP -4        /* result rank exceeds the output capacity;
+                                     output left unchanged                         */
+#define SGTT_E_NONFINITE -5       /* NaN/Inf met in a reduction                    */
+#define SGTT_E_SETUP -6           /* problem setup failed (mesh / factorization)   */
+
+typedef struct sgtt_context sgtt_context;
+typedef struct sgtt_system sgtt_system;
+typedef struct sgtt_host_problem sgtt_host_problem;
+
+/* A tensor train with three cores in device memory (caller-owned buffers).
+ *   core1: n1 x r1, row-major, leading dimension r1     (n1 * cap1 doubles)
+ *   core2: r1 x n2 x r2, row-major [a][i][b]            (cap1 * n2 * cap2)
+ *   core3: n3 x r2, row-major (node-major), ld r2       (n3 * cap2 doubles)
+ * core3 is the transpose of the paper's third core (eq. 4.2): row = space
+ * index, so that sparse products over space read contiguous rank vectors.
+ * r1, r2 are the live ranks: inputs read them, outputs write them. */
+typedef struct {
+  int n1, n2, n3;
+  int r1, r2;
+  int cap1, cap2;
+  double* core1;
+  double* core2;
+  double* core3;
+} sgtt_tt;
+
+/* velocity TT (n3 = n_u) and pressure TT (n3 = n_p) of one all-at-once vector */
+typedef struct {
+  sgtt_tt u;
+  sgtt_tt p;
+} sgtt_tt_pair;
+
+/* Problem description (sec. 6.1; viscosity nu0 (1 + nu_coef sum_k xi_k/k^2),
+ * xi_k ~ U[-1,1], Legendre chaos of total degree <= p in m variables). */
+typedef struct {
+  double h;          /* mesh size: 1/h even integer                         */
+  double L;          /* channel length (12 in the paper)                    */
+  int m;             /* number of random variables                          */
+  int p;             /* total chaos degree                                  */
+  int nt;            /* time steps                                          */
+  double tau;        /* time step                                           */
+  double nu0;        /* mean viscosity                                      */
+  double nu_coef;    /* relative amplitude of the viscosity expansion       */
+  double ramp;       /* inflow ramp rate: u_D = (1-4 x2^2)(1-exp(-ramp t))  */
+  double eps_conv;   /* truncation of the convection field (eq. 4.13)       */
+  double eps_rhs;    /* truncation of a Picard residual right-hand side     */
+} sgtt_problem_desc;
+
+typedef struct {
+  int n_s, n_u, n_p, n_xi, nt, n_all;
+  int conv_r1, conv_r2;   /* ranks of the convection field w~ (0 for Stokes) */
+  int rhs_r1u, rhs_r2u, rhs_r1p, rhs_r2p;
+  double setup_seconds;
+} sgtt_system_info;
+
+typedef struct {
+  double tol;          /* exact relative residual target (1e-8)             */
+  double eps_krylov;   /* truncation of Krylov vectors (1e-6)               */
+  double tol_cycle;    /* relative tolerance of one flexible GMRES cycle    */
+  int restart;         /* iterations per cycle                              */
+  int max_cycles;      /* refinement cycles                                 */
+  double inner_tol;    /* mean-matrix inner solve tolerance (1e-1)          */
+  double inner_eps;    /* truncation inside the inner solve (1e-3)          */
+  int inner_maxit;     /* inner iterations                                  */
+  int verbose;         /* 1: per-iteration line on stderr                   */
+} sgtt_solve_opts;
+
+typedef struct {
+  int cycles, outer_iters, inner_iters;
+  double rel_residual;       /* exact ||b - L x|| / ||b|| at return          */
+  double seconds;
+  int max_rank_krylov_u, max_rank_krylov_p;
+  int roundings;
+  double t_apply, t_round, t_precond, t_residual;   /* seconds by phase     */
+} sgtt_solve_stats;
+
+/* ------------------------------------------------------------- context */
+/* One device, one stream.  hip_stream may be NULL (the library creates a
+ * default-priority stream) or an existing hipStream_t (e.g. torch's). */
+int sgtt_context_create(int device, void* hip_stream, sgtt_context** out);
+int sgtt_context_destroy(sgtt_context* ctx);
+const char* sgtt_last_error(const sgtt_context* ctx);
+/* build identification string (static storage) */
+const char* sgtt_version(void);
+
+/* ------------------------------------------------------------- system */
+/* Assemble the Picard-step system eq. 3.14: operator L(w~) with
+ * w~ = T_eps_conv(w) (eq. 4.13), right-hand side r = f - L(w)[w; p_w]
+ * (eq. 3.15) truncated with eps_rhs, preconditioner factorizations
+ * (eq. 5.19, 5.23).  prior = NULL gives the Stokes system (N = 0, r = f).
+ * Host setup runs on the CPU; device data are uploaded on the context
+ * stream.  The system owns its workspace until sgtt_system_destroy. */
+int sgtt_assemble(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_tt_pair* prior,
+                  sgtt_system** out);
+int sgtt_system_destroy(sgtt_system* sys);
+int sgtt_system_info_get(const sgtt_system* sys, sgtt_system_info* info);
+
+/* Write the right-hand side into caller buffers b (capacities checked). */
+int sgtt_rhs(sgtt_system* sys, sgtt_tt_pair* b);
+
+/* y = L x (eq. 3.11-3.12 with eq. 4.4 and eq. 4.12), exact when eps == 0,
+ * else followed by T_eps on u and p separately. */
+int sgtt_apply(sgtt_system* sys, const sgtt_tt_pair* x, sgtt_tt_pair* y, double eps);
+
+/* z = P^-1 r for the mean-based LSC block-triangular preconditioner
+ * (eq. 5.2, 5.19, 5.22-5.23).  opts supplies eps_krylov and the inner solve
+ * parameters; NULL uses defaults. */
+int sgtt_precondition(sgtt_system* sys, const sgtt_tt_pair* r, sgtt_tt_pair* z,
+                      const sgtt_solve_opts* opts);
+
+/* In-place truncation T_eps (eq. 4.5-4.7): ||round(x) - x|| <= eps ||x||
+ * (up to the accuracy of FP64 Gram matrices, about 1e-8 relative).  If a
+ * rank would exceed max_rank (> 0) the call fails with SGTT_E_RANK_CAP. */
+int sgtt_round(sgtt_context* ctx, sgtt_tt* x, double eps, int max_rank);
+
+/* <x, y> = <x.u, y.u> + <x.p, y.p>; result to host memory (synchronizes). */
+int sgtt_dot(sgtt_context* ctx, const sgtt_tt_pair* x, const sgtt_tt_pair* y, double* out);
+
+/* y = alpha x + beta y as an exact TT (ranks add; capacity checked). */
+int sgtt_axpby(sgtt_context* ctx, double alpha, const sgtt_tt_pair* x, double beta, sgtt_tt_pair* y);
+
+/* Solve L x = b (Alg. 4.2 with refinement to an exact relative residual).
+ * x is output only (z_0 = 0).  opts = NULL uses defaults. */
+int sgtt_solve(sgtt_system* sys, const sgtt_tt_pair* b, sgtt_tt_pair* x, const sgtt_solve_opts* opts,
+               sgtt_solve_stats* stats);
+
+/* Exact ||b - L x|| / ||b|| evaluated in full format on the device
+ * (synchronizes; result to host). */
+int sgtt_residual(sgtt_system* sys, const sgtt_tt_pair* b, const sgtt_tt_pair* x, double* rel);
+
+/* Expand a TT to the full tensor out (n1*n2*n3 doubles, device, C order). */
+int sgtt_expand(sgtt_context* ctx, const sgtt_tt* x, double* out);
+
+/* Least squares argmin_y || beta e1 - H y || for the (k+1) x k upper
+ * Hessenberg matrix H (host, column-major, leading dimension k+1), solved by
+ * Givens rotations on the device (Alg. 4.2, line 12).  y: host, length k. */
+int sgtt_hessenberg_lsq(sgtt_context* ctx, const double* H, int k, double beta, double* y,
+                        double* resid);
+
+/* ------------------------------------------------------------- host setup */
+/* Host-only problem setup (no device calls), for inspection and checks:
+ * mesh sizes, CSR matrices and chaos matrices. */
+int sgtt_host_problem_create(const sgtt_problem_desc* desc, sgtt_host_problem** out);
+int sgtt_host_problem_destroy(sgtt_host_problem* hp);
+/* sizes[0..5] = n_s, n_u, n_p, n_xi, nt, n_all */
+int sgtt_host_sizes(const sgtt_host_problem* hp, int* sizes);
+/* CSR export.  which: 0 = M (free x free), 1 = A unit viscosity (free x free),
+ * 2 = B (n_p x n_u), 3 = B M*^-1 B^T (n_p x n_p), 4 = B M*^-1 M M*^-1 B^T,
+ * 5 = B M*^-1 A M*^-1 B^T.  Call with NULL arrays to get nrows/ncols/nnz. */
+int sgtt_host_csr(const sgtt_host_problem* hp, int which, int* nrows, int* ncols, int* nnz,
+                  int* rowptr, int* col, double* val);
+/* chaos: which 0 = G (m+1 x n_xi x n_xi), 1 = H (n_xi^3), 2 = G_nu (n_xi^2) */
+int sgtt_host_gpc(const sgtt_host_problem* hp, int which, double* out);
+/* Dirichlet lift g over all velocity nodes (2 n_all) and node coordinates
+ * (n_all x 2), free node list (n_s) */
+int sgtt_host_mesh(const sgtt_host_problem* hp, double* coords, int* free_nodes, double* g_all);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGTT_H */

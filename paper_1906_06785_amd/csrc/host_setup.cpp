@@ -1,0 +1,629 @@
+// Host-side setup: step mesh, Q2-Q1 assembly, chaos matrices, LSC pressure
+// matrices and block-tridiagonal factorizations.  See host_setup.h.
+#include "host_setup.h"
+
+#include <algorithm>
+#include <climits>
+#include <functional>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+#include <tuple>
+
+namespace sgtt {
+
+namespace {
+
+inline int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
+
+// ---------------------------------------------------------------- reference element
+struct RefTables {
+  double w[9];          // Gauss weights (tensor 3x3)
+  double phi[9][9];     // [g][k]  Q2, k = a + 3 b
+  double dxi[9][9];     // d/dxi
+  double deta[9][9];    // d/deta
+  double psi[9][4];     // Q1, k = a + 2 b
+};
+
+RefTables make_ref() {
+  RefTables t;
+  const double gp[3] = {-std::sqrt(0.6), 0.0, std::sqrt(0.6)};
+  const double gw[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+  auto q2 = [](double x, int a) {
+    return a == 0 ? 0.5 * x * (x - 1) : (a == 1 ? 1 - x * x : 0.5 * x * (x + 1));
+  };
+  auto dq2 = [](double x, int a) { return a == 0 ? x - 0.5 : (a == 1 ? -2 * x : x + 0.5); };
+  auto q1 = [](double x, int a) { return a == 0 ? 0.5 * (1 - x) : 0.5 * (1 + x); };
+  for (int jb = 0; jb < 3; ++jb)
+    for (int ia = 0; ia < 3; ++ia) {
+      int g = ia + 3 * jb;
+      double xi = gp[ia], eta = gp[jb];
+      t.w[g] = gw[ia] * gw[jb];
+      for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a) {
+          int k = a + 3 * b;
+          t.phi[g][k] = q2(xi, a) * q2(eta, b);
+          t.dxi[g][k] = dq2(xi, a) * q2(eta, b);
+          t.deta[g][k] = q2(xi, a) * dq2(eta, b);
+        }
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) t.psi[g][a + 2 * b] = q1(xi, a) * q1(eta, b);
+    }
+  return t;
+}
+
+const RefTables& ref() {
+  static RefTables t = make_ref();
+  return t;
+}
+
+// ---------------------------------------------------------------- CSR helpers
+void finalize_pattern(std::vector<std::vector<int>>& rows, int ncols, Csr& c) {
+  c.nrows = (int)rows.size();
+  c.ncols = ncols;
+  c.rowptr.assign(c.nrows + 1, 0);
+  for (int i = 0; i < c.nrows; ++i) {
+    auto& r = rows[i];
+    std::sort(r.begin(), r.end());
+    r.erase(std::unique(r.begin(), r.end()), r.end());
+    c.rowptr[i + 1] = c.rowptr[i] + (int)r.size();
+  }
+  c.col.resize(c.rowptr[c.nrows]);
+  for (int i = 0; i < c.nrows; ++i)
+    std::copy(rows[i].begin(), rows[i].end(), c.col.begin() + c.rowptr[i]);
+  c.val.assign(c.col.size(), 0.0);
+}
+
+inline int find_pos(const Csr& c, int i, int j) {
+  auto b = c.col.begin() + c.rowptr[i], e = c.col.begin() + c.rowptr[i + 1];
+  auto it = std::lower_bound(b, e, j);
+  if (it == e || *it != j) throw std::runtime_error("pattern miss");
+  return (int)(it - c.col.begin());
+}
+
+// ---------------------------------------------------------------- mesh
+void build_mesh(double h, double L, Mesh& m) {
+  m.h = h;
+  m.L = L;
+  int q = (int)std::lround(1.0 / h);
+  if (std::fabs(q * h - 1.0) > 1e-12 || q % 2) throw std::runtime_error("1/h must be an even integer");
+  m.q = q;
+  int nL = (int)std::lround(q * L);
+  std::vector<std::pair<int, int>> elems;
+  for (int ec = -q; ec < 0; ++ec)
+    for (int er = -q / 2; er < q / 2; ++er) elems.push_back({ec, er});
+  for (int ec = 0; ec < nL; ++ec)
+    for (int er = -q; er < q; ++er) elems.push_back({ec, er});
+  // dense lattice index maps
+  int I0 = -2 * q, I1 = 2 * nL, J0 = -2 * q, J1 = 2 * q;
+  int NI = I1 - I0 + 1, NJ = J1 - J0 + 1;
+  std::vector<int> vmark((size_t)NI * NJ, -1), pmark((size_t)NI * NJ, -1);
+  for (auto& e : elems)
+    for (int b = 0; b < 3; ++b)
+      for (int a = 0; a < 3; ++a) {
+        int I = 2 * e.first + a, J = 2 * e.second + b;
+        vmark[(size_t)(I - I0) * NJ + (J - J0)] = 1;
+        if (a % 2 == 0 && b % 2 == 0) pmark[(size_t)(I - I0) * NJ + (J - J0)] = 1;
+      }
+  // sorted by (I, J) lexicographically == scan I outer, J inner
+  for (int I = I0; I <= I1; ++I)
+    for (int J = J0; J <= J1; ++J) {
+      size_t k = (size_t)(I - I0) * NJ + (J - J0);
+      if (vmark[k] >= 0) {
+        vmark[k] = (int)m.I.size();
+        m.I.push_back(I);
+        m.J.push_back(J);
+      }
+      if (pmark[k] >= 0) {
+        pmark[k] = (int)m.pI.size();
+        m.pI.push_back(I);
+        m.pJ.push_back(J);
+      }
+    }
+  for (auto& e : elems) {
+    std::array<int, 9> c;
+    std::array<int, 4> pc;
+    for (int b = 0; b < 3; ++b)
+      for (int a = 0; a < 3; ++a)
+        c[a + 3 * b] = vmark[(size_t)(2 * e.first + a - I0) * NJ + (2 * e.second + b - J0)];
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a)
+        pc[a + 2 * b] = pmark[(size_t)(2 * e.first + 2 * a - I0) * NJ + (2 * e.second + 2 * b - J0)];
+    m.conn.push_back(c);
+    m.pconn.push_back(pc);
+  }
+  int n = m.n_all();
+  m.free_id.assign(n, -1);
+  m.dir_id.assign(n, -1);
+  m.g1.assign(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    int I = m.I[k], J = m.J[k];
+    bool inflow = (I == -2 * q);
+    bool inlet_wall = (std::abs(J) == q) && (I <= 0);
+    bool channel_wall = (std::abs(J) == 2 * q);
+    bool step_face = (I == 0) && (std::abs(J) >= q);
+    if (inflow || inlet_wall || channel_wall || step_face) {
+      m.dir_id[k] = (int)m.dir_nodes.size();
+      m.dir_nodes.push_back(k);
+      if (inflow) {
+        double x2 = J * h / 2.0;
+        m.g1[k] = 1.0 - 4.0 * x2 * x2;
+      }
+    } else {
+      m.free_id[k] = (int)m.free_nodes.size();
+      m.free_nodes.push_back(k);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- chaos
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(3.14159265358979323846 * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double pn = (n == 1) ? z : p1;
+      double pnm1 = (n == 1) ? 1.0 : p0;
+      double dp = n * (z * pn - pnm1) / (z * z - 1);
+      double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double pn = (n == 1) ? z : p1, pnm1 = (n == 1) ? 1.0 : p0;
+    double dp = n * (z * pn - pnm1) / (z * z - 1);
+    x[i] = z;
+    w[i] = 2.0 / ((1 - z * z) * dp * dp);
+  }
+}
+
+// orthonormal Legendre sqrt(2n+1) P_n at x, n = 0..p
+void psi_all(int p, double x, double* out) {
+  double p0 = 1, p1 = x;
+  out[0] = 1.0;
+  if (p >= 1) out[1] = std::sqrt(3.0) * x;
+  for (int k = 2; k <= p; ++k) {
+    double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+    out[k] = std::sqrt(2.0 * k + 1) * p2;
+  }
+}
+
+void build_gpc(int m, int p, HostProblem& hp) {
+  // multi-indices: graded, descending lexicographic within each degree
+  std::vector<std::vector<int>> all;
+  for (int deg = 0; deg <= p; ++deg) {
+    std::vector<std::vector<int>> lev;
+    std::vector<int> a(m, 0);
+    // enumerate all tuples with entries in [0, deg] and sum == deg
+    std::function<void(int, int)> rec = [&](int pos, int rem) {
+      if (pos == m - 1) {
+        a[pos] = rem;
+        lev.push_back(a);
+        return;
+      }
+      for (int v = rem; v >= 0; --v) {
+        a[pos] = v;
+        rec(pos + 1, rem - v);
+      }
+    };
+    rec(0, deg);
+    std::sort(lev.begin(), lev.end(), std::greater<std::vector<int>>());
+    for (auto& t : lev) all.push_back(t);
+  }
+  hp.midx = all;
+  int n = (int)all.size();
+  hp.n_xi = n;
+  // 1-D tables by Gauss-Legendre quadrature (expectation = integral / 2)
+  int npts = (3 * p + 2) / 2 + 2;
+  std::vector<double> gx, gw;
+  gauss_legendre(npts, gx, gw);
+  std::vector<double> P((size_t)npts * (p + 1));
+  for (int g = 0; g < npts; ++g) psi_all(p, gx[g], &P[(size_t)g * (p + 1)]);
+  auto T3 = [&](int a, int b, int c) {
+    double s = 0;
+    for (int g = 0; g < npts; ++g)
+      s += 0.5 * gw[g] * P[g * (p + 1) + a] * P[g * (p + 1) + b] * P[g * (p + 1) + c];
+    return s;
+  };
+  auto X2 = [&](int a, int b) {
+    double s = 0;
+    for (int g = 0; g < npts; ++g) s += 0.5 * gw[g] * gx[g] * P[g * (p + 1) + a] * P[g * (p + 1) + b];
+    return s;
+  };
+  hp.G.assign((size_t)(m + 1) * n * n, 0.0);
+  for (int r = 0; r < n; ++r) hp.G[(size_t)r * n + r] = 1.0;
+  for (int l = 0; l < m; ++l)
+    for (int r = 0; r < n; ++r)
+      for (int s = 0; s < n; ++s) {
+        bool same = true;
+        for (int k = 0; k < m; ++k)
+          if (k != l && all[r][k] != all[s][k]) same = false;
+        if (same) hp.G[((size_t)(l + 1) * n + r) * n + s] = X2(all[r][l], all[s][l]);
+      }
+  hp.H.assign((size_t)n * n * n, 0.0);
+  for (int l = 0; l < n; ++l)
+    for (int r = 0; r < n; ++r)
+      for (int s = 0; s < n; ++s) {
+        double v = 1.0;
+        for (int k = 0; k < m; ++k) v *= T3(all[l][k], all[r][k], all[s][k]);
+        hp.H[((size_t)l * n + r) * n + s] = v;
+      }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- problem
+void build_problem(const ProblemParams& prm, HostProblem& hp) {
+  hp.prm = prm;
+  Mesh& m = hp.mesh;
+  build_mesh(prm.h, prm.L, m);
+  const int ns = m.n_s(), na = m.n_all(), np = m.n_p();
+  hp.n_s = ns;
+  hp.n_u = 2 * ns;
+  hp.n_p = np;
+  hp.n_all = na;
+  hp.nt = prm.nt;
+  const RefTables& R = ref();
+  const double h = prm.h, jac = 0.25 * h * h;
+  // element matrices (identical on every square)
+  double Me[9][9], Ae[9][9], B1e[4][9], B2e[4][9];
+  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j < 9; ++j) {
+      double sm = 0, sa = 0;
+      for (int g = 0; g < 9; ++g) {
+        sm += R.w[g] * R.phi[g][i] * R.phi[g][j];
+        sa += R.w[g] * (R.dxi[g][i] * R.dxi[g][j] + R.deta[g][i] * R.deta[g][j]);
+      }
+      Me[i][j] = sm * jac;
+      Ae[i][j] = sa;          // (2/h)^2 * jac = 1
+    }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 9; ++j) {
+      double s1 = 0, s2 = 0;
+      for (int g = 0; g < 9; ++g) {
+        s1 += R.w[g] * R.psi[g][i] * R.dxi[g][j];
+        s2 += R.w[g] * R.psi[g][i] * R.deta[g][j];
+      }
+      B1e[i][j] = -s1 * jac * (2.0 / h);
+      B2e[i][j] = -s2 * jac * (2.0 / h);
+    }
+  // patterns
+  std::vector<std::vector<int>> rff(ns), rfa(ns), rb(np), rball(np);
+  for (size_t e = 0; e < m.conn.size(); ++e) {
+    const auto& c = m.conn[e];
+    for (int i = 0; i < 9; ++i) {
+      int fi = m.free_id[c[i]];
+      if (fi < 0) continue;
+      for (int j = 0; j < 9; ++j) {
+        rfa[fi].push_back(c[j]);
+        int fj = m.free_id[c[j]];
+        if (fj >= 0) rff[fi].push_back(fj);
+      }
+    }
+    for (int i = 0; i < 4; ++i) {
+      int k = m.pconn[e][i];
+      for (int j = 0; j < 9; ++j) {
+        rball[k].push_back(c[j]);
+        rball[k].push_back(na + c[j]);
+        int fj = m.free_id[c[j]];
+        if (fj >= 0) {
+          rb[k].push_back(fj);
+          rb[k].push_back(ns + fj);
+        }
+      }
+    }
+  }
+  finalize_pattern(rff, ns, hp.Kff);
+  finalize_pattern(rfa, na, hp.Kfa);
+  finalize_pattern(rb, 2 * ns, hp.B);
+  finalize_pattern(rball, 2 * na, hp.Ball);
+  hp.Mff.assign(hp.Kff.nnz(), 0.0);
+  hp.Aff.assign(hp.Kff.nnz(), 0.0);
+  hp.Mfa.assign(hp.Kfa.nnz(), 0.0);
+  hp.Afa.assign(hp.Kfa.nnz(), 0.0);
+  for (size_t e = 0; e < m.conn.size(); ++e) {
+    const auto& c = m.conn[e];
+    for (int i = 0; i < 9; ++i) {
+      int fi = m.free_id[c[i]];
+      if (fi < 0) continue;
+      for (int j = 0; j < 9; ++j) {
+        int pa = find_pos(hp.Kfa, fi, c[j]);
+        hp.Mfa[pa] += Me[i][j];
+        hp.Afa[pa] += Ae[i][j];
+        int fj = m.free_id[c[j]];
+        if (fj >= 0) {
+          int pf = find_pos(hp.Kff, fi, fj);
+          hp.Mff[pf] += Me[i][j];
+          hp.Aff[pf] += Ae[i][j];
+        }
+      }
+    }
+    for (int i = 0; i < 4; ++i) {
+      int k = m.pconn[e][i];
+      for (int j = 0; j < 9; ++j) {
+        hp.Ball.val[find_pos(hp.Ball, k, c[j])] += B1e[i][j];
+        hp.Ball.val[find_pos(hp.Ball, k, na + c[j])] += B2e[i][j];
+        int fj = m.free_id[c[j]];
+        if (fj >= 0) {
+          hp.B.val[find_pos(hp.B, k, fj)] += B1e[i][j];
+          hp.B.val[find_pos(hp.B, k, ns + fj)] += B2e[i][j];
+        }
+      }
+    }
+  }
+  // B^T (n_u x n_p)
+  {
+    std::vector<std::vector<int>> rt(2 * ns);
+    for (int k = 0; k < np; ++k)
+      for (int t = hp.B.rowptr[k]; t < hp.B.rowptr[k + 1]; ++t) rt[hp.B.col[t]].push_back(k);
+    finalize_pattern(rt, np, hp.Bt);
+    for (int k = 0; k < np; ++k)
+      for (int t = hp.B.rowptr[k]; t < hp.B.rowptr[k + 1]; ++t)
+        hp.Bt.val[find_pos(hp.Bt, hp.B.col[t], k)] = hp.B.val[t];
+  }
+  // chaos and viscosity
+  build_gpc(prm.m, prm.p, hp);
+  const int nx = hp.n_xi;
+  hp.visc.assign(prm.m + 1, 0.0);
+  hp.visc[0] = prm.nu0;
+  for (int k = 1; k <= prm.m; ++k) hp.visc[k] = prm.nu_coef * prm.nu0 / ((double)k * k);
+  hp.Gnu.assign((size_t)nx * nx, 0.0);
+  for (int l = 0; l <= prm.m; ++l)
+    for (int i = 0; i < nx * nx; ++i) hp.Gnu[i] += hp.visc[l] * hp.G[(size_t)l * nx * nx + i];
+  // time ramp
+  hp.ramp.resize(prm.nt);
+  for (int k = 0; k < prm.nt; ++k) hp.ramp[k] = 1.0 - std::exp(-prm.ramp * prm.tau * (k + 1));
+  // Dirichlet lift
+  hp.g_all.assign(2 * na, 0.0);
+  for (int k = 0; k < na; ++k)
+    if (m.dir_id[k] >= 0) hp.g_all[k] = m.g1[k];
+  // M_* = diag(M)
+  hp.Mstar.assign(ns, 0.0);
+  for (int i = 0; i < ns; ++i) hp.Mstar[i] = hp.Mff[find_pos(hp.Kff, i, i)];
+  // X = B M*^-1 B^T pattern/values, and the LSC middle pattern
+  {
+    std::vector<std::vector<int>> rx(np), rmid(np);
+    std::vector<int> mark(np, -1), mark2(np, -1);
+    for (int k = 0; k < np; ++k) {
+      for (int t = hp.B.rowptr[k]; t < hp.B.rowptr[k + 1]; ++t) {
+        int cj = hp.B.col[t];
+        for (int u = hp.Bt.rowptr[cj]; u < hp.Bt.rowptr[cj + 1]; ++u) {
+          int k2 = hp.Bt.col[u];
+          if (mark[k2] != k) { mark[k2] = k; rx[k].push_back(k2); }
+        }
+        int c = cj / ns, j = cj % ns;
+        for (int s = hp.Kff.rowptr[j]; s < hp.Kff.rowptr[j + 1]; ++s) {
+          int l = hp.Kff.col[s];
+          int cl = c * ns + l;
+          for (int u = hp.Bt.rowptr[cl]; u < hp.Bt.rowptr[cl + 1]; ++u) {
+            int k2 = hp.Bt.col[u];
+            if (mark2[k2] != k) { mark2[k2] = k; rmid[k].push_back(k2); }
+          }
+        }
+      }
+    }
+    finalize_pattern(rx, np, hp.Xp);
+    finalize_pattern(rmid, np, hp.Xmid);
+    std::vector<double> acc(np, 0.0);
+    for (int k = 0; k < np; ++k) {
+      for (int t = hp.B.rowptr[k]; t < hp.B.rowptr[k + 1]; ++t) {
+        int cj = hp.B.col[t];
+        double w = hp.B.val[t] / hp.Mstar[cj % ns];
+        for (int u = hp.Bt.rowptr[cj]; u < hp.Bt.rowptr[cj + 1]; ++u) acc[hp.Bt.col[u]] += w * hp.Bt.val[u];
+      }
+      for (int t = hp.Xp.rowptr[k]; t < hp.Xp.rowptr[k + 1]; ++t) {
+        hp.Xp.val[t] = acc[hp.Xp.col[t]];
+        acc[hp.Xp.col[t]] = 0.0;
+      }
+    }
+    hp.XM.assign(hp.Xmid.nnz(), 0.0);
+    hp.XA.assign(hp.Xmid.nnz(), 0.0);
+    lsc_middle_values(hp, hp.Mff.data(), hp.XM.data());
+    lsc_middle_values(hp, hp.Aff.data(), hp.XA.data());
+  }
+  // slab partitions: velocity node column I -> slab floor(I/2); pressure
+  // vertex column I -> slab floor(I/4).  Both orderings are sorted by I first.
+  {
+    hp.vel_blocks.clear();
+    int prev = INT32_MIN;
+    for (int i = 0; i < ns; ++i) {
+      int s = floordiv(m.I[m.free_nodes[i]], 2);
+      if (s != prev) { hp.vel_blocks.push_back(i); prev = s; }
+    }
+    hp.vel_blocks.push_back(ns);
+    hp.p_blocks.clear();
+    prev = INT32_MIN;
+    for (int k = 0; k < np; ++k) {
+      int s = floordiv(m.pI[k], 4);
+      if (s != prev) { hp.p_blocks.push_back(k); prev = s; }
+    }
+    hp.p_blocks.push_back(np);
+  }
+}
+
+void lsc_middle_values(const HostProblem& hp, const double* S, double* out) {
+  const int ns = hp.n_s, np = hp.n_p;
+  std::vector<double> acc(np, 0.0);
+  for (int k = 0; k < np; ++k) {
+    for (int t = hp.B.rowptr[k]; t < hp.B.rowptr[k + 1]; ++t) {
+      int cj = hp.B.col[t];
+      int c = cj / ns, j = cj % ns;
+      double w = hp.B.val[t] / hp.Mstar[j];
+      for (int s = hp.Kff.rowptr[j]; s < hp.Kff.rowptr[j + 1]; ++s) {
+        int l = hp.Kff.col[s];
+        double v = w * S[s] / hp.Mstar[l];
+        int cl = c * ns + l;
+        for (int u = hp.Bt.rowptr[cl]; u < hp.Bt.rowptr[cl + 1]; ++u) acc[hp.Bt.col[u]] += v * hp.Bt.val[u];
+      }
+    }
+    for (int t = hp.Xmid.rowptr[k]; t < hp.Xmid.rowptr[k + 1]; ++t) {
+      out[t] = acc[hp.Xmid.col[t]];
+      acc[hp.Xmid.col[t]] = 0.0;
+    }
+  }
+}
+
+void convection_values(const HostProblem& hp, const double* w1, const double* w2, double* vff,
+                       double* vfa) {
+  const Mesh& m = hp.mesh;
+  const RefTables& R = ref();
+  const double hh = 0.5 * hp.prm.h;   // jac * (2/h)
+  std::fill(vff, vff + hp.Kff.nnz(), 0.0);
+  if (vfa) std::fill(vfa, vfa + hp.Kfa.nnz(), 0.0);
+  for (size_t e = 0; e < m.conn.size(); ++e) {
+    const auto& c = m.conn[e];
+    double W1[9], W2[9];
+    for (int g = 0; g < 9; ++g) {
+      double a = 0, b = 0;
+      for (int k = 0; k < 9; ++k) {
+        a += w1[c[k]] * R.phi[g][k];
+        b += w2[c[k]] * R.phi[g][k];
+      }
+      W1[g] = a;
+      W2[g] = b;
+    }
+    for (int i = 0; i < 9; ++i) {
+      int fi = m.free_id[c[i]];
+      if (fi < 0) continue;
+      for (int j = 0; j < 9; ++j) {
+        double s = 0;
+        for (int g = 0; g < 9; ++g) s += R.w[g] * (W1[g] * R.dxi[g][j] + W2[g] * R.deta[g][j]) * R.phi[g][i];
+        s *= hh;
+        if (vfa) vfa[find_pos(hp.Kfa, fi, c[j])] += s;
+        int fj = m.free_id[c[j]];
+        if (fj >= 0) vff[find_pos(hp.Kff, fi, fj)] += s;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- block tridiagonal
+namespace {
+// in-place inverse of a dense column-major n x n matrix (Gauss-Jordan with
+// partial pivoting); returns false if singular
+bool dense_inverse(int n, double* A) {
+  std::vector<int> piv(n);
+  std::vector<double> inv((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  auto at = [&](std::vector<double>& M, int r, int c) -> double& { return M[(size_t)c * n + r]; };
+  std::vector<double> a(A, A + (size_t)n * n);
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = std::fabs(at(a, k, k));
+    for (int r = k + 1; r < n; ++r)
+      if (std::fabs(at(a, r, k)) > best) { best = std::fabs(at(a, r, k)); p = r; }
+    if (best == 0.0) return false;
+    if (p != k)
+      for (int c = 0; c < n; ++c) {
+        std::swap(at(a, k, c), at(a, p, c));
+        std::swap(at(inv, k, c), at(inv, p, c));
+      }
+    double d = 1.0 / at(a, k, k);
+    for (int c = 0; c < n; ++c) { at(a, k, c) *= d; at(inv, k, c) *= d; }
+    for (int r = 0; r < n; ++r) {
+      if (r == k) continue;
+      double f = at(a, r, k);
+      if (f == 0.0) continue;
+      for (int c = 0; c < n; ++c) {
+        at(a, r, c) -= f * at(a, k, c);
+        at(inv, r, c) -= f * at(inv, k, c);
+      }
+    }
+  }
+  std::copy(inv.begin(), inv.end(), A);
+  return true;
+}
+
+// C (m x n) = A (m x k) * B (k x n), column-major
+void gemm_cm(int m, int n, int k, const double* A, const double* B, double* C, double alpha, double beta) {
+  for (int j = 0; j < n; ++j) {
+    double* cj = C + (size_t)j * m;
+    for (int i = 0; i < m; ++i) cj[i] *= beta;
+    for (int l = 0; l < k; ++l) {
+      double b = alpha * B[(size_t)j * k + l];
+      if (b == 0.0) continue;
+      const double* al = A + (size_t)l * m;
+      for (int i = 0; i < m; ++i) cj[i] += al[i] * b;
+    }
+  }
+}
+}  // namespace
+
+void blocktri_factor(const Csr& pat, const double* vals, const std::vector<int>& blocks, BlockTri& bt,
+                     std::string& err) {
+  const int n = pat.nrows, nb = (int)blocks.size() - 1;
+  bt.n = n;
+  bt.nblk = nb;
+  bt.start = blocks;
+  std::vector<int> blk(n);
+  bt.maxbs = 0;
+  for (int b = 0; b < nb; ++b) {
+    bt.maxbs = std::max(bt.maxbs, blocks[b + 1] - blocks[b]);
+    for (int i = blocks[b]; i < blocks[b + 1]; ++i) blk[i] = b;
+  }
+  for (int i = 0; i < n; ++i)
+    for (int t = pat.rowptr[i]; t < pat.rowptr[i + 1]; ++t)
+      if (std::abs(blk[i] - blk[pat.col[t]]) > 1) {
+        err = "matrix is not block tridiagonal in the slab ordering";
+        return;
+      }
+  auto bs = [&](int b) { return blocks[b + 1] - blocks[b]; };
+  bt.off_sinv.assign(nb, 0);
+  bt.off_p.assign(nb, -1);
+  bt.off_q.assign(nb, -1);
+  int64_t off = 0;
+  for (int b = 0; b < nb; ++b) {
+    bt.off_sinv[b] = off;
+    off += (int64_t)bs(b) * bs(b);
+    if (b > 0) { bt.off_p[b] = off; off += (int64_t)bs(b) * bs(b - 1); }
+    if (b < nb - 1) { bt.off_q[b] = off; off += (int64_t)bs(b) * bs(b + 1); }
+  }
+  bt.data.assign(off, 0.0);
+  // dense blocks: D_b, L_b (b, b-1), U_b (b, b+1), column-major
+  auto extract = [&](int b, int c, std::vector<double>& out) {
+    int r0 = blocks[b], nr = bs(b), c0 = blocks[c], nc = bs(c);
+    out.assign((size_t)nr * nc, 0.0);
+    for (int i = 0; i < nr; ++i)
+      for (int t = pat.rowptr[r0 + i]; t < pat.rowptr[r0 + i + 1]; ++t) {
+        int j = pat.col[t] - c0;
+        if (j >= 0 && j < nc) out[(size_t)j * nr + i] += vals[t];
+      }
+  };
+  std::vector<double> D, Lb, Ub, prevUb, tmp;
+  for (int b = 0; b < nb; ++b) {
+    extract(b, b, D);
+    if (b > 0) {
+      // S'_b = D_b - L_b Sinv_{b-1} U_{b-1} = D_b - L_b Q_{b-1}
+      extract(b, b - 1, Lb);
+      const double* Qprev = bt.data.data() + bt.off_q[b - 1];
+      gemm_cm(bs(b), bs(b), bs(b - 1), Lb.data(), Qprev, D.data(), -1.0, 1.0);
+    }
+    if (!dense_inverse(bs(b), D.data())) {
+      err = "singular diagonal block in block-tridiagonal factorization";
+      return;
+    }
+    std::copy(D.begin(), D.end(), bt.data.begin() + bt.off_sinv[b]);
+    const double* Sinv = bt.data.data() + bt.off_sinv[b];
+    if (b > 0) gemm_cm(bs(b), bs(b - 1), bs(b), Sinv, Lb.data(), bt.data.data() + bt.off_p[b], 1.0, 0.0);
+    if (b < nb - 1) {
+      extract(b, b + 1, Ub);
+      gemm_cm(bs(b), bs(b + 1), bs(b), Sinv, Ub.data(), bt.data.data() + bt.off_q[b], 1.0, 0.0);
+    }
+  }
+}
+
+}  // namespace sgtt

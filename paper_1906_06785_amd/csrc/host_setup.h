@@ -1,0 +1,110 @@
+// Host-side problem setup for the step-domain stochastic Galerkin system.
+//
+// Mesh and Q2-Q1 Taylor-Hood assembly (sec. 3.2, eq. 3.7-3.8; sec. 6.1),
+// Legendre chaos matrices G_l, H_l (eq. 3.9), convection matrices N(w)
+// (eq. 3.7) for given wind vectors, pressure-space LSC matrices
+// B M*^-1 S M*^-1 B^T (eq. 5.19), and block-tridiagonal factorizations of
+// the spatial matrices used by the mean-based preconditioner (eq. 5.19,
+// eq. 5.23).  Plain C++; no device code here.
+#pragma once
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace sgtt {
+
+struct Csr {
+  int nrows = 0, ncols = 0;
+  std::vector<int> rowptr, col;
+  std::vector<double> val;           // one value array; extra value sets live elsewhere
+  int nnz() const { return (int)col.size(); }
+};
+
+struct ProblemParams {
+  double h = 0.25, L = 12.0;
+  int m = 2, p = 2, nt = 10;
+  double tau = 0.1, nu0 = 1.0 / 50, nu_coef = 0.1, ramp = 10.0;
+};
+
+struct Mesh {
+  double h = 0, L = 0;
+  int q = 0;                          // 1/h
+  std::vector<int> I, J;              // lattice coordinates of velocity nodes (x = I*h/2)
+  std::vector<int> pI, pJ;            // lattice coordinates of pressure nodes
+  std::vector<std::array<int, 9>> conn;   // element -> velocity node (local a + 3 b)
+  std::vector<std::array<int, 4>> pconn;  // element -> pressure node (local a + 2 b)
+  std::vector<int> free_nodes, dir_nodes;  // sorted by (x1, x2)
+  std::vector<int> free_id;           // node -> free index or -1
+  std::vector<int> dir_id;            // node -> Dirichlet index or -1
+  std::vector<double> g1;             // x1 inflow value at each node (0 if not inflow)
+  int n_all() const { return (int)I.size(); }
+  int n_s() const { return (int)free_nodes.size(); }
+  int n_p() const { return (int)pI.size(); }
+};
+
+// Block-tridiagonal factorization for x = S^-1 b with the block LU recursion
+// S'_1 = D_1, S'_i = D_i - L_i S'_{i-1}^-1 U_{i-1}.  Stored per block i:
+// Sinv_i (bs_i x bs_i), P_i = Sinv_i L_i (bs_i x bs_{i-1}),
+// Q_i = Sinv_i U_i (bs_i x bs_{i+1}), all column-major.
+struct BlockTri {
+  int n = 0, nblk = 0, maxbs = 0;
+  std::vector<int> start;             // nblk + 1
+  std::vector<int64_t> off_sinv, off_p, off_q;   // offsets into data (doubles)
+  std::vector<double> data;
+};
+
+struct HostProblem {
+  ProblemParams prm;
+  Mesh mesh;
+  int n_s = 0, n_u = 0, n_p = 0, n_all = 0, n_xi = 0, nt = 0;
+  // scalar velocity pattern on free x free nodes with M and unit-viscosity A
+  Csr Kff;                            // pattern; val unused
+  std::vector<double> Mff, Aff;
+  // scalar pattern free rows x all nodes (for residuals with the Dirichlet lift)
+  Csr Kfa;
+  std::vector<double> Mfa, Afa;
+  // divergence: B (n_p x n_u, free dofs, columns [comp1 | comp2]) and B^T
+  Csr B, Bt;
+  // divergence against all velocity nodes: n_p x 2 n_all
+  Csr Ball;
+  // chaos
+  std::vector<std::vector<int>> midx;
+  std::vector<double> G;              // (m+1) x n_xi x n_xi
+  std::vector<double> H;              // n_xi x n_xi x n_xi  (H[0] = I)
+  std::vector<double> visc;           // c_0..c_m
+  std::vector<double> Gnu;            // n_xi x n_xi
+  // time
+  std::vector<double> ramp;           // a_k = 1 - exp(-ramp t_k), k = 1..nt
+  // Dirichlet lift over all velocity nodes: g_all (2 n_all)
+  std::vector<double> g_all;
+  // M_* = diag(M) on free dofs (length n_s; both components share it)
+  std::vector<double> Mstar;
+  // pressure Laplacian X = B M*^-1 B^T and its pattern (n_p x n_p)
+  Csr Xp;                             // pattern + values of X
+  Csr Xmid;                           // pattern for B M*^-1 S M*^-1 B^T (S = M, A, N)
+  std::vector<double> XM, XA;         // values on Xmid for S = M, S = A (unit)
+  // slab partitions (block-tridiagonal orderings) of free velocity nodes and
+  // pressure nodes
+  std::vector<int> vel_blocks, p_blocks;
+};
+
+// Build everything that does not depend on a prior iterate.
+void build_problem(const ProblemParams& prm, HostProblem& hp);
+
+// Convection matrix values N(w) (eq. 3.7) for a wind given at all velocity
+// nodes (w1, w2 of length n_all): values on Kff (free x free) and, if
+// vals_fa != nullptr, on Kfa (free x all).
+void convection_values(const HostProblem& hp, const double* w1, const double* w2,
+                       double* vals_ff, double* vals_fa);
+
+// Values of B M*^-1 S M*^-1 B^T on the Xmid pattern for a scalar velocity
+// matrix S given by values on Kff (applied to both components).
+void lsc_middle_values(const HostProblem& hp, const double* Svals, double* out);
+
+// Block-tridiagonal factorization of a scalar matrix on pattern `pat` with
+// values `vals`, block partition `blocks` (nblk + 1 starts).
+void blocktri_factor(const Csr& pat, const double* vals, const std::vector<int>& blocks,
+                     BlockTri& bt, std::string& err);
+
+}  // namespace sgtt

@@ -1,0 +1,103 @@
+// Device kernels for the tensor-train Picard-step solver (gfx950).
+// Launch wrappers only; every numeric step of the solve runs in these kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace sgtt {
+
+// C[b](i,j) = alpha * sum_k A[b](i,k) B[b](k,j) + beta * C[b](i,j)
+// element (i,k) of A[b] at A + b*sAb + i*sAi + k*sAk (likewise B, C).
+// If klimit > 0, batch b only sums k < min(k, klimit - b*kstep) (split-K).
+void gemm(hipStream_t s, int batch, int m, int n, int k, double alpha, const double* A, long sAb,
+          long sAi, long sAk, const double* B, long sBb, long sBk, long sBj, double beta, double* C,
+          long sCb, long sCi, long sCj, int kstep = 0, long klimit = 0);
+
+// out (nx x ny, row-major) = X^T Y over `rows` rows; X(r,i) at X + r*sXr + i*sXc.
+// ws: scratch of ws_doubles doubles for split-K partial sums.
+void gram(hipStream_t s, long rows, int nx, int ny, const double* X, long sXr, long sXc,
+          const double* Y, long sYr, long sYc, double* out, double* ws, size_t ws_doubles);
+
+// Sum of squares of n doubles into *out (single value, device) -- deterministic.
+void sumsq(hipStream_t s, const double* x, long n, double* out, double* ws, size_t ws_doubles);
+
+void fill(hipStream_t s, double* p, long n, double v);
+// 2-D strided copy with scale: dst[i*ldd + j] = alpha * (*dscale if dscale) * src[i*lds + j]
+void copy2d(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst, long ldd,
+            double alpha, const double* dscale = nullptr, int dscale_inv = 0);
+
+// CSR SpMM over the space index with several value arrays sharing a pattern
+// and `ncomp` velocity components:
+//  y[(c*ocs + r)*ldy + ycol0 + v*yvstep + j] =
+//     alpha * sum_t vals[v*vstride + t] * x[(c*ics + col[t])*ldx + xcol0 + j]
+// for rows r < nrows, components c < ncomp, v < nv (<= 16), columns j < ncols.
+void spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* rowptr, const int* col,
+          const double* vals, int nv, long vstride, const double* x, int ldx, int xcol0, int ncols,
+          double* y, int ldy, int ycol0, int yvstep, double alpha);
+
+// core1 block ops on row-major n1 x r matrices
+// out[t, col0 + a] = scale*(in[t,a] - in[t-1,a])          (kind 0: (I - C)/tau)
+// out[t, col0 + a] = scale*in[t,a] (times *dscale)          (kind 1: copy)
+// out[t, col0 + a] = scale*sum_{s<=t} in[s,a]               (kind 2: (I - C)^-1)
+void core1_op(hipStream_t s, int kind, int n1, int r, const double* in, int ldi, double* out, int ldo,
+              int col0, double scale, const double* dscale = nullptr);
+// out[t, col0 + a*r + al] = w[t*ldw + a] * in[t*ldi + al] for a < k
+void core1_diag(hipStream_t s, int n1, int r, int k, const double* w, int ldw, const double* in, int ldi,
+                double* out, int ldo, int col0);
+
+// core2 block: out[(row0 + a*r1 + al), i, (col0 + b*r2 + be)] =
+//   sum_j X_ab(i,j) in[al, j, be]  for a < k1, b < k2, with X_ab at
+//   X + (a*k2 + b)*n2*n2 (row-major n2 x n2), or identity if X == nullptr.
+// out is R1 x n2 x R2 row-major.
+void core2_block(hipStream_t s, int r1, int n2, int r2, const double* in, const double* X, int k1, int k2,
+                 double* out, int R1, int R2, int row0, int col0);
+
+// One-workgroup truncated eigen-decomposition of a symmetric PSD Gram
+// matrix S (N x N row-major, overwritten), following the TT-SVD rank rule:
+// pivoted Cholesky until the remaining trace is <= frac*delta^2, Jacobi
+// eigen-decomposition of the small factor, rank k = smallest r >= 1 with
+// tail + residual <= delta^2, U (N x k, ldU = kmax) orthonormal leading
+// eigenvectors.  delta^2 = eps^2 * normsq / 2 where normsq = *normsq_in if
+// given, else trace(S) (written to *normsq_out).  Writes k to *k_out and
+// the kept eigenvalue sum to *kept_out.  L: scratch N x kmax (+ N).
+// *info = 1 when kmax pivots were not enough and kmax < rank_bound (the
+// largest rank the matrix can have), i.e. the rank capacity is exceeded.
+void trunc_eig(hipStream_t s, int N, double* S, double eps, const double* normsq_in, double* normsq_out,
+               double* U, int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound);
+
+// Block-tridiagonal solve X <- A^-1 X on ncols columns of a node-major
+// matrix (row = space index, ld = ldx) with `ncomp` components stacked by
+// rows (component c occupies rows [c*n, (c+1)*n)).
+void blocktri_solve(hipStream_t s, int n, int nblk, int maxbs, const int* start, const long* off_sinv,
+                    const long* off_p, const long* off_q, const double* data, int ncomp, double* X, int ldx,
+                    int ncols, double* Y);
+
+// Givens least squares for the (k+1) x k Hessenberg H (column-major, ld),
+// y = argmin || beta e1 - H y ||; resid = |final rotated rhs entry|.
+void hessenberg_lsq(hipStream_t s, const double* H, int ld, int k, const double* beta, double* y,
+                    double* resid);
+
+// Modified Gram-Schmidt coefficients from <x, v_i> (d, i < k) and the basis
+// Gram matrix GV (ld): h_i = d_i - sum_{j<i} h_j GV[j, i].  Writes h into
+// Hcol[0..k-1] and coef[0] = 1, coef[1+i] = -h_i.
+void mgs_coef(hipStream_t s, int k, const double* d, const double* GV, int ldg, double* Hcol, double* coef);
+
+// small scalar helpers on device values
+// out = sqrt(a + b) (kind 0), out = 1/a (kind 1), out = a * b (kind 2),
+// out = a + b (kind 3), out = -a (kind 4), out = sqrt(a) (kind 5)
+void scalar_op(hipStream_t s, int kind, const double* a, const double* b, double* out);
+
+// sum_i w[i] * k[i] over n entries -> out (or out += if accumulate)
+void dot_reduce(hipStream_t s, long n, const double* w, const double* k, double* out, int accumulate);
+
+// scale n doubles by *dscale (or 1 / *dscale if inv)
+void scale_by(hipStream_t s, double* p, long n, const double* dscale, int inv);
+
+// full residual helper: out[i] = a[i] - b[i]
+void sub_arrays(hipStream_t s, const double* a, const double* b, double* out, long n);
+
+// check finite: *flag = 1 if any non-finite in x[0..n)
+void check_finite(hipStream_t s, const double* x, long n, int* flag);
+
+}  // namespace sgtt

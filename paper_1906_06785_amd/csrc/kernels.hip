@@ -1,0 +1,810 @@
+// Device kernels for the tensor-train Picard-step solver on gfx950.
+// See kernels.h for the contract of each launcher.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+
+#include "kernels.h"
+
+namespace sgtt {
+
+namespace {
+constexpr int WAVE = 64;
+
+inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+// ------------------------------------------------------------------ GEMM
+constexpr int TM = 64, TN = 64, TK = 16;
+
+__global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, double alpha, const double* __restrict__ A,
+                                              long sAb, long sAi, long sAk, const double* __restrict__ B, long sBb,
+                                              long sBk, long sBj, double beta, double* __restrict__ C, long sCb,
+                                              long sCi, long sCj, int kstep, long klimit) {
+  const int b = blockIdx.z;
+  long kb = k;
+  if (klimit > 0) {
+    long rem = klimit - (long)b * kstep;
+    kb = rem < k ? rem : k;
+  }
+  A += b * sAb;
+  B += b * sBb;
+  C += b * sCb;
+  const int i0 = blockIdx.y * TM, j0 = blockIdx.x * TN;
+  __shared__ double As[TK][TM + 1];
+  __shared__ double Bs[TK][TN + 1];
+  const int tid = threadIdx.x;
+  const int ti = tid / 16, tj = tid % 16;
+  double acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+  const bool a_kfast = (sAk == 1);
+  const bool b_kfast = (sBk == 1);
+  for (long kk = 0; kk < kb; kk += TK) {
+    for (int e = tid; e < TM * TK; e += 256) {
+      int ii, kx;
+      if (a_kfast) { kx = e % TK; ii = e / TK; } else { ii = e % TM; kx = e / TM; }
+      long gi = i0 + ii, gk = kk + kx;
+      As[kx][ii] = (gi < m && gk < kb) ? A[gi * sAi + gk * sAk] : 0.0;
+    }
+    for (int e = tid; e < TK * TN; e += 256) {
+      int jj, kx;
+      if (b_kfast) { kx = e % TK; jj = e / TK; } else { jj = e % TN; kx = e / TN; }
+      long gj = j0 + jj, gk = kk + kx;
+      Bs[kx][jj] = (gj < n && gk < kb) ? B[gk * sBk + gj * sBj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kx = 0; kx < TK; ++kx) {
+      double a[4], bb[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = As[kx][ti + 16 * r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bb[c] = Bs[kx][tj + 16 * c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], bb[c], acc[r][c]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    long gi = i0 + ti + 16 * r;
+    if (gi >= m) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      long gj = j0 + tj + 16 * c;
+      if (gj >= n) continue;
+      double* cp = C + gi * sCi + gj * sCj;
+      double v = alpha * acc[r][c];
+      if (beta != 0.0) v += beta * (*cp);
+      *cp = v;
+    }
+  }
+}
+
+__global__ void k_reduce_partials(int nb, long ne, const double* __restrict__ ws, double* __restrict__ out) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += ws[(long)b * ne + e];
+  out[e] = s;
+}
+
+// ------------------------------------------------------------------ reductions
+__device__ double block_sum(double v, double* sh) {
+  // 1024 threads max; sh has >= 32 entries
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_down(v, o, WAVE);
+  int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  int nw = (blockDim.x + WAVE - 1) / WAVE;
+  double t = 0.0;
+  if (threadIdx.x < WAVE) {
+    t = (l < nw) ? sh[l] : 0.0;
+    for (int o = WAVE / 2; o > 0; o >>= 1) t += __shfl_down(t, o, WAVE);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) sh[0] = t;
+  __syncthreads();
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_sumsq_stage1(const double* __restrict__ x, long n, double* __restrict__ ws) {
+  __shared__ double sh[32];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double v = x[i];
+    s = fma(v, v, s);
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) ws[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(1024) void k_sum_stage2(const double* __restrict__ ws, int nb, double* out) {
+  __shared__ double sh[32];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += ws[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) *out = s;
+}
+
+__global__ __launch_bounds__(1024) void k_dot_reduce(long n, const double* __restrict__ w, const double* __restrict__ k,
+                                                    double* out, int acc) {
+  __shared__ double sh[32];
+  double s = 0.0;
+  for (long i = threadIdx.x; i < n; i += blockDim.x) s = fma(w[i], k[i], s);
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) *out = acc ? (*out + s) : s;
+}
+
+// ------------------------------------------------------------------ elementwise
+__global__ void k_fill(double* p, long n, double v) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_copy2d(int rows, int cols, const double* __restrict__ src, long lds, double* __restrict__ dst,
+                         long ldd, double alpha, const double* dscale, int inv) {
+  double a = alpha;
+  if (dscale) a *= inv ? 1.0 / (*dscale) : (*dscale);
+  long total = (long)rows * cols;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    long i = e / cols, j = e % cols;
+    dst[i * ldd + j] = a * src[i * lds + j];
+  }
+}
+
+__global__ void k_scale_by(double* p, long n, const double* ds, int inv) {
+  double a = inv ? 1.0 / (*ds) : (*ds);
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] *= a;
+}
+
+__global__ void k_sub(const double* a, const double* b, double* o, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    o[i] = a[i] - b[i];
+}
+
+__global__ void k_check_finite(const double* x, long n, int* flag) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    if (!isfinite(x[i])) *flag = 1;
+}
+
+__global__ void k_scalar(int kind, const double* a, const double* b, double* out) {
+  double va = a ? *a : 0.0, vb = b ? *b : 0.0, r = 0.0;
+  switch (kind) {
+    case 0: r = sqrt(fmax(va + vb, 0.0)); break;
+    case 1: r = 1.0 / va; break;
+    case 2: r = va * vb; break;
+    case 3: r = va + vb; break;
+    case 4: r = -va; break;
+    case 5: r = sqrt(fmax(va, 0.0)); break;
+  }
+  *out = r;
+}
+
+// ------------------------------------------------------------------ SpMM
+constexpr int NVMAX = 16;
+
+__global__ __launch_bounds__(256) void k_spmm(int nrows, int ics, int ocs, const int* __restrict__ rowptr,
+                                              const int* __restrict__ col, const double* __restrict__ vals, int nv,
+                                              long vstride, const double* __restrict__ x, int ldx, int xcol0,
+                                              int ncols, double* __restrict__ y, int ldy, int ycol0, int yvstep,
+                                              double alpha) {
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int r = blockIdx.x * (blockDim.x / WAVE) + wave;
+  const int c = blockIdx.y;
+  if (r >= nrows) return;
+  const int t0 = rowptr[r], t1 = rowptr[r + 1];
+  const double* xb = x + (long)c * ics * ldx + xcol0;
+  double* yb = y + ((long)c * ocs + r) * ldy + ycol0;
+  for (int j0 = 0; j0 < ncols; j0 += WAVE) {
+    const int j = j0 + lane;
+    const bool act = j < ncols;
+    double acc[NVMAX];
+#pragma unroll
+    for (int v = 0; v < NVMAX; ++v) acc[v] = 0.0;
+    for (int t = t0; t < t1; ++t) {
+      const double xv = act ? xb[(long)col[t] * ldx + j] : 0.0;
+#pragma unroll
+      for (int v = 0; v < NVMAX; ++v)
+        if (v < nv) acc[v] = fma(vals[v * vstride + t], xv, acc[v]);
+    }
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < NVMAX; ++v)
+        if (v < nv) yb[v * yvstep + j] = alpha * acc[v];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ core ops
+__global__ void k_core1_op(int kind, int n1, int r, const double* __restrict__ in, int ldi, double* __restrict__ out,
+                           int ldo, int col0, double scale, const double* dscale) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= r) return;
+  double sc = scale * (dscale ? *dscale : 1.0);
+  if (kind == 0) {
+    double prev = 0.0;
+    for (int t = 0; t < n1; ++t) {
+      double v = in[(long)t * ldi + a];
+      out[(long)t * ldo + col0 + a] = sc * (v - prev);
+      prev = v;
+    }
+  } else if (kind == 1) {
+    for (int t = 0; t < n1; ++t) out[(long)t * ldo + col0 + a] = sc * in[(long)t * ldi + a];
+  } else {
+    double s = 0.0;
+    for (int t = 0; t < n1; ++t) {
+      s += in[(long)t * ldi + a];
+      out[(long)t * ldo + col0 + a] = sc * s;
+    }
+  }
+}
+
+__global__ void k_core1_diag(int n1, int r, int k, const double* __restrict__ w, int ldw, const double* __restrict__ in,
+                             int ldi, double* __restrict__ out, int ldo, int col0) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long total = (long)n1 * k * r;
+  if (e >= total) return;
+  int al = e % r;
+  long q = e / r;
+  int a = q % k;
+  int t = q / k;
+  out[(long)t * ldo + col0 + a * r + al] = w[(long)t * ldw + a] * in[(long)t * ldi + al];
+}
+
+__global__ void k_core2_block(int r1, int n2, int r2, const double* __restrict__ in, const double* __restrict__ X,
+                              int k1, int k2, double* __restrict__ out, int R1, int R2, int row0, int col0) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long total = (long)k1 * k2 * r1 * n2 * r2;
+  if (e >= total) return;
+  int be = e % r2;
+  long q = e / r2;
+  int i = q % n2;
+  q /= n2;
+  int al = q % r1;
+  q /= r1;
+  int b = q % k2;
+  int a = q / k2;
+  double s;
+  if (X == nullptr) {
+    s = in[((long)al * n2 + i) * r2 + be];
+  } else {
+    const double* Xab = X + ((long)a * k2 + b) * n2 * n2 + (long)i * n2;
+    s = 0.0;
+    for (int j = 0; j < n2; ++j) s = fma(Xab[j], in[((long)al * n2 + j) * r2 + be], s);
+  }
+  out[((long)(row0 + a * r1 + al) * n2 + i) * R2 + col0 + b * r2 + be] = s;
+}
+
+// ------------------------------------------------------------------ truncation
+constexpr int TE_THREADS = 1024;
+constexpr int KSMALL = 96;     // max rank handled by the LDS eigen solver
+
+__device__ void argmax_block(double v, int idx, double* shv, int* shi, double& bv, int& bi) {
+  // block-wide argmax (ties -> smallest index)
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    double ov = __shfl_down(v, o, WAVE);
+    int oi = __shfl_down(idx, o, WAVE);
+    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+  }
+  int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+  __syncthreads();
+  if (l == 0) { shv[w] = v; shi[w] = idx; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int nw = blockDim.x / WAVE;
+    double best = shv[0];
+    int bidx = shi[0];
+    for (int q = 1; q < nw; ++q)
+      if (shv[q] > best || (shv[q] == best && shi[q] < bidx)) { best = shv[q]; bidx = shi[q]; }
+    shv[0] = best;
+    shi[0] = bidx;
+  }
+  __syncthreads();
+  bv = shv[0];
+  bi = shi[0];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restrict__ S, double eps,
+                                                          const double* normsq_in, double* normsq_out,
+                                                          double* __restrict__ U, int kmax, double* __restrict__ L,
+                                                          double* __restrict__ dwork, int* k_out, double* kept_out,
+                                                          int* info, int rank_bound) {
+  __shared__ double T[KSMALL * KSMALL];
+  __shared__ double V[KSMALL * KSMALL];
+  __shared__ double shv[32];
+  __shared__ int shi[32];
+  __shared__ double lp[KSMALL];
+  __shared__ double rc[KSMALL / 2 + 1], rs[KSMALL / 2 + 1];
+  __shared__ int rp[KSMALL / 2 + 1], rq[KSMALL / 2 + 1];
+  __shared__ double lam[KSMALL];
+  __shared__ int order[KSMALL];
+  __shared__ int s_flag;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if (kmax > KSMALL) kmax = KSMALL;
+  // --- trace and tolerance
+  double tr = 0.0;
+  for (int i = tid; i < N; i += nth) {
+    double d = S[(long)i * N + i];
+    dwork[i] = d > 0.0 ? d : 0.0;
+    tr += dwork[i];
+  }
+  tr = block_sum(tr, shv);
+  double normsq = normsq_in ? *normsq_in : tr;
+  if (normsq_out && tid == 0) *normsq_out = tr;
+  const double delta2 = 0.5 * eps * eps * normsq;
+  const double zero_thr = 64.0 * 2.220446049250313e-16 * (tr > 0.0 ? tr : 0.0);
+  const double res_stop = delta2 * 0.0625;
+  // --- pivoted Cholesky S ~ L L^T with early stop
+  double resid = tr;
+  int kp = 0;
+  for (int j = 0; j < kmax; ++j) {
+    if (resid <= res_stop) break;
+    double bv;
+    int bi;
+    double mv = -1.0;
+    int mi = 0;
+    for (int i = tid; i < N; i += nth)
+      if (dwork[i] > mv) { mv = dwork[i]; mi = i; }
+    argmax_block(mv, mi, shv, shi, bv, bi);
+    if (bv <= zero_thr || bv <= 0.0) break;
+    const int p = bi;
+    if (tid < j) lp[tid] = L[(long)p * kmax + tid];
+    __syncthreads();
+    const double ljj = sqrt(bv);
+    for (int i = tid; i < N; i += nth) {
+      double s = S[(long)i * N + p];
+      for (int t = 0; t < j; ++t) s -= L[(long)i * kmax + t] * lp[t];
+      double lij = (i == p) ? ljj : s / ljj;
+      L[(long)i * kmax + j] = lij;
+      double d = dwork[i] - lij * lij;
+      dwork[i] = (i == p || d < 0.0) ? 0.0 : d;
+    }
+    __syncthreads();
+    double rr = 0.0;
+    for (int i = tid; i < N; i += nth) rr += dwork[i];
+    resid = block_sum(rr, shv);
+    kp = j + 1;
+  }
+  if (kp == 0) {
+    // zero (or numerically zero) matrix: rank-1 zero
+    for (int i = tid; i < N; i += nth) U[(long)i * kmax] = (i == 0) ? 1.0 : 0.0;
+    if (tid == 0) {
+      *k_out = 1;
+      *kept_out = 0.0;
+      *info = 0;
+    }
+    return;
+  }
+  if (kp == kmax && kmax < rank_bound && resid > res_stop && resid > zero_thr) {
+    if (tid == 0) *info = 1;   // rank capacity exceeded
+  } else if (tid == 0) {
+    *info = 0;
+  }
+  // --- T = L^T L (kp x kp), V = I
+  for (int e = tid; e < kp * kp; e += nth) {
+    int a = e / kp, b = e % kp;
+    double s = 0.0;
+    if (b >= a)
+      for (int i = 0; i < N; ++i) s = fma(L[(long)i * kmax + a], L[(long)i * kmax + b], s);
+    T[a * KSMALL + b] = s;
+    V[a * KSMALL + b] = (a == b) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < kp * kp; e += nth) {
+    int a = e / kp, b = e % kp;
+    if (b < a) T[a * KSMALL + b] = T[b * KSMALL + a];
+  }
+  __syncthreads();
+  // --- cyclic Jacobi (round-robin pairs)
+  const int n = kp;
+  const int np2 = n + (n & 1);
+  const int npairs = np2 / 2;
+  for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
+    if (tid == 0) s_flag = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < np2 - 1; ++rnd) {
+      if (tid < npairs) {
+        int a, b;
+        if (tid == 0) { a = np2 - 1; b = rnd; }
+        else { a = (rnd + tid) % (np2 - 1); b = (rnd - tid + (np2 - 1)) % (np2 - 1); }
+        int p = a < b ? a : b, q = a < b ? b : a;
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          double apq = T[p * KSMALL + q], app = T[p * KSMALL + p], aqq = T[q * KSMALL + q];
+          if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && apq != 0.0) {
+            double th = (aqq - app) / (2.0 * apq);
+            double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+            s_flag = 1;
+          }
+        } else {
+          q = p;   // dummy pair
+        }
+        rp[tid] = p;
+        rq[tid] = q;
+        rc[tid] = c;
+        rs[tid] = s;
+      }
+      __syncthreads();
+      // rows: T <- J^T T
+      for (int e = tid; e < npairs * n; e += nth) {
+        int pr = e / n, j = e % n;
+        int p = rp[pr], q = rq[pr];
+        if (p == q || rs[pr] == 0.0) continue;
+        double c = rc[pr], s = rs[pr];
+        double tp = T[p * KSMALL + j], tq = T[q * KSMALL + j];
+        T[p * KSMALL + j] = c * tp - s * tq;
+        T[q * KSMALL + j] = s * tp + c * tq;
+      }
+      __syncthreads();
+      // columns: T <- T J, V <- V J
+      for (int e = tid; e < npairs * n; e += nth) {
+        int pr = e / n, i = e % n;
+        int p = rp[pr], q = rq[pr];
+        if (p == q || rs[pr] == 0.0) continue;
+        double c = rc[pr], s = rs[pr];
+        double tp = T[i * KSMALL + p], tq = T[i * KSMALL + q];
+        T[i * KSMALL + p] = c * tp - s * tq;
+        T[i * KSMALL + q] = s * tp + c * tq;
+        double vp = V[i * KSMALL + p], vq = V[i * KSMALL + q];
+        V[i * KSMALL + p] = c * vp - s * vq;
+        V[i * KSMALL + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    int f = s_flag;
+    __syncthreads();
+    if (!f) break;
+  }
+  // --- sort eigenvalues descending
+  if (tid < n) lam[tid] = T[tid * KSMALL + tid] > 0.0 ? T[tid * KSMALL + tid] : 0.0;
+  __syncthreads();
+  if (tid < n) {
+    double v = lam[tid];
+    int rank = 0;
+    for (int j = 0; j < n; ++j)
+      if (lam[j] > v || (lam[j] == v && j < tid)) ++rank;
+    order[rank] = tid;
+  }
+  __syncthreads();
+  // --- rank cut: smallest k >= 1 with tail + resid <= delta2
+  if (tid == 0) {
+    int k = 0;
+    double kept = 0.0;
+    if (delta2 > 0.0) {
+      double tail = resid;
+      for (int j = 0; j < n; ++j) tail += lam[order[j]];
+      k = n;
+      for (int j = 0; j < n; ++j) {
+        tail -= lam[order[j]];
+        kept += lam[order[j]];
+        if (tail <= delta2) { k = j + 1; break; }
+      }
+    } else {
+      // exact mode: keep every numerically nonzero direction
+      for (int j = 0; j < n; ++j)
+        if (lam[order[j]] > zero_thr) { ++k; kept += lam[order[j]]; }
+      if (k == 0) k = 1;
+    }
+    shi[0] = k;
+    *k_out = k;
+    *kept_out = kept;
+  }
+  __syncthreads();
+  const int k = shi[0];
+  __syncthreads();
+  // --- U = L V_k diag(lambda^-1/2)
+  for (long e = tid; e < (long)N * k; e += nth) {
+    int i = e / k, c = e % k;
+    int oc = order[c];
+    double s = 0.0;
+    for (int a = 0; a < n; ++a) s = fma(L[(long)i * kmax + a], V[a * KSMALL + oc], s);
+    double l = lam[oc];
+    U[(long)i * kmax + c] = l > 0.0 ? s / sqrt(l) : 0.0;
+  }
+  __syncthreads();
+  // --- re-orthonormalize U (classical Gram-Schmidt, two passes); the
+  // coefficients of one column are computed one wave per coefficient.
+  const int wv = tid / WAVE, ln = tid % WAVE, nwv = nth / WAVE;
+  for (int c = 0; c < k; ++c) {
+    for (int pass = 0; pass < 2 && c > 0; ++pass) {
+      for (int d = wv; d < c; d += nwv) {
+        double s = 0.0;
+        for (int i = ln; i < N; i += WAVE) s = fma(U[(long)i * kmax + d], U[(long)i * kmax + c], s);
+        for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_down(s, o, WAVE);
+        if (ln == 0) lp[d] = s;
+      }
+      __syncthreads();
+      for (int i = tid; i < N; i += nth) {
+        double u = U[(long)i * kmax + c];
+        for (int d = 0; d < c; ++d) u -= lp[d] * U[(long)i * kmax + d];
+        U[(long)i * kmax + c] = u;
+      }
+      __syncthreads();
+    }
+    double s = 0.0;
+    for (int i = tid; i < N; i += nth) s = fma(U[(long)i * kmax + c], U[(long)i * kmax + c], s);
+    s = block_sum(s, shv);
+    double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    for (int i = tid; i < N; i += nth) U[(long)i * kmax + c] *= inv;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ block tridiagonal
+constexpr int BT_CB = 8;
+constexpr int BT_MAXBS = 256;
+
+__global__ __launch_bounds__(256) void k_blocktri(int n, int nblk, const int* __restrict__ start,
+                                                  const long* __restrict__ off_sinv, const long* __restrict__ off_p,
+                                                  const long* __restrict__ off_q, const double* __restrict__ data,
+                                                  const double* __restrict__ X, double* __restrict__ Y, int ldx,
+                                                  int ncols) {
+  __shared__ double xb[BT_MAXBS * BT_CB];
+  __shared__ double yprev[BT_MAXBS * BT_CB];
+  const int comp = blockIdx.y;
+  const int c0 = blockIdx.x * BT_CB;
+  const int nc = min(BT_CB, ncols - c0);
+  const double* Xc = X + (long)comp * n * ldx + c0;
+  double* Yc = Y + (long)comp * n * ldx + c0;
+  const int tid = threadIdx.x;
+  // forward: y_b = Sinv_b x_b - P_b y_{b-1}
+  int prevbs = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const int r0 = start[b], bs = start[b + 1] - r0;
+    for (int e = tid; e < bs * BT_CB; e += 256) {
+      int r = e % bs, c = e / bs;
+      xb[c * BT_MAXBS + r] = (c < nc) ? Xc[(long)(r0 + r) * ldx + c] : 0.0;
+    }
+    __syncthreads();
+    const double* Si = data + off_sinv[b];
+    const double* Pb = (b > 0) ? data + off_p[b] : nullptr;
+    double outv[(BT_MAXBS * BT_CB + 255) / 256];
+    int cnt = 0;
+    for (int e = tid; e < bs * BT_CB; e += 256, ++cnt) {
+      int r = e % bs, c = e / bs;
+      double s = 0.0;
+      for (int kk = 0; kk < bs; ++kk) s = fma(Si[(long)kk * bs + r], xb[c * BT_MAXBS + kk], s);
+      if (Pb)
+        for (int kk = 0; kk < prevbs; ++kk) s = fma(-Pb[(long)kk * bs + r], yprev[c * BT_MAXBS + kk], s);
+      outv[cnt] = s;
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int e = tid; e < bs * BT_CB; e += 256, ++cnt) {
+      int r = e % bs, c = e / bs;
+      yprev[c * BT_MAXBS + r] = outv[cnt];
+      if (c < nc) Yc[(long)(r0 + r) * ldx + c] = outv[cnt];
+    }
+    __syncthreads();
+    prevbs = bs;
+  }
+  // backward: x_b = y_b - Q_b x_{b+1}; yprev holds x_{b+1}
+  int nextbs = prevbs;   // block nblk-1 is final already (x = y)
+  for (int b = nblk - 2; b >= 0; --b) {
+    const int r0 = start[b], bs = start[b + 1] - r0;
+    const double* Qb = data + off_q[b];
+    double outv[(BT_MAXBS * BT_CB + 255) / 256];
+    int cnt = 0;
+    for (int e = tid; e < bs * BT_CB; e += 256, ++cnt) {
+      int r = e % bs, c = e / bs;
+      double s = (c < nc) ? Yc[(long)(r0 + r) * ldx + c] : 0.0;
+      for (int kk = 0; kk < nextbs; ++kk) s = fma(-Qb[(long)kk * bs + r], yprev[c * BT_MAXBS + kk], s);
+      outv[cnt] = s;
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int e = tid; e < bs * BT_CB; e += 256, ++cnt) {
+      int r = e % bs, c = e / bs;
+      yprev[c * BT_MAXBS + r] = outv[cnt];
+      if (c < nc) Yc[(long)(r0 + r) * ldx + c] = outv[cnt];
+    }
+    __syncthreads();
+    nextbs = bs;
+  }
+}
+
+// ------------------------------------------------------------------ small sequential kernels
+__global__ void k_hessenberg_lsq(const double* H, int ld, int k, const double* beta, double* y, double* resid) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  extern __shared__ double sm[];
+  double* Rm = sm;                 // (k+1) x k column-major, ld k+1
+  double* g = sm + (k + 1) * k;    // k+1
+  double* cs = g + (k + 1);        // k
+  double* sn = cs + k;             // k
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i <= k; ++i) Rm[j * (k + 1) + i] = (i <= j + 1) ? H[(long)j * ld + i] : 0.0;
+  for (int i = 0; i <= k; ++i) g[i] = 0.0;
+  g[0] = *beta;
+  for (int j = 0; j < k; ++j) {
+    for (int i = 0; i < j; ++i) {
+      double a = Rm[j * (k + 1) + i], b = Rm[j * (k + 1) + i + 1];
+      Rm[j * (k + 1) + i] = cs[i] * a + sn[i] * b;
+      Rm[j * (k + 1) + i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    double a = Rm[j * (k + 1) + j], b = Rm[j * (k + 1) + j + 1];
+    double r = hypot(a, b);
+    double c = (r == 0.0) ? 1.0 : a / r, s = (r == 0.0) ? 0.0 : b / r;
+    cs[j] = c;
+    sn[j] = s;
+    Rm[j * (k + 1) + j] = r;
+    Rm[j * (k + 1) + j + 1] = 0.0;
+    double ga = g[j], gb = g[j + 1];
+    g[j] = c * ga + s * gb;
+    g[j + 1] = -s * ga + c * gb;
+  }
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int j = i + 1; j < k; ++j) s -= Rm[j * (k + 1) + i] * y[j];
+    double d = Rm[i * (k + 1) + i];
+    y[i] = (d != 0.0) ? s / d : 0.0;
+  }
+  if (resid) *resid = fabs(g[k]);
+}
+
+__global__ void k_mgs_coef(int k, const double* d, const double* GV, int ldg, double* Hcol, double* coef) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  coef[0] = 1.0;
+  for (int i = 0; i < k; ++i) {
+    double h = d[i];
+    for (int j = 0; j < i; ++j) h -= Hcol[j] * GV[(long)j * ldg + i];
+    Hcol[i] = h;
+    coef[1 + i] = -h;
+  }
+}
+
+}  // namespace
+
+// ====================================================================== launchers
+void gemm(hipStream_t s, int batch, int m, int n, int k, double alpha, const double* A, long sAb, long sAi, long sAk,
+          const double* B, long sBb, long sBk, long sBj, double beta, double* C, long sCb, long sCi, long sCj,
+          int kstep, long klimit) {
+  if (m <= 0 || n <= 0 || batch <= 0) return;
+  if (k <= 0) {
+    // C = beta * C
+    dim3 grid(cdiv(n, TN), cdiv(m, TM), batch);
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, m, n, 0, alpha, A, sAb, sAi, sAk, B, sBb, sBk, sBj, beta, C,
+                       sCb, sCi, sCj, kstep, klimit);
+    return;
+  }
+  dim3 grid(cdiv(n, TN), cdiv(m, TM), batch);
+  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, m, n, k, alpha, A, sAb, sAi, sAk, B, sBb, sBk, sBj, beta, C, sCb,
+                     sCi, sCj, kstep, klimit);
+}
+
+void gram(hipStream_t s, long rows, int nx, int ny, const double* X, long sXr, long sXc, const double* Y, long sYr,
+          long sYc, double* out, double* ws, size_t ws_doubles) {
+  const long ne = (long)nx * ny;
+  long nch = std::max<long>(1, std::min<long>((rows + 511) / 512, (long)(ws_doubles / std::max<long>(ne, 1))));
+  nch = std::min<long>(nch, 2048);
+  if (rows <= 0) {
+    fill(s, out, ne, 0.0);
+    return;
+  }
+  if (nch <= 1) {
+    gemm(s, 1, nx, ny, (int)std::min<long>(rows, INT_MAX), 1.0, X, 0, sXc, sXr, Y, 0, sYr, sYc, 0.0, out, 0, ny, 1);
+    return;
+  }
+  long chunk = (rows + nch - 1) / nch;
+  nch = (rows + chunk - 1) / chunk;
+  gemm(s, (int)nch, nx, ny, (int)chunk, 1.0, X, chunk * sXr, sXc, sXr, Y, chunk * sYr, sYr, sYc, 0.0, ws, ne, ny, 1,
+       (int)chunk, rows);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(cdiv(ne, 256)), dim3(256), 0, s, (int)nch, ne, ws, out);
+}
+
+void sumsq(hipStream_t s, const double* x, long n, double* out, double* ws, size_t ws_doubles) {
+  int nb = (int)std::min<long>(std::min<long>(1024, (long)ws_doubles), std::max<long>(1, cdiv(n, 256)));
+  hipLaunchKernelGGL(k_sumsq_stage1, dim3(nb), dim3(256), 0, s, x, n, ws);
+  hipLaunchKernelGGL(k_sum_stage2, dim3(1), dim3(1024), 0, s, ws, nb, out);
+}
+
+void fill(hipStream_t s, double* p, long n, double v) {
+  if (n <= 0) return;
+  unsigned nb = std::min<unsigned>(cdiv(n, 256), 8192);
+  hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, p, n, v);
+}
+
+void copy2d(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst, long ldd, double alpha,
+            const double* dscale, int inv) {
+  long total = (long)rows * cols;
+  if (total <= 0) return;
+  unsigned nb = std::min<unsigned>(cdiv(total, 256), 8192);
+  hipLaunchKernelGGL(k_copy2d, dim3(nb), dim3(256), 0, s, rows, cols, src, lds, dst, ldd, alpha, dscale, inv);
+}
+
+void spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* rowptr, const int* col, const double* vals,
+          int nv, long vstride, const double* x, int ldx, int xcol0, int ncols, double* y, int ldy, int ycol0,
+          int yvstep, double alpha) {
+  if (nrows <= 0 || ncols <= 0 || nv <= 0) return;
+  for (int v0 = 0; v0 < nv; v0 += NVMAX) {
+    int nvb = std::min(NVMAX, nv - v0);
+    dim3 grid(cdiv(nrows, 4), ncomp);
+    hipLaunchKernelGGL(k_spmm, grid, dim3(256), 0, s, nrows, ics, ocs, rowptr, col, vals + v0 * vstride, nvb, vstride,
+                       x, ldx, xcol0, ncols, y, ldy, ycol0 + v0 * yvstep, yvstep, alpha);
+  }
+}
+
+void core1_op(hipStream_t s, int kind, int n1, int r, const double* in, int ldi, double* out, int ldo, int col0,
+              double scale, const double* dscale) {
+  if (r <= 0) return;
+  hipLaunchKernelGGL(k_core1_op, dim3(cdiv(r, 64)), dim3(64), 0, s, kind, n1, r, in, ldi, out, ldo, col0, scale,
+                     dscale);
+}
+
+void core1_diag(hipStream_t s, int n1, int r, int k, const double* w, int ldw, const double* in, int ldi, double* out,
+                int ldo, int col0) {
+  long total = (long)n1 * k * r;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_core1_diag, dim3(cdiv(total, 256)), dim3(256), 0, s, n1, r, k, w, ldw, in, ldi, out, ldo, col0);
+}
+
+void core2_block(hipStream_t s, int r1, int n2, int r2, const double* in, const double* X, int k1, int k2, double* out,
+                 int R1, int R2, int row0, int col0) {
+  long total = (long)k1 * k2 * r1 * n2 * r2;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_core2_block, dim3(cdiv(total, 256)), dim3(256), 0, s, r1, n2, r2, in, X, k1, k2, out, R1, R2,
+                     row0, col0);
+}
+
+void trunc_eig(hipStream_t s, int N, double* S, double eps, const double* normsq_in, double* normsq_out, double* U,
+               int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound) {
+  // dwork: N doubles placed after L (caller sizes L as N*kmax + N)
+  double* dwork = L + (long)N * kmax;
+  hipLaunchKernelGGL(k_trunc_eig, dim3(1), dim3(TE_THREADS), 0, s, N, S, eps, normsq_in, normsq_out, U, kmax, L, dwork,
+                     k_out, kept_out, info, rank_bound);
+}
+
+void blocktri_solve(hipStream_t s, int n, int nblk, int maxbs, const int* start, const long* off_sinv, const long* off_p,
+                    const long* off_q, const double* data, int ncomp, double* X, int ldx, int ncols, double* Y) {
+  if (ncols <= 0) return;
+  (void)maxbs;
+  dim3 grid(cdiv(ncols, BT_CB), ncomp);
+  hipLaunchKernelGGL(k_blocktri, grid, dim3(256), 0, s, n, nblk, start, off_sinv, off_p, off_q, data, X, Y, ldx, ncols);
+}
+
+void hessenberg_lsq(hipStream_t s, const double* H, int ld, int k, const double* beta, double* y, double* resid) {
+  size_t shm = sizeof(double) * ((size_t)(k + 1) * k + (k + 1) + 2 * k);
+  hipLaunchKernelGGL(k_hessenberg_lsq, dim3(1), dim3(64), shm, s, H, ld, k, beta, y, resid);
+}
+
+void mgs_coef(hipStream_t s, int k, const double* d, const double* GV, int ldg, double* Hcol, double* coef) {
+  hipLaunchKernelGGL(k_mgs_coef, dim3(1), dim3(64), 0, s, k, d, GV, ldg, Hcol, coef);
+}
+
+void scalar_op(hipStream_t s, int kind, const double* a, const double* b, double* out) {
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(1), 0, s, kind, a, b, out);
+}
+
+void dot_reduce(hipStream_t s, long n, const double* w, const double* k, double* out, int accumulate) {
+  hipLaunchKernelGGL(k_dot_reduce, dim3(1), dim3(1024), 0, s, n, w, k, out, accumulate);
+}
+
+void scale_by(hipStream_t s, double* p, long n, const double* dscale, int inv) {
+  if (n <= 0) return;
+  unsigned nb = std::min<unsigned>(cdiv(n, 256), 8192);
+  hipLaunchKernelGGL(k_scale_by, dim3(nb), dim3(256), 0, s, p, n, dscale, inv);
+}
+
+void sub_arrays(hipStream_t s, const double* a, const double* b, double* out, long n) {
+  unsigned nb = std::min<unsigned>(cdiv(n, 256), 8192);
+  hipLaunchKernelGGL(k_sub, dim3(nb), dim3(256), 0, s, a, b, out, n);
+}
+
+void check_finite(hipStream_t s, const double* x, long n, int* flag) {
+  if (n <= 0) return;
+  unsigned nb = std::min<unsigned>(cdiv(n, 256), 8192);
+  hipLaunchKernelGGL(k_check_finite, dim3(nb), dim3(256), 0, s, x, n, flag);
+}
+
+}  // namespace sgtt

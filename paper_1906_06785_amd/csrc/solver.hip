@@ -1,0 +1,1158 @@
+// Picard-step system, operator, mean-based LSC preconditioner, low-rank
+// flexible GMRES with refinement, and the C ABI (include/sgtt.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/sgtt.h"
+#include "host_setup.h"
+#include "kernels.h"
+#include "tt_core.h"
+
+using namespace sgtt;
+
+// ====================================================================== context
+struct sgtt_context {
+  int device = 0;
+  bool own_stream = false;
+  std::string err;
+  Ctx c;
+};
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <class T>
+T* dev_upload(Ctx& c, const std::vector<T>& h) {
+  T* p = nullptr;
+  size_t n = std::max<size_t>(h.size(), 1);
+  SGTT_HIP(hipMalloc(&p, n * sizeof(T)));
+  if (!h.empty()) SGTT_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c.s));
+  return p;
+}
+
+struct DevCsr {
+  int nrows = 0, ncols = 0, nnz = 0, nv = 0;
+  int *rowptr = nullptr, *col = nullptr;
+  double* vals = nullptr;   // nv value arrays of nnz each
+  void free_all() {
+    (void)hipFree(rowptr);
+    (void)hipFree(col);
+    (void)hipFree(vals);
+    rowptr = col = nullptr;
+    vals = nullptr;
+  }
+};
+
+DevCsr upload_csr(Ctx& c, const Csr& pat, const std::vector<const double*>& valsets) {
+  DevCsr d;
+  d.nrows = pat.nrows;
+  d.ncols = pat.ncols;
+  d.nnz = pat.nnz();
+  d.nv = (int)valsets.size();
+  d.rowptr = dev_upload(c, pat.rowptr);
+  d.col = dev_upload(c, pat.col);
+  std::vector<double> all((size_t)d.nnz * std::max(d.nv, 1));
+  for (int v = 0; v < d.nv; ++v) std::copy(valsets[v], valsets[v] + d.nnz, all.begin() + (size_t)v * d.nnz);
+  d.vals = dev_upload(c, all);
+  return d;
+}
+
+struct DevBT {
+  int n = 0, nblk = 0, maxbs = 0;
+  int* start = nullptr;
+  long *off_sinv = nullptr, *off_p = nullptr, *off_q = nullptr;
+  double* data = nullptr;
+  void free_all() {
+    (void)hipFree(start);
+    (void)hipFree(off_sinv);
+    (void)hipFree(off_p);
+    (void)hipFree(off_q);
+    (void)hipFree(data);
+  }
+};
+
+DevBT upload_bt(Ctx& c, const BlockTri& bt) {
+  DevBT d;
+  d.n = bt.n;
+  d.nblk = bt.nblk;
+  d.maxbs = bt.maxbs;
+  if (bt.maxbs > 256) throw SgttError(-6, "block-tridiagonal block too large");
+  d.start = dev_upload(c, bt.start);
+  std::vector<long> a(bt.off_sinv.begin(), bt.off_sinv.end()), b(bt.off_p.begin(), bt.off_p.end()),
+      q(bt.off_q.begin(), bt.off_q.end());
+  d.off_sinv = dev_upload(c, a);
+  d.off_p = dev_upload(c, b);
+  d.off_q = dev_upload(c, q);
+  d.data = dev_upload(c, bt.data);
+  return d;
+}
+
+}  // namespace
+
+// ====================================================================== system
+struct sgtt_system {
+  sgtt_context* ctx = nullptr;
+  HostProblem hp;
+  sgtt_problem_desc desc{};
+  int nt = 0, nxi = 0, ns = 0, nu = 0, np = 0, nall = 0;
+  double tau = 0, nu0 = 0;
+  // operator data
+  DevCsr Kop;       // free x free scalar pattern: [M, A, N_1..N_k2]
+  DevCsr Bd, Btd;   // B (n_p x n_u), B^T (n_u x n_p)
+  DevCsr Xmid;      // pressure pattern: [XM, XA, XN_1..XN_k2]
+  double* Gnu = nullptr;   // n_xi x n_xi
+  int k1 = 0, k2 = 0;      // convection TT-operator ranks (0: Stokes)
+  double* w1 = nullptr;    // nt x k1
+  double* Hw = nullptr;    // k1 x k2 x nxi x nxi
+  double* omega = nullptr; // nt x k2 (mean-mode time factors)
+  DevBT Fbt, Xbt;          // F_avg and X = B M*^-1 B^T factorizations
+  TT bu, bp;               // right-hand side
+  double setup_s = 0;
+  // solve scratch (device scalars)
+  double* dsc = nullptr;   // 32768 doubles: outer GMRES [0,16384), inner [16384,30000), residual [30000,)
+  ~sgtt_system() {
+    Kop.free_all();
+    Bd.free_all();
+    Btd.free_all();
+    Xmid.free_all();
+    Fbt.free_all();
+    Xbt.free_all();
+    for (double* p : {Gnu, w1, Hw, omega, dsc}) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+// ---------------------------------------------------------------- operators
+// L applied to (u, p): velocity part (eq. 3.12 with eq. 4.4 and eq. 4.12)
+TT apply_velocity(sgtt_system& S, const TT& u, const TT& p) {
+  Ctx& c = S.ctx->c;
+  const int r1u = u.r1, r2u = u.r2, r1p = p.r1, r2p = p.r2, k1 = S.k1, k2 = S.k2;
+  const int R1 = 2 * r1u + k1 * r1u + r1p, R2 = 2 * r2u + k2 * r2u + r2p;
+  TT o = tt_new(c, S.nt, S.nxi, S.nu, R1, R2);
+  // core 1: [(I - C)/tau u1 | u1 | diag(w1_a) u1 | p1]
+  core1_op(c.s, 0, S.nt, r1u, u.c1, r1u, o.c1, R1, 0, 1.0 / S.tau);
+  core1_op(c.s, 1, S.nt, r1u, u.c1, r1u, o.c1, R1, r1u, 1.0);
+  if (k1) core1_diag(c.s, S.nt, r1u, k1, S.w1, k1, u.c1, r1u, o.c1, R1, 2 * r1u);
+  core1_op(c.s, 1, S.nt, r1p, p.c1, r1p, o.c1, R1, 2 * r1u + k1 * r1u, 1.0);
+  // core 2: blocks [u2 ; G_nu u2 ; (sum_l w2(a,l,b) H_l) u2 ; p2]
+  fill(c.s, o.c2, o.n_c2(), 0.0);
+  core2_block(c.s, r1u, S.nxi, r2u, u.c2, nullptr, 1, 1, o.c2, R1, R2, 0, 0);
+  core2_block(c.s, r1u, S.nxi, r2u, u.c2, S.Gnu, 1, 1, o.c2, R1, R2, r1u, r2u);
+  if (k1) core2_block(c.s, r1u, S.nxi, r2u, u.c2, S.Hw, k1, k2, o.c2, R1, R2, 2 * r1u, 2 * r2u);
+  core2_block(c.s, r1p, S.nxi, r2p, p.c2, nullptr, 1, 1, o.c2, R1, R2, 2 * r1u + k1 * r1u, 2 * r2u + k2 * r2u);
+  // core 3: [M u3 | A u3 | N_b u3 | B^T p3]
+  spmm(c.s, S.ns, 2, S.ns, S.ns, S.Kop.rowptr, S.Kop.col, S.Kop.vals, 2 + k2, S.Kop.nnz, u.c3, r2u, 0, r2u, o.c3,
+       R2, 0, r2u, 1.0);
+  spmm(c.s, S.nu, 1, 0, 0, S.Btd.rowptr, S.Btd.col, S.Btd.vals, 1, 0, p.c3, r2p, 0, r2p, o.c3, R2,
+       2 * r2u + k2 * r2u, 0, 1.0);
+  return o;
+}
+
+TT apply_pressure(sgtt_system& S, const TT& u) {
+  Ctx& c = S.ctx->c;
+  TT o = tt_new(c, S.nt, S.nxi, S.np, u.r1, u.r2);
+  SGTT_HIP(hipMemcpyAsync(o.c1, u.c1, sizeof(double) * u.n_c1(), hipMemcpyDeviceToDevice, c.s));
+  SGTT_HIP(hipMemcpyAsync(o.c2, u.c2, sizeof(double) * u.n_c2(), hipMemcpyDeviceToDevice, c.s));
+  spmm(c.s, S.np, 1, 0, 0, S.Bd.rowptr, S.Bd.col, S.Bd.vals, 1, 0, u.c3, u.r2, 0, u.r2, o.c3, u.r2, 0, 0, 1.0);
+  return o;
+}
+
+Vec apply_L(sgtt_system& S, const Vec& x) {
+  Vec y;
+  y.nc = 2;
+  y.c[0] = apply_velocity(S, x.c[0], x.c[1]);
+  y.c[1] = apply_pressure(S, x.c[0]);
+  return y;
+}
+
+// Kronecker sum with the mean structure of eq. 5.20-5.21:
+//   tau^-1 (I - C) (x) I (x) K_0 + nu0 I (x) I (x) K_1 + sum_b diag(omega_b) (x) I (x) K_{2+b}
+// on a pattern with value sets [K_0, K_1, K_2..]: used for F_0 + C (velocity,
+// two components) and for B M*^-1 (F_0 + C) M*^-1 B^T (pressure).
+TT apply_mean_sum(sgtt_system& S, const TT& x, const DevCsr& K, int ncomp, int ncs) {
+  Ctx& c = S.ctx->c;
+  const int r1 = x.r1, r2 = x.r2, k2 = S.k2;
+  const int R1 = (2 + k2) * r1, R2 = (2 + k2) * r2;
+  TT o = tt_new(c, S.nt, S.nxi, x.n3, R1, R2);
+  core1_op(c.s, 0, S.nt, r1, x.c1, r1, o.c1, R1, 0, 1.0 / S.tau);
+  core1_op(c.s, 1, S.nt, r1, x.c1, r1, o.c1, R1, r1, S.nu0);
+  if (k2) core1_diag(c.s, S.nt, r1, k2, S.omega, k2, x.c1, r1, o.c1, R1, 2 * r1);
+  fill(c.s, o.c2, o.n_c2(), 0.0);
+  for (int b = 0; b < 2 + k2; ++b) core2_block(c.s, r1, S.nxi, r2, x.c2, nullptr, 1, 1, o.c2, R1, R2, b * r1, b * r2);
+  spmm(c.s, ncs, ncomp, ncs, ncs, K.rowptr, K.col, K.vals, 2 + k2, K.nnz, x.c3, r2, 0, r2, o.c3, R2, 0, r2, 1.0);
+  return o;
+}
+
+// spatial solve along the space core: out = A^-1 x3 (ranks unchanged)
+TT space_solve(sgtt_system& S, const TT& x, const DevBT& bt, int ncomp, double c1scale) {
+  Ctx& c = S.ctx->c;
+  TT o = tt_new(c, x.n1, x.n2, x.n3, x.r1, x.r2);
+  copy2d(c.s, x.n1, x.r1, x.c1, x.r1, o.c1, x.r1, c1scale, nullptr, 0);
+  SGTT_HIP(hipMemcpyAsync(o.c2, x.c2, sizeof(double) * x.n_c2(), hipMemcpyDeviceToDevice, c.s));
+  blocktri_solve(c.s, bt.n, bt.nblk, bt.maxbs, bt.start, bt.off_sinv, bt.off_p, bt.off_q, bt.data, ncomp, x.c3, x.r2,
+                 x.r2, o.c3);
+  return o;
+}
+
+// M^-1 = (I - C)^-1 (x) I (x) F_avg^-1 (eq. 5.23): prefix sum in time,
+// F_avg solve on both velocity components of core 3
+TT apply_Minv(sgtt_system& S, const TT& u) {
+  Ctx& c = S.ctx->c;
+  TT o = tt_new(c, u.n1, u.n2, u.n3, u.r1, u.r2);
+  core1_op(c.s, 2, S.nt, u.r1, u.c1, u.r1, o.c1, u.r1, 0, 1.0);
+  SGTT_HIP(hipMemcpyAsync(o.c2, u.c2, sizeof(double) * u.n_c2(), hipMemcpyDeviceToDevice, c.s));
+  blocktri_solve(c.s, S.Fbt.n, S.Fbt.nblk, S.Fbt.maxbs, S.Fbt.start, S.Fbt.off_sinv, S.Fbt.off_p, S.Fbt.off_q,
+                 S.Fbt.data, 2, u.c3, u.r2, u.r2, o.c3);
+  return o;
+}
+
+// ---------------------------------------------------------------- vector helpers
+Vec vec_round(Ctx& c, const Vec& x, double eps, double* d_normsq, double* d_kept) {
+  // d_normsq / d_kept: device arrays of 2 (per component), may be null
+  Vec y;
+  y.nc = x.nc;
+  for (int i = 0; i < x.nc; ++i)
+    y.c[i] = tt_round(c, x.c[i], eps, d_normsq ? d_normsq + i : nullptr, d_kept ? d_kept + i : nullptr);
+  return y;
+}
+
+Vec vec_concat(Ctx& c, const std::vector<const Vec*>& xs, const double* dcoef, const std::vector<double>& hcoef) {
+  Vec y;
+  y.nc = xs[0]->nc;
+  for (int i = 0; i < y.nc; ++i) {
+    std::vector<const TT*> parts;
+    for (auto* v : xs) parts.push_back(&v->c[i]);
+    y.c[i] = tt_concat(c, parts, dcoef, hcoef);
+  }
+  return y;
+}
+
+void vec_dot(Ctx& c, const Vec& x, const Vec& y, double* dout) {
+  for (int i = 0; i < x.nc; ++i) tt_dot(c, x.c[i], y.c[i], dout, i > 0);
+}
+
+Vec vec_copy(Ctx& c, const Vec& x) {
+  Vec y;
+  y.nc = x.nc;
+  for (int i = 0; i < x.nc; ++i) y.c[i] = tt_copy(c, x.c[i]);
+  return y;
+}
+
+Vec vec_scale3(Ctx& c, Vec&& x, const double* ds, int inv) {
+  for (int i = 0; i < x.nc; ++i) tt_scale3(c, x.c[i], ds, inv);
+  return std::move(x);
+}
+
+double read_double(Ctx& c, const double* d) {
+  SGTT_HIP(hipMemcpyAsync(c.hdbl, d, sizeof(double), hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  return c.hdbl[0];
+}
+
+// ---------------------------------------------------------------- Alg. 4.2
+struct Space {
+  virtual Vec apply(const Vec&) = 0;
+  virtual Vec precond(const Vec&) = 0;
+  virtual ~Space() = default;
+};
+
+struct SolveCounters {
+  int inner = 0, outer = 0;
+  int maxr_u = 0, maxr_p = 0;
+  double t_apply = 0, t_round = 0, t_prec = 0;
+  int verbose = 0;
+};
+
+// Low-rank flexible GMRES (Alg. 4.2) with z_0 = 0.  dscal: device scratch of
+// at least (maxit+2)^2 * 2 + 16 * (maxit+2) doubles.
+Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int maxit, double* dscal, int& iters,
+                   double& relres, SolveCounters* cnt, const char* tag) {
+  const int ld = maxit + 1;
+  double* H = dscal;                          // ld x maxit, column-major
+  double* GV = H + (size_t)ld * maxit;        // ld x ld
+  double* d = GV + (size_t)ld * ld;           // ld
+  double* coef = d + ld;                      // ld + 1
+  double* y = coef + ld + 1;                  // maxit
+  double* sc = y + maxit;                     // 16 scalars
+  fill(c.s, H, (long)ld * maxit, 0.0);
+  // line 1: s_0 = T(b), beta = ||s_0||, v_1 = s_0 / beta
+  Vec s = vec_round(c, b, eps, sc + 0, sc + 2);
+  scalar_op(c.s, 0, sc + 0, b.nc > 1 ? sc + 1 : nullptr, sc + 4);   // ||b||
+  scalar_op(c.s, 0, sc + 2, b.nc > 1 ? sc + 3 : nullptr, sc + 5);   // beta
+  SGTT_HIP(hipMemcpyAsync(c.hdbl, sc + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  const double bnorm = c.hdbl[0], beta = c.hdbl[1];
+  iters = 0;
+  relres = bnorm > 0 ? beta / bnorm : 0.0;
+  std::vector<Vec> V, Vh;
+  if (beta == 0.0) {
+    Vec z = vec_copy(c, s);
+    return z;
+  }
+  V.push_back(vec_scale3(c, std::move(s), sc + 5, 1));
+  vec_dot(c, V[0], V[0], GV);
+  Vec z;
+  double res = beta;
+  int k = 0;
+  while (res > tol * bnorm && k < maxit) {
+    ++k;
+    double t0 = now_s();
+    Vec vh = sp.precond(V[k - 1]);
+    double t1 = now_s();
+    if (cnt) cnt->t_prec += t1 - t0;
+    Vec x = vec_round(c, sp.apply(vh), eps, nullptr, nullptr);
+    Vh.push_back(std::move(vh));
+    for (int i = 0; i < k; ++i) vec_dot(c, x, V[i], d + i);
+    mgs_coef(c.s, k, d, GV, ld, H + (size_t)(k - 1) * ld, coef);
+    std::vector<const Vec*> parts{&x};
+    for (int i = 0; i < k; ++i) parts.push_back(&V[i]);
+    Vec xx = vec_concat(c, parts, coef, {});
+    Vec vn = vec_round(c, xx, eps, sc + 6, nullptr);
+    scalar_op(c.s, 0, sc + 6, V[0].nc > 1 ? sc + 7 : nullptr, H + (size_t)(k - 1) * ld + k);   // h_{k+1,k}
+    double hk = read_double(c, H + (size_t)(k - 1) * ld + k);
+    bool breakdown = !(hk > 1e-14 * beta);
+    if (!breakdown) {
+      V.push_back(vec_scale3(c, std::move(vn), H + (size_t)(k - 1) * ld + k, 1));
+      for (int i = 0; i <= k; ++i) {
+        vec_dot(c, V[k], V[i], GV + (size_t)i * ld + k);
+        if (i < k)
+          SGTT_HIP(hipMemcpyAsync(GV + (size_t)k * ld + i, GV + (size_t)i * ld + k, sizeof(double),
+                                  hipMemcpyDeviceToDevice, c.s));
+      }
+    }
+    hessenberg_lsq(c.s, H, ld, k, sc + 5, y, sc + 8);
+    std::vector<const Vec*> hp;
+    for (int i = 0; i < k; ++i) hp.push_back(&Vh[i]);
+    Vec zz = vec_concat(c, hp, y, {});
+    z = vec_round(c, zz, eps, nullptr, nullptr);
+    double t2 = now_s();
+    Vec Lz = sp.apply(z);
+    if (cnt) cnt->t_apply += now_s() - t2;
+    Vec ss = vec_concat(c, {&b, &Lz}, nullptr, {1.0, -1.0});
+    Vec sk = vec_round(c, ss, eps, nullptr, sc + 9);
+    scalar_op(c.s, 0, sc + 9, b.nc > 1 ? sc + 10 : nullptr, sc + 11);
+    res = read_double(c, sc + 11);
+    if (cnt) {
+      for (int i = 0; i < V[0].nc; ++i) {
+        int r2 = V.back().c[i].r2;
+        if (i == 0) cnt->maxr_u = std::max(cnt->maxr_u, r2);
+        else cnt->maxr_p = std::max(cnt->maxr_p, r2);
+      }
+    }
+    if (cnt && cnt->verbose)
+      fprintf(stderr, "[sgtt %s] it %d  rel %.3e  ranks v=(%d,%d) z=(%d,%d)\n", tag, k, res / bnorm, V.back().c[0].r1,
+              V.back().c[0].r2, z.c[0].r1, z.c[0].r2);
+    if (breakdown) break;
+  }
+  iters = k;
+  relres = res / bnorm;
+  if (k == 0) z = vec_copy(c, V[0]);
+  return z;
+}
+
+// ---------------------------------------------------------------- preconditioner
+struct InnerSpace : Space {
+  sgtt_system& S;
+  explicit InnerSpace(sgtt_system& s) : S(s) {}
+  Vec apply(const Vec& x) override {
+    Vec y;
+    y.nc = 1;
+    y.c[0] = apply_mean_sum(S, x.c[0], S.Kop, 2, S.ns);
+    return y;
+  }
+  Vec precond(const Vec& x) override {
+    Vec y;
+    y.nc = 1;
+    y.c[0] = apply_Minv(S, x.c[0]);
+    return y;
+  }
+};
+
+struct PrecOpts {
+  double eps = 1e-6, inner_tol = 1e-1, inner_eps = 1e-3;
+  int inner_maxit = 20;
+};
+
+Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCounters* cnt) {
+  Ctx& c = S.ctx->c;
+  const TT& yu = y.c[0];
+  const TT& yp = y.c[1];
+  // p^ = -X^-1 [B M*^-1 (F_0 + C) M*^-1 B^T] X^-1 y_p   (eq. 5.19)
+  TT t1 = space_solve(S, yp, S.Xbt, 1, 1.0);
+  TT t2 = apply_mean_sum(S, t1, S.Xmid, 1, S.np);
+  TT t3 = tt_round(c, t2, po.eps, nullptr, nullptr);
+  TT ph = space_solve(S, t3, S.Xbt, 1, -1.0);
+  // right-hand side of the (1,1) solve: y_u - B^T p^
+  TT bph = tt_new(c, S.nt, S.nxi, S.nu, ph.r1, ph.r2);
+  copy2d(c.s, S.nt, ph.r1, ph.c1, ph.r1, bph.c1, ph.r1, -1.0, nullptr, 0);
+  SGTT_HIP(hipMemcpyAsync(bph.c2, ph.c2, sizeof(double) * ph.n_c2(), hipMemcpyDeviceToDevice, c.s));
+  spmm(c.s, S.nu, 1, 0, 0, S.Btd.rowptr, S.Btd.col, S.Btd.vals, 1, 0, ph.c3, ph.r2, 0, ph.r2, bph.c3, ph.r2, 0, 0,
+       1.0);
+  Vec rhs;
+  rhs.nc = 1;
+  rhs.c[0] = tt_concat(c, {&yu, &bph}, nullptr, {});
+  // inner low-rank GMRES on (F_0 + C) v = rhs, preconditioned by M (eq. 5.22-5.23)
+  InnerSpace isp(S);
+  int its = 0;
+  double rr = 0;
+  Vec v = lowrank_fgmres(c, isp, rhs, po.inner_tol, po.inner_eps, po.inner_maxit, S.dsc + 16384, its, rr, nullptr,
+                         "inner");
+  if (cnt) cnt->inner += its;
+  Vec out;
+  out.nc = 2;
+  out.c[0] = std::move(v.c[0]);
+  out.c[1] = std::move(ph);
+  return out;
+}
+
+struct OuterSpace : Space {
+  sgtt_system& S;
+  PrecOpts po;
+  SolveCounters* cnt;
+  OuterSpace(sgtt_system& s, const PrecOpts& p, SolveCounters* c) : S(s), po(p), cnt(c) {}
+  Vec apply(const Vec& x) override { return apply_L(S, x); }
+  Vec precond(const Vec& x) override { return lsc_precondition(S, x, po, cnt); }
+};
+
+// exact ||b - L z|| / ||b|| in full format
+double full_residual(sgtt_system& S, const Vec& b, const Vec& z, double* d_out_sq, Vec* r_tt, double eps_tt,
+                     double* bnorm_cache) {
+  Ctx& c = S.ctx->c;
+  Vec Lz = apply_L(S, z);
+  Vec r = vec_concat(c, {&b, &Lz}, nullptr, {1.0, -1.0});
+  double tot = 0.0, bn2 = bnorm_cache ? *bnorm_cache : -1.0;
+  double* ws = c.scratch(1 << 16);
+  double* sq = S.dsc + 30000;
+  double res_sq[2] = {0, 0};
+  std::vector<TT> rt(2);
+  for (int i = 0; i < 2; ++i) {
+    const TT& ri = r.c[i];
+    long n = (long)ri.n1 * ri.n2 * ri.n3;
+    double* full = c.pool.get(n);
+    tt_expand(c, ri, full);
+    sumsq(c.s, full, n, sq + i, ws, 1 << 16);
+    if (r_tt) rt[i] = tt_from_full(c, full, ri.n1, ri.n2, ri.n3, eps_tt, nullptr);
+    if (bn2 < 0) {
+      tt_expand(c, b.c[i], full);
+      sumsq(c.s, full, n, sq + 2 + i, ws, 1 << 16);
+    }
+    c.pool.put(full);
+  }
+  SGTT_HIP(hipMemcpyAsync(c.hdbl, sq, 4 * sizeof(double), hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  res_sq[0] = c.hdbl[0];
+  res_sq[1] = c.hdbl[1];
+  if (bn2 < 0) {
+    bn2 = c.hdbl[2] + c.hdbl[3];
+    if (bnorm_cache) *bnorm_cache = bn2;
+  }
+  tot = res_sq[0] + res_sq[1];
+  if (d_out_sq) *d_out_sq = tot;
+  if (r_tt) {
+    r_tt->nc = 2;
+    r_tt->c[0] = std::move(rt[0]);
+    r_tt->c[1] = std::move(rt[1]);
+  }
+  return bn2 > 0 ? std::sqrt(tot / bn2) : 0.0;
+}
+
+// ---------------------------------------------------------------- helpers for the ABI
+Vec vec_from_pair(const sgtt_tt_pair* p) {
+  Vec v;
+  v.nc = 2;
+  v.c[0] = tt_view(p->u.n1, p->u.n2, p->u.n3, p->u.r1, p->u.r2, p->u.core1, p->u.core2, p->u.core3);
+  v.c[1] = tt_view(p->p.n1, p->p.n2, p->p.n3, p->p.r1, p->p.r2, p->p.core1, p->p.core2, p->p.core3);
+  return v;
+}
+
+void check_tt(const sgtt_tt& t, int n1, int n2, int n3) {
+  if (t.n1 != n1 || t.n2 != n2 || t.n3 != n3) throw SgttError(-1, "TT dimensions do not match the system");
+  if (t.r1 < 1 || t.r2 < 1 || t.r1 > t.cap1 || t.r2 > t.cap2 || !t.core1 || !t.core2 || !t.core3)
+    throw SgttError(-1, "invalid TT ranks or buffers");
+}
+
+void write_tt(Ctx& c, const TT& x, sgtt_tt* out) {
+  if (x.r1 > out->cap1 || x.r2 > out->cap2)
+    throw SgttError(-4, "result rank (" + std::to_string(x.r1) + "," + std::to_string(x.r2) +
+                            ") exceeds output capacity (" + std::to_string(out->cap1) + "," +
+                            std::to_string(out->cap2) + ")");
+  SGTT_HIP(hipMemcpyAsync(out->core1, x.c1, sizeof(double) * x.n_c1(), hipMemcpyDeviceToDevice, c.s));
+  SGTT_HIP(hipMemcpyAsync(out->core2, x.c2, sizeof(double) * x.n_c2(), hipMemcpyDeviceToDevice, c.s));
+  SGTT_HIP(hipMemcpyAsync(out->core3, x.c3, sizeof(double) * x.n_c3(), hipMemcpyDeviceToDevice, c.s));
+  out->r1 = x.r1;
+  out->r2 = x.r2;
+}
+
+void write_pair(Ctx& c, const Vec& v, sgtt_tt_pair* out) {
+  if (v.c[0].r1 > out->u.cap1 || v.c[0].r2 > out->u.cap2 || v.c[1].r1 > out->p.cap1 || v.c[1].r2 > out->p.cap2)
+    throw SgttError(-4, "result rank exceeds output capacity");
+  write_tt(c, v.c[0], &out->u);
+  write_tt(c, v.c[1], &out->p);
+}
+
+PrecOpts prec_opts(const sgtt_solve_opts* o) {
+  PrecOpts p;
+  if (o) {
+    p.eps = o->eps_krylov;
+    p.inner_tol = o->inner_tol;
+    p.inner_eps = o->inner_eps;
+    p.inner_maxit = o->inner_maxit;
+  }
+  return p;
+}
+
+sgtt_solve_opts default_opts() {
+  sgtt_solve_opts o;
+  o.tol = 1e-8;
+  o.eps_krylov = 1e-6;
+  o.tol_cycle = 1e-4;
+  o.restart = 30;
+  o.max_cycles = 8;
+  o.inner_tol = 1e-1;
+  o.inner_eps = 1e-3;
+  o.inner_maxit = 20;
+  o.verbose = 0;
+  return o;
+}
+
+// ---------------------------------------------------------------- assembly
+void build_convection(sgtt_system& S, Ctx& c, const TT& wtil) {
+  // w~ (all-node velocity TT) -> host: N(w3_b) values, Hw, omega, avg coefficients
+  HostProblem& hp = S.hp;
+  const int nall = S.nall, nxi = S.nxi, nt = S.nt;
+  const int k1 = wtil.r1, k2 = wtil.r2;
+  std::vector<double> h1((size_t)nt * k1), h2((size_t)k1 * nxi * k2), h3((size_t)2 * nall * k2);
+  SGTT_HIP(hipMemcpyAsync(h1.data(), wtil.c1, h1.size() * 8, hipMemcpyDeviceToHost, c.s));
+  SGTT_HIP(hipMemcpyAsync(h2.data(), wtil.c2, h2.size() * 8, hipMemcpyDeviceToHost, c.s));
+  SGTT_HIP(hipMemcpyAsync(h3.data(), wtil.c3, h3.size() * 8, hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  S.k1 = k1;
+  S.k2 = k2;
+  const int nnz = hp.Kff.nnz(), nnzx = hp.Xmid.nnz();
+  std::vector<std::vector<double>> Nv(k2, std::vector<double>(nnz)), XNv(k2, std::vector<double>(nnzx));
+  std::vector<double> w1(nall), w2(nall);
+  for (int b = 0; b < k2; ++b) {
+    for (int i = 0; i < nall; ++i) {
+      w1[i] = h3[(size_t)i * k2 + b];
+      w2[i] = h3[(size_t)(nall + i) * k2 + b];
+    }
+    convection_values(hp, w1.data(), w2.data(), Nv[b].data(), nullptr);
+    lsc_middle_values(hp, Nv[b].data(), XNv[b].data());
+  }
+  // Hw[a,b] = sum_l w2(a,l,b) H_l ; omega[t,b] = sum_a w1[t,a] w2(a,0,b)
+  std::vector<double> Hw((size_t)k1 * k2 * nxi * nxi, 0.0), om((size_t)nt * k2, 0.0), avg(k2, 0.0);
+  for (int a = 0; a < k1; ++a)
+    for (int b = 0; b < k2; ++b)
+      for (int l = 0; l < nxi; ++l) {
+        double wv = h2[((size_t)a * nxi + l) * k2 + b];
+        if (wv == 0.0) continue;
+        const double* Hl = hp.H.data() + (size_t)l * nxi * nxi;
+        double* dst = Hw.data() + ((size_t)a * k2 + b) * nxi * nxi;
+        for (int q = 0; q < nxi * nxi; ++q) dst[q] += wv * Hl[q];
+      }
+  for (int t = 0; t < nt; ++t)
+    for (int b = 0; b < k2; ++b) {
+      double s = 0;
+      for (int a = 0; a < k1; ++a) s += h1[(size_t)t * k1 + a] * h2[((size_t)a * nxi + 0) * k2 + b];
+      om[(size_t)t * k2 + b] = s;
+      avg[b] += s / nt;
+    }
+  S.w1 = dev_upload(c, h1);
+  S.Hw = dev_upload(c, Hw);
+  S.omega = dev_upload(c, om);
+  // operator value sets
+  std::vector<const double*> vs{hp.Mff.data(), hp.Aff.data()};
+  for (int b = 0; b < k2; ++b) vs.push_back(Nv[b].data());
+  S.Kop = upload_csr(c, hp.Kff, vs);
+  std::vector<const double*> xs{hp.XM.data(), hp.XA.data()};
+  for (int b = 0; b < k2; ++b) xs.push_back(XNv[b].data());
+  S.Xmid = upload_csr(c, hp.Xmid, xs);
+  // F_avg = tau^-1 M + nu0 A + N(w_avg), N linear in the wind
+  std::vector<double> F(nnz);
+  for (int t = 0; t < nnz; ++t) {
+    double v = hp.Mff[t] / S.tau + S.nu0 * hp.Aff[t];
+    for (int b = 0; b < k2; ++b) v += avg[b] * Nv[b][t];
+    F[t] = v;
+  }
+  BlockTri bt;
+  std::string err;
+  blocktri_factor(hp.Kff, F.data(), hp.vel_blocks, bt, err);
+  if (!err.empty()) throw SgttError(-6, err);
+  S.Fbt = upload_bt(c, bt);
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+namespace {
+template <class F>
+int guarded(sgtt_context* ctx, F&& f) {
+  try {
+    f();
+    return SGTT_OK;
+  } catch (const SgttError& e) {
+    if (ctx) ctx->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->err = e.what();
+    return SGTT_E_INVALID;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+const char* sgtt_version(void) { return "sgtt 0.1 gfx950 fp64"; }
+
+int sgtt_context_create(int device, void* stream, sgtt_context** out) {
+  if (!out) return SGTT_E_INVALID;
+  sgtt_context* ctx = new sgtt_context();
+  try {
+    ctx->device = device;
+    SGTT_HIP(hipSetDevice(device));
+    if (stream) {
+      ctx->c.s = (hipStream_t)stream;
+    } else {
+      SGTT_HIP(hipStreamCreate(&ctx->c.s));   // blocking: ordered after the legacy default stream
+      ctx->own_stream = true;
+    }
+    SGTT_HIP(hipHostMalloc((void**)&ctx->c.hint, 64 * sizeof(int), hipHostMallocDefault));
+    SGTT_HIP(hipHostMalloc((void**)&ctx->c.hdbl, 256 * sizeof(double), hipHostMallocDefault));
+    ctx->c.dint = (int*)ctx->c.pool.get(64);
+    ctx->c.dscal = ctx->c.pool.get(256);
+  } catch (const SgttError& e) {
+    delete ctx;
+    return e.code;
+  }
+  *out = ctx;
+  return SGTT_OK;
+}
+
+int sgtt_context_destroy(sgtt_context* ctx) {
+  if (!ctx) return SGTT_E_INVALID;
+  (void)hipStreamSynchronize(ctx->c.s);
+  hipStream_t s = ctx->c.s;
+  bool own = ctx->own_stream;
+  delete ctx;
+  if (own) (void)hipStreamDestroy(s);
+  return SGTT_OK;
+}
+
+const char* sgtt_last_error(const sgtt_context* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int sgtt_assemble(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_tt_pair* prior, sgtt_system** out) {
+  if (!ctx || !desc || !out) return SGTT_E_INVALID;
+  return guarded(ctx, [&]() {
+    double t0 = now_s();
+    auto S = std::make_unique<sgtt_system>();
+    S->ctx = ctx;
+    S->desc = *desc;
+    Ctx& c = ctx->c;
+    ProblemParams prm;
+    prm.h = desc->h;
+    prm.L = desc->L;
+    prm.m = desc->m;
+    prm.p = desc->p;
+    prm.nt = desc->nt;
+    prm.tau = desc->tau;
+    prm.nu0 = desc->nu0;
+    prm.nu_coef = desc->nu_coef;
+    prm.ramp = desc->ramp;
+    try {
+      build_problem(prm, S->hp);
+    } catch (const std::exception& e) {
+      throw SgttError(-6, std::string("setup: ") + e.what());
+    }
+    HostProblem& hp = S->hp;
+    S->nt = hp.nt;
+    S->nxi = hp.n_xi;
+    S->ns = hp.n_s;
+    S->nu = hp.n_u;
+    S->np = hp.n_p;
+    S->nall = hp.n_all;
+    S->tau = prm.tau;
+    S->nu0 = prm.nu0;
+    SGTT_HIP(hipMalloc(&S->dsc, 32768 * sizeof(double)));
+    S->Gnu = dev_upload(c, hp.Gnu);
+    S->Bd = upload_csr(c, hp.B, {hp.B.val.data()});
+    S->Btd = upload_csr(c, hp.Bt, {hp.Bt.val.data()});
+    {
+      BlockTri bt;
+      std::string err;
+      blocktri_factor(hp.Xp, hp.Xp.val.data(), hp.p_blocks, bt, err);
+      if (!err.empty()) throw SgttError(-6, err);
+      S->Xbt = upload_bt(c, bt);
+    }
+    const int nt = S->nt, nxi = S->nxi, nall = S->nall, ns = S->ns;
+    // Dirichlet lift TT over all nodes: ramp (x) e_1 (x) g_all
+    std::vector<double> e1(nxi, 0.0);
+    e1[0] = 1.0;
+    TT lift = tt_new(c, nt, nxi, 2 * nall, 1, 1);
+    SGTT_HIP(hipMemcpyAsync(lift.c1, hp.ramp.data(), nt * 8, hipMemcpyHostToDevice, c.s));
+    SGTT_HIP(hipMemcpyAsync(lift.c2, e1.data(), nxi * 8, hipMemcpyHostToDevice, c.s));
+    SGTT_HIP(hipMemcpyAsync(lift.c3, hp.g_all.data(), 2 * nall * 8, hipMemcpyHostToDevice, c.s));
+    c.sync();
+    if (!prior) {
+      // Stokes system: no convection; f = -L_{free,all}(0) lift (ranks 2 and 1)
+      S->k1 = S->k2 = 0;
+      S->Kop = upload_csr(c, hp.Kff, {hp.Mff.data(), hp.Aff.data()});
+      S->Xmid = upload_csr(c, hp.Xmid, {hp.XM.data(), hp.XA.data()});
+      std::vector<double> F(hp.Kff.nnz());
+      for (int t = 0; t < hp.Kff.nnz(); ++t) F[t] = hp.Mff[t] / S->tau + S->nu0 * hp.Aff[t];
+      BlockTri bt;
+      std::string err;
+      blocktri_factor(hp.Kff, F.data(), hp.vel_blocks, bt, err);
+      if (!err.empty()) throw SgttError(-6, err);
+      S->Fbt = upload_bt(c, bt);
+      // f^u: core1 [(I-C)a/tau | a], core2 [e1 ; G_nu e1], core3 -[M_fa g | A_fa g]
+      std::vector<double> Ca(nt), c1((size_t)nt * 2), c2((size_t)2 * nxi * 2, 0.0);
+      for (int k = 0; k < nt; ++k) {
+        c1[(size_t)k * 2 + 0] = (hp.ramp[k] - (k > 0 ? hp.ramp[k - 1] : 0.0)) / S->tau;
+        c1[(size_t)k * 2 + 1] = hp.ramp[k];
+      }
+      for (int i = 0; i < nxi; ++i) {
+        c2[((size_t)0 * nxi + i) * 2 + 0] = e1[i];
+        c2[((size_t)1 * nxi + i) * 2 + 1] = hp.Gnu[(size_t)i * nxi + 0];
+      }
+      std::vector<double> c3((size_t)2 * ns * 2, 0.0), pc3(hp.n_p, 0.0);
+      for (int comp = 0; comp < 2; ++comp)
+        for (int i = 0; i < ns; ++i) {
+          double sm = 0, sa = 0;
+          for (int t = hp.Kfa.rowptr[i]; t < hp.Kfa.rowptr[i + 1]; ++t) {
+            double g = hp.g_all[(size_t)comp * nall + hp.Kfa.col[t]];
+            sm += hp.Mfa[t] * g;
+            sa += hp.Afa[t] * g;
+          }
+          c3[((size_t)comp * ns + i) * 2 + 0] = -sm;
+          c3[((size_t)comp * ns + i) * 2 + 1] = -sa;
+        }
+      for (int k = 0; k < hp.n_p; ++k) {
+        double s = 0;
+        for (int t = hp.Ball.rowptr[k]; t < hp.Ball.rowptr[k + 1]; ++t) s += hp.Ball.val[t] * hp.g_all[hp.Ball.col[t]];
+        pc3[k] = -s;
+      }
+      S->bu = tt_new(c, nt, nxi, hp.n_u, 2, 2);
+      SGTT_HIP(hipMemcpyAsync(S->bu.c1, c1.data(), c1.size() * 8, hipMemcpyHostToDevice, c.s));
+      SGTT_HIP(hipMemcpyAsync(S->bu.c2, c2.data(), c2.size() * 8, hipMemcpyHostToDevice, c.s));
+      SGTT_HIP(hipMemcpyAsync(S->bu.c3, c3.data(), c3.size() * 8, hipMemcpyHostToDevice, c.s));
+      S->bp = tt_new(c, nt, nxi, hp.n_p, 1, 1);
+      SGTT_HIP(hipMemcpyAsync(S->bp.c1, hp.ramp.data(), nt * 8, hipMemcpyHostToDevice, c.s));
+      SGTT_HIP(hipMemcpyAsync(S->bp.c2, e1.data(), nxi * 8, hipMemcpyHostToDevice, c.s));
+      SGTT_HIP(hipMemcpyAsync(S->bp.c3, pc3.data(), hp.n_p * 8, hipMemcpyHostToDevice, c.s));
+      c.sync();
+    } else {
+      check_tt(prior->u, nt, nxi, hp.n_u);
+      check_tt(prior->p, nt, nxi, hp.n_p);
+      // wind over all nodes: embed free velocity, then add the lift
+      const sgtt_tt& pu = prior->u;
+      TT wemb = tt_new(c, nt, nxi, 2 * nall, pu.r1, pu.r2);
+      SGTT_HIP(hipMemcpyAsync(wemb.c1, pu.core1, sizeof(double) * pu.n1 * pu.r1, hipMemcpyDeviceToDevice, c.s));
+      SGTT_HIP(hipMemcpyAsync(wemb.c2, pu.core2, sizeof(double) * pu.r1 * pu.n2 * pu.r2, hipMemcpyDeviceToDevice, c.s));
+      {
+        std::vector<double> hu((size_t)hp.n_u * pu.r2), ha((size_t)2 * nall * pu.r2, 0.0);
+        SGTT_HIP(hipMemcpyAsync(hu.data(), pu.core3, hu.size() * 8, hipMemcpyDeviceToHost, c.s));
+        c.sync();
+        for (int comp = 0; comp < 2; ++comp)
+          for (int i = 0; i < ns; ++i) {
+            int node = hp.mesh.free_nodes[i];
+            std::memcpy(&ha[((size_t)comp * nall + node) * pu.r2], &hu[((size_t)comp * ns + i) * pu.r2],
+                        sizeof(double) * pu.r2);
+          }
+        SGTT_HIP(hipMemcpyAsync(wemb.c3, ha.data(), ha.size() * 8, hipMemcpyHostToDevice, c.s));
+        c.sync();
+      }
+      TT wall = tt_concat(c, {&wemb, &lift}, nullptr, {});
+      TT wtil = tt_round(c, wall, desc->eps_conv, nullptr, nullptr);
+      build_convection(*S, c, wtil);
+      // right-hand side r = -(L_{free,all}(w) w_all + B^T p) with the
+      // untruncated wind (eq. 3.15): build a temporary system view whose
+      // convection is N(w_all) on the free x all pattern
+      {
+        const int K1 = wall.r1, K2 = wall.r2;
+        std::vector<double> h1((size_t)nt * K1), h2((size_t)K1 * nxi * K2), h3((size_t)2 * nall * K2);
+        SGTT_HIP(hipMemcpyAsync(h1.data(), wall.c1, h1.size() * 8, hipMemcpyDeviceToHost, c.s));
+        SGTT_HIP(hipMemcpyAsync(h2.data(), wall.c2, h2.size() * 8, hipMemcpyDeviceToHost, c.s));
+        SGTT_HIP(hipMemcpyAsync(h3.data(), wall.c3, h3.size() * 8, hipMemcpyDeviceToHost, c.s));
+        c.sync();
+        const int nnzfa = hp.Kfa.nnz();
+        std::vector<std::vector<double>> Nfa(K2, std::vector<double>(nnzfa));
+        std::vector<double> ff(hp.Kff.nnz()), w1(nall), w2(nall);
+        for (int b = 0; b < K2; ++b) {
+          for (int i = 0; i < nall; ++i) {
+            w1[i] = h3[(size_t)i * K2 + b];
+            w2[i] = h3[(size_t)(nall + i) * K2 + b];
+          }
+          convection_values(hp, w1.data(), w2.data(), ff.data(), Nfa[b].data());
+        }
+        std::vector<double> Hw((size_t)K1 * K2 * nxi * nxi, 0.0);
+        for (int a = 0; a < K1; ++a)
+          for (int b = 0; b < K2; ++b)
+            for (int l = 0; l < nxi; ++l) {
+              double wv = h2[((size_t)a * nxi + l) * K2 + b];
+              if (wv == 0.0) continue;
+              const double* Hl = hp.H.data() + (size_t)l * nxi * nxi;
+              double* dst = Hw.data() + ((size_t)a * K2 + b) * nxi * nxi;
+              for (int q = 0; q < nxi * nxi; ++q) dst[q] += wv * Hl[q];
+            }
+        std::vector<const double*> vs{hp.Mfa.data(), hp.Afa.data()};
+        for (int b = 0; b < K2; ++b) vs.push_back(Nfa[b].data());
+        DevCsr Kfa = upload_csr(c, hp.Kfa, vs);
+        DevCsr Ball = upload_csr(c, hp.Ball, {hp.Ball.val.data()});
+        double* dw1 = dev_upload(c, h1);
+        double* dHw = dev_upload(c, Hw);
+        const TT& w = wall;
+        TT pview = tt_view(prior->p.n1, prior->p.n2, prior->p.n3, prior->p.r1, prior->p.r2, prior->p.core1,
+                           prior->p.core2, prior->p.core3);
+        const TT& p = pview;
+        const int r1u = w.r1, r2u = w.r2, r1p = p.r1, r2p = p.r2;
+        const int R1 = 2 * r1u + K1 * r1u + r1p, R2 = 2 * r2u + K2 * r2u + r2p;
+        TT ru = tt_new(c, nt, nxi, hp.n_u, R1, R2);
+        core1_op(c.s, 0, nt, r1u, w.c1, r1u, ru.c1, R1, 0, 1.0 / S->tau);
+        core1_op(c.s, 1, nt, r1u, w.c1, r1u, ru.c1, R1, r1u, 1.0);
+        core1_diag(c.s, nt, r1u, K1, dw1, K1, w.c1, r1u, ru.c1, R1, 2 * r1u);
+        core1_op(c.s, 1, nt, r1p, p.c1, r1p, ru.c1, R1, 2 * r1u + K1 * r1u, 1.0);
+        copy2d(c.s, nt, R1, ru.c1, R1, ru.c1, R1, -1.0, nullptr, 0);   // r = -(...)
+        fill(c.s, ru.c2, ru.n_c2(), 0.0);
+        core2_block(c.s, r1u, nxi, r2u, w.c2, nullptr, 1, 1, ru.c2, R1, R2, 0, 0);
+        core2_block(c.s, r1u, nxi, r2u, w.c2, S->Gnu, 1, 1, ru.c2, R1, R2, r1u, r2u);
+        core2_block(c.s, r1u, nxi, r2u, w.c2, dHw, K1, K2, ru.c2, R1, R2, 2 * r1u, 2 * r2u);
+        core2_block(c.s, r1p, nxi, r2p, p.c2, nullptr, 1, 1, ru.c2, R1, R2, 2 * r1u + K1 * r1u, 2 * r2u + K2 * r2u);
+        spmm(c.s, ns, 2, nall, ns, Kfa.rowptr, Kfa.col, Kfa.vals, 2 + K2, Kfa.nnz, w.c3, r2u, 0, r2u, ru.c3, R2, 0,
+             r2u, 1.0);
+        spmm(c.s, hp.n_u, 1, 0, 0, S->Btd.rowptr, S->Btd.col, S->Btd.vals, 1, 0, p.c3, r2p, 0, r2p, ru.c3, R2,
+             2 * r2u + K2 * r2u, 0, 1.0);
+        TT rp = tt_new(c, nt, nxi, hp.n_p, r1u, r2u);
+        copy2d(c.s, nt, r1u, w.c1, r1u, rp.c1, r1u, -1.0, nullptr, 0);
+        SGTT_HIP(hipMemcpyAsync(rp.c2, w.c2, sizeof(double) * w.n_c2(), hipMemcpyDeviceToDevice, c.s));
+        spmm(c.s, hp.n_p, 1, 0, 0, Ball.rowptr, Ball.col, Ball.vals, 1, 0, w.c3, r2u, 0, r2u, rp.c3, r2u, 0, 0, 1.0);
+        // TT-SVD of the full residual (Alg. 4.1)
+        for (int i = 0; i < 2; ++i) {
+          const TT& ri = i == 0 ? ru : rp;
+          long n = (long)ri.n1 * ri.n2 * ri.n3;
+          double* full = c.pool.get(n);
+          tt_expand(c, ri, full);
+          TT t = tt_from_full(c, full, ri.n1, ri.n2, ri.n3, desc->eps_rhs, nullptr);
+          c.pool.put(full);
+          if (i == 0) S->bu = std::move(t);
+          else S->bp = std::move(t);
+        }
+        c.sync();
+        Kfa.free_all();
+        Ball.free_all();
+        (void)hipFree(dw1);
+        (void)hipFree(dHw);
+      }
+    }
+    c.sync();
+    S->setup_s = now_s() - t0;
+    *out = S.release();
+  });
+}
+
+int sgtt_system_destroy(sgtt_system* sys) {
+  if (!sys) return SGTT_E_INVALID;
+  (void)hipStreamSynchronize(sys->ctx->c.s);
+  delete sys;
+  return SGTT_OK;
+}
+
+int sgtt_system_info_get(const sgtt_system* S, sgtt_system_info* info) {
+  if (!S || !info) return SGTT_E_INVALID;
+  info->n_s = S->ns;
+  info->n_u = S->nu;
+  info->n_p = S->np;
+  info->n_xi = S->nxi;
+  info->nt = S->nt;
+  info->n_all = S->nall;
+  info->conv_r1 = S->k1;
+  info->conv_r2 = S->k2;
+  info->rhs_r1u = S->bu.r1;
+  info->rhs_r2u = S->bu.r2;
+  info->rhs_r1p = S->bp.r1;
+  info->rhs_r2p = S->bp.r2;
+  info->setup_seconds = S->setup_s;
+  return SGTT_OK;
+}
+
+int sgtt_rhs(sgtt_system* S, sgtt_tt_pair* b) {
+  if (!S || !b) return SGTT_E_INVALID;
+  sgtt_context* ctx = S->ctx;
+  return guarded(ctx, [&]() {
+    Vec v;
+    v.nc = 2;
+    v.c[0] = tt_view(S->bu.n1, S->bu.n2, S->bu.n3, S->bu.r1, S->bu.r2, S->bu.c1, S->bu.c2, S->bu.c3);
+    v.c[1] = tt_view(S->bp.n1, S->bp.n2, S->bp.n3, S->bp.r1, S->bp.r2, S->bp.c1, S->bp.c2, S->bp.c3);
+    write_pair(ctx->c, v, b);
+    ctx->c.sync();
+  });
+}
+
+int sgtt_apply(sgtt_system* S, const sgtt_tt_pair* x, sgtt_tt_pair* y, double eps) {
+  if (!S || !x || !y) return SGTT_E_INVALID;
+  sgtt_context* ctx = S->ctx;
+  return guarded(ctx, [&]() {
+    check_tt(x->u, S->nt, S->nxi, S->nu);
+    check_tt(x->p, S->nt, S->nxi, S->np);
+    Vec xv = vec_from_pair(x);
+    Vec yv = apply_L(*S, xv);
+    if (eps > 0) yv = vec_round(ctx->c, yv, eps, nullptr, nullptr);
+    write_pair(ctx->c, yv, y);
+    ctx->c.sync();
+  });
+}
+
+int sgtt_precondition(sgtt_system* S, const sgtt_tt_pair* r, sgtt_tt_pair* z, const sgtt_solve_opts* opts) {
+  if (!S || !r || !z) return SGTT_E_INVALID;
+  sgtt_context* ctx = S->ctx;
+  return guarded(ctx, [&]() {
+    check_tt(r->u, S->nt, S->nxi, S->nu);
+    check_tt(r->p, S->nt, S->nxi, S->np);
+    sgtt_solve_opts o = opts ? *opts : default_opts();
+    Vec rv = vec_from_pair(r);
+    Vec zv = lsc_precondition(*S, rv, prec_opts(&o), nullptr);
+    write_pair(ctx->c, zv, z);
+    ctx->c.sync();
+  });
+}
+
+int sgtt_round(sgtt_context* ctx, sgtt_tt* x, double eps, int max_rank) {
+  if (!ctx || !x) return SGTT_E_INVALID;
+  return guarded(ctx, [&]() {
+    if (x->r1 < 1 || x->r2 < 1 || x->r1 > x->cap1 || x->r2 > x->cap2) throw SgttError(-1, "invalid TT");
+    TT v = tt_view(x->n1, x->n2, x->n3, x->r1, x->r2, x->core1, x->core2, x->core3);
+    TT r = tt_round(ctx->c, v, eps, nullptr, nullptr, max_rank > 0 ? max_rank : 96);
+    write_tt(ctx->c, r, x);
+    ctx->c.sync();
+  });
+}
+
+int sgtt_dot(sgtt_context* ctx, const sgtt_tt_pair* x, const sgtt_tt_pair* y, double* out) {
+  if (!ctx || !x || !y || !out) return SGTT_E_INVALID;
+  return guarded(ctx, [&]() {
+    Vec xv = vec_from_pair(x), yv = vec_from_pair(y);
+    vec_dot(ctx->c, xv, yv, ctx->c.dscal + 200);
+    *out = read_double(ctx->c, ctx->c.dscal + 200);
+    if (!std::isfinite(*out)) throw SgttError(-5, "non-finite inner product");
+  });
+}
+
+int sgtt_axpby(sgtt_context* ctx, double alpha, const sgtt_tt_pair* x, double beta, sgtt_tt_pair* y) {
+  if (!ctx || !x || !y) return SGTT_E_INVALID;
+  return guarded(ctx, [&]() {
+    Vec xv = vec_from_pair(x), yv = vec_from_pair(y);
+    Vec s = vec_concat(ctx->c, {&xv, &yv}, nullptr, {alpha, beta});
+    write_pair(ctx->c, s, y);
+    ctx->c.sync();
+  });
+}
+
+int sgtt_expand(sgtt_context* ctx, const sgtt_tt* x, double* out) {
+  if (!ctx || !x || !out) return SGTT_E_INVALID;
+  return guarded(ctx, [&]() {
+    TT v = tt_view(x->n1, x->n2, x->n3, x->r1, x->r2, x->core1, x->core2, x->core3);
+    tt_expand(ctx->c, v, out);
+    ctx->c.sync();
+  });
+}
+
+int sgtt_hessenberg_lsq(sgtt_context* ctx, const double* H, int k, double beta, double* y, double* resid) {
+  if (!ctx || !H || !y || k < 1 || k > 120) return SGTT_E_INVALID;
+  return guarded(ctx, [&]() {
+    Ctx& c = ctx->c;
+    double* dH = c.pool.get((size_t)(k + 1) * k + k + 4);
+    double* dy = dH + (size_t)(k + 1) * k;
+    double* db = dy + k;
+    SGTT_HIP(hipMemcpyAsync(dH, H, sizeof(double) * (k + 1) * k, hipMemcpyHostToDevice, c.s));
+    SGTT_HIP(hipMemcpyAsync(db, &beta, sizeof(double), hipMemcpyHostToDevice, c.s));
+    hessenberg_lsq(c.s, dH, k + 1, k, db, dy, db + 1);
+    SGTT_HIP(hipMemcpyAsync(y, dy, sizeof(double) * k, hipMemcpyDeviceToHost, c.s));
+    double r = 0;
+    SGTT_HIP(hipMemcpyAsync(c.hdbl, db + 1, sizeof(double), hipMemcpyDeviceToHost, c.s));
+    c.sync();
+    r = c.hdbl[0];
+    if (resid) *resid = r;
+    c.pool.put(dH);
+  });
+}
+
+int sgtt_residual(sgtt_system* S, const sgtt_tt_pair* b, const sgtt_tt_pair* x, double* rel) {
+  if (!S || !b || !x || !rel) return SGTT_E_INVALID;
+  sgtt_context* ctx = S->ctx;
+  return guarded(ctx, [&]() {
+    check_tt(x->u, S->nt, S->nxi, S->nu);
+    check_tt(x->p, S->nt, S->nxi, S->np);
+    Vec bv = vec_from_pair(b), xv = vec_from_pair(x);
+    *rel = full_residual(*S, bv, xv, nullptr, nullptr, 0.0, nullptr);
+  });
+}
+
+int sgtt_solve(sgtt_system* S, const sgtt_tt_pair* b, sgtt_tt_pair* x, const sgtt_solve_opts* opts,
+               sgtt_solve_stats* stats) {
+  if (!S || !b || !x) return SGTT_E_INVALID;
+  sgtt_context* ctx = S->ctx;
+  int status = SGTT_OK;
+  try {
+    check_tt(b->u, S->nt, S->nxi, S->nu);
+    check_tt(b->p, S->nt, S->nxi, S->np);
+    Ctx& c = ctx->c;
+    sgtt_solve_opts o = opts ? *opts : default_opts();
+    if (o.restart < 1 || o.restart > 60 || o.max_cycles < 1 || o.inner_maxit < 1 || o.inner_maxit > 60)
+      throw SgttError(-1, "invalid solve options");
+    double t0 = now_s();
+    long r0 = c.roundings;
+    SolveCounters cnt;
+    cnt.verbose = o.verbose;
+    OuterSpace sp(*S, prec_opts(&o), &cnt);
+    Vec bv = vec_from_pair(b);
+    std::vector<Vec> terms;
+    Vec r = vec_copy(c, bv);
+    double bn2 = -1.0, rel = 1.0;
+    int cycles = 0;
+    Vec z;
+    for (int cyc = 0; cyc < o.max_cycles; ++cyc) {
+      int its = 0;
+      double rr = 0;
+      Vec d = lowrank_fgmres(c, sp, r, o.tol_cycle, o.eps_krylov, o.restart, S->dsc, its, rr, &cnt, "outer");
+      cnt.outer += its;
+      ++cycles;
+      terms.push_back(std::move(d));
+      std::vector<const Vec*> parts;
+      for (auto& t : terms) parts.push_back(&t);
+      z = vec_concat(c, parts, nullptr, {});
+      Vec rnext;
+      rel = full_residual(*S, bv, z, nullptr, &rnext, o.eps_krylov, &bn2);
+      if (o.verbose) fprintf(stderr, "[sgtt] cycle %d: outer its %d, exact rel residual %.3e\n", cyc, its, rel);
+      if (!std::isfinite(rel)) throw SgttError(-5, "non-finite residual");
+      if (rel <= o.tol) break;
+      r = std::move(rnext);
+    }
+    write_pair(c, z, x);
+    c.sync();
+    if (rel > o.tol) status = SGTT_W_NOT_CONVERGED;
+    if (stats) {
+      stats->cycles = cycles;
+      stats->outer_iters = cnt.outer;
+      stats->inner_iters = cnt.inner;
+      stats->rel_residual = rel;
+      stats->seconds = now_s() - t0;
+      stats->max_rank_krylov_u = cnt.maxr_u;
+      stats->max_rank_krylov_p = cnt.maxr_p;
+      stats->roundings = (int)(c.roundings - r0);
+      stats->t_apply = cnt.t_apply;
+      stats->t_round = 0;
+      stats->t_precond = cnt.t_prec;
+      stats->t_residual = 0;
+    }
+  } catch (const SgttError& e) {
+    ctx->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return SGTT_E_INVALID;
+  }
+  return status;
+}
+
+// ---------------------------------------------------------------- host-only
+struct sgtt_host_problem {
+  HostProblem hp;
+};
+
+int sgtt_host_problem_create(const sgtt_problem_desc* desc, sgtt_host_problem** out) {
+  if (!desc || !out) return SGTT_E_INVALID;
+  try {
+    auto h = std::make_unique<sgtt_host_problem>();
+    ProblemParams prm;
+    prm.h = desc->h;
+    prm.L = desc->L;
+    prm.m = desc->m;
+    prm.p = desc->p;
+    prm.nt = desc->nt;
+    prm.tau = desc->tau;
+    prm.nu0 = desc->nu0;
+    prm.nu_coef = desc->nu_coef;
+    prm.ramp = desc->ramp;
+    build_problem(prm, h->hp);
+    *out = h.release();
+  } catch (...) {
+    return SGTT_E_SETUP;
+  }
+  return SGTT_OK;
+}
+
+int sgtt_host_problem_destroy(sgtt_host_problem* h) {
+  delete h;
+  return SGTT_OK;
+}
+
+int sgtt_host_sizes(const sgtt_host_problem* h, int* sizes) {
+  if (!h || !sizes) return SGTT_E_INVALID;
+  sizes[0] = h->hp.n_s;
+  sizes[1] = h->hp.n_u;
+  sizes[2] = h->hp.n_p;
+  sizes[3] = h->hp.n_xi;
+  sizes[4] = h->hp.nt;
+  sizes[5] = h->hp.n_all;
+  return SGTT_OK;
+}
+
+int sgtt_host_csr(const sgtt_host_problem* h, int which, int* nrows, int* ncols, int* nnz, int* rowptr, int* col,
+                  double* val) {
+  if (!h) return SGTT_E_INVALID;
+  const HostProblem& hp = h->hp;
+  const Csr* pat = nullptr;
+  const double* v = nullptr;
+  switch (which) {
+    case 0: pat = &hp.Kff; v = hp.Mff.data(); break;
+    case 1: pat = &hp.Kff; v = hp.Aff.data(); break;
+    case 2: pat = &hp.B; v = hp.B.val.data(); break;
+    case 3: pat = &hp.Xp; v = hp.Xp.val.data(); break;
+    case 4: pat = &hp.Xmid; v = hp.XM.data(); break;
+    case 5: pat = &hp.Xmid; v = hp.XA.data(); break;
+    default: return SGTT_E_INVALID;
+  }
+  if (nrows) *nrows = pat->nrows;
+  if (ncols) *ncols = pat->ncols;
+  if (nnz) *nnz = pat->nnz();
+  if (rowptr) std::copy(pat->rowptr.begin(), pat->rowptr.end(), rowptr);
+  if (col) std::copy(pat->col.begin(), pat->col.end(), col);
+  if (val) std::copy(v, v + pat->nnz(), val);
+  return SGTT_OK;
+}
+
+int sgtt_host_gpc(const sgtt_host_problem* h, int which, double* out) {
+  if (!h || !out) return SGTT_E_INVALID;
+  const HostProblem& hp = h->hp;
+  const std::vector<double>* src = which == 0 ? &hp.G : which == 1 ? &hp.H : which == 2 ? &hp.Gnu : nullptr;
+  if (!src) return SGTT_E_INVALID;
+  std::copy(src->begin(), src->end(), out);
+  return SGTT_OK;
+}
+
+int sgtt_host_mesh(const sgtt_host_problem* h, double* coords, int* free_nodes, double* g_all) {
+  if (!h) return SGTT_E_INVALID;
+  const HostProblem& hp = h->hp;
+  const double s = hp.prm.h / 2.0;
+  if (coords)
+    for (int i = 0; i < hp.n_all; ++i) {
+      coords[2 * i] = hp.mesh.I[i] * s;
+      coords[2 * i + 1] = hp.mesh.J[i] * s;
+    }
+  if (free_nodes) std::copy(hp.mesh.free_nodes.begin(), hp.mesh.free_nodes.end(), free_nodes);
+  if (g_all) std::copy(hp.g_all.begin(), hp.g_all.end(), g_all);
+  return SGTT_OK;
+}
+
+}  // extern "C"

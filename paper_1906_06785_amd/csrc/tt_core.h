@@ -1,0 +1,103 @@
+// Internal device-side tensor-train handles, memory pool and TT algebra.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "kernels.h"
+
+namespace sgtt {
+
+struct SgttError : std::runtime_error {
+  int code;
+  SgttError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SGTT_HIP(x)                                                                                  \
+  do {                                                                                               \
+    hipError_t e_ = (x);                                                                             \
+    if (e_ != hipSuccess)                                                                            \
+      throw ::sgtt::SgttError(-2, std::string(#x) + ": " + hipGetErrorString(e_) + " at " __FILE__); \
+  } while (0)
+
+// Caching device allocator: blocks are reused stream-ordered on one stream.
+class Pool {
+ public:
+  ~Pool();
+  double* get(size_t ndoubles);
+  void put(double* p);
+  size_t bytes_held() const { return held_; }
+
+ private:
+  std::unordered_map<double*, size_t> size_;
+  std::multimap<size_t, double*> free_;
+  size_t held_ = 0;
+};
+
+// Device TT: core1 n1 x r1 (ld r1), core2 r1 x n2 x r2, core3 n3 x r2 (ld r2).
+struct TT {
+  int n1 = 0, n2 = 0, n3 = 0, r1 = 0, r2 = 0;
+  double *c1 = nullptr, *c2 = nullptr, *c3 = nullptr;
+  Pool* pool = nullptr;   // owning pool, or nullptr for a view
+  TT() = default;
+  TT(const TT&) = delete;
+  TT& operator=(const TT&) = delete;
+  TT(TT&& o) noexcept { *this = std::move(o); }
+  TT& operator=(TT&& o) noexcept;
+  ~TT() { release(); }
+  void release();
+  long n_c1() const { return (long)n1 * r1; }
+  long n_c2() const { return (long)r1 * n2 * r2; }
+  long n_c3() const { return (long)n3 * r2; }
+};
+
+// A vector of the all-at-once system: 1 (velocity only) or 2 (u, p) TTs.
+struct Vec {
+  TT c[2];
+  int nc = 2;
+};
+
+struct Ctx {
+  hipStream_t s = nullptr;
+  Pool pool;
+  // scratch (grown on demand)
+  double* ws = nullptr;
+  size_t ws_n = 0;
+  double* ws2 = nullptr;
+  size_t ws2_n = 0;
+  int* dint = nullptr;         // small device int scratch (64)
+  double* dscal = nullptr;     // small device double scratch (256)
+  int* hint = nullptr;         // pinned host mirror (64)
+  double* hdbl = nullptr;      // pinned host mirror (256)
+  long syncs = 0;
+  long roundings = 0;
+  double* scratch(size_t n);   // general scratch for gram partials
+  double* scratch2(size_t n);  // trunc L + dwork
+  void sync();
+  ~Ctx();
+};
+
+TT tt_new(Ctx& c, int n1, int n2, int n3, int r1, int r2);
+TT tt_view(int n1, int n2, int n3, int r1, int r2, double* c1, double* c2, double* c3);
+TT tt_copy(Ctx& c, const TT& x);
+
+// sum_i coef_i x_i by concatenation; coefficient i = hcoef[i] * (dcoef ? dcoef[i] : 1)
+TT tt_concat(Ctx& c, const std::vector<const TT*>& xs, const double* dcoef, const std::vector<double>& hcoef);
+// <x, y> into *dout (device); accumulate if acc
+void tt_dot(Ctx& c, const TT& x, const TT& y, double* dout, int acc);
+// T_eps(x) (Gram-based, FP64).  Writes ||x||^2 to *d_normsq and the squared
+// norm of the result to *d_kept (device) when non-null.  maxrank caps ranks.
+TT tt_round(Ctx& c, const TT& x, double eps, double* d_normsq, double* d_kept, int maxrank = 96);
+// TT-SVD (Alg. 4.1) of a full n1 x n2 x n3 tensor (device, C order)
+TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, double* d_normsq, int maxrank = 96);
+// full tensor (device buffer of n1*n2*n3)
+void tt_expand(Ctx& c, const TT& x, double* out);
+// scale core3 by *dscale (inv: 1 / *dscale)
+void tt_scale3(Ctx& c, TT& x, const double* dscale, int inv);
+
+}  // namespace sgtt

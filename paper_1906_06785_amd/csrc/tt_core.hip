@@ -1,0 +1,288 @@
+// Tensor-train algebra on the device: concatenation (sums), inner products,
+// Gram-based truncation T_eps, TT-SVD of full tensors, expansion.
+//
+// Truncation (eq. 4.5-4.7, Alg. 4.1 applied to a TT input) is done with Gram
+// matrices of the unfoldings (the "Gram SVD" approach to TT rounding of
+// Al Daas, Ballard and Benner, SISC 2022), which keeps the O(n3 R^2) work in
+// two passes over core 3 (one Gram, one projection) and reduces the SVDs to
+// eigen-decompositions of small symmetric matrices:
+//   bond 1: S1 = G1 K2 G1^T with K2 = sum_i G2_i K3 G2_i^T, K3 = G3^T G3,
+//   bond 2: S2 = C K3 C^T with C = (U1^T G1) x_1 G2 unfolded (k1 n2) x R2,
+// each truncated with delta = eps ||z|| / sqrt(2) (eq. 4.7, d = 3).
+#include "tt_core.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace sgtt {
+
+// ------------------------------------------------------------------ pool
+Pool::~Pool() {
+  for (auto& kv : size_) (void)hipFree(kv.first);
+}
+
+double* Pool::get(size_t n) {
+  if (n == 0) n = 1;
+  size_t want = (n + 255) / 256 * 256;
+  auto it = free_.lower_bound(want);
+  if (it != free_.end() && it->first <= 2 * want + (1u << 20)) {
+    double* p = it->second;
+    free_.erase(it);
+    return p;
+  }
+  double* p = nullptr;
+  hipError_t e = hipMalloc(&p, want * sizeof(double));
+  if (e != hipSuccess) {
+    // release cached blocks and retry once
+    for (auto& kv : free_) {
+      (void)hipFree(kv.second);
+      held_ -= size_[kv.second] * sizeof(double);
+      size_.erase(kv.second);
+    }
+    free_.clear();
+    (void)hipGetLastError();
+    e = hipMalloc(&p, want * sizeof(double));
+    if (e != hipSuccess) throw SgttError(-3, "device allocation failed");
+  }
+  size_[p] = want;
+  held_ += want * sizeof(double);
+  return p;
+}
+
+void Pool::put(double* p) {
+  if (!p) return;
+  auto it = size_.find(p);
+  if (it == size_.end()) return;
+  free_.insert({it->second, p});
+}
+
+TT& TT::operator=(TT&& o) noexcept {
+  if (this != &o) {
+    release();
+    n1 = o.n1; n2 = o.n2; n3 = o.n3; r1 = o.r1; r2 = o.r2;
+    c1 = o.c1; c2 = o.c2; c3 = o.c3; pool = o.pool;
+    o.c1 = o.c2 = o.c3 = nullptr;
+    o.pool = nullptr;
+  }
+  return *this;
+}
+
+void TT::release() {
+  if (pool) {
+    pool->put(c1);
+    pool->put(c2);
+    pool->put(c3);
+  }
+  c1 = c2 = c3 = nullptr;
+  pool = nullptr;
+}
+
+Ctx::~Ctx() {
+  if (hint) (void)hipHostFree(hint);
+  if (hdbl) (void)hipHostFree(hdbl);
+}
+
+double* Ctx::scratch(size_t n) {
+  if (n > ws_n) {
+    if (ws) pool.put(ws);
+    ws = pool.get(n);
+    ws_n = n;
+  }
+  return ws;
+}
+
+double* Ctx::scratch2(size_t n) {
+  if (n > ws2_n) {
+    if (ws2) pool.put(ws2);
+    ws2 = pool.get(n);
+    ws2_n = n;
+  }
+  return ws2;
+}
+
+void Ctx::sync() {
+  ++syncs;
+  SGTT_HIP(hipStreamSynchronize(s));
+}
+
+TT tt_new(Ctx& c, int n1, int n2, int n3, int r1, int r2) {
+  TT t;
+  t.n1 = n1; t.n2 = n2; t.n3 = n3; t.r1 = r1; t.r2 = r2;
+  t.pool = &c.pool;
+  t.c1 = c.pool.get((size_t)n1 * r1);
+  t.c2 = c.pool.get((size_t)r1 * n2 * r2);
+  t.c3 = c.pool.get((size_t)n3 * r2);
+  return t;
+}
+
+TT tt_view(int n1, int n2, int n3, int r1, int r2, double* c1, double* c2, double* c3) {
+  TT t;
+  t.n1 = n1; t.n2 = n2; t.n3 = n3; t.r1 = r1; t.r2 = r2;
+  t.c1 = c1; t.c2 = c2; t.c3 = c3;
+  return t;
+}
+
+TT tt_copy(Ctx& c, const TT& x) {
+  TT t = tt_new(c, x.n1, x.n2, x.n3, x.r1, x.r2);
+  SGTT_HIP(hipMemcpyAsync(t.c1, x.c1, sizeof(double) * x.n_c1(), hipMemcpyDeviceToDevice, c.s));
+  SGTT_HIP(hipMemcpyAsync(t.c2, x.c2, sizeof(double) * x.n_c2(), hipMemcpyDeviceToDevice, c.s));
+  SGTT_HIP(hipMemcpyAsync(t.c3, x.c3, sizeof(double) * x.n_c3(), hipMemcpyDeviceToDevice, c.s));
+  return t;
+}
+
+TT tt_concat(Ctx& c, const std::vector<const TT*>& xs, const double* dcoef, const std::vector<double>& hcoef) {
+  const TT& x0 = *xs[0];
+  int R1 = 0, R2 = 0;
+  for (auto* x : xs) { R1 += x->r1; R2 += x->r2; }
+  TT t = tt_new(c, x0.n1, x0.n2, x0.n3, R1, R2);
+  fill(c.s, t.c2, t.n_c2(), 0.0);
+  int o1 = 0, o2 = 0;
+  for (size_t i = 0; i < xs.size(); ++i) {
+    const TT& x = *xs[i];
+    double hc = hcoef.empty() ? 1.0 : hcoef[i];
+    copy2d(c.s, x.n1, x.r1, x.c1, x.r1, t.c1 + o1, R1, hc, dcoef ? dcoef + i : nullptr, 0);
+    core2_block(c.s, x.r1, x.n2, x.r2, x.c2, nullptr, 1, 1, t.c2, R1, R2, o1, o2);
+    copy2d(c.s, x.n3, x.r2, x.c3, x.r2, t.c3 + o2, R2, 1.0, nullptr, 0);
+    o1 += x.r1;
+    o2 += x.r2;
+  }
+  return t;
+}
+
+void tt_dot(Ctx& c, const TT& x, const TT& y, double* dout, int acc) {
+  const int n1 = x.n1, n2 = x.n2;
+  const int a1 = x.r1, a2 = x.r2, b1 = y.r1, b2 = y.r2;
+  double* W1 = c.pool.get((size_t)a1 * b1);
+  double* Z = c.pool.get((size_t)a1 * n2 * b2);
+  double* W2 = c.pool.get((size_t)a2 * b2);
+  double* K3 = c.pool.get((size_t)a2 * b2);
+  // W1 = X1^T Y1
+  gemm(c.s, 1, a1, b1, n1, 1.0, x.c1, 0, 1, a1, y.c1, 0, b1, 1, 0.0, W1, 0, b1, 1);
+  // Z = W1 Y2 (flattened a1 x (n2 b2))
+  gemm(c.s, 1, a1, n2 * b2, b1, 1.0, W1, 0, b1, 1, y.c2, 0, (long)n2 * b2, 1, 0.0, Z, 0, (long)n2 * b2, 1);
+  // W2 = X2flat^T Zflat over (a, i)
+  gemm(c.s, 1, a2, b2, a1 * n2, 1.0, x.c2, 0, 1, a2, Z, 0, b2, 1, 0.0, W2, 0, b2, 1);
+  // K3 = X3^T Y3 over space
+  size_t wsn = std::max<size_t>((size_t)a2 * b2 * 64, 1 << 20);
+  gram(c.s, x.n3, a2, b2, x.c3, a2, 1, y.c3, b2, 1, K3, c.scratch(wsn), wsn);
+  dot_reduce(c.s, (long)a2 * b2, W2, K3, dout, acc);
+  c.pool.put(W1);
+  c.pool.put(Z);
+  c.pool.put(W2);
+  c.pool.put(K3);
+}
+
+static void read_ints(Ctx& c, const int* d, int n, int* h) {
+  SGTT_HIP(hipMemcpyAsync(c.hint, d, sizeof(int) * n, hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  std::memcpy(h, c.hint, sizeof(int) * n);
+}
+
+TT tt_round(Ctx& c, const TT& x, double eps, double* d_normsq, double* d_kept, int maxrank) {
+  ++c.roundings;
+  const int n1 = x.n1, n2 = x.n2, n3 = x.n3, R1 = x.r1, R2 = x.r2;
+  int* dk = c.dint;               // [0]=k1 [1]=info1 [2]=k2 [3]=info2
+  double* dnorm = d_normsq ? d_normsq : c.dscal + 250;
+  double* dkept1 = c.dscal + 251;
+  double* dkept2 = d_kept ? d_kept : c.dscal + 252;
+  // K3 = G3^T G3
+  double* K3 = c.pool.get((size_t)R2 * R2);
+  size_t wsn = std::max<size_t>((size_t)R2 * R2 * 64, 1 << 20);
+  gram(c.s, n3, R2, R2, x.c3, R2, 1, x.c3, R2, 1, K3, c.scratch(wsn), wsn);
+  // T = G2flat (R1 n2 x R2) K3
+  double* T = c.pool.get((size_t)R1 * n2 * R2);
+  gemm(c.s, 1, R1 * n2, R2, R2, 1.0, x.c2, 0, R2, 1, K3, 0, R2, 1, 0.0, T, 0, R2, 1);
+  // K2 = T' G2'^T with ' = R1 x (n2 R2)
+  double* K2 = c.pool.get((size_t)R1 * R1);
+  gemm(c.s, 1, R1, R1, n2 * R2, 1.0, T, 0, (long)n2 * R2, 1, x.c2, 0, 1, (long)n2 * R2, 0.0, K2, 0, R1, 1);
+  // S1 = G1 K2 G1^T
+  double* T1 = c.pool.get((size_t)n1 * R1);
+  gemm(c.s, 1, n1, R1, R1, 1.0, x.c1, 0, R1, 1, K2, 0, R1, 1, 0.0, T1, 0, R1, 1);
+  double* S1 = c.pool.get((size_t)n1 * n1);
+  gemm(c.s, 1, n1, n1, R1, 1.0, T1, 0, R1, 1, x.c1, 0, 1, R1, 0.0, S1, 0, n1, 1);
+  const int kmax1 = std::min({n1, R1, maxrank, 96});
+  double* U1 = c.pool.get((size_t)n1 * kmax1);
+  double* Lw = c.scratch2((size_t)std::max(n1, n2 * kmax1) * 96 + std::max(n1, n2 * kmax1) + 64);
+  trunc_eig(c.s, n1, S1, eps, nullptr, dnorm, U1, kmax1, Lw, dk, dkept1, dk + 1, std::min(n1, R1));
+  int h[4];
+  read_ints(c, dk, 2, h);
+  if (h[1] != 0) throw SgttError(-4, "TT rank capacity exceeded (bond 1)");
+  const int k1 = h[0];
+  // C1 = U1_k^T G1 (k1 x R1);  C = C1 G2' (k1 x n2 R2)
+  double* C1 = c.pool.get((size_t)k1 * R1);
+  gemm(c.s, 1, k1, R1, n1, 1.0, U1, 0, 1, kmax1, x.c1, 0, R1, 1, 0.0, C1, 0, R1, 1);
+  double* C = c.pool.get((size_t)k1 * n2 * R2);
+  gemm(c.s, 1, k1, n2 * R2, R1, 1.0, C1, 0, R1, 1, x.c2, 0, (long)n2 * R2, 1, 0.0, C, 0, (long)n2 * R2, 1);
+  const int N2 = k1 * n2;
+  // S2 = C K3 C^T
+  double* T2 = c.pool.get((size_t)N2 * R2);
+  gemm(c.s, 1, N2, R2, R2, 1.0, C, 0, R2, 1, K3, 0, R2, 1, 0.0, T2, 0, R2, 1);
+  double* S2 = c.pool.get((size_t)N2 * N2);
+  gemm(c.s, 1, N2, N2, R2, 1.0, T2, 0, R2, 1, C, 0, 1, R2, 0.0, S2, 0, N2, 1);
+  const int kmax2 = std::min({N2, R2, maxrank, 96});
+  double* U2 = c.pool.get((size_t)N2 * kmax2);
+  trunc_eig(c.s, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw, dk + 2, dkept2, dk + 3, std::min(N2, R2));
+  read_ints(c, dk + 2, 2, h + 2);
+  if (h[3] != 0) throw SgttError(-4, "TT rank capacity exceeded (bond 2)");
+  const int k2 = h[2];
+  // W = U2_k^T C (k2 x R2); new G3 = G3 W^T
+  double* W = c.pool.get((size_t)k2 * R2);
+  gemm(c.s, 1, k2, R2, N2, 1.0, U2, 0, 1, kmax2, C, 0, R2, 1, 0.0, W, 0, R2, 1);
+  TT t = tt_new(c, n1, n2, n3, k1, k2);
+  copy2d(c.s, n1, k1, U1, kmax1, t.c1, k1, 1.0, nullptr, 0);
+  copy2d(c.s, N2, k2, U2, kmax2, t.c2, k2, 1.0, nullptr, 0);
+  gemm(c.s, 1, n3, k2, R2, 1.0, x.c3, 0, R2, 1, W, 0, 1, R2, 0.0, t.c3, 0, k2, 1);
+  for (double* p : {K3, T, K2, T1, S1, U1, C1, C, T2, S2, U2, W}) c.pool.put(p);
+  return t;
+}
+
+TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, double* d_normsq, int maxrank) {
+  ++c.roundings;
+  const long n23 = (long)n2 * n3;
+  int* dk = c.dint + 8;
+  double* dnorm = d_normsq ? d_normsq : c.dscal + 249;
+  double* dkept = c.dscal + 248;
+  double* S1 = c.pool.get((size_t)n1 * n1);
+  size_t wsn = std::max<size_t>((size_t)n1 * n1 * 256, 1 << 20);
+  gram(c.s, n23, n1, n1, X, 1, n23, X, 1, n23, S1, c.scratch(wsn), wsn);
+  const int kmax1 = std::min({n1, maxrank, 96});
+  double* U1 = c.pool.get((size_t)n1 * kmax1);
+  double* Lw = c.scratch2((size_t)std::max(n1, n2 * kmax1) * 96 + std::max(n1, n2 * kmax1) + 64);
+  trunc_eig(c.s, n1, S1, eps, nullptr, dnorm, U1, kmax1, Lw, dk, dkept, dk + 1, n1);
+  int h[4];
+  read_ints(c, dk, 2, h);
+  if (h[1] != 0) throw SgttError(-4, "TT rank capacity exceeded (full bond 1)");
+  const int k1 = h[0];
+  const int N2 = k1 * n2;
+  double* Y = c.pool.get((size_t)k1 * n23);
+  gemm(c.s, 1, k1, (int)std::min<long>(n23, INT32_MAX), n1, 1.0, U1, 0, 1, kmax1, X, 0, n23, 1, 0.0, Y, 0, n23, 1);
+  double* S2 = c.pool.get((size_t)N2 * N2);
+  size_t wsn2 = std::max<size_t>((size_t)N2 * N2 * 64, 1 << 20);
+  gram(c.s, n3, N2, N2, Y, 1, n3, Y, 1, n3, S2, c.scratch(wsn2), wsn2);
+  const int kmax2 = std::min({N2, maxrank, 96});
+  double* U2 = c.pool.get((size_t)N2 * kmax2);
+  double* Lw2 = c.scratch2((size_t)std::max(n1, N2) * 96 + std::max(n1, N2) + 64);
+  trunc_eig(c.s, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw2, dk + 2, dkept, dk + 3, std::min(N2, n3));
+  read_ints(c, dk + 2, 2, h + 2);
+  if (h[3] != 0) throw SgttError(-4, "TT rank capacity exceeded (full bond 2)");
+  const int k2 = h[2];
+  TT t = tt_new(c, n1, n2, n3, k1, k2);
+  copy2d(c.s, n1, k1, U1, kmax1, t.c1, k1, 1.0, nullptr, 0);
+  copy2d(c.s, N2, k2, U2, kmax2, t.c2, k2, 1.0, nullptr, 0);
+  // G3 (n3 x k2) = Y(12)^T U2_k
+  gemm(c.s, 1, n3, k2, N2, 1.0, Y, 0, 1, n3, U2, 0, kmax2, 1, 0.0, t.c3, 0, k2, 1);
+  for (double* p : {S1, U1, Y, S2, U2}) c.pool.put(p);
+  return t;
+}
+
+void tt_expand(Ctx& c, const TT& x, double* out) {
+  const int n1 = x.n1, n2 = x.n2, n3 = x.n3, R1 = x.r1, R2 = x.r2;
+  double* Lf = c.pool.get((size_t)n1 * n2 * R2);
+  gemm(c.s, 1, n1, n2 * R2, R1, 1.0, x.c1, 0, R1, 1, x.c2, 0, (long)n2 * R2, 1, 0.0, Lf, 0, (long)n2 * R2, 1);
+  gemm(c.s, 1, n1 * n2, n3, R2, 1.0, Lf, 0, R2, 1, x.c3, 0, 1, R2, 0.0, out, 0, n3, 1);
+  c.pool.put(Lf);
+}
+
+void tt_scale3(Ctx& c, TT& x, const double* dscale, int inv) { scale_by(c.s, x.c3, x.n_c3(), dscale, inv); }
+
+}  // namespace sgtt

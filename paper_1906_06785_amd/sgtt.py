@@ -1,0 +1,357 @@
+"""Python binding of the sgtt C ABI (include/sgtt.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library
+(libsgtt.so).  PyTorch provides device memory and the stream.  If the
+library is missing, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgtt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"sgtt native library not built: {LIB_PATH} (run paper_1906_06785_amd.build)")
+_lib = C.CDLL(LIB_PATH)
+
+SGTT_OK = 0
+SGTT_W_NOT_CONVERGED = 1
+SGTT_E_RANK_CAP = -4
+
+
+class SgttTT(C.Structure):
+    _fields_ = [("n1", C.c_int), ("n2", C.c_int), ("n3", C.c_int), ("r1", C.c_int), ("r2", C.c_int),
+                ("cap1", C.c_int), ("cap2", C.c_int), ("core1", C.c_void_p), ("core2", C.c_void_p),
+                ("core3", C.c_void_p)]
+
+
+class SgttPair(C.Structure):
+    _fields_ = [("u", SgttTT), ("p", SgttTT)]
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("h", C.c_double), ("L", C.c_double), ("m", C.c_int), ("p", C.c_int), ("nt", C.c_int),
+                ("tau", C.c_double), ("nu0", C.c_double), ("nu_coef", C.c_double), ("ramp", C.c_double),
+                ("eps_conv", C.c_double), ("eps_rhs", C.c_double)]
+
+
+class SystemInfo(C.Structure):
+    _fields_ = [("n_s", C.c_int), ("n_u", C.c_int), ("n_p", C.c_int), ("n_xi", C.c_int), ("nt", C.c_int),
+                ("n_all", C.c_int), ("conv_r1", C.c_int), ("conv_r2", C.c_int), ("rhs_r1u", C.c_int),
+                ("rhs_r2u", C.c_int), ("rhs_r1p", C.c_int), ("rhs_r2p", C.c_int), ("setup_seconds", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("eps_krylov", C.c_double), ("tol_cycle", C.c_double),
+                ("restart", C.c_int), ("max_cycles", C.c_int), ("inner_tol", C.c_double),
+                ("inner_eps", C.c_double), ("inner_maxit", C.c_int), ("verbose", C.c_int)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("cycles", C.c_int), ("outer_iters", C.c_int), ("inner_iters", C.c_int),
+                ("rel_residual", C.c_double), ("seconds", C.c_double), ("max_rank_krylov_u", C.c_int),
+                ("max_rank_krylov_p", C.c_int), ("roundings", C.c_int), ("t_apply", C.c_double),
+                ("t_round", C.c_double), ("t_precond", C.c_double), ("t_residual", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = C.c_void_p
+_sig = {
+    "sgtt_version": (C.c_char_p, []),
+    "sgtt_context_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
+    "sgtt_context_destroy": (C.c_int, [_P]),
+    "sgtt_last_error": (C.c_char_p, [_P]),
+    "sgtt_assemble": (C.c_int, [_P, C.POINTER(ProblemDesc), C.POINTER(SgttPair), C.POINTER(_P)]),
+    "sgtt_system_destroy": (C.c_int, [_P]),
+    "sgtt_system_info_get": (C.c_int, [_P, C.POINTER(SystemInfo)]),
+    "sgtt_rhs": (C.c_int, [_P, C.POINTER(SgttPair)]),
+    "sgtt_apply": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), C.c_double]),
+    "sgtt_precondition": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), C.POINTER(SolveOpts)]),
+    "sgtt_round": (C.c_int, [_P, C.POINTER(SgttTT), C.c_double, C.c_int]),
+    "sgtt_dot": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), C.POINTER(C.c_double)]),
+    "sgtt_axpby": (C.c_int, [_P, C.c_double, C.POINTER(SgttPair), C.c_double, C.POINTER(SgttPair)]),
+    "sgtt_solve": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), C.POINTER(SolveOpts),
+                             C.POINTER(SolveStats)]),
+    "sgtt_residual": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), C.POINTER(C.c_double)]),
+    "sgtt_expand": (C.c_int, [_P, C.POINTER(SgttTT), _P]),
+    "sgtt_hessenberg_lsq": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int, C.c_double, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]),
+    "sgtt_host_problem_create": (C.c_int, [C.POINTER(ProblemDesc), C.POINTER(_P)]),
+    "sgtt_host_problem_destroy": (C.c_int, [_P]),
+    "sgtt_host_sizes": (C.c_int, [_P, C.POINTER(C.c_int)]),
+    "sgtt_host_csr": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "sgtt_host_gpc": (C.c_int, [_P, C.c_int, C.POINTER(C.c_double)]),
+    "sgtt_host_mesh": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig.keys())
+
+
+class SgttError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sgtt error {code}: {msg}")
+        self.code = code
+
+
+def make_desc(cfg: dict, eps_conv=1e-3, eps_rhs=1e-6) -> ProblemDesc:
+    return ProblemDesc(float(cfg["h"]), float(cfg.get("L", 12.0)), int(cfg["m"]), int(cfg["p"]), int(cfg["nt"]),
+                       float(cfg["tau"]), float(cfg["nu0"]), float(cfg["nu_coef"]), float(cfg.get("ramp", 10.0)),
+                       float(cfg.get("eps_conv", eps_conv)), float(cfg.get("eps_rhs", eps_rhs)))
+
+
+def make_opts(**kw) -> SolveOpts:
+    d = dict(tol=1e-8, eps_krylov=1e-6, tol_cycle=1e-4, restart=30, max_cycles=8, inner_tol=1e-1,
+             inner_eps=1e-3, inner_maxit=20, verbose=0)
+    d.update(kw)
+    return SolveOpts(d["tol"], d["eps_krylov"], d["tol_cycle"], int(d["restart"]), int(d["max_cycles"]),
+                     d["inner_tol"], d["inner_eps"], int(d["inner_maxit"]), int(d["verbose"]))
+
+
+# ------------------------------------------------------------------ host-only
+class HostProblem:
+    """Host-side setup of the library (no device calls)."""
+
+    def __init__(self, cfg: dict):
+        self._h = _P()
+        d = make_desc(cfg)
+        rc = _lib.sgtt_host_problem_create(C.byref(d), C.byref(self._h))
+        if rc != 0:
+            raise SgttError(rc, "host problem setup failed")
+        s = (C.c_int * 6)()
+        _lib.sgtt_host_sizes(self._h, s)
+        self.n_s, self.n_u, self.n_p, self.n_xi, self.nt, self.n_all = list(s)
+        self.m = int(cfg["m"])
+
+    def csr(self, which: int):
+        import scipy.sparse as sp
+        nr, nc, nnz = C.c_int(), C.c_int(), C.c_int()
+        _lib.sgtt_host_csr(self._h, which, C.byref(nr), C.byref(nc), C.byref(nnz), None, None, None)
+        rp = np.zeros(nr.value + 1, np.int32)
+        col = np.zeros(nnz.value, np.int32)
+        val = np.zeros(nnz.value, np.float64)
+        _lib.sgtt_host_csr(self._h, which, None, None, None, rp.ctypes.data_as(C.POINTER(C.c_int)),
+                           col.ctypes.data_as(C.POINTER(C.c_int)), val.ctypes.data_as(C.POINTER(C.c_double)))
+        return sp.csr_matrix((val, col, rp), shape=(nr.value, nc.value))
+
+    def gpc(self, which: int):
+        n = self.n_xi
+        size = {0: (self.m + 1) * n * n, 1: n ** 3, 2: n * n}[which]
+        out = np.zeros(size)
+        _lib.sgtt_host_gpc(self._h, which, out.ctypes.data_as(C.POINTER(C.c_double)))
+        shape = {0: (self.m + 1, n, n), 1: (n, n, n), 2: (n, n)}[which]
+        return out.reshape(shape)
+
+    def mesh(self):
+        coords = np.zeros(2 * self.n_all)
+        free = np.zeros(self.n_s, np.int32)
+        g = np.zeros(2 * self.n_all)
+        _lib.sgtt_host_mesh(self._h, coords.ctypes.data_as(C.POINTER(C.c_double)),
+                            free.ctypes.data_as(C.POINTER(C.c_int)), g.ctypes.data_as(C.POINTER(C.c_double)))
+        return coords.reshape(-1, 2), free, g
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.sgtt_host_problem_destroy(self._h)
+            self._h = None
+
+
+# ------------------------------------------------------------------ device
+def _torch():
+    import torch
+    return torch
+
+
+class TTBuf:
+    """Device buffers (torch, float64) for one TT with fixed capacities."""
+
+    def __init__(self, n1, n2, n3, cap1, cap2, device="cuda:0"):
+        torch = _torch()
+        self.n1, self.n2, self.n3, self.cap1, self.cap2 = n1, n2, n3, cap1, cap2
+        self.c1 = torch.zeros(n1 * cap1, dtype=torch.float64, device=device)
+        self.c2 = torch.zeros(cap1 * n2 * cap2, dtype=torch.float64, device=device)
+        self.c3 = torch.zeros(n3 * cap2, dtype=torch.float64, device=device)
+        self.r1 = self.r2 = 1
+
+    def struct(self) -> SgttTT:
+        return SgttTT(self.n1, self.n2, self.n3, self.r1, self.r2, self.cap1, self.cap2, self.c1.data_ptr(),
+                      self.c2.data_ptr(), self.c3.data_ptr())
+
+    def update(self, s: SgttTT):
+        self.r1, self.r2 = s.r1, s.r2
+
+    def set_cores(self, G1, G2, G3):
+        """Paper-convention cores G1 (n1 x r1), G2 (r1 x n2 x r2), G3 (r2 x n3)."""
+        torch = _torch()
+        r1, r2 = G1.shape[1], G3.shape[0]
+        if r1 > self.cap1 or r2 > self.cap2:
+            raise ValueError("ranks exceed capacity")
+        self.c1[: self.n1 * r1].copy_(torch.from_numpy(np.ascontiguousarray(G1).ravel()))
+        self.c2[: r1 * self.n2 * r2].copy_(torch.from_numpy(np.ascontiguousarray(G2).ravel()))
+        self.c3[: self.n3 * r2].copy_(torch.from_numpy(np.ascontiguousarray(G3.T).ravel()))
+        self.r1, self.r2 = r1, r2
+        return self
+
+    def cores(self):
+        r1, r2 = self.r1, self.r2
+        G1 = self.c1[: self.n1 * r1].cpu().numpy().reshape(self.n1, r1)
+        G2 = self.c2[: r1 * self.n2 * r2].cpu().numpy().reshape(r1, self.n2, r2)
+        G3 = self.c3[: self.n3 * r2].cpu().numpy().reshape(self.n3, r2).T.copy()
+        return G1, G2, G3
+
+
+class PairBuf:
+    def __init__(self, nt, nxi, nu, npp, cap1=64, cap2=256, capp1=None, capp2=None, device="cuda:0"):
+        self.u = TTBuf(nt, nxi, nu, cap1, cap2, device)
+        self.p = TTBuf(nt, nxi, npp, capp1 or cap1, capp2 or cap2, device)
+
+    def struct(self) -> SgttPair:
+        return SgttPair(self.u.struct(), self.p.struct())
+
+    def update(self, s: SgttPair):
+        self.u.update(s.u)
+        self.p.update(s.p)
+
+    def set(self, pair):
+        self.u.set_cores(*pair[0])
+        self.p.set_cores(*pair[1])
+        return self
+
+    def cores(self):
+        return self.u.cores(), self.p.cores()
+
+    @property
+    def ranks(self):
+        return (self.u.r1, self.u.r2), (self.p.r1, self.p.r2)
+
+
+class Context:
+    def __init__(self, device: int = 0, use_torch_stream: bool = True):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("sgtt needs a GPU (no HIP device visible)")
+        self.device = device
+        stream = torch.cuda.current_stream(device).cuda_stream if use_torch_stream else None
+        self._c = _P()
+        rc = _lib.sgtt_context_create(device, stream, C.byref(self._c))
+        if rc != 0:
+            raise SgttError(rc, "context create failed")
+
+    def check(self, rc):
+        if rc < 0:
+            raise SgttError(rc, _lib.sgtt_last_error(self._c).decode())
+        return rc
+
+    def round(self, buf: TTBuf, eps: float, max_rank: int = 0):
+        s = buf.struct()
+        self.check(_lib.sgtt_round(self._c, C.byref(s), eps, max_rank))
+        buf.update(s)
+        return buf
+
+    def dot(self, x: PairBuf, y: PairBuf) -> float:
+        out = C.c_double()
+        sx, sy = x.struct(), y.struct()
+        self.check(_lib.sgtt_dot(self._c, C.byref(sx), C.byref(sy), C.byref(out)))
+        return out.value
+
+    def axpby(self, alpha, x: PairBuf, beta, y: PairBuf):
+        sx, sy = x.struct(), y.struct()
+        self.check(_lib.sgtt_axpby(self._c, alpha, C.byref(sx), beta, C.byref(sy)))
+        y.update(sy)
+        return y
+
+    def expand(self, buf: TTBuf):
+        torch = _torch()
+        out = torch.empty(buf.n1 * buf.n2 * buf.n3, dtype=torch.float64, device=buf.c1.device)
+        s = buf.struct()
+        self.check(_lib.sgtt_expand(self._c, C.byref(s), out.data_ptr()))
+        return out.reshape(buf.n1, buf.n2, buf.n3)
+
+    def hessenberg_lsq(self, H: np.ndarray, beta: float):
+        k = H.shape[1]
+        Hc = np.asfortranarray(H, dtype=np.float64)
+        y = np.zeros(k)
+        res = C.c_double()
+        self.check(_lib.sgtt_hessenberg_lsq(self._c, Hc.ctypes.data_as(C.POINTER(C.c_double)), k, beta,
+                                            y.ctypes.data_as(C.POINTER(C.c_double)), C.byref(res)))
+        return y, res.value
+
+    def __del__(self):
+        if getattr(self, "_c", None):
+            _lib.sgtt_context_destroy(self._c)
+            self._c = None
+
+
+class System:
+    def __init__(self, ctx: Context, cfg: dict, prior: PairBuf | None = None, eps_conv=1e-3, eps_rhs=1e-6):
+        self.ctx = ctx
+        self.cfg = dict(cfg)
+        d = make_desc(cfg, eps_conv, eps_rhs)
+        self._s = _P()
+        pr = prior.struct() if prior is not None else None
+        ctx.check(_lib.sgtt_assemble(ctx._c, C.byref(d), C.byref(pr) if pr is not None else None,
+                                     C.byref(self._s)))
+        info = SystemInfo()
+        _lib.sgtt_system_info_get(self._s, C.byref(info))
+        self.info = info
+        self.nt, self.nxi, self.nu, self.np = info.nt, info.n_xi, info.n_u, info.n_p
+
+    def pair(self, cap1=64, cap2=256, capp1=None, capp2=None):
+        return PairBuf(self.nt, self.nxi, self.nu, self.np, cap1, cap2, capp1, capp2,
+                       device=f"cuda:{self.ctx.device}")
+
+    def rhs(self, out: PairBuf | None = None):
+        out = out or self.pair(16, 128)
+        s = out.struct()
+        self.ctx.check(_lib.sgtt_rhs(self._s, C.byref(s)))
+        out.update(s)
+        return out
+
+    def apply(self, x: PairBuf, out: PairBuf | None = None, eps: float = 0.0):
+        out = out or self.pair(4 * x.u.cap1 + 8, 4 * x.u.cap2 + 8)
+        sx, so = x.struct(), out.struct()
+        self.ctx.check(_lib.sgtt_apply(self._s, C.byref(sx), C.byref(so), eps))
+        out.update(so)
+        return out
+
+    def precondition(self, r: PairBuf, out: PairBuf | None = None, **opts):
+        out = out or self.pair()
+        o = make_opts(**opts)
+        sr, so = r.struct(), out.struct()
+        self.ctx.check(_lib.sgtt_precondition(self._s, C.byref(sr), C.byref(so), C.byref(o)))
+        out.update(so)
+        return out
+
+    def solve(self, b: PairBuf, out: PairBuf | None = None, **opts):
+        out = out or self.pair(96, 512)
+        o = make_opts(**opts)
+        st = SolveStats()
+        sb, so = b.struct(), out.struct()
+        rc = self.ctx.check(_lib.sgtt_solve(self._s, C.byref(sb), C.byref(so), C.byref(o), C.byref(st)))
+        out.update(so)
+        return out, st.as_dict(), rc
+
+    def residual(self, b: PairBuf, x: PairBuf) -> float:
+        r = C.c_double()
+        sb, sx = b.struct(), x.struct()
+        self.ctx.check(_lib.sgtt_residual(self._s, C.byref(sb), C.byref(sx), C.byref(r)))
+        return r.value
+
+    def __del__(self):
+        if getattr(self, "_s", None):
+            _lib.sgtt_system_destroy(self._s)
+            self._s = None
+
+
+def version() -> str:
+    return _lib.sgtt_version().decode()

@@ -1,0 +1,168 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on
+the same seeded inputs.  Tolerances: FP64 kernels without truncation agree to
+1e-12..1e-13 relative; truncated results are compared through what is unique
+(full values, norms, residuals, exact solutions), never through cores."""
+import numpy as np
+import pytest
+
+from oracle import tt
+from oracle.solver import MeanLSC
+from oracle.system import Problem
+from synthetic_inputs import CONFIGS, random_tt_cores, random_tt_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sg():
+    from paper_1906_06785_amd import sgtt
+    return sgtt
+
+
+@pytest.fixture(scope="module")
+def ctx(sg):
+    return sg.Context(0)
+
+
+@pytest.fixture(scope="module")
+def tiny(sg, ctx):
+    P = Problem(CONFIGS["tiny"])
+    S = sg.System(ctx, CONFIGS["tiny"])
+    return P, S
+
+
+@pytest.fixture(scope="module")
+def c1(sg, ctx):
+    P = Problem(CONFIGS["C1"])
+    S = sg.System(ctx, CONFIGS["C1"])
+    return P, S
+
+
+def _pair_buf(S, pair, cap1=32, cap2=128):
+    return S.pair(cap1, cap2).set(pair)
+
+
+def test_dot_and_expand(sg, ctx, tiny):
+    P, S = tiny
+    _flush("dot/expand tiny")
+    x = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (3, 7), (2, 5), 1)
+    y = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 9), (3, 4), 2)
+    bx, by = _pair_buf(S, x), _pair_buf(S, y)
+    ref = tt.pair_dot(x, y)
+    got = ctx.dot(bx, by)
+    assert abs(got - ref) <= 1e-12 * abs(ref)
+    full = ctx.expand(bx.u).cpu().numpy()
+    assert np.abs(full - tt.full(x[0])).max() <= 1e-13 * np.abs(full).max()
+
+
+@pytest.mark.parametrize("n,ranks,eps", [((10, 6, 2992), (8, 24), 1e-3), ((10, 6, 2992), (8, 24), 1e-6),
+                                         ((128, 35, 3000), (12, 40), 1e-6), ((7, 5, 137), (5, 9), 0.3)])
+def test_round_error_bound_and_ranks(sg, ctx, n, ranks, eps):
+    _flush(f"round n={n} ranks={ranks} eps={eps}")
+    G = random_tt_cores(*n, *ranks, seed=11, decay=0.35)
+    X = tt.full(G)
+    buf = sg.TTBuf(*n, 96, 96).set_cores(*G)
+    ctx.round(buf, eps)
+    Y = ctx.expand(buf).cpu().numpy()
+    nrm = np.linalg.norm(X)
+    err = np.linalg.norm(Y - X)
+    # eq. 4.6, up to the accuracy of FP64 Gram matrices (~1e-8 relative)
+    assert err <= eps * nrm * (1 + 1e-6) + 1e-8 * nrm
+    ref = tt.tt_round(G, eps)
+    r_ref = tt.ranks(ref)
+    assert abs(buf.r1 - r_ref[0]) <= 1 and abs(buf.r2 - r_ref[1]) <= 1
+    # output is left-orthonormal: ||z|| = ||core3||
+    G1, G2, G3 = buf.cores()
+    assert np.abs(G1.T @ G1 - np.eye(buf.r1)).max() < 1e-10
+    L = G2.reshape(-1, buf.r2)
+    assert np.abs(L.T @ L - np.eye(buf.r2)).max() < 1e-10
+
+
+def test_round_sum_cancellation(sg, ctx):
+    # x + x - x rounds back to x's ranks and values
+    _flush("round cancellation")
+    G = random_tt_cores(10, 6, 500, 4, 6, 5)
+    buf = sg.TTBuf(10, 6, 500, 32, 32).set_cores(*tt.concat([G, G, G], [1.0, 1.0, -1.0]))
+    ctx.round(buf, 1e-10)
+    assert (buf.r1, buf.r2) == (4, 6)
+    Y = ctx.expand(buf).cpu().numpy()
+    assert np.linalg.norm(Y - tt.full(G)) <= 1e-7 * np.linalg.norm(tt.full(G))
+
+
+@pytest.mark.parametrize("which", ["tiny", "c1"])
+def test_apply_matches_oracle(sg, ctx, tiny, c1, which):
+    P, S = tiny if which == "tiny" else c1
+    _flush(f"apply {which}")
+    x = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (3, 5), (2, 4), 3)
+    bx = _pair_buf(S, x)
+    out = S.apply(bx)
+    ref = P.apply(x)
+    assert out.ranks == (tt.ranks(ref[0]), tt.ranks(ref[1]))
+    got = tt.pair_full(out.cores())
+    want = tt.pair_full(ref)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_rhs_matches_oracle(sg, ctx, c1):
+    P, S = c1
+    _flush("rhs c1")
+    b = S.rhs()
+    ref = P.rhs()
+    got = tt.pair_full(b.cores())
+    want = tt.pair_full(ref)
+    assert np.abs(got - want).max() <= 1e-14 * np.abs(want).max()
+
+
+def test_hessenberg_lsq(sg, ctx):
+    _flush("hessenberg lsq")
+    g = np.random.default_rng(4)
+    for k in (1, 3, 12, 30):
+        H = np.triu(g.standard_normal((k + 1, k)), -1)
+        beta = 1.7
+        y, res = ctx.hessenberg_lsq(H, beta)
+        e1 = np.zeros(k + 1)
+        e1[0] = beta
+        yr = np.linalg.lstsq(H, e1, rcond=None)[0]
+        assert np.abs(y - yr).max() <= 1e-11 * max(1.0, np.abs(yr).max())
+        assert abs(res - np.linalg.norm(H @ yr - e1)) <= 1e-11
+
+
+def test_preconditioner_matches_oracle(sg, ctx, tiny):
+    # with truncation switched (almost) off, P^-1 r of the library equals the
+    # oracle's full-rank TT preconditioner (same inner iteration count)
+    P, S = tiny
+    _flush("precondition tiny")
+    r = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 4), (2, 3), 9)
+    br = _pair_buf(S, r)
+    out = S.precondition(br, eps_krylov=1e-13, inner_eps=1e-13, inner_tol=1e-1)
+    prec = MeanLSC(P, None, "tt", 1e-1, 1e-13, 20, 1e-13)
+    ref = prec.apply_tt(r)
+    got = tt.pair_full(out.cores())
+    want = tt.pair_full(ref)
+    assert np.linalg.norm(got - want) <= 1e-6 * np.linalg.norm(want)
+
+
+def test_solve_c1_stokes_to_1e8(sg, ctx, c1):
+    P, S = c1
+    _flush("solve C1 Stokes")
+    b = S.rhs()
+    x, st, rc = S.solve(b)
+    _flush(f"stats {st}")
+    assert rc == 0
+    assert st["rel_residual"] <= 1e-8
+    # the oracle evaluates the residual of the GPU solution independently
+    bu, bp = [tt.full(c) for c in b.cores()]
+    xu, xp = [tt.full(c) for c in x.cores()]
+    yu, yp = P.apply_full(xu, xp)
+    rel = np.sqrt(np.sum((bu - yu) ** 2) + np.sum((bp - yp) ** 2)) / np.sqrt(np.sum(bu ** 2) + np.sum(bp ** 2))
+    assert rel <= 1e-8
+    # and the error against the exact (time-stepping) solution
+    u, p = P.solve_direct(bu, bp)
+    zd = np.concatenate([u.ravel(), p.ravel()])
+    zg = np.concatenate([xu.ravel(), xp.ravel()])
+    assert np.linalg.norm(zg - zd) <= 1e-7 * np.linalg.norm(zd)
+    assert abs(S.residual(b, x) - rel) <= 1e-3 * rel + 1e-14
