@@ -97,6 +97,10 @@ typedef struct {
   double inner_eps;    /* truncation inside the inner solve (1e-3)          */
   int inner_maxit;     /* inner iterations                                  */
   int verbose;         /* 1: per-iteration line on stderr                   */
+  int outer_explicit;  /* 1: Alg. 4.2 literally, z_k and s_k = T(b - L z_k)
+                          every outer iteration; 0: stop a cycle on the
+                          least-squares residual estimate, form z at its end */
+  int inner_explicit;  /* same choice for the inner mean-matrix solve       */
 } sgtt_solve_opts;
 
 typedef struct {
@@ -113,6 +117,7 @@ typedef struct {
  * default-priority stream) or an existing hipStream_t (e.g. torch's). */
 int sgtt_context_create(int device, void* hip_stream, sgtt_context** out);
 int sgtt_context_destroy(sgtt_context* ctx);
+/* last error of the context; with ctx == NULL, the last failed context creation */
 const char* sgtt_last_error(const sgtt_context* ctx);
 /* build identification string (static storage) */
 const char* sgtt_version(void);

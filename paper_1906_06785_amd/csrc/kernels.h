@@ -14,6 +14,21 @@ void gemm(hipStream_t s, int batch, int m, int n, int k, double alpha, const dou
           long sAi, long sAk, const double* B, long sBb, long sBk, long sBj, double beta, double* C,
           long sCb, long sCi, long sCj, int kstep = 0, long klimit = 0);
 
+// Descriptor of one GEMM of a pointer-array batch (same convention as gemm).
+struct GemmDesc {
+  int m, n, k;
+  double alpha, beta;
+  const double* A;
+  long sAi, sAk;
+  const double* B;
+  long sBk, sBj;
+  double* C;
+  long sCi, sCj;
+};
+// Run nb independent GEMMs described by d_desc (device array of GemmDesc);
+// max_m / max_n bound the grid.
+void gemm_batched(hipStream_t s, int nb, const GemmDesc* d_desc, int max_m, int max_n);
+
 // out (nx x ny, row-major) = X^T Y over `rows` rows; X(r,i) at X + r*sXr + i*sXc.
 // ws: scratch of ws_doubles doubles for split-K partial sums.
 void gram(hipStream_t s, long rows, int nx, int ny, const double* X, long sXr, long sXc,
@@ -26,6 +41,9 @@ void fill(hipStream_t s, double* p, long n, double v);
 // 2-D strided copy with scale: dst[i*ldd + j] = alpha * (*dscale if dscale) * src[i*lds + j]
 void copy2d(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst, long ldd,
             double alpha, const double* dscale = nullptr, int dscale_inv = 0);
+
+// dst[j*ldd + i] = src[i*lds + j] for i < rows, j < cols
+void transpose_copy(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst, long ldd);
 
 // CSR SpMM over the space index with several value arrays sharing a pattern
 // and `ncomp` velocity components:
@@ -66,9 +84,11 @@ void core2_block(hipStream_t s, int r1, int n2, int r2, const double* in, const 
 void trunc_eig(hipStream_t s, int N, double* S, double eps, const double* normsq_in, double* normsq_out,
                double* U, int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound);
 
-// Block-tridiagonal solve X <- A^-1 X on ncols columns of a node-major
+// Block-tridiagonal solve Y = A^-1 X on ncols columns of a node-major
 // matrix (row = space index, ld = ldx) with `ncomp` components stacked by
-// rows (component c occupies rows [c*n, (c+1)*n)).
+// rows (component c occupies rows [c*n, (c+1)*n)).  Blocks up to 256 rows.
+// Stage 1 forms Y_b = Sinv_b X_b for all blocks in parallel; stage 2 and 3
+// are the forward (P_b) and backward (Q_b) sweeps.  X and Y may alias.
 void blocktri_solve(hipStream_t s, int n, int nblk, int maxbs, const int* start, const long* off_sinv,
                     const long* off_p, const long* off_q, const double* data, int ncomp, double* X, int ldx,
                     int ncols, double* Y);

@@ -5,6 +5,9 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <mutex>
+#include <unordered_map>
+#include <utility>
 
 #include "kernels.h"
 
@@ -18,20 +21,43 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 // ------------------------------------------------------------------ GEMM
 constexpr int TM = 64, TN = 64, TK = 16;
 
-__global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, double alpha, const double* __restrict__ A,
-                                              long sAb, long sAi, long sAk, const double* __restrict__ B, long sBb,
-                                              long sBk, long sBj, double beta, double* __restrict__ C, long sCb,
-                                              long sCi, long sCj, int kstep, long klimit) {
-  const int b = blockIdx.z;
-  long kb = k;
-  if (klimit > 0) {
-    long rem = klimit - (long)b * kstep;
-    kb = rem < k ? rem : k;
+// Tiled FP64 GEMM: 64 x 64 output tile per 256-thread workgroup (4 x 4 per
+// thread), K staged through LDS in slices of 16 with the next slice
+// prefetched into registers while the current one is consumed.
+__device__ __forceinline__ void gemm_load_tile(const double* __restrict__ A, long sAi, long sAk, int m, const double* __restrict__ B,
+                                               long sBk, long sBj, int n, long kb, int i0, int j0, long kk, bool a_kfast,
+                                               bool b_kfast, int tid, double ra[4], double rb[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int e = tid + 256 * q;
+    int ii, kx;
+    if (a_kfast) { kx = e % TK; ii = e / TK; } else { ii = e % TM; kx = e / TM; }
+    long gi = i0 + ii, gk = kk + kx;
+    ra[q] = (gi < m && gk < kb) ? A[gi * sAi + gk * sAk] : 0.0;
+    int jj, kx2;
+    if (b_kfast) { kx2 = e % TK; jj = e / TK; } else { jj = e % TN; kx2 = e / TN; }
+    long gj = j0 + jj, gk2 = kk + kx2;
+    rb[q] = (gj < n && gk2 < kb) ? B[gk2 * sBk + gj * sBj] : 0.0;
   }
-  A += b * sAb;
-  B += b * sBb;
-  C += b * sCb;
-  const int i0 = blockIdx.y * TM, j0 = blockIdx.x * TN;
+}
+
+__device__ __forceinline__ void gemm_store_tile(double As[TK][TM + 1], double Bs[TK][TN + 1], bool a_kfast, bool b_kfast,
+                                                int tid, const double ra[4], const double rb[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int e = tid + 256 * q;
+    int ii, kx;
+    if (a_kfast) { kx = e % TK; ii = e / TK; } else { ii = e % TM; kx = e / TM; }
+    As[kx][ii] = ra[q];
+    int jj, kx2;
+    if (b_kfast) { kx2 = e % TK; jj = e / TK; } else { jj = e % TN; kx2 = e / TN; }
+    Bs[kx2][jj] = rb[q];
+  }
+}
+
+__device__ __forceinline__ void gemm_core(int m, int n, long kb, double alpha, const double* __restrict__ A, long sAi,
+                                          long sAk, const double* __restrict__ B, long sBk, long sBj, double beta,
+                                          double* __restrict__ C, long sCi, long sCj, int i0, int j0) {
   __shared__ double As[TK][TM + 1];
   __shared__ double Bs[TK][TN + 1];
   const int tid = threadIdx.x;
@@ -43,20 +69,12 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, double alpha,
     for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
   const bool a_kfast = (sAk == 1);
   const bool b_kfast = (sBk == 1);
+  double ra[4], rb[4];
+  if (kb > 0) gemm_load_tile(A, sAi, sAk, m, B, sBk, sBj, n, kb, i0, j0, 0, a_kfast, b_kfast, tid, ra, rb);
   for (long kk = 0; kk < kb; kk += TK) {
-    for (int e = tid; e < TM * TK; e += 256) {
-      int ii, kx;
-      if (a_kfast) { kx = e % TK; ii = e / TK; } else { ii = e % TM; kx = e / TM; }
-      long gi = i0 + ii, gk = kk + kx;
-      As[kx][ii] = (gi < m && gk < kb) ? A[gi * sAi + gk * sAk] : 0.0;
-    }
-    for (int e = tid; e < TK * TN; e += 256) {
-      int jj, kx;
-      if (b_kfast) { kx = e % TK; jj = e / TK; } else { jj = e % TN; kx = e / TN; }
-      long gj = j0 + jj, gk = kk + kx;
-      Bs[kx][jj] = (gj < n && gk < kb) ? B[gk * sBk + gj * sBj] : 0.0;
-    }
+    gemm_store_tile(As, Bs, a_kfast, b_kfast, tid, ra, rb);
     __syncthreads();
+    if (kk + TK < kb) gemm_load_tile(A, sAi, sAk, m, B, sBk, sBj, n, kb, i0, j0, kk + TK, a_kfast, b_kfast, tid, ra, rb);
 #pragma unroll
     for (int kx = 0; kx < TK; ++kx) {
       double a[4], bb[4];
@@ -87,12 +105,40 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, double alpha,
   }
 }
 
-__global__ void k_reduce_partials(int nb, long ne, const double* __restrict__ ws, double* __restrict__ out) {
-  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
+__global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, double alpha, const double* __restrict__ A,
+                                              long sAb, long sAi, long sAk, const double* __restrict__ B, long sBb,
+                                              long sBk, long sBj, double beta, double* __restrict__ C, long sCb,
+                                              long sCi, long sCj, int kstep, long klimit) {
+  const int b = blockIdx.z;
+  long kb = k;
+  if (klimit > 0) {
+    long rem = klimit - (long)b * kstep;
+    kb = rem < k ? rem : k;
+  }
+  gemm_core(m, n, kb, alpha, A + b * sAb, sAi, sAk, B + b * sBb, sBk, sBj, beta, C + b * sCb, sCi, sCj,
+            blockIdx.y * TM, blockIdx.x * TN);
+}
+
+__global__ __launch_bounds__(256) void k_gemm_ptr(const GemmDesc* __restrict__ descs) {
+  const GemmDesc d = descs[blockIdx.z];
+  const int i0 = blockIdx.y * TM, j0 = blockIdx.x * TN;
+  if (i0 >= d.m || j0 >= d.n) return;
+  gemm_core(d.m, d.n, d.k, d.alpha, d.A, d.sAi, d.sAk, d.B, d.sBk, d.sBj, d.beta, d.C, d.sCi, d.sCj, i0, j0);
+}
+
+// out[e] = sum_b ws[b*ne + e]: 64 elements per 256-thread block, the
+// four waves split the partial sums and combine through LDS
+__global__ __launch_bounds__(256) void k_reduce_partials(int nb, long ne, const double* __restrict__ ws,
+                                                         double* __restrict__ out) {
+  __shared__ double sh[4][64];
+  const int lane = threadIdx.x % 64, grp = threadIdx.x / 64;
+  const long e = (long)blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += ws[(long)b * ne + e];
-  out[e] = s;
+  if (e < ne)
+    for (int b = grp; b < nb; b += 4) s += ws[(long)b * ne + e];
+  sh[grp][lane] = s;
+  __syncthreads();
+  if (grp == 0 && e < ne) out[e] = sh[0][lane] + sh[1][lane] + sh[2][lane] + sh[3][lane];
 }
 
 // ------------------------------------------------------------------ reductions
@@ -158,6 +204,15 @@ __global__ void k_copy2d(int rows, int cols, const double* __restrict__ src, lon
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
     long i = e / cols, j = e % cols;
     dst[i * ldd + j] = a * src[i * lds + j];
+  }
+}
+
+__global__ void k_transpose_copy(int rows, int cols, const double* __restrict__ src, long lds,
+                                 double* __restrict__ dst, long ldd) {
+  long total = (long)rows * cols;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    long i = e / cols, j = e % cols;
+    dst[j * ldd + i] = src[i * lds + j];
   }
 }
 
@@ -287,6 +342,7 @@ __global__ void k_core2_block(int r1, int n2, int r2, const double* __restrict__
 // ------------------------------------------------------------------ truncation
 constexpr int TE_THREADS = 1024;
 constexpr int KSMALL = 96;     // max rank handled by the LDS eigen solver
+constexpr int KCAP = 512;      // max rank of any truncation
 
 __device__ void argmax_block(double v, int idx, double* shv, int* shi, double& bv, int& bi) {
   // block-wide argmax (ties -> smallest index)
@@ -323,14 +379,14 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
   __shared__ double V[KSMALL * KSMALL];
   __shared__ double shv[32];
   __shared__ int shi[32];
-  __shared__ double lp[KSMALL];
+  __shared__ double lp[KCAP];
   __shared__ double rc[KSMALL / 2 + 1], rs[KSMALL / 2 + 1];
   __shared__ int rp[KSMALL / 2 + 1], rq[KSMALL / 2 + 1];
   __shared__ double lam[KSMALL];
   __shared__ int order[KSMALL];
   __shared__ int s_flag;
   const int tid = threadIdx.x, nth = blockDim.x;
-  if (kmax > KSMALL) kmax = KSMALL;
+  if (kmax > KCAP) kmax = KCAP;
   // --- trace and tolerance
   double tr = 0.0;
   for (int i = tid; i < N; i += nth) {
@@ -344,11 +400,22 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
   const double delta2 = 0.5 * eps * eps * normsq;
   const double zero_thr = 64.0 * 2.220446049250313e-16 * (tr > 0.0 ? tr : 0.0);
   const double res_stop = delta2 * 0.0625;
-  // --- pivoted Cholesky S ~ L L^T with early stop
+  // --- pivoted Cholesky S ~ L L^T.  Stops at resid <= delta2/16 (then the
+  // eigen-decomposition of the small factor decides the rank), or, when more
+  // than KSMALL pivots would be needed, at resid <= delta2 (then the pivoted
+  // Cholesky subspace itself is the truncation: mode 1).
   double resid = tr;
-  int kp = 0;
+  int kp = 0, ka = -1, mode = 0;
   for (int j = 0; j < kmax; ++j) {
-    if (resid <= res_stop) break;
+    if (delta2 > 0.0) {
+      if (resid <= delta2 && ka < 0) ka = kp;
+      if (mode == 0 && resid <= res_stop) break;
+      if (mode == 0 && kp == KSMALL) {
+        if (ka >= 0) break;
+        mode = 1;
+      }
+      if (mode == 1 && resid <= delta2) break;
+    }
     double bv;
     int bi;
     double mv = -1.0;
@@ -358,14 +425,14 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
     argmax_block(mv, mi, shv, shi, bv, bi);
     if (bv <= zero_thr || bv <= 0.0) break;
     const int p = bi;
-    if (tid < j) lp[tid] = L[(long)p * kmax + tid];
+    for (int t = tid; t < j; t += nth) lp[t] = L[(long)t * N + p];
     __syncthreads();
     const double ljj = sqrt(bv);
     for (int i = tid; i < N; i += nth) {
       double s = S[(long)i * N + p];
-      for (int t = 0; t < j; ++t) s -= L[(long)i * kmax + t] * lp[t];
+      for (int t = 0; t < j; ++t) s -= L[(long)t * N + i] * lp[t];
       double lij = (i == p) ? ljj : s / ljj;
-      L[(long)i * kmax + j] = lij;
+      L[(long)j * N + i] = lij;
       double d = dwork[i] - lij * lij;
       dwork[i] = (i == p || d < 0.0) ? 0.0 : d;
     }
@@ -375,6 +442,7 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
     resid = block_sum(rr, shv);
     kp = j + 1;
   }
+  if (mode == 0 && kp > KSMALL) mode = 1;
   if (kp == 0) {
     // zero (or numerically zero) matrix: rank-1 zero
     for (int i = tid; i < N; i += nth) U[(long)i * kmax] = (i == 0) ? 1.0 : 0.0;
@@ -385,28 +453,42 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
     }
     return;
   }
-  if (kp == kmax && kmax < rank_bound && resid > res_stop && resid > zero_thr) {
-    if (tid == 0) *info = 1;   // rank capacity exceeded
-  } else if (tid == 0) {
-    *info = 0;
+  if (tid == 0) *info = (kp == kmax && kmax < rank_bound && resid > (mode ? delta2 : res_stop) && resid > zero_thr) ? 1 : 0;
+  if (mode == 1) {
+    // truncation = span of the pivoted Cholesky columns (rank kp); U is an
+    // orthonormal basis of that span (Gram-Schmidt below)
+    if (tid == 0) {
+      shi[0] = kp;
+      *k_out = kp;
+      *kept_out = tr - resid;
+    }
+    __syncthreads();
   }
-  // --- T = L^T L (kp x kp), V = I
-  for (int e = tid; e < kp * kp; e += nth) {
-    int a = e / kp, b = e % kp;
-    double s = 0.0;
-    if (b >= a)
-      for (int i = 0; i < N; ++i) s = fma(L[(long)i * kmax + a], L[(long)i * kmax + b], s);
-    T[a * KSMALL + b] = s;
-    V[a * KSMALL + b] = (a == b) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int e = tid; e < kp * kp; e += nth) {
-    int a = e / kp, b = e % kp;
-    if (b < a) T[a * KSMALL + b] = T[b * KSMALL + a];
+  const int n = kp;
+  if (mode == 0) {
+  // --- T = L^T L (kp x kp), one wavefront per entry; V = I
+  {
+    const int wv = tid / WAVE, ln = tid % WAVE, nwv = nth / WAVE;
+    for (int e = wv; e < kp * kp; e += nwv) {
+      int a = e / kp, b = e % kp;
+      if (b < a) continue;
+      double s = 0.0;
+      for (int i = ln; i < N; i += WAVE) s = fma(L[(long)a * N + i], L[(long)b * N + i], s);
+      for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_down(s, o, WAVE);
+      if (ln == 0) {
+        T[a * KSMALL + b] = s;
+        T[b * KSMALL + a] = s;
+      }
+    }
+    for (int e = tid; e < kp * kp; e += nth) {
+      int a = e / kp, b = e % kp;
+      V[a * KSMALL + b] = (a == b) ? 1.0 : 0.0;
+    }
   }
   __syncthreads();
   // --- cyclic Jacobi (round-robin pairs)
-  const int n = kp;
+  double ttr = 0.0;
+  for (int i = 0; i < n; ++i) ttr += fabs(T[i * KSMALL + i]);
   const int np2 = n + (n & 1);
   const int npairs = np2 / 2;
   for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
@@ -421,7 +503,7 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
         double c = 1.0, s = 0.0;
         if (q < n) {
           double apq = T[p * KSMALL + q], app = T[p * KSMALL + p], aqq = T[q * KSMALL + q];
-          if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && apq != 0.0) {
+          if (fabs(apq) > fmax(1e-15 * sqrt(fabs(app * aqq)), 1e-17 * ttr) && apq != 0.0) {
             double th = (aqq - app) / (2.0 * apq);
             double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
@@ -502,116 +584,192 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
     *kept_out = kept;
   }
   __syncthreads();
-  const int k = shi[0];
+  const int kc = shi[0];
   __syncthreads();
-  // --- U = L V_k diag(lambda^-1/2)
-  for (long e = tid; e < (long)N * k; e += nth) {
-    int i = e / k, c = e % k;
+  // --- U = L V_k diag(lambda^-1/2), column-major into the U buffer
+  for (long e = tid; e < (long)N * kc; e += nth) {
+    int c = e / N, i = e % N;
     int oc = order[c];
     double s = 0.0;
-    for (int a = 0; a < n; ++a) s = fma(L[(long)i * kmax + a], V[a * KSMALL + oc], s);
+    for (int a = 0; a < n; ++a) s = fma(L[(long)a * N + i], V[a * KSMALL + oc], s);
     double l = lam[oc];
-    U[(long)i * kmax + c] = l > 0.0 ? s / sqrt(l) : 0.0;
+    U[(long)c * N + i] = l > 0.0 ? s / sqrt(l) : 0.0;
   }
   __syncthreads();
-  // --- re-orthonormalize U (classical Gram-Schmidt, two passes); the
-  // coefficients of one column are computed one wave per coefficient.
+  // move to L (column-major work area for Gram-Schmidt)
+  for (long e = tid; e < (long)N * kc; e += nth) L[e] = U[e];
+  __syncthreads();
+  }  // mode == 0
+  const int k = shi[0];
+  __syncthreads();
+  // --- orthonormalize the k columns of L (column-major) by classical
+  // Gram-Schmidt with two passes, one wave per coefficient; write U (N x k,
+  // row-major, ld kmax)
   const int wv = tid / WAVE, ln = tid % WAVE, nwv = nth / WAVE;
   for (int c = 0; c < k; ++c) {
+    double* xc = L + (long)c * N;
     for (int pass = 0; pass < 2 && c > 0; ++pass) {
       for (int d = wv; d < c; d += nwv) {
+        const double* xd = L + (long)d * N;
         double s = 0.0;
-        for (int i = ln; i < N; i += WAVE) s = fma(U[(long)i * kmax + d], U[(long)i * kmax + c], s);
+        for (int i = ln; i < N; i += WAVE) s = fma(xd[i], xc[i], s);
         for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_down(s, o, WAVE);
         if (ln == 0) lp[d] = s;
       }
       __syncthreads();
       for (int i = tid; i < N; i += nth) {
-        double u = U[(long)i * kmax + c];
-        for (int d = 0; d < c; ++d) u -= lp[d] * U[(long)i * kmax + d];
-        U[(long)i * kmax + c] = u;
+        double u = xc[i];
+        for (int d = 0; d < c; ++d) u -= lp[d] * L[(long)d * N + i];
+        xc[i] = u;
       }
       __syncthreads();
     }
     double s = 0.0;
-    for (int i = tid; i < N; i += nth) s = fma(U[(long)i * kmax + c], U[(long)i * kmax + c], s);
+    for (int i = tid; i < N; i += nth) s = fma(xc[i], xc[i], s);
     s = block_sum(s, shv);
     double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-    for (int i = tid; i < N; i += nth) U[(long)i * kmax + c] *= inv;
+    for (int i = tid; i < N; i += nth) xc[i] *= inv;
     __syncthreads();
+  }
+  for (long e = tid; e < (long)N * k; e += nth) {
+    int i = e / k, c = e % k;
+    U[(long)i * kmax + c] = L[(long)c * N + i];
   }
 }
 
 // ------------------------------------------------------------------ block tridiagonal
-constexpr int BT_CB = 8;
+// Sequential sweeps of the block-LU solve after y_b = Sinv_b x_b has been
+// formed for every block in parallel:
+//   forward  (dir = 0): y_b <- y_b - P_b y_{b-1},   b = 1 .. nblk-1
+//   backward (dir = 1): x_b <- y_b - Q_b x_{b+1},   b = nblk-2 .. 0
+// One workgroup owns BT_CB columns of one component and walks the blocks in
+// order; the previous block's result stays in LDS.  Thread t handles row
+// (t % 128) + 128 i of the block for BT_CB/2 columns (half t / 128).
+constexpr int BT_CB = 16;
 constexpr int BT_MAXBS = 256;
+constexpr int BT_KU = 16;   // loads in flight per thread (prev rows beyond prevbs are zero)
 
-__global__ __launch_bounds__(256) void k_blocktri(int n, int nblk, const int* __restrict__ start,
-                                                  const long* __restrict__ off_sinv, const long* __restrict__ off_p,
-                                                  const long* __restrict__ off_q, const double* __restrict__ data,
-                                                  const double* __restrict__ X, double* __restrict__ Y, int ldx,
-                                                  int ncols) {
-  __shared__ double xb[BT_MAXBS * BT_CB];
-  __shared__ double yprev[BT_MAXBS * BT_CB];
+__global__ __launch_bounds__(256) void k_bt_sweep(int dir, int n, int nblk, const int* __restrict__ start,
+                                                  const long* __restrict__ off_m, const double* __restrict__ data,
+                                                  double* __restrict__ Y, int ldx, int ncols) {
+  __shared__ double prev[(BT_MAXBS + BT_KU) * BT_CB];
+  for (int e = threadIdx.x; e < (BT_MAXBS + BT_KU) * BT_CB; e += 256) prev[e] = 0.0;
+  __syncthreads();
   const int comp = blockIdx.y;
   const int c0 = blockIdx.x * BT_CB;
   const int nc = min(BT_CB, ncols - c0);
-  const double* Xc = X + (long)comp * n * ldx + c0;
   double* Yc = Y + (long)comp * n * ldx + c0;
   const int tid = threadIdx.x;
-  // forward: y_b = Sinv_b x_b - P_b y_{b-1}
-  int prevbs = 0;
-  for (int b = 0; b < nblk; ++b) {
-    const int r0 = start[b], bs = start[b + 1] - r0;
-    for (int e = tid; e < bs * BT_CB; e += 256) {
-      int r = e % bs, c = e / bs;
-      xb[c * BT_MAXBS + r] = (c < nc) ? Xc[(long)(r0 + r) * ldx + c] : 0.0;
+  const int half = tid / 128, rr = tid % 128;
+  const int cb0 = half * (BT_CB / 2);
+  // initial block: b0 = 0 (forward) or nblk-1 (backward)
+  int b = dir == 0 ? 0 : nblk - 1;
+  int r0 = start[b], bs = start[b + 1] - r0;
+  for (int e = tid; e < bs * BT_CB; e += 256) {
+    int r = e / BT_CB, c = e % BT_CB;
+    prev[r * BT_CB + c] = (c < nc) ? Yc[(long)(r0 + r) * ldx + c] : 0.0;
+  }
+  __syncthreads();
+  int prevbs = bs;
+  for (int step = 1; step < nblk; ++step) {
+    b = dir == 0 ? step : nblk - 1 - step;
+    r0 = start[b];
+    bs = start[b + 1] - r0;
+    const double* M = data + off_m[b];   // bs x prevbs, column-major
+    double acc[2][BT_CB / 2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int c = 0; c < BT_CB / 2; ++c) acc[i][c] = 0.0;
+    // 16 independent loads in flight per thread per chunk of k
+    for (int k0 = 0; k0 < prevbs; k0 += BT_KU) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = rr + 128 * i;
+        if (r >= bs) continue;
+        double m[BT_KU];
+#pragma unroll
+        for (int u = 0; u < BT_KU; ++u) m[u] = (k0 + u < prevbs) ? M[(long)(k0 + u) * bs + r] : 0.0;
+#pragma unroll
+        for (int u = 0; u < BT_KU; ++u) {
+          const double* pk = prev + (k0 + u) * BT_CB + cb0;
+#pragma unroll
+          for (int c = 0; c < BT_CB / 2; ++c) acc[i][c] = fma(m[u], pk[c], acc[i][c]);
+        }
+      }
     }
     __syncthreads();
-    const double* Si = data + off_sinv[b];
-    const double* Pb = (b > 0) ? data + off_p[b] : nullptr;
-    double outv[(BT_MAXBS * BT_CB + 255) / 256];
-    int cnt = 0;
-    for (int e = tid; e < bs * BT_CB; e += 256, ++cnt) {
-      int r = e % bs, c = e / bs;
-      double s = 0.0;
-      for (int kk = 0; kk < bs; ++kk) s = fma(Si[(long)kk * bs + r], xb[c * BT_MAXBS + kk], s);
-      if (Pb)
-        for (int kk = 0; kk < prevbs; ++kk) s = fma(-Pb[(long)kk * bs + r], yprev[c * BT_MAXBS + kk], s);
-      outv[cnt] = s;
-    }
-    __syncthreads();
-    cnt = 0;
-    for (int e = tid; e < bs * BT_CB; e += 256, ++cnt) {
-      int r = e % bs, c = e / bs;
-      yprev[c * BT_MAXBS + r] = outv[cnt];
-      if (c < nc) Yc[(long)(r0 + r) * ldx + c] = outv[cnt];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int r = rr + 128 * i;
+      if (r < bs) {
+#pragma unroll
+        for (int c = 0; c < BT_CB / 2; ++c) {
+          int cc = cb0 + c;
+          double v = (cc < nc) ? Yc[(long)(r0 + r) * ldx + cc] - acc[i][c] : 0.0;
+          prev[r * BT_CB + cc] = v;
+          if (cc < nc) Yc[(long)(r0 + r) * ldx + cc] = v;
+        }
+      }
     }
     __syncthreads();
     prevbs = bs;
   }
-  // backward: x_b = y_b - Q_b x_{b+1}; yprev holds x_{b+1}
-  int nextbs = prevbs;   // block nblk-1 is final already (x = y)
-  for (int b = nblk - 2; b >= 0; --b) {
-    const int r0 = start[b], bs = start[b + 1] - r0;
-    const double* Qb = data + off_q[b];
-    double outv[(BT_MAXBS * BT_CB + 255) / 256];
-    int cnt = 0;
-    for (int e = tid; e < bs * BT_CB; e += 256, ++cnt) {
-      int r = e % bs, c = e / bs;
-      double s = (c < nc) ? Yc[(long)(r0 + r) * ldx + c] : 0.0;
-      for (int kk = 0; kk < nextbs; ++kk) s = fma(-Qb[(long)kk * bs + r], yprev[c * BT_MAXBS + kk], s);
-      outv[cnt] = s;
+}
+
+// parallel stage: Y_b = Sinv_b X_b for every block b (grid.x), component
+// (grid.y) and column chunk (grid.z); X and Y may alias.
+__global__ __launch_bounds__(256) void k_bt_diag(int n, const int* __restrict__ start, const long* __restrict__ off_sinv,
+                                                 const double* __restrict__ data, const double* X, double* Y, int ldx,
+                                                 int ncols) {
+  __shared__ double xb[(BT_MAXBS + BT_KU) * BT_CB];
+  for (int e = threadIdx.x; e < (BT_MAXBS + BT_KU) * BT_CB; e += 256) xb[e] = 0.0;
+  __syncthreads();
+  const int b = blockIdx.x, comp = blockIdx.y;
+  const int c0 = blockIdx.z * BT_CB;
+  const int nc = min(BT_CB, ncols - c0);
+  const int r0 = start[b], bs = start[b + 1] - r0;
+  const double* Xc = X + ((long)comp * n + r0) * ldx + c0;
+  double* Yc = Y + ((long)comp * n + r0) * ldx + c0;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < bs * BT_CB; e += 256) {
+    int r = e / BT_CB, c = e % BT_CB;
+    xb[r * BT_CB + c] = (c < nc) ? Xc[(long)r * ldx + c] : 0.0;
+  }
+  __syncthreads();
+  const int half = tid / 128, rr = tid % 128;
+  const int cb0 = half * (BT_CB / 2);
+  const double* M = data + off_sinv[b];
+  double acc[2][BT_CB / 2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int c = 0; c < BT_CB / 2; ++c) acc[i][c] = 0.0;
+  for (int k0 = 0; k0 < bs; k0 += BT_KU) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = rr + 128 * i;
+      if (r >= bs) continue;
+      double m[BT_KU];
+#pragma unroll
+      for (int u = 0; u < BT_KU; ++u) m[u] = (k0 + u < bs) ? M[(long)(k0 + u) * bs + r] : 0.0;
+#pragma unroll
+      for (int u = 0; u < BT_KU; ++u) {
+        const double* xk = xb + (k0 + u) * BT_CB + cb0;
+#pragma unroll
+        for (int c = 0; c < BT_CB / 2; ++c) acc[i][c] = fma(m[u], xk[c], acc[i][c]);
+      }
     }
-    __syncthreads();
-    cnt = 0;
-    for (int e = tid; e < bs * BT_CB; e += 256, ++cnt) {
-      int r = e % bs, c = e / bs;
-      yprev[c * BT_MAXBS + r] = outv[cnt];
-      if (c < nc) Yc[(long)(r0 + r) * ldx + c] = outv[cnt];
+  }
+  __syncthreads();   // X may alias Y: all reads of this block are done
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    int r = rr + 128 * i;
+    if (r < bs) {
+#pragma unroll
+      for (int c = 0; c < BT_CB / 2; ++c)
+        if (cb0 + c < nc) Yc[(long)r * ldx + cb0 + c] = acc[i][c];
     }
-    __syncthreads();
-    nextbs = bs;
   }
 }
 
@@ -667,31 +825,91 @@ __global__ void k_mgs_coef(int k, const double* d, const double* GV, int ldg, do
 }  // namespace
 
 // ====================================================================== launchers
+namespace {
+// library-internal workspace for split-K partial sums, one per stream (work
+// on one stream is ordered, so the buffer is reused safely); grown on demand
+std::mutex g_splitk_mu;
+std::unordered_map<hipStream_t, std::pair<double*, size_t>> g_splitk;
+double* splitk_ws(hipStream_t s, size_t n) {
+  std::lock_guard<std::mutex> lk(g_splitk_mu);
+  auto& e = g_splitk[s];
+  if (n > e.second) {
+    if (e.first) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(e.first);
+    }
+    e.first = nullptr;
+    e.second = 0;
+    if (hipMalloc(&e.first, n * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      e.first = nullptr;
+      return nullptr;
+    }
+    e.second = n;
+  }
+  return e.first;
+}
+
+__global__ void k_reduce_scaled(int nb, int m, int n, const double* __restrict__ ws, double alpha, double beta,
+                                double* __restrict__ C, long sCi, long sCj) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long ne = (long)m * n;
+  if (e >= ne) return;
+  double sum = 0.0;
+  for (int b = 0; b < nb; ++b) sum += ws[(long)b * ne + e];
+  long i = e / n, j = e % n;
+  double* cp = C + i * sCi + j * sCj;
+  double v = alpha * sum;
+  if (beta != 0.0) v += beta * (*cp);
+  *cp = v;
+}
+}  // namespace
+
 void gemm(hipStream_t s, int batch, int m, int n, int k, double alpha, const double* A, long sAb, long sAi, long sAk,
           const double* B, long sBb, long sBk, long sBj, double beta, double* C, long sCb, long sCi, long sCj,
           int kstep, long klimit) {
   if (m <= 0 || n <= 0 || batch <= 0) return;
-  if (k <= 0) {
-    // C = beta * C
-    dim3 grid(cdiv(n, TN), cdiv(m, TM), batch);
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, m, n, 0, alpha, A, sAb, sAi, sAk, B, sBb, sBk, sBj, beta, C,
-                       sCb, sCi, sCj, kstep, klimit);
-    return;
+  const long tiles = (long)cdiv(m, TM) * cdiv(n, TN);
+  if (batch == 1 && klimit == 0 && tiles <= 16 && k >= 2048) {
+    // small output, long reduction: split K over workgroups, then reduce
+    long nch = std::min<long>(k / 512, 256 / tiles);
+    long ne = (long)m * n;
+    double* ws = nch > 1 ? splitk_ws(s, (size_t)(nch * ne)) : nullptr;
+    if (ws) {
+      long chunk = (k + nch - 1) / nch;
+      nch = (k + chunk - 1) / chunk;
+      dim3 grid(cdiv(n, TN), cdiv(m, TM), (unsigned)nch);
+      hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, m, n, (int)chunk, 1.0, A, chunk * sAk, sAi, sAk, B,
+                         chunk * sBk, sBk, sBj, 0.0, ws, ne, (long)n, 1L, (int)chunk, (long)k);
+      hipLaunchKernelGGL(k_reduce_scaled, dim3(cdiv(ne, 256)), dim3(256), 0, s, (int)nch, m, n, ws, alpha, beta, C,
+                         sCi, sCj);
+      return;
+    }
   }
   dim3 grid(cdiv(n, TN), cdiv(m, TM), batch);
   hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, m, n, k, alpha, A, sAb, sAi, sAk, B, sBb, sBk, sBj, beta, C, sCb,
                      sCi, sCj, kstep, klimit);
 }
 
+void gemm_batched(hipStream_t s, int nb, const GemmDesc* d_desc, int max_m, int max_n) {
+  if (nb <= 0 || max_m <= 0 || max_n <= 0) return;
+  for (int b0 = 0; b0 < nb; b0 += 65535) {
+    int n = std::min(65535, nb - b0);
+    dim3 grid(cdiv(max_n, TN), cdiv(max_m, TM), n);
+    hipLaunchKernelGGL(k_gemm_ptr, grid, dim3(256), 0, s, d_desc + b0);
+  }
+}
+
 void gram(hipStream_t s, long rows, int nx, int ny, const double* X, long sXr, long sXc, const double* Y, long sYr,
           long sYc, double* out, double* ws, size_t ws_doubles) {
   const long ne = (long)nx * ny;
-  long nch = std::max<long>(1, std::min<long>((rows + 511) / 512, (long)(ws_doubles / std::max<long>(ne, 1))));
-  nch = std::min<long>(nch, 2048);
   if (rows <= 0) {
     fill(s, out, ne, 0.0);
     return;
   }
+  const long tiles = (long)cdiv(nx, TM) * cdiv(ny, TN);
+  long nch = std::min<long>(rows / 128, 1024 / tiles);
+  nch = std::min<long>(nch, (long)(ws_doubles / std::max<long>(ne, 1)));
   if (nch <= 1) {
     gemm(s, 1, nx, ny, (int)std::min<long>(rows, INT_MAX), 1.0, X, 0, sXc, sXr, Y, 0, sYr, sYc, 0.0, out, 0, ny, 1);
     return;
@@ -700,7 +918,7 @@ void gram(hipStream_t s, long rows, int nx, int ny, const double* X, long sXr, l
   nch = (rows + chunk - 1) / chunk;
   gemm(s, (int)nch, nx, ny, (int)chunk, 1.0, X, chunk * sXr, sXc, sXr, Y, chunk * sYr, sYr, sYc, 0.0, ws, ne, ny, 1,
        (int)chunk, rows);
-  hipLaunchKernelGGL(k_reduce_partials, dim3(cdiv(ne, 256)), dim3(256), 0, s, (int)nch, ne, ws, out);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(cdiv(ne, 64)), dim3(256), 0, s, (int)nch, ne, ws, out);
 }
 
 void sumsq(hipStream_t s, const double* x, long n, double* out, double* ws, size_t ws_doubles) {
@@ -721,6 +939,13 @@ void copy2d(hipStream_t s, int rows, int cols, const double* src, long lds, doub
   if (total <= 0) return;
   unsigned nb = std::min<unsigned>(cdiv(total, 256), 8192);
   hipLaunchKernelGGL(k_copy2d, dim3(nb), dim3(256), 0, s, rows, cols, src, lds, dst, ldd, alpha, dscale, inv);
+}
+
+void transpose_copy(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst, long ldd) {
+  long total = (long)rows * cols;
+  if (total <= 0) return;
+  unsigned nb = std::min<unsigned>(cdiv(total, 256), 8192);
+  hipLaunchKernelGGL(k_transpose_copy, dim3(nb), dim3(256), 0, s, rows, cols, src, lds, dst, ldd);
 }
 
 void spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* rowptr, const int* col, const double* vals,
@@ -769,8 +994,13 @@ void blocktri_solve(hipStream_t s, int n, int nblk, int maxbs, const int* start,
                     const long* off_q, const double* data, int ncomp, double* X, int ldx, int ncols, double* Y) {
   if (ncols <= 0) return;
   (void)maxbs;
+  // parallel stage: Y_b = Sinv_b X_b for all blocks and components
+  hipLaunchKernelGGL(k_bt_diag, dim3(nblk, ncomp, cdiv(ncols, BT_CB)), dim3(256), 0, s, n, start, off_sinv, data, X, Y,
+                     ldx, ncols);
+  // sequential sweeps
   dim3 grid(cdiv(ncols, BT_CB), ncomp);
-  hipLaunchKernelGGL(k_blocktri, grid, dim3(256), 0, s, n, nblk, start, off_sinv, off_p, off_q, data, X, Y, ldx, ncols);
+  hipLaunchKernelGGL(k_bt_sweep, grid, dim3(256), 0, s, 0, n, nblk, start, off_p, data, Y, ldx, ncols);
+  hipLaunchKernelGGL(k_bt_sweep, grid, dim3(256), 0, s, 1, n, nblk, start, off_q, data, Y, ldx, ncols);
 }
 
 void hessenberg_lsq(hipStream_t s, const double* H, int ld, int k, const double* beta, double* y, double* resid) {

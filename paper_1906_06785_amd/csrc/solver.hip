@@ -275,11 +275,30 @@ struct SolveCounters {
   int verbose = 0;
 };
 
+// Core-3 Gram blocks of a growing basis, per TT component: blk(c, i, j) for
+// i <= j holds basis_i.core3^T basis_j.core3 (device, pool-owned).
+struct GramCache {
+  Ctx* c = nullptr;
+  int nc = 2, cap = 0;
+  std::vector<double*> blk;   // [comp][i][j]
+  GramCache(Ctx& ctx, int ncomp, int capacity) : c(&ctx), nc(ncomp), cap(capacity) {
+    blk.assign((size_t)nc * cap * cap, nullptr);
+  }
+  double*& at(int comp, int i, int j) { return blk[((size_t)comp * cap + i) * cap + j]; }
+  ~GramCache() {
+    for (double* p : blk) c->pool.put(p);
+  }
+};
+
 // Low-rank flexible GMRES (Alg. 4.2) with z_0 = 0.  dscal: device scratch of
-// at least (maxit+2)^2 * 2 + 16 * (maxit+2) doubles.
+// at least (maxit+1)*maxit + (maxit+1)^2 + 3*(maxit+1) + maxit + 16 doubles.
+// explicit_res = true follows Alg. 4.2 literally (z_k and s_k = T(b - L z_k)
+// every iteration); false stops on the least-squares residual estimate
+// |rotated rhs| and forms z once at the end of the cycle.
 Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int maxit, double* dscal, int& iters,
-                   double& relres, SolveCounters* cnt, const char* tag) {
+                   double& relres, SolveCounters* cnt, const char* tag, bool explicit_res) {
   const int ld = maxit + 1;
+  const int nc = b.nc;
   double* H = dscal;                          // ld x maxit, column-major
   double* GV = H + (size_t)ld * maxit;        // ld x ld
   double* d = GV + (size_t)ld * ld;           // ld
@@ -289,8 +308,8 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
   fill(c.s, H, (long)ld * maxit, 0.0);
   // line 1: s_0 = T(b), beta = ||s_0||, v_1 = s_0 / beta
   Vec s = vec_round(c, b, eps, sc + 0, sc + 2);
-  scalar_op(c.s, 0, sc + 0, b.nc > 1 ? sc + 1 : nullptr, sc + 4);   // ||b||
-  scalar_op(c.s, 0, sc + 2, b.nc > 1 ? sc + 3 : nullptr, sc + 5);   // beta
+  scalar_op(c.s, 0, sc + 0, nc > 1 ? sc + 1 : nullptr, sc + 4);   // ||b||
+  scalar_op(c.s, 0, sc + 2, nc > 1 ? sc + 3 : nullptr, sc + 5);   // beta
   SGTT_HIP(hipMemcpyAsync(c.hdbl, sc + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, c.s));
   c.sync();
   const double bnorm = c.hdbl[0], beta = c.hdbl[1];
@@ -301,8 +320,16 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
     Vec z = vec_copy(c, s);
     return z;
   }
+  GramCache KV(c, nc, maxit + 1), KVh(c, nc, maxit + 1), KX(c, nc, maxit + 1);
+  auto dot_cached = [&](const Vec& x, const Vec& yv, double* dout, GramCache& G, int i, int j) {
+    for (int q = 0; q < nc; ++q) {
+      double*& slot = G.at(q, i, j);
+      if (!slot) slot = c.pool.get((size_t)x.c[q].r2 * yv.c[q].r2);
+      tt_dot(c, x.c[q], yv.c[q], dout, q > 0, slot);
+    }
+  };
   V.push_back(vec_scale3(c, std::move(s), sc + 5, 1));
-  vec_dot(c, V[0], V[0], GV);
+  dot_cached(V[0], V[0], GV, KV, 0, 0);
   Vec z;
   double res = beta;
   int k = 0;
@@ -314,50 +341,111 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
     if (cnt) cnt->t_prec += t1 - t0;
     Vec x = vec_round(c, sp.apply(vh), eps, nullptr, nullptr);
     Vh.push_back(std::move(vh));
-    for (int i = 0; i < k; ++i) vec_dot(c, x, V[i], d + i);
+    // Gram blocks of the preconditioned basis (for the solution sum)
+    for (int q = 0; q < nc; ++q)
+      for (int i = 0; i < k; ++i) {
+        double*& slot = KVh.at(q, i, k - 1);
+        const TT& ti = Vh[i].c[q];
+        const TT& tj = Vh[k - 1].c[q];
+        slot = c.pool.get((size_t)ti.r2 * tj.r2);
+        size_t wsn = std::max<size_t>((size_t)ti.r2 * tj.r2 * 256, 1 << 22);
+        gram(c.s, ti.n3, ti.r2, tj.r2, ti.c3, ti.r2, 1, tj.c3, tj.r2, 1, slot, c.scratch(wsn), wsn);
+      }
+    // lines 6-9: modified Gram-Schmidt coefficients from <x, v_i> and the
+    // Gram matrix of the basis (exact in exact arithmetic)
+    for (int i = 0; i < k; ++i) {
+      for (int q = 0; q < nc; ++q) {
+        double*& slot = KX.at(q, 0, i);
+        c.pool.put(slot);
+        slot = c.pool.get((size_t)x.c[q].r2 * V[i].c[q].r2);
+        tt_dot(c, x.c[q], V[i].c[q], d + i, q > 0, slot);
+      }
+    }
     mgs_coef(c.s, k, d, GV, ld, H + (size_t)(k - 1) * ld, coef);
-    std::vector<const Vec*> parts{&x};
-    for (int i = 0; i < k; ++i) parts.push_back(&V[i]);
-    Vec xx = vec_concat(c, parts, coef, {});
-    Vec vn = vec_round(c, xx, eps, sc + 6, nullptr);
-    scalar_op(c.s, 0, sc + 6, V[0].nc > 1 ? sc + 7 : nullptr, H + (size_t)(k - 1) * ld + k);   // h_{k+1,k}
+    // line 10: h_{k+1,k} = ||x - sum h v||, v_{k+1} = T(x / h)
+    Vec vn;
+    vn.nc = nc;
+    for (int q = 0; q < nc; ++q) {
+      std::vector<Term> terms{Term{&x.c[q], coef, 1.0}};
+      std::vector<const double*> cache((size_t)(k + 1) * (k + 1), nullptr);
+      for (int i = 0; i < k; ++i) {
+        terms.push_back(Term{&V[i].c[q], coef + 1 + i, 1.0});
+        cache[(size_t)0 * (k + 1) + 1 + i] = KX.at(q, 0, i);
+        for (int j = i; j < k; ++j) cache[(size_t)(1 + i) * (k + 1) + 1 + j] = KV.at(q, i, j);
+      }
+      vn.c[q] = tt_round_sum(c, terms, eps, sc + 6 + q, nullptr, &cache);
+    }
+    scalar_op(c.s, 0, sc + 6, nc > 1 ? sc + 7 : nullptr, H + (size_t)(k - 1) * ld + k);   // h_{k+1,k}
     double hk = read_double(c, H + (size_t)(k - 1) * ld + k);
     bool breakdown = !(hk > 1e-14 * beta);
-    if (!breakdown) {
+    if (!breakdown && k < maxit) {
       V.push_back(vec_scale3(c, std::move(vn), H + (size_t)(k - 1) * ld + k, 1));
       for (int i = 0; i <= k; ++i) {
-        vec_dot(c, V[k], V[i], GV + (size_t)i * ld + k);
+        dot_cached(V[i], V[k], GV + (size_t)i * ld + k, KV, i, k);
         if (i < k)
           SGTT_HIP(hipMemcpyAsync(GV + (size_t)k * ld + i, GV + (size_t)i * ld + k, sizeof(double),
                                   hipMemcpyDeviceToDevice, c.s));
       }
     }
+    // lines 12-13: least squares, z_k = T(V^ y)
     hessenberg_lsq(c.s, H, ld, k, sc + 5, y, sc + 8);
-    std::vector<const Vec*> hp;
-    for (int i = 0; i < k; ++i) hp.push_back(&Vh[i]);
-    Vec zz = vec_concat(c, hp, y, {});
-    z = vec_round(c, zz, eps, nullptr, nullptr);
+    if (!explicit_res) {
+      res = read_double(c, sc + 8);
+      if (cnt && cnt->verbose > 1)
+        fprintf(stderr, "[sgtt %s] it %d  est %.3e  ranks v=(%d,%d)\n", tag, k, res / bnorm, V.back().c[0].r1,
+                V.back().c[0].r2);
+      if (breakdown) break;
+      continue;
+    }
+    z = Vec();
+    z.nc = nc;
+    for (int q = 0; q < nc; ++q) {
+      std::vector<Term> terms;
+      std::vector<const double*> cache((size_t)k * k, nullptr);
+      for (int i = 0; i < k; ++i) {
+        terms.push_back(Term{&Vh[i].c[q], y + i, 1.0});
+        for (int j = i; j < k; ++j) cache[(size_t)i * k + j] = KVh.at(q, i, j);
+      }
+      z.c[q] = tt_round_sum(c, terms, eps, nullptr, nullptr, &cache);
+    }
+    // line 14: s_k = T(b - L z_k)
     double t2 = now_s();
     Vec Lz = sp.apply(z);
     if (cnt) cnt->t_apply += now_s() - t2;
-    Vec ss = vec_concat(c, {&b, &Lz}, nullptr, {1.0, -1.0});
-    Vec sk = vec_round(c, ss, eps, nullptr, sc + 9);
-    scalar_op(c.s, 0, sc + 9, b.nc > 1 ? sc + 10 : nullptr, sc + 11);
+    for (int q = 0; q < nc; ++q) {
+      std::vector<Term> terms{Term{&b.c[q], nullptr, 1.0}, Term{&Lz.c[q], nullptr, -1.0}};
+      TT sk = tt_round_sum(c, terms, eps, nullptr, sc + 9 + q, nullptr);
+      (void)sk;
+    }
+    scalar_op(c.s, 0, sc + 9, nc > 1 ? sc + 10 : nullptr, sc + 11);
     res = read_double(c, sc + 11);
     if (cnt) {
-      for (int i = 0; i < V[0].nc; ++i) {
+      for (int i = 0; i < nc; ++i) {
         int r2 = V.back().c[i].r2;
         if (i == 0) cnt->maxr_u = std::max(cnt->maxr_u, r2);
         else cnt->maxr_p = std::max(cnt->maxr_p, r2);
       }
     }
     if (cnt && cnt->verbose)
-      fprintf(stderr, "[sgtt %s] it %d  rel %.3e  ranks v=(%d,%d) z=(%d,%d)\n", tag, k, res / bnorm, V.back().c[0].r1,
-              V.back().c[0].r2, z.c[0].r1, z.c[0].r2);
+      fprintf(stderr, "[sgtt %s] it %d  rel %.3e  ranks v=(%d,%d) z=(%d,%d) Lz=(%d,%d)\n", tag, k, res / bnorm,
+              V.back().c[0].r1, V.back().c[0].r2, z.c[0].r1, z.c[0].r2, Lz.c[0].r1, Lz.c[0].r2);
     if (breakdown) break;
   }
   iters = k;
   relres = res / bnorm;
+  if (!explicit_res && k > 0) {
+    z = Vec();
+    z.nc = nc;
+    for (int q = 0; q < nc; ++q) {
+      std::vector<Term> terms;
+      std::vector<const double*> cache((size_t)k * k, nullptr);
+      for (int i = 0; i < k; ++i) {
+        terms.push_back(Term{&Vh[i].c[q], y + i, 1.0});
+        for (int j = i; j < k; ++j) cache[(size_t)i * k + j] = KVh.at(q, i, j);
+      }
+      z.c[q] = tt_round_sum(c, terms, eps, nullptr, nullptr, &cache);
+    }
+  }
   if (k == 0) z = vec_copy(c, V[0]);
   return z;
 }
@@ -383,6 +471,7 @@ struct InnerSpace : Space {
 struct PrecOpts {
   double eps = 1e-6, inner_tol = 1e-1, inner_eps = 1e-3;
   int inner_maxit = 20;
+  bool inner_explicit = false;
 };
 
 Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCounters* cnt) {
@@ -408,7 +497,7 @@ Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCoun
   int its = 0;
   double rr = 0;
   Vec v = lowrank_fgmres(c, isp, rhs, po.inner_tol, po.inner_eps, po.inner_maxit, S.dsc + 16384, its, rr, nullptr,
-                         "inner");
+                         "inner", po.inner_explicit);
   if (cnt) cnt->inner += its;
   Vec out;
   out.nc = 2;
@@ -509,6 +598,7 @@ PrecOpts prec_opts(const sgtt_solve_opts* o) {
     p.inner_tol = o->inner_tol;
     p.inner_eps = o->inner_eps;
     p.inner_maxit = o->inner_maxit;
+    p.inner_explicit = o->inner_explicit != 0;
   }
   return p;
 }
@@ -524,6 +614,8 @@ sgtt_solve_opts default_opts() {
   o.inner_eps = 1e-3;
   o.inner_maxit = 20;
   o.verbose = 0;
+  o.outer_explicit = 1;
+  o.inner_explicit = 0;
   return o;
 }
 
@@ -616,6 +708,8 @@ extern "C" {
 
 const char* sgtt_version(void) { return "sgtt 0.1 gfx950 fp64"; }
 
+static thread_local std::string g_create_err;
+
 int sgtt_context_create(int device, void* stream, sgtt_context** out) {
   if (!out) return SGTT_E_INVALID;
   sgtt_context* ctx = new sgtt_context();
@@ -633,6 +727,7 @@ int sgtt_context_create(int device, void* stream, sgtt_context** out) {
     ctx->c.dint = (int*)ctx->c.pool.get(64);
     ctx->c.dscal = ctx->c.pool.get(256);
   } catch (const SgttError& e) {
+    g_create_err = e.what();
     delete ctx;
     return e.code;
   }
@@ -650,7 +745,7 @@ int sgtt_context_destroy(sgtt_context* ctx) {
   return SGTT_OK;
 }
 
-const char* sgtt_last_error(const sgtt_context* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* sgtt_last_error(const sgtt_context* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
 int sgtt_assemble(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_tt_pair* prior, sgtt_system** out) {
   if (!ctx || !desc || !out) return SGTT_E_INVALID;
@@ -1024,7 +1119,8 @@ int sgtt_solve(sgtt_system* S, const sgtt_tt_pair* b, sgtt_tt_pair* x, const sgt
     for (int cyc = 0; cyc < o.max_cycles; ++cyc) {
       int its = 0;
       double rr = 0;
-      Vec d = lowrank_fgmres(c, sp, r, o.tol_cycle, o.eps_krylov, o.restart, S->dsc, its, rr, &cnt, "outer");
+      Vec d = lowrank_fgmres(c, sp, r, o.tol_cycle, o.eps_krylov, o.restart, S->dsc, its, rr, &cnt, "outer",
+                             o.outer_explicit != 0);
       cnt.outer += its;
       ++cycles;
       terms.push_back(std::move(d));

@@ -88,13 +88,28 @@ TT tt_copy(Ctx& c, const TT& x);
 
 // sum_i coef_i x_i by concatenation; coefficient i = hcoef[i] * (dcoef ? dcoef[i] : 1)
 TT tt_concat(Ctx& c, const std::vector<const TT*>& xs, const double* dcoef, const std::vector<double>& hcoef);
-// <x, y> into *dout (device); accumulate if acc
-void tt_dot(Ctx& c, const TT& x, const TT& y, double* dout, int acc);
-// T_eps(x) (Gram-based, FP64).  Writes ||x||^2 to *d_normsq and the squared
-// norm of the result to *d_kept (device) when non-null.  maxrank caps ranks.
-TT tt_round(Ctx& c, const TT& x, double eps, double* d_normsq, double* d_kept, int maxrank = 96);
+// <x, y> into *dout (device); accumulate if acc.  If k3_out is given, the
+// core-3 cross Gram X3^T Y3 (x.r2 x y.r2, row-major) is left there.
+void tt_dot(Ctx& c, const TT& x, const TT& y, double* dout, int acc, double* k3_out = nullptr);
+
+// One term of a sum of TTs: coefficient = hcoef * (dcoef ? *dcoef : 1).
+struct Term {
+  const TT* t;
+  const double* dcoef;
+  double hcoef;
+};
+constexpr int RANK_CAP = 512;
+// T_eps(sum_i c_i t_i) (Gram-based, FP64), exploiting the block structure of
+// the concatenated cores.  cache (k*k, row-major, may be null or hold nulls):
+// cache[i*k + j] for i <= j = device block t_i.core3^T t_j.core3 (row-major).
+// Writes ||sum||^2 to *d_normsq and the squared norm of the result to
+// *d_kept (device) when non-null.
+TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_normsq, double* d_kept,
+                const std::vector<const double*>* cache = nullptr, int maxrank = RANK_CAP);
+TT tt_round(Ctx& c, const TT& x, double eps, double* d_normsq, double* d_kept, int maxrank = RANK_CAP);
 // TT-SVD (Alg. 4.1) of a full n1 x n2 x n3 tensor (device, C order)
-TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, double* d_normsq, int maxrank = 96);
+TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, double* d_normsq,
+                int maxrank = RANK_CAP);
 // full tensor (device buffer of n1*n2*n3)
 void tt_expand(Ctx& c, const TT& x, double* out);
 // scale core3 by *dscale (inv: 1 / *dscale)

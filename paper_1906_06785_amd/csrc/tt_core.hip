@@ -149,13 +149,13 @@ TT tt_concat(Ctx& c, const std::vector<const TT*>& xs, const double* dcoef, cons
   return t;
 }
 
-void tt_dot(Ctx& c, const TT& x, const TT& y, double* dout, int acc) {
+void tt_dot(Ctx& c, const TT& x, const TT& y, double* dout, int acc, double* k3_out) {
   const int n1 = x.n1, n2 = x.n2;
   const int a1 = x.r1, a2 = x.r2, b1 = y.r1, b2 = y.r2;
   double* W1 = c.pool.get((size_t)a1 * b1);
   double* Z = c.pool.get((size_t)a1 * n2 * b2);
   double* W2 = c.pool.get((size_t)a2 * b2);
-  double* K3 = c.pool.get((size_t)a2 * b2);
+  double* K3 = k3_out ? k3_out : c.pool.get((size_t)a2 * b2);
   // W1 = X1^T Y1
   gemm(c.s, 1, a1, b1, n1, 1.0, x.c1, 0, 1, a1, y.c1, 0, b1, 1, 0.0, W1, 0, b1, 1);
   // Z = W1 Y2 (flattened a1 x (n2 b2))
@@ -163,13 +163,13 @@ void tt_dot(Ctx& c, const TT& x, const TT& y, double* dout, int acc) {
   // W2 = X2flat^T Zflat over (a, i)
   gemm(c.s, 1, a2, b2, a1 * n2, 1.0, x.c2, 0, 1, a2, Z, 0, b2, 1, 0.0, W2, 0, b2, 1);
   // K3 = X3^T Y3 over space
-  size_t wsn = std::max<size_t>((size_t)a2 * b2 * 64, 1 << 20);
+  size_t wsn = std::max<size_t>((size_t)a2 * b2 * 256, 1 << 22);
   gram(c.s, x.n3, a2, b2, x.c3, a2, 1, y.c3, b2, 1, K3, c.scratch(wsn), wsn);
   dot_reduce(c.s, (long)a2 * b2, W2, K3, dout, acc);
   c.pool.put(W1);
   c.pool.put(Z);
   c.pool.put(W2);
-  c.pool.put(K3);
+  if (!k3_out) c.pool.put(K3);
 }
 
 static void read_ints(Ctx& c, const int* d, int n, int* h) {
@@ -178,62 +178,155 @@ static void read_ints(Ctx& c, const int* d, int n, int* h) {
   std::memcpy(h, c.hint, sizeof(int) * n);
 }
 
-TT tt_round(Ctx& c, const TT& x, double eps, double* d_normsq, double* d_kept, int maxrank) {
+namespace {
+double* upload_descs(Ctx& c, const std::vector<GemmDesc>& d) {
+  size_t nd = (d.size() * sizeof(GemmDesc) + sizeof(double) - 1) / sizeof(double);
+  double* buf = c.pool.get(nd);
+  SGTT_HIP(hipMemcpyAsync(buf, d.data(), d.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, c.s));
+  return buf;
+}
+}  // namespace
+
+TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_normsq, double* d_kept,
+                const std::vector<const double*>* cache, int maxrank) {
   ++c.roundings;
-  const int n1 = x.n1, n2 = x.n2, n3 = x.n3, R1 = x.r1, R2 = x.r2;
-  int* dk = c.dint;               // [0]=k1 [1]=info1 [2]=k2 [3]=info2
+  const int k = (int)terms.size();
+  const TT& t0 = *terms[0].t;
+  const int n1 = t0.n1, n2 = t0.n2, n3 = t0.n3;
+  std::vector<int> a(k), b(k), oa(k + 1, 0), ob(k + 1, 0);
+  for (int i = 0; i < k; ++i) {
+    a[i] = terms[i].t->r1;
+    b[i] = terms[i].t->r2;
+    oa[i + 1] = oa[i] + a[i];
+    ob[i + 1] = ob[i] + b[i];
+  }
+  const int R1 = oa[k], R2 = ob[k];
+  // GEMM descriptor lists stay alive until the stream has been synchronized
+  std::vector<GemmDesc> d1, d2, dC;
+  int* dk = c.dint;   // [0]=k1 [1]=info1 [2]=k2 [3]=info2
   double* dnorm = d_normsq ? d_normsq : c.dscal + 250;
   double* dkept1 = c.dscal + 251;
   double* dkept2 = d_kept ? d_kept : c.dscal + 252;
-  // K3 = G3^T G3
+  // ---- K3 = G3^T G3 (R2 x R2) assembled from blocks (cached or computed)
   double* K3 = c.pool.get((size_t)R2 * R2);
-  size_t wsn = std::max<size_t>((size_t)R2 * R2 * 64, 1 << 20);
-  gram(c.s, n3, R2, R2, x.c3, R2, 1, x.c3, R2, 1, K3, c.scratch(wsn), wsn);
-  // T = G2flat (R1 n2 x R2) K3
-  double* T = c.pool.get((size_t)R1 * n2 * R2);
-  gemm(c.s, 1, R1 * n2, R2, R2, 1.0, x.c2, 0, R2, 1, K3, 0, R2, 1, 0.0, T, 0, R2, 1);
-  // K2 = T' G2'^T with ' = R1 x (n2 R2)
+  int maxb = 0;
+  for (int i = 0; i < k; ++i) maxb = std::max(maxb, b[i]);
+  double* blk = c.pool.get((size_t)maxb * maxb);
+  for (int i = 0; i < k; ++i)
+    for (int j = i; j < k; ++j) {
+      const double* src = cache ? (*cache)[(size_t)i * k + j] : nullptr;
+      if (!src) {
+        size_t wsn = std::max<size_t>((size_t)b[i] * b[j] * 256, 1 << 22);
+        gram(c.s, n3, b[i], b[j], terms[i].t->c3, b[i], 1, terms[j].t->c3, b[j], 1, blk, c.scratch(wsn), wsn);
+        src = blk;
+      }
+      copy2d(c.s, b[i], b[j], src, b[j], K3 + (size_t)ob[i] * R2 + ob[j], R2, 1.0, nullptr, 0);
+      if (j != i) transpose_copy(c.s, b[i], b[j], src, b[j], K3 + (size_t)ob[j] * R2 + ob[i], R2);
+    }
+  c.pool.put(blk);
+  // ---- G1 = [c_i A_i] (n1 x R1)
+  double* G1 = c.pool.get((size_t)n1 * R1);
+  for (int i = 0; i < k; ++i)
+    copy2d(c.s, n1, a[i], terms[i].t->c1, a[i], G1 + oa[i], R1, terms[i].hcoef, terms[i].dcoef, 0);
+  // ---- K2 (R1 x R1): K2_ij = sum_l B_i,l K3_ij B_j,l^T via T_ij = B_i K3_ij
   double* K2 = c.pool.get((size_t)R1 * R1);
-  gemm(c.s, 1, R1, R1, n2 * R2, 1.0, T, 0, (long)n2 * R2, 1, x.c2, 0, 1, (long)n2 * R2, 0.0, K2, 0, R1, 1);
-  // S1 = G1 K2 G1^T
+  {
+    std::vector<size_t> toff((size_t)k * k + 1, 0);
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) toff[(size_t)i * k + j + 1] = toff[(size_t)i * k + j] + (size_t)a[i] * n2 * b[j];
+    double* Tb = c.pool.get(toff[(size_t)k * k]);
+    int mm1 = 0, nn1 = 0, mm2 = 0, nn2 = 0;
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        double* Tij = Tb + toff[(size_t)i * k + j];
+        // T_ij (a_i n2 x b_j) = B_iflat (a_i n2 x b_i) * K3[ob_i.., ob_j..]
+        d1.push_back(GemmDesc{a[i] * n2, b[j], b[i], 1.0, 0.0, terms[i].t->c2, b[i], 1,
+                              K3 + (size_t)ob[i] * R2 + ob[j], R2, 1, Tij, b[j], 1});
+        mm1 = std::max(mm1, a[i] * n2);
+        nn1 = std::max(nn1, b[j]);
+        // K2_ij (a_i x a_j) = T_ij' (a_i x n2 b_j) * B_j'^T (n2 b_j x a_j)
+        d2.push_back(GemmDesc{a[i], a[j], n2 * b[j], 1.0, 0.0, Tij, (long)n2 * b[j], 1, terms[j].t->c2, 1,
+                              (long)n2 * b[j], K2 + (size_t)oa[i] * R1 + oa[j], R1, 1});
+        mm2 = std::max(mm2, a[i]);
+        nn2 = std::max(nn2, a[j]);
+      }
+    double* dd1 = upload_descs(c, d1);
+    gemm_batched(c.s, (int)d1.size(), (const GemmDesc*)dd1, mm1, nn1);
+    double* dd2 = upload_descs(c, d2);
+    gemm_batched(c.s, (int)d2.size(), (const GemmDesc*)dd2, mm2, nn2);
+    c.pool.put(dd1);
+    c.pool.put(dd2);
+    c.pool.put(Tb);
+  }
+  // ---- S1 = G1 K2 G1^T (n1 x n1), truncate bond 1
   double* T1 = c.pool.get((size_t)n1 * R1);
-  gemm(c.s, 1, n1, R1, R1, 1.0, x.c1, 0, R1, 1, K2, 0, R1, 1, 0.0, T1, 0, R1, 1);
+  gemm(c.s, 1, n1, R1, R1, 1.0, G1, 0, R1, 1, K2, 0, R1, 1, 0.0, T1, 0, R1, 1);
   double* S1 = c.pool.get((size_t)n1 * n1);
-  gemm(c.s, 1, n1, n1, R1, 1.0, T1, 0, R1, 1, x.c1, 0, 1, R1, 0.0, S1, 0, n1, 1);
-  const int kmax1 = std::min({n1, R1, maxrank, 96});
+  gemm(c.s, 1, n1, n1, R1, 1.0, T1, 0, R1, 1, G1, 0, 1, R1, 0.0, S1, 0, n1, 1);
+  const int kmax1 = std::min({n1, R1, maxrank, RANK_CAP});
   double* U1 = c.pool.get((size_t)n1 * kmax1);
-  double* Lw = c.scratch2((size_t)std::max(n1, n2 * kmax1) * 96 + std::max(n1, n2 * kmax1) + 64);
-  trunc_eig(c.s, n1, S1, eps, nullptr, dnorm, U1, kmax1, Lw, dk, dkept1, dk + 1, std::min(n1, R1));
+  {
+    double* Lw = c.scratch2((size_t)n1 * kmax1 + n1 + 64);
+    trunc_eig(c.s, n1, S1, eps, nullptr, dnorm, U1, kmax1, Lw, dk, dkept1, dk + 1, std::min(n1, R1));
+  }
   int h[4];
-  read_ints(c, dk, 2, h);
+  SGTT_HIP(hipMemcpyAsync(c.hint, dk, 2 * sizeof(int), hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  h[0] = c.hint[0];
+  h[1] = c.hint[1];
   if (h[1] != 0) throw SgttError(-4, "TT rank capacity exceeded (bond 1)");
   const int k1 = h[0];
-  // C1 = U1_k^T G1 (k1 x R1);  C = C1 G2' (k1 x n2 R2)
-  double* C1 = c.pool.get((size_t)k1 * R1);
-  gemm(c.s, 1, k1, R1, n1, 1.0, U1, 0, 1, kmax1, x.c1, 0, R1, 1, 0.0, C1, 0, R1, 1);
-  double* C = c.pool.get((size_t)k1 * n2 * R2);
-  gemm(c.s, 1, k1, n2 * R2, R1, 1.0, C1, 0, R1, 1, x.c2, 0, (long)n2 * R2, 1, 0.0, C, 0, (long)n2 * R2, 1);
+  // ---- C (k1 n2 x R2): block j = (U1^T c_j A_j) x_1 B_j
+  double* D = c.pool.get((size_t)k1 * R1);
+  gemm(c.s, 1, k1, R1, n1, 1.0, U1, 0, 1, kmax1, G1, 0, R1, 1, 0.0, D, 0, R1, 1);
+  double* Cm = c.pool.get((size_t)k1 * n2 * R2);
+  {
+    std::vector<GemmDesc>& d = dC;
+    int mm = 0, nn = 0;
+    for (int j = 0; j < k; ++j)
+      for (int l = 0; l < n2; ++l) {
+        d.push_back(GemmDesc{k1, b[j], a[j], 1.0, 0.0, D + oa[j], R1, 1, terms[j].t->c2 + (size_t)l * b[j],
+                             (long)n2 * b[j], 1, Cm + (size_t)l * R2 + ob[j], (long)n2 * R2, 1});
+        mm = std::max(mm, k1);
+        nn = std::max(nn, b[j]);
+      }
+    double* dd = upload_descs(c, d);
+    gemm_batched(c.s, (int)d.size(), (const GemmDesc*)dd, mm, nn);
+    c.pool.put(dd);
+  }
   const int N2 = k1 * n2;
-  // S2 = C K3 C^T
+  // ---- S2 = C K3 C^T, truncate bond 2
   double* T2 = c.pool.get((size_t)N2 * R2);
-  gemm(c.s, 1, N2, R2, R2, 1.0, C, 0, R2, 1, K3, 0, R2, 1, 0.0, T2, 0, R2, 1);
+  gemm(c.s, 1, N2, R2, R2, 1.0, Cm, 0, R2, 1, K3, 0, R2, 1, 0.0, T2, 0, R2, 1);
   double* S2 = c.pool.get((size_t)N2 * N2);
-  gemm(c.s, 1, N2, N2, R2, 1.0, T2, 0, R2, 1, C, 0, 1, R2, 0.0, S2, 0, N2, 1);
-  const int kmax2 = std::min({N2, R2, maxrank, 96});
+  gemm(c.s, 1, N2, N2, R2, 1.0, T2, 0, R2, 1, Cm, 0, 1, R2, 0.0, S2, 0, N2, 1);
+  const int kmax2 = std::min({N2, R2, maxrank, RANK_CAP});
   double* U2 = c.pool.get((size_t)N2 * kmax2);
-  trunc_eig(c.s, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw, dk + 2, dkept2, dk + 3, std::min(N2, R2));
-  read_ints(c, dk + 2, 2, h + 2);
+  {
+    double* Lw = c.scratch2((size_t)N2 * kmax2 + N2 + 64);
+    trunc_eig(c.s, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw, dk + 2, dkept2, dk + 3, std::min(N2, R2));
+  }
+  SGTT_HIP(hipMemcpyAsync(c.hint, dk + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  h[2] = c.hint[0];
+  h[3] = c.hint[1];
   if (h[3] != 0) throw SgttError(-4, "TT rank capacity exceeded (bond 2)");
   const int k2 = h[2];
-  // W = U2_k^T C (k2 x R2); new G3 = G3 W^T
+  // ---- W = U2^T C (k2 x R2); new G3 = sum_j C_j W_j^T
   double* W = c.pool.get((size_t)k2 * R2);
-  gemm(c.s, 1, k2, R2, N2, 1.0, U2, 0, 1, kmax2, C, 0, R2, 1, 0.0, W, 0, R2, 1);
+  gemm(c.s, 1, k2, R2, N2, 1.0, U2, 0, 1, kmax2, Cm, 0, R2, 1, 0.0, W, 0, R2, 1);
   TT t = tt_new(c, n1, n2, n3, k1, k2);
   copy2d(c.s, n1, k1, U1, kmax1, t.c1, k1, 1.0, nullptr, 0);
   copy2d(c.s, N2, k2, U2, kmax2, t.c2, k2, 1.0, nullptr, 0);
-  gemm(c.s, 1, n3, k2, R2, 1.0, x.c3, 0, R2, 1, W, 0, 1, R2, 0.0, t.c3, 0, k2, 1);
-  for (double* p : {K3, T, K2, T1, S1, U1, C1, C, T2, S2, U2, W}) c.pool.put(p);
+  for (int j = 0; j < k; ++j)
+    gemm(c.s, 1, n3, k2, b[j], 1.0, terms[j].t->c3, 0, b[j], 1, W + ob[j], 0, 1, R2, j == 0 ? 0.0 : 1.0, t.c3, 0,
+         k2, 1);
+  for (double* p : {K3, G1, K2, T1, S1, U1, D, Cm, T2, S2, U2, W}) c.pool.put(p);
   return t;
+}
+
+TT tt_round(Ctx& c, const TT& x, double eps, double* d_normsq, double* d_kept, int maxrank) {
+  return tt_round_sum(c, {Term{&x, nullptr, 1.0}}, eps, d_normsq, d_kept, nullptr, maxrank);
 }
 
 TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, double* d_normsq, int maxrank) {
@@ -245,9 +338,9 @@ TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, dou
   double* S1 = c.pool.get((size_t)n1 * n1);
   size_t wsn = std::max<size_t>((size_t)n1 * n1 * 256, 1 << 20);
   gram(c.s, n23, n1, n1, X, 1, n23, X, 1, n23, S1, c.scratch(wsn), wsn);
-  const int kmax1 = std::min({n1, maxrank, 96});
+  const int kmax1 = std::min({n1, maxrank, RANK_CAP});
   double* U1 = c.pool.get((size_t)n1 * kmax1);
-  double* Lw = c.scratch2((size_t)std::max(n1, n2 * kmax1) * 96 + std::max(n1, n2 * kmax1) + 64);
+  double* Lw = c.scratch2((size_t)n1 * kmax1 + n1 + 64);
   trunc_eig(c.s, n1, S1, eps, nullptr, dnorm, U1, kmax1, Lw, dk, dkept, dk + 1, n1);
   int h[4];
   read_ints(c, dk, 2, h);
@@ -259,9 +352,9 @@ TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, dou
   double* S2 = c.pool.get((size_t)N2 * N2);
   size_t wsn2 = std::max<size_t>((size_t)N2 * N2 * 64, 1 << 20);
   gram(c.s, n3, N2, N2, Y, 1, n3, Y, 1, n3, S2, c.scratch(wsn2), wsn2);
-  const int kmax2 = std::min({N2, maxrank, 96});
+  const int kmax2 = std::min({N2, maxrank, RANK_CAP});
   double* U2 = c.pool.get((size_t)N2 * kmax2);
-  double* Lw2 = c.scratch2((size_t)std::max(n1, N2) * 96 + std::max(n1, N2) + 64);
+  double* Lw2 = c.scratch2((size_t)N2 * kmax2 + N2 + 64);
   trunc_eig(c.s, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw2, dk + 2, dkept, dk + 3, std::min(N2, n3));
   read_ints(c, dk + 2, 2, h + 2);
   if (h[3] != 0) throw SgttError(-4, "TT rank capacity exceeded (full bond 2)");

@@ -16,6 +16,10 @@ LIB_PATH = os.path.join(_HERE, "libsgtt.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"sgtt native library not built: {LIB_PATH} (run paper_1906_06785_amd.build)")
+# PyTorch owns device memory and streams; load its HIP runtime first so that
+# libsgtt.so binds to the same libamdhip64.so.7 (one HIP runtime per process).
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 SGTT_OK = 0
@@ -48,7 +52,8 @@ class SystemInfo(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("eps_krylov", C.c_double), ("tol_cycle", C.c_double),
                 ("restart", C.c_int), ("max_cycles", C.c_int), ("inner_tol", C.c_double),
-                ("inner_eps", C.c_double), ("inner_maxit", C.c_int), ("verbose", C.c_int)]
+                ("inner_eps", C.c_double), ("inner_maxit", C.c_int), ("verbose", C.c_int),
+                ("outer_explicit", C.c_int), ("inner_explicit", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -112,10 +117,11 @@ def make_desc(cfg: dict, eps_conv=1e-3, eps_rhs=1e-6) -> ProblemDesc:
 
 def make_opts(**kw) -> SolveOpts:
     d = dict(tol=1e-8, eps_krylov=1e-6, tol_cycle=1e-4, restart=30, max_cycles=8, inner_tol=1e-1,
-             inner_eps=1e-3, inner_maxit=20, verbose=0)
+             inner_eps=1e-3, inner_maxit=20, verbose=0, outer_explicit=1, inner_explicit=0)
     d.update(kw)
     return SolveOpts(d["tol"], d["eps_krylov"], d["tol_cycle"], int(d["restart"]), int(d["max_cycles"]),
-                     d["inner_tol"], d["inner_eps"], int(d["inner_maxit"]), int(d["verbose"]))
+                     d["inner_tol"], d["inner_eps"], int(d["inner_maxit"]), int(d["verbose"]),
+                     int(d["outer_explicit"]), int(d["inner_explicit"]))
 
 
 # ------------------------------------------------------------------ host-only
@@ -161,7 +167,7 @@ class HostProblem:
         return coords.reshape(-1, 2), free, g
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.sgtt_host_problem_destroy(self._h)
             self._h = None
 
@@ -245,7 +251,7 @@ class Context:
         self._c = _P()
         rc = _lib.sgtt_context_create(device, stream, C.byref(self._c))
         if rc != 0:
-            raise SgttError(rc, "context create failed")
+            raise SgttError(rc, "context create failed: " + _lib.sgtt_last_error(None).decode())
 
     def check(self, rc):
         if rc < 0:
@@ -287,7 +293,7 @@ class Context:
         return y, res.value
 
     def __del__(self):
-        if getattr(self, "_c", None):
+        if getattr(self, "_c", None) and _lib is not None:
             _lib.sgtt_context_destroy(self._c)
             self._c = None
 
@@ -348,7 +354,7 @@ class System:
         return r.value
 
     def __del__(self):
-        if getattr(self, "_s", None):
+        if getattr(self, "_s", None) and _lib is not None:
             _lib.sgtt_system_destroy(self._s)
             self._s = None
 
