@@ -101,6 +101,9 @@ typedef struct {
                           every outer iteration; 0: stop a cycle on the
                           least-squares residual estimate, form z at its end */
   int inner_explicit;  /* same choice for the inner mean-matrix solve       */
+  int relax;           /* 0: fixed eps_krylov (Alg. 4.2); 1: truncate the
+                          k-th Krylov vectors with eps_krylov ||b||/||r_k-1||
+                          (capped at 1e-2), an inexact-Krylov relaxation    */
 } sgtt_solve_opts;
 
 typedef struct {
@@ -149,7 +152,11 @@ int sgtt_precondition(sgtt_system* sys, const sgtt_tt_pair* r, sgtt_tt_pair* z,
 
 /* In-place truncation T_eps (eq. 4.5-4.7): ||round(x) - x|| <= eps ||x||
  * (up to the accuracy of FP64 Gram matrices, about 1e-8 relative).  If a
- * rank would exceed max_rank (> 0) the call fails with SGTT_E_RANK_CAP. */
+ * rank would exceed max_rank (> 0; 0 means 4096) or the capacity of x, the
+ * call fails with SGTT_E_RANK_CAP.  The first rank is at most 512.  A second
+ * rank above 96 is truncated by a blocked pivoted Cholesky of the Gram
+ * matrix with a skeleton (interpolative) factor: the bound above still
+ * holds, core 2 is then not orthonormal. */
 int sgtt_round(sgtt_context* ctx, sgtt_tt* x, double eps, int max_rank);
 
 /* <x, y> = <x.u, y.u> + <x.p, y.p>; result to host memory (synchronizes). */
@@ -175,6 +182,21 @@ int sgtt_expand(sgtt_context* ctx, const sgtt_tt* x, double* out);
  * Givens rotations on the device (Alg. 4.2, line 12).  y: host, length k. */
 int sgtt_hessenberg_lsq(sgtt_context* ctx, const double* H, int k, double beta, double* y,
                         double* resid);
+
+/* ------------------------------------------------------------- profiling */
+/* Per-launch timing of the library's kernels with HIP events recorded on the
+ * context stream (process-wide switch; enabling clears earlier records).
+ * Adds two event records per launch while enabled. */
+int sgtt_profile_enable(sgtt_context* ctx, int enable);
+/* Sums since enabling, per kernel class (index = class id, see
+ * sgtt_profile_class_name): event seconds, algorithmic bytes and flops (what
+ * each launch's operation must read/write and compute, from its arguments),
+ * launch counts.  Arrays of length max_classes; *nclasses gets the number of
+ * classes.  Synchronizes the context stream. */
+int sgtt_profile_read(sgtt_context* ctx, int max_classes, double* seconds, double* bytes, double* flops,
+                      long* launches, int* nclasses);
+/* kernel symbol name of a class id (static storage) */
+const char* sgtt_profile_class_name(int cls);
 
 /* ------------------------------------------------------------- host setup */
 /* Host-only problem setup (no device calls), for inspection and checks:

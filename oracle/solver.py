@@ -106,9 +106,10 @@ class TTOps:
 # --------------------------------------------------------------------------
 # Alg. 4.2: low-rank (flexible, right-preconditioned) GMRES
 # --------------------------------------------------------------------------
-def lowrank_fgmres(ops, apply_op, precond, b, tol, eps, maxit, record=None):
+def lowrank_fgmres(ops, apply_op, precond, b, tol, eps, maxit, record=None, deadline=None):
     """Alg. 4.2 with z_0 = 0.  apply_op(x) returns the exact operator image,
-    precond(v) the preconditioned vector; returns (z_k, k, ||s_k||, ||b||)."""
+    precond(v) the preconditioned vector; returns (z_k, k, ||s_k||, ||b||).
+    deadline (time.perf_counter value) only bounds timing samples."""
     bnorm = ops.norm(b)
     s = ops.round(b, eps)
     beta = ops.norm(s)
@@ -121,6 +122,8 @@ def lowrank_fgmres(ops, apply_op, precond, b, tol, eps, maxit, record=None):
     z = ops.zero()
     res = beta
     while res > tol * bnorm and k < maxit:
+        if deadline is not None and time.perf_counter() > deadline:
+            break
         k += 1
         vh = precond(V[k - 1])
         Vhat.append(vh)
@@ -290,10 +293,12 @@ class _FlatOps:
 # driver: one Picard-step linear solve to an exact relative residual
 # --------------------------------------------------------------------------
 def solve_tt(prob, b, conv=None, tol=1e-8, eps_krylov=1e-6, tol_cycle=1e-4, restart=30,
-             max_cycles=8, inner_tol=1e-1, inner_eps=1e-3, inner_maxit=20, record=None):
+             max_cycles=8, inner_tol=1e-1, inner_eps=1e-3, inner_maxit=20, record=None, max_seconds=None):
     """Low-rank FGMRES cycles + exact-residual refinement; returns (z, stats),
-    z an exact TT sum of the cycle corrections."""
+    z an exact TT sum of the cycle corrections.  max_seconds bounds a timing
+    sample: the outer loop stops once it is exceeded (stats["sampled"])."""
     t0 = time.perf_counter()
+    deadline = None if max_seconds is None else t0 + max_seconds
     ops = TTOps(prob, conv)
     prec = MeanLSC(prob, conv, "tt", inner_tol, inner_eps, inner_maxit, eps_krylov)
     bu_f, bp_f = tt.full(b[0]), tt.full(b[1])
@@ -303,9 +308,13 @@ def solve_tt(prob, b, conv=None, tol=1e-8, eps_krylov=1e-6, tol_cycle=1e-4, rest
     stats = dict(cycles=0, outer=0, rel=[], inner=prec.inner_iters)
     for cyc in range(max_cycles):
         d, its, _, _ = lowrank_fgmres(ops, ops.apply, lambda v: prec.apply_tt(v), r,
-                                      tol_cycle, eps_krylov, restart, record)
+                                      tol_cycle, eps_krylov, restart, record, deadline)
         stats["cycles"] += 1
         stats["outer"] += its
+        if deadline is not None and time.perf_counter() > deadline:
+            stats["sampled"] = True
+            stats["time"] = time.perf_counter() - t0
+            return d, stats
         terms.append(d)
         z = tt.pair_concat(terms)
         yu, yp = prob.apply_full(tt.full(z[0]), tt.full(z[1]), conv)

@@ -7,6 +7,18 @@
 
 namespace sgtt {
 
+// ---------------------------------------------------------------- profiling
+// Optional per-launch timing with HIP events on the launch stream, with the
+// algorithmic bytes / flops of each launch (what the operation must move and
+// compute, not what the hardware counted).  Kernel classes:
+enum KernelClass { KC_GEMM = 0, KC_GEMM_PTR, KC_SPMM, KC_BT_DIAG, KC_BT_SWEEP, KC_TRUNC, KC_REDUCE, KC_OTHER, KC_COUNT };
+const char* kernel_class_name(int cls);
+void prof_enable(bool on);
+bool prof_enabled();
+// sums since the last reset: seconds (from events), bytes, flops, launches
+void prof_read(double* seconds, double* bytes, double* flops, long* launches);
+void prof_reset();
+
 // C[b](i,j) = alpha * sum_k A[b](i,k) B[b](k,j) + beta * C[b](i,j)
 // element (i,k) of A[b] at A + b*sAb + i*sAi + k*sAk (likewise B, C).
 // If klimit > 0, batch b only sums k < min(k, klimit - b*kstep) (split-K).
@@ -80,18 +92,42 @@ void core2_block(hipStream_t s, int r1, int n2, int r2, const double* in, const 
 // given, else trace(S) (written to *normsq_out).  Writes k to *k_out and
 // the kept eigenvalue sum to *kept_out.  L: scratch N x kmax (+ N).
 // *info = 1 when kmax pivots were not enough and kmax < rank_bound (the
-// largest rank the matrix can have), i.e. the rank capacity is exceeded.
+// largest rank the matrix can have), i.e. the rank capacity is exceeded;
+// *info = 2 when more than 96 pivots are needed and large_ok is set (the
+// caller then runs the blocked path); without large_ok the pivoted Cholesky
+// subspace (orthonormalized) is the truncation, up to 512 columns.
 void trunc_eig(hipStream_t s, int N, double* S, double eps, const double* normsq_in, double* normsq_out,
-               double* U, int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound);
+               double* U, int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound,
+               int large_ok = 0);
+
+// Blocked pivoted Cholesky of a symmetric PSD Gram matrix S (N x N),
+// used when more than 96 pivots are needed.  pc_init: d = diag(S),
+// state = {trace, delta^2 = eps^2 normsq / 2, zero threshold}; pc_panel: up
+// to nsteps (<= 64) pivots on the current Schur complement into the panel Lp
+// (N x nsteps, column-major), out = {pivots taken, finished}.  The caller
+// subtracts Lp Lp^T from S between panels (GEMM).
+void pc_init(hipStream_t s, int N, const double* S, double eps, const double* normsq_in, double* normsq_out,
+             double* d, double* state);
+void pc_panel(hipStream_t s, int N, const double* S, double* d, double* Lp, int* piv, int nsteps, double* state,
+              int* out, double* kept);
+// Skeleton (interpolative) factor F = L L_P^{-1} of the pivoted Cholesky
+// factor L (N x k, column-major), L_P = L[piv, :] lower triangular: then
+// S[:, piv] S[piv, piv]^{-1} = F.  F is N x k column-major; LP: k*k scratch.
+void skeleton_factor(hipStream_t s, int N, int k, const double* L, const int* piv, double* LP, double* F);
+// out[a, :] = in[piv[a], :] for a < k
+void gather_rows(hipStream_t s, int k, int cols, const double* in, long ld_in, const int* piv, double* out,
+                 long ld_out);
 
 // Block-tridiagonal solve Y = A^-1 X on ncols columns of a node-major
 // matrix (row = space index, ld = ldx) with `ncomp` components stacked by
 // rows (component c occupies rows [c*n, (c+1)*n)).  Blocks up to 256 rows.
 // Stage 1 forms Y_b = Sinv_b X_b for all blocks in parallel; stage 2 and 3
 // are the forward (P_b) and backward (Q_b) sweeps.  X and Y may alias.
+// mat_doubles (host, 3): total doubles of the Sinv, P and Q blocks (for the
+// algorithmic byte count of the profiler).
 void blocktri_solve(hipStream_t s, int n, int nblk, int maxbs, const int* start, const long* off_sinv,
                     const long* off_p, const long* off_q, const double* data, int ncomp, double* X, int ldx,
-                    int ncols, double* Y);
+                    int ncols, double* Y, const double* mat_doubles);
 
 // Givens least squares for the (k+1) x k Hessenberg H (column-major, ld),
 // y = argmin || beta e1 - H y ||; resid = |final rotated rhs entry|.

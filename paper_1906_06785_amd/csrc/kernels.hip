@@ -6,12 +6,87 @@
 #include <climits>
 #include <cmath>
 #include <mutex>
+#include <vector>
 #include <unordered_map>
 #include <utility>
 
 #include "kernels.h"
 
 namespace sgtt {
+
+// ---------------------------------------------------------------- profiling
+namespace {
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+  double bytes, flops;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t ev() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+Profiler g_prof;
+std::mutex g_prof_mu;
+
+struct ProfScope {
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  double bytes, flops;
+  ProfScope(int c, hipStream_t st, double by, double fl) : cls(c), s(st), bytes(by), flops(fl) {
+    if (!g_prof.on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    a = g_prof.ev();
+    (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    hipEvent_t b = g_prof.ev();
+    (void)hipEventRecord(b, s);
+    g_prof.recs.push_back(ProfRec{cls, a, b, bytes, flops});
+  }
+};
+}  // namespace
+
+const char* kernel_class_name(int cls) {
+  static const char* names[] = {"k_gemm", "k_gemm_ptr", "k_spmm", "k_bt_diag", "k_bt_sweep", "k_trunc_eig",
+                                "k_reduce_partials", "other"};
+  return (cls >= 0 && cls < KC_COUNT) ? names[cls] : "?";
+}
+void prof_enable(bool on) { g_prof.on = on; }
+bool prof_enabled() { return g_prof.on; }
+void prof_reset() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.recs.clear();
+  g_prof.used = 0;
+}
+void prof_read(double* seconds, double* bytes, double* flops, long* launches) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (int c = 0; c < KC_COUNT; ++c) {
+    seconds[c] = bytes[c] = flops[c] = 0.0;
+    launches[c] = 0;
+  }
+  for (auto& r : g_prof.recs) {
+    (void)hipEventSynchronize(r.b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    seconds[r.cls] += ms * 1e-3;
+    bytes[r.cls] += r.bytes;
+    flops[r.cls] += r.flops;
+    launches[r.cls] += 1;
+  }
+}
 
 namespace {
 constexpr int WAVE = 64;
@@ -374,7 +449,7 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
                                                           const double* normsq_in, double* normsq_out,
                                                           double* __restrict__ U, int kmax, double* __restrict__ L,
                                                           double* __restrict__ dwork, int* k_out, double* kept_out,
-                                                          int* info, int rank_bound) {
+                                                          int* info, int rank_bound, int large_ok) {
   __shared__ double T[KSMALL * KSMALL];
   __shared__ double V[KSMALL * KSMALL];
   __shared__ double shv[32];
@@ -413,6 +488,7 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
       if (mode == 0 && kp == KSMALL) {
         if (ka >= 0) break;
         mode = 1;
+        if (large_ok) break;   // more than KSMALL pivots: the caller runs the blocked path
       }
       if (mode == 1 && resid <= delta2) break;
     }
@@ -429,7 +505,7 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
     __syncthreads();
     const double ljj = sqrt(bv);
     for (int i = tid; i < N; i += nth) {
-      double s = S[(long)i * N + p];
+      double s = S[(long)p * N + i];   // S is symmetric: row p read coalesced
       for (int t = 0; t < j; ++t) s -= L[(long)t * N + i] * lp[t];
       double lij = (i == p) ? ljj : s / ljj;
       L[(long)j * N + i] = lij;
@@ -442,7 +518,10 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
     resid = block_sum(rr, shv);
     kp = j + 1;
   }
-  if (mode == 0 && kp > KSMALL) mode = 1;
+  if (mode == 1 && large_ok) {
+    if (tid == 0) *info = 2;
+    return;
+  }
   if (kp == 0) {
     // zero (or numerically zero) matrix: rank-1 zero
     for (int i = tid; i < N; i += nth) U[(long)i * kmax] = (i == 0) ? 1.0 : 0.0;
@@ -635,6 +714,133 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
     int i = e / k, c = e % k;
     U[(long)i * kmax + c] = L[(long)c * N + i];
   }
+}
+
+// ------------------------------------------------------------------ blocked pivoted Cholesky
+// state[0] = residual trace, [1] = target (delta^2), [2] = zero threshold,
+// [3] = trace
+__global__ __launch_bounds__(1024) void k_pc_init(int N, const double* __restrict__ S, double eps,
+                                                  const double* normsq_in, double* normsq_out,
+                                                  double* __restrict__ d, double* state) {
+  __shared__ double sh[32];
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    double v = S[(long)i * N + i];
+    v = v > 0.0 ? v : 0.0;
+    d[i] = v;
+    tr += v;
+  }
+  tr = block_sum(tr, sh);
+  if (threadIdx.x == 0) {
+    double nrm = normsq_in ? *normsq_in : tr;
+    if (normsq_out) *normsq_out = tr;
+    state[0] = tr;
+    state[1] = 0.5 * eps * eps * nrm;
+    state[2] = 64.0 * 2.220446049250313e-16 * tr;
+    state[3] = tr;
+  }
+}
+
+// Up to nsteps pivots on the current Schur complement S (earlier panels
+// already subtracted): column t of the panel Lp (N x nsteps, column-major,
+// ld N) = (S[:, p] - Lp[:, :t] Lp[p, :t]^T) / sqrt(d[p]).  Stops when the
+// residual trace reaches the target or the largest pivot is numerically 0.
+// out[0] = pivots taken, out[1] = 1 if finished.
+__global__ __launch_bounds__(1024) void k_pc_panel(int N, const double* __restrict__ S, double* __restrict__ d,
+                                                   double* __restrict__ Lp, int* __restrict__ piv, int nsteps,
+                                                   double* state, int* out, double* kept) {
+  __shared__ double shv[32];
+  __shared__ int shi[32];
+  __shared__ double lp[64];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  double resid = state[0];
+  const double target = state[1], zero_thr = state[2];
+  int t = 0, done = 0;
+  for (; t < nsteps; ++t) {
+    if (resid <= target) { done = 1; break; }
+    double mv = -1.0;
+    int mi = 0;
+    for (int i = tid; i < N; i += nth)
+      if (d[i] > mv) { mv = d[i]; mi = i; }
+    double bv;
+    int bi;
+    argmax_block(mv, mi, shv, shi, bv, bi);
+    if (bv <= zero_thr || bv <= 0.0) { done = 1; break; }
+    const int p = bi;
+    if (tid < t) lp[tid] = Lp[(long)tid * N + p];
+    if (tid == 0) piv[t] = p;
+    __syncthreads();
+    const double l = sqrt(bv);
+    for (int i = tid; i < N; i += nth) {
+      double v = S[(long)p * N + i];   // S is symmetric: row p read coalesced
+      for (int u = 0; u < t; ++u) v -= Lp[(long)u * N + i] * lp[u];
+      // rows already eliminated (zero Schur diagonal) have a zero Schur row
+      double li = (i == p) ? l : (d[i] > 0.0 ? v / l : 0.0);
+      Lp[(long)t * N + i] = li;
+      double dd = d[i] - li * li;
+      d[i] = (i == p || dd < 0.0) ? 0.0 : dd;
+    }
+    __syncthreads();
+    double rr = 0.0;
+    for (int i = tid; i < N; i += nth) rr += d[i];
+    resid = block_sum(rr, shv);
+  }
+  if (resid <= target) done = 1;
+  if (tid == 0) {
+    state[0] = resid;
+    out[0] = t;
+    out[1] = done;
+    if (kept) *kept = state[3] - resid;
+  }
+}
+
+// LP[a*k + c] = L[c*N + piv[a]]: the pivot rows of L (row-major k x k,
+// lower triangular up to rounding)
+__global__ void k_gather_pivot_rows(int N, int k, const double* __restrict__ L, const int* __restrict__ piv,
+                                    double* __restrict__ LP) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)k * k) return;
+  int a = e / k, c = e % k;
+  LP[e] = (c <= a) ? L[(long)c * N + piv[a]] : 0.0;
+}
+
+// In place, per row i of F (column-major, ld N, nb <= 64 columns):
+// F[i, :] <- F[i, :] T^{-1}, T = LP block (lower triangular, row-major ld).
+__global__ __launch_bounds__(256) void k_skel_tri(int N, int nb, const double* __restrict__ T, int ldt,
+                                                  double* __restrict__ F) {
+  __shared__ double t[64 * 64];
+  for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+    int a = e / 64, c = e % 64;
+    double v = 0.0;
+    if (a < nb && c < nb) v = (c <= a) ? T[(long)a * ldt + c] : 0.0;
+    else if (a == c) v = 1.0;
+    t[e] = v;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double f[64];
+#pragma unroll
+  for (int c = 0; c < 64; ++c) f[c] = (c < nb) ? F[(long)c * N + i] : 0.0;
+#pragma unroll
+  for (int c = 63; c >= 0; --c) {
+    double v = f[c];
+#pragma unroll
+    for (int a = c + 1; a < 64; ++a) v -= f[a] * t[a * 64 + c];
+    f[c] = v / t[c * 64 + c];
+  }
+#pragma unroll
+  for (int c = 0; c < 64; ++c)
+    if (c < nb) F[(long)c * N + i] = f[c];
+}
+
+// out[a*ld + j] = in[piv[a]*ld_in + j]
+__global__ void k_gather_rows(int k, int cols, const double* __restrict__ in, long ld_in, const int* __restrict__ piv,
+                              double* __restrict__ out, long ld_out) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)k * cols) return;
+  int a = e / cols, j = e % cols;
+  out[(long)a * ld_out + j] = in[(long)piv[a] * ld_in + j];
 }
 
 // ------------------------------------------------------------------ block tridiagonal
@@ -879,14 +1085,21 @@ void gemm(hipStream_t s, int batch, int m, int n, int k, double alpha, const dou
       long chunk = (k + nch - 1) / nch;
       nch = (k + chunk - 1) / chunk;
       dim3 grid(cdiv(n, TN), cdiv(m, TM), (unsigned)nch);
-      hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, m, n, (int)chunk, 1.0, A, chunk * sAk, sAi, sAk, B,
-                         chunk * sBk, sBk, sBj, 0.0, ws, ne, (long)n, 1L, (int)chunk, (long)k);
+      {
+        ProfScope ps(KC_GEMM, s, 8.0 * ((double)k * (m + n) + (double)ne * nch), 2.0 * m * n * (double)k);
+        hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, m, n, (int)chunk, 1.0, A, chunk * sAk, sAi, sAk, B,
+                           chunk * sBk, sBk, sBj, 0.0, ws, ne, (long)n, 1L, (int)chunk, (long)k);
+      }
       hipLaunchKernelGGL(k_reduce_scaled, dim3(cdiv(ne, 256)), dim3(256), 0, s, (int)nch, m, n, ws, alpha, beta, C,
                          sCi, sCj);
       return;
     }
   }
   dim3 grid(cdiv(n, TN), cdiv(m, TM), batch);
+  double kk = klimit > 0 ? (double)klimit : (double)k * batch;   // total reduction length
+  double by = klimit > 0 ? 8.0 * (kk * (m + n) + (double)m * n * batch)
+                         : 8.0 * batch * ((double)m * k + (double)k * n + (double)m * n * (beta != 0.0 ? 2 : 1));
+  ProfScope ps(KC_GEMM, s, by, 2.0 * m * n * kk);
   hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, m, n, k, alpha, A, sAb, sAi, sAk, B, sBb, sBk, sBj, beta, C, sCb,
                      sCi, sCj, kstep, klimit);
 }
@@ -896,6 +1109,7 @@ void gemm_batched(hipStream_t s, int nb, const GemmDesc* d_desc, int max_m, int 
   for (int b0 = 0; b0 < nb; b0 += 65535) {
     int n = std::min(65535, nb - b0);
     dim3 grid(cdiv(max_n, TN), cdiv(max_m, TM), n);
+    ProfScope ps(KC_GEMM_PTR, s, 0.0, 0.0);
     hipLaunchKernelGGL(k_gemm_ptr, grid, dim3(256), 0, s, d_desc + b0);
   }
 }
@@ -918,6 +1132,7 @@ void gram(hipStream_t s, long rows, int nx, int ny, const double* X, long sXr, l
   nch = (rows + chunk - 1) / chunk;
   gemm(s, (int)nch, nx, ny, (int)chunk, 1.0, X, chunk * sXr, sXc, sXr, Y, chunk * sYr, sYr, sYc, 0.0, ws, ne, ny, 1,
        (int)chunk, rows);
+  ProfScope ps(KC_REDUCE, s, 8.0 * (double)ne * (nch + 1), (double)ne * nch);
   hipLaunchKernelGGL(k_reduce_partials, dim3(cdiv(ne, 64)), dim3(256), 0, s, (int)nch, ne, ws, out);
 }
 
@@ -955,6 +1170,11 @@ void spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* rowp
   for (int v0 = 0; v0 < nv; v0 += NVMAX) {
     int nvb = std::min(NVMAX, nv - v0);
     dim3 grid(cdiv(nrows, 4), ncomp);
+    // algorithmic bytes: pattern + values once, each input row once, each output once
+    double nnz = (double)vstride > 0 ? (double)vstride : 0.0;
+    double by = 4.0 * (nrows + 1) + nnz * (4.0 + 8.0 * nvb) + 8.0 * ncomp * ((double)std::max(ics, nrows) * ncols) +
+                8.0 * ncomp * (double)nrows * nvb * ncols;
+    ProfScope ps(KC_SPMM, s, by, 2.0 * nnz * ncomp * nvb * ncols);
     hipLaunchKernelGGL(k_spmm, grid, dim3(256), 0, s, nrows, ics, ocs, rowptr, col, vals + v0 * vstride, nvb, vstride,
                        x, ldx, xcol0, ncols, y, ldy, ycol0 + v0 * yvstep, yvstep, alpha);
   }
@@ -983,24 +1203,72 @@ void core2_block(hipStream_t s, int r1, int n2, int r2, const double* in, const 
 }
 
 void trunc_eig(hipStream_t s, int N, double* S, double eps, const double* normsq_in, double* normsq_out, double* U,
-               int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound) {
+               int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound, int large_ok) {
   // dwork: N doubles placed after L (caller sizes L as N*kmax + N)
   double* dwork = L + (long)N * kmax;
+  ProfScope ps(KC_TRUNC, s, 8.0 * (double)N * N, 0.0);
   hipLaunchKernelGGL(k_trunc_eig, dim3(1), dim3(TE_THREADS), 0, s, N, S, eps, normsq_in, normsq_out, U, kmax, L, dwork,
-                     k_out, kept_out, info, rank_bound);
+                     k_out, kept_out, info, rank_bound, large_ok);
 }
 
 void blocktri_solve(hipStream_t s, int n, int nblk, int maxbs, const int* start, const long* off_sinv, const long* off_p,
-                    const long* off_q, const double* data, int ncomp, double* X, int ldx, int ncols, double* Y) {
+                    const long* off_q, const double* data, int ncomp, double* X, int ldx, int ncols, double* Y,
+                    const double* mat_doubles) {
   if (ncols <= 0) return;
   (void)maxbs;
   // parallel stage: Y_b = Sinv_b X_b for all blocks and components
-  hipLaunchKernelGGL(k_bt_diag, dim3(nblk, ncomp, cdiv(ncols, BT_CB)), dim3(256), 0, s, n, start, off_sinv, data, X, Y,
-                     ldx, ncols);
+  const double vec = 8.0 * 2.0 * ncomp * (double)n * ncols;   // read + write of the columns
+  {
+    ProfScope ps(KC_BT_DIAG, s, vec + 8.0 * mat_doubles[0], 2.0 * ncomp * ncols * mat_doubles[0]);
+    hipLaunchKernelGGL(k_bt_diag, dim3(nblk, ncomp, cdiv(ncols, BT_CB)), dim3(256), 0, s, n, start, off_sinv, data, X,
+                       Y, ldx, ncols);
+  }
   // sequential sweeps
   dim3 grid(cdiv(ncols, BT_CB), ncomp);
-  hipLaunchKernelGGL(k_bt_sweep, grid, dim3(256), 0, s, 0, n, nblk, start, off_p, data, Y, ldx, ncols);
-  hipLaunchKernelGGL(k_bt_sweep, grid, dim3(256), 0, s, 1, n, nblk, start, off_q, data, Y, ldx, ncols);
+  {
+    ProfScope ps(KC_BT_SWEEP, s, vec + 8.0 * mat_doubles[1], 2.0 * ncomp * ncols * mat_doubles[1]);
+    hipLaunchKernelGGL(k_bt_sweep, grid, dim3(256), 0, s, 0, n, nblk, start, off_p, data, Y, ldx, ncols);
+  }
+  {
+    ProfScope ps(KC_BT_SWEEP, s, vec + 8.0 * mat_doubles[2], 2.0 * ncomp * ncols * mat_doubles[2]);
+    hipLaunchKernelGGL(k_bt_sweep, grid, dim3(256), 0, s, 1, n, nblk, start, off_q, data, Y, ldx, ncols);
+  }
+}
+
+void pc_init(hipStream_t s, int N, const double* S, double eps, const double* normsq_in, double* normsq_out, double* d,
+             double* state) {
+  hipLaunchKernelGGL(k_pc_init, dim3(1), dim3(1024), 0, s, N, S, eps, normsq_in, normsq_out, d, state);
+}
+
+void pc_panel(hipStream_t s, int N, const double* S, double* d, double* Lp, int* piv, int nsteps, double* state,
+              int* out, double* kept) {
+  ProfScope ps(KC_TRUNC, s, 8.0 * (double)N * nsteps * 2, (double)N * nsteps * nsteps);
+  hipLaunchKernelGGL(k_pc_panel, dim3(1), dim3(1024), 0, s, N, S, d, Lp, piv, nsteps, state, out, kept);
+}
+
+void skeleton_factor(hipStream_t s, int N, int k, const double* L, const int* piv, double* LP, double* F) {
+  if (k <= 0) return;
+  ProfScope ps(KC_TRUNC, s, 8.0 * (3.0 * N * (double)k + (double)k * k), (double)N * k * k);
+  long kk = (long)k * k;
+  hipLaunchKernelGGL(k_gather_pivot_rows, dim3(cdiv(kk, 256)), dim3(256), 0, s, N, k, L, piv, LP);
+  copy2d(s, k, N, L, N, F, N, 1.0, nullptr, 0);
+  // column blocks of 64 from the right: F_J = (L_J - F_{>J} LP_{>J,J}) LP_JJ^{-1}
+  const int nblk = cdiv(k, 64);
+  for (int jb = nblk - 1; jb >= 0; --jb) {
+    const int j0 = jb * 64, j1 = std::min(k, j0 + 64), nb = j1 - j0;
+    if (j1 < k)
+      gemm(s, 1, N, nb, k - j1, -1.0, F + (long)j1 * N, 0, 1, N, LP + (long)j1 * k + j0, 0, k, 1, 1.0,
+           F + (long)j0 * N, 0, 1, N);
+    hipLaunchKernelGGL(k_skel_tri, dim3(cdiv(N, 256)), dim3(256), 0, s, N, nb, LP + (long)j0 * k + j0, k,
+                       F + (long)j0 * N);
+  }
+}
+
+void gather_rows(hipStream_t s, int k, int cols, const double* in, long ld_in, const int* piv, double* out,
+                 long ld_out) {
+  long total = (long)k * cols;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3(cdiv(total, 256)), dim3(256), 0, s, k, cols, in, ld_in, piv, out, ld_out);
 }
 
 void hessenberg_lsq(hipStream_t s, const double* H, int ld, int k, const double* beta, double* y, double* resid) {

@@ -70,6 +70,7 @@ DevCsr upload_csr(Ctx& c, const Csr& pat, const std::vector<const double*>& vals
 
 struct DevBT {
   int n = 0, nblk = 0, maxbs = 0;
+  double nd[3] = {0, 0, 0};   // doubles in the Sinv, P and Q blocks
   int* start = nullptr;
   long *off_sinv = nullptr, *off_p = nullptr, *off_q = nullptr;
   double* data = nullptr;
@@ -95,6 +96,12 @@ DevBT upload_bt(Ctx& c, const BlockTri& bt) {
   d.off_p = dev_upload(c, b);
   d.off_q = dev_upload(c, q);
   d.data = dev_upload(c, bt.data);
+  for (int b = 0; b < bt.nblk; ++b) {
+    int bs = bt.start[b + 1] - bt.start[b];
+    d.nd[0] += (double)bs * bs;
+    if (b > 0) d.nd[1] += (double)bs * (bt.start[b] - bt.start[b - 1]);
+    if (b < bt.nblk - 1) d.nd[2] += (double)bs * (bt.start[b + 2] - bt.start[b + 1]);
+  }
   return d;
 }
 
@@ -202,7 +209,7 @@ TT space_solve(sgtt_system& S, const TT& x, const DevBT& bt, int ncomp, double c
   copy2d(c.s, x.n1, x.r1, x.c1, x.r1, o.c1, x.r1, c1scale, nullptr, 0);
   SGTT_HIP(hipMemcpyAsync(o.c2, x.c2, sizeof(double) * x.n_c2(), hipMemcpyDeviceToDevice, c.s));
   blocktri_solve(c.s, bt.n, bt.nblk, bt.maxbs, bt.start, bt.off_sinv, bt.off_p, bt.off_q, bt.data, ncomp, x.c3, x.r2,
-                 x.r2, o.c3);
+                 x.r2, o.c3, bt.nd);
   return o;
 }
 
@@ -214,7 +221,7 @@ TT apply_Minv(sgtt_system& S, const TT& u) {
   core1_op(c.s, 2, S.nt, u.r1, u.c1, u.r1, o.c1, u.r1, 0, 1.0);
   SGTT_HIP(hipMemcpyAsync(o.c2, u.c2, sizeof(double) * u.n_c2(), hipMemcpyDeviceToDevice, c.s));
   blocktri_solve(c.s, S.Fbt.n, S.Fbt.nblk, S.Fbt.maxbs, S.Fbt.start, S.Fbt.off_sinv, S.Fbt.off_p, S.Fbt.off_q,
-                 S.Fbt.data, 2, u.c3, u.r2, u.r2, o.c3);
+                 S.Fbt.data, 2, u.c3, u.r2, u.r2, o.c3, S.Fbt.nd);
   return o;
 }
 
@@ -295,8 +302,13 @@ struct GramCache {
 // explicit_res = true follows Alg. 4.2 literally (z_k and s_k = T(b - L z_k)
 // every iteration); false stops on the least-squares residual estimate
 // |rotated rhs| and forms z once at the end of the cycle.
+// relax = true truncates the k-th Krylov basis vectors (x = T(L v^_k) and
+// v_{k+1}) with eps_k = eps * min(||b|| / ||r_{k-1}||, eps_max / eps): the
+// relaxation of inexact Krylov methods (Simoncini & Szyld 2003); z_k and s_k
+// keep eps.  relax = false is the fixed truncation of Alg. 4.2.
 Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int maxit, double* dscal, int& iters,
-                   double& relres, SolveCounters* cnt, const char* tag, bool explicit_res) {
+                   double& relres, SolveCounters* cnt, const char* tag, bool explicit_res, bool relax = false,
+                   double eps_max = 1e-2) {
   const int ld = maxit + 1;
   const int nc = b.nc;
   double* H = dscal;                          // ld x maxit, column-major
@@ -339,7 +351,8 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
     Vec vh = sp.precond(V[k - 1]);
     double t1 = now_s();
     if (cnt) cnt->t_prec += t1 - t0;
-    Vec x = vec_round(c, sp.apply(vh), eps, nullptr, nullptr);
+    const double eps_k = relax ? std::min(eps_max, eps * bnorm / std::max(res, 1e-300)) : eps;
+    Vec x = vec_round(c, sp.apply(vh), eps_k, nullptr, nullptr);
     Vh.push_back(std::move(vh));
     // Gram blocks of the preconditioned basis (for the solution sum)
     for (int q = 0; q < nc; ++q)
@@ -373,7 +386,7 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
         cache[(size_t)0 * (k + 1) + 1 + i] = KX.at(q, 0, i);
         for (int j = i; j < k; ++j) cache[(size_t)(1 + i) * (k + 1) + 1 + j] = KV.at(q, i, j);
       }
-      vn.c[q] = tt_round_sum(c, terms, eps, sc + 6 + q, nullptr, &cache);
+      vn.c[q] = tt_round_sum(c, terms, eps_k, sc + 6 + q, nullptr, &cache);
     }
     scalar_op(c.s, 0, sc + 6, nc > 1 ? sc + 7 : nullptr, H + (size_t)(k - 1) * ld + k);   // h_{k+1,k}
     double hk = read_double(c, H + (size_t)(k - 1) * ld + k);
@@ -616,6 +629,7 @@ sgtt_solve_opts default_opts() {
   o.verbose = 0;
   o.outer_explicit = 1;
   o.inner_explicit = 0;
+  o.relax = 0;
   return o;
 }
 
@@ -1027,7 +1041,7 @@ int sgtt_round(sgtt_context* ctx, sgtt_tt* x, double eps, int max_rank) {
   return guarded(ctx, [&]() {
     if (x->r1 < 1 || x->r2 < 1 || x->r1 > x->cap1 || x->r2 > x->cap2) throw SgttError(-1, "invalid TT");
     TT v = tt_view(x->n1, x->n2, x->n3, x->r1, x->r2, x->core1, x->core2, x->core3);
-    TT r = tt_round(ctx->c, v, eps, nullptr, nullptr, max_rank > 0 ? max_rank : 96);
+    TT r = tt_round(ctx->c, v, eps, nullptr, nullptr, max_rank > 0 ? max_rank : RANK_CAP_LARGE);
     write_tt(ctx->c, r, x);
     ctx->c.sync();
   });
@@ -1120,7 +1134,7 @@ int sgtt_solve(sgtt_system* S, const sgtt_tt_pair* b, sgtt_tt_pair* x, const sgt
       int its = 0;
       double rr = 0;
       Vec d = lowrank_fgmres(c, sp, r, o.tol_cycle, o.eps_krylov, o.restart, S->dsc, its, rr, &cnt, "outer",
-                             o.outer_explicit != 0);
+                             o.outer_explicit != 0, o.relax != 0);
       cnt.outer += its;
       ++cycles;
       terms.push_back(std::move(d));
@@ -1128,7 +1142,18 @@ int sgtt_solve(sgtt_system* S, const sgtt_tt_pair* b, sgtt_tt_pair* x, const sgt
       for (auto& t : terms) parts.push_back(&t);
       z = vec_concat(c, parts, nullptr, {});
       Vec rnext;
-      rel = full_residual(*S, bv, z, nullptr, &rnext, o.eps_krylov, &bn2);
+      // the correction equation L d = r_j only has to be solved to relative
+      // accuracy tol ||b|| / ||r_j||, so its right-hand side is compressed
+      // to a fraction of that (never finer than eps_krylov)
+      double rel_prev = rel;
+      double eps_r = o.eps_krylov;
+      (void)rel_prev;
+      rel = full_residual(*S, bv, z, nullptr, nullptr, 0.0, &bn2);
+      if (rel > o.tol && cyc + 1 < o.max_cycles) {
+        eps_r = std::max(o.eps_krylov, std::min(1e-3, 0.05 * o.tol / std::max(rel, 1e-300)));
+        full_residual(*S, bv, z, nullptr, &rnext, eps_r, &bn2);
+      }
+      if (o.verbose) fprintf(stderr, "[sgtt] next right-hand side truncated at %.2e\n", eps_r);
       if (o.verbose) fprintf(stderr, "[sgtt] cycle %d: outer its %d, exact rel residual %.3e\n", cyc, its, rel);
       if (!std::isfinite(rel)) throw SgttError(-5, "non-finite residual");
       if (rel <= o.tol) break;
@@ -1160,6 +1185,34 @@ int sgtt_solve(sgtt_system* S, const sgtt_tt_pair* b, sgtt_tt_pair* x, const sgt
   }
   return status;
 }
+
+int sgtt_profile_enable(sgtt_context* ctx, int enable) {
+  if (!ctx) return SGTT_E_INVALID;
+  (void)hipStreamSynchronize(ctx->c.s);
+  prof_reset();
+  prof_enable(enable != 0);
+  return SGTT_OK;
+}
+
+int sgtt_profile_read(sgtt_context* ctx, int max_classes, double* seconds, double* bytes, double* flops,
+                      long* launches, int* nclasses) {
+  if (!ctx || !seconds || !bytes || !flops || !launches) return SGTT_E_INVALID;
+  (void)hipStreamSynchronize(ctx->c.s);
+  double s[KC_COUNT], b[KC_COUNT], f[KC_COUNT];
+  long l[KC_COUNT];
+  prof_read(s, b, f, l);
+  int n = std::min(max_classes, (int)KC_COUNT);
+  for (int i = 0; i < n; ++i) {
+    seconds[i] = s[i];
+    bytes[i] = b[i];
+    flops[i] = f[i];
+    launches[i] = l[i];
+  }
+  if (nclasses) *nclasses = KC_COUNT;
+  return SGTT_OK;
+}
+
+const char* sgtt_profile_class_name(int cls) { return kernel_class_name(cls); }
 
 // ---------------------------------------------------------------- host-only
 struct sgtt_host_problem {

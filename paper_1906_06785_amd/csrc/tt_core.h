@@ -98,18 +98,19 @@ struct Term {
   const double* dcoef;
   double hcoef;
 };
-constexpr int RANK_CAP = 512;
+constexpr int RANK_CAP = 512;         // first bond (single-workgroup truncation)
+constexpr int RANK_CAP_LARGE = 4096;  // second bond (blocked pivoted Cholesky + skeleton)
 // T_eps(sum_i c_i t_i) (Gram-based, FP64), exploiting the block structure of
 // the concatenated cores.  cache (k*k, row-major, may be null or hold nulls):
 // cache[i*k + j] for i <= j = device block t_i.core3^T t_j.core3 (row-major).
 // Writes ||sum||^2 to *d_normsq and the squared norm of the result to
 // *d_kept (device) when non-null.
 TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_normsq, double* d_kept,
-                const std::vector<const double*>* cache = nullptr, int maxrank = RANK_CAP);
-TT tt_round(Ctx& c, const TT& x, double eps, double* d_normsq, double* d_kept, int maxrank = RANK_CAP);
+                const std::vector<const double*>* cache = nullptr, int maxrank = RANK_CAP_LARGE);
+TT tt_round(Ctx& c, const TT& x, double eps, double* d_normsq, double* d_kept, int maxrank = RANK_CAP_LARGE);
 // TT-SVD (Alg. 4.1) of a full n1 x n2 x n3 tensor (device, C order)
 TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, double* d_normsq,
-                int maxrank = RANK_CAP);
+                int maxrank = RANK_CAP_LARGE);
 // full tensor (device buffer of n1*n2*n3)
 void tt_expand(Ctx& c, const TT& x, double* out);
 // scale core3 by *dscale (inv: 1 / *dscale)

@@ -178,6 +178,65 @@ static void read_ints(Ctx& c, const int* d, int n, int* h) {
   std::memcpy(h, c.hint, sizeof(int) * n);
 }
 
+// Truncation of the last bond when more than 96 pivots are needed: blocked
+// pivoted Cholesky of the Gram S (N x N, overwritten by Schur complements)
+// until the residual trace is <= eps^2 ||x||^2 / 2, then the skeleton factor
+// F = L L_P^{-1}.  The tensor is replaced by F times its rows P, whose error
+// equals the residual trace.  F: N x k column-major; piv: k ints.
+struct Skeleton {
+  int k = 0;
+  double* F = nullptr;
+  double* pivbuf = nullptr;
+  const int* piv() const { return (const int*)pivbuf; }
+  void release(Pool& p) {
+    if (F) p.put(F);
+    if (pivbuf) p.put(pivbuf);
+    F = pivbuf = nullptr;
+  }
+};
+
+static Skeleton trunc_skeleton(Ctx& c, int N, double* S, double eps, const double* dnorm_in, double* d_kept,
+                               int kcap, int rank_bound, const char* what) {
+  double* L = c.pool.get((size_t)N * kcap);
+  double* d = c.pool.get((size_t)N + 8);
+  double* state = d + N;
+  Skeleton sk;
+  sk.pivbuf = c.pool.get((size_t)kcap / 2 + 1);
+  int* piv = (int*)sk.pivbuf;
+  int* out = c.dint + 16;
+  pc_init(c.s, N, S, eps, dnorm_in, nullptr, d, state);
+  int k = 0;
+  for (;;) {
+    const int ns = std::min(64, kcap - k);
+    if (ns <= 0) {
+      if (kcap < rank_bound) {
+        c.pool.put(L);
+        c.pool.put(d);
+        sk.release(c.pool);
+        throw SgttError(-4, std::string("TT rank capacity exceeded (") + what + ")");
+      }
+      break;
+    }
+    pc_panel(c.s, N, S, d, L + (size_t)k * N, piv + k, ns, state, out, d_kept);
+    int h[2];
+    read_ints(c, out, 2, h);
+    const int k0 = k;
+    k += h[0];
+    if (h[1] || h[0] == 0) break;
+    // Schur complement update S -= L_panel L_panel^T
+    gemm(c.s, 1, N, N, h[0], -1.0, L + (size_t)k0 * N, 0, 1, N, L + (size_t)k0 * N, 0, N, 1, 1.0, S, 0, N, 1);
+  }
+  if (k == 0) throw SgttError(-6, "internal: empty blocked truncation");
+  sk.k = k;
+  sk.F = c.pool.get((size_t)N * k);
+  double* LP = c.pool.get((size_t)k * k);
+  skeleton_factor(c.s, N, k, L, piv, LP, sk.F);
+  c.pool.put(LP);
+  c.pool.put(L);
+  c.pool.put(d);
+  return sk;
+}
+
 namespace {
 double* upload_descs(Ctx& c, const std::vector<GemmDesc>& d) {
   size_t nd = (d.size() * sizeof(GemmDesc) + sizeof(double) - 1) / sizeof(double);
@@ -304,23 +363,34 @@ TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_no
   double* U2 = c.pool.get((size_t)N2 * kmax2);
   {
     double* Lw = c.scratch2((size_t)N2 * kmax2 + N2 + 64);
-    trunc_eig(c.s, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw, dk + 2, dkept2, dk + 3, std::min(N2, R2));
+    trunc_eig(c.s, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw, dk + 2, dkept2, dk + 3, std::min(N2, R2), 1);
   }
   SGTT_HIP(hipMemcpyAsync(c.hint, dk + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, c.s));
   c.sync();
   h[2] = c.hint[0];
   h[3] = c.hint[1];
-  if (h[3] != 0) throw SgttError(-4, "TT rank capacity exceeded (bond 2)");
-  const int k2 = h[2];
-  // ---- W = U2^T C (k2 x R2); new G3 = sum_j C_j W_j^T
+  if (h[3] == 1) throw SgttError(-4, "TT rank capacity exceeded (bond 2)");
+  Skeleton sk;
+  if (h[3] == 2)
+    sk = trunc_skeleton(c, N2, S2, eps, dnorm, dkept2, std::min({N2, R2, maxrank, RANK_CAP_LARGE}),
+                        std::min(N2, R2), "bond 2");
+  const int k2 = h[3] == 2 ? sk.k : h[2];
+  // ---- W (k2 x R2) = U2^T C, or the skeleton rows C[P, :]; new G3 = sum_j C_j W_j^T
   double* W = c.pool.get((size_t)k2 * R2);
-  gemm(c.s, 1, k2, R2, N2, 1.0, U2, 0, 1, kmax2, Cm, 0, R2, 1, 0.0, W, 0, R2, 1);
+  if (h[3] == 2)
+    gather_rows(c.s, k2, R2, Cm, R2, sk.piv(), W, R2);
+  else
+    gemm(c.s, 1, k2, R2, N2, 1.0, U2, 0, 1, kmax2, Cm, 0, R2, 1, 0.0, W, 0, R2, 1);
   TT t = tt_new(c, n1, n2, n3, k1, k2);
   copy2d(c.s, n1, k1, U1, kmax1, t.c1, k1, 1.0, nullptr, 0);
-  copy2d(c.s, N2, k2, U2, kmax2, t.c2, k2, 1.0, nullptr, 0);
+  if (h[3] == 2)
+    transpose_copy(c.s, k2, N2, sk.F, N2, t.c2, k2);
+  else
+    copy2d(c.s, N2, k2, U2, kmax2, t.c2, k2, 1.0, nullptr, 0);
   for (int j = 0; j < k; ++j)
     gemm(c.s, 1, n3, k2, b[j], 1.0, terms[j].t->c3, 0, b[j], 1, W + ob[j], 0, 1, R2, j == 0 ? 0.0 : 1.0, t.c3, 0,
          k2, 1);
+  sk.release(c.pool);
   for (double* p : {K3, G1, K2, T1, S1, U1, D, Cm, T2, S2, U2, W}) c.pool.put(p);
   return t;
 }
@@ -355,15 +425,29 @@ TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, dou
   const int kmax2 = std::min({N2, maxrank, RANK_CAP});
   double* U2 = c.pool.get((size_t)N2 * kmax2);
   double* Lw2 = c.scratch2((size_t)N2 * kmax2 + N2 + 64);
-  trunc_eig(c.s, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw2, dk + 2, dkept, dk + 3, std::min(N2, n3));
+  trunc_eig(c.s, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw2, dk + 2, dkept, dk + 3, std::min(N2, n3), 1);
   read_ints(c, dk + 2, 2, h + 2);
-  if (h[3] != 0) throw SgttError(-4, "TT rank capacity exceeded (full bond 2)");
-  const int k2 = h[2];
+  if (h[3] == 1) throw SgttError(-4, "TT rank capacity exceeded (full bond 2)");
+  Skeleton sk;
+  if (h[3] == 2)
+    sk = trunc_skeleton(c, N2, S2, eps, dnorm, dkept, std::min({N2, n3, maxrank, RANK_CAP_LARGE}), std::min(N2, n3),
+                        "full bond 2");
+  const int k2 = h[3] == 2 ? sk.k : h[2];
   TT t = tt_new(c, n1, n2, n3, k1, k2);
   copy2d(c.s, n1, k1, U1, kmax1, t.c1, k1, 1.0, nullptr, 0);
-  copy2d(c.s, N2, k2, U2, kmax2, t.c2, k2, 1.0, nullptr, 0);
-  // G3 (n3 x k2) = Y(12)^T U2_k
-  gemm(c.s, 1, n3, k2, N2, 1.0, Y, 0, 1, n3, U2, 0, kmax2, 1, 0.0, t.c3, 0, k2, 1);
+  if (h[3] == 2) {
+    transpose_copy(c.s, k2, N2, sk.F, N2, t.c2, k2);
+    // G3 (n3 x k2) = rows P of Y(12), transposed
+    double* YP = c.pool.get((size_t)k2 * n3);
+    gather_rows(c.s, k2, n3, Y, n3, sk.piv(), YP, n3);
+    transpose_copy(c.s, k2, n3, YP, n3, t.c3, k2);
+    c.pool.put(YP);
+  } else {
+    copy2d(c.s, N2, k2, U2, kmax2, t.c2, k2, 1.0, nullptr, 0);
+    // G3 (n3 x k2) = Y(12)^T U2_k
+    gemm(c.s, 1, n3, k2, N2, 1.0, Y, 0, 1, n3, U2, 0, kmax2, 1, 0.0, t.c3, 0, k2, 1);
+  }
+  sk.release(c.pool);
   for (double* p : {S1, U1, Y, S2, U2}) c.pool.put(p);
   return t;
 }

@@ -53,7 +53,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("eps_krylov", C.c_double), ("tol_cycle", C.c_double),
                 ("restart", C.c_int), ("max_cycles", C.c_int), ("inner_tol", C.c_double),
                 ("inner_eps", C.c_double), ("inner_maxit", C.c_int), ("verbose", C.c_int),
-                ("outer_explicit", C.c_int), ("inner_explicit", C.c_int)]
+                ("outer_explicit", C.c_int), ("inner_explicit", C.c_int), ("relax", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -87,6 +87,10 @@ _sig = {
     "sgtt_expand": (C.c_int, [_P, C.POINTER(SgttTT), _P]),
     "sgtt_hessenberg_lsq": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int, C.c_double, C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]),
+    "sgtt_profile_enable": (C.c_int, [_P, C.c_int]),
+    "sgtt_profile_read": (C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_long), C.POINTER(C.c_int)]),
+    "sgtt_profile_class_name": (C.c_char_p, [C.c_int]),
     "sgtt_host_problem_create": (C.c_int, [C.POINTER(ProblemDesc), C.POINTER(_P)]),
     "sgtt_host_problem_destroy": (C.c_int, [_P]),
     "sgtt_host_sizes": (C.c_int, [_P, C.POINTER(C.c_int)]),
@@ -117,11 +121,11 @@ def make_desc(cfg: dict, eps_conv=1e-3, eps_rhs=1e-6) -> ProblemDesc:
 
 def make_opts(**kw) -> SolveOpts:
     d = dict(tol=1e-8, eps_krylov=1e-6, tol_cycle=1e-4, restart=30, max_cycles=8, inner_tol=1e-1,
-             inner_eps=1e-3, inner_maxit=20, verbose=0, outer_explicit=1, inner_explicit=0)
+             inner_eps=1e-3, inner_maxit=20, verbose=0, outer_explicit=1, inner_explicit=0, relax=0)
     d.update(kw)
     return SolveOpts(d["tol"], d["eps_krylov"], d["tol_cycle"], int(d["restart"]), int(d["max_cycles"]),
                      d["inner_tol"], d["inner_eps"], int(d["inner_maxit"]), int(d["verbose"]),
-                     int(d["outer_explicit"]), int(d["inner_explicit"]))
+                     int(d["outer_explicit"]), int(d["inner_explicit"]), int(d["relax"]))
 
 
 # ------------------------------------------------------------------ host-only
@@ -282,6 +286,23 @@ class Context:
         s = buf.struct()
         self.check(_lib.sgtt_expand(self._c, C.byref(s), out.data_ptr()))
         return out.reshape(buf.n1, buf.n2, buf.n3)
+
+    def profile(self, enable: bool):
+        self.check(_lib.sgtt_profile_enable(self._c, int(enable)))
+
+    def profile_read(self):
+        n = 16
+        sec = (C.c_double * n)()
+        by = (C.c_double * n)()
+        fl = (C.c_double * n)()
+        la = (C.c_long * n)()
+        nc = C.c_int()
+        self.check(_lib.sgtt_profile_read(self._c, n, sec, by, fl, la, C.byref(nc)))
+        out = {}
+        for i in range(nc.value):
+            out[_lib.sgtt_profile_class_name(i).decode()] = dict(seconds=sec[i], bytes=by[i], flops=fl[i],
+                                                                 launches=la[i])
+        return out
 
     def hessenberg_lsq(self, H: np.ndarray, beta: float):
         k = H.shape[1]

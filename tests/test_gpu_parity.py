@@ -82,6 +82,27 @@ def test_round_error_bound_and_ranks(sg, ctx, n, ranks, eps):
     assert np.abs(L.T @ L - np.eye(buf.r2)).max() < 1e-10
 
 
+@pytest.mark.parametrize("eps", [1e-2, 1e-3])
+def test_round_large_rank_second_bond(sg, ctx, eps):
+    # second-bond rank above 96: blocked pivoted Cholesky + skeleton path.
+    # The error bound of eq. 4.6 still holds; the rank is close to (and not
+    # below) the optimal one of the SVD truncation at the same tolerance.
+    _flush(f"round large rank eps={eps}")
+    G = random_tt_cores(12, 40, 3000, 12, 480, seed=12)
+    G = (G[0], G[1], G[2] * np.exp(-0.03 * np.arange(480))[:, None])
+    X = tt.full(G)
+    buf = sg.TTBuf(12, 40, 3000, 16, 480).set_cores(*G)
+    ctx.round(buf, eps)
+    Y = ctx.expand(buf).cpu().numpy()
+    nrm = np.linalg.norm(X)
+    err = np.linalg.norm(Y - X)
+    assert err <= eps * nrm * (1 + 1e-6) + 1e-8 * nrm
+    r_ref = tt.ranks(tt.tt_round(G, eps))
+    assert r_ref[1] > 96
+    assert buf.r2 >= r_ref[1] - 1 and buf.r2 <= 1.5 * r_ref[1] + 4
+    assert abs(buf.r1 - r_ref[0]) <= 1
+
+
 def test_round_sum_cancellation(sg, ctx):
     # x + x - x rounds back to x's ranks and values
     _flush("round cancellation")
