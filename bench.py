@@ -33,13 +33,14 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and FP64 matrix) peak
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="C2")
     ap.add_argument("--outer-explicit", type=int, default=1,
                     help="1: Alg. 4.2 literally (z_k, s_k every outer iteration); 0: least-squares estimate")
     ap.add_argument("--restart", type=int, default=20)
-    ap.add_argument("--relax", type=int, default=0, help="1: relaxed truncation of late Krylov vectors")
+    ap.add_argument("--relax", type=int, default=1,
+                    help="1: relaxed truncation of late Krylov vectors (inexact Krylov); 0: fixed eps of Alg. 4.2")
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", type=int, default=0)
@@ -112,6 +113,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile_read()
+    phases = ctx.profile_regions()
     ctx.profile(False)
     elapsed = t1 - t0
     ev_s = ev0.elapsed_time(ev1) * 1e-3
@@ -155,6 +157,7 @@ def main():
         "roofline": roof,
         "kernels": {k: {"ms": v["seconds"] * 1e3, "launches": v["launches"]} for k, v in prof.items()
                     if v["launches"]},
+        "phases_ms": {r: {k: round(v * 1e3, 1) for k, v in row.items()} for r, row in phases.items()},
     }
     if not args.no_cpu_baseline:
         try:

@@ -197,6 +197,16 @@ int sgtt_profile_read(sgtt_context* ctx, int max_classes, double* seconds, doubl
                       long* launches, int* nclasses);
 /* kernel symbol name of a class id (static storage) */
 const char* sgtt_profile_class_name(int cls);
+/* The same event seconds split by phase of the solve (outer apply, outer
+ * Gram-Schmidt, outer solution/residual sums, LSC pressure part, inner
+ * right-hand side, inner M^-1, inner apply, inner Gram-Schmidt, inner
+ * solution, exact residual, other): seconds[r * max_classes + c] for
+ * r < max_regions, c < max_classes.  *nregions gets the number of phases.
+ * Synchronizes the context stream. */
+int sgtt_profile_read_regions(sgtt_context* ctx, int max_regions, int max_classes, double* seconds,
+                              int* nregions);
+/* name of a phase id (static storage) */
+const char* sgtt_profile_region_name(int region);
 
 /* ------------------------------------------------------------- host setup */
 /* Host-only problem setup (no device calls), for inspection and checks:

@@ -18,6 +18,21 @@ bool prof_enabled();
 // sums since the last reset: seconds (from events), bytes, flops, launches
 void prof_read(double* seconds, double* bytes, double* flops, long* launches);
 void prof_reset();
+// Phases of the solve that launches are attributed to (prof_region sets the
+// current one and returns the previous one).
+enum Region {
+  RG_OTHER = 0, RG_OUT_APPLY, RG_OUT_MGS, RG_OUT_SOL, RG_LSC, RG_IN_RHS, RG_IN_MINV, RG_IN_APPLY, RG_IN_MGS,
+  RG_IN_SOL, RG_RESIDUAL, RG_COUNT
+};
+const char* region_name(int r);
+int prof_region(int r);
+// seconds[r * KC_COUNT + c] since the last reset
+void prof_read_regions(double* seconds);
+struct RegionScope {
+  int old;
+  explicit RegionScope(int r) : old(prof_region(r)) {}
+  ~RegionScope() { prof_region(old); }
+};
 
 // C[b](i,j) = alpha * sum_k A[b](i,k) B[b](k,j) + beta * C[b](i,j)
 // element (i,k) of A[b] at A + b*sAb + i*sAi + k*sAk (likewise B, C).

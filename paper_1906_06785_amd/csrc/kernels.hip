@@ -17,7 +17,7 @@ namespace sgtt {
 // ---------------------------------------------------------------- profiling
 namespace {
 struct ProfRec {
-  int cls;
+  int cls, region;
   hipEvent_t a, b;
   double bytes, flops;
 };
@@ -37,6 +37,7 @@ struct Profiler {
 };
 Profiler g_prof;
 std::mutex g_prof_mu;
+int g_region = 0;
 
 struct ProfScope {
   int cls;
@@ -54,7 +55,7 @@ struct ProfScope {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     hipEvent_t b = g_prof.ev();
     (void)hipEventRecord(b, s);
-    g_prof.recs.push_back(ProfRec{cls, a, b, bytes, flops});
+    g_prof.recs.push_back(ProfRec{cls, g_region, a, b, bytes, flops});
   }
 };
 }  // namespace
@@ -63,6 +64,27 @@ const char* kernel_class_name(int cls) {
   static const char* names[] = {"k_gemm", "k_gemm_ptr", "k_spmm", "k_bt_diag", "k_bt_sweep", "k_trunc_eig",
                                 "k_reduce_partials", "other"};
   return (cls >= 0 && cls < KC_COUNT) ? names[cls] : "?";
+}
+const char* region_name(int r) {
+  static const char* names[] = {"other",       "outer_apply", "outer_mgs", "outer_solution", "lsc_pressure",
+                                "inner_rhs",   "inner_minv",  "inner_apply", "inner_mgs",    "inner_solution",
+                                "residual"};
+  return (r >= 0 && r < RG_COUNT) ? names[r] : "?";
+}
+int prof_region(int r) {
+  int old = g_region;
+  g_region = (r >= 0 && r < RG_COUNT) ? r : 0;
+  return old;
+}
+void prof_read_regions(double* seconds) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (int i = 0; i < RG_COUNT * KC_COUNT; ++i) seconds[i] = 0.0;
+  for (auto& r : g_prof.recs) {
+    (void)hipEventSynchronize(r.b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    seconds[r.region * KC_COUNT + r.cls] += ms * 1e-3;
+  }
 }
 void prof_enable(bool on) { g_prof.on = on; }
 bool prof_enabled() { return g_prof.on; }
@@ -96,9 +118,8 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 // ------------------------------------------------------------------ GEMM
 constexpr int TM = 64, TN = 64, TK = 16;
 
-// Tiled FP64 GEMM: 64 x 64 output tile per 256-thread workgroup (4 x 4 per
-// thread), K staged through LDS in slices of 16 with the next slice
-// prefetched into registers while the current one is consumed.
+// Tiled FP64 GEMM: global -> register -> LDS staging of 64 x 16 (A) and
+// 16 x 64 (B) slices, 4 elements per thread.
 __device__ __forceinline__ void gemm_load_tile(const double* __restrict__ A, long sAi, long sAk, int m, const double* __restrict__ B,
                                                long sBk, long sBj, int n, long kb, int i0, int j0, long kk, bool a_kfast,
                                                bool b_kfast, int tid, double ra[4], double rb[4]) {
@@ -130,18 +151,27 @@ __device__ __forceinline__ void gemm_store_tile(double As[TK][TM + 1], double Bs
   }
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// 64 x 64 output tile per 256-thread workgroup on the FP64 matrix cores: each
+// wave owns a 32 x 32 quarter as 2 x 2 tiles of v_mfma_f64_16x16x4 (lane l
+// supplies A[l%16][l/16] and B[l/16][l%16]; accumulator item v of lane l is
+// D[4v + l/16][l%16]).  K is staged through LDS in slices of 16, the next
+// slice prefetched into registers while the current one is consumed.
 __device__ __forceinline__ void gemm_core(int m, int n, long kb, double alpha, const double* __restrict__ A, long sAi,
                                           long sAk, const double* __restrict__ B, long sBk, long sBj, double beta,
                                           double* __restrict__ C, long sCi, long sCj, int i0, int j0) {
   __shared__ double As[TK][TM + 1];
   __shared__ double Bs[TK][TN + 1];
   const int tid = threadIdx.x;
-  const int ti = tid / 16, tj = tid % 16;
-  double acc[4][4];
+  const int wave = tid / 64, lane = tid % 64;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int lr = lane % 16, lk = lane / 16;
+  dbl4 acc[2][2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int c = 0; c < 2; ++c) acc[r][c] = dbl4{0.0, 0.0, 0.0, 0.0};
   const bool a_kfast = (sAk == 1);
   const bool b_kfast = (sBk == 1);
   double ra[4], rb[4];
@@ -151,33 +181,33 @@ __device__ __forceinline__ void gemm_core(int m, int n, long kb, double alpha, c
     __syncthreads();
     if (kk + TK < kb) gemm_load_tile(A, sAi, sAk, m, B, sBk, sBj, n, kb, i0, j0, kk + TK, a_kfast, b_kfast, tid, ra, rb);
 #pragma unroll
-    for (int kx = 0; kx < TK; ++kx) {
-      double a[4], bb[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = As[kx][ti + 16 * r];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) bb[c] = Bs[kx][tj + 16 * c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], bb[c], acc[r][c]);
+    for (int kq = 0; kq < TK / 4; ++kq) {
+      const int kr = kq * 4 + lk;
+      const double a0 = As[kr][wr + lr], a1 = As[kr][wr + 16 + lr];
+      const double b0 = Bs[kr][wc + lr], b1 = Bs[kr][wc + 16 + lr];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    long gi = i0 + ti + 16 * r;
-    if (gi >= m) continue;
+  for (int tr = 0; tr < 2; ++tr)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      long gj = j0 + tj + 16 * c;
-      if (gj >= n) continue;
-      double* cp = C + gi * sCi + gj * sCj;
-      double v = alpha * acc[r][c];
-      if (beta != 0.0) v += beta * (*cp);
-      *cp = v;
+    for (int v = 0; v < 4; ++v) {
+      const long gi = i0 + wr + tr * 16 + 4 * v + lk;
+      if (gi >= m) continue;
+#pragma unroll
+      for (int tc = 0; tc < 2; ++tc) {
+        const long gj = j0 + wc + tc * 16 + lr;
+        if (gj >= n) continue;
+        double* cp = C + gi * sCi + gj * sCj;
+        double val = alpha * acc[tr][tc][v];
+        if (beta != 0.0) val += beta * (*cp);
+        *cp = val;
+      }
     }
-  }
 }
 
 __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, double alpha, const double* __restrict__ A,

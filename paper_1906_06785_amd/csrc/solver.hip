@@ -311,6 +311,10 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
                    double eps_max = 1e-2) {
   const int ld = maxit + 1;
   const int nc = b.nc;
+  const bool inner = std::strcmp(tag, "inner") == 0;
+  const int rg_apply = inner ? RG_IN_APPLY : RG_OUT_APPLY, rg_mgs = inner ? RG_IN_MGS : RG_OUT_MGS,
+            rg_sol = inner ? RG_IN_SOL : RG_OUT_SOL;
+  RegionScope rg0(inner ? RG_IN_RHS : RG_OUT_SOL);
   double* H = dscal;                          // ld x maxit, column-major
   double* GV = H + (size_t)ld * maxit;        // ld x ld
   double* d = GV + (size_t)ld * ld;           // ld
@@ -348,11 +352,17 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
   while (res > tol * bnorm && k < maxit) {
     ++k;
     double t0 = now_s();
-    Vec vh = sp.precond(V[k - 1]);
+    Vec vh;
+    {
+      RegionScope rg(inner ? RG_IN_MINV : RG_LSC);
+      vh = sp.precond(V[k - 1]);
+    }
     double t1 = now_s();
     if (cnt) cnt->t_prec += t1 - t0;
     const double eps_k = relax ? std::min(eps_max, eps * bnorm / std::max(res, 1e-300)) : eps;
+    prof_region(rg_apply);
     Vec x = vec_round(c, sp.apply(vh), eps_k, nullptr, nullptr);
+    prof_region(rg_mgs);
     Vh.push_back(std::move(vh));
     // Gram blocks of the preconditioned basis (for the solution sum)
     for (int q = 0; q < nc; ++q)
@@ -401,12 +411,13 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
       }
     }
     // lines 12-13: least squares, z_k = T(V^ y)
+    prof_region(rg_sol);
     hessenberg_lsq(c.s, H, ld, k, sc + 5, y, sc + 8);
     if (!explicit_res) {
       res = read_double(c, sc + 8);
       if (cnt && cnt->verbose > 1)
-        fprintf(stderr, "[sgtt %s] it %d  est %.3e  ranks v=(%d,%d)\n", tag, k, res / bnorm, V.back().c[0].r1,
-                V.back().c[0].r2);
+        fprintf(stderr, "[sgtt %s] it %d  est %.3e  ranks v=(%d,%d) x=(%d,%d) rhs=(%d,%d)\n", tag, k, res / bnorm,
+                V.back().c[0].r1, V.back().c[0].r2, x.c[0].r1, x.c[0].r2, V[0].c[0].r1, V[0].c[0].r2);
       if (breakdown) break;
       continue;
     }
@@ -446,6 +457,7 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
   }
   iters = k;
   relres = res / bnorm;
+  prof_region(rg_sol);
   if (!explicit_res && k > 0) {
     z = Vec();
     z.nc = nc;
@@ -509,7 +521,9 @@ Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCoun
   InnerSpace isp(S);
   int its = 0;
   double rr = 0;
-  Vec v = lowrank_fgmres(c, isp, rhs, po.inner_tol, po.inner_eps, po.inner_maxit, S.dsc + 16384, its, rr, nullptr,
+  SolveCounters icnt;
+  icnt.verbose = cnt ? cnt->verbose : 0;
+  Vec v = lowrank_fgmres(c, isp, rhs, po.inner_tol, po.inner_eps, po.inner_maxit, S.dsc + 16384, its, rr, &icnt,
                          "inner", po.inner_explicit);
   if (cnt) cnt->inner += its;
   Vec out;
@@ -532,6 +546,7 @@ struct OuterSpace : Space {
 double full_residual(sgtt_system& S, const Vec& b, const Vec& z, double* d_out_sq, Vec* r_tt, double eps_tt,
                      double* bnorm_cache) {
   Ctx& c = S.ctx->c;
+  RegionScope rg(RG_RESIDUAL);
   Vec Lz = apply_L(S, z);
   Vec r = vec_concat(c, {&b, &Lz}, nullptr, {1.0, -1.0});
   double tot = 0.0, bn2 = bnorm_cache ? *bnorm_cache : -1.0;
@@ -1213,6 +1228,20 @@ int sgtt_profile_read(sgtt_context* ctx, int max_classes, double* seconds, doubl
 }
 
 const char* sgtt_profile_class_name(int cls) { return kernel_class_name(cls); }
+
+int sgtt_profile_read_regions(sgtt_context* ctx, int max_regions, int max_classes, double* seconds, int* nregions) {
+  if (!ctx || !seconds || max_regions < 0 || max_classes < 0) return SGTT_E_INVALID;
+  (void)hipStreamSynchronize(ctx->c.s);
+  std::vector<double> all((size_t)RG_COUNT * KC_COUNT);
+  prof_read_regions(all.data());
+  for (int r = 0; r < std::min(max_regions, (int)RG_COUNT); ++r)
+    for (int k = 0; k < std::min(max_classes, (int)KC_COUNT); ++k)
+      seconds[(size_t)r * max_classes + k] = all[(size_t)r * KC_COUNT + k];
+  if (nregions) *nregions = RG_COUNT;
+  return SGTT_OK;
+}
+
+const char* sgtt_profile_region_name(int region) { return region_name(region); }
 
 // ---------------------------------------------------------------- host-only
 struct sgtt_host_problem {

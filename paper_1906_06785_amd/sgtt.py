@@ -91,6 +91,8 @@ _sig = {
     "sgtt_profile_read": (C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), C.POINTER(C.c_long), C.POINTER(C.c_int)]),
     "sgtt_profile_class_name": (C.c_char_p, [C.c_int]),
+    "sgtt_profile_read_regions": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+    "sgtt_profile_region_name": (C.c_char_p, [C.c_int]),
     "sgtt_host_problem_create": (C.c_int, [C.POINTER(ProblemDesc), C.POINTER(_P)]),
     "sgtt_host_problem_destroy": (C.c_int, [_P]),
     "sgtt_host_sizes": (C.c_int, [_P, C.POINTER(C.c_int)]),
@@ -302,6 +304,20 @@ class Context:
         for i in range(nc.value):
             out[_lib.sgtt_profile_class_name(i).decode()] = dict(seconds=sec[i], bytes=by[i], flops=fl[i],
                                                                  launches=la[i])
+        return out
+
+    def profile_regions(self):
+        """{phase: {kernel class: event seconds}} since profiling was enabled."""
+        nr, ncls = 32, 16
+        sec = (C.c_double * (nr * ncls))()
+        got = C.c_int()
+        self.check(_lib.sgtt_profile_read_regions(self._c, nr, ncls, sec, C.byref(got)))
+        out = {}
+        for r in range(min(got.value, nr)):
+            row = {_lib.sgtt_profile_class_name(c).decode(): sec[r * ncls + c] for c in range(ncls)
+                   if sec[r * ncls + c] > 0}
+            if row:
+                out[_lib.sgtt_profile_region_name(r).decode()] = row
         return out
 
     def hessenberg_lsq(self, H: np.ndarray, beta: float):
