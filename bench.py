@@ -30,7 +30,7 @@ PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and FP64 matrix) peak
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
@@ -44,7 +44,17 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", type=int, default=0)
-    return ap.parse_args()
+    return ap.parse_args(argv)
+
+
+def solve_options(args=None):
+    """Options of the timed solve; the defaults are the configuration bench.py times."""
+    if args is None:
+        args = parse([])
+    return dict(restart=args.restart, outer_explicit=args.outer_explicit, verbose=args.verbose, relax=args.relax)
+
+
+OUT_CAPS = (128, 4096)   # output TT capacity (core-1 rank, core-2 rank) of the solution
 
 
 def cpu_baseline(cfg, budget, gpu_outer_per_solve):
@@ -94,8 +104,8 @@ def main():
     S = sgtt.System(ctx, cfg)
     b = S.rhs()
     setup_s = time.perf_counter() - t_setup
-    opts = dict(restart=args.restart, outer_explicit=args.outer_explicit, verbose=args.verbose, relax=args.relax)
-    out = S.pair(128, 4096)
+    opts = solve_options(args)
+    out = S.pair(*OUT_CAPS)
     for _ in range(args.warmup):
         S.solve(b, out, **opts)
     torch.cuda.synchronize()

@@ -174,6 +174,14 @@ int sgtt_solve(sgtt_system* sys, const sgtt_tt_pair* b, sgtt_tt_pair* x, const s
  * (synchronizes; result to host). */
 int sgtt_residual(sgtt_system* sys, const sgtt_tt_pair* b, const sgtt_tt_pair* x, double* rel);
 
+/* The same exact residual r = b - L x, also written out in full format:
+ * ru (device, n_t * n_xi * n_u doubles) and rp (device, n_t * n_xi * n_p),
+ * C order (time slowest, space fastest; eq. 4.1), caller-owned.  *rel gets
+ * ||r|| / ||b||.  For checking a solve at sizes where a full tensor still
+ * fits in HBM (2 GB per velocity tensor at the 64 x 192 grid). */
+int sgtt_residual_tensor(sgtt_system* sys, const sgtt_tt_pair* b, const sgtt_tt_pair* x, double* ru,
+                         double* rp, double* rel);
+
 /* Expand a TT to the full tensor out (n1*n2*n3 doubles, device, C order). */
 int sgtt_expand(sgtt_context* ctx, const sgtt_tt* x, double* out);
 

@@ -175,6 +175,54 @@ class Problem:
         yp = np.asarray(self.B @ U.T).T.reshape(nt, nx, -1)
         return yu, yp
 
+    def residual_entries(self, b, x, which, t, i, j, conv=None):
+        """Entries r[t_k, i_k, j_k] of r = b - L x (eq. 3.11-3.12), one by one
+        from the TT cores: each sparse operator row touches only the core-3
+        columns of its nonzeros.  which = "u" (velocity rows, free dofs) or
+        "p" (pressure rows).  No full tensor is formed, so this works at any
+        size.  Convection is not supported here (Stokes systems)."""
+        if conv is not None:
+            raise NotImplementedError("residual_entries: Stokes systems only")
+        u, pp = x
+        t = np.asarray(t, dtype=np.int64)
+        i = np.asarray(i, dtype=np.int64)
+        j = np.asarray(j, dtype=np.int64)
+        # core1 x core2 contracted once per TT: G12[t] is the (n_xi x r2) slice
+        g12 = {}
+
+        def G12(G):
+            key = id(G)
+            if key not in g12:
+                g12[key] = np.einsum("ta,aib->tib", G[0], G[1])
+            return g12[key]
+
+        def row_vals(G, mat, tk, row):
+            # (mat @ X_t^T)[row] for all chaos indices: (n_xi,)  with X_t = G1[t] G2 G3
+            lo, hi = mat.indptr[row], mat.indptr[row + 1]
+            cols, vals = mat.indices[lo:hi], mat.data[lo:hi]
+            return G12(G)[tk] @ (G[2][:, cols] @ vals)
+
+        def entry_of(G, tk, ik, row, mat):
+            return row_vals(G, mat, tk, row)[ik]
+
+        out = np.empty(len(t))
+        if which == "u":
+            Iu = sp.identity(self.n_u, format="csr")
+            for k in range(len(t)):
+                tk, ik, jk = int(t[k]), int(i[k]), int(j[k])
+                mu = row_vals(u, self.Mb, tk, jk)
+                if tk > 0:
+                    mu = mu - row_vals(u, self.Mb, tk - 1, jk)
+                au = row_vals(u, self.Ab, tk, jk)
+                lx = mu[ik] / self.tau + self.Gnu[ik] @ au + entry_of(pp, tk, ik, jk, self.Bt)
+                out[k] = entry_of(b[0], tk, ik, jk, Iu) - lx
+        else:
+            Ip = sp.identity(self.n_p, format="csr")
+            for k in range(len(t)):
+                tk, ik, jk = int(t[k]), int(i[k]), int(j[k])
+                out[k] = entry_of(b[1], tk, ik, jk, Ip) - entry_of(u, tk, ik, jk, self.B)
+        return out
+
     def explicit(self, conv=None):
         """Explicit sparse all-at-once matrix (scipy.sparse.kron), small sizes."""
         kron = sp.kron

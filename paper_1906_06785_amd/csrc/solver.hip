@@ -544,7 +544,7 @@ struct OuterSpace : Space {
 
 // exact ||b - L z|| / ||b|| in full format
 double full_residual(sgtt_system& S, const Vec& b, const Vec& z, double* d_out_sq, Vec* r_tt, double eps_tt,
-                     double* bnorm_cache) {
+                     double* bnorm_cache, double* const* full_out = nullptr) {
   Ctx& c = S.ctx->c;
   RegionScope rg(RG_RESIDUAL);
   Vec Lz = apply_L(S, z);
@@ -557,15 +557,17 @@ double full_residual(sgtt_system& S, const Vec& b, const Vec& z, double* d_out_s
   for (int i = 0; i < 2; ++i) {
     const TT& ri = r.c[i];
     long n = (long)ri.n1 * ri.n2 * ri.n3;
-    double* full = c.pool.get(n);
+    double* full = full_out ? full_out[i] : c.pool.get(n);
     tt_expand(c, ri, full);
     sumsq(c.s, full, n, sq + i, ws, 1 << 16);
     if (r_tt) rt[i] = tt_from_full(c, full, ri.n1, ri.n2, ri.n3, eps_tt, nullptr);
     if (bn2 < 0) {
-      tt_expand(c, b.c[i], full);
-      sumsq(c.s, full, n, sq + 2 + i, ws, 1 << 16);
+      double* fb = full_out ? c.pool.get(n) : full;
+      tt_expand(c, b.c[i], fb);
+      sumsq(c.s, fb, n, sq + 2 + i, ws, 1 << 16);
+      if (full_out) c.pool.put(fb);
     }
-    c.pool.put(full);
+    if (!full_out) c.pool.put(full);
   }
   SGTT_HIP(hipMemcpyAsync(c.hdbl, sq, 4 * sizeof(double), hipMemcpyDeviceToHost, c.s));
   c.sync();
@@ -1119,6 +1121,21 @@ int sgtt_residual(sgtt_system* S, const sgtt_tt_pair* b, const sgtt_tt_pair* x, 
     check_tt(x->p, S->nt, S->nxi, S->np);
     Vec bv = vec_from_pair(b), xv = vec_from_pair(x);
     *rel = full_residual(*S, bv, xv, nullptr, nullptr, 0.0, nullptr);
+  });
+}
+
+int sgtt_residual_tensor(sgtt_system* S, const sgtt_tt_pair* b, const sgtt_tt_pair* x, double* ru, double* rp,
+                         double* rel) {
+  if (!S || !b || !x || !ru || !rp || !rel) return SGTT_E_INVALID;
+  sgtt_context* ctx = S->ctx;
+  return guarded(ctx, [&]() {
+    check_tt(b->u, S->nt, S->nxi, S->nu);
+    check_tt(b->p, S->nt, S->nxi, S->np);
+    check_tt(x->u, S->nt, S->nxi, S->nu);
+    check_tt(x->p, S->nt, S->nxi, S->np);
+    Vec bv = vec_from_pair(b), xv = vec_from_pair(x);
+    double* outs[2] = {ru, rp};
+    *rel = full_residual(*S, bv, xv, nullptr, nullptr, 0.0, nullptr, outs);
   });
 }
 

@@ -91,6 +91,8 @@ _sig = {
     "sgtt_profile_read": (C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), C.POINTER(C.c_long), C.POINTER(C.c_int)]),
     "sgtt_profile_class_name": (C.c_char_p, [C.c_int]),
+    "sgtt_residual_tensor": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), _P, _P,
+                                       C.POINTER(C.c_double)]),
     "sgtt_profile_read_regions": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "sgtt_profile_region_name": (C.c_char_p, [C.c_int]),
     "sgtt_host_problem_create": (C.c_int, [C.POINTER(ProblemDesc), C.POINTER(_P)]),
@@ -389,6 +391,18 @@ class System:
         sb, sx = b.struct(), x.struct()
         self.ctx.check(_lib.sgtt_residual(self._s, C.byref(sb), C.byref(sx), C.byref(r)))
         return r.value
+
+    def residual_tensor(self, b: PairBuf, x: PairBuf):
+        """(ru, rp, rel): the exact residual b - L x as full device tensors."""
+        torch = _torch()
+        dev = torch.device("cuda", self.ctx.device)
+        ru = torch.empty((self.nt, self.nxi, self.nu), dtype=torch.float64, device=dev)
+        rp = torch.empty((self.nt, self.nxi, self.np), dtype=torch.float64, device=dev)
+        r = C.c_double()
+        sb, sx = b.struct(), x.struct()
+        self.ctx.check(_lib.sgtt_residual_tensor(self._s, C.byref(sb), C.byref(sx), ru.data_ptr(), rp.data_ptr(),
+                                                 C.byref(r)))
+        return ru, rp, r.value
 
     def __del__(self):
         if getattr(self, "_s", None) and _lib is not None:

@@ -241,3 +241,18 @@ def test_stochastic_galerkin_mean_matches_quadrature():
         ud, _ = Pd.solve_direct(tt.full(bd[0]), tt.full(bd[1]))
         mean += 0.5 * w * ud[-1, 0]
     assert np.linalg.norm(u[-1, 0] - mean) <= 1e-9 * np.linalg.norm(mean)
+
+
+def test_residual_entries_match_full_residual():
+    # the entry-by-entry residual (used at sizes where no full tensor fits
+    # the oracle) equals the full-tensor residual b - L x at every entry
+    P = Problem(CONFIGS["tiny"])
+    x = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (3, 4), (2, 3), 5)
+    b = P.rhs()
+    yu, yp = P.apply_full(tt.full(x[0]), tt.full(x[1]))
+    ru, rp = tt.full(b[0]) - yu, tt.full(b[1]) - yp
+    g = np.random.default_rng(0)
+    for which, full, n in (("u", ru, P.n_u), ("p", rp, P.n_p)):
+        t, i, j = g.integers(0, P.nt, 60), g.integers(0, P.n_xi, 60), g.integers(0, n, 60)
+        e = P.residual_entries(b, x, which, t, i, j)
+        assert np.abs(e - full[t, i, j]).max() <= 1e-13 * np.abs(full).max()
