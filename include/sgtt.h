@@ -85,6 +85,8 @@ typedef struct {
   int conv_r1, conv_r2;   /* ranks of the convection field w~ (0 for Stokes) */
   int rhs_r1u, rhs_r2u, rhs_r1p, rhs_r2p;
   double setup_seconds;
+  double rhs_norm;     /* ||f|| (Stokes) or the norm of the untruncated
+                          nonlinear residual of the prior iterate (Picard) */
 } sgtt_system_info;
 
 typedef struct {
@@ -169,6 +171,43 @@ int sgtt_axpby(sgtt_context* ctx, double alpha, const sgtt_tt_pair* x, double be
  * x is output only (z_0 = 0).  opts = NULL uses defaults. */
 int sgtt_solve(sgtt_system* sys, const sgtt_tt_pair* b, sgtt_tt_pair* x, const sgtt_solve_opts* opts,
                sgtt_solve_stats* stats);
+
+/* ------------------------------------------------------------- Picard */
+#define SGTT_PICARD_MAX_STEPS 16
+
+typedef struct {
+  int max_steps;          /* Picard steps after the Stokes solve (Alg. 3.1, maxit) */
+  double tol_picard;      /* stop when ||r^(i)|| <= tol_picard ||f|| (Alg. 3.1)    */
+  double eps_soln;        /* truncation of the updated iterates (eq. 4.8)          */
+  sgtt_solve_opts solve;  /* options of every linear solve                        */
+} sgtt_picard_opts;
+
+typedef struct {
+  int steps;                                            /* Picard steps taken     */
+  double nonlinear_residual[SGTT_PICARD_MAX_STEPS + 1]; /* ||r^(i)|| / ||f||      */
+  double linear_residual[SGTT_PICARD_MAX_STEPS + 1];    /* solve i (0 = Stokes)   */
+  int outer_iters[SGTT_PICARD_MAX_STEPS + 1];
+  int inner_iters[SGTT_PICARD_MAX_STEPS + 1];
+  double solve_seconds[SGTT_PICARD_MAX_STEPS + 1];
+  double assemble_seconds[SGTT_PICARD_MAX_STEPS + 2];
+  int rank_u[SGTT_PICARD_MAX_STEPS + 1][2];             /* iterate ranks after    */
+  int rank_p[SGTT_PICARD_MAX_STEPS + 1][2];             /* solve i and eq. 4.8    */
+  double seconds;
+} sgtt_picard_stats;
+
+/* Picard's method (Alg. 3.1) with the low-rank variant of sec. 4.3: the
+ * Stokes solve gives u^(0), p^(0); each step assembles the system with the
+ * convection of w~ = T_eps_conv(u^(i-1)) (eq. 4.13), takes the nonlinear
+ * residual r^(i-1) = f - L(u^(i-1)) [u^(i-1); p^(i-1)] of the untruncated
+ * iterate (truncated at desc->eps_rhs for the right-hand side), solves for
+ * (du, dp) with opts->solve, and sets u^(i) = T_eps_soln(u^(i-1) + du),
+ * p^(i) likewise (eq. 4.8).  Stops when ||r^(i)|| <= tol_picard ||f|| or
+ * after max_steps (<= SGTT_PICARD_MAX_STEPS) steps; the residual of the
+ * returned iterate is always evaluated (nonlinear_residual[steps]).  x:
+ * caller buffers for the last iterate (capacity checked).  Returns
+ * SGTT_W_NOT_CONVERGED if a linear solve missed its tolerance. */
+int sgtt_picard(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_picard_opts* opts,
+                sgtt_tt_pair* x, sgtt_picard_stats* stats);
 
 /* Exact ||b - L x|| / ||b|| evaluated in full format on the device
  * (synchronizes; result to host). */

@@ -345,3 +345,30 @@ def solve_full(prob, bu, bp, conv=None, tol=1e-8, maxit=60, inner_tol=1e-1, inne
     b = ops.join(bu, bp)
     z, k, res, bn = lowrank_fgmres(ops, ops.apply, pc, b, tol, 0.0, maxit, record)
     return ops.split(z), dict(outer=k, rel=res / bn, inner=prec.inner_iters)
+
+
+def picard_direct(prob, steps, eps_conv=None):
+    """Picard's method (Alg. 3.1) with exact linear solves and no truncation
+    of the iterates: the Stokes solve gives (u0, p0); step i solves the
+    residual equation eq. 3.14 with N(w~), w~ = T_eps_conv(w) (w~ = w when
+    eps_conv is None), right-hand side r = f - L(w)[w; p] of the untruncated
+    iterate (eq. 3.15), and adds the update.  Returns the full iterates
+    [(U_i, P_i)] and the norms ||r^(i)|| / ||f|| of the nonlinear residual
+    of each iterate (i = 0..steps).  Glue around pinned pieces (direct
+    solves, exact residual TTs, convection operator); the loop itself is
+    parity unpinned."""
+    f = prob.rhs(None)
+    fnorm = np.sqrt(tt.tt_dot(f[0], f[0]) + tt.tt_dot(f[1], f[1]))
+    U, Pp = prob.solve_direct(tt.full(f[0]), tt.full(f[1]))
+    iterates, res = [(U, Pp)], []
+    for i in range(steps + 1):
+        prior = (tt.tt_svd(U, 1e-15), tt.tt_svd(Pp, 1e-15))
+        r = prob.residual_tt(prior)
+        res.append(np.sqrt(tt.tt_dot(r[0], r[0]) + tt.tt_dot(r[1], r[1])) / fnorm)
+        if i == steps:
+            break
+        conv = prob.convection(prior, 1e-15 if eps_conv is None else eps_conv)
+        dU, dP = prob.solve_direct(tt.full(r[0]), tt.full(r[1]), conv)
+        U, Pp = U + dU, Pp + dP
+        iterates.append((U, Pp))
+    return iterates, res

@@ -477,6 +477,17 @@ void lsc_middle_values(const HostProblem& hp, const double* S, double* out) {
   }
 }
 
+void reference_tables(double* out) {
+  const RefTables& R = ref();
+  for (int g = 0; g < 9; ++g) out[g] = R.w[g];
+  for (int g = 0; g < 9; ++g)
+    for (int k = 0; k < 9; ++k) {
+      out[9 + g * 9 + k] = R.phi[g][k];
+      out[90 + g * 9 + k] = R.dxi[g][k];
+      out[171 + g * 9 + k] = R.deta[g][k];
+    }
+}
+
 void convection_values(const HostProblem& hp, const double* w1, const double* w2, double* vff,
                        double* vfa) {
   const Mesh& m = hp.mesh;

@@ -98,6 +98,11 @@ void build_problem(const ProblemParams& prm, HostProblem& hp);
 void convection_values(const HostProblem& hp, const double* w1, const double* w2,
                        double* vals_ff, double* vals_fa);
 
+// Q2 reference-element tables on the 3 x 3 Gauss points (the ones every
+// assembly here uses): out[0..8] weights, then phi, d/dxi, d/deta as [g][k]
+// (81 each, k = a + 3 b): 252 doubles.
+void reference_tables(double* out);
+
 // Values of B M*^-1 S M*^-1 B^T on the Xmid pattern for a scalar velocity
 // matrix S given by values on Kff (applied to both components).
 void lsc_middle_values(const HostProblem& hp, const double* Svals, double* out);

@@ -133,6 +133,17 @@ void skeleton_factor(hipStream_t s, int N, int k, const double* L, const int* pi
 void gather_rows(hipStream_t s, int k, int cols, const double* in, long ld_in, const int* piv, double* out,
                  long ld_out);
 
+// Stochastic Galerkin convection N(w) w in full format (eq. 3.7, eq. 4.12):
+// out[t, i, c*ns + f] += sign * (SG convection of the wind with itself),
+// with the wind = ufree (n_t x n_xi x n_u, free dofs [comp1; comp2]) plus the
+// Dirichlet lift ramp(t) e_1 gall (gall: 2 n_all).  conn: 9 Q2 nodes per
+// element; free_id: node -> free index or -1; H_{ilk} as rows i (hrow,
+// hl, hk, hv); ref: reference tables (252 doubles); hh = h / 2.  n_xi <= 64.
+void sg_convection_full(hipStream_t s, int nt, int nxi, int n_u, int ns, int nall, int nelem, const int* conn,
+                        const int* free_id, const double* ufree, const double* ramp, const double* gall,
+                        const int* hrow, const int* hl, const int* hk, const double* hv, const double* ref, double hh,
+                        double sign, double* out);
+
 // Block-tridiagonal solve Y = A^-1 X on ncols columns of a node-major
 // matrix (row = space index, ld = ldx) with `ncomp` components stacked by
 // rows (component c occupies rows [c*n, (c+1)*n)).  Blocks up to 256 rows.

@@ -746,6 +746,88 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
   }
 }
 
+// ------------------------------------------------------------------ SG convection, full format
+constexpr int SGC_NXI = 64;   // largest chaos dimension of the full-format convection
+
+// One wave per (element, time step): out[t, i, c*ns + free(a)] += sign *
+//   sum_g w_g phi_a(g) sum_{l,k} H_{ilk} (W_l(g) . grad) U_{k,c}(g) * (h/2),
+// the stochastic Galerkin convection N(w) w of eq. 3.7 / eq. 4.12 with the
+// wind w = free velocity (full tensor) + Dirichlet lift ramp(t) e_1 g.
+__global__ __launch_bounds__(64) void k_sg_convection(int nxi, int n_u, int ns, int nall,
+                                                      const int* __restrict__ conn, const int* __restrict__ free_id,
+                                                      const double* __restrict__ ufree,
+                                                      const double* __restrict__ ramp,
+                                                      const double* __restrict__ gall, const int* __restrict__ hrow,
+                                                      const int* __restrict__ hl, const int* __restrict__ hk,
+                                                      const double* __restrict__ hv, const double* __restrict__ ref,
+                                                      double hh, double sign, double* __restrict__ out) {
+  __shared__ double wl[9 * 2 * SGC_NXI];        // nodal wind [a][c][l]; later reused for C[g][c][i]
+  __shared__ double Wq[9 * 2 * SGC_NXI];        // wind at Gauss points [g][c][l]
+  __shared__ double Gq[9 * 4 * SGC_NXI];        // reference gradients [g][c][d][k]
+  __shared__ double rt[252];
+  __shared__ int nodes[9], fids[9];
+  const int e = blockIdx.x, t = blockIdx.y, tid = threadIdx.x;
+  for (int q = tid; q < 252; q += 64) rt[q] = ref[q];
+  if (tid < 9) {
+    nodes[tid] = conn[(long)e * 9 + tid];
+    fids[tid] = free_id[nodes[tid]];
+  }
+  __syncthreads();
+  const double* W = rt;
+  const double* PHI = rt + 9;
+  const double* DX = rt + 90;
+  const double* DY = rt + 171;
+  const double rmp = ramp[t];
+  for (int o = tid; o < 18 * nxi; o += 64) {
+    const int a = o / (2 * nxi), c = (o / nxi) % 2, l = o % nxi;
+    const int f = fids[a];
+    double v;
+    if (f >= 0) v = ufree[((long)t * nxi + l) * n_u + (long)c * ns + f];
+    else v = (l == 0) ? rmp * gall[(long)c * nall + nodes[a]] : 0.0;
+    wl[(a * 2 + c) * SGC_NXI + l] = v;
+  }
+  __syncthreads();
+  for (int o = tid; o < 18 * nxi; o += 64) {
+    const int g = o / (2 * nxi), c = (o / nxi) % 2, l = o % nxi;
+    double sv = 0.0, sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      const double v = wl[(a * 2 + c) * SGC_NXI + l];
+      sv = fma(PHI[g * 9 + a], v, sv);
+      sx = fma(DX[g * 9 + a], v, sx);
+      sy = fma(DY[g * 9 + a], v, sy);
+    }
+    Wq[(g * 2 + c) * SGC_NXI + l] = sv;
+    Gq[((g * 2 + c) * 2 + 0) * SGC_NXI + l] = sx;
+    Gq[((g * 2 + c) * 2 + 1) * SGC_NXI + l] = sy;
+  }
+  __syncthreads();
+  double* Cq = wl;
+  for (int o = tid; o < 18 * nxi; o += 64) {
+    const int g = o / (2 * nxi), c = (o / nxi) % 2, i = o % nxi;
+    const double* w0 = Wq + (g * 2 + 0) * SGC_NXI;
+    const double* w1 = Wq + (g * 2 + 1) * SGC_NXI;
+    const double* gx = Gq + ((g * 2 + c) * 2 + 0) * SGC_NXI;
+    const double* gy = Gq + ((g * 2 + c) * 2 + 1) * SGC_NXI;
+    double s = 0.0;
+    for (int q = hrow[i]; q < hrow[i + 1]; ++q) {
+      const int l = hl[q], k = hk[q];
+      s = fma(hv[q], fma(w0[l], gx[k], w1[l] * gy[k]), s);
+    }
+    Cq[(g * 2 + c) * SGC_NXI + i] = s;
+  }
+  __syncthreads();
+  for (int o = tid; o < 18 * nxi; o += 64) {
+    const int a = o / (2 * nxi), c = (o / nxi) % 2, i = o % nxi;
+    const int f = fids[a];
+    if (f < 0) continue;
+    double s = 0.0;
+#pragma unroll
+    for (int g = 0; g < 9; ++g) s = fma(W[g] * PHI[g * 9 + a], Cq[(g * 2 + c) * SGC_NXI + i], s);
+    atomicAdd(out + ((long)t * nxi + i) * n_u + (long)c * ns + f, sign * hh * s);
+  }
+}
+
 // ------------------------------------------------------------------ blocked pivoted Cholesky
 // state[0] = residual trace, [1] = target (delta^2), [2] = zero threshold,
 // [3] = trace
@@ -1299,6 +1381,16 @@ void gather_rows(hipStream_t s, int k, int cols, const double* in, long ld_in, c
   long total = (long)k * cols;
   if (total <= 0) return;
   hipLaunchKernelGGL(k_gather_rows, dim3(cdiv(total, 256)), dim3(256), 0, s, k, cols, in, ld_in, piv, out, ld_out);
+}
+
+void sg_convection_full(hipStream_t s, int nt, int nxi, int n_u, int ns, int nall, int nelem, const int* conn,
+                        const int* free_id, const double* ufree, const double* ramp, const double* gall,
+                        const int* hrow, const int* hl, const int* hk, const double* hv, const double* ref, double hh,
+                        double sign, double* out) {
+  if (nt <= 0 || nelem <= 0) return;
+  ProfScope ps(KC_OTHER, s, 8.0 * 2.0 * nt * nxi * (double)n_u, 0.0);
+  hipLaunchKernelGGL(k_sg_convection, dim3(nelem, nt), dim3(64), 0, s, nxi, n_u, ns, nall, conn, free_id, ufree,
+                     ramp, gall, hrow, hl, hk, hv, ref, hh, sign, out);
 }
 
 void hessenberg_lsq(hipStream_t s, const double* H, int ld, int k, const double* beta, double* y, double* resid) {

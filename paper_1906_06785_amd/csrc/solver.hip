@@ -125,6 +125,7 @@ struct sgtt_system {
   double* omega = nullptr; // nt x k2 (mean-mode time factors)
   DevBT Fbt, Xbt;          // F_avg and X = B M*^-1 B^T factorizations
   TT bu, bp;               // right-hand side
+  double rhs_norm = 0;     // ||f|| (Stokes) or ||r|| of the untruncated nonlinear residual (Picard)
   double setup_s = 0;
   // solve scratch (device scalars)
   double* dsc = nullptr;   // 32768 doubles: outer GMRES [0,16384), inner [16384,30000), residual [30000,)
@@ -778,213 +779,232 @@ int sgtt_context_destroy(sgtt_context* ctx) {
 
 const char* sgtt_last_error(const sgtt_context* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
-int sgtt_assemble(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_tt_pair* prior, sgtt_system** out) {
-  if (!ctx || !desc || !out) return SGTT_E_INVALID;
-  return guarded(ctx, [&]() {
-    double t0 = now_s();
-    auto S = std::make_unique<sgtt_system>();
-    S->ctx = ctx;
-    S->desc = *desc;
-    Ctx& c = ctx->c;
-    ProblemParams prm;
-    prm.h = desc->h;
-    prm.L = desc->L;
-    prm.m = desc->m;
-    prm.p = desc->p;
-    prm.nt = desc->nt;
-    prm.tau = desc->tau;
-    prm.nu0 = desc->nu0;
-    prm.nu_coef = desc->nu_coef;
-    prm.ramp = desc->ramp;
-    try {
-      build_problem(prm, S->hp);
-    } catch (const std::exception& e) {
-      throw SgttError(-6, std::string("setup: ") + e.what());
+// Builds a system (throws SgttError); see sgtt_assemble.
+sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_tt_pair* prior) {
+  double t0 = now_s();
+  auto S = std::make_unique<sgtt_system>();
+  S->ctx = ctx;
+  S->desc = *desc;
+  Ctx& c = ctx->c;
+  ProblemParams prm;
+  prm.h = desc->h;
+  prm.L = desc->L;
+  prm.m = desc->m;
+  prm.p = desc->p;
+  prm.nt = desc->nt;
+  prm.tau = desc->tau;
+  prm.nu0 = desc->nu0;
+  prm.nu_coef = desc->nu_coef;
+  prm.ramp = desc->ramp;
+  try {
+    build_problem(prm, S->hp);
+  } catch (const std::exception& e) {
+    throw SgttError(-6, std::string("setup: ") + e.what());
+  }
+  HostProblem& hp = S->hp;
+  S->nt = hp.nt;
+  S->nxi = hp.n_xi;
+  S->ns = hp.n_s;
+  S->nu = hp.n_u;
+  S->np = hp.n_p;
+  S->nall = hp.n_all;
+  S->tau = prm.tau;
+  S->nu0 = prm.nu0;
+  SGTT_HIP(hipMalloc(&S->dsc, 32768 * sizeof(double)));
+  S->Gnu = dev_upload(c, hp.Gnu);
+  S->Bd = upload_csr(c, hp.B, {hp.B.val.data()});
+  S->Btd = upload_csr(c, hp.Bt, {hp.Bt.val.data()});
+  {
+    BlockTri bt;
+    std::string err;
+    blocktri_factor(hp.Xp, hp.Xp.val.data(), hp.p_blocks, bt, err);
+    if (!err.empty()) throw SgttError(-6, err);
+    S->Xbt = upload_bt(c, bt);
+  }
+  const int nt = S->nt, nxi = S->nxi, nall = S->nall, ns = S->ns;
+  // Dirichlet lift TT over all nodes: ramp (x) e_1 (x) g_all
+  std::vector<double> e1(nxi, 0.0);
+  e1[0] = 1.0;
+  TT lift = tt_new(c, nt, nxi, 2 * nall, 1, 1);
+  SGTT_HIP(hipMemcpyAsync(lift.c1, hp.ramp.data(), nt * 8, hipMemcpyHostToDevice, c.s));
+  SGTT_HIP(hipMemcpyAsync(lift.c2, e1.data(), nxi * 8, hipMemcpyHostToDevice, c.s));
+  SGTT_HIP(hipMemcpyAsync(lift.c3, hp.g_all.data(), 2 * nall * 8, hipMemcpyHostToDevice, c.s));
+  c.sync();
+  if (!prior) {
+    // Stokes system: no convection; f = -L_{free,all}(0) lift (ranks 2 and 1)
+    S->k1 = S->k2 = 0;
+    S->Kop = upload_csr(c, hp.Kff, {hp.Mff.data(), hp.Aff.data()});
+    S->Xmid = upload_csr(c, hp.Xmid, {hp.XM.data(), hp.XA.data()});
+    std::vector<double> F(hp.Kff.nnz());
+    for (int t = 0; t < hp.Kff.nnz(); ++t) F[t] = hp.Mff[t] / S->tau + S->nu0 * hp.Aff[t];
+    BlockTri bt;
+    std::string err;
+    blocktri_factor(hp.Kff, F.data(), hp.vel_blocks, bt, err);
+    if (!err.empty()) throw SgttError(-6, err);
+    S->Fbt = upload_bt(c, bt);
+    // f^u: core1 [(I-C)a/tau | a], core2 [e1 ; G_nu e1], core3 -[M_fa g | A_fa g]
+    std::vector<double> Ca(nt), c1((size_t)nt * 2), c2((size_t)2 * nxi * 2, 0.0);
+    for (int k = 0; k < nt; ++k) {
+      c1[(size_t)k * 2 + 0] = (hp.ramp[k] - (k > 0 ? hp.ramp[k - 1] : 0.0)) / S->tau;
+      c1[(size_t)k * 2 + 1] = hp.ramp[k];
     }
-    HostProblem& hp = S->hp;
-    S->nt = hp.nt;
-    S->nxi = hp.n_xi;
-    S->ns = hp.n_s;
-    S->nu = hp.n_u;
-    S->np = hp.n_p;
-    S->nall = hp.n_all;
-    S->tau = prm.tau;
-    S->nu0 = prm.nu0;
-    SGTT_HIP(hipMalloc(&S->dsc, 32768 * sizeof(double)));
-    S->Gnu = dev_upload(c, hp.Gnu);
-    S->Bd = upload_csr(c, hp.B, {hp.B.val.data()});
-    S->Btd = upload_csr(c, hp.Bt, {hp.Bt.val.data()});
-    {
-      BlockTri bt;
-      std::string err;
-      blocktri_factor(hp.Xp, hp.Xp.val.data(), hp.p_blocks, bt, err);
-      if (!err.empty()) throw SgttError(-6, err);
-      S->Xbt = upload_bt(c, bt);
+    for (int i = 0; i < nxi; ++i) {
+      c2[((size_t)0 * nxi + i) * 2 + 0] = e1[i];
+      c2[((size_t)1 * nxi + i) * 2 + 1] = hp.Gnu[(size_t)i * nxi + 0];
     }
-    const int nt = S->nt, nxi = S->nxi, nall = S->nall, ns = S->ns;
-    // Dirichlet lift TT over all nodes: ramp (x) e_1 (x) g_all
-    std::vector<double> e1(nxi, 0.0);
-    e1[0] = 1.0;
-    TT lift = tt_new(c, nt, nxi, 2 * nall, 1, 1);
-    SGTT_HIP(hipMemcpyAsync(lift.c1, hp.ramp.data(), nt * 8, hipMemcpyHostToDevice, c.s));
-    SGTT_HIP(hipMemcpyAsync(lift.c2, e1.data(), nxi * 8, hipMemcpyHostToDevice, c.s));
-    SGTT_HIP(hipMemcpyAsync(lift.c3, hp.g_all.data(), 2 * nall * 8, hipMemcpyHostToDevice, c.s));
+    std::vector<double> c3((size_t)2 * ns * 2, 0.0), pc3(hp.n_p, 0.0);
+    for (int comp = 0; comp < 2; ++comp)
+      for (int i = 0; i < ns; ++i) {
+        double sm = 0, sa = 0;
+        for (int t = hp.Kfa.rowptr[i]; t < hp.Kfa.rowptr[i + 1]; ++t) {
+          double g = hp.g_all[(size_t)comp * nall + hp.Kfa.col[t]];
+          sm += hp.Mfa[t] * g;
+          sa += hp.Afa[t] * g;
+        }
+        c3[((size_t)comp * ns + i) * 2 + 0] = -sm;
+        c3[((size_t)comp * ns + i) * 2 + 1] = -sa;
+      }
+    for (int k = 0; k < hp.n_p; ++k) {
+      double s = 0;
+      for (int t = hp.Ball.rowptr[k]; t < hp.Ball.rowptr[k + 1]; ++t) s += hp.Ball.val[t] * hp.g_all[hp.Ball.col[t]];
+      pc3[k] = -s;
+    }
+    S->bu = tt_new(c, nt, nxi, hp.n_u, 2, 2);
+    SGTT_HIP(hipMemcpyAsync(S->bu.c1, c1.data(), c1.size() * 8, hipMemcpyHostToDevice, c.s));
+    SGTT_HIP(hipMemcpyAsync(S->bu.c2, c2.data(), c2.size() * 8, hipMemcpyHostToDevice, c.s));
+    SGTT_HIP(hipMemcpyAsync(S->bu.c3, c3.data(), c3.size() * 8, hipMemcpyHostToDevice, c.s));
+    S->bp = tt_new(c, nt, nxi, hp.n_p, 1, 1);
+    SGTT_HIP(hipMemcpyAsync(S->bp.c1, hp.ramp.data(), nt * 8, hipMemcpyHostToDevice, c.s));
+    SGTT_HIP(hipMemcpyAsync(S->bp.c2, e1.data(), nxi * 8, hipMemcpyHostToDevice, c.s));
+    SGTT_HIP(hipMemcpyAsync(S->bp.c3, pc3.data(), hp.n_p * 8, hipMemcpyHostToDevice, c.s));
+    tt_dot(c, S->bu, S->bu, S->dsc + 30010, 0);
+    tt_dot(c, S->bp, S->bp, S->dsc + 30010, 1);
+    SGTT_HIP(hipMemcpyAsync(c.hdbl, S->dsc + 30010, sizeof(double), hipMemcpyDeviceToHost, c.s));
     c.sync();
-    if (!prior) {
-      // Stokes system: no convection; f = -L_{free,all}(0) lift (ranks 2 and 1)
-      S->k1 = S->k2 = 0;
-      S->Kop = upload_csr(c, hp.Kff, {hp.Mff.data(), hp.Aff.data()});
-      S->Xmid = upload_csr(c, hp.Xmid, {hp.XM.data(), hp.XA.data()});
-      std::vector<double> F(hp.Kff.nnz());
-      for (int t = 0; t < hp.Kff.nnz(); ++t) F[t] = hp.Mff[t] / S->tau + S->nu0 * hp.Aff[t];
-      BlockTri bt;
-      std::string err;
-      blocktri_factor(hp.Kff, F.data(), hp.vel_blocks, bt, err);
-      if (!err.empty()) throw SgttError(-6, err);
-      S->Fbt = upload_bt(c, bt);
-      // f^u: core1 [(I-C)a/tau | a], core2 [e1 ; G_nu e1], core3 -[M_fa g | A_fa g]
-      std::vector<double> Ca(nt), c1((size_t)nt * 2), c2((size_t)2 * nxi * 2, 0.0);
-      for (int k = 0; k < nt; ++k) {
-        c1[(size_t)k * 2 + 0] = (hp.ramp[k] - (k > 0 ? hp.ramp[k - 1] : 0.0)) / S->tau;
-        c1[(size_t)k * 2 + 1] = hp.ramp[k];
-      }
-      for (int i = 0; i < nxi; ++i) {
-        c2[((size_t)0 * nxi + i) * 2 + 0] = e1[i];
-        c2[((size_t)1 * nxi + i) * 2 + 1] = hp.Gnu[(size_t)i * nxi + 0];
-      }
-      std::vector<double> c3((size_t)2 * ns * 2, 0.0), pc3(hp.n_p, 0.0);
+    S->rhs_norm = std::sqrt(std::max(c.hdbl[0], 0.0));
+  } else {
+    check_tt(prior->u, nt, nxi, hp.n_u);
+    check_tt(prior->p, nt, nxi, hp.n_p);
+    // wind over all nodes: embed free velocity, then add the lift
+    const sgtt_tt& pu = prior->u;
+    TT wemb = tt_new(c, nt, nxi, 2 * nall, pu.r1, pu.r2);
+    SGTT_HIP(hipMemcpyAsync(wemb.c1, pu.core1, sizeof(double) * pu.n1 * pu.r1, hipMemcpyDeviceToDevice, c.s));
+    SGTT_HIP(hipMemcpyAsync(wemb.c2, pu.core2, sizeof(double) * pu.r1 * pu.n2 * pu.r2, hipMemcpyDeviceToDevice, c.s));
+    {
+      std::vector<double> hu((size_t)hp.n_u * pu.r2), ha((size_t)2 * nall * pu.r2, 0.0);
+      SGTT_HIP(hipMemcpyAsync(hu.data(), pu.core3, hu.size() * 8, hipMemcpyDeviceToHost, c.s));
+      c.sync();
       for (int comp = 0; comp < 2; ++comp)
         for (int i = 0; i < ns; ++i) {
-          double sm = 0, sa = 0;
-          for (int t = hp.Kfa.rowptr[i]; t < hp.Kfa.rowptr[i + 1]; ++t) {
-            double g = hp.g_all[(size_t)comp * nall + hp.Kfa.col[t]];
-            sm += hp.Mfa[t] * g;
-            sa += hp.Afa[t] * g;
-          }
-          c3[((size_t)comp * ns + i) * 2 + 0] = -sm;
-          c3[((size_t)comp * ns + i) * 2 + 1] = -sa;
+          int node = hp.mesh.free_nodes[i];
+          std::memcpy(&ha[((size_t)comp * nall + node) * pu.r2], &hu[((size_t)comp * ns + i) * pu.r2],
+                      sizeof(double) * pu.r2);
         }
-      for (int k = 0; k < hp.n_p; ++k) {
-        double s = 0;
-        for (int t = hp.Ball.rowptr[k]; t < hp.Ball.rowptr[k + 1]; ++t) s += hp.Ball.val[t] * hp.g_all[hp.Ball.col[t]];
-        pc3[k] = -s;
-      }
-      S->bu = tt_new(c, nt, nxi, hp.n_u, 2, 2);
-      SGTT_HIP(hipMemcpyAsync(S->bu.c1, c1.data(), c1.size() * 8, hipMemcpyHostToDevice, c.s));
-      SGTT_HIP(hipMemcpyAsync(S->bu.c2, c2.data(), c2.size() * 8, hipMemcpyHostToDevice, c.s));
-      SGTT_HIP(hipMemcpyAsync(S->bu.c3, c3.data(), c3.size() * 8, hipMemcpyHostToDevice, c.s));
-      S->bp = tt_new(c, nt, nxi, hp.n_p, 1, 1);
-      SGTT_HIP(hipMemcpyAsync(S->bp.c1, hp.ramp.data(), nt * 8, hipMemcpyHostToDevice, c.s));
-      SGTT_HIP(hipMemcpyAsync(S->bp.c2, e1.data(), nxi * 8, hipMemcpyHostToDevice, c.s));
-      SGTT_HIP(hipMemcpyAsync(S->bp.c3, pc3.data(), hp.n_p * 8, hipMemcpyHostToDevice, c.s));
+      SGTT_HIP(hipMemcpyAsync(wemb.c3, ha.data(), ha.size() * 8, hipMemcpyHostToDevice, c.s));
       c.sync();
-    } else {
-      check_tt(prior->u, nt, nxi, hp.n_u);
-      check_tt(prior->p, nt, nxi, hp.n_p);
-      // wind over all nodes: embed free velocity, then add the lift
-      const sgtt_tt& pu = prior->u;
-      TT wemb = tt_new(c, nt, nxi, 2 * nall, pu.r1, pu.r2);
-      SGTT_HIP(hipMemcpyAsync(wemb.c1, pu.core1, sizeof(double) * pu.n1 * pu.r1, hipMemcpyDeviceToDevice, c.s));
-      SGTT_HIP(hipMemcpyAsync(wemb.c2, pu.core2, sizeof(double) * pu.r1 * pu.n2 * pu.r2, hipMemcpyDeviceToDevice, c.s));
-      {
-        std::vector<double> hu((size_t)hp.n_u * pu.r2), ha((size_t)2 * nall * pu.r2, 0.0);
-        SGTT_HIP(hipMemcpyAsync(hu.data(), pu.core3, hu.size() * 8, hipMemcpyDeviceToHost, c.s));
-        c.sync();
-        for (int comp = 0; comp < 2; ++comp)
-          for (int i = 0; i < ns; ++i) {
-            int node = hp.mesh.free_nodes[i];
-            std::memcpy(&ha[((size_t)comp * nall + node) * pu.r2], &hu[((size_t)comp * ns + i) * pu.r2],
-                        sizeof(double) * pu.r2);
-          }
-        SGTT_HIP(hipMemcpyAsync(wemb.c3, ha.data(), ha.size() * 8, hipMemcpyHostToDevice, c.s));
-        c.sync();
-      }
-      TT wall = tt_concat(c, {&wemb, &lift}, nullptr, {});
-      TT wtil = tt_round(c, wall, desc->eps_conv, nullptr, nullptr);
-      build_convection(*S, c, wtil);
-      // right-hand side r = -(L_{free,all}(w) w_all + B^T p) with the
-      // untruncated wind (eq. 3.15): build a temporary system view whose
-      // convection is N(w_all) on the free x all pattern
-      {
-        const int K1 = wall.r1, K2 = wall.r2;
-        std::vector<double> h1((size_t)nt * K1), h2((size_t)K1 * nxi * K2), h3((size_t)2 * nall * K2);
-        SGTT_HIP(hipMemcpyAsync(h1.data(), wall.c1, h1.size() * 8, hipMemcpyDeviceToHost, c.s));
-        SGTT_HIP(hipMemcpyAsync(h2.data(), wall.c2, h2.size() * 8, hipMemcpyDeviceToHost, c.s));
-        SGTT_HIP(hipMemcpyAsync(h3.data(), wall.c3, h3.size() * 8, hipMemcpyDeviceToHost, c.s));
-        c.sync();
-        const int nnzfa = hp.Kfa.nnz();
-        std::vector<std::vector<double>> Nfa(K2, std::vector<double>(nnzfa));
-        std::vector<double> ff(hp.Kff.nnz()), w1(nall), w2(nall);
-        for (int b = 0; b < K2; ++b) {
-          for (int i = 0; i < nall; ++i) {
-            w1[i] = h3[(size_t)i * K2 + b];
-            w2[i] = h3[(size_t)(nall + i) * K2 + b];
-          }
-          convection_values(hp, w1.data(), w2.data(), ff.data(), Nfa[b].data());
-        }
-        std::vector<double> Hw((size_t)K1 * K2 * nxi * nxi, 0.0);
-        for (int a = 0; a < K1; ++a)
-          for (int b = 0; b < K2; ++b)
-            for (int l = 0; l < nxi; ++l) {
-              double wv = h2[((size_t)a * nxi + l) * K2 + b];
-              if (wv == 0.0) continue;
-              const double* Hl = hp.H.data() + (size_t)l * nxi * nxi;
-              double* dst = Hw.data() + ((size_t)a * K2 + b) * nxi * nxi;
-              for (int q = 0; q < nxi * nxi; ++q) dst[q] += wv * Hl[q];
-            }
-        std::vector<const double*> vs{hp.Mfa.data(), hp.Afa.data()};
-        for (int b = 0; b < K2; ++b) vs.push_back(Nfa[b].data());
-        DevCsr Kfa = upload_csr(c, hp.Kfa, vs);
-        DevCsr Ball = upload_csr(c, hp.Ball, {hp.Ball.val.data()});
-        double* dw1 = dev_upload(c, h1);
-        double* dHw = dev_upload(c, Hw);
-        const TT& w = wall;
-        TT pview = tt_view(prior->p.n1, prior->p.n2, prior->p.n3, prior->p.r1, prior->p.r2, prior->p.core1,
-                           prior->p.core2, prior->p.core3);
-        const TT& p = pview;
-        const int r1u = w.r1, r2u = w.r2, r1p = p.r1, r2p = p.r2;
-        const int R1 = 2 * r1u + K1 * r1u + r1p, R2 = 2 * r2u + K2 * r2u + r2p;
-        TT ru = tt_new(c, nt, nxi, hp.n_u, R1, R2);
-        core1_op(c.s, 0, nt, r1u, w.c1, r1u, ru.c1, R1, 0, 1.0 / S->tau);
-        core1_op(c.s, 1, nt, r1u, w.c1, r1u, ru.c1, R1, r1u, 1.0);
-        core1_diag(c.s, nt, r1u, K1, dw1, K1, w.c1, r1u, ru.c1, R1, 2 * r1u);
-        core1_op(c.s, 1, nt, r1p, p.c1, r1p, ru.c1, R1, 2 * r1u + K1 * r1u, 1.0);
-        copy2d(c.s, nt, R1, ru.c1, R1, ru.c1, R1, -1.0, nullptr, 0);   // r = -(...)
-        fill(c.s, ru.c2, ru.n_c2(), 0.0);
-        core2_block(c.s, r1u, nxi, r2u, w.c2, nullptr, 1, 1, ru.c2, R1, R2, 0, 0);
-        core2_block(c.s, r1u, nxi, r2u, w.c2, S->Gnu, 1, 1, ru.c2, R1, R2, r1u, r2u);
-        core2_block(c.s, r1u, nxi, r2u, w.c2, dHw, K1, K2, ru.c2, R1, R2, 2 * r1u, 2 * r2u);
-        core2_block(c.s, r1p, nxi, r2p, p.c2, nullptr, 1, 1, ru.c2, R1, R2, 2 * r1u + K1 * r1u, 2 * r2u + K2 * r2u);
-        spmm(c.s, ns, 2, nall, ns, Kfa.rowptr, Kfa.col, Kfa.vals, 2 + K2, Kfa.nnz, w.c3, r2u, 0, r2u, ru.c3, R2, 0,
-             r2u, 1.0);
-        spmm(c.s, hp.n_u, 1, 0, 0, S->Btd.rowptr, S->Btd.col, S->Btd.vals, 1, 0, p.c3, r2p, 0, r2p, ru.c3, R2,
-             2 * r2u + K2 * r2u, 0, 1.0);
-        TT rp = tt_new(c, nt, nxi, hp.n_p, r1u, r2u);
-        copy2d(c.s, nt, r1u, w.c1, r1u, rp.c1, r1u, -1.0, nullptr, 0);
-        SGTT_HIP(hipMemcpyAsync(rp.c2, w.c2, sizeof(double) * w.n_c2(), hipMemcpyDeviceToDevice, c.s));
-        spmm(c.s, hp.n_p, 1, 0, 0, Ball.rowptr, Ball.col, Ball.vals, 1, 0, w.c3, r2u, 0, r2u, rp.c3, r2u, 0, 0, 1.0);
-        // TT-SVD of the full residual (Alg. 4.1)
-        for (int i = 0; i < 2; ++i) {
-          const TT& ri = i == 0 ? ru : rp;
-          long n = (long)ri.n1 * ri.n2 * ri.n3;
-          double* full = c.pool.get(n);
-          tt_expand(c, ri, full);
-          TT t = tt_from_full(c, full, ri.n1, ri.n2, ri.n3, desc->eps_rhs, nullptr);
-          c.pool.put(full);
-          if (i == 0) S->bu = std::move(t);
-          else S->bp = std::move(t);
-        }
-        c.sync();
-        Kfa.free_all();
-        Ball.free_all();
-        (void)hipFree(dw1);
-        (void)hipFree(dHw);
-      }
     }
-    c.sync();
-    S->setup_s = now_s() - t0;
-    *out = S.release();
-  });
+    TT wall = tt_concat(c, {&wemb, &lift}, nullptr, {});
+    TT wtil = tt_round(c, wall, desc->eps_conv, nullptr, nullptr);
+    build_convection(*S, c, wtil);
+    // right-hand side r = -(L_{free,all}(w) w_all + B^T p) with the
+    // untruncated wind (eq. 3.15, sec. 4.3): the linear terms as an exact
+    // TT, expanded to full format, minus the stochastic Galerkin
+    // convection N(w_all) w_all evaluated in full format element by
+    // element (its TT ranks would be the squares of the iterate's)
+    {
+      if (nxi > 64) throw SgttError(-1, "Picard residual: n_xi > 64 not supported");
+      DevCsr Kfa = upload_csr(c, hp.Kfa, {hp.Mfa.data(), hp.Afa.data()});
+      DevCsr Ball = upload_csr(c, hp.Ball, {hp.Ball.val.data()});
+      const TT& w = wall;
+      TT pview = tt_view(prior->p.n1, prior->p.n2, prior->p.n3, prior->p.r1, prior->p.r2, prior->p.core1,
+                         prior->p.core2, prior->p.core3);
+      TT uview = tt_view(pu.n1, pu.n2, pu.n3, pu.r1, pu.r2, pu.core1, pu.core2, pu.core3);
+      const TT& p = pview;
+      const int r1u = w.r1, r2u = w.r2, r1p = p.r1, r2p = p.r2;
+      const int R1 = 2 * r1u + r1p, R2 = 2 * r2u + r2p;
+      TT ru = tt_new(c, nt, nxi, hp.n_u, R1, R2);
+      core1_op(c.s, 0, nt, r1u, w.c1, r1u, ru.c1, R1, 0, 1.0 / S->tau);
+      core1_op(c.s, 1, nt, r1u, w.c1, r1u, ru.c1, R1, r1u, 1.0);
+      core1_op(c.s, 1, nt, r1p, p.c1, r1p, ru.c1, R1, 2 * r1u, 1.0);
+      copy2d(c.s, nt, R1, ru.c1, R1, ru.c1, R1, -1.0, nullptr, 0);   // r = -(...)
+      fill(c.s, ru.c2, ru.n_c2(), 0.0);
+      core2_block(c.s, r1u, nxi, r2u, w.c2, nullptr, 1, 1, ru.c2, R1, R2, 0, 0);
+      core2_block(c.s, r1u, nxi, r2u, w.c2, S->Gnu, 1, 1, ru.c2, R1, R2, r1u, r2u);
+      core2_block(c.s, r1p, nxi, r2p, p.c2, nullptr, 1, 1, ru.c2, R1, R2, 2 * r1u, 2 * r2u);
+      spmm(c.s, ns, 2, nall, ns, Kfa.rowptr, Kfa.col, Kfa.vals, 2, Kfa.nnz, w.c3, r2u, 0, r2u, ru.c3, R2, 0, r2u,
+           1.0);
+      spmm(c.s, hp.n_u, 1, 0, 0, S->Btd.rowptr, S->Btd.col, S->Btd.vals, 1, 0, p.c3, r2p, 0, r2p, ru.c3, R2,
+           2 * r2u, 0, 1.0);
+      TT rp = tt_new(c, nt, nxi, hp.n_p, r1u, r2u);
+      copy2d(c.s, nt, r1u, w.c1, r1u, rp.c1, r1u, -1.0, nullptr, 0);
+      SGTT_HIP(hipMemcpyAsync(rp.c2, w.c2, sizeof(double) * w.n_c2(), hipMemcpyDeviceToDevice, c.s));
+      spmm(c.s, hp.n_p, 1, 0, 0, Ball.rowptr, Ball.col, Ball.vals, 1, 0, w.c3, r2u, 0, r2u, rp.c3, r2u, 0, 0, 1.0);
+      // device copies of the mesh, lift and chaos triple products
+      std::vector<int> conn9((size_t)hp.mesh.conn.size() * 9);
+      for (size_t e = 0; e < hp.mesh.conn.size(); ++e)
+        for (int a = 0; a < 9; ++a) conn9[e * 9 + a] = hp.mesh.conn[e][a];
+      std::vector<int> hrow(nxi + 1, 0), hl, hk;
+      std::vector<double> hv;
+      for (int i = 0; i < nxi; ++i) {
+        for (int l = 0; l < nxi; ++l)
+          for (int k = 0; k < nxi; ++k) {
+            double v = hp.H[((size_t)l * nxi + i) * nxi + k];
+            if (v == 0.0) continue;
+            hl.push_back(l);
+            hk.push_back(k);
+            hv.push_back(v);
+          }
+        hrow[i + 1] = (int)hv.size();
+      }
+      std::vector<double> reft(252);
+      reference_tables(reft.data());
+      int* d_conn = dev_upload(c, conn9);
+      int* d_fid = dev_upload(c, hp.mesh.free_id);
+      int* d_hrow = dev_upload(c, hrow);
+      int* d_hl = dev_upload(c, hl);
+      int* d_hk = dev_upload(c, hk);
+      double* d_hv = dev_upload(c, hv);
+      double* d_ref = dev_upload(c, reft);
+      double* d_ramp = dev_upload(c, hp.ramp);
+      double* d_gall = dev_upload(c, hp.g_all);
+      const long nu_full = (long)nt * nxi * hp.n_u;
+      double* R = c.pool.get(nu_full);
+      double* U = c.pool.get(nu_full);
+      tt_expand(c, ru, R);
+      tt_expand(c, uview, U);
+      sg_convection_full(c.s, nt, nxi, hp.n_u, ns, nall, (int)hp.mesh.conn.size(), d_conn, d_fid, U, d_ramp, d_gall,
+                         d_hrow, d_hl, d_hk, d_hv, d_ref, 0.5 * hp.prm.h, -1.0, R);
+      c.pool.put(U);
+      // ||r||^2 of the untruncated nonlinear residual (Alg. 3.1, line 7)
+      double* ws = c.scratch(1 << 16);
+      double* sq = S->dsc + 30010;
+      sumsq(c.s, R, nu_full, sq, ws, 1 << 16);
+      S->bu = tt_from_full(c, R, nt, nxi, hp.n_u, desc->eps_rhs, nullptr);
+      c.pool.put(R);
+      const long np_full = (long)nt * nxi * hp.n_p;
+      double* Rp = c.pool.get(np_full);
+      tt_expand(c, rp, Rp);
+      sumsq(c.s, Rp, np_full, sq + 1, ws, 1 << 16);
+      S->bp = tt_from_full(c, Rp, nt, nxi, hp.n_p, desc->eps_rhs, nullptr);
+      c.pool.put(Rp);
+      SGTT_HIP(hipMemcpyAsync(c.hdbl, sq, 2 * sizeof(double), hipMemcpyDeviceToHost, c.s));
+      c.sync();
+      S->rhs_norm = std::sqrt(c.hdbl[0] + c.hdbl[1]);
+      Kfa.free_all();
+      Ball.free_all();
+      for (void* q : {(void*)d_conn, (void*)d_fid, (void*)d_hrow, (void*)d_hl, (void*)d_hk, (void*)d_hv,
+                      (void*)d_ref, (void*)d_ramp, (void*)d_gall})
+        (void)hipFree(q);
+    }
+  }
+  c.sync();
+  S->setup_s = now_s() - t0;
+  return S.release();
+}
+
+int sgtt_assemble(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_tt_pair* prior, sgtt_system** out) {
+  if (!ctx || !desc || !out) return SGTT_E_INVALID;
+  return guarded(ctx, [&]() { *out = assemble_internal(ctx, desc, prior); });
 }
 
 int sgtt_system_destroy(sgtt_system* sys) {
@@ -1009,6 +1029,7 @@ int sgtt_system_info_get(const sgtt_system* S, sgtt_system_info* info) {
   info->rhs_r1p = S->bp.r1;
   info->rhs_r2p = S->bp.r2;
   info->setup_seconds = S->setup_s;
+  info->rhs_norm = S->rhs_norm;
   return SGTT_OK;
 }
 
@@ -1139,6 +1160,66 @@ int sgtt_residual_tensor(sgtt_system* S, const sgtt_tt_pair* b, const sgtt_tt_pa
   });
 }
 
+// Refinement cycles of Alg. 4.2 until the exact relative residual is <= tol
+// (throws SgttError).  Returns SGTT_OK or SGTT_W_NOT_CONVERGED; z is the
+// exact sum of the cycle corrections.
+int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec& z, sgtt_solve_stats* stats) {
+  Ctx& c = S->ctx->c;
+  if (o.restart < 1 || o.restart > 60 || o.max_cycles < 1 || o.inner_maxit < 1 || o.inner_maxit > 60)
+    throw SgttError(-1, "invalid solve options");
+  double t0 = now_s();
+  long r0 = c.roundings;
+  SolveCounters cnt;
+  cnt.verbose = o.verbose;
+  OuterSpace sp(*S, prec_opts(&o), &cnt);
+  std::vector<Vec> terms;
+  Vec r = vec_copy(c, bv);
+  double bn2 = -1.0, rel = 1.0;
+  int cycles = 0;
+  for (int cyc = 0; cyc < o.max_cycles; ++cyc) {
+    int its = 0;
+    double rr = 0;
+    Vec d = lowrank_fgmres(c, sp, r, o.tol_cycle, o.eps_krylov, o.restart, S->dsc, its, rr, &cnt, "outer",
+                           o.outer_explicit != 0, o.relax != 0);
+    cnt.outer += its;
+    ++cycles;
+    terms.push_back(std::move(d));
+    std::vector<const Vec*> parts;
+    for (auto& t : terms) parts.push_back(&t);
+    z = vec_concat(c, parts, nullptr, {});
+    Vec rnext;
+    // the correction equation L d = r_j only has to be solved to relative
+    // accuracy tol ||b|| / ||r_j||, so its right-hand side is compressed
+    // to a fraction of that (never finer than eps_krylov)
+    double eps_r = o.eps_krylov;
+    rel = full_residual(*S, bv, z, nullptr, nullptr, 0.0, &bn2);
+    if (rel > o.tol && cyc + 1 < o.max_cycles) {
+      eps_r = std::max(o.eps_krylov, std::min(1e-3, 0.05 * o.tol / std::max(rel, 1e-300)));
+      full_residual(*S, bv, z, nullptr, &rnext, eps_r, &bn2);
+    }
+    if (o.verbose) fprintf(stderr, "[sgtt] cycle %d: outer its %d, exact rel residual %.3e\n", cyc, its, rel);
+    if (!std::isfinite(rel)) throw SgttError(-5, "non-finite residual");
+    if (rel <= o.tol) break;
+    if (o.verbose) fprintf(stderr, "[sgtt] next right-hand side truncated at %.2e\n", eps_r);
+    r = std::move(rnext);
+  }
+  if (stats) {
+    stats->cycles = cycles;
+    stats->outer_iters = cnt.outer;
+    stats->inner_iters = cnt.inner;
+    stats->rel_residual = rel;
+    stats->seconds = now_s() - t0;
+    stats->max_rank_krylov_u = cnt.maxr_u;
+    stats->max_rank_krylov_p = cnt.maxr_p;
+    stats->roundings = (int)(c.roundings - r0);
+    stats->t_apply = cnt.t_apply;
+    stats->t_round = 0;
+    stats->t_precond = cnt.t_prec;
+    stats->t_residual = 0;
+  }
+  return rel > o.tol ? SGTT_W_NOT_CONVERGED : SGTT_OK;
+}
+
 int sgtt_solve(sgtt_system* S, const sgtt_tt_pair* b, sgtt_tt_pair* x, const sgtt_solve_opts* opts,
                sgtt_solve_stats* stats) {
   if (!S || !b || !x) return SGTT_E_INVALID;
@@ -1147,67 +1228,101 @@ int sgtt_solve(sgtt_system* S, const sgtt_tt_pair* b, sgtt_tt_pair* x, const sgt
   try {
     check_tt(b->u, S->nt, S->nxi, S->nu);
     check_tt(b->p, S->nt, S->nxi, S->np);
-    Ctx& c = ctx->c;
     sgtt_solve_opts o = opts ? *opts : default_opts();
-    if (o.restart < 1 || o.restart > 60 || o.max_cycles < 1 || o.inner_maxit < 1 || o.inner_maxit > 60)
-      throw SgttError(-1, "invalid solve options");
-    double t0 = now_s();
-    long r0 = c.roundings;
-    SolveCounters cnt;
-    cnt.verbose = o.verbose;
-    OuterSpace sp(*S, prec_opts(&o), &cnt);
-    Vec bv = vec_from_pair(b);
-    std::vector<Vec> terms;
-    Vec r = vec_copy(c, bv);
-    double bn2 = -1.0, rel = 1.0;
-    int cycles = 0;
     Vec z;
-    for (int cyc = 0; cyc < o.max_cycles; ++cyc) {
-      int its = 0;
-      double rr = 0;
-      Vec d = lowrank_fgmres(c, sp, r, o.tol_cycle, o.eps_krylov, o.restart, S->dsc, its, rr, &cnt, "outer",
-                             o.outer_explicit != 0, o.relax != 0);
-      cnt.outer += its;
-      ++cycles;
-      terms.push_back(std::move(d));
-      std::vector<const Vec*> parts;
-      for (auto& t : terms) parts.push_back(&t);
-      z = vec_concat(c, parts, nullptr, {});
-      Vec rnext;
-      // the correction equation L d = r_j only has to be solved to relative
-      // accuracy tol ||b|| / ||r_j||, so its right-hand side is compressed
-      // to a fraction of that (never finer than eps_krylov)
-      double rel_prev = rel;
-      double eps_r = o.eps_krylov;
-      (void)rel_prev;
-      rel = full_residual(*S, bv, z, nullptr, nullptr, 0.0, &bn2);
-      if (rel > o.tol && cyc + 1 < o.max_cycles) {
-        eps_r = std::max(o.eps_krylov, std::min(1e-3, 0.05 * o.tol / std::max(rel, 1e-300)));
-        full_residual(*S, bv, z, nullptr, &rnext, eps_r, &bn2);
+    status = solve_internal(S, vec_from_pair(b), o, z, stats);
+    write_pair(ctx->c, z, x);
+    ctx->c.sync();
+  } catch (const SgttError& e) {
+    ctx->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return SGTT_E_INVALID;
+  }
+  return status;
+}
+
+// Picard's method (Alg. 3.1) with truncated iterates (eq. 4.8).
+int sgtt_picard(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_picard_opts* opts, sgtt_tt_pair* x,
+                sgtt_picard_stats* stats) {
+  if (!ctx || !desc || !opts || !x) return SGTT_E_INVALID;
+  if (opts->max_steps < 0 || opts->max_steps > SGTT_PICARD_MAX_STEPS) return SGTT_E_INVALID;
+  int status = SGTT_OK;
+  try {
+    Ctx& c = ctx->c;
+    const double t0 = now_s();
+    sgtt_picard_stats st;
+    std::memset(&st, 0, sizeof(st));
+    // line 1: Stokes solve for the initial iterate
+    double ta = now_s();
+    std::unique_ptr<sgtt_system> S(assemble_internal(ctx, desc, nullptr));
+    st.assemble_seconds[0] = now_s() - ta;
+    const double fnorm = S->rhs_norm;
+    auto record = [&](int i, const sgtt_solve_stats& ls, const Vec& it) {
+      st.linear_residual[i] = ls.rel_residual;
+      st.outer_iters[i] = ls.outer_iters;
+      st.inner_iters[i] = ls.inner_iters;
+      st.solve_seconds[i] = ls.seconds;
+      st.rank_u[i][0] = it.c[0].r1;
+      st.rank_u[i][1] = it.c[0].r2;
+      st.rank_p[i][0] = it.c[1].r1;
+      st.rank_p[i][1] = it.c[1].r2;
+    };
+    Vec cur;
+    {
+      Vec b;
+      b.c[0] = tt_view(S->bu.n1, S->bu.n2, S->bu.n3, S->bu.r1, S->bu.r2, S->bu.c1, S->bu.c2, S->bu.c3);
+      b.c[1] = tt_view(S->bp.n1, S->bp.n2, S->bp.n3, S->bp.r1, S->bp.r2, S->bp.c1, S->bp.c2, S->bp.c3);
+      Vec z;
+      sgtt_solve_stats ls{};
+      if (solve_internal(S.get(), b, opts->solve, z, &ls) != SGTT_OK) status = SGTT_W_NOT_CONVERGED;
+      cur = vec_round(c, z, opts->eps_soln, nullptr, nullptr);
+      record(0, ls, cur);
+    }
+    S.reset();
+    int i = 0;
+    for (;;) {
+      // lines 6-7: convection matrix and nonlinear residual of the current iterate
+      sgtt_tt_pair prior;
+      for (int q = 0; q < 2; ++q) {
+        sgtt_tt& t = q == 0 ? prior.u : prior.p;
+        const TT& src = cur.c[q];
+        t.n1 = src.n1;
+        t.n2 = src.n2;
+        t.n3 = src.n3;
+        t.r1 = t.cap1 = src.r1;
+        t.r2 = t.cap2 = src.r2;
+        t.core1 = src.c1;
+        t.core2 = src.c2;
+        t.core3 = src.c3;
       }
-      if (o.verbose) fprintf(stderr, "[sgtt] next right-hand side truncated at %.2e\n", eps_r);
-      if (o.verbose) fprintf(stderr, "[sgtt] cycle %d: outer its %d, exact rel residual %.3e\n", cyc, its, rel);
-      if (!std::isfinite(rel)) throw SgttError(-5, "non-finite residual");
-      if (rel <= o.tol) break;
-      r = std::move(rnext);
+      ta = now_s();
+      S.reset(assemble_internal(ctx, desc, &prior));
+      st.assemble_seconds[i + 1] = now_s() - ta;
+      st.nonlinear_residual[i] = fnorm > 0 ? S->rhs_norm / fnorm : 0.0;
+      if (opts->solve.verbose)
+        fprintf(stderr, "[sgtt picard] step %d: nonlinear residual %.3e, ranks u (%d,%d)\n", i,
+                st.nonlinear_residual[i], cur.c[0].r1, cur.c[0].r2);
+      if (st.nonlinear_residual[i] <= opts->tol_picard || i >= opts->max_steps) break;
+      ++i;
+      // lines 4-5: solve for the update and truncate the new iterate (eq. 4.8)
+      Vec b;
+      b.c[0] = tt_view(S->bu.n1, S->bu.n2, S->bu.n3, S->bu.r1, S->bu.r2, S->bu.c1, S->bu.c2, S->bu.c3);
+      b.c[1] = tt_view(S->bp.n1, S->bp.n2, S->bp.n3, S->bp.r1, S->bp.r2, S->bp.c1, S->bp.c2, S->bp.c3);
+      Vec d;
+      sgtt_solve_stats ls{};
+      if (solve_internal(S.get(), b, opts->solve, d, &ls) != SGTT_OK) status = SGTT_W_NOT_CONVERGED;
+      Vec next = vec_concat(c, {&cur, &d}, nullptr, {});
+      cur = vec_round(c, next, opts->eps_soln, nullptr, nullptr);
+      record(i, ls, cur);
     }
-    write_pair(c, z, x);
+    S.reset();
+    st.steps = i;
+    write_pair(c, cur, x);
     c.sync();
-    if (rel > o.tol) status = SGTT_W_NOT_CONVERGED;
-    if (stats) {
-      stats->cycles = cycles;
-      stats->outer_iters = cnt.outer;
-      stats->inner_iters = cnt.inner;
-      stats->rel_residual = rel;
-      stats->seconds = now_s() - t0;
-      stats->max_rank_krylov_u = cnt.maxr_u;
-      stats->max_rank_krylov_p = cnt.maxr_p;
-      stats->roundings = (int)(c.roundings - r0);
-      stats->t_apply = cnt.t_apply;
-      stats->t_round = 0;
-      stats->t_precond = cnt.t_prec;
-      stats->t_residual = 0;
-    }
+    st.seconds = now_s() - t0;
+    if (stats) *stats = st;
   } catch (const SgttError& e) {
     ctx->err = e.what();
     return e.code;

@@ -46,7 +46,8 @@ class ProblemDesc(C.Structure):
 class SystemInfo(C.Structure):
     _fields_ = [("n_s", C.c_int), ("n_u", C.c_int), ("n_p", C.c_int), ("n_xi", C.c_int), ("nt", C.c_int),
                 ("n_all", C.c_int), ("conv_r1", C.c_int), ("conv_r2", C.c_int), ("rhs_r1u", C.c_int),
-                ("rhs_r2u", C.c_int), ("rhs_r1p", C.c_int), ("rhs_r2p", C.c_int), ("setup_seconds", C.c_double)]
+                ("rhs_r2u", C.c_int), ("rhs_r1p", C.c_int), ("rhs_r2p", C.c_int), ("setup_seconds", C.c_double),
+                ("rhs_norm", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -54,6 +55,31 @@ class SolveOpts(C.Structure):
                 ("restart", C.c_int), ("max_cycles", C.c_int), ("inner_tol", C.c_double),
                 ("inner_eps", C.c_double), ("inner_maxit", C.c_int), ("verbose", C.c_int),
                 ("outer_explicit", C.c_int), ("inner_explicit", C.c_int), ("relax", C.c_int)]
+
+
+PICARD_MAX_STEPS = 16
+
+
+class PicardOpts(C.Structure):
+    _fields_ = [("max_steps", C.c_int), ("tol_picard", C.c_double), ("eps_soln", C.c_double),
+                ("solve", SolveOpts)]
+
+
+class PicardStats(C.Structure):
+    _n = PICARD_MAX_STEPS + 1
+    _fields_ = [("steps", C.c_int), ("nonlinear_residual", C.c_double * _n), ("linear_residual", C.c_double * _n),
+                ("outer_iters", C.c_int * _n), ("inner_iters", C.c_int * _n), ("solve_seconds", C.c_double * _n),
+                ("assemble_seconds", C.c_double * (_n + 1)), ("rank_u", (C.c_int * 2) * _n),
+                ("rank_p", (C.c_int * 2) * _n), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        n = self.steps + 1
+        return {"steps": self.steps, "nonlinear_residual": list(self.nonlinear_residual[:n]),
+                "linear_residual": list(self.linear_residual[:n]), "outer_iters": list(self.outer_iters[:n]),
+                "inner_iters": list(self.inner_iters[:n]), "solve_seconds": list(self.solve_seconds[:n]),
+                "assemble_seconds": list(self.assemble_seconds[:n + 1]),
+                "rank_u": [tuple(r) for r in self.rank_u[:n]], "rank_p": [tuple(r) for r in self.rank_p[:n]],
+                "seconds": self.seconds}
 
 
 class SolveStats(C.Structure):
@@ -91,6 +117,8 @@ _sig = {
     "sgtt_profile_read": (C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), C.POINTER(C.c_long), C.POINTER(C.c_int)]),
     "sgtt_profile_class_name": (C.c_char_p, [C.c_int]),
+    "sgtt_picard": (C.c_int, [_P, C.POINTER(ProblemDesc), C.POINTER(PicardOpts), C.POINTER(SgttPair),
+                              C.POINTER(PicardStats)]),
     "sgtt_residual_tensor": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), _P, _P,
                                        C.POINTER(C.c_double)]),
     "sgtt_profile_read_regions": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
@@ -408,6 +436,21 @@ class System:
         if getattr(self, "_s", None) and _lib is not None:
             _lib.sgtt_system_destroy(self._s)
             self._s = None
+
+
+def picard(ctx: Context, cfg: dict, steps: int = 5, tol_picard: float = 1e-5, eps_soln: float = 1e-10,
+           eps_conv: float = 1e-3, eps_rhs: float = 1e-6, out: PairBuf | None = None, caps=(128, 2048), **solve_opts):
+    """Picard's method (Alg. 3.1, eq. 4.8) on the device: returns (iterate, stats dict, status)."""
+    d = make_desc(cfg, eps_conv, eps_rhs)
+    o = PicardOpts(int(steps), float(tol_picard), float(eps_soln), make_opts(**solve_opts))
+    if out is None:
+        hp = HostProblem(cfg)
+        out = PairBuf(hp.nt, hp.n_xi, hp.n_u, hp.n_p, caps[0], caps[1], device=f"cuda:{ctx.device}")
+    st = PicardStats()
+    so = out.struct()
+    rc = ctx.check(_lib.sgtt_picard(ctx._c, C.byref(d), C.byref(o), C.byref(so), C.byref(st)))
+    out.update(so)
+    return out, st.as_dict(), rc
 
 
 def version() -> str:

@@ -256,3 +256,12 @@ def test_residual_entries_match_full_residual():
         t, i, j = g.integers(0, P.nt, 60), g.integers(0, P.n_xi, 60), g.integers(0, n, 60)
         e = P.residual_entries(b, x, which, t, i, j)
         assert np.abs(e - full[t, i, j]).max() <= 1e-13 * np.abs(full).max()
+
+
+def test_picard_direct_contracts(tiny):
+    # Picard's method (Alg. 3.1) at Reynolds ~100 converges linearly: the
+    # nonlinear residual drops by a steady factor at every step
+    from oracle.solver import picard_direct
+    its, res = picard_direct(tiny, 3)
+    assert len(its) == 4 and len(res) == 4
+    assert all(res[i + 1] < 0.2 * res[i] for i in range(3))
