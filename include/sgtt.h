@@ -106,6 +106,12 @@ typedef struct {
   int relax;           /* 0: fixed eps_krylov (Alg. 4.2); 1: truncate the
                           k-th Krylov vectors with eps_krylov ||b||/||r_k-1||
                           (capped at 1e-2), an inexact-Krylov relaxation    */
+  int precision;       /* dense products of the inner mean-matrix solve
+                          (eq. 5.22-5.23): 0 FP64; 1 FP32 and 2 BF16 operands
+                          on the matrix cores with FP32 accumulation.  The
+                          outer iteration, truncation eigen-solves, Hessenberg
+                          least squares and the exact residual stay FP64, so
+                          the refinement still reaches tol                   */
 } sgtt_solve_opts;
 
 typedef struct {

@@ -11,7 +11,9 @@ namespace sgtt {
 // Optional per-launch timing with HIP events on the launch stream, with the
 // algorithmic bytes / flops of each launch (what the operation must move and
 // compute, not what the hardware counted).  Kernel classes:
-enum KernelClass { KC_GEMM = 0, KC_GEMM_PTR, KC_SPMM, KC_BT_DIAG, KC_BT_SWEEP, KC_TRUNC, KC_REDUCE, KC_OTHER, KC_COUNT };
+enum KernelClass {
+  KC_GEMM = 0, KC_GEMM_PTR, KC_SPMM, KC_BT_DIAG, KC_BT_SWEEP, KC_TRUNC, KC_REDUCE, KC_OTHER, KC_GEMM_LOWP, KC_COUNT
+};
 const char* kernel_class_name(int cls);
 void prof_enable(bool on);
 bool prof_enabled();
@@ -32,6 +34,18 @@ struct RegionScope {
   int old;
   explicit RegionScope(int r) : old(prof_region(r)) {}
   ~RegionScope() { prof_region(old); }
+};
+
+// Arithmetic of the dense products (gemm, gemm_batched, gram): FP64 matrix
+// cores, or FP32 / BF16 operands on the matrix cores with FP32 accumulation
+// (operands and results stay FP64 in memory).  gemm_precision sets the mode
+// for later launches and returns the previous one.
+enum GemmPrecision { GP_F64 = 0, GP_F32 = 1, GP_BF16 = 2 };
+int gemm_precision(int p);
+struct GemmPrecisionScope {
+  int old;
+  explicit GemmPrecisionScope(int p) : old(gemm_precision(p)) {}
+  ~GemmPrecisionScope() { gemm_precision(old); }
 };
 
 // C[b](i,j) = alpha * sum_k A[b](i,k) B[b](k,j) + beta * C[b](i,j)

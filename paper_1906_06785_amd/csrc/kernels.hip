@@ -6,6 +6,7 @@
 #include <climits>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 #include <unordered_map>
 #include <utility>
@@ -62,7 +63,7 @@ struct ProfScope {
 
 const char* kernel_class_name(int cls) {
   static const char* names[] = {"k_gemm", "k_gemm_ptr", "k_spmm", "k_bt_diag", "k_bt_sweep", "k_trunc_eig",
-                                "k_reduce_partials", "other"};
+                                "k_reduce_partials", "other", "k_gemm_lowp"};
   return (cls >= 0 && cls < KC_COUNT) ? names[cls] : "?";
 }
 const char* region_name(int r) {
@@ -87,6 +88,15 @@ void prof_read_regions(double* seconds) {
   }
 }
 void prof_enable(bool on) { g_prof.on = on; }
+
+namespace {
+int g_gemm_prec = GP_F64;
+}
+int gemm_precision(int p) {
+  int old = g_gemm_prec;
+  g_gemm_prec = (p == GP_F32 || p == GP_BF16) ? p : GP_F64;
+  return old;
+}
 bool prof_enabled() { return g_prof.on; }
 void prof_reset() {
   std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -137,58 +147,93 @@ __device__ __forceinline__ void gemm_load_tile(const double* __restrict__ A, lon
   }
 }
 
-__device__ __forceinline__ void gemm_store_tile(double As[TK][TM + 1], double Bs[TK][TN + 1], bool a_kfast, bool b_kfast,
-                                                int tid, const double ra[4], const double rb[4]) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int e = tid + 256 * q;
-    int ii, kx;
-    if (a_kfast) { kx = e % TK; ii = e / TK; } else { ii = e % TM; kx = e / TM; }
-    As[kx][ii] = ra[q];
-    int jj, kx2;
-    if (b_kfast) { kx2 = e % TK; jj = e / TK; } else { jj = e % TN; kx2 = e / TN; }
-    Bs[kx2][jj] = rb[q];
-  }
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ short to_bf16(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
 }
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
-// 64 x 64 output tile per 256-thread workgroup on the FP64 matrix cores: each
-// wave owns a 32 x 32 quarter as 2 x 2 tiles of v_mfma_f64_16x16x4 (lane l
-// supplies A[l%16][l/16] and B[l/16][l%16]; accumulator item v of lane l is
-// D[4v + l/16][l%16]).  K is staged through LDS in slices of 16, the next
-// slice prefetched into registers while the current one is consumed.
+// 64 x 64 output tile per 256-thread workgroup on the matrix cores: each wave
+// owns a 32 x 32 quarter as 2 x 2 MFMA tiles of 16 x 16.  PREC selects the
+// arithmetic: GP_F64 v_mfma_f64_16x16x4 (lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator item v is D[4v + l/16][l%16]); GP_F32
+// v_mfma_f32_16x16x4f32 (same inputs; item v is D[4(l/16) + v][l%16]);
+// GP_BF16 v_mfma_f32_16x16x16_bf16 (lane l supplies A[l%16][4(l/16)+j] and
+// B[4(l/16)+j][l%16], j < 4; output as GP_F32).  The reduced precisions
+// round the FP64 operands when they are staged and accumulate in FP32.
+// K is staged through LDS in slices of 16, the next slice prefetched into
+// registers while the current one is consumed.
+template <int PREC>
 __device__ __forceinline__ void gemm_core(int m, int n, long kb, double alpha, const double* __restrict__ A, long sAi,
                                           long sAk, const double* __restrict__ B, long sBk, long sBj, double beta,
                                           double* __restrict__ C, long sCi, long sCj, int i0, int j0) {
-  __shared__ double As[TK][TM + 1];
-  __shared__ double Bs[TK][TN + 1];
+  typedef typename std::conditional<PREC == GP_F64, double, float>::type st_t;
+  typedef typename std::conditional<PREC == GP_F64, dbl4, flt4>::type acc_t;
+  __shared__ st_t As[TK][TM + 1];
+  __shared__ st_t Bs[TK][TN + 1];
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int lr = lane % 16, lk = lane / 16;
-  dbl4 acc[2][2];
+  acc_t acc[2][2];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int c = 0; c < 2; ++c) acc[r][c] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < 2; ++c) acc[r][c] = acc_t{0, 0, 0, 0};
   const bool a_kfast = (sAk == 1);
   const bool b_kfast = (sBk == 1);
   double ra[4], rb[4];
   if (kb > 0) gemm_load_tile(A, sAi, sAk, m, B, sBk, sBj, n, kb, i0, j0, 0, a_kfast, b_kfast, tid, ra, rb);
   for (long kk = 0; kk < kb; kk += TK) {
-    gemm_store_tile(As, Bs, a_kfast, b_kfast, tid, ra, rb);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int e = tid + 256 * q;
+      int ii, kx;
+      if (a_kfast) { kx = e % TK; ii = e / TK; } else { ii = e % TM; kx = e / TM; }
+      As[kx][ii] = (st_t)ra[q];
+      int jj, kx2;
+      if (b_kfast) { kx2 = e % TK; jj = e / TK; } else { jj = e % TN; kx2 = e / TN; }
+      Bs[kx2][jj] = (st_t)rb[q];
+    }
     __syncthreads();
     if (kk + TK < kb) gemm_load_tile(A, sAi, sAk, m, B, sBk, sBj, n, kb, i0, j0, kk + TK, a_kfast, b_kfast, tid, ra, rb);
+    if constexpr (PREC == GP_BF16) {
+      bf16x4 a0, a1, b0, b1;
 #pragma unroll
-    for (int kq = 0; kq < TK / 4; ++kq) {
-      const int kr = kq * 4 + lk;
-      const double a0 = As[kr][wr + lr], a1 = As[kr][wr + 16 + lr];
-      const double b0 = Bs[kr][wc + lr], b1 = Bs[kr][wc + 16 + lr];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      for (int j = 0; j < 4; ++j) {
+        const int kr = 4 * lk + j;
+        a0[j] = to_bf16(As[kr][wr + lr]);
+        a1[j] = to_bf16(As[kr][wr + 16 + lr]);
+        b0[j] = to_bf16(Bs[kr][wc + lr]);
+        b1[j] = to_bf16(Bs[kr][wc + 16 + lr]);
+      }
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int kq = 0; kq < TK / 4; ++kq) {
+        const int kr = kq * 4 + lk;
+        const st_t a0 = As[kr][wr + lr], a1 = As[kr][wr + 16 + lr];
+        const st_t b0 = Bs[kr][wc + lr], b1 = Bs[kr][wc + 16 + lr];
+        if constexpr (PREC == GP_F64) {
+          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        } else {
+          acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+      }
     }
     __syncthreads();
   }
@@ -196,20 +241,22 @@ __device__ __forceinline__ void gemm_core(int m, int n, long kb, double alpha, c
   for (int tr = 0; tr < 2; ++tr)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const long gi = i0 + wr + tr * 16 + 4 * v + lk;
+      const int row = (PREC == GP_F64) ? (4 * v + lk) : (4 * lk + v);
+      const long gi = i0 + wr + tr * 16 + row;
       if (gi >= m) continue;
 #pragma unroll
       for (int tc = 0; tc < 2; ++tc) {
         const long gj = j0 + wc + tc * 16 + lr;
         if (gj >= n) continue;
         double* cp = C + gi * sCi + gj * sCj;
-        double val = alpha * acc[tr][tc][v];
+        double val = alpha * (double)acc[tr][tc][v];
         if (beta != 0.0) val += beta * (*cp);
         *cp = val;
       }
     }
 }
 
+template <int PREC>
 __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, double alpha, const double* __restrict__ A,
                                               long sAb, long sAi, long sAk, const double* __restrict__ B, long sBb,
                                               long sBk, long sBj, double beta, double* __restrict__ C, long sCb,
@@ -220,15 +267,16 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, double alpha,
     long rem = klimit - (long)b * kstep;
     kb = rem < k ? rem : k;
   }
-  gemm_core(m, n, kb, alpha, A + b * sAb, sAi, sAk, B + b * sBb, sBk, sBj, beta, C + b * sCb, sCi, sCj,
-            blockIdx.y * TM, blockIdx.x * TN);
+  gemm_core<PREC>(m, n, kb, alpha, A + b * sAb, sAi, sAk, B + b * sBb, sBk, sBj, beta, C + b * sCb, sCi, sCj,
+                  blockIdx.y * TM, blockIdx.x * TN);
 }
 
+template <int PREC>
 __global__ __launch_bounds__(256) void k_gemm_ptr(const GemmDesc* __restrict__ descs) {
   const GemmDesc d = descs[blockIdx.z];
   const int i0 = blockIdx.y * TM, j0 = blockIdx.x * TN;
   if (i0 >= d.m || j0 >= d.n) return;
-  gemm_core(d.m, d.n, d.k, d.alpha, d.A, d.sAi, d.sAk, d.B, d.sBk, d.sBj, d.beta, d.C, d.sCi, d.sCj, i0, j0);
+  gemm_core<PREC>(d.m, d.n, d.k, d.alpha, d.A, d.sAi, d.sAk, d.B, d.sBk, d.sBj, d.beta, d.C, d.sCi, d.sCj, i0, j0);
 }
 
 // out[e] = sum_b ws[b*ne + e]: 64 elements per 256-thread block, the
@@ -1198,8 +1246,10 @@ void gemm(hipStream_t s, int batch, int m, int n, int k, double alpha, const dou
       nch = (k + chunk - 1) / chunk;
       dim3 grid(cdiv(n, TN), cdiv(m, TM), (unsigned)nch);
       {
-        ProfScope ps(KC_GEMM, s, 8.0 * ((double)k * (m + n) + (double)ne * nch), 2.0 * m * n * (double)k);
-        hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, m, n, (int)chunk, 1.0, A, chunk * sAk, sAi, sAk, B,
+        ProfScope ps(g_gemm_prec == GP_F64 ? KC_GEMM : KC_GEMM_LOWP, s, 8.0 * ((double)k * (m + n) + (double)ne * nch),
+                     2.0 * m * n * (double)k);
+        auto kern = g_gemm_prec == GP_F32 ? k_gemm<GP_F32> : (g_gemm_prec == GP_BF16 ? k_gemm<GP_BF16> : k_gemm<GP_F64>);
+        hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, m, n, (int)chunk, 1.0, A, chunk * sAk, sAi, sAk, B,
                            chunk * sBk, sBk, sBj, 0.0, ws, ne, (long)n, 1L, (int)chunk, (long)k);
       }
       hipLaunchKernelGGL(k_reduce_scaled, dim3(cdiv(ne, 256)), dim3(256), 0, s, (int)nch, m, n, ws, alpha, beta, C,
@@ -1211,8 +1261,9 @@ void gemm(hipStream_t s, int batch, int m, int n, int k, double alpha, const dou
   double kk = klimit > 0 ? (double)klimit : (double)k * batch;   // total reduction length
   double by = klimit > 0 ? 8.0 * (kk * (m + n) + (double)m * n * batch)
                          : 8.0 * batch * ((double)m * k + (double)k * n + (double)m * n * (beta != 0.0 ? 2 : 1));
-  ProfScope ps(KC_GEMM, s, by, 2.0 * m * n * kk);
-  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, m, n, k, alpha, A, sAb, sAi, sAk, B, sBb, sBk, sBj, beta, C, sCb,
+  ProfScope ps(g_gemm_prec == GP_F64 ? KC_GEMM : KC_GEMM_LOWP, s, by, 2.0 * m * n * kk);
+  auto kern = g_gemm_prec == GP_F32 ? k_gemm<GP_F32> : (g_gemm_prec == GP_BF16 ? k_gemm<GP_BF16> : k_gemm<GP_F64>);
+  hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, m, n, k, alpha, A, sAb, sAi, sAk, B, sBb, sBk, sBj, beta, C, sCb,
                      sCi, sCj, kstep, klimit);
 }
 
@@ -1222,12 +1273,15 @@ void gemm_batched(hipStream_t s, int nb, const GemmDesc* d_desc, int max_m, int 
     int n = std::min(65535, nb - b0);
     dim3 grid(cdiv(max_n, TN), cdiv(max_m, TM), n);
     ProfScope ps(KC_GEMM_PTR, s, 0.0, 0.0);
-    hipLaunchKernelGGL(k_gemm_ptr, grid, dim3(256), 0, s, d_desc + b0);
+    auto kern = g_gemm_prec == GP_F32 ? k_gemm_ptr<GP_F32>
+                                      : (g_gemm_prec == GP_BF16 ? k_gemm_ptr<GP_BF16> : k_gemm_ptr<GP_F64>);
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, d_desc + b0);
   }
 }
 
 void gram(hipStream_t s, long rows, int nx, int ny, const double* X, long sXr, long sXc, const double* Y, long sYr,
           long sYc, double* out, double* ws, size_t ws_doubles) {
+  GemmPrecisionScope f64(GP_F64);   // Grams decide truncations: always FP64
   const long ne = (long)nx * ny;
   if (rows <= 0) {
     fill(s, out, ne, 0.0);

@@ -498,6 +498,7 @@ struct PrecOpts {
   double eps = 1e-6, inner_tol = 1e-1, inner_eps = 1e-3;
   int inner_maxit = 20;
   bool inner_explicit = false;
+  int precision = GP_F64;   // dense products of the inner solve
 };
 
 Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCounters* cnt) {
@@ -524,6 +525,7 @@ Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCoun
   double rr = 0;
   SolveCounters icnt;
   icnt.verbose = cnt ? cnt->verbose : 0;
+  GemmPrecisionScope gp(po.precision);
   Vec v = lowrank_fgmres(c, isp, rhs, po.inner_tol, po.inner_eps, po.inner_maxit, S.dsc + 16384, its, rr, &icnt,
                          "inner", po.inner_explicit);
   if (cnt) cnt->inner += its;
@@ -630,6 +632,8 @@ PrecOpts prec_opts(const sgtt_solve_opts* o) {
     p.inner_eps = o->inner_eps;
     p.inner_maxit = o->inner_maxit;
     p.inner_explicit = o->inner_explicit != 0;
+    if (o->precision < 0 || o->precision > 2) throw SgttError(-1, "invalid precision option");
+    p.precision = o->precision;
   }
   return p;
 }
@@ -648,6 +652,7 @@ sgtt_solve_opts default_opts() {
   o.outer_explicit = 1;
   o.inner_explicit = 0;
   o.relax = 0;
+  o.precision = 0;
   return o;
 }
 

@@ -150,6 +150,7 @@ TT tt_concat(Ctx& c, const std::vector<const TT*>& xs, const double* dcoef, cons
 }
 
 void tt_dot(Ctx& c, const TT& x, const TT& y, double* dout, int acc, double* k3_out) {
+  GemmPrecisionScope f64(GP_F64);   // inner products stay FP64
   const int n1 = x.n1, n2 = x.n2;
   const int a1 = x.r1, a2 = x.r2, b1 = y.r1, b2 = y.r2;
   double* W1 = c.pool.get((size_t)a1 * b1);
@@ -197,6 +198,7 @@ struct Skeleton {
 
 static Skeleton trunc_skeleton(Ctx& c, int N, double* S, double eps, const double* dnorm_in, double* d_kept,
                                int kcap, int rank_bound, const char* what) {
+  GemmPrecisionScope f64(GP_F64);
   double* L = c.pool.get((size_t)N * kcap);
   double* d = c.pool.get((size_t)N + 8);
   double* state = d + N;
@@ -266,6 +268,9 @@ TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_no
   double* dnorm = d_normsq ? d_normsq : c.dscal + 250;
   double* dkept1 = c.dscal + 251;
   double* dkept2 = d_kept ? d_kept : c.dscal + 252;
+  // Gram-forming products (K3, K2, S1, S2) run in FP64 whatever the ambient
+  // precision; the projections (D, C, W, new core 3) use the ambient one.
+  const int amb = gemm_precision(GP_F64);
   // ---- K3 = G3^T G3 (R2 x R2) assembled from blocks (cached or computed)
   double* K3 = c.pool.get((size_t)R2 * R2);
   int maxb = 0;
@@ -335,6 +340,7 @@ TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_no
   h[1] = c.hint[1];
   if (h[1] != 0) throw SgttError(-4, "TT rank capacity exceeded (bond 1)");
   const int k1 = h[0];
+  gemm_precision(amb);
   // ---- C (k1 n2 x R2): block j = (U1^T c_j A_j) x_1 B_j
   double* D = c.pool.get((size_t)k1 * R1);
   gemm(c.s, 1, k1, R1, n1, 1.0, U1, 0, 1, kmax1, G1, 0, R1, 1, 0.0, D, 0, R1, 1);
@@ -354,6 +360,7 @@ TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_no
     c.pool.put(dd);
   }
   const int N2 = k1 * n2;
+  gemm_precision(GP_F64);
   // ---- S2 = C K3 C^T, truncate bond 2
   double* T2 = c.pool.get((size_t)N2 * R2);
   gemm(c.s, 1, N2, R2, R2, 1.0, Cm, 0, R2, 1, K3, 0, R2, 1, 0.0, T2, 0, R2, 1);
@@ -375,6 +382,7 @@ TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_no
     sk = trunc_skeleton(c, N2, S2, eps, dnorm, dkept2, std::min({N2, R2, maxrank, RANK_CAP_LARGE}),
                         std::min(N2, R2), "bond 2");
   const int k2 = h[3] == 2 ? sk.k : h[2];
+  gemm_precision(amb);
   // ---- W (k2 x R2) = U2^T C, or the skeleton rows C[P, :]; new G3 = sum_j C_j W_j^T
   double* W = c.pool.get((size_t)k2 * R2);
   if (h[3] == 2)

@@ -187,3 +187,31 @@ def test_solve_c1_stokes_to_1e8(sg, ctx, c1):
     zg = np.concatenate([xu.ravel(), xp.ravel()])
     assert np.linalg.norm(zg - zd) <= 1e-7 * np.linalg.norm(zd)
     assert abs(S.residual(b, x) - rel) <= 1e-3 * rel + 1e-14
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_solve_c1_mixed_precision_to_1e8(sg, ctx, c1, precision):
+    # FP32 / BF16 matrix-core products inside the preconditioner's inner
+    # solve; the FP64 outer refinement still reaches the exact solution
+    P, S = c1
+    _flush(f"solve c1 precision={precision}")
+    b = S.rhs()
+    x, st, rc = S.solve(b, S.pair(64, 1024), restart=20, relax=1, precision=precision)
+    assert rc == 0 and st["rel_residual"] <= 1e-8
+    bo = P.rhs()
+    u, p = P.solve_direct(tt.full(bo[0]), tt.full(bo[1]))
+    zd = np.concatenate([u.ravel(), p.ravel()])
+    assert np.linalg.norm(tt.pair_full(x.cores()) - zd) <= 1e-7 * np.linalg.norm(zd)
+
+
+@pytest.mark.parametrize("precision,bound", [(1, 1e-3), (2, 1e-1)])
+def test_preconditioner_reduced_precision_close(sg, ctx, tiny, precision, bound):
+    # the reduced-precision inner solve stays close to the FP64 one (it is a
+    # preconditioner: its error only costs iterations, not accuracy)
+    P, S = tiny
+    _flush(f"precondition tiny precision={precision}")
+    r = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 4), (2, 3), 9)
+    br = _pair_buf(S, r)
+    ref = tt.pair_full(S.precondition(br, inner_eps=1e-3).cores())
+    got = tt.pair_full(S.precondition(br, inner_eps=1e-3, precision=precision).cores())
+    assert np.linalg.norm(got - ref) <= bound * np.linalg.norm(ref)
