@@ -178,6 +178,18 @@ int sgtt_axpby(sgtt_context* ctx, double alpha, const sgtt_tt_pair* x, double be
 int sgtt_solve(sgtt_system* sys, const sgtt_tt_pair* b, sgtt_tt_pair* x, const sgtt_solve_opts* opts,
                sgtt_solve_stats* stats);
 
+/* Solve n independent systems (b[i], x[i] as in sgtt_solve).  Systems
+ * assembled on different contexts run concurrently (one host worker per
+ * context driving that context's stream; the streams share the device);
+ * systems on the same context run in order.  status[i] gets each solve's
+ * return code and stats[i] (may be NULL) its statistics.  Returns the worst
+ * status, or SGTT_E_INVALID if any solve failed (see status[i] and
+ * sgtt_last_error of that system's context).  A context must not be used by
+ * other calls while the batch runs. */
+int sgtt_solve_batched(sgtt_system* const* systems, int n, const sgtt_tt_pair* const* b,
+                       sgtt_tt_pair* const* x, const sgtt_solve_opts* opts, sgtt_solve_stats* stats,
+                       int* status);
+
 /* ------------------------------------------------------------- Picard */
 #define SGTT_PICARD_MAX_STEPS 16
 

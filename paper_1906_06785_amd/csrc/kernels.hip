@@ -38,7 +38,7 @@ struct Profiler {
 };
 Profiler g_prof;
 std::mutex g_prof_mu;
-int g_region = 0;
+thread_local int g_region = 0;   // per host thread (workers of batched solves)
 
 struct ProfScope {
   int cls;
@@ -90,7 +90,7 @@ void prof_read_regions(double* seconds) {
 void prof_enable(bool on) { g_prof.on = on; }
 
 namespace {
-int g_gemm_prec = GP_F64;
+thread_local int g_gemm_prec = GP_F64;
 }
 int gemm_precision(int p) {
   int old = g_gemm_prec;

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/sgtt.h"
@@ -1246,6 +1247,44 @@ int sgtt_solve(sgtt_system* S, const sgtt_tt_pair* b, sgtt_tt_pair* x, const sgt
     return SGTT_E_INVALID;
   }
   return status;
+}
+
+int sgtt_solve_batched(sgtt_system* const* systems, int n, const sgtt_tt_pair* const* b, sgtt_tt_pair* const* x,
+                       const sgtt_solve_opts* opts, sgtt_solve_stats* stats, int* status) {
+  if (n < 0 || (n > 0 && (!systems || !b || !x || !status))) return SGTT_E_INVALID;
+  for (int i = 0; i < n; ++i)
+    if (!systems[i] || !b[i] || !x[i]) return SGTT_E_INVALID;
+  // one worker per context: its problems run in order on its stream, the
+  // contexts' streams run concurrently on the device
+  std::vector<sgtt_context*> ctxs;
+  std::vector<std::vector<int>> work;
+  for (int i = 0; i < n; ++i) {
+    sgtt_context* c = systems[i]->ctx;
+    size_t w = 0;
+    while (w < ctxs.size() && ctxs[w] != c) ++w;
+    if (w == ctxs.size()) {
+      ctxs.push_back(c);
+      work.emplace_back();
+    }
+    work[w].push_back(i);
+  }
+  auto run = [&](size_t w) {
+    for (int i : work[w]) {
+      sgtt_solve_stats st{};
+      status[i] = sgtt_solve(systems[i], b[i], x[i], opts, &st);
+      if (stats) stats[i] = st;
+    }
+  };
+  std::vector<std::thread> th;
+  for (size_t w = 1; w < ctxs.size(); ++w) th.emplace_back(run, w);
+  if (!ctxs.empty()) run(0);
+  for (auto& t : th) t.join();
+  int worst = SGTT_OK;
+  for (int i = 0; i < n; ++i) {
+    if (status[i] < 0) return SGTT_E_INVALID;
+    if (status[i] > worst) worst = status[i];
+  }
+  return worst;
 }
 
 // Picard's method (Alg. 3.1) with truncated iterates (eq. 4.8).

@@ -120,6 +120,9 @@ _sig = {
     "sgtt_profile_class_name": (C.c_char_p, [C.c_int]),
     "sgtt_picard": (C.c_int, [_P, C.POINTER(ProblemDesc), C.POINTER(PicardOpts), C.POINTER(SgttPair),
                               C.POINTER(PicardStats)]),
+    "sgtt_solve_batched": (C.c_int, [C.POINTER(_P), C.c_int, C.POINTER(C.POINTER(SgttPair)),
+                                     C.POINTER(C.POINTER(SgttPair)), C.POINTER(SolveOpts), C.POINTER(SolveStats),
+                                     C.POINTER(C.c_int)]),
     "sgtt_residual_tensor": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), _P, _P,
                                        C.POINTER(C.c_double)]),
     "sgtt_profile_read_regions": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
@@ -437,6 +440,28 @@ class System:
         if getattr(self, "_s", None) and _lib is not None:
             _lib.sgtt_system_destroy(self._s)
             self._s = None
+
+
+def solve_batched(systems, bs, xs, **opts):
+    """Solve independent systems; those on different contexts run concurrently.
+    Returns ([stats dict], [status])."""
+    n = len(systems)
+    o = make_opts(**opts)
+    sysarr = (_P * n)(*[S._s for S in systems])
+    bstructs = [b.struct() for b in bs]
+    xstructs = [x.struct() for x in xs]
+    barr = (C.POINTER(SgttPair) * n)(*[C.pointer(t) for t in bstructs])
+    xarr = (C.POINTER(SgttPair) * n)(*[C.pointer(t) for t in xstructs])
+    st = (SolveStats * n)()
+    status = (C.c_int * n)()
+    rc = _lib.sgtt_solve_batched(sysarr, n, barr, xarr, C.byref(o), st, status)
+    for x, t in zip(xs, xstructs):
+        x.update(t)
+    if rc < 0:
+        bad = [i for i in range(n) if status[i] < 0]
+        raise SgttError(rc, f"batched solve failed for problems {bad}: "
+                            + _lib.sgtt_last_error(systems[bad[0]].ctx._c).decode())
+    return [st[i].as_dict() for i in range(n)], list(status)
 
 
 def picard(ctx: Context, cfg: dict, steps: int = 5, tol_picard: float = 1e-5, eps_soln: float = 1e-10,

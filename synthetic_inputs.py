@@ -75,3 +75,23 @@ def random_tt_pair(nt: int, nxi: int, nu: int, np_: int, ranks_u, ranks_p,
     u = random_tt_cores(nt, nxi, nu, ranks_u[0], ranks_u[1], seed, decay)
     p = random_tt_cores(nt, nxi, np_, ranks_p[0], ranks_p[1], seed + 7919, decay)
     return u, p
+
+
+def batch_configs(n: int = 64, seed: int = 0, small: bool = False):
+    """Independent problems for batched solves, drawn in a fixed order by
+    default_rng(seed): grid h, number of random variables m, chaos degree p,
+    time steps n_t (tau = 0.05) and a mean viscosity nu0 log-uniform in
+    [1/200, 1/20]; the viscosity law and inflow are those of CONFIGS.  small
+    selects coarse grids and short horizons (for tests)."""
+    g = rng(seed)
+    hs = (0.25, 0.125) if small else (0.125, 1.0 / 12.0, 0.0625)
+    ms = (2, 3) if small else (2, 3, 4)
+    ps = (1, 2) if small else (2, 3)
+    nts = (8, 16) if small else (32, 64, 128)
+    out = []
+    for _ in range(n):
+        out.append(dict(h=float(g.choice(hs)), L=12.0, m=int(g.choice(ms)), p=int(g.choice(ps)),
+                        nt=int(g.choice(nts)), tau=0.05,
+                        nu0=float(np.exp(g.uniform(np.log(1 / 200), np.log(1 / 20)))), nu_coef=0.1,
+                        ramp=10.0))
+    return out
