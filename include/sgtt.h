@@ -121,6 +121,8 @@ typedef struct {
   int max_rank_krylov_u, max_rank_krylov_p;
   int roundings;
   double t_apply, t_round, t_precond, t_residual;   /* seconds by phase     */
+  int learned_calls;         /* mean solves done by an attached network      */
+  int learned_fallback;      /* 1 if the solve switched back to the exact one */
 } sgtt_solve_stats;
 
 /* ------------------------------------------------------------- context */
@@ -247,6 +249,52 @@ int sgtt_expand(sgtt_context* ctx, const sgtt_tt* x, double* out);
  * Givens rotations on the device (Alg. 4.2, line 12).  y: host, length k. */
 int sgtt_hessenberg_lsq(sgtt_context* ctx, const double* H, int k, double beta, double* y,
                         double* resid);
+
+/* ------------------------------------------------ learned mean solve
+ * A correction of the mean spatial solve used inside the inner
+ * preconditioner M^-1 = (I - C)^-1 (x) I (x) F_avg^-1 (eq. 5.23).  The
+ * paper's inner solve only needs to be approximate (sec. 5.2) and the outer
+ * solve is flexible (sec. 4.2), so F_avg^-1 may be replaced there by
+ *     z = D^-1 r + ||r|| MLP(r / ||r||),   D = diag(F_avg),
+ * applied to every spatial column (each velocity component separately).
+ * MLP: n -> width -> width -> n with ReLU; weights FP16, activations and
+ * accumulation FP32 on the matrix cores; trained on the device with Adam on
+ * FP32 masters, minimizing the mean relative squared error against the
+ * exact correction (F_avg^-1 r - D^-1 r) / ||r|| over pairs that the solver
+ * records from its own exact mean solves.  The exact solve remains the
+ * fallback: after two inner solves that miss their tolerance with the
+ * network, the rest of that solve uses the exact one (learned_fallback). */
+typedef struct sgtt_mlp sgtt_mlp;
+
+/* n = spatial size of one component (n_s of the system), capacity = pairs
+ * that can be recorded (2 per velocity column of a mean solve). */
+int sgtt_mlp_create(sgtt_context* ctx, int n, int width, long capacity, unsigned seed, sgtt_mlp** out);
+int sgtt_mlp_destroy(sgtt_mlp* mlp);
+/* number of parameters (W1 w x n, b1 w, W2 w x w, b2 w, W3 n x w, b3 n, in
+ * this order, row-major) and of recorded pairs */
+int sgtt_mlp_size(const sgtt_mlp* mlp, long* nparam, long* npairs);
+/* host FP32 parameter vectors in the order above (set rounds the working
+ * weights to FP16 and resets the optimizer state) */
+int sgtt_mlp_set_params(sgtt_mlp* mlp, const float* host);
+int sgtt_mlp_get_params(sgtt_mlp* mlp, float* host);
+/* y = MLP(x) for batch host columns (column s at x + s*n) */
+int sgtt_mlp_forward(sgtt_mlp* mlp, const float* x, int batch, float* y);
+/* loss (mean relative squared error) and its gradient (host, nparam floats,
+ * may be NULL) for host inputs x and targets t */
+int sgtt_mlp_loss_grad(sgtt_mlp* mlp, const float* x, const float* t, int batch, double* loss, float* grad);
+/* append host training pairs (x_s, t_s at x + s*n, t + s*n) while capacity
+ * lasts; *added gets how many were stored */
+int sgtt_mlp_add_pairs(sgtt_mlp* mlp, const float* x, const float* t, long count, long* added);
+/* steps Adam minibatches of batch recorded pairs (uniform with replacement,
+ * seeded; batch >= the number of pairs uses all pairs in order every step);
+ * losses: host array of steps values or NULL */
+int sgtt_mlp_train(sgtt_mlp* mlp, int steps, int batch, double lr, unsigned seed, double* losses);
+/* record (r, F_avg^-1 r) pairs from this system's exact mean solves during
+ * later solves (NULL stops recording); network and system must share the
+ * context and the spatial size */
+int sgtt_mlp_collect(sgtt_system* sys, sgtt_mlp* mlp);
+/* use the network for the mean solves of this system (NULL: exact solve) */
+int sgtt_mlp_attach(sgtt_system* sys, sgtt_mlp* mlp);
 
 /* ------------------------------------------------------------- profiling */
 /* Per-launch timing of the library's kernels with HIP events recorded on the

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsgtt.so")
 ARCH = os.environ.get("SGTT_ARCH", "gfx950")
 
-HIP_SOURCES = ["kernels.hip", "tt_core.hip", "solver.hip"]
+HIP_SOURCES = ["kernels.hip", "tt_core.hip", "learned.hip", "solver.hip"]
 CXX_SOURCES = ["host_setup.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

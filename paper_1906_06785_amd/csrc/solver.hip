@@ -15,6 +15,7 @@
 #include "../../include/sgtt.h"
 #include "host_setup.h"
 #include "kernels.h"
+#include "learned.h"
 #include "tt_core.h"
 
 using namespace sgtt;
@@ -108,6 +109,15 @@ DevBT upload_bt(Ctx& c, const BlockTri& bt) {
 
 }  // namespace
 
+// 1 / diag of a scalar matrix given by values on the pattern `pat`
+std::vector<double> inverse_diagonal(const Csr& pat, const double* vals) {
+  std::vector<double> d(pat.nrows, 0.0);
+  for (int i = 0; i < pat.nrows; ++i)
+    for (int t = pat.rowptr[i]; t < pat.rowptr[i + 1]; ++t)
+      if (pat.col[t] == i) d[i] = vals[t] != 0.0 ? 1.0 / vals[t] : 0.0;
+  return d;
+}
+
 // ====================================================================== system
 struct sgtt_system {
   sgtt_context* ctx = nullptr;
@@ -126,6 +136,11 @@ struct sgtt_system {
   double* omega = nullptr; // nt x k2 (mean-mode time factors)
   DevBT Fbt, Xbt;          // F_avg and X = B M*^-1 B^T factorizations
   TT bu, bp;               // right-hand side
+  double* Dinv = nullptr;  // 1 / diag(F_avg) on free scalar nodes
+  sgtt::Mlp* mlp_collect = nullptr;   // records (r, F_avg^-1 r) pairs from mean solves
+  sgtt::Mlp* mlp_apply = nullptr;     // learned mean solve in M^-1 (eq. 5.23)
+  bool mlp_off = false;               // fallback taken in the current solve
+  int mlp_fails = 0, mlp_calls = 0;
   double rhs_norm = 0;     // ||f|| (Stokes) or ||r|| of the untruncated nonlinear residual (Picard)
   double setup_s = 0;
   // solve scratch (device scalars)
@@ -137,7 +152,7 @@ struct sgtt_system {
     Xmid.free_all();
     Fbt.free_all();
     Xbt.free_all();
-    for (double* p : {Gnu, w1, Hw, omega, dsc}) (void)hipFree(p);
+    for (double* p : {Gnu, w1, Hw, omega, dsc, Dinv}) (void)hipFree(p);
   }
 };
 
@@ -217,13 +232,32 @@ TT space_solve(sgtt_system& S, const TT& x, const DevBT& bt, int ncomp, double c
 
 // M^-1 = (I - C)^-1 (x) I (x) F_avg^-1 (eq. 5.23): prefix sum in time,
 // F_avg solve on both velocity components of core 3
+// With a learned mean solve attached (and no fallback taken), F_avg^-1 is
+// replaced by D^-1 + ||r|| MLP(r/||r||) on every column; with a collector
+// attached, the exact solve's (r, F_avg^-1 r) pairs are recorded.
 TT apply_Minv(sgtt_system& S, const TT& u) {
   Ctx& c = S.ctx->c;
   TT o = tt_new(c, u.n1, u.n2, u.n3, u.r1, u.r2);
   core1_op(c.s, 2, S.nt, u.r1, u.c1, u.r1, o.c1, u.r1, 0, 1.0);
   SGTT_HIP(hipMemcpyAsync(o.c2, u.c2, sizeof(double) * u.n_c2(), hipMemcpyDeviceToDevice, c.s));
+  if (S.mlp_apply && !S.mlp_off) {
+    ++S.mlp_calls;
+    try {
+      mlp_apply(*S.mlp_apply, S.ns, 2, u.r2, u.c3, o.c3, u.r2, S.Dinv);
+    } catch (const std::exception& e) {
+      throw SgttError(-2, std::string("learned mean solve: ") + e.what());
+    }
+    return o;
+  }
   blocktri_solve(c.s, S.Fbt.n, S.Fbt.nblk, S.Fbt.maxbs, S.Fbt.start, S.Fbt.off_sinv, S.Fbt.off_p, S.Fbt.off_q,
                  S.Fbt.data, 2, u.c3, u.r2, u.r2, o.c3, S.Fbt.nd);
+  if (S.mlp_collect) {
+    try {
+      mlp_collect(*S.mlp_collect, S.ns, 2, u.r2, u.c3, o.c3, u.r2, S.Dinv);
+    } catch (const std::exception& e) {
+      throw SgttError(-2, std::string("collecting mean-solve pairs: ") + e.what());
+    }
+  }
   return o;
 }
 
@@ -530,6 +564,9 @@ Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCoun
   Vec v = lowrank_fgmres(c, isp, rhs, po.inner_tol, po.inner_eps, po.inner_maxit, S.dsc + 16384, its, rr, &icnt,
                          "inner", po.inner_explicit);
   if (cnt) cnt->inner += its;
+  // fallback: two inner solves that miss their tolerance with the learned
+  // mean solve switch the rest of this solve back to the exact one
+  if (S.mlp_apply && !S.mlp_off && rr > po.inner_tol && ++S.mlp_fails >= 2) S.mlp_off = true;
   Vec out;
   out.nc = 2;
   out.c[0] = std::move(v.c[0]);
@@ -718,6 +755,8 @@ void build_convection(sgtt_system& S, Ctx& c, const TT& wtil) {
   }
   BlockTri bt;
   std::string err;
+  if (S.Dinv) (void)hipFree(S.Dinv);
+  S.Dinv = dev_upload(c, inverse_diagonal(hp.Kff, F.data()));
   blocktri_factor(hp.Kff, F.data(), hp.vel_blocks, bt, err);
   if (!err.empty()) throw SgttError(-6, err);
   S.Fbt = upload_bt(c, bt);
@@ -843,6 +882,7 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
     S->Xmid = upload_csr(c, hp.Xmid, {hp.XM.data(), hp.XA.data()});
     std::vector<double> F(hp.Kff.nnz());
     for (int t = 0; t < hp.Kff.nnz(); ++t) F[t] = hp.Mff[t] / S->tau + S->nu0 * hp.Aff[t];
+    S->Dinv = dev_upload(c, inverse_diagonal(hp.Kff, F.data()));
     BlockTri bt;
     std::string err;
     blocktri_factor(hp.Kff, F.data(), hp.vel_blocks, bt, err);
@@ -1178,6 +1218,9 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
   SolveCounters cnt;
   cnt.verbose = o.verbose;
   OuterSpace sp(*S, prec_opts(&o), &cnt);
+  S->mlp_off = false;
+  S->mlp_fails = 0;
+  S->mlp_calls = 0;
   std::vector<Vec> terms;
   Vec r = vec_copy(c, bv);
   double bn2 = -1.0, rel = 1.0;
@@ -1222,6 +1265,8 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
     stats->t_round = 0;
     stats->t_precond = cnt.t_prec;
     stats->t_residual = 0;
+    stats->learned_calls = S->mlp_calls;
+    stats->learned_fallback = S->mlp_off ? 1 : 0;
   }
   return rel > o.tol ? SGTT_W_NOT_CONVERGED : SGTT_OK;
 }
@@ -1375,6 +1420,91 @@ int sgtt_picard(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_pic
     return SGTT_E_INVALID;
   }
   return status;
+}
+
+// ---------------------------------------------------------------- learned mean solve
+struct sgtt_mlp {
+  sgtt_context* ctx = nullptr;
+  std::unique_ptr<Mlp> m;
+};
+
+int sgtt_mlp_create(sgtt_context* ctx, int n, int width, long capacity, unsigned seed, sgtt_mlp** out) {
+  if (!ctx || !out || n < 1 || width < 1 || capacity < 0) return SGTT_E_INVALID;
+  return guarded(ctx, [&]() {
+    auto h = std::make_unique<sgtt_mlp>();
+    h->ctx = ctx;
+    h->m.reset(mlp_create(ctx->c.s, n, width, capacity, seed));
+    *out = h.release();
+  });
+}
+
+int sgtt_mlp_destroy(sgtt_mlp* m) {
+  if (m && m->ctx) (void)hipStreamSynchronize(m->ctx->c.s);
+  delete m;
+  return SGTT_OK;
+}
+
+int sgtt_mlp_size(const sgtt_mlp* m, long* nparam, long* npairs) {
+  if (!m) return SGTT_E_INVALID;
+  if (nparam) *nparam = (long)m->m->nparam;
+  if (npairs) *npairs = m->m->count;
+  return SGTT_OK;
+}
+
+int sgtt_mlp_set_params(sgtt_mlp* m, const float* host) {
+  if (!m || !host) return SGTT_E_INVALID;
+  return guarded(m->ctx, [&]() { mlp_set_params(*m->m, host); });
+}
+
+int sgtt_mlp_get_params(sgtt_mlp* m, float* host) {
+  if (!m || !host) return SGTT_E_INVALID;
+  return guarded(m->ctx, [&]() { mlp_get_params(*m->m, host); });
+}
+
+int sgtt_mlp_forward(sgtt_mlp* m, const float* x, int batch, float* y) {
+  if (!m || !x || !y || batch < 1) return SGTT_E_INVALID;
+  return guarded(m->ctx, [&]() { mlp_forward_host(*m->m, x, batch, y); });
+}
+
+int sgtt_mlp_loss_grad(sgtt_mlp* m, const float* x, const float* t, int batch, double* loss, float* grad) {
+  if (!m || !x || !t || batch < 1) return SGTT_E_INVALID;
+  return guarded(m->ctx, [&]() {
+    double L = mlp_loss_grad_host(*m->m, x, t, batch, grad);
+    if (loss) *loss = L;
+  });
+}
+
+int sgtt_mlp_train(sgtt_mlp* m, int steps, int batch, double lr, unsigned seed, double* losses) {
+  if (!m || steps < 0 || batch < 1 || !(lr > 0)) return SGTT_E_INVALID;
+  return guarded(m->ctx, [&]() { mlp_train(*m->m, steps, batch, lr, seed, losses); });
+}
+
+int sgtt_mlp_add_pairs(sgtt_mlp* m, const float* x, const float* t, long count, long* added) {
+  if (!m || !x || !t || count < 0) return SGTT_E_INVALID;
+  return guarded(m->ctx, [&]() {
+    long k = mlp_add_pairs(*m->m, x, t, count);
+    if (added) *added = k;
+  });
+}
+
+int sgtt_mlp_collect(sgtt_system* S, sgtt_mlp* m) {
+  if (!S) return SGTT_E_INVALID;
+  if (m && (m->ctx != S->ctx || m->m->n != S->ns)) {
+    S->ctx->err = "network and system do not match (context or spatial size)";
+    return SGTT_E_INVALID;
+  }
+  S->mlp_collect = m ? m->m.get() : nullptr;
+  return SGTT_OK;
+}
+
+int sgtt_mlp_attach(sgtt_system* S, sgtt_mlp* m) {
+  if (!S) return SGTT_E_INVALID;
+  if (m && (m->ctx != S->ctx || m->m->n != S->ns)) {
+    S->ctx->err = "network and system do not match (context or spatial size)";
+    return SGTT_E_INVALID;
+  }
+  S->mlp_apply = m ? m->m.get() : nullptr;
+  return SGTT_OK;
 }
 
 int sgtt_profile_enable(sgtt_context* ctx, int enable) {

@@ -87,7 +87,8 @@ class SolveStats(C.Structure):
     _fields_ = [("cycles", C.c_int), ("outer_iters", C.c_int), ("inner_iters", C.c_int),
                 ("rel_residual", C.c_double), ("seconds", C.c_double), ("max_rank_krylov_u", C.c_int),
                 ("max_rank_krylov_p", C.c_int), ("roundings", C.c_int), ("t_apply", C.c_double),
-                ("t_round", C.c_double), ("t_precond", C.c_double), ("t_residual", C.c_double)]
+                ("t_round", C.c_double), ("t_precond", C.c_double), ("t_residual", C.c_double),
+                ("learned_calls", C.c_int), ("learned_fallback", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -123,6 +124,19 @@ _sig = {
     "sgtt_solve_batched": (C.c_int, [C.POINTER(_P), C.c_int, C.POINTER(C.POINTER(SgttPair)),
                                      C.POINTER(C.POINTER(SgttPair)), C.POINTER(SolveOpts), C.POINTER(SolveStats),
                                      C.POINTER(C.c_int)]),
+    "sgtt_mlp_create": (C.c_int, [_P, C.c_int, C.c_int, C.c_long, C.c_uint, C.POINTER(_P)]),
+    "sgtt_mlp_destroy": (C.c_int, [_P]),
+    "sgtt_mlp_size": (C.c_int, [_P, C.POINTER(C.c_long), C.POINTER(C.c_long)]),
+    "sgtt_mlp_set_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "sgtt_mlp_get_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "sgtt_mlp_forward": (C.c_int, [_P, C.POINTER(C.c_float), C.c_int, C.POINTER(C.c_float)]),
+    "sgtt_mlp_loss_grad": (C.c_int, [_P, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_float)]),
+    "sgtt_mlp_train": (C.c_int, [_P, C.c_int, C.c_int, C.c_double, C.c_uint, C.POINTER(C.c_double)]),
+    "sgtt_mlp_add_pairs": (C.c_int, [_P, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_long,
+                                     C.POINTER(C.c_long)]),
+    "sgtt_mlp_collect": (C.c_int, [_P, _P]),
+    "sgtt_mlp_attach": (C.c_int, [_P, _P]),
     "sgtt_residual_tensor": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), _P, _P,
                                        C.POINTER(C.c_double)]),
     "sgtt_profile_read_regions": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
@@ -440,6 +454,89 @@ class System:
         if getattr(self, "_s", None) and _lib is not None:
             _lib.sgtt_system_destroy(self._s)
             self._s = None
+
+
+class Mlp:
+    """Learned correction of the mean spatial solve (see include/sgtt.h)."""
+
+    def __init__(self, ctx: Context, n: int, width: int = 256, capacity: int = 0, seed: int = 0):
+        self.ctx = ctx
+        self.n, self.width = n, width
+        self._m = _P()
+        ctx.check(_lib.sgtt_mlp_create(ctx._c, n, width, capacity, seed, C.byref(self._m)))
+
+    def size(self):
+        npar, npairs = C.c_long(), C.c_long()
+        _lib.sgtt_mlp_size(self._m, C.byref(npar), C.byref(npairs))
+        return npar.value, npairs.value
+
+    def split(self, flat):
+        """flat parameter vector -> dict W1, b1, W2, b2, W3, b3 (views)."""
+        n, w = self.n, self.width
+        out, o = {}, 0
+        for k, shp in (("W1", (w, n)), ("b1", (w,)), ("W2", (w, w)), ("b2", (w,)), ("W3", (n, w)), ("b3", (n,))):
+            sz = int(np.prod(shp))
+            out[k] = flat[o:o + sz].reshape(shp)
+            o += sz
+        return out
+
+    def flatten(self, p):
+        return np.concatenate([np.asarray(p[k], dtype=np.float32).ravel()
+                               for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+    def set_params(self, p):
+        flat = np.ascontiguousarray(self.flatten(p) if isinstance(p, dict) else p, dtype=np.float32)
+        self.ctx.check(_lib.sgtt_mlp_set_params(self._m, flat.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def get_params(self):
+        flat = np.zeros(self.size()[0], dtype=np.float32)
+        self.ctx.check(_lib.sgtt_mlp_get_params(self._m, flat.ctypes.data_as(C.POINTER(C.c_float))))
+        return self.split(flat)
+
+    def forward(self, X):
+        """X: (n, B) -> (n, B) float32."""
+        Xc = np.ascontiguousarray(np.asarray(X, dtype=np.float32).T)
+        B = Xc.shape[0]
+        Y = np.zeros_like(Xc)
+        self.ctx.check(_lib.sgtt_mlp_forward(self._m, Xc.ctypes.data_as(C.POINTER(C.c_float)), B,
+                                             Y.ctypes.data_as(C.POINTER(C.c_float))))
+        return Y.T
+
+    def loss_grad(self, X, T):
+        Xc = np.ascontiguousarray(np.asarray(X, dtype=np.float32).T)
+        Tc = np.ascontiguousarray(np.asarray(T, dtype=np.float32).T)
+        g = np.zeros(self.size()[0], dtype=np.float32)
+        L = C.c_double()
+        self.ctx.check(_lib.sgtt_mlp_loss_grad(self._m, Xc.ctypes.data_as(C.POINTER(C.c_float)),
+                                               Tc.ctypes.data_as(C.POINTER(C.c_float)), Xc.shape[0], C.byref(L),
+                                               g.ctypes.data_as(C.POINTER(C.c_float))))
+        return L.value, self.split(g)
+
+    def train(self, steps, batch=64, lr=1e-3, seed=0):
+        losses = np.zeros(max(steps, 1))
+        self.ctx.check(_lib.sgtt_mlp_train(self._m, steps, batch, lr, seed,
+                                           losses.ctypes.data_as(C.POINTER(C.c_double))))
+        return losses[:steps]
+
+    def add_pairs(self, X, T):
+        """Append columns of X, T ((n, k) each) as training pairs; returns how many fit."""
+        Xc = np.ascontiguousarray(np.asarray(X, dtype=np.float32).T)
+        Tc = np.ascontiguousarray(np.asarray(T, dtype=np.float32).T)
+        k = C.c_long()
+        self.ctx.check(_lib.sgtt_mlp_add_pairs(self._m, Xc.ctypes.data_as(C.POINTER(C.c_float)),
+                                               Tc.ctypes.data_as(C.POINTER(C.c_float)), Xc.shape[0], C.byref(k)))
+        return k.value
+
+    def collect(self, system, on=True):
+        self.ctx.check(_lib.sgtt_mlp_collect(system._s, self._m if on else None))
+
+    def attach(self, system, on=True):
+        self.ctx.check(_lib.sgtt_mlp_attach(system._s, self._m if on else None))
+
+    def __del__(self):
+        if getattr(self, "_m", None) and _lib is not None:
+            _lib.sgtt_mlp_destroy(self._m)
+            self._m = None
 
 
 def solve_batched(systems, bs, xs, **opts):

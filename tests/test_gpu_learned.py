@@ -1,0 +1,117 @@
+"""GPU parity of the learned correction of the mean spatial solve: the
+hand-written forward and backward kernels against the FP64 oracle (same
+FP16-rounded weights), training on pairs the solver records from its own
+exact mean solves, and solves with the network in the preconditioner (which
+must still reach the exact-residual target; iteration counts are reported
+against the plain preconditioner)."""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from oracle import tt
+from synthetic_inputs import CONFIGS
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sg():
+    from paper_1906_06785_amd import sgtt
+    return sgtt
+
+
+@pytest.fixture(scope="module")
+def ctx(sg):
+    return sg.Context(0)
+
+
+def _params(n, w, seed):
+    p = omlp.init_params(n, w, seed)
+    g = np.random.default_rng(seed + 7)
+    p["b1"] = (0.1 * g.standard_normal(w)).astype(np.float32).astype(np.float64)
+    p["b2"] = (0.1 * g.standard_normal(w)).astype(np.float32).astype(np.float64)
+    p["b3"] = (0.1 * g.standard_normal(n)).astype(np.float32).astype(np.float64)
+    return p
+
+
+@pytest.mark.parametrize("n,w,B", [(40, 16, 7), (70, 48, 37), (130, 96, 65)])
+def test_mlp_forward_and_gradients_match_oracle(sg, ctx, n, w, B):
+    _flush(f"mlp n={n} w={w} B={B}")
+    p = _params(n, w, n)
+    net = sg.Mlp(ctx, n, w, 0, 0)
+    net.set_params(p)
+    g = np.random.default_rng(n + 1)
+    X = g.standard_normal((n, B)).astype(np.float32).astype(np.float64)
+    T = g.standard_normal((n, B)).astype(np.float32).astype(np.float64)
+    Y = net.forward(X)
+    Yo, _ = omlp.forward(p, X)
+    assert np.linalg.norm(Y - Yo) <= 1e-5 * np.linalg.norm(Yo)
+    L, gr = net.loss_grad(X, T)
+    Lo, go = omlp.grads(p, X, T)
+    assert abs(L - Lo) <= 1e-5 * Lo
+    for k in go:
+        assert np.linalg.norm(gr[k] - go[k]) <= 1e-4 * np.linalg.norm(go[k]), k
+
+
+def test_mlp_adam_steps_match_oracle(sg, ctx):
+    # full-batch Adam from zero state, three steps, against the oracle's
+    # update on its own FP64 gradients of the FP16-rounded working weights
+    _flush("mlp adam")
+    n, w, B, lr = 40, 16, 9, 1e-3
+    p = _params(n, w, 3)
+    net = sg.Mlp(ctx, n, w, B, 0)
+    net.set_params(p)
+    g = np.random.default_rng(4)
+    X = g.standard_normal((n, B)).astype(np.float32).astype(np.float64)
+    T = g.standard_normal((n, B)).astype(np.float32).astype(np.float64)
+    assert net.add_pairs(X, T) == B
+    losses = net.train(3, batch=B, lr=lr)
+    master = {k: v.copy() for k, v in p.items()}
+    work = {k: v.copy() for k, v in p.items()}
+    state = {k: [np.zeros_like(v), np.zeros_like(v)] for k, v in p.items()}
+    for t in range(1, 4):
+        L, gr = omlp.grads(work, X, T)
+        assert abs(losses[t - 1] - L) <= 1e-5 * L
+        for k in p:
+            master[k], w16 = omlp.adam_step(master[k], gr[k], state[k], lr, t)
+            work[k] = w16 if k.startswith("W") else master[k]
+    got = net.get_params()
+    for k in p:
+        # FP32 masters vs FP64: agreement to FP32 resolution of the weights
+        # (each step moves a parameter by about lr, so a wrong update rule
+        # shows at that scale); gradients near Adam's eps may flip
+        d = np.abs(got[k] - master[k])
+        assert np.mean(d <= 1e-4 * lr + 4e-7 * np.abs(master[k])) >= 0.98, k
+        assert d.max() <= 6 * lr + 1e-6, k
+
+
+def test_learned_mean_solve_c1(sg, ctx):
+    _flush("learned mean solve c1")
+    cfg = CONFIGS["C1"]
+    S = sg.System(ctx, cfg)
+    b = S.rhs()
+    ns = S.info.n_s
+    x0, st0, rc0 = S.solve(b, S.pair(64, 1024), restart=20, relax=1)
+    assert rc0 == 0
+    net = sg.Mlp(ctx, ns, 256, 20000, 1)
+    net.collect(S)
+    S.solve(b, S.pair(64, 1024), restart=20, relax=1)
+    net.collect(S, False)
+    npar, npairs = net.size()
+    assert npairs > 1000
+    losses = net.train(600, batch=128, lr=1e-3, seed=2)
+    print("pairs", npairs, "loss first", losses[:5].mean(), "last", losses[-20:].mean(), flush=True)
+    # an output of zero is the plain Jacobi step: relative error 1
+    assert losses[-20:].mean() < 0.5
+    net.attach(S)
+    x1, st1, rc1 = S.solve(b, S.pair(64, 1024), restart=20, relax=1)
+    print("plain", st0, flush=True)
+    print("learned", st1, flush=True)
+    assert rc1 == 0 and st1["rel_residual"] <= 1e-8
+    assert st1["learned_calls"] > 0
+    got, want = tt.pair_full(x1.cores()), tt.pair_full(x0.cores())
+    assert np.linalg.norm(got - want) <= 1e-7 * np.linalg.norm(want)
