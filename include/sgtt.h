@@ -112,6 +112,12 @@ typedef struct {
                           outer iteration, truncation eigen-solves, Hessenberg
                           least squares and the exact residual stay FP64, so
                           the refinement still reaches tol                   */
+  double inner_rhs_eps;    /* truncation of the inner solve's right-hand side
+                              (0: inner_eps); the inner solve only has to
+                              reach inner_tol                              */
+  double cycle_rhs_factor; /* a refinement cycle's right-hand side r_j is
+                              compressed at max(eps_krylov, min(1e-3,
+                              factor tol ||b|| / ||r_j||)); 0 means 0.05    */
 } sgtt_solve_opts;
 
 typedef struct {

@@ -6,6 +6,7 @@
 #include <climits>
 #include <cmath>
 #include <mutex>
+#include <stdexcept>
 #include <type_traits>
 #include <vector>
 #include <unordered_map>
@@ -127,14 +128,15 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
 // ------------------------------------------------------------------ GEMM
 constexpr int TM = 64, TN = 64, TK = 16;
+constexpr int LQ = TM * TK / 256;   // staged elements per thread and operand
 
 // Tiled FP64 GEMM: global -> register -> LDS staging of 64 x 16 (A) and
 // 16 x 64 (B) slices, 4 elements per thread.
 __device__ __forceinline__ void gemm_load_tile(const double* __restrict__ A, long sAi, long sAk, int m, const double* __restrict__ B,
                                                long sBk, long sBj, int n, long kb, int i0, int j0, long kk, bool a_kfast,
-                                               bool b_kfast, int tid, double ra[4], double rb[4]) {
+                                               bool b_kfast, int tid, double ra[LQ], double rb[LQ]) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < LQ; ++q) {
     int e = tid + 256 * q;
     int ii, kx;
     if (a_kfast) { kx = e % TK; ii = e / TK; } else { ii = e % TM; kx = e / TM; }
@@ -187,11 +189,11 @@ __device__ __forceinline__ void gemm_core(int m, int n, long kb, double alpha, c
     for (int c = 0; c < 2; ++c) acc[r][c] = acc_t{0, 0, 0, 0};
   const bool a_kfast = (sAk == 1);
   const bool b_kfast = (sBk == 1);
-  double ra[4], rb[4];
+  double ra[LQ], rb[LQ];
   if (kb > 0) gemm_load_tile(A, sAi, sAk, m, B, sBk, sBj, n, kb, i0, j0, 0, a_kfast, b_kfast, tid, ra, rb);
   for (long kk = 0; kk < kb; kk += TK) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < LQ; ++q) {
       int e = tid + 256 * q;
       int ii, kx;
       if (a_kfast) { kx = e % TK; ii = e / TK; } else { ii = e % TM; kx = e / TM; }
@@ -203,10 +205,12 @@ __device__ __forceinline__ void gemm_core(int m, int n, long kb, double alpha, c
     __syncthreads();
     if (kk + TK < kb) gemm_load_tile(A, sAi, sAk, m, B, sBk, sBj, n, kb, i0, j0, kk + TK, a_kfast, b_kfast, tid, ra, rb);
     if constexpr (PREC == GP_BF16) {
+#pragma unroll
+      for (int kh = 0; kh < TK / 16; ++kh) {
       bf16x4 a0, a1, b0, b1;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int kr = 4 * lk + j;
+        const int kr = kh * 16 + 4 * lk + j;
         a0[j] = to_bf16(As[kr][wr + lr]);
         a1[j] = to_bf16(As[kr][wr + 16 + lr]);
         b0[j] = to_bf16(Bs[kr][wc + lr]);
@@ -216,6 +220,7 @@ __device__ __forceinline__ void gemm_core(int m, int n, long kb, double alpha, c
       acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
+      }
     } else {
 #pragma unroll
       for (int kq = 0; kq < TK / 4; ++kq) {
@@ -905,47 +910,94 @@ __global__ __launch_bounds__(1024) void k_pc_init(int N, const double* __restric
 // already subtracted): column t of the panel Lp (N x nsteps, column-major,
 // ld N) = (S[:, p] - Lp[:, :t] Lp[p, :t]^T) / sqrt(d[p]).  Stops when the
 // residual trace reaches the target or the largest pivot is numerically 0.
-// out[0] = pivots taken, out[1] = 1 if finished.
+// out[0] = pivots taken, out[1] = 1 if finished.  Each thread keeps the
+// Schur diagonal of its rows (i = tid + q * blockDim, q < PC_Q) in
+// registers; one combined reduction per pivot yields both the next pivot
+// and the residual trace (three workgroup barriers per pivot).
+constexpr int PC_Q = 8;
 __global__ __launch_bounds__(1024) void k_pc_panel(int N, const double* __restrict__ S, double* __restrict__ d,
                                                    double* __restrict__ Lp, int* __restrict__ piv, int nsteps,
                                                    double* state, int* out, double* kept) {
-  __shared__ double shv[32];
-  __shared__ int shi[32];
+  __shared__ double shv[16], shs[16];
+  __shared__ int shi[16];
   __shared__ double lp[64];
+  __shared__ double s_bv, s_res;
+  __shared__ int s_p;
   const int tid = threadIdx.x, nth = blockDim.x;
-  double resid = state[0];
+  const int wv = tid / WAVE, ln = tid % WAVE, nwv = nth / WAVE;
+  double dl[PC_Q];
+#pragma unroll
+  for (int q = 0; q < PC_Q; ++q) {
+    const int i = tid + q * nth;
+    dl[q] = (i < N) ? d[i] : 0.0;
+  }
   const double target = state[1], zero_thr = state[2];
+  double resid = state[0];
   int t = 0, done = 0;
-  for (; t < nsteps; ++t) {
-    if (resid <= target) { done = 1; break; }
-    double mv = -1.0;
+  for (;; ++t) {
+    // combined block reduction: argmax of the Schur diagonal and its sum
+    double mv = -1.0, sm = 0.0;
     int mi = 0;
-    for (int i = tid; i < N; i += nth)
-      if (d[i] > mv) { mv = d[i]; mi = i; }
-    double bv;
-    int bi;
-    argmax_block(mv, mi, shv, shi, bv, bi);
+#pragma unroll
+    for (int q = 0; q < PC_Q; ++q) {
+      const int i = tid + q * nth;
+      if (i < N) {
+        sm += dl[q];
+        if (dl[q] > mv) { mv = dl[q]; mi = i; }
+      }
+    }
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      const double ov = __shfl_down(mv, o, WAVE);
+      const int oi = __shfl_down(mi, o, WAVE);
+      sm += __shfl_down(sm, o, WAVE);
+      if (ov > mv || (ov == mv && oi < mi)) { mv = ov; mi = oi; }
+    }
+    if (ln == 0) {
+      shv[wv] = mv;
+      shi[wv] = mi;
+      shs[wv] = sm;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double bv = shv[0], tot = shs[0];
+      int bi = shi[0];
+      for (int q = 1; q < nwv; ++q) {
+        tot += shs[q];
+        if (shv[q] > bv || (shv[q] == bv && shi[q] < bi)) { bv = shv[q]; bi = shi[q]; }
+      }
+      s_bv = bv;
+      s_p = bi;
+      s_res = tot;
+    }
+    __syncthreads();
+    const double bv = s_bv;
+    const int p = s_p;
+    if (t > 0) resid = s_res;   // the first pass keeps the trace handed in
+    if (resid <= target) { done = 1; break; }
+    if (t == nsteps) break;
     if (bv <= zero_thr || bv <= 0.0) { done = 1; break; }
-    const int p = bi;
     if (tid < t) lp[tid] = Lp[(long)tid * N + p];
     if (tid == 0) piv[t] = p;
     __syncthreads();
     const double l = sqrt(bv);
-    for (int i = tid; i < N; i += nth) {
+#pragma unroll
+    for (int q = 0; q < PC_Q; ++q) {
+      const int i = tid + q * nth;
+      if (i >= N) continue;
       double v = S[(long)p * N + i];   // S is symmetric: row p read coalesced
       for (int u = 0; u < t; ++u) v -= Lp[(long)u * N + i] * lp[u];
       // rows already eliminated (zero Schur diagonal) have a zero Schur row
-      double li = (i == p) ? l : (d[i] > 0.0 ? v / l : 0.0);
+      const double li = (i == p) ? l : (dl[q] > 0.0 ? v / l : 0.0);
       Lp[(long)t * N + i] = li;
-      double dd = d[i] - li * li;
-      d[i] = (i == p || dd < 0.0) ? 0.0 : dd;
+      const double dd = dl[q] - li * li;
+      dl[q] = (i == p || dd < 0.0) ? 0.0 : dd;
     }
-    __syncthreads();
-    double rr = 0.0;
-    for (int i = tid; i < N; i += nth) rr += d[i];
-    resid = block_sum(rr, shv);
   }
-  if (resid <= target) done = 1;
+#pragma unroll
+  for (int q = 0; q < PC_Q; ++q) {
+    const int i = tid + q * nth;
+    if (i < N) d[i] = dl[q];
+  }
   if (tid == 0) {
     state[0] = resid;
     out[0] = t;
@@ -1408,6 +1460,7 @@ void pc_init(hipStream_t s, int N, const double* S, double eps, const double* no
 
 void pc_panel(hipStream_t s, int N, const double* S, double* d, double* Lp, int* piv, int nsteps, double* state,
               int* out, double* kept) {
+  if (N > PC_Q * 1024 || nsteps > 64) throw std::runtime_error("pivoted Cholesky panel: size out of range");
   ProfScope ps(KC_TRUNC, s, 8.0 * (double)N * nsteps * 2, (double)N * nsteps * nsteps);
   hipLaunchKernelGGL(k_pc_panel, dim3(1), dim3(1024), 0, s, N, S, d, Lp, piv, nsteps, state, out, kept);
 }

@@ -344,7 +344,7 @@ struct GramCache {
 // keep eps.  relax = false is the fixed truncation of Alg. 4.2.
 Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int maxit, double* dscal, int& iters,
                    double& relres, SolveCounters* cnt, const char* tag, bool explicit_res, bool relax = false,
-                   double eps_max = 1e-2) {
+                   double eps_max = 1e-2, double rhs_eps = 0.0) {
   const int ld = maxit + 1;
   const int nc = b.nc;
   const bool inner = std::strcmp(tag, "inner") == 0;
@@ -359,7 +359,7 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
   double* sc = y + maxit;                     // 16 scalars
   fill(c.s, H, (long)ld * maxit, 0.0);
   // line 1: s_0 = T(b), beta = ||s_0||, v_1 = s_0 / beta
-  Vec s = vec_round(c, b, eps, sc + 0, sc + 2);
+  Vec s = vec_round(c, b, rhs_eps > eps ? rhs_eps : eps, sc + 0, sc + 2);
   scalar_op(c.s, 0, sc + 0, nc > 1 ? sc + 1 : nullptr, sc + 4);   // ||b||
   scalar_op(c.s, 0, sc + 2, nc > 1 ? sc + 3 : nullptr, sc + 5);   // beta
   SGTT_HIP(hipMemcpyAsync(c.hdbl, sc + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, c.s));
@@ -530,7 +530,7 @@ struct InnerSpace : Space {
 };
 
 struct PrecOpts {
-  double eps = 1e-6, inner_tol = 1e-1, inner_eps = 1e-3;
+  double eps = 1e-6, inner_tol = 1e-1, inner_eps = 1e-3, inner_rhs_eps = 0.0;
   int inner_maxit = 20;
   bool inner_explicit = false;
   int precision = GP_F64;   // dense products of the inner solve
@@ -562,7 +562,7 @@ Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCoun
   icnt.verbose = cnt ? cnt->verbose : 0;
   GemmPrecisionScope gp(po.precision);
   Vec v = lowrank_fgmres(c, isp, rhs, po.inner_tol, po.inner_eps, po.inner_maxit, S.dsc + 16384, its, rr, &icnt,
-                         "inner", po.inner_explicit);
+                         "inner", po.inner_explicit, false, 1e-2, po.inner_rhs_eps);
   if (cnt) cnt->inner += its;
   // fallback: two inner solves that miss their tolerance with the learned
   // mean solve switch the rest of this solve back to the exact one
@@ -671,6 +671,8 @@ PrecOpts prec_opts(const sgtt_solve_opts* o) {
     p.inner_maxit = o->inner_maxit;
     p.inner_explicit = o->inner_explicit != 0;
     if (o->precision < 0 || o->precision > 2) throw SgttError(-1, "invalid precision option");
+    if (o->inner_rhs_eps < 0.0 || o->cycle_rhs_factor < 0.0) throw SgttError(-1, "invalid truncation option");
+    p.inner_rhs_eps = o->inner_rhs_eps;
     p.precision = o->precision;
   }
   return p;
@@ -691,6 +693,8 @@ sgtt_solve_opts default_opts() {
   o.inner_explicit = 0;
   o.relax = 0;
   o.precision = 0;
+  o.inner_rhs_eps = 0.0;
+  o.cycle_rhs_factor = 0.0;
   return o;
 }
 
@@ -1243,7 +1247,8 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
     double eps_r = o.eps_krylov;
     rel = full_residual(*S, bv, z, nullptr, nullptr, 0.0, &bn2);
     if (rel > o.tol && cyc + 1 < o.max_cycles) {
-      eps_r = std::max(o.eps_krylov, std::min(1e-3, 0.05 * o.tol / std::max(rel, 1e-300)));
+      const double fac = o.cycle_rhs_factor > 0.0 ? o.cycle_rhs_factor : 0.05;
+      eps_r = std::max(o.eps_krylov, std::min(1e-3, fac * o.tol / std::max(rel, 1e-300)));
       full_residual(*S, bv, z, nullptr, &rnext, eps_r, &bn2);
     }
     if (o.verbose) fprintf(stderr, "[sgtt] cycle %d: outer its %d, exact rel residual %.3e\n", cyc, its, rel);

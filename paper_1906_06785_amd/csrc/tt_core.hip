@@ -371,11 +371,11 @@ TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_no
   {
     double* Lw = c.scratch2((size_t)N2 * kmax2 + N2 + 64);
     trunc_eig(c.s, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw, dk + 2, dkept2, dk + 3, std::min(N2, R2), 1);
+    SGTT_HIP(hipMemcpyAsync(c.hint, dk + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, c.s));
+    c.sync();
+    h[2] = c.hint[0];
+    h[3] = c.hint[1];
   }
-  SGTT_HIP(hipMemcpyAsync(c.hint, dk + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, c.s));
-  c.sync();
-  h[2] = c.hint[0];
-  h[3] = c.hint[1];
   if (h[3] == 1) throw SgttError(-4, "TT rank capacity exceeded (bond 2)");
   Skeleton sk;
   if (h[3] == 2)

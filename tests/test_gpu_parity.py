@@ -82,16 +82,17 @@ def test_round_error_bound_and_ranks(sg, ctx, n, ranks, eps):
     assert np.abs(L.T @ L - np.eye(buf.r2)).max() < 1e-10
 
 
-@pytest.mark.parametrize("eps", [1e-2, 1e-3])
-def test_round_large_rank_second_bond(sg, ctx, eps):
-    # second-bond rank above 96: blocked pivoted Cholesky + skeleton path.
-    # The error bound of eq. 4.6 still holds; the rank is close to (and not
-    # below) the optimal one of the SVD truncation at the same tolerance.
-    _flush(f"round large rank eps={eps}")
-    G = random_tt_cores(12, 40, 3000, 12, 480, seed=12)
-    G = (G[0], G[1], G[2] * np.exp(-0.03 * np.arange(480))[:, None])
+@pytest.mark.parametrize("n1,r2,eps", [(12, 480, 1e-2), (12, 480, 1e-3), (20, 300, 1e-3)])
+def test_round_large_rank_second_bond(sg, ctx, n1, r2, eps):
+    # second-bond rank above 96: blocked pivoted Cholesky + skeleton path
+    # (n1 = 20 makes the second Gram larger than 512, which takes that path
+    # directly).  The error bound of eq. 4.6 still holds; the rank is close
+    # to (and not below) the optimal one of the SVD truncation.
+    _flush(f"round large rank n1={n1} r2={r2} eps={eps}")
+    G = random_tt_cores(n1, 40, 3000, n1, r2, seed=12)
+    G = (G[0], G[1], G[2] * np.exp(-0.03 * np.arange(r2))[:, None])
     X = tt.full(G)
-    buf = sg.TTBuf(12, 40, 3000, 16, 480).set_cores(*G)
+    buf = sg.TTBuf(n1, 40, 3000, n1 + 4, r2).set_cores(*G)
     ctx.round(buf, eps)
     Y = ctx.expand(buf).cpu().numpy()
     nrm = np.linalg.norm(X)
