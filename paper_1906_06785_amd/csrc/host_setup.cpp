@@ -9,6 +9,9 @@
 #include <cstring>
 #include <stdexcept>
 #include <tuple>
+#include <atomic>
+#include <thread>
+#include <vector>
 
 namespace sgtt {
 
@@ -574,16 +577,35 @@ void gemm_cm(int m, int n, int k, const double* A, const double* B, double* C, d
 }
 }  // namespace
 
-void blocktri_factor(const Csr& pat, const double* vals, const std::vector<int>& blocks, BlockTri& bt,
-                     std::string& err) {
+namespace {
+// run f(i) for i < n on up to 16 host threads
+template <class F>
+void parallel_for(int n, F&& f) {
+  const int nt = std::max(1, std::min<int>({n, 16, (int)std::thread::hardware_concurrency()}));
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int> next(0);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&]() {
+      for (int i = next++; i < n; i = next++) f(i);
+    });
+  for (auto& t : th) t.join();
+}
+}  // namespace
+
+void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& blocks, BcrFactor& f,
+                std::string& err) {
   const int n = pat.nrows, nb = (int)blocks.size() - 1;
-  bt.n = n;
-  bt.nblk = nb;
-  bt.start = blocks;
+  f = BcrFactor();
+  f.n = n;
+  f.nblk = nb;
+  f.start = blocks;
   std::vector<int> blk(n);
-  bt.maxbs = 0;
   for (int b = 0; b < nb; ++b) {
-    bt.maxbs = std::max(bt.maxbs, blocks[b + 1] - blocks[b]);
+    f.maxbs = std::max(f.maxbs, blocks[b + 1] - blocks[b]);
     for (int i = blocks[b]; i < blocks[b + 1]; ++i) blk[i] = b;
   }
   for (int i = 0; i < n; ++i)
@@ -593,18 +615,6 @@ void blocktri_factor(const Csr& pat, const double* vals, const std::vector<int>&
         return;
       }
   auto bs = [&](int b) { return blocks[b + 1] - blocks[b]; };
-  bt.off_sinv.assign(nb, 0);
-  bt.off_p.assign(nb, -1);
-  bt.off_q.assign(nb, -1);
-  int64_t off = 0;
-  for (int b = 0; b < nb; ++b) {
-    bt.off_sinv[b] = off;
-    off += (int64_t)bs(b) * bs(b);
-    if (b > 0) { bt.off_p[b] = off; off += (int64_t)bs(b) * bs(b - 1); }
-    if (b < nb - 1) { bt.off_q[b] = off; off += (int64_t)bs(b) * bs(b + 1); }
-  }
-  bt.data.assign(off, 0.0);
-  // dense blocks: D_b, L_b (b, b-1), U_b (b, b+1), column-major
   auto extract = [&](int b, int c, std::vector<double>& out) {
     int r0 = blocks[b], nr = bs(b), c0 = blocks[c], nc = bs(c);
     out.assign((size_t)nr * nc, 0.0);
@@ -614,27 +624,160 @@ void blocktri_factor(const Csr& pat, const double* vals, const std::vector<int>&
         if (j >= 0 && j < nc) out[(size_t)j * nr + i] += vals[t];
       }
   };
-  std::vector<double> D, Lb, Ub, prevUb, tmp;
+  // level-l system: positions p -> original block ob[p], dense D, L, U
+  std::vector<int> ob(nb);
+  std::vector<std::vector<double>> D(nb), L(nb), U(nb);
   for (int b = 0; b < nb; ++b) {
-    extract(b, b, D);
-    if (b > 0) {
-      // S'_b = D_b - L_b Sinv_{b-1} U_{b-1} = D_b - L_b Q_{b-1}
-      extract(b, b - 1, Lb);
-      const double* Qprev = bt.data.data() + bt.off_q[b - 1];
-      gemm_cm(bs(b), bs(b), bs(b - 1), Lb.data(), Qprev, D.data(), -1.0, 1.0);
+    ob[b] = b;
+    extract(b, b, D[b]);
+    if (b > 0) extract(b, b - 1, L[b]);
+    if (b + 1 < nb) extract(b, b + 1, U[b]);
+  }
+  auto put = [&](const std::vector<double>& m) {
+    int64_t off = (int64_t)f.data.size();
+    f.data.insert(f.data.end(), m.begin(), m.end());
+    return off;
+  };
+  struct Op {
+    int out, self, nterm, in[3];
+    int64_t off[3];
+    double coef[3];
+  };
+  std::vector<std::vector<Op>> fwd, bwd;
+  bool ok = true;
+  int np = nb;
+  while (np > 1) {
+    // odd positions: D^-1, D^-1 L, D^-1 U
+    const int nodd = np / 2, nev = (np + 1) / 2;
+    std::vector<std::vector<double>> Dinv(np), Bt(np), Dl(np);
+    std::vector<std::vector<double>> alpha(np), gamma(np);
+    std::atomic<bool> bad(false);
+    parallel_for(nodd, [&](int q) {
+      const int p = 2 * q + 1, b = ob[p];
+      Dinv[p] = D[p];
+      if (!dense_inverse(bs(b), Dinv[p].data())) {
+        bad = true;
+        return;
+      }
+      const int bl = ob[p - 1];
+      Bt[p].assign((size_t)bs(b) * bs(bl), 0.0);
+      gemm_cm(bs(b), bs(bl), bs(b), Dinv[p].data(), L[p].data(), Bt[p].data(), 1.0, 0.0);
+      if (p + 1 < np) {
+        const int br = ob[p + 1];
+        Dl[p].assign((size_t)bs(b) * bs(br), 0.0);
+        gemm_cm(bs(b), bs(br), bs(b), Dinv[p].data(), U[p].data(), Dl[p].data(), 1.0, 0.0);
+      }
+    });
+    if (bad) {
+      ok = false;
+      break;
     }
-    if (!dense_inverse(bs(b), D.data())) {
-      err = "singular diagonal block in block-tridiagonal factorization";
-      return;
+    // even positions: alpha = L D_{p-1}^-1, gamma = U D_{p+1}^-1, reduced blocks
+    std::vector<std::vector<double>> D2(nev), L2(nev), U2(nev);
+    parallel_for(nev, [&](int q) {
+      const int p = 2 * q, b = ob[p];
+      D2[q] = D[p];
+      if (p - 1 >= 0) {
+        const int bl = ob[p - 1];
+        alpha[p].assign((size_t)bs(b) * bs(bl), 0.0);
+        gemm_cm(bs(b), bs(bl), bs(bl), L[p].data(), Dinv[p - 1].data(), alpha[p].data(), 1.0, 0.0);
+        gemm_cm(bs(b), bs(b), bs(bl), alpha[p].data(), U[p - 1].data(), D2[q].data(), -1.0, 1.0);
+        if (p - 2 >= 0) {
+          L2[q].assign((size_t)bs(b) * bs(ob[p - 2]), 0.0);
+          gemm_cm(bs(b), bs(ob[p - 2]), bs(bl), alpha[p].data(), L[p - 1].data(), L2[q].data(), -1.0, 0.0);
+        }
+      }
+      if (p + 1 < np) {
+        const int br = ob[p + 1];
+        gamma[p].assign((size_t)bs(b) * bs(br), 0.0);
+        gemm_cm(bs(b), bs(br), bs(br), U[p].data(), Dinv[p + 1].data(), gamma[p].data(), 1.0, 0.0);
+        gemm_cm(bs(b), bs(b), bs(br), gamma[p].data(), L[p + 1].data(), D2[q].data(), -1.0, 1.0);
+        if (p + 2 < np) {
+          U2[q].assign((size_t)bs(b) * bs(ob[p + 2]), 0.0);
+          gemm_cm(bs(b), bs(ob[p + 2]), bs(br), gamma[p].data(), U[p + 1].data(), U2[q].data(), -1.0, 0.0);
+        }
+      }
+    });
+    std::vector<Op> fo, bo;
+    for (int p = 0; p < np; p += 2) {
+      Op o{};
+      o.out = ob[p];
+      o.self = 1;
+      if (p - 1 >= 0) {
+        o.in[o.nterm] = ob[p - 1];
+        o.off[o.nterm] = put(alpha[p]);
+        o.coef[o.nterm++] = -1.0;
+      }
+      if (p + 1 < np) {
+        o.in[o.nterm] = ob[p + 1];
+        o.off[o.nterm] = put(gamma[p]);
+        o.coef[o.nterm++] = -1.0;
+      }
+      fo.push_back(o);
     }
-    std::copy(D.begin(), D.end(), bt.data.begin() + bt.off_sinv[b]);
-    const double* Sinv = bt.data.data() + bt.off_sinv[b];
-    if (b > 0) gemm_cm(bs(b), bs(b - 1), bs(b), Sinv, Lb.data(), bt.data.data() + bt.off_p[b], 1.0, 0.0);
-    if (b < nb - 1) {
-      extract(b, b + 1, Ub);
-      gemm_cm(bs(b), bs(b + 1), bs(b), Sinv, Ub.data(), bt.data.data() + bt.off_q[b], 1.0, 0.0);
+    for (int p = 1; p < np; p += 2) {
+      Op o{};
+      o.out = ob[p];
+      o.self = 0;
+      o.in[o.nterm] = ob[p];
+      o.off[o.nterm] = put(Dinv[p]);
+      o.coef[o.nterm++] = 1.0;
+      o.in[o.nterm] = ob[p - 1];
+      o.off[o.nterm] = put(Bt[p]);
+      o.coef[o.nterm++] = -1.0;
+      if (p + 1 < np) {
+        o.in[o.nterm] = ob[p + 1];
+        o.off[o.nterm] = put(Dl[p]);
+        o.coef[o.nterm++] = -1.0;
+      }
+      bo.push_back(o);
+    }
+    fwd.push_back(fo);
+    bwd.push_back(bo);
+    // next level
+    std::vector<int> ob2(nev);
+    for (int q = 0; q < nev; ++q) ob2[q] = ob[2 * q];
+    ob.swap(ob2);
+    D.swap(D2);
+    L.swap(L2);
+    U.swap(U2);
+    np = nev;
+  }
+  if (ok) {
+    std::vector<double> Dt = D[0];
+    if (!dense_inverse(bs(ob[0]), Dt.data())) ok = false;
+    if (ok) {
+      Op o{};
+      o.out = ob[0];
+      o.self = 0;
+      o.in[0] = ob[0];
+      o.off[0] = put(Dt);
+      o.coef[0] = 1.0;
+      o.nterm = 1;
+      fwd.push_back({o});   // the top solve runs after the forward passes
     }
   }
+  if (!ok) {
+    err = "singular block in block cyclic reduction";
+    return;
+  }
+  auto emit = [&](const std::vector<Op>& ops) {
+    for (const Op& o : ops) {
+      f.op_out.push_back(o.out);
+      f.op_self.push_back(o.self);
+      f.op_nterm.push_back(o.nterm);
+      for (int t = 0; t < 3; ++t) {
+        f.op_in.push_back(t < o.nterm ? o.in[t] : 0);
+        f.op_off.push_back(t < o.nterm ? o.off[t] : 0);
+        f.op_coef.push_back(t < o.nterm ? o.coef[t] : 0.0);
+      }
+    }
+    f.pass_begin.push_back((int)f.op_out.size());
+  };
+  f.pass_begin.push_back(0);
+  for (const auto& ops : fwd) emit(ops);
+  for (int l = (int)bwd.size() - 1; l >= 0; --l) emit(bwd[l]);
 }
+
 
 }  // namespace sgtt

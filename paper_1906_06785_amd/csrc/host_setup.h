@@ -43,16 +43,6 @@ struct Mesh {
   int n_p() const { return (int)pI.size(); }
 };
 
-// Block-tridiagonal factorization for x = S^-1 b with the block LU recursion
-// S'_1 = D_1, S'_i = D_i - L_i S'_{i-1}^-1 U_{i-1}.  Stored per block i:
-// Sinv_i (bs_i x bs_i), P_i = Sinv_i L_i (bs_i x bs_{i-1}),
-// Q_i = Sinv_i U_i (bs_i x bs_{i+1}), all column-major.
-struct BlockTri {
-  int n = 0, nblk = 0, maxbs = 0;
-  std::vector<int> start;             // nblk + 1
-  std::vector<int64_t> off_sinv, off_p, off_q;   // offsets into data (doubles)
-  std::vector<double> data;
-};
 
 struct HostProblem {
   ProblemParams prm;
@@ -107,9 +97,28 @@ void reference_tables(double* out);
 // matrix S given by values on Kff (applied to both components).
 void lsc_middle_values(const HostProblem& hp, const double* Svals, double* out);
 
-// Block-tridiagonal factorization of a scalar matrix on pattern `pat` with
-// values `vals`, block partition `blocks` (nblk + 1 starts).
-void blocktri_factor(const Csr& pat, const double* vals, const std::vector<int>& blocks,
-                     BlockTri& bt, std::string& err);
+// Block cyclic reduction of the same block-tridiagonal matrix: level l
+// eliminates the odd positions of the level-l system (stride 2^l in the
+// original block numbering); the solve is a sequence of passes, each a set of
+// independent block operations
+//     y_out = [v_out] + sum_t coef_t M_t v_{in_t}      (M_t dense, col-major)
+// applied in place: forward passes (levels 0, 1, ...) update the even
+// positions' right-hand sides, one pass solves the last block, backward
+// passes (top level down) solve the odd positions.
+struct BcrFactor {
+  int n = 0, nblk = 0, maxbs = 0;
+  std::vector<int> start;              // nblk + 1
+  std::vector<int> op_out, op_self;    // per op: output block, 1 = add v_out
+  std::vector<int> op_nterm;           // per op: number of terms (<= 3)
+  std::vector<int> op_in;              // 3 per op
+  std::vector<int64_t> op_off;         // 3 per op: matrix offsets in data
+  std::vector<double> op_coef;         // 3 per op
+  std::vector<int> pass_begin;         // op ranges of the passes (npass + 1)
+  std::vector<double> data;
+};
+void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& blocks, BcrFactor& f,
+                std::string& err);
+
+
 
 }  // namespace sgtt

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <vector>
 
 namespace sgtt {
 
@@ -12,7 +13,7 @@ namespace sgtt {
 // algorithmic bytes / flops of each launch (what the operation must move and
 // compute, not what the hardware counted).  Kernel classes:
 enum KernelClass {
-  KC_GEMM = 0, KC_GEMM_PTR, KC_SPMM, KC_BT_DIAG, KC_BT_SWEEP, KC_TRUNC, KC_REDUCE, KC_OTHER, KC_GEMM_LOWP, KC_COUNT
+  KC_GEMM = 0, KC_GEMM_PTR, KC_SPMM, KC_BCR, KC_TRUNC, KC_REDUCE, KC_OTHER, KC_GEMM_LOWP, KC_COUNT
 };
 const char* kernel_class_name(int cls);
 void prof_enable(bool on);
@@ -158,16 +159,21 @@ void sg_convection_full(hipStream_t s, int nt, int nxi, int n_u, int ns, int nal
                         const int* hrow, const int* hl, const int* hk, const double* hv, const double* ref, double hh,
                         double sign, double* out);
 
-// Block-tridiagonal solve Y = A^-1 X on ncols columns of a node-major
-// matrix (row = space index, ld = ldx) with `ncomp` components stacked by
-// rows (component c occupies rows [c*n, (c+1)*n)).  Blocks up to 256 rows.
-// Stage 1 forms Y_b = Sinv_b X_b for all blocks in parallel; stage 2 and 3
-// are the forward (P_b) and backward (Q_b) sweeps.  X and Y may alias.
-// mat_doubles (host, 3): total doubles of the Sinv, P and Q blocks (for the
-// algorithmic byte count of the profiler).
-void blocktri_solve(hipStream_t s, int n, int nblk, int maxbs, const int* start, const long* off_sinv,
-                    const long* off_p, const long* off_q, const double* data, int ncomp, double* X, int ldx,
-                    int ncols, double* Y, const double* mat_doubles);
+// Block cyclic reduction solve (factor built on the host): device copies of
+// the op lists and block data; pass_begin stays on the host.
+struct BcrDev {
+  int n = 0, nblk = 0, maxbs = 0, npass = 0;
+  double ndata = 0;                 // doubles of block data (for the profiler)
+  std::vector<int> pass_begin;      // host: npass + 1
+  int *start = nullptr, *op_out = nullptr, *op_self = nullptr, *op_nterm = nullptr, *op_in = nullptr;
+  long* op_off = nullptr;
+  double *op_coef = nullptr, *data = nullptr;
+};
+// In place: X (rows of one component, row stride ld; ncomp components at
+// X + z * n * ld) <- A^-1 X for ncols columns.
+void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* X, long ld, int ncols);
+
+
 
 // Givens least squares for the (k+1) x k Hessenberg H (column-major, ld),
 // y = argmin || beta e1 - H y ||; resid = |final rotated rhs entry|.

@@ -63,7 +63,7 @@ struct ProfScope {
 }  // namespace
 
 const char* kernel_class_name(int cls) {
-  static const char* names[] = {"k_gemm", "k_gemm_ptr", "k_spmm", "k_bt_diag", "k_bt_sweep", "k_trunc_eig",
+  static const char* names[] = {"k_gemm", "k_gemm_ptr", "k_spmm", "k_bcr_pass", "k_trunc_eig",
                                 "k_reduce_partials", "other", "k_gemm_lowp"};
   return (cls >= 0 && cls < KC_COUNT) ? names[cls] : "?";
 }
@@ -881,6 +881,66 @@ __global__ __launch_bounds__(64) void k_sg_convection(int nxi, int n_u, int ns, 
   }
 }
 
+// ------------------------------------------------------------------ block cyclic reduction
+constexpr int BCR_CB = 32, BCR_MAXBS = 256;
+
+// One pass of a block cyclic reduction solve, in place on X (rows = scalar
+// unknowns of one component, row stride ld; component z at X + z*comp_rows*ld):
+// workgroup (op, column tile, component) sets block out = [X_out] +
+// sum_t coef_t M_t X_{in_t}.  The ops of one pass write distinct blocks and
+// read only blocks that the pass does not write (or their own block, which
+// is staged in LDS before any write).
+__global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict__ start, const int* __restrict__ op_out,
+                                                  const int* __restrict__ op_self, const int* __restrict__ op_nterm,
+                                                  const int* __restrict__ op_in, const long* __restrict__ op_off,
+                                                  const double* __restrict__ op_coef, const double* __restrict__ data,
+                                                  double* __restrict__ X, long ld, int ncols, long comp_rows) {
+  __shared__ double vin[BCR_MAXBS][BCR_CB];
+  const int o = op0 + blockIdx.x;
+  const int c0 = blockIdx.y * BCR_CB;
+  const int cn = min(BCR_CB, ncols - c0);
+  double* Xc = X + (long)blockIdx.z * comp_rows * ld;
+  const int ob = op_out[o];
+  const int r0 = start[ob], bo = start[ob + 1] - r0;
+  const int r = threadIdx.x;
+  double acc[BCR_CB];
+#pragma unroll
+  for (int c = 0; c < BCR_CB; ++c) acc[c] = 0.0;
+  if (op_self[o] && r < bo) {
+    const double* xr = Xc + (long)(r0 + r) * ld + c0;
+#pragma unroll
+    for (int c = 0; c < BCR_CB; ++c)
+      if (c < cn) acc[c] = xr[c];
+  }
+  const int nterm = op_nterm[o];
+  for (int t = 0; t < nterm; ++t) {
+    const int ib = op_in[3 * o + t];
+    const int i0 = start[ib], bi = start[ib + 1] - i0;
+    const double* M = data + op_off[3 * o + t];
+    const double coef = op_coef[3 * o + t];
+    __syncthreads();
+    for (int e = threadIdx.x; e < bi * BCR_CB; e += blockDim.x) {
+      const int k = e / BCR_CB, c = e % BCR_CB;
+      vin[k][c] = (c < cn) ? Xc[(long)(i0 + k) * ld + c0 + c] : 0.0;
+    }
+    __syncthreads();
+    if (r < bo) {
+      for (int k = 0; k < bi; ++k) {
+        const double m = coef * M[(long)k * bo + r];
+#pragma unroll
+        for (int c = 0; c < BCR_CB; ++c) acc[c] = fma(m, vin[k][c], acc[c]);
+      }
+    }
+  }
+  __syncthreads();
+  if (r < bo) {
+    double* xr = Xc + (long)(r0 + r) * ld + c0;
+#pragma unroll
+    for (int c = 0; c < BCR_CB; ++c)
+      if (c < cn) xr[c] = acc[c];
+  }
+}
+
 // ------------------------------------------------------------------ blocked pivoted Cholesky
 // state[0] = residual trace, [1] = target (delta^2), [2] = zero threshold,
 // [3] = trace
@@ -1053,142 +1113,6 @@ __global__ void k_gather_rows(int k, int cols, const double* __restrict__ in, lo
   if (e >= (long)k * cols) return;
   int a = e / cols, j = e % cols;
   out[(long)a * ld_out + j] = in[(long)piv[a] * ld_in + j];
-}
-
-// ------------------------------------------------------------------ block tridiagonal
-// Sequential sweeps of the block-LU solve after y_b = Sinv_b x_b has been
-// formed for every block in parallel:
-//   forward  (dir = 0): y_b <- y_b - P_b y_{b-1},   b = 1 .. nblk-1
-//   backward (dir = 1): x_b <- y_b - Q_b x_{b+1},   b = nblk-2 .. 0
-// One workgroup owns BT_CB columns of one component and walks the blocks in
-// order; the previous block's result stays in LDS.  Thread t handles row
-// (t % 128) + 128 i of the block for BT_CB/2 columns (half t / 128).
-constexpr int BT_CB = 16;
-constexpr int BT_MAXBS = 256;
-constexpr int BT_KU = 16;   // loads in flight per thread (prev rows beyond prevbs are zero)
-
-__global__ __launch_bounds__(256) void k_bt_sweep(int dir, int n, int nblk, const int* __restrict__ start,
-                                                  const long* __restrict__ off_m, const double* __restrict__ data,
-                                                  double* __restrict__ Y, int ldx, int ncols) {
-  __shared__ double prev[(BT_MAXBS + BT_KU) * BT_CB];
-  for (int e = threadIdx.x; e < (BT_MAXBS + BT_KU) * BT_CB; e += 256) prev[e] = 0.0;
-  __syncthreads();
-  const int comp = blockIdx.y;
-  const int c0 = blockIdx.x * BT_CB;
-  const int nc = min(BT_CB, ncols - c0);
-  double* Yc = Y + (long)comp * n * ldx + c0;
-  const int tid = threadIdx.x;
-  const int half = tid / 128, rr = tid % 128;
-  const int cb0 = half * (BT_CB / 2);
-  // initial block: b0 = 0 (forward) or nblk-1 (backward)
-  int b = dir == 0 ? 0 : nblk - 1;
-  int r0 = start[b], bs = start[b + 1] - r0;
-  for (int e = tid; e < bs * BT_CB; e += 256) {
-    int r = e / BT_CB, c = e % BT_CB;
-    prev[r * BT_CB + c] = (c < nc) ? Yc[(long)(r0 + r) * ldx + c] : 0.0;
-  }
-  __syncthreads();
-  int prevbs = bs;
-  for (int step = 1; step < nblk; ++step) {
-    b = dir == 0 ? step : nblk - 1 - step;
-    r0 = start[b];
-    bs = start[b + 1] - r0;
-    const double* M = data + off_m[b];   // bs x prevbs, column-major
-    double acc[2][BT_CB / 2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int c = 0; c < BT_CB / 2; ++c) acc[i][c] = 0.0;
-    // 16 independent loads in flight per thread per chunk of k
-    for (int k0 = 0; k0 < prevbs; k0 += BT_KU) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int r = rr + 128 * i;
-        if (r >= bs) continue;
-        double m[BT_KU];
-#pragma unroll
-        for (int u = 0; u < BT_KU; ++u) m[u] = (k0 + u < prevbs) ? M[(long)(k0 + u) * bs + r] : 0.0;
-#pragma unroll
-        for (int u = 0; u < BT_KU; ++u) {
-          const double* pk = prev + (k0 + u) * BT_CB + cb0;
-#pragma unroll
-          for (int c = 0; c < BT_CB / 2; ++c) acc[i][c] = fma(m[u], pk[c], acc[i][c]);
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      int r = rr + 128 * i;
-      if (r < bs) {
-#pragma unroll
-        for (int c = 0; c < BT_CB / 2; ++c) {
-          int cc = cb0 + c;
-          double v = (cc < nc) ? Yc[(long)(r0 + r) * ldx + cc] - acc[i][c] : 0.0;
-          prev[r * BT_CB + cc] = v;
-          if (cc < nc) Yc[(long)(r0 + r) * ldx + cc] = v;
-        }
-      }
-    }
-    __syncthreads();
-    prevbs = bs;
-  }
-}
-
-// parallel stage: Y_b = Sinv_b X_b for every block b (grid.x), component
-// (grid.y) and column chunk (grid.z); X and Y may alias.
-__global__ __launch_bounds__(256) void k_bt_diag(int n, const int* __restrict__ start, const long* __restrict__ off_sinv,
-                                                 const double* __restrict__ data, const double* X, double* Y, int ldx,
-                                                 int ncols) {
-  __shared__ double xb[(BT_MAXBS + BT_KU) * BT_CB];
-  for (int e = threadIdx.x; e < (BT_MAXBS + BT_KU) * BT_CB; e += 256) xb[e] = 0.0;
-  __syncthreads();
-  const int b = blockIdx.x, comp = blockIdx.y;
-  const int c0 = blockIdx.z * BT_CB;
-  const int nc = min(BT_CB, ncols - c0);
-  const int r0 = start[b], bs = start[b + 1] - r0;
-  const double* Xc = X + ((long)comp * n + r0) * ldx + c0;
-  double* Yc = Y + ((long)comp * n + r0) * ldx + c0;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < bs * BT_CB; e += 256) {
-    int r = e / BT_CB, c = e % BT_CB;
-    xb[r * BT_CB + c] = (c < nc) ? Xc[(long)r * ldx + c] : 0.0;
-  }
-  __syncthreads();
-  const int half = tid / 128, rr = tid % 128;
-  const int cb0 = half * (BT_CB / 2);
-  const double* M = data + off_sinv[b];
-  double acc[2][BT_CB / 2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int c = 0; c < BT_CB / 2; ++c) acc[i][c] = 0.0;
-  for (int k0 = 0; k0 < bs; k0 += BT_KU) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int r = rr + 128 * i;
-      if (r >= bs) continue;
-      double m[BT_KU];
-#pragma unroll
-      for (int u = 0; u < BT_KU; ++u) m[u] = (k0 + u < bs) ? M[(long)(k0 + u) * bs + r] : 0.0;
-#pragma unroll
-      for (int u = 0; u < BT_KU; ++u) {
-        const double* xk = xb + (k0 + u) * BT_CB + cb0;
-#pragma unroll
-        for (int c = 0; c < BT_CB / 2; ++c) acc[i][c] = fma(m[u], xk[c], acc[i][c]);
-      }
-    }
-  }
-  __syncthreads();   // X may alias Y: all reads of this block are done
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    int r = rr + 128 * i;
-    if (r < bs) {
-#pragma unroll
-      for (int c = 0; c < BT_CB / 2; ++c)
-        if (cb0 + c < nc) Yc[(long)r * ldx + cb0 + c] = acc[i][c];
-    }
-  }
 }
 
 // ------------------------------------------------------------------ small sequential kernels
@@ -1429,29 +1353,6 @@ void trunc_eig(hipStream_t s, int N, double* S, double eps, const double* normsq
                      k_out, kept_out, info, rank_bound, large_ok);
 }
 
-void blocktri_solve(hipStream_t s, int n, int nblk, int maxbs, const int* start, const long* off_sinv, const long* off_p,
-                    const long* off_q, const double* data, int ncomp, double* X, int ldx, int ncols, double* Y,
-                    const double* mat_doubles) {
-  if (ncols <= 0) return;
-  (void)maxbs;
-  // parallel stage: Y_b = Sinv_b X_b for all blocks and components
-  const double vec = 8.0 * 2.0 * ncomp * (double)n * ncols;   // read + write of the columns
-  {
-    ProfScope ps(KC_BT_DIAG, s, vec + 8.0 * mat_doubles[0], 2.0 * ncomp * ncols * mat_doubles[0]);
-    hipLaunchKernelGGL(k_bt_diag, dim3(nblk, ncomp, cdiv(ncols, BT_CB)), dim3(256), 0, s, n, start, off_sinv, data, X,
-                       Y, ldx, ncols);
-  }
-  // sequential sweeps
-  dim3 grid(cdiv(ncols, BT_CB), ncomp);
-  {
-    ProfScope ps(KC_BT_SWEEP, s, vec + 8.0 * mat_doubles[1], 2.0 * ncomp * ncols * mat_doubles[1]);
-    hipLaunchKernelGGL(k_bt_sweep, grid, dim3(256), 0, s, 0, n, nblk, start, off_p, data, Y, ldx, ncols);
-  }
-  {
-    ProfScope ps(KC_BT_SWEEP, s, vec + 8.0 * mat_doubles[2], 2.0 * ncomp * ncols * mat_doubles[2]);
-    hipLaunchKernelGGL(k_bt_sweep, grid, dim3(256), 0, s, 1, n, nblk, start, off_q, data, Y, ldx, ncols);
-  }
-}
 
 void pc_init(hipStream_t s, int N, const double* S, double eps, const double* normsq_in, double* normsq_out, double* d,
              double* state) {
@@ -1498,6 +1399,19 @@ void sg_convection_full(hipStream_t s, int nt, int nxi, int n_u, int ns, int nal
   ProfScope ps(KC_OTHER, s, 8.0 * 2.0 * nt * nxi * (double)n_u, 0.0);
   hipLaunchKernelGGL(k_sg_convection, dim3(nelem, nt), dim3(64), 0, s, nxi, n_u, ns, nall, conn, free_id, ufree,
                      ramp, gall, hrow, hl, hk, hv, ref, hh, sign, out);
+}
+
+void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* X, long ld, int ncols) {
+  if (ncols <= 0 || f.npass == 0) return;
+  if (f.maxbs > BCR_MAXBS) throw std::runtime_error("block cyclic reduction: block larger than 256");
+  ProfScope ps(KC_BCR, s, 8.0 * (f.ndata + 2.0 * ncomp * (double)f.n * ncols * f.npass / 2),
+               2.0 * f.ndata * ncols * ncomp);
+  for (int p = 0; p < f.npass; ++p) {
+    const int o0 = f.pass_begin[p], no = f.pass_begin[p + 1] - o0;
+    if (no <= 0) continue;
+    hipLaunchKernelGGL(k_bcr_pass, dim3(no, cdiv(ncols, BCR_CB), ncomp), dim3(256), 0, s, o0, f.start, f.op_out,
+                       f.op_self, f.op_nterm, f.op_in, f.op_off, f.op_coef, f.data, X, ld, ncols, (long)f.n);
+  }
 }
 
 void hessenberg_lsq(hipStream_t s, const double* H, int ld, int k, const double* beta, double* y, double* resid) {

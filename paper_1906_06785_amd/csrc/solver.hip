@@ -70,41 +70,41 @@ DevCsr upload_csr(Ctx& c, const Csr& pat, const std::vector<const double*>& vals
   return d;
 }
 
-struct DevBT {
-  int n = 0, nblk = 0, maxbs = 0;
-  double nd[3] = {0, 0, 0};   // doubles in the Sinv, P and Q blocks
-  int* start = nullptr;
-  long *off_sinv = nullptr, *off_p = nullptr, *off_q = nullptr;
-  double* data = nullptr;
-  void free_all() {
-    (void)hipFree(start);
-    (void)hipFree(off_sinv);
-    (void)hipFree(off_p);
-    (void)hipFree(off_q);
-    (void)hipFree(data);
-  }
-};
+void free_bcr(BcrDev& d) {
+  for (void* p : {(void*)d.start, (void*)d.op_out, (void*)d.op_self, (void*)d.op_nterm, (void*)d.op_in,
+                  (void*)d.op_off, (void*)d.op_coef, (void*)d.data})
+    if (p) (void)hipFree(p);
+  d = BcrDev();
+}
 
-DevBT upload_bt(Ctx& c, const BlockTri& bt) {
-  DevBT d;
-  d.n = bt.n;
-  d.nblk = bt.nblk;
-  d.maxbs = bt.maxbs;
-  if (bt.maxbs > 256) throw SgttError(-6, "block-tridiagonal block too large");
-  d.start = dev_upload(c, bt.start);
-  std::vector<long> a(bt.off_sinv.begin(), bt.off_sinv.end()), b(bt.off_p.begin(), bt.off_p.end()),
-      q(bt.off_q.begin(), bt.off_q.end());
-  d.off_sinv = dev_upload(c, a);
-  d.off_p = dev_upload(c, b);
-  d.off_q = dev_upload(c, q);
-  d.data = dev_upload(c, bt.data);
-  for (int b = 0; b < bt.nblk; ++b) {
-    int bs = bt.start[b + 1] - bt.start[b];
-    d.nd[0] += (double)bs * bs;
-    if (b > 0) d.nd[1] += (double)bs * (bt.start[b] - bt.start[b - 1]);
-    if (b < bt.nblk - 1) d.nd[2] += (double)bs * (bt.start[b + 2] - bt.start[b + 1]);
-  }
+BcrDev upload_bcr(Ctx& c, const BcrFactor& f) {
+  if (f.maxbs > 256) throw SgttError(-6, "block cyclic reduction: block larger than 256");
+  BcrDev d;
+  d.n = f.n;
+  d.nblk = f.nblk;
+  d.maxbs = f.maxbs;
+  d.npass = (int)f.pass_begin.size() - 1;
+  d.pass_begin = f.pass_begin;
+  d.ndata = (double)f.data.size();
+  d.start = dev_upload(c, f.start);
+  d.op_out = dev_upload(c, f.op_out);
+  d.op_self = dev_upload(c, f.op_self);
+  d.op_nterm = dev_upload(c, f.op_nterm);
+  d.op_in = dev_upload(c, f.op_in);
+  std::vector<long> off(f.op_off.begin(), f.op_off.end());
+  d.op_off = dev_upload(c, off);
+  d.op_coef = dev_upload(c, f.op_coef);
+  d.data = dev_upload(c, f.data);
   return d;
+}
+
+// block cyclic reduction factor of a scalar matrix on pattern `pat`
+BcrDev factor_bcr(Ctx& c, const Csr& pat, const double* vals, const std::vector<int>& blocks) {
+  BcrFactor f;
+  std::string err;
+  bcr_factor(pat, vals, blocks, f, err);
+  if (!err.empty()) throw SgttError(-6, err);
+  return upload_bcr(c, f);
 }
 
 }  // namespace
@@ -134,7 +134,7 @@ struct sgtt_system {
   double* w1 = nullptr;    // nt x k1
   double* Hw = nullptr;    // k1 x k2 x nxi x nxi
   double* omega = nullptr; // nt x k2 (mean-mode time factors)
-  DevBT Fbt, Xbt;          // F_avg and X = B M*^-1 B^T factorizations
+  BcrDev Fbt, Xbt;         // F_avg and X = B M*^-1 B^T (block cyclic reduction)
   TT bu, bp;               // right-hand side
   double* Dinv = nullptr;  // 1 / diag(F_avg) on free scalar nodes
   sgtt::Mlp* mlp_collect = nullptr;   // records (r, F_avg^-1 r) pairs from mean solves
@@ -150,8 +150,8 @@ struct sgtt_system {
     Bd.free_all();
     Btd.free_all();
     Xmid.free_all();
-    Fbt.free_all();
-    Xbt.free_all();
+    free_bcr(Fbt);
+    free_bcr(Xbt);
     for (double* p : {Gnu, w1, Hw, omega, dsc, Dinv}) (void)hipFree(p);
   }
 };
@@ -220,13 +220,13 @@ TT apply_mean_sum(sgtt_system& S, const TT& x, const DevCsr& K, int ncomp, int n
 }
 
 // spatial solve along the space core: out = A^-1 x3 (ranks unchanged)
-TT space_solve(sgtt_system& S, const TT& x, const DevBT& bt, int ncomp, double c1scale) {
+TT space_solve(sgtt_system& S, const TT& x, const BcrDev& bt, int ncomp, double c1scale) {
   Ctx& c = S.ctx->c;
   TT o = tt_new(c, x.n1, x.n2, x.n3, x.r1, x.r2);
   copy2d(c.s, x.n1, x.r1, x.c1, x.r1, o.c1, x.r1, c1scale, nullptr, 0);
   SGTT_HIP(hipMemcpyAsync(o.c2, x.c2, sizeof(double) * x.n_c2(), hipMemcpyDeviceToDevice, c.s));
-  blocktri_solve(c.s, bt.n, bt.nblk, bt.maxbs, bt.start, bt.off_sinv, bt.off_p, bt.off_q, bt.data, ncomp, x.c3, x.r2,
-                 x.r2, o.c3, bt.nd);
+  SGTT_HIP(hipMemcpyAsync(o.c3, x.c3, sizeof(double) * x.n_c3(), hipMemcpyDeviceToDevice, c.s));
+  bcr_solve(c.s, bt, ncomp, o.c3, x.r2, x.r2);
   return o;
 }
 
@@ -249,8 +249,8 @@ TT apply_Minv(sgtt_system& S, const TT& u) {
     }
     return o;
   }
-  blocktri_solve(c.s, S.Fbt.n, S.Fbt.nblk, S.Fbt.maxbs, S.Fbt.start, S.Fbt.off_sinv, S.Fbt.off_p, S.Fbt.off_q,
-                 S.Fbt.data, 2, u.c3, u.r2, u.r2, o.c3, S.Fbt.nd);
+  SGTT_HIP(hipMemcpyAsync(o.c3, u.c3, sizeof(double) * u.n_c3(), hipMemcpyDeviceToDevice, c.s));
+  bcr_solve(c.s, S.Fbt, 2, o.c3, u.r2, u.r2);
   if (S.mlp_collect) {
     try {
       mlp_collect(*S.mlp_collect, S.ns, 2, u.r2, u.c3, o.c3, u.r2, S.Dinv);
@@ -757,13 +757,10 @@ void build_convection(sgtt_system& S, Ctx& c, const TT& wtil) {
     for (int b = 0; b < k2; ++b) v += avg[b] * Nv[b][t];
     F[t] = v;
   }
-  BlockTri bt;
-  std::string err;
   if (S.Dinv) (void)hipFree(S.Dinv);
   S.Dinv = dev_upload(c, inverse_diagonal(hp.Kff, F.data()));
-  blocktri_factor(hp.Kff, F.data(), hp.vel_blocks, bt, err);
-  if (!err.empty()) throw SgttError(-6, err);
-  S.Fbt = upload_bt(c, bt);
+  free_bcr(S.Fbt);
+  S.Fbt = factor_bcr(c, hp.Kff, F.data(), hp.vel_blocks);
 }
 
 }  // namespace
@@ -863,13 +860,7 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
   S->Gnu = dev_upload(c, hp.Gnu);
   S->Bd = upload_csr(c, hp.B, {hp.B.val.data()});
   S->Btd = upload_csr(c, hp.Bt, {hp.Bt.val.data()});
-  {
-    BlockTri bt;
-    std::string err;
-    blocktri_factor(hp.Xp, hp.Xp.val.data(), hp.p_blocks, bt, err);
-    if (!err.empty()) throw SgttError(-6, err);
-    S->Xbt = upload_bt(c, bt);
-  }
+  S->Xbt = factor_bcr(c, hp.Xp, hp.Xp.val.data(), hp.p_blocks);
   const int nt = S->nt, nxi = S->nxi, nall = S->nall, ns = S->ns;
   // Dirichlet lift TT over all nodes: ramp (x) e_1 (x) g_all
   std::vector<double> e1(nxi, 0.0);
@@ -887,11 +878,7 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
     std::vector<double> F(hp.Kff.nnz());
     for (int t = 0; t < hp.Kff.nnz(); ++t) F[t] = hp.Mff[t] / S->tau + S->nu0 * hp.Aff[t];
     S->Dinv = dev_upload(c, inverse_diagonal(hp.Kff, F.data()));
-    BlockTri bt;
-    std::string err;
-    blocktri_factor(hp.Kff, F.data(), hp.vel_blocks, bt, err);
-    if (!err.empty()) throw SgttError(-6, err);
-    S->Fbt = upload_bt(c, bt);
+    S->Fbt = factor_bcr(c, hp.Kff, F.data(), hp.vel_blocks);
     // f^u: core1 [(I-C)a/tau | a], core2 [e1 ; G_nu e1], core3 -[M_fa g | A_fa g]
     std::vector<double> Ca(nt), c1((size_t)nt * 2), c2((size_t)2 * nxi * 2, 0.0);
     for (int k = 0; k < nt; ++k) {
