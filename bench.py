@@ -33,7 +33,7 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and FP64 matrix) peak
 def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="C2")
     ap.add_argument("--outer-explicit", type=int, default=1,
@@ -45,6 +45,11 @@ def parse(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", type=int, default=0)
     ap.add_argument("--precision", type=int, default=0, help="inner-solve products: 0 FP64, 1 FP32, 2 BF16")
+    ap.add_argument("--inner-mode", type=int, default=1,
+                    help="velocity block of the preconditioner: 1 time-stepped mean solve on the full tensor, "
+                         "0 inner low-rank GMRES with M (eq. 5.22-5.23)")
+    ap.add_argument("--inner-rhs-eps", type=float, default=1e-2,
+                    help="truncation of the inner GMRES right-hand side (inner mode 0)")
     ap.add_argument("--batch", type=int, default=0,
                     help="N > 0: instead, time N independent problems (batch_configs) on --contexts streams")
     ap.add_argument("--contexts", type=int, default=8)
@@ -57,7 +62,7 @@ def solve_options(args=None):
     if args is None:
         args = parse([])
     return dict(restart=args.restart, outer_explicit=args.outer_explicit, verbose=args.verbose, relax=args.relax,
-                precision=args.precision)
+                precision=args.precision, inner_mode=args.inner_mode, inner_rhs_eps=args.inner_rhs_eps)
 
 
 OUT_CAPS = (128, 4096)   # output TT capacity (core-1 rank, core-2 rank) of the solution
@@ -204,7 +209,9 @@ def main():
                    "unknowns": int(128 * 35 * (S.nu + S.np)) if args.config == "C2" else None,
                    "solver": ("Alg. 4.2 (explicit residual each outer iteration)" if args.outer_explicit
                               else "Alg. 4.2 cycles stopped on the least-squares estimate"),
-                   "restart": args.restart, "relaxed_truncation": bool(args.relax)},
+                   "restart": args.restart, "relaxed_truncation": bool(args.relax),
+                   "preconditioner_velocity_block": ("time-stepped mean solve (full tensor)" if args.inner_mode == 1
+                                                     else "inner low-rank GMRES with M")},
         "solve": {"outer_iters": outer, "cycles": stats[-1]["cycles"], "inner_iters": stats[-1]["inner_iters"],
                   "max_rel_residual": worst, "converged": worst <= 1e-8,
                   "max_krylov_rank_u": stats[-1]["max_rank_krylov_u"], "setup_s": setup_s},

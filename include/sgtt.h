@@ -118,6 +118,16 @@ typedef struct {
   double cycle_rhs_factor; /* a refinement cycle's right-hand side r_j is
                               compressed at max(eps_krylov, min(1e-3,
                               factor tol ||b|| / ||r_j||)); 0 means 0.05    */
+  int inner_mode;          /* velocity block of the preconditioner:
+                              0: inner low-rank GMRES on (F_0 + C) with M
+                                 (eq. 5.22-5.23);
+                              1: block forward substitution in time on the
+                                 full velocity tensor with F_avg (eq. 5.23)
+                                 on the diagonal and -tau^-1 M below, then
+                                 TT-SVD at inner_eps: (F_0 + C)^-1 exactly
+                                 without convection; with convection the
+                                 time-averaged convection of F_avg stands
+                                 for N_0 (an approximation, as is M)       */
 } sgtt_solve_opts;
 
 typedef struct {

@@ -228,6 +228,36 @@ class MeanLSC:
         W = np.cumsum(U, axis=0)
         return self._Finv(W.reshape(nt * nx, -1)).reshape(U.shape)
 
+    def mean_solve_exact_full(self, Y):
+        """(F_0 + C)^-1 Y for a system without convection (eq. 5.21): the
+        mean matrix is the identity in the chaos mode and lower
+        block-bidiagonal in time, so block forward substitution with one
+        sparse LU of F_avg = tau^-1 M + A_0 solves it exactly."""
+        if self.conv is not None:
+            raise NotImplementedError("exact mean solve: systems without convection only")
+        P = self.prob
+        V = np.zeros_like(Y)
+        for k in range(P.nt):
+            rhs = Y[k].copy()
+            if k > 0:
+                rhs += np.asarray(P.Mb @ V[k - 1].T).T / P.tau
+            V[k] = self._Finv(rhs)
+        return V
+
+    def apply_full_exact(self, yu, yp):
+        """P^-1 [yu; yp] (eq. 5.2) with the LSC Schur approximation (eq. 5.19)
+        and the velocity block (F_0 + C)^-1 applied exactly."""
+        P = self.prob
+        nt, nx = P.nt, P.n_xi
+        sh = (nt * nx, -1)
+        t1 = self._Xinv(yp.reshape(sh))
+        t2 = np.asarray(self.MsBt @ t1.T).T.reshape(nt, nx, -1)
+        t3 = self._mean_apply_full(t2)
+        t4 = np.asarray(self.BMs @ t3.reshape(sh).T).T
+        ph = -self._Xinv(t4).reshape(nt, nx, -1)
+        rhs = yu - np.asarray(P.Bt @ ph.reshape(sh).T).T.reshape(nt, nx, -1)
+        return self.mean_solve_exact_full(rhs), ph
+
     def apply_full(self, yu, yp):
         P = self.prob
         nt, nx = P.nt, P.n_xi

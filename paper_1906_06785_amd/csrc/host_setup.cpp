@@ -775,6 +775,7 @@ void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& bloc
     f.pass_begin.push_back((int)f.op_out.size());
   };
   f.pass_begin.push_back(0);
+  f.nfwd = (int)fwd.size() - 1;   // the last list of fwd is the top solve
   for (const auto& ops : fwd) emit(ops);
   for (int l = (int)bwd.size() - 1; l >= 0; --l) emit(bwd[l]);
 }

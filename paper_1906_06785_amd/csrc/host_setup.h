@@ -97,14 +97,14 @@ void reference_tables(double* out);
 // matrix S given by values on Kff (applied to both components).
 void lsc_middle_values(const HostProblem& hp, const double* Svals, double* out);
 
-// Block cyclic reduction of the same block-tridiagonal matrix: level l
-// eliminates the odd positions of the level-l system (stride 2^l in the
-// original block numbering); the solve is a sequence of passes, each a set of
-// independent block operations
-//     y_out = [v_out] + sum_t coef_t M_t v_{in_t}      (M_t dense, col-major)
-// applied in place: forward passes (levels 0, 1, ...) update the even
-// positions' right-hand sides, one pass solves the last block, backward
-// passes (top level down) solve the odd positions.
+// Block cyclic reduction of a block-tridiagonal matrix: level l eliminates
+// the odd positions of the level-l system (stride 2^l in the original block
+// numbering).  The solve is a sequence of passes, each a set of independent
+// block operations  out = [b_out] + sum_t coef_t M_t v_{in_t}  (M_t dense,
+// col-major): forward passes (levels 0, 1, ...) update the even positions'
+// right-hand sides b in place from their odd neighbours' b; then the top
+// solve and the backward passes (top level down) write the solution x of the
+// odd positions from their own b and their neighbours' x.
 struct BcrFactor {
   int n = 0, nblk = 0, maxbs = 0;
   std::vector<int> start;              // nblk + 1
@@ -114,6 +114,8 @@ struct BcrFactor {
   std::vector<int64_t> op_off;         // 3 per op: matrix offsets in data
   std::vector<double> op_coef;         // 3 per op
   std::vector<int> pass_begin;         // op ranges of the passes (npass + 1)
+  int nfwd = 0;                        // passes [0, nfwd) reduce the right-hand side in place;
+                                       // the rest (top solve, back substitution) write the solution
   std::vector<double> data;
 };
 void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& blocks, BcrFactor& f,

@@ -91,10 +91,11 @@ void transpose_copy(hipStream_t s, int rows, int cols, const double* src, long l
 // and `ncomp` velocity components:
 //  y[(c*ocs + r)*ldy + ycol0 + v*yvstep + j] =
 //     alpha * sum_t vals[v*vstride + t] * x[(c*ics + col[t])*ldx + xcol0 + j]
+//     (+ beta * the old value)
 // for rows r < nrows, components c < ncomp, v < nv (<= 16), columns j < ncols.
 void spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* rowptr, const int* col,
           const double* vals, int nv, long vstride, const double* x, int ldx, int xcol0, int ncols,
-          double* y, int ldy, int ycol0, int yvstep, double alpha);
+          double* y, int ldy, int ycol0, int yvstep, double alpha, double beta = 0.0);
 
 // core1 block ops on row-major n1 x r matrices
 // out[t, col0 + a] = scale*(in[t,a] - in[t-1,a])          (kind 0: (I - C)/tau)
@@ -162,16 +163,17 @@ void sg_convection_full(hipStream_t s, int nt, int nxi, int n_u, int ns, int nal
 // Block cyclic reduction solve (factor built on the host): device copies of
 // the op lists and block data; pass_begin stays on the host.
 struct BcrDev {
-  int n = 0, nblk = 0, maxbs = 0, npass = 0;
+  int n = 0, nblk = 0, maxbs = 0, npass = 0, nfwd = 0;
   double ndata = 0;                 // doubles of block data (for the profiler)
   std::vector<int> pass_begin;      // host: npass + 1
   int *start = nullptr, *op_out = nullptr, *op_self = nullptr, *op_nterm = nullptr, *op_in = nullptr;
   long* op_off = nullptr;
   double *op_coef = nullptr, *data = nullptr;
 };
-// In place: X (rows of one component, row stride ld; ncomp components at
-// X + z * n * ld) <- A^-1 X for ncols columns.
-void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* X, long ld, int ncols);
+// X <- A^-1 B for ncols columns of ncomp components (rows of one component;
+// component z of B at B + z * n * ldb, of X at X + z * n * ldx).  B is
+// overwritten (reduced right-hand sides); X must not overlap B.
+void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols);
 
 
 

@@ -409,7 +409,7 @@ __global__ __launch_bounds__(256) void k_spmm(int nrows, int ics, int ocs, const
                                               const int* __restrict__ col, const double* __restrict__ vals, int nv,
                                               long vstride, const double* __restrict__ x, int ldx, int xcol0,
                                               int ncols, double* __restrict__ y, int ldy, int ycol0, int yvstep,
-                                              double alpha) {
+                                              double alpha, double beta) {
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   const int r = blockIdx.x * (blockDim.x / WAVE) + wave;
   const int c = blockIdx.y;
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(256) void k_spmm(int nrows, int ics, int ocs, const
     if (act) {
 #pragma unroll
       for (int v = 0; v < NVMAX; ++v)
-        if (v < nv) yb[v * yvstep + j] = alpha * acc[v];
+        if (v < nv) yb[v * yvstep + j] = alpha * acc[v] + (beta != 0.0 ? beta * yb[v * yvstep + j] : 0.0);
     }
   }
 }
@@ -882,63 +882,109 @@ __global__ __launch_bounds__(64) void k_sg_convection(int nxi, int n_u, int ns, 
 }
 
 // ------------------------------------------------------------------ block cyclic reduction
-constexpr int BCR_CB = 32, BCR_MAXBS = 256;
+constexpr int BCR_CB = 32, BCR_MAXBS = 256, BCR_PF = 8;
 
-// One pass of a block cyclic reduction solve, in place on X (rows = scalar
-// unknowns of one component, row stride ld; component z at X + z*comp_rows*ld):
-// workgroup (op, column tile, component) sets block out = [X_out] +
-// sum_t coef_t M_t X_{in_t}.  The ops of one pass write distinct blocks and
-// read only blocks that the pass does not write (or their own block, which
-// is staged in LDS before any write).
+// One pass of a block cyclic reduction solve.  Rows = scalar unknowns of one
+// component; component z of a vector V with row stride ld starts at
+// V + z*comp_rows*ld.  Block out <- [B_out] + sum_t coef_t M_t V_{in_t} with
+// V_{in} = B_in for the op's own block and for every input of a forward pass
+// (solve == 0; out goes to B in place), and V_{in} = the solution X for the
+// neighbours of the top / backward passes (solve == 1; out goes to X).  No op
+// reads a block that the pass writes, so every op spreads its row groups
+// (rows [64 g, 64 g + 64), grid z) over workgroups.  BCR_CB combined columns
+// per workgroup (component-major: combined column j is column j % ncols of
+// component j / ncols), on the FP64 matrix cores: wave w owns row tile
+// 4g + w times two 16-column tiles (v_mfma_f64_16x16x4: lane l supplies
+// M[row l%16][k l/16] and V[k l/16][col l%16]; accumulator item v is row
+// 4v + l/16).  Inputs are staged in LDS; the next k-step's M fragment is
+// loaded while the current one is multiplied.
 __global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict__ start, const int* __restrict__ op_out,
                                                   const int* __restrict__ op_self, const int* __restrict__ op_nterm,
                                                   const int* __restrict__ op_in, const long* __restrict__ op_off,
                                                   const double* __restrict__ op_coef, const double* __restrict__ data,
-                                                  double* __restrict__ X, long ld, int ncols, long comp_rows) {
-  __shared__ double vin[BCR_MAXBS][BCR_CB];
+                                                  double* __restrict__ B, long ldb, double* __restrict__ X, long ldx,
+                                                  int solve, int ncols, int ncomp, long comp_rows) {
+  __shared__ double xs[BCR_MAXBS + 4][BCR_CB + 1];
   const int o = op0 + blockIdx.x;
-  const int c0 = blockIdx.y * BCR_CB;
-  const int cn = min(BCR_CB, ncols - c0);
-  double* Xc = X + (long)blockIdx.z * comp_rows * ld;
+  const int j0 = blockIdx.y * BCR_CB;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int lr = lane % 16, lk = lane / 16;
   const int ob = op_out[o];
   const int r0 = start[ob], bo = start[ob + 1] - r0;
-  const int r = threadIdx.x;
-  double acc[BCR_CB];
+  if ((int)blockIdx.z * 64 >= bo) return;   // uniform per workgroup
+  const int rt = blockIdx.z * 4 + wave;
+  const bool active = rt * 16 < bo;
+  const int ctot = ncomp * ncols;
+  auto addr = [&](int row, int j, long ld) -> long {
+    const int comp = j / ncols, c = j - comp * ncols;
+    return ((long)comp * comp_rows + row) * ld + c;
+  };
+  double* out = solve ? X : B;
+  const long ldo = solve ? ldx : ldb;
+  dbl4 acc[2];
+  acc[0] = dbl4{0.0, 0.0, 0.0, 0.0};
+  acc[1] = dbl4{0.0, 0.0, 0.0, 0.0};
+  if (active && op_self[o]) {
 #pragma unroll
-  for (int c = 0; c < BCR_CB; ++c) acc[c] = 0.0;
-  if (op_self[o] && r < bo) {
-    const double* xr = Xc + (long)(r0 + r) * ld + c0;
+    for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-    for (int c = 0; c < BCR_CB; ++c)
-      if (c < cn) acc[c] = xr[c];
+      for (int v = 0; v < 4; ++v) {
+        const int r = rt * 16 + 4 * v + lk, j = j0 + ct * 16 + lr;
+        if (r < bo && j < ctot) acc[ct][v] = B[addr(r0 + r, j, ldb)];
+      }
   }
   const int nterm = op_nterm[o];
+  const int ra = rt * 16 + lr;
   for (int t = 0; t < nterm; ++t) {
     const int ib = op_in[3 * o + t];
     const int i0 = start[ib], bi = start[ib + 1] - i0;
+    const int bi4 = (bi + 3) & ~3;
     const double* M = data + op_off[3 * o + t];
     const double coef = op_coef[3 * o + t];
+    const bool from_x = solve && ib != ob;
+    const double* src = from_x ? X : B;
+    const long lds = from_x ? ldx : ldb;
     __syncthreads();
-    for (int e = threadIdx.x; e < bi * BCR_CB; e += blockDim.x) {
-      const int k = e / BCR_CB, c = e % BCR_CB;
-      vin[k][c] = (c < cn) ? Xc[(long)(i0 + k) * ld + c0 + c] : 0.0;
+    for (int e = tid; e < bi4 * BCR_CB; e += blockDim.x) {
+      const int k = e / BCR_CB, jj = e % BCR_CB, j = j0 + jj;
+      xs[k][jj] = (k < bi && j < ctot) ? src[addr(i0 + k, j, lds)] : 0.0;
     }
     __syncthreads();
-    if (r < bo) {
-      for (int k = 0; k < bi; ++k) {
-        const double m = coef * M[(long)k * bo + r];
+    if (!active) continue;
+    // M fragments stream from memory: BCR_PF k-steps are kept in flight
+    double an[BCR_PF];
 #pragma unroll
-        for (int c = 0; c < BCR_CB; ++c) acc[c] = fma(m, vin[k][c], acc[c]);
+    for (int d = 0; d < BCR_PF; ++d) {
+      const int kk = 4 * d + lk;
+      an[d] = (ra < bo && kk < bi) ? M[(long)kk * bo + ra] : 0.0;
+    }
+    for (int k = 0; k < bi4; k += 4 * BCR_PF) {
+      double a[BCR_PF];
+#pragma unroll
+      for (int d = 0; d < BCR_PF; ++d) a[d] = coef * an[d];
+#pragma unroll
+      for (int d = 0; d < BCR_PF; ++d) {
+        const int kk = k + 4 * (BCR_PF + d) + lk;
+        an[d] = (ra < bo && kk < bi) ? M[(long)kk * bo + ra] : 0.0;
+      }
+#pragma unroll
+      for (int d = 0; d < BCR_PF; ++d) {
+        const int kr = k + 4 * d;
+        if (kr >= bi4) break;
+        const double b0 = xs[kr + lk][lr], b1 = xs[kr + lk][16 + lr];
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[d], b0, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[d], b1, acc[1], 0, 0, 0);
       }
     }
   }
-  __syncthreads();
-  if (r < bo) {
-    double* xr = Xc + (long)(r0 + r) * ld + c0;
+  if (!active) return;
 #pragma unroll
-    for (int c = 0; c < BCR_CB; ++c)
-      if (c < cn) xr[c] = acc[c];
-  }
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = rt * 16 + 4 * v + lk, j = j0 + ct * 16 + lr;
+      if (r < bo && j < ctot) out[addr(r0 + r, j, ldo)] = acc[ct][v];
+    }
 }
 
 // ------------------------------------------------------------------ blocked pivoted Cholesky
@@ -1307,7 +1353,7 @@ void transpose_copy(hipStream_t s, int rows, int cols, const double* src, long l
 
 void spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* rowptr, const int* col, const double* vals,
           int nv, long vstride, const double* x, int ldx, int xcol0, int ncols, double* y, int ldy, int ycol0,
-          int yvstep, double alpha) {
+          int yvstep, double alpha, double beta) {
   if (nrows <= 0 || ncols <= 0 || nv <= 0) return;
   for (int v0 = 0; v0 < nv; v0 += NVMAX) {
     int nvb = std::min(NVMAX, nv - v0);
@@ -1318,7 +1364,7 @@ void spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* rowp
                 8.0 * ncomp * (double)nrows * nvb * ncols;
     ProfScope ps(KC_SPMM, s, by, 2.0 * nnz * ncomp * nvb * ncols);
     hipLaunchKernelGGL(k_spmm, grid, dim3(256), 0, s, nrows, ics, ocs, rowptr, col, vals + v0 * vstride, nvb, vstride,
-                       x, ldx, xcol0, ncols, y, ldy, ycol0 + v0 * yvstep, yvstep, alpha);
+                       x, ldx, xcol0, ncols, y, ldy, ycol0 + v0 * yvstep, yvstep, alpha, beta);
   }
 }
 
@@ -1401,16 +1447,17 @@ void sg_convection_full(hipStream_t s, int nt, int nxi, int n_u, int ns, int nal
                      ramp, gall, hrow, hl, hk, hv, ref, hh, sign, out);
 }
 
-void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* X, long ld, int ncols) {
+void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols) {
   if (ncols <= 0 || f.npass == 0) return;
   if (f.maxbs > BCR_MAXBS) throw std::runtime_error("block cyclic reduction: block larger than 256");
-  ProfScope ps(KC_BCR, s, 8.0 * (f.ndata + 2.0 * ncomp * (double)f.n * ncols * f.npass / 2),
+  ProfScope ps(KC_BCR, s, 8.0 * (f.ndata + 3.0 * ncomp * (double)f.n * ncols),
                2.0 * f.ndata * ncols * ncomp);
   for (int p = 0; p < f.npass; ++p) {
     const int o0 = f.pass_begin[p], no = f.pass_begin[p + 1] - o0;
     if (no <= 0) continue;
-    hipLaunchKernelGGL(k_bcr_pass, dim3(no, cdiv(ncols, BCR_CB), ncomp), dim3(256), 0, s, o0, f.start, f.op_out,
-                       f.op_self, f.op_nterm, f.op_in, f.op_off, f.op_coef, f.data, X, ld, ncols, (long)f.n);
+    hipLaunchKernelGGL(k_bcr_pass, dim3(no, cdiv((long)ncomp * ncols, BCR_CB), cdiv(f.maxbs, 64)), dim3(256), 0, s,
+                       o0, f.start, f.op_out, f.op_self, f.op_nterm, f.op_in, f.op_off, f.op_coef, f.data, B, ldb, X,
+                       ldx, p >= f.nfwd ? 1 : 0, ncols, ncomp, (long)f.n);
   }
 }
 

@@ -84,6 +84,7 @@ BcrDev upload_bcr(Ctx& c, const BcrFactor& f) {
   d.nblk = f.nblk;
   d.maxbs = f.maxbs;
   d.npass = (int)f.pass_begin.size() - 1;
+  d.nfwd = f.nfwd;
   d.pass_begin = f.pass_begin;
   d.ndata = (double)f.data.size();
   d.start = dev_upload(c, f.start);
@@ -225,8 +226,10 @@ TT space_solve(sgtt_system& S, const TT& x, const BcrDev& bt, int ncomp, double 
   TT o = tt_new(c, x.n1, x.n2, x.n3, x.r1, x.r2);
   copy2d(c.s, x.n1, x.r1, x.c1, x.r1, o.c1, x.r1, c1scale, nullptr, 0);
   SGTT_HIP(hipMemcpyAsync(o.c2, x.c2, sizeof(double) * x.n_c2(), hipMemcpyDeviceToDevice, c.s));
-  SGTT_HIP(hipMemcpyAsync(o.c3, x.c3, sizeof(double) * x.n_c3(), hipMemcpyDeviceToDevice, c.s));
-  bcr_solve(c.s, bt, ncomp, o.c3, x.r2, x.r2);
+  double* rhs = c.pool.get(x.n_c3());
+  SGTT_HIP(hipMemcpyAsync(rhs, x.c3, sizeof(double) * x.n_c3(), hipMemcpyDeviceToDevice, c.s));
+  bcr_solve(c.s, bt, ncomp, rhs, x.r2, o.c3, x.r2, x.r2);
+  c.pool.put(rhs);
   return o;
 }
 
@@ -249,8 +252,10 @@ TT apply_Minv(sgtt_system& S, const TT& u) {
     }
     return o;
   }
-  SGTT_HIP(hipMemcpyAsync(o.c3, u.c3, sizeof(double) * u.n_c3(), hipMemcpyDeviceToDevice, c.s));
-  bcr_solve(c.s, S.Fbt, 2, o.c3, u.r2, u.r2);
+  double* rhs = c.pool.get(u.n_c3());
+  SGTT_HIP(hipMemcpyAsync(rhs, u.c3, sizeof(double) * u.n_c3(), hipMemcpyDeviceToDevice, c.s));
+  bcr_solve(c.s, S.Fbt, 2, rhs, u.r2, o.c3, u.r2, u.r2);
+  c.pool.put(rhs);
   if (S.mlp_collect) {
     try {
       mlp_collect(*S.mlp_collect, S.ns, 2, u.r2, u.c3, o.c3, u.r2, S.Dinv);
@@ -531,10 +536,43 @@ struct InnerSpace : Space {
 
 struct PrecOpts {
   double eps = 1e-6, inner_tol = 1e-1, inner_eps = 1e-3, inner_rhs_eps = 0.0;
+  int inner_mode = 0;       // 0: inner GMRES with M (eq. 5.22-5.23); 1: exact mean solve
   int inner_maxit = 20;
   bool inner_explicit = false;
   int precision = GP_F64;   // dense products of the inner solve
 };
+
+// (tau^-1 (I - C) (x) I (x) M + I (x) I (x) (F_avg - tau^-1 M))^-1 y: the mean
+// matrix F_0 + C of eq. 5.21 with its convection N_0 replaced by the
+// time-averaged one inside F_avg (eq. 5.23).  Without convection this is
+// (F_0 + C)^-1 exactly.  The matrix is lower block-bidiagonal in time with
+// F_avg on the diagonal and -tau^-1 M below, identity in the chaos mode:
+// block forward substitution in time on the full-format velocity (node-major,
+// columns (t, xi)), then TT-SVD (Alg. 4.1) at eps.
+TT exact_mean_solve(sgtt_system& S, const TT& y, double eps) {
+  Ctx& c = S.ctx->c;
+  const int nt = S.nt, nxi = S.nxi, nu = S.nu, ns = S.ns;
+  const long ldw = (long)nt * nxi;
+  double* Z = c.pool.get((size_t)ldw * y.r2);   // G1 x_1 G2: (nt nxi) x r2
+  gemm(c.s, 1, nt, nxi * y.r2, y.r1, 1.0, y.c1, 0, y.r1, 1, y.c2, 0, (long)nxi * y.r2, 1, 0.0, Z, 0,
+       (long)nxi * y.r2, 1);
+  double* W = c.pool.get((size_t)nu * ldw);     // node-major full tensor: W[x][t nxi + i]
+  gemm(c.s, 1, nu, (int)ldw, y.r2, 1.0, y.c3, 0, y.r2, 1, Z, 0, 1, y.r2, 0.0, W, 0, ldw, 1);
+  c.pool.put(Z);
+  double* Vn = c.pool.get((size_t)nu * ldw);    // solution, same layout
+  for (int t = 0; t < nt; ++t) {
+    if (t > 0)   // y_t + tau^-1 M v_{t-1} (value set 0 of the operator pattern is M)
+      spmm(c.s, ns, 2, ns, ns, S.Kop.rowptr, S.Kop.col, S.Kop.vals, 1, S.Kop.nnz, Vn, (int)ldw, (t - 1) * nxi, nxi,
+           W, (int)ldw, t * nxi, 0, 1.0 / S.tau, 1.0);
+    bcr_solve(c.s, S.Fbt, 2, W + (long)t * nxi, ldw, Vn + (long)t * nxi, ldw, nxi);
+  }
+  double* V = W;                                 // C order (t, xi, x), reusing the consumed right-hand side
+  transpose_copy(c.s, nu, (int)ldw, Vn, ldw, V, nu);
+  c.pool.put(Vn);
+  TT out = tt_from_full(c, V, nt, nxi, nu, eps, nullptr);
+  c.pool.put(W);
+  return out;
+}
 
 Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCounters* cnt) {
   Ctx& c = S.ctx->c;
@@ -555,6 +593,14 @@ Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCoun
   rhs.nc = 1;
   rhs.c[0] = tt_concat(c, {&yu, &bph}, nullptr, {});
   // inner low-rank GMRES on (F_0 + C) v = rhs, preconditioned by M (eq. 5.22-5.23)
+  if (po.inner_mode == 1) {
+    RegionScope rg(RG_IN_MINV);
+    Vec out;
+    out.nc = 2;
+    out.c[0] = exact_mean_solve(S, rhs.c[0], po.inner_eps);
+    out.c[1] = std::move(ph);
+    return out;
+  }
   InnerSpace isp(S);
   int its = 0;
   double rr = 0;
@@ -673,6 +719,8 @@ PrecOpts prec_opts(const sgtt_solve_opts* o) {
     if (o->precision < 0 || o->precision > 2) throw SgttError(-1, "invalid precision option");
     if (o->inner_rhs_eps < 0.0 || o->cycle_rhs_factor < 0.0) throw SgttError(-1, "invalid truncation option");
     p.inner_rhs_eps = o->inner_rhs_eps;
+    if (o->inner_mode < 0 || o->inner_mode > 1) throw SgttError(-1, "invalid inner_mode option");
+    p.inner_mode = o->inner_mode;
     p.precision = o->precision;
   }
   return p;
@@ -695,6 +743,7 @@ sgtt_solve_opts default_opts() {
   o.precision = 0;
   o.inner_rhs_eps = 0.0;
   o.cycle_rhs_factor = 0.0;
+  o.inner_mode = 0;
   return o;
 }
 

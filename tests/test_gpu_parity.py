@@ -168,6 +168,21 @@ def test_preconditioner_matches_oracle(sg, ctx, tiny):
     assert np.linalg.norm(got - want) <= 1e-6 * np.linalg.norm(want)
 
 
+def test_preconditioner_exact_inner_matches_oracle(sg, ctx, c1):
+    # velocity block (F_0 + C)^-1 applied exactly (time stepping on the full
+    # tensor, BCR spatial solves), compressed at 1e-13: equals the oracle's
+    # exact mean-based preconditioner
+    P, S = c1
+    _flush("precondition exact inner c1")
+    r = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (3, 5), (2, 4), 19)
+    out = S.precondition(_pair_buf(S, r, 32, 256), eps_krylov=1e-13, inner_eps=1e-13, inner_mode=1)
+    ref_u, ref_p = MeanLSC(P, None, "full").apply_full_exact(tt.full(r[0]), tt.full(r[1]))
+    want = np.concatenate([ref_u.ravel(), ref_p.ravel()])
+    got = tt.pair_full(out.cores())
+    # Gram-based TT-SVD of the full result: about sqrt(u) relative accuracy
+    assert np.linalg.norm(got - want) <= 1e-8 * np.linalg.norm(want)
+
+
 def test_solve_c1_stokes_to_1e8(sg, ctx, c1):
     P, S = c1
     _flush("solve C1 Stokes")
@@ -188,6 +203,17 @@ def test_solve_c1_stokes_to_1e8(sg, ctx, c1):
     zg = np.concatenate([xu.ravel(), xp.ravel()])
     assert np.linalg.norm(zg - zd) <= 1e-7 * np.linalg.norm(zd)
     assert abs(S.residual(b, x) - rel) <= 1e-3 * rel + 1e-14
+
+
+def test_solve_c1_exact_inner_to_1e8(sg, ctx, c1):
+    P, S = c1
+    _flush("solve c1 exact inner")
+    x, st, rc = S.solve(S.rhs(), S.pair(64, 1024), restart=20, relax=1, inner_mode=1)
+    assert rc == 0 and st["rel_residual"] <= 1e-8
+    bo = P.rhs()
+    u, p = P.solve_direct(tt.full(bo[0]), tt.full(bo[1]))
+    zd = np.concatenate([u.ravel(), p.ravel()])
+    assert np.linalg.norm(tt.pair_full(x.cores()) - zd) <= 1e-7 * np.linalg.norm(zd)
 
 
 @pytest.mark.parametrize("precision", [1, 2])

@@ -103,6 +103,20 @@ def test_picard_step_solve_c1(c1_sys):
     del r
 
 
+def test_picard_step_solve_c1_exact_inner(c1_sys):
+    # time-stepped mean solve with the time-averaged convection as the
+    # velocity block: still reaches the exact solution of the Picard system
+    P, prior, S = c1_sys
+    _flush("picard step solve c1 exact inner")
+    b = S.rhs(S.pair(64, 512))
+    x, st, rc = S.solve(b, S.pair(64, 1024), restart=20, relax=1, inner_mode=1)
+    assert rc == 0 and st["rel_residual"] <= 1e-8
+    bu, bp = P.rhs(prior, eps_rhs=1e-12)
+    u, p = P.solve_direct(tt.full(bu), tt.full(bp), P.convection(prior, 1e-12))
+    zd = np.concatenate([u.ravel(), p.ravel()])
+    assert np.linalg.norm(tt.pair_full(x.cores()) - zd) <= 1e-7 * np.linalg.norm(zd)
+
+
 def test_picard_driver_tiny(sg, ctx):
     _flush("picard driver tiny")
     P = Problem(CONFIGS["tiny"])

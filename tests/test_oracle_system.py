@@ -265,3 +265,15 @@ def test_picard_direct_contracts(tiny):
     its, res = picard_direct(tiny, 3)
     assert len(its) == 4 and len(res) == 4
     assert all(res[i + 1] < 0.2 * res[i] for i in range(3))
+
+
+def test_exact_mean_solve_inverts_mean_matrix(tiny):
+    # (F_0 + C) applied to the exact mean solve gives back the right-hand side
+    from oracle.solver import MeanLSC
+    P = tiny
+    prec = MeanLSC(P, None, "full")
+    g = np.random.default_rng(3)
+    Y = g.standard_normal((P.nt, P.n_xi, P.n_u))
+    V = prec.mean_solve_exact_full(Y)
+    back = prec._mean_apply_full(V)
+    assert np.linalg.norm(back - Y) <= 1e-12 * np.linalg.norm(Y)
