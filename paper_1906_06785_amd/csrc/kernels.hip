@@ -5,7 +5,9 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <stdexcept>
 #include <type_traits>
 #include <vector>
@@ -882,7 +884,7 @@ __global__ __launch_bounds__(64) void k_sg_convection(int nxi, int n_u, int ns, 
 }
 
 // ------------------------------------------------------------------ block cyclic reduction
-constexpr int BCR_CB = 32, BCR_MAXBS = 256, BCR_PF = 8;
+constexpr int BCR_MAXBS = 256;
 
 // One pass of a block cyclic reduction solve.  Rows = scalar unknowns of one
 // component; component z of a vector V with row stride ld starts at
@@ -891,22 +893,24 @@ constexpr int BCR_CB = 32, BCR_MAXBS = 256, BCR_PF = 8;
 // (solve == 0; out goes to B in place), and V_{in} = the solution X for the
 // neighbours of the top / backward passes (solve == 1; out goes to X).  No op
 // reads a block that the pass writes, so every op spreads its row groups
-// (rows [64 g, 64 g + 64), grid z) over workgroups.  BCR_CB combined columns
-// per workgroup (component-major: combined column j is column j % ncols of
+// (rows [64 g, 64 g + 64), grid z) over workgroups.  CB combined columns per
+// workgroup (component-major: combined column j is column j % ncols of
 // component j / ncols), on the FP64 matrix cores: wave w owns row tile
-// 4g + w times two 16-column tiles (v_mfma_f64_16x16x4: lane l supplies
+// 4g + w times CB/16 column tiles (v_mfma_f64_16x16x4: lane l supplies
 // M[row l%16][k l/16] and V[k l/16][col l%16]; accumulator item v is row
-// 4v + l/16).  Inputs are staged in LDS; the next k-step's M fragment is
-// loaded while the current one is multiplied.
+// 4v + l/16).  Inputs are staged in LDS; the M fragments of the next PF
+// k-steps are in flight while the current ones are multiplied.  CB and PF
+// are chosen per factor and column count by timing (bcr_solve).
+template <int CB, int PF>
 __global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict__ start, const int* __restrict__ op_out,
                                                   const int* __restrict__ op_self, const int* __restrict__ op_nterm,
                                                   const int* __restrict__ op_in, const long* __restrict__ op_off,
                                                   const double* __restrict__ op_coef, const double* __restrict__ data,
                                                   double* __restrict__ B, long ldb, double* __restrict__ X, long ldx,
                                                   int solve, int ncols, int ncomp, long comp_rows) {
-  __shared__ double xs[BCR_MAXBS + 4][BCR_CB + 1];
+  __shared__ double xs[BCR_MAXBS + 4][CB + 1];
   const int o = op0 + blockIdx.x;
-  const int j0 = blockIdx.y * BCR_CB;
+  const int j0 = blockIdx.y * CB;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int lr = lane % 16, lk = lane / 16;
   const int ob = op_out[o];
@@ -921,12 +925,13 @@ __global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict
   };
   double* out = solve ? X : B;
   const long ldo = solve ? ldx : ldb;
-  dbl4 acc[2];
-  acc[0] = dbl4{0.0, 0.0, 0.0, 0.0};
-  acc[1] = dbl4{0.0, 0.0, 0.0, 0.0};
+  constexpr int NCT = CB / 16;
+  dbl4 acc[NCT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) acc[ct] = dbl4{0.0, 0.0, 0.0, 0.0};
   if (active && op_self[o]) {
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct)
+    for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = rt * 16 + 4 * v + lk, j = j0 + ct * 16 + lr;
@@ -945,41 +950,41 @@ __global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict
     const double* src = from_x ? X : B;
     const long lds = from_x ? ldx : ldb;
     __syncthreads();
-    for (int e = tid; e < bi4 * BCR_CB; e += blockDim.x) {
-      const int k = e / BCR_CB, jj = e % BCR_CB, j = j0 + jj;
+    for (int e = tid; e < bi4 * CB; e += blockDim.x) {
+      const int k = e / CB, jj = e % CB, j = j0 + jj;
       xs[k][jj] = (k < bi && j < ctot) ? src[addr(i0 + k, j, lds)] : 0.0;
     }
     __syncthreads();
     if (!active) continue;
-    // M fragments stream from memory: BCR_PF k-steps are kept in flight
-    double an[BCR_PF];
+    // M fragments stream from memory: PF k-steps are kept in flight
+    double an[PF];
 #pragma unroll
-    for (int d = 0; d < BCR_PF; ++d) {
+    for (int d = 0; d < PF; ++d) {
       const int kk = 4 * d + lk;
       an[d] = (ra < bo && kk < bi) ? M[(long)kk * bo + ra] : 0.0;
     }
-    for (int k = 0; k < bi4; k += 4 * BCR_PF) {
-      double a[BCR_PF];
+    for (int k = 0; k < bi4; k += 4 * PF) {
+      double a[PF];
 #pragma unroll
-      for (int d = 0; d < BCR_PF; ++d) a[d] = coef * an[d];
+      for (int d = 0; d < PF; ++d) a[d] = coef * an[d];
 #pragma unroll
-      for (int d = 0; d < BCR_PF; ++d) {
-        const int kk = k + 4 * (BCR_PF + d) + lk;
+      for (int d = 0; d < PF; ++d) {
+        const int kk = k + 4 * (PF + d) + lk;
         an[d] = (ra < bo && kk < bi) ? M[(long)kk * bo + ra] : 0.0;
       }
 #pragma unroll
-      for (int d = 0; d < BCR_PF; ++d) {
+      for (int d = 0; d < PF; ++d) {
         const int kr = k + 4 * d;
         if (kr >= bi4) break;
-        const double b0 = xs[kr + lk][lr], b1 = xs[kr + lk][16 + lr];
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[d], b0, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[d], b1, acc[1], 0, 0, 0);
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+          acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[d], xs[kr + lk][ct * 16 + lr], acc[ct], 0, 0, 0);
       }
     }
   }
   if (!active) return;
 #pragma unroll
-  for (int ct = 0; ct < 2; ++ct)
+  for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = rt * 16 + 4 * v + lk, j = j0 + ct * 16 + lr;
@@ -1447,18 +1452,99 @@ void sg_convection_full(hipStream_t s, int nt, int nxi, int n_u, int ns, int nal
                      ramp, gall, hrow, hl, hk, hv, ref, hh, sign, out);
 }
 
-void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols) {
-  if (ncols <= 0 || f.npass == 0) return;
-  if (f.maxbs > BCR_MAXBS) throw std::runtime_error("block cyclic reduction: block larger than 256");
-  ProfScope ps(KC_BCR, s, 8.0 * (f.ndata + 3.0 * ncomp * (double)f.n * ncols),
-               2.0 * f.ndata * ncols * ncomp);
+namespace {
+// the (CB, PF) variants of k_bcr_pass that the tuner chooses from
+struct BcrVariant {
+  int cb;
+  decltype(&k_bcr_pass<32, 8>) fn;
+};
+const BcrVariant kBcrVariants[] = {{32, k_bcr_pass<32, 8>}, {32, k_bcr_pass<32, 16>}, {16, k_bcr_pass<16, 8>},
+                                   {16, k_bcr_pass<16, 16>}, {64, k_bcr_pass<64, 8>}, {32, k_bcr_pass<32, 4>}};
+constexpr int kNumBcrVariants = sizeof(kBcrVariants) / sizeof(kBcrVariants[0]);
+std::mutex g_bcr_mu;
+std::map<std::tuple<const double*, int, int>, int> g_bcr_choice;   // (factor, ncols, ncomp) -> variant
+
+void bcr_run(hipStream_t s, const BcrDev& f, int var, int ncomp, double* B, long ldb, double* X, long ldx, int ncols) {
+  const BcrVariant& v = kBcrVariants[var];
   for (int p = 0; p < f.npass; ++p) {
     const int o0 = f.pass_begin[p], no = f.pass_begin[p + 1] - o0;
     if (no <= 0) continue;
-    hipLaunchKernelGGL(k_bcr_pass, dim3(no, cdiv((long)ncomp * ncols, BCR_CB), cdiv(f.maxbs, 64)), dim3(256), 0, s,
-                       o0, f.start, f.op_out, f.op_self, f.op_nterm, f.op_in, f.op_off, f.op_coef, f.data, B, ldb, X,
-                       ldx, p >= f.nfwd ? 1 : 0, ncols, ncomp, (long)f.n);
+    hipLaunchKernelGGL(v.fn, dim3(no, cdiv((long)ncomp * ncols, v.cb), cdiv(f.maxbs, 64)), dim3(256), 0, s, o0, f.start,
+                       f.op_out, f.op_self, f.op_nterm, f.op_in, f.op_off, f.op_coef, f.data, B, ldb, X, ldx,
+                       p >= f.nfwd ? 1 : 0, ncols, ncomp, (long)f.n);
   }
+}
+
+// time every variant on scratch copies of the right-hand side; keep the fastest
+int bcr_tune(hipStream_t s, const BcrDev& f, int ncomp, const double* B, long ldb, int ncols) {
+  const long rows = (long)ncomp * f.n;
+  double *b0 = nullptr, *bw = nullptr, *xw = nullptr;
+  if (hipMalloc(&b0, sizeof(double) * rows * ncols) != hipSuccess ||
+      hipMalloc(&bw, sizeof(double) * rows * ncols) != hipSuccess ||
+      hipMalloc(&xw, sizeof(double) * rows * ncols) != hipSuccess) {
+    (void)hipGetLastError();
+    for (double* p : {b0, bw, xw})
+      if (p) (void)hipFree(p);
+    return 0;
+  }
+  copy2d(s, (int)rows, ncols, B, ldb, b0, ncols, 1.0, nullptr, 0);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int v = 0; v < kNumBcrVariants; ++v) {
+    float tot = 0.f;
+    for (int rep = 0; rep < 3; ++rep) {
+      copy2d(s, (int)rows, ncols, b0, ncols, bw, ncols, 1.0, nullptr, 0);
+      (void)hipEventRecord(e0, s);
+      bcr_run(s, f, v, ncomp, bw, ncols, xw, ncols, ncols);
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) tot += ms;   // the first run warms the caches
+    }
+    if (tot < best_ms) {
+      best_ms = tot;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  for (double* p : {b0, bw, xw}) (void)hipFree(p);
+  return best;
+}
+}  // namespace
+
+void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols) {
+  if (ncols <= 0 || f.npass == 0) return;
+  if (f.maxbs > BCR_MAXBS) throw std::runtime_error("block cyclic reduction: block larger than 256");
+  int var = 0;
+  {
+    const auto key = std::make_tuple((const double*)f.data, ncols, ncomp);
+    std::unique_lock<std::mutex> lk(g_bcr_mu);
+    auto it = g_bcr_choice.find(key);
+    if (it != g_bcr_choice.end()) {
+      var = it->second;
+    } else {
+      lk.unlock();
+      const bool was = prof_enabled();
+      prof_enable(false);
+      var = bcr_tune(s, f, ncomp, B, ldb, ncols);
+      prof_enable(was);
+      lk.lock();
+      g_bcr_choice[key] = var;
+    }
+  }
+  ProfScope ps(KC_BCR, s, 8.0 * (f.ndata + 3.0 * ncomp * (double)f.n * ncols), 2.0 * f.ndata * ncols * ncomp);
+  bcr_run(s, f, var, ncomp, B, ldb, X, ldx, ncols);
+}
+
+int bcr_choice_count() {
+  std::lock_guard<std::mutex> lk(g_bcr_mu);
+  return (int)g_bcr_choice.size();
 }
 
 void hessenberg_lsq(hipStream_t s, const double* H, int ld, int k, const double* beta, double* y, double* resid) {
