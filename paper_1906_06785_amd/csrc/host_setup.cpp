@@ -596,6 +596,50 @@ void parallel_for(int n, F&& f) {
 }
 }  // namespace
 
+namespace {
+// in-place inverse of a dense row-major n x n matrix by Gauss-Jordan with
+// partial pivoting; the row updates of each pivot run on host threads
+bool dense_inverse_rowmajor_par(int n, double* A) {
+  std::vector<double> I((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = std::fabs(A[(size_t)k * n + k]);
+    for (int r = k + 1; r < n; ++r)
+      if (std::fabs(A[(size_t)r * n + k]) > best) { best = std::fabs(A[(size_t)r * n + k]); p = r; }
+    if (best == 0.0) return false;
+    if (p != k)
+      for (int c = 0; c < n; ++c) {
+        std::swap(A[(size_t)k * n + c], A[(size_t)p * n + c]);
+        std::swap(I[(size_t)k * n + c], I[(size_t)p * n + c]);
+      }
+    const double inv = 1.0 / A[(size_t)k * n + k];
+    for (int c = 0; c < n; ++c) {
+      A[(size_t)k * n + c] *= inv;
+      I[(size_t)k * n + c] *= inv;
+    }
+    const double* ak = A + (size_t)k * n;
+    const double* ik = I.data() + (size_t)k * n;
+    const int nchunk = std::min(n, 64);
+    parallel_for(nchunk, [&](int ch) {
+      for (int r = ch; r < n; r += nchunk) {
+        if (r == k) continue;
+        const double fct = A[(size_t)r * n + k];
+        if (fct == 0.0) continue;
+        double* ar = A + (size_t)r * n;
+        double* ir = I.data() + (size_t)r * n;
+        for (int c = 0; c < n; ++c) {
+          ar[c] -= fct * ak[c];
+          ir[c] -= fct * ik[c];
+        }
+      }
+    });
+  }
+  std::copy(I.begin(), I.end(), A);
+  return true;
+}
+}  // namespace
+
 void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& blocks, BcrFactor& f,
                 std::string& err) {
   const int n = pat.nrows, nb = (int)blocks.size() - 1;
@@ -638,15 +682,16 @@ void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& bloc
     f.data.insert(f.data.end(), m.begin(), m.end());
     return off;
   };
+  constexpr int NT = BcrFactor::NT, NTOP = 8;
   struct Op {
-    int out, self, nterm, in[3];
-    int64_t off[3];
-    double coef[3];
+    int out, self, nterm, in[NT];
+    int64_t off[NT];
+    double coef[NT];
   };
   std::vector<std::vector<Op>> fwd, bwd;
   bool ok = true;
   int np = nb;
-  while (np > 1) {
+  while (np > NTOP) {
     // odd positions: D^-1, D^-1 L, D^-1 U
     const int nodd = np / 2, nev = (np + 1) / 2;
     std::vector<std::vector<double>> Dinv(np), Bt(np), Dl(np);
@@ -743,18 +788,39 @@ void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& bloc
     U.swap(U2);
     np = nev;
   }
+  std::vector<Op> top;
   if (ok) {
-    std::vector<double> Dt = D[0];
-    if (!dense_inverse(bs(ob[0]), Dt.data())) ok = false;
-    if (ok) {
+    // dense system of the remaining np <= NTOP positions, inverted on the host
+    std::vector<int> off0(np + 1, 0);
+    for (int p = 0; p < np; ++p) off0[p + 1] = off0[p] + bs(ob[p]);
+    const int nd = off0[np];
+    std::vector<double> A((size_t)nd * nd, 0.0);   // row-major
+    auto place = [&](int p, int q, const std::vector<double>& m) {   // m: bs(p) x bs(q), column-major
+      const int np_ = bs(ob[p]), nq = bs(ob[q]);
+      for (int c = 0; c < nq; ++c)
+        for (int r = 0; r < np_; ++r) A[(size_t)(off0[p] + r) * nd + off0[q] + c] = m[(size_t)c * np_ + r];
+    };
+    for (int p = 0; p < np; ++p) {
+      place(p, p, D[p]);
+      if (p > 0) place(p, p - 1, L[p]);
+      if (p + 1 < np) place(p, p + 1, U[p]);
+    }
+    if (!dense_inverse_rowmajor_par(nd, A.data())) ok = false;
+    for (int q = 0; ok && q < np; ++q) {
       Op o{};
-      o.out = ob[0];
+      o.out = ob[q];
       o.self = 0;
-      o.in[0] = ob[0];
-      o.off[0] = put(Dt);
-      o.coef[0] = 1.0;
-      o.nterm = 1;
-      fwd.push_back({o});   // the top solve runs after the forward passes
+      const int nq = bs(ob[q]);
+      for (int p = 0; p < np; ++p) {
+        const int npp = bs(ob[p]);
+        std::vector<double> blk((size_t)nq * npp);   // column-major nq x npp
+        for (int c = 0; c < npp; ++c)
+          for (int r = 0; r < nq; ++r) blk[(size_t)c * nq + r] = A[(size_t)(off0[q] + r) * nd + off0[p] + c];
+        o.in[o.nterm] = ob[p];
+        o.off[o.nterm] = put(blk);
+        o.coef[o.nterm++] = 1.0;
+      }
+      top.push_back(o);
     }
   }
   if (!ok) {
@@ -766,7 +832,7 @@ void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& bloc
       f.op_out.push_back(o.out);
       f.op_self.push_back(o.self);
       f.op_nterm.push_back(o.nterm);
-      for (int t = 0; t < 3; ++t) {
+      for (int t = 0; t < NT; ++t) {
         f.op_in.push_back(t < o.nterm ? o.in[t] : 0);
         f.op_off.push_back(t < o.nterm ? o.off[t] : 0);
         f.op_coef.push_back(t < o.nterm ? o.coef[t] : 0.0);
@@ -775,9 +841,16 @@ void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& bloc
     f.pass_begin.push_back((int)f.op_out.size());
   };
   f.pass_begin.push_back(0);
-  f.nfwd = (int)fwd.size() - 1;   // the last list of fwd is the top solve
-  for (const auto& ops : fwd) emit(ops);
-  for (int l = (int)bwd.size() - 1; l >= 0; --l) emit(bwd[l]);
+  for (const auto& ops : fwd) {
+    emit(ops);
+    f.pass_mode.push_back(0);
+  }
+  emit(top);
+  f.pass_mode.push_back(2);
+  for (int l = (int)bwd.size() - 1; l >= 0; --l) {
+    emit(bwd[l]);
+    f.pass_mode.push_back(1);
+  }
 }
 
 

@@ -104,18 +104,23 @@ void lsc_middle_values(const HostProblem& hp, const double* Svals, double* out);
 // col-major): forward passes (levels 0, 1, ...) update the even positions'
 // right-hand sides b in place from their odd neighbours' b; then the top
 // solve and the backward passes (top level down) write the solution x of the
-// odd positions from their own b and their neighbours' x.
+// odd positions from their own b and their neighbours' x.  The reduction stops
+// at 8 blocks or fewer; their system is solved with a dense inverse (one op
+// per block, one term per block of the top system).
 struct BcrFactor {
   int n = 0, nblk = 0, maxbs = 0;
   std::vector<int> start;              // nblk + 1
   std::vector<int> op_out, op_self;    // per op: output block, 1 = add v_out
-  std::vector<int> op_nterm;           // per op: number of terms (<= 3)
-  std::vector<int> op_in;              // 3 per op
-  std::vector<int64_t> op_off;         // 3 per op: matrix offsets in data
-  std::vector<double> op_coef;         // 3 per op
+  static constexpr int NT = 8;          // terms per op (at most)
+  std::vector<int> op_nterm;           // per op: number of terms
+  std::vector<int> op_in;              // NT per op
+  std::vector<int64_t> op_off;         // NT per op: matrix offsets in data
+  std::vector<double> op_coef;         // NT per op
   std::vector<int> pass_begin;         // op ranges of the passes (npass + 1)
-  int nfwd = 0;                        // passes [0, nfwd) reduce the right-hand side in place;
-                                       // the rest (top solve, back substitution) write the solution
+  // per pass: 0 reduce the right-hand side in place (inputs from b);
+  // 2 solve the top system (inputs from b, output x); 1 back substitution
+  // (own block from b, neighbours from x, output x)
+  std::vector<int> pass_mode;
   std::vector<double> data;
 };
 void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& blocks, BcrFactor& f,

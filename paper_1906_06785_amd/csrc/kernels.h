@@ -163,11 +163,12 @@ void sg_convection_full(hipStream_t s, int nt, int nxi, int n_u, int ns, int nal
 // Block cyclic reduction solve (factor built on the host): device copies of
 // the op lists and block data; pass_begin stays on the host.
 struct BcrDev {
-  int n = 0, nblk = 0, maxbs = 0, npass = 0, nfwd = 0;
+  int n = 0, nblk = 0, maxbs = 0, npass = 0;
   double ndata = 0;                 // doubles of block data (for the profiler)
   std::vector<int> pass_begin;      // host: npass + 1
+  std::vector<int> pass_mode;       // host: 0 reduce, 2 top solve, 1 back substitution
   int *start = nullptr, *op_out = nullptr, *op_self = nullptr, *op_nterm = nullptr, *op_in = nullptr;
-  long* op_off = nullptr;
+  long* op_off = nullptr;            // 8 terms per op (op_in, op_off, op_coef)
   double *op_coef = nullptr, *data = nullptr;
 };
 // X <- A^-1 B for ncols columns of ncomp components (rows of one component;

@@ -884,30 +884,31 @@ __global__ __launch_bounds__(64) void k_sg_convection(int nxi, int n_u, int ns, 
 }
 
 // ------------------------------------------------------------------ block cyclic reduction
-constexpr int BCR_MAXBS = 256;
+constexpr int BCR_MAXBS = 256, BCR_NT = 8;
 
 // One pass of a block cyclic reduction solve.  Rows = scalar unknowns of one
 // component; component z of a vector V with row stride ld starts at
-// V + z*comp_rows*ld.  Block out <- [B_out] + sum_t coef_t M_t V_{in_t} with
-// V_{in} = B_in for the op's own block and for every input of a forward pass
-// (solve == 0; out goes to B in place), and V_{in} = the solution X for the
-// neighbours of the top / backward passes (solve == 1; out goes to X).  No op
-// reads a block that the pass writes, so every op spreads its row groups
-// (rows [64 g, 64 g + 64), grid z) over workgroups.  CB combined columns per
-// workgroup (component-major: combined column j is column j % ncols of
-// component j / ncols), on the FP64 matrix cores: wave w owns row tile
-// 4g + w times CB/16 column tiles (v_mfma_f64_16x16x4: lane l supplies
-// M[row l%16][k l/16] and V[k l/16][col l%16]; accumulator item v is row
-// 4v + l/16).  Inputs are staged in LDS; the M fragments of the next PF
-// k-steps are in flight while the current ones are multiplied.  CB and PF
-// are chosen per factor and column count by timing (bcr_solve).
+// V + z*comp_rows*ld.  Block out <- [B_out] + sum_t coef_t M_t V_{in_t}
+// (at most BCR_NT terms).  mode 0 (forward reduction): every input from B,
+// out to B in place; mode 2 (top system): every input from B, out to X;
+// mode 1 (back substitution): the op's own block from B, the neighbours
+// from the solution X, out to X.  No op reads a block that the pass writes,
+// so every op spreads its row groups (rows [64 g, 64 g + 64), grid z) over
+// workgroups.  CB combined columns per workgroup (component-major: combined
+// column j is column j % ncols of component j / ncols), on the FP64 matrix
+// cores: wave w owns row tile 4g + w times CB/16 column tiles
+// (v_mfma_f64_16x16x4: lane l supplies M[row l%16][k l/16] and V[k l/16][col
+// l%16]; accumulator item v is row 4v + l/16).  Inputs are staged in LDS; the
+// M fragments of the next PF k-steps are in flight while the current ones are
+// multiplied.  CB and PF are chosen per factor and column count by timing
+// (bcr_solve).
 template <int CB, int PF>
 __global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict__ start, const int* __restrict__ op_out,
                                                   const int* __restrict__ op_self, const int* __restrict__ op_nterm,
                                                   const int* __restrict__ op_in, const long* __restrict__ op_off,
                                                   const double* __restrict__ op_coef, const double* __restrict__ data,
                                                   double* __restrict__ B, long ldb, double* __restrict__ X, long ldx,
-                                                  int solve, int ncols, int ncomp, long comp_rows) {
+                                                  int mode, int ncols, int ncomp, long comp_rows) {
   __shared__ double xs[BCR_MAXBS + 4][CB + 1];
   const int o = op0 + blockIdx.x;
   const int j0 = blockIdx.y * CB;
@@ -923,8 +924,8 @@ __global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict
     const int comp = j / ncols, c = j - comp * ncols;
     return ((long)comp * comp_rows + row) * ld + c;
   };
-  double* out = solve ? X : B;
-  const long ldo = solve ? ldx : ldb;
+  double* out = mode ? X : B;
+  const long ldo = mode ? ldx : ldb;
   constexpr int NCT = CB / 16;
   dbl4 acc[NCT];
 #pragma unroll
@@ -941,12 +942,12 @@ __global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict
   const int nterm = op_nterm[o];
   const int ra = rt * 16 + lr;
   for (int t = 0; t < nterm; ++t) {
-    const int ib = op_in[3 * o + t];
+    const int ib = op_in[BCR_NT * o + t];
     const int i0 = start[ib], bi = start[ib + 1] - i0;
     const int bi4 = (bi + 3) & ~3;
-    const double* M = data + op_off[3 * o + t];
-    const double coef = op_coef[3 * o + t];
-    const bool from_x = solve && ib != ob;
+    const double* M = data + op_off[BCR_NT * o + t];
+    const double coef = op_coef[BCR_NT * o + t];
+    const bool from_x = mode == 1 && ib != ob;
     const double* src = from_x ? X : B;
     const long lds = from_x ? ldx : ldb;
     __syncthreads();
@@ -1471,7 +1472,7 @@ void bcr_run(hipStream_t s, const BcrDev& f, int var, int ncomp, double* B, long
     if (no <= 0) continue;
     hipLaunchKernelGGL(v.fn, dim3(no, cdiv((long)ncomp * ncols, v.cb), cdiv(f.maxbs, 64)), dim3(256), 0, s, o0, f.start,
                        f.op_out, f.op_self, f.op_nterm, f.op_in, f.op_off, f.op_coef, f.data, B, ldb, X, ldx,
-                       p >= f.nfwd ? 1 : 0, ncols, ncomp, (long)f.n);
+                       f.pass_mode[p], ncols, ncomp, (long)f.n);
   }
 }
 

@@ -84,7 +84,8 @@ BcrDev upload_bcr(Ctx& c, const BcrFactor& f) {
   d.nblk = f.nblk;
   d.maxbs = f.maxbs;
   d.npass = (int)f.pass_begin.size() - 1;
-  d.nfwd = f.nfwd;
+  d.pass_mode = f.pass_mode;
+  if (BcrFactor::NT != 8) throw SgttError(-6, "block cyclic reduction: op layout mismatch");
   d.pass_begin = f.pass_begin;
   d.ndata = (double)f.data.size();
   d.start = dev_upload(c, f.start);
