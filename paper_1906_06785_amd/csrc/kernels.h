@@ -173,7 +173,9 @@ struct BcrDev {
 };
 // X <- A^-1 B for ncols columns of ncomp components (rows of one component;
 // component z of B at B + z * n * ldb, of X at X + z * n * ldx).  B is
-// overwritten (reduced right-hand sides); X must not overlap B.
+// overwritten (reduced right-hand sides); X must not overlap B.  With the op
+// list of a block-tridiagonal product (one mode-3 pass) the same call adds
+// A X to B instead.
 void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols);
 
 

@@ -892,7 +892,8 @@ constexpr int BCR_MAXBS = 256, BCR_NT = 8;
 // (at most BCR_NT terms).  mode 0 (forward reduction): every input from B,
 // out to B in place; mode 2 (top system): every input from B, out to X;
 // mode 1 (back substitution): the op's own block from B, the neighbours
-// from the solution X, out to X.  No op reads a block that the pass writes,
+// from the solution X, out to X; mode 3 (block-tridiagonal product): every
+// input from X, out to B (added to B_out).  No op reads a block that the pass writes,
 // so every op spreads its row groups (rows [64 g, 64 g + 64), grid z) over
 // workgroups.  CB combined columns per workgroup (component-major: combined
 // column j is column j % ncols of component j / ncols), on the FP64 matrix
@@ -924,8 +925,8 @@ __global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict
     const int comp = j / ncols, c = j - comp * ncols;
     return ((long)comp * comp_rows + row) * ld + c;
   };
-  double* out = mode ? X : B;
-  const long ldo = mode ? ldx : ldb;
+  double* out = (mode == 1 || mode == 2) ? X : B;
+  const long ldo = (mode == 1 || mode == 2) ? ldx : ldb;
   constexpr int NCT = CB / 16;
   dbl4 acc[NCT];
 #pragma unroll
@@ -947,7 +948,7 @@ __global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict
     const int bi4 = (bi + 3) & ~3;
     const double* M = data + op_off[BCR_NT * o + t];
     const double coef = op_coef[BCR_NT * o + t];
-    const bool from_x = mode == 1 && ib != ob;
+    const bool from_x = (mode == 1 && ib != ob) || mode == 3;
     const double* src = from_x ? X : B;
     const long lds = from_x ? ldx : ldb;
     __syncthreads();
@@ -1489,6 +1490,7 @@ int bcr_tune(hipStream_t s, const BcrDev& f, int ncomp, const double* B, long ld
     return 0;
   }
   copy2d(s, (int)rows, ncols, B, ldb, b0, ncols, 1.0, nullptr, 0);
+  copy2d(s, (int)rows, ncols, b0, ncols, xw, ncols, 1.0, nullptr, 0);   // finite inputs for product passes
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);

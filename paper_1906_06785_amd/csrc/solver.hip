@@ -137,6 +137,7 @@ struct sgtt_system {
   double* Hw = nullptr;    // k1 x k2 x nxi x nxi
   double* omega = nullptr; // nt x k2 (mean-mode time factors)
   BcrDev Fbt, Xbt;         // F_avg and X = B M*^-1 B^T (block cyclic reduction)
+  BcrDev Mblk;             // tau^-1 M as dense slab blocks (time coupling of the mean solve)
   TT bu, bp;               // right-hand side
   double* Dinv = nullptr;  // 1 / diag(F_avg) on free scalar nodes
   sgtt::Mlp* mlp_collect = nullptr;   // records (r, F_avg^-1 r) pairs from mean solves
@@ -154,6 +155,7 @@ struct sgtt_system {
     Xmid.free_all();
     free_bcr(Fbt);
     free_bcr(Xbt);
+    free_bcr(Mblk);
     for (double* p : {Gnu, w1, Hw, omega, dsc, Dinv}) (void)hipFree(p);
   }
 };
@@ -552,7 +554,7 @@ struct PrecOpts {
 // columns (t, xi)), then TT-SVD (Alg. 4.1) at eps.
 TT exact_mean_solve(sgtt_system& S, const TT& y, double eps) {
   Ctx& c = S.ctx->c;
-  const int nt = S.nt, nxi = S.nxi, nu = S.nu, ns = S.ns;
+  const int nt = S.nt, nxi = S.nxi, nu = S.nu;
   const long ldw = (long)nt * nxi;
   double* Z = c.pool.get((size_t)ldw * y.r2);   // G1 x_1 G2: (nt nxi) x r2
   gemm(c.s, 1, nt, nxi * y.r2, y.r1, 1.0, y.c1, 0, y.r1, 1, y.c2, 0, (long)nxi * y.r2, 1, 0.0, Z, 0,
@@ -562,9 +564,8 @@ TT exact_mean_solve(sgtt_system& S, const TT& y, double eps) {
   c.pool.put(Z);
   double* Vn = c.pool.get((size_t)nu * ldw);    // solution, same layout
   for (int t = 0; t < nt; ++t) {
-    if (t > 0)   // y_t + tau^-1 M v_{t-1} (value set 0 of the operator pattern is M)
-      spmm(c.s, ns, 2, ns, ns, S.Kop.rowptr, S.Kop.col, S.Kop.vals, 1, S.Kop.nnz, Vn, (int)ldw, (t - 1) * nxi, nxi,
-           W, (int)ldw, t * nxi, 0, 1.0 / S.tau, 1.0);
+    if (t > 0)   // y_t + tau^-1 M v_{t-1}: M as dense slab blocks, one pass on the matrix cores
+      bcr_solve(c.s, S.Mblk, 2, W + (long)t * nxi, ldw, Vn + (long)(t - 1) * nxi, ldw, nxi);
     bcr_solve(c.s, S.Fbt, 2, W + (long)t * nxi, ldw, Vn + (long)t * nxi, ldw, nxi);
   }
   double* V = W;                                 // C order (t, xi, x), reusing the consumed right-hand side
@@ -911,6 +912,13 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
   S->Bd = upload_csr(c, hp.B, {hp.B.val.data()});
   S->Btd = upload_csr(c, hp.Bt, {hp.Bt.val.data()});
   S->Xbt = factor_bcr(c, hp.Xp, hp.Xp.val.data(), hp.p_blocks);
+  {
+    BcrFactor mf;
+    std::string err;
+    block_tridiag_matvec_ops(hp.Kff, hp.Mff.data(), 1.0 / prm.tau, hp.vel_blocks, mf, err);
+    if (!err.empty()) throw SgttError(-6, err);
+    S->Mblk = upload_bcr(c, mf);
+  }
   const int nt = S->nt, nxi = S->nxi, nall = S->nall, ns = S->ns;
   // Dirichlet lift TT over all nodes: ramp (x) e_1 (x) g_all
   std::vector<double> e1(nxi, 0.0);
