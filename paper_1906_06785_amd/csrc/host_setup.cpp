@@ -640,55 +640,6 @@ bool dense_inverse_rowmajor_par(int n, double* A) {
 }
 }  // namespace
 
-void block_tridiag_matvec_ops(const Csr& pat, const double* vals, double scale, const std::vector<int>& blocks,
-                              BcrFactor& f, std::string& err) {
-  const int n = pat.nrows, nb = (int)blocks.size() - 1;
-  f = BcrFactor();
-  f.n = n;
-  f.nblk = nb;
-  f.start = blocks;
-  std::vector<int> blk(n);
-  for (int b = 0; b < nb; ++b) {
-    f.maxbs = std::max(f.maxbs, blocks[b + 1] - blocks[b]);
-    for (int i = blocks[b]; i < blocks[b + 1]; ++i) blk[i] = b;
-  }
-  for (int i = 0; i < n; ++i)
-    for (int t = pat.rowptr[i]; t < pat.rowptr[i + 1]; ++t)
-      if (std::abs(blk[i] - blk[pat.col[t]]) > 1) {
-        err = "matrix is not block tridiagonal in the slab ordering";
-        return;
-      }
-  auto bs = [&](int b) { return blocks[b + 1] - blocks[b]; };
-  f.pass_begin.push_back(0);
-  for (int b = 0; b < nb; ++b) {
-    f.op_out.push_back(b);
-    f.op_self.push_back(1);
-    int nterm = 0;
-    for (int c = std::max(0, b - 1); c <= std::min(nb - 1, b + 1); ++c) {
-      const int r0 = blocks[b], nr = bs(b), c0 = blocks[c], nc = bs(c);
-      std::vector<double> m((size_t)nr * nc, 0.0);
-      for (int i = 0; i < nr; ++i)
-        for (int t = pat.rowptr[r0 + i]; t < pat.rowptr[r0 + i + 1]; ++t) {
-          const int j = pat.col[t] - c0;
-          if (j >= 0 && j < nc) m[(size_t)j * nr + i] += scale * vals[t];
-        }
-      f.op_in.push_back(c);
-      f.op_off.push_back((int64_t)f.data.size());
-      f.op_coef.push_back(1.0);
-      f.data.insert(f.data.end(), m.begin(), m.end());
-      ++nterm;
-    }
-    for (int t = nterm; t < BcrFactor::NT; ++t) {
-      f.op_in.push_back(0);
-      f.op_off.push_back(0);
-      f.op_coef.push_back(0.0);
-    }
-    f.op_nterm.push_back(nterm);
-  }
-  f.pass_begin.push_back(nb);
-  f.pass_mode.push_back(3);
-}
-
 void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& blocks, BcrFactor& f,
                 std::string& err) {
   const int n = pat.nrows, nb = (int)blocks.size() - 1;

@@ -119,18 +119,13 @@ struct BcrFactor {
   std::vector<int> pass_begin;         // op ranges of the passes (npass + 1)
   // per pass: 0 reduce the right-hand side in place (inputs from b);
   // 2 solve the top system (inputs from b, output x); 1 back substitution
-  // (own block from b, neighbours from x, output x); 3 product added to b
-  // (inputs from x)
+  // (own block from b, neighbours from x, output x)
   std::vector<int> pass_mode;
   std::vector<double> data;
 };
 void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& blocks, BcrFactor& f,
                 std::string& err);
-// The product  b <- b + scale * A x  for a block-tridiagonal A in the same
-// op format: one pass (mode 3: inputs from x, output added to b), one op per
-// block with the dense blocks (b, b-1), (b, b), (b, b+1).
-void block_tridiag_matvec_ops(const Csr& pat, const double* vals, double scale, const std::vector<int>& blocks,
-                              BcrFactor& f, std::string& err);
+
 
 
 

@@ -86,6 +86,9 @@ void copy2d(hipStream_t s, int rows, int cols, const double* src, long lds, doub
 
 // dst[j*ldd + i] = src[i*lds + j] for i < rows, j < cols
 void transpose_copy(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst, long ldd);
+// batch transposes: source b at src + b*sbatch, destination at dst + b*dbatch
+void transpose_copy_batched(hipStream_t s, int batch, int rows, int cols, const double* src, long sbatch, long lds,
+                            double* dst, long dbatch, long ldd);
 
 // CSR SpMM over the space index with several value arrays sharing a pattern
 // and `ncomp` velocity components:
@@ -93,9 +96,21 @@ void transpose_copy(hipStream_t s, int rows, int cols, const double* src, long l
 //     alpha * sum_t vals[v*vstride + t] * x[(c*ics + col[t])*ldx + xcol0 + j]
 //     (+ beta * the old value)
 // for rows r < nrows, components c < ncomp, v < nv (<= 16), columns j < ncols.
+// max_row_nnz (> 0 when known) bounds the entries of a row; with one value
+// array and at most 32 entries a row's loads are all issued at once.
 void spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* rowptr, const int* col,
           const double* vals, int nv, long vstride, const double* x, int ldx, int xcol0, int ncols,
-          double* y, int ldy, int ycol0, int yvstep, double alpha, double beta = 0.0);
+          double* y, int ldy, int ycol0, int yvstep, double alpha, double beta = 0.0, int max_row_nnz = 0);
+
+// The same product for a square matrix with one value array in padded-row
+// (ELL) form: row r has ELL_WIDTH entries at ecol/eval[r * ELL_WIDTH ...],
+// padded with (column r, value 0); rows of the input x are at
+// (c*ics + col)*ldx + xcol0, of y at (c*ocs + r)*ldy + ycol0.
+// y = alpha * A x + beta * y.
+constexpr int ELL_WIDTH = 32;
+void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const double* eval,
+              const double* x, int ldx, int xcol0, int ncols, double* y, int ldy, int ycol0, double alpha,
+              double beta);
 
 // core1 block ops on row-major n1 x r matrices
 // out[t, col0 + a] = scale*(in[t,a] - in[t-1,a])          (kind 0: (I - C)/tau)
@@ -162,20 +177,38 @@ void sg_convection_full(hipStream_t s, int nt, int nxi, int n_u, int ns, int nal
 
 // Block cyclic reduction solve (factor built on the host): device copies of
 // the op lists and block data; pass_begin stays on the host.
+// One op of a block cyclic reduction pass: output block rows [r0, r0 + bo)
+// <- [own rows of B if flags & 1] + sum_t coef[t] * M_t * (rows
+// [in_r0[t], in_r0[t] + in_bi[t]) of X if bit t of in_x, else of B), with
+// the bo x in_bi[t] block M_t at data + off[t] in matrix-core fragment order
+// (bcr_fragment_order); the output goes to X if flags & 2, else to B.
+constexpr int BCR_NT = 8;
+constexpr int BCR_DATA_PAD = 64 * 64;   // doubles of padding behind the block data
+// Element (i, k) of a rows x cols block in fragment order: row tile i / 16,
+// k-step k / 4, lane (i % 16) + 16 (k % 4), at ((i/16) nq + k/4) 64 + lane
+// with nq = ceil(cols / 4); the tiles are zero-padded.
+inline long bcr_fragment_size(int rows, int cols) { return (long)((rows + 15) / 16) * ((cols + 3) / 4) * 64; }
+inline long bcr_fragment_index(int i, int k, int cols) {
+  return ((long)(i / 16) * ((cols + 3) / 4) + k / 4) * 64 + (i % 16) + 16 * (k % 4);
+}
+struct BcrOpDesc {
+  int r0, bo, nterm, flags;
+  int in_r0[BCR_NT];
+  int in_bi[BCR_NT];
+  int in_x, pad_[3];
+  long off[BCR_NT];
+  double coef[BCR_NT];
+};
 struct BcrDev {
   int n = 0, nblk = 0, maxbs = 0, npass = 0;
   double ndata = 0;                 // doubles of block data (for the profiler)
-  std::vector<int> pass_begin;      // host: npass + 1
-  std::vector<int> pass_mode;       // host: 0 reduce, 2 top solve, 1 back substitution
-  int *start = nullptr, *op_out = nullptr, *op_self = nullptr, *op_nterm = nullptr, *op_in = nullptr;
-  long* op_off = nullptr;            // 8 terms per op (op_in, op_off, op_coef)
-  double *op_coef = nullptr, *data = nullptr;
+  std::vector<int> pass_begin;      // host: ops of pass p are [pass_begin[p], pass_begin[p + 1])
+  BcrOpDesc* ops = nullptr;
+  double* data = nullptr;
 };
 // X <- A^-1 B for ncols columns of ncomp components (rows of one component;
 // component z of B at B + z * n * ldb, of X at X + z * n * ldx).  B is
-// overwritten (reduced right-hand sides); X must not overlap B.  With the op
-// list of a block-tridiagonal product (one mode-3 pass) the same call adds
-// A X to B instead.
+// overwritten (reduced right-hand sides); X must not overlap B.
 void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols);
 
 

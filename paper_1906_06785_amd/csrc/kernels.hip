@@ -367,12 +367,31 @@ __global__ void k_copy2d(int rows, int cols, const double* __restrict__ src, lon
   }
 }
 
-__global__ void k_transpose_copy(int rows, int cols, const double* __restrict__ src, long lds,
-                                 double* __restrict__ dst, long ldd) {
-  long total = (long)rows * cols;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    long i = e / cols, j = e % cols;
-    dst[j * ldd + i] = src[i * lds + j];
+// dst[j][i] = src[i][j] through a 32 x 32 LDS tile: both the reads (along j)
+// and the writes (along i) are coalesced.  blockDim (32, 8); tiles walk the
+// rows with a grid stride so any row count fits the grid.
+__global__ __launch_bounds__(256) void k_transpose_copy(int rows, int cols, const double* __restrict__ src, long lds,
+                                                        long sbatch, double* __restrict__ dst, long ldd, long dbatch) {
+  __shared__ double tile[32][33];
+  src += blockIdx.z * sbatch;   // batch of independent transposes along grid z
+  dst += blockIdx.z * dbatch;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int j0 = blockIdx.x * 32;
+  for (long i0 = (long)blockIdx.y * 32; i0 < rows; i0 += (long)gridDim.y * 32) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long i = i0 + ty + 8 * q;
+      const int j = j0 + tx;
+      if (i < rows && j < cols) tile[ty + 8 * q][tx] = src[i * lds + j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + ty + 8 * q;
+      const long i = i0 + tx;
+      if (i < rows && j < cols) dst[(long)j * ldd + i] = tile[tx][ty + 8 * q];
+    }
+    __syncthreads();
   }
 }
 
@@ -439,6 +458,97 @@ __global__ __launch_bounds__(256) void k_spmm(int nrows, int ics, int ocs, const
   }
 }
 
+// lane l's value, as a wave-uniform (scalar) value
+__device__ inline double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// One value array, rows of at most NZ entries: each lane holds one entry of
+// its wave's row, broadcast across the wave, so all the row's input loads
+// are issued back to back (one memory round trip per row instead of one per
+// entry).
+template <int NZ>
+__global__ __launch_bounds__(256) void k_spmm_short(int nrows, int ics, int ocs, const int* __restrict__ rowptr,
+                                                    const int* __restrict__ col, const double* __restrict__ vals,
+                                                    const double* __restrict__ x, int ldx, int xcol0, int ncols,
+                                                    double* __restrict__ y, int ldy, int ycol0, double alpha,
+                                                    double beta) {
+  static_assert(NZ <= WAVE, "one entry per lane");
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int r = blockIdx.x * (blockDim.x / WAVE) + wave;
+  const int c = blockIdx.y;
+  if (r >= nrows) return;
+  const int t0 = __builtin_amdgcn_readfirstlane(rowptr[r]);   // uniform per wave
+  const int n = __builtin_amdgcn_readfirstlane(rowptr[r + 1]) - t0;
+  double* yb = y + ((long)c * ocs + r) * ldy + ycol0;
+  if (n == 0) {
+    for (int j = lane; j < ncols; j += WAVE) yb[j] = beta != 0.0 ? beta * yb[j] : 0.0;
+    return;
+  }
+  // lanes past the row's end repeat its first column with value 0, so every
+  // load below is valid and none is predicated
+  int my_col = lane < n ? col[t0 + lane] : 0;
+  my_col = lane < n ? my_col : __builtin_amdgcn_readfirstlane(my_col);
+  const double my_val = lane < n ? vals[t0 + lane] : 0.0;
+  const double* xb = x + (long)c * ics * ldx + xcol0;
+  for (int j0 = 0; j0 < ncols; j0 += WAVE) {
+    const int j = j0 + lane;
+    const bool act = j < ncols;
+    const int jc = act ? j : ncols - 1;   // idle lanes read a valid column
+    double xv[NZ];
+#pragma unroll
+    for (int q = 0; q < NZ; ++q) xv[q] = xb[(long)__builtin_amdgcn_readlane(my_col, q) * ldx + jc];
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < NZ; ++q) acc = fma(readlane_f64(my_val, q), xv[q], acc);
+    if (act) yb[j] = alpha * acc + (beta != 0.0 ? beta * yb[j] : 0.0);
+  }
+}
+
+// Padded-row (ELL) SpMM for one value array: row r holds EW entries at
+// ecol/eval[r*EW ...], padded with (column r, value 0).  A wave computes one row for up to 64
+// columns; the row's entries sit one per lane and all of its input loads are
+// issued together.  Workgroups are remapped so that each XCD (workgroup ids
+// are dealt round-robin over the 8 XCDs) takes a contiguous range of rows:
+// neighbouring rows share most of their inputs, which then stay in that
+// XCD's L2.  The grid is a multiple of 8 workgroups.
+template <int EW>
+__global__ __launch_bounds__(256) void k_ell_spmm(int nrows, int ics, int ocs,
+                                                  const int* __restrict__ ecol, const double* __restrict__ eval,
+                                                  const double* __restrict__ x, int ldx, int xcol0, int ncols,
+                                                  double* __restrict__ y, int ldy, int ycol0, double alpha,
+                                                  double beta) {
+  static_assert(EW <= WAVE, "one entry per lane");
+  const unsigned per = gridDim.x / 8;
+  const unsigned lb = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const long r = (long)lb * (blockDim.x / WAVE) + wave;
+  const int c = blockIdx.y;
+  if (r >= nrows) return;
+  const int my_col = lane < EW ? ecol[r * EW + lane] : 0;
+  const double my_val = lane < EW ? eval[r * EW + lane] : 0.0;
+  const double* xb = x + (long)c * ics * ldx + xcol0;
+  double* yb = y + ((long)c * ocs + r) * ldy + ycol0;
+  for (int j0 = 0; j0 < ncols; j0 += WAVE) {
+    const int j = j0 + lane;
+    const bool act = j < ncols;
+    const int jc = act ? j : ncols - 1;   // idle lanes read a valid column
+    const double yo = (act && beta != 0.0) ? yb[j] : 0.0;
+    double xv[EW];
+    // padded entries (q >= n) point at row r with value 0: every load is
+    // valid, so none is predicated and all are issued back to back
+#pragma unroll
+    for (int q = 0; q < EW; ++q) xv[q] = xb[(long)__builtin_amdgcn_readlane(my_col, q) * ldx + jc];
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < EW; ++q) acc = fma(readlane_f64(my_val, q), xv[q], acc);
+    if (act) yb[j] = alpha * acc + beta * yo;
+  }
+}
+
 // ------------------------------------------------------------------ core ops
 __global__ void k_core1_op(int kind, int n1, int r, const double* __restrict__ in, int ldi, double* __restrict__ out,
                            int ldo, int col0, double scale, const double* dscale) {
@@ -502,32 +612,92 @@ __global__ void k_core2_block(int r1, int n2, int r2, const double* __restrict__
 // ------------------------------------------------------------------ truncation
 constexpr int TE_THREADS = 1024;
 constexpr int KSMALL = 96;     // max rank handled by the LDS eigen solver
+constexpr int KLD = KSMALL + 1;   // LDS row stride of its matrices (odd: rows start on different banks)
 constexpr int KCAP = 512;      // max rank of any truncation
 
-__device__ void argmax_block(double v, int idx, double* shv, int* shi, double& bv, int& bi) {
-  // block-wide argmax (ties -> smallest index)
+// sum_t L[t*N + i] * coef[t*cs] for t < j (L column-major in global memory,
+// coef in LDS): eight loads in flight, four partial sums.
+__device__ inline double col_combo(const double* __restrict__ L, long N, int i, const double* coef, int cs, int j) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int t = 0;
+  for (; t + 8 <= j; t += 8) {
+    double l[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) l[q] = L[(long)(t + q) * N + i];
+    a0 = fma(l[0], coef[(t + 0) * cs], a0);
+    a1 = fma(l[1], coef[(t + 1) * cs], a1);
+    a2 = fma(l[2], coef[(t + 2) * cs], a2);
+    a3 = fma(l[3], coef[(t + 3) * cs], a3);
+    a0 = fma(l[4], coef[(t + 4) * cs], a0);
+    a1 = fma(l[5], coef[(t + 5) * cs], a1);
+    a2 = fma(l[6], coef[(t + 6) * cs], a2);
+    a3 = fma(l[7], coef[(t + 7) * cs], a3);
+  }
+  for (; t < j; ++t) a0 = fma(L[(long)t * N + i], coef[t * cs], a0);
+  return (a0 + a1) + (a2 + a3);
+}
+
+// wave-wide dot product of two length-N vectors in global memory (result on
+// every lane): eight loads per vector in flight
+__device__ inline double wave_dot(const double* __restrict__ x, const double* __restrict__ y, int N) {
+  const int ln = threadIdx.x % WAVE;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = ln;
+  for (; i + 7 * WAVE < N; i += 8 * WAVE) {
+    double xv[8], yv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      xv[q] = x[i + q * WAVE];
+      yv[q] = y[i + q * WAVE];
+    }
+    a0 = fma(xv[0], yv[0], a0);
+    a1 = fma(xv[1], yv[1], a1);
+    a2 = fma(xv[2], yv[2], a2);
+    a3 = fma(xv[3], yv[3], a3);
+    a0 = fma(xv[4], yv[4], a0);
+    a1 = fma(xv[5], yv[5], a1);
+    a2 = fma(xv[6], yv[6], a2);
+    a3 = fma(xv[7], yv[7], a3);
+  }
+  for (; i < N; i += WAVE) a0 = fma(x[i], y[i], a0);
+  double s = (a0 + a1) + (a2 + a3);
+  for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, WAVE);
+  return s;
+}
+
+// Block-wide (max with smallest index on ties, sum) in one barrier: each wave
+// posts its partials to buffer `par` (alternate two buffers between calls),
+// then every thread combines all of them.
+__device__ inline void block_argmax_sum(double v, int idx, double sm, double* shv, int* shi, double* shs, int par,
+                                        double& bv, int& bi, double& bsum) {
   for (int o = WAVE / 2; o > 0; o >>= 1) {
-    double ov = __shfl_down(v, o, WAVE);
-    int oi = __shfl_down(idx, o, WAVE);
-    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    const double ov = __shfl_down(v, o, WAVE);
+    const int oi = __shfl_down(idx, o, WAVE);
+    sm += __shfl_down(sm, o, WAVE);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
   }
-  int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
-  __syncthreads();
-  if (l == 0) { shv[w] = v; shi[w] = idx; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int nw = blockDim.x / WAVE;
-    double best = shv[0];
-    int bidx = shi[0];
-    for (int q = 1; q < nw; ++q)
-      if (shv[q] > best || (shv[q] == best && shi[q] < bidx)) { best = shv[q]; bidx = shi[q]; }
-    shv[0] = best;
-    shi[0] = bidx;
+  const int w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  if (threadIdx.x % WAVE == 0) {
+    shv[par * 16 + w] = v;
+    shi[par * 16 + w] = idx;
+    shs[par * 16 + w] = sm;
   }
   __syncthreads();
-  bv = shv[0];
-  bi = shi[0];
-  __syncthreads();
+  bv = shv[par * 16];
+  bi = shi[par * 16];
+  bsum = shs[par * 16];
+  for (int q = 1; q < nw; ++q) {
+    const double qv = shv[par * 16 + q];
+    const int qi = shi[par * 16 + q];
+    if (qv > bv || (qv == bv && qi < bi)) {
+      bv = qv;
+      bi = qi;
+    }
+    bsum += shs[par * 16 + q];
+  }
 }
 
 __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restrict__ S, double eps,
@@ -535,10 +705,11 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
                                                           double* __restrict__ U, int kmax, double* __restrict__ L,
                                                           double* __restrict__ dwork, int* k_out, double* kept_out,
                                                           int* info, int rank_bound, int large_ok) {
-  __shared__ double T[KSMALL * KSMALL];
-  __shared__ double V[KSMALL * KSMALL];
+  __shared__ double T[KSMALL * KLD];
+  __shared__ double V[KSMALL * KLD];
   __shared__ double shv[32];
   __shared__ int shi[32];
+  __shared__ double shs[32];
   __shared__ double lp[KCAP];
   __shared__ double rc[KSMALL / 2 + 1], rs[KSMALL / 2 + 1];
   __shared__ int rp[KSMALL / 2 + 1], rq[KSMALL / 2 + 1];
@@ -566,6 +737,17 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
   // Cholesky subspace itself is the truncation: mode 1).
   double resid = tr;
   int kp = 0, ka = -1, mode = 0;
+  // largest remaining diagonal entry (bv at index bi) and the residual trace
+  // are reduced together, once per pivot
+  double bv, rsum;
+  int bi;
+  {
+    double mv = -1.0;
+    int mi = 0;
+    for (int i = tid; i < N; i += nth)
+      if (dwork[i] > mv) { mv = dwork[i]; mi = i; }
+    block_argmax_sum(mv, mi, 0.0, shv, shi, shs, 0, bv, bi, rsum);
+  }
   for (int j = 0; j < kmax; ++j) {
     if (delta2 > 0.0) {
       if (resid <= delta2 && ka < 0) ka = kp;
@@ -577,32 +759,28 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
       }
       if (mode == 1 && resid <= delta2) break;
     }
-    double bv;
-    int bi;
-    double mv = -1.0;
-    int mi = 0;
-    for (int i = tid; i < N; i += nth)
-      if (dwork[i] > mv) { mv = dwork[i]; mi = i; }
-    argmax_block(mv, mi, shv, shi, bv, bi);
     if (bv <= zero_thr || bv <= 0.0) break;
     const int p = bi;
     for (int t = tid; t < j; t += nth) lp[t] = L[(long)t * N + p];
     __syncthreads();
     const double ljj = sqrt(bv);
+    double mv = -1.0, rr = 0.0;
+    int mi = 0;
     for (int i = tid; i < N; i += nth) {
-      double s = S[(long)p * N + i];   // S is symmetric: row p read coalesced
-      for (int t = 0; t < j; ++t) s -= L[(long)t * N + i] * lp[t];
-      double lij = (i == p) ? ljj : s / ljj;
+      // S is symmetric: row p read coalesced
+      const double sv = S[(long)p * N + i] - col_combo(L, N, i, lp, 1, j);
+      const double lij = (i == p) ? ljj : sv / ljj;
       L[(long)j * N + i] = lij;
-      double d = dwork[i] - lij * lij;
-      dwork[i] = (i == p || d < 0.0) ? 0.0 : d;
+      const double d = dwork[i] - lij * lij;
+      const double dn = (i == p || d < 0.0) ? 0.0 : d;
+      dwork[i] = dn;
+      rr += dn;
+      if (dn > mv) { mv = dn; mi = i; }
     }
-    __syncthreads();
-    double rr = 0.0;
-    for (int i = tid; i < N; i += nth) rr += dwork[i];
-    resid = block_sum(rr, shv);
+    block_argmax_sum(mv, mi, rr, shv, shi, shs, (j + 1) & 1, bv, bi, resid);
     kp = j + 1;
   }
+  __syncthreads();
   if (mode == 1 && large_ok) {
     if (tid == 0) *info = 2;
     return;
@@ -633,26 +811,28 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
   // --- T = L^T L (kp x kp), one wavefront per entry; V = I
   {
     const int wv = tid / WAVE, ln = tid % WAVE, nwv = nth / WAVE;
-    for (int e = wv; e < kp * kp; e += nwv) {
-      int a = e / kp, b = e % kp;
-      if (b < a) continue;
-      double s = 0.0;
-      for (int i = ln; i < N; i += WAVE) s = fma(L[(long)a * N + i], L[(long)b * N + i], s);
-      for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_down(s, o, WAVE);
+    const int ntri = kp * (kp + 1) / 2;
+    for (int e = wv; e < ntri; e += nwv) {
+      // e -> (a, b) with a <= b, row-major over the upper triangle
+      int a = (int)((2.0 * kp + 1.0 - sqrt((2.0 * kp + 1.0) * (2.0 * kp + 1.0) - 8.0 * e)) / 2.0);
+      while (a > 0 && a * kp - a * (a - 1) / 2 > e) --a;
+      while ((a + 1) * kp - (a + 1) * a / 2 <= e) ++a;
+      const int b = a + (e - (a * kp - a * (a - 1) / 2));
+      const double s = wave_dot(L + (long)a * N, L + (long)b * N, N);
       if (ln == 0) {
-        T[a * KSMALL + b] = s;
-        T[b * KSMALL + a] = s;
+        T[a * KLD + b] = s;
+        T[b * KLD + a] = s;
       }
     }
     for (int e = tid; e < kp * kp; e += nth) {
       int a = e / kp, b = e % kp;
-      V[a * KSMALL + b] = (a == b) ? 1.0 : 0.0;
+      V[a * KLD + b] = (a == b) ? 1.0 : 0.0;
     }
   }
   __syncthreads();
   // --- cyclic Jacobi (round-robin pairs)
   double ttr = 0.0;
-  for (int i = 0; i < n; ++i) ttr += fabs(T[i * KSMALL + i]);
+  for (int i = 0; i < n; ++i) ttr += fabs(T[i * KLD + i]);
   const int np2 = n + (n & 1);
   const int npairs = np2 / 2;
   for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
@@ -666,7 +846,7 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
         int p = a < b ? a : b, q = a < b ? b : a;
         double c = 1.0, s = 0.0;
         if (q < n) {
-          double apq = T[p * KSMALL + q], app = T[p * KSMALL + p], aqq = T[q * KSMALL + q];
+          double apq = T[p * KLD + q], app = T[p * KLD + p], aqq = T[q * KLD + q];
           if (fabs(apq) > fmax(1e-15 * sqrt(fabs(app * aqq)), 1e-17 * ttr) && apq != 0.0) {
             double th = (aqq - app) / (2.0 * apq);
             double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
@@ -683,29 +863,35 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
         rs[tid] = s;
       }
       __syncthreads();
-      // rows: T <- J^T T
-      for (int e = tid; e < npairs * n; e += nth) {
-        int pr = e / n, j = e % n;
-        int p = rp[pr], q = rq[pr];
-        if (p == q || rs[pr] == 0.0) continue;
-        double c = rc[pr], s = rs[pr];
-        double tp = T[p * KSMALL + j], tq = T[q * KSMALL + j];
-        T[p * KSMALL + j] = c * tp - s * tq;
-        T[q * KSMALL + j] = s * tp + c * tq;
+      // T <- J^T T J in one pass: the pairs are disjoint, so every 2 x 2
+      // block (rows of pair a, columns of pair b) is updated on its own by
+      // the two rotations; V <- V J alongside
+      for (int e = tid; e < npairs * npairs; e += nth) {
+        const int a = e / npairs, b = e - a * npairs;
+        const double sa = rs[a], sb = rs[b];
+        if (sa == 0.0 && sb == 0.0) continue;
+        const double ca = rc[a], cb = rc[b];
+        const int pa = rp[a], qa = rq[a], pb = rp[b], qb = rq[b];
+        const bool ra = pa != qa, rb = pb != qb;   // a dummy pair is one index
+        const double bpp = T[pa * KLD + pb];
+        const double bpq = rb ? T[pa * KLD + qb] : 0.0;
+        const double bqp = ra ? T[qa * KLD + pb] : 0.0;
+        const double bqq = (ra && rb) ? T[qa * KLD + qb] : 0.0;
+        const double xpp = ca * bpp - sa * bqp, xpq = ca * bpq - sa * bqq;
+        const double xqp = sa * bpp + ca * bqp, xqq = sa * bpq + ca * bqq;
+        T[pa * KLD + pb] = cb * xpp - sb * xpq;
+        if (rb) T[pa * KLD + qb] = sb * xpp + cb * xpq;
+        if (ra) T[qa * KLD + pb] = cb * xqp - sb * xqq;
+        if (ra && rb) T[qa * KLD + qb] = sb * xqp + cb * xqq;
       }
-      __syncthreads();
-      // columns: T <- T J, V <- V J
       for (int e = tid; e < npairs * n; e += nth) {
-        int pr = e / n, i = e % n;
-        int p = rp[pr], q = rq[pr];
+        const int pr = e / n, i = e - pr * n;
+        const int p = rp[pr], q = rq[pr];
         if (p == q || rs[pr] == 0.0) continue;
-        double c = rc[pr], s = rs[pr];
-        double tp = T[i * KSMALL + p], tq = T[i * KSMALL + q];
-        T[i * KSMALL + p] = c * tp - s * tq;
-        T[i * KSMALL + q] = s * tp + c * tq;
-        double vp = V[i * KSMALL + p], vq = V[i * KSMALL + q];
-        V[i * KSMALL + p] = c * vp - s * vq;
-        V[i * KSMALL + q] = s * vp + c * vq;
+        const double c = rc[pr], s = rs[pr];
+        const double vp = V[i * KLD + p], vq = V[i * KLD + q];
+        V[i * KLD + p] = c * vp - s * vq;
+        V[i * KLD + q] = s * vp + c * vq;
       }
       __syncthreads();
     }
@@ -714,7 +900,7 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
     if (!f) break;
   }
   // --- sort eigenvalues descending
-  if (tid < n) lam[tid] = T[tid * KSMALL + tid] > 0.0 ? T[tid * KSMALL + tid] : 0.0;
+  if (tid < n) lam[tid] = T[tid * KLD + tid] > 0.0 ? T[tid * KLD + tid] : 0.0;
   __syncthreads();
   if (tid < n) {
     double v = lam[tid];
@@ -752,12 +938,11 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
   __syncthreads();
   // --- U = L V_k diag(lambda^-1/2), column-major into the U buffer
   for (long e = tid; e < (long)N * kc; e += nth) {
-    int c = e / N, i = e % N;
-    int oc = order[c];
-    double s = 0.0;
-    for (int a = 0; a < n; ++a) s = fma(L[(long)a * N + i], V[a * KSMALL + oc], s);
-    double l = lam[oc];
-    U[(long)c * N + i] = l > 0.0 ? s / sqrt(l) : 0.0;
+    const int c = e / N, i = e % N;
+    const int oc = order[c];
+    const double sv = col_combo(L, N, i, V + oc, KLD, n);
+    const double l = lam[oc];
+    U[(long)c * N + i] = l > 0.0 ? sv / sqrt(l) : 0.0;
   }
   __syncthreads();
   // move to L (column-major work area for Gram-Schmidt)
@@ -774,18 +959,11 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
     double* xc = L + (long)c * N;
     for (int pass = 0; pass < 2 && c > 0; ++pass) {
       for (int d = wv; d < c; d += nwv) {
-        const double* xd = L + (long)d * N;
-        double s = 0.0;
-        for (int i = ln; i < N; i += WAVE) s = fma(xd[i], xc[i], s);
-        for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_down(s, o, WAVE);
-        if (ln == 0) lp[d] = s;
+        const double sv = wave_dot(L + (long)d * N, xc, N);
+        if (ln == 0) lp[d] = sv;
       }
       __syncthreads();
-      for (int i = tid; i < N; i += nth) {
-        double u = xc[i];
-        for (int d = 0; d < c; ++d) u -= lp[d] * L[(long)d * N + i];
-        xc[i] = u;
-      }
+      for (int i = tid; i < N; i += nth) xc[i] -= col_combo(L, N, i, lp, 1, c);
       __syncthreads();
     }
     double s = 0.0;
@@ -884,39 +1062,39 @@ __global__ __launch_bounds__(64) void k_sg_convection(int nxi, int n_u, int ns, 
 }
 
 // ------------------------------------------------------------------ block cyclic reduction
-constexpr int BCR_MAXBS = 256, BCR_NT = 8;
+constexpr int BCR_MAXBS = 256;
+static_assert(sizeof(BcrOpDesc) % 8 == 0, "descriptor layout");
 
 // One pass of a block cyclic reduction solve.  Rows = scalar unknowns of one
 // component; component z of a vector V with row stride ld starts at
-// V + z*comp_rows*ld.  Block out <- [B_out] + sum_t coef_t M_t V_{in_t}
-// (at most BCR_NT terms).  mode 0 (forward reduction): every input from B,
-// out to B in place; mode 2 (top system): every input from B, out to X;
-// mode 1 (back substitution): the op's own block from B, the neighbours
-// from the solution X, out to X; mode 3 (block-tridiagonal product): every
-// input from X, out to B (added to B_out).  No op reads a block that the pass writes,
-// so every op spreads its row groups (rows [64 g, 64 g + 64), grid z) over
-// workgroups.  CB combined columns per workgroup (component-major: combined
-// column j is column j % ncols of component j / ncols), on the FP64 matrix
-// cores: wave w owns row tile 4g + w times CB/16 column tiles
-// (v_mfma_f64_16x16x4: lane l supplies M[row l%16][k l/16] and V[k l/16][col
-// l%16]; accumulator item v is row 4v + l/16).  Inputs are staged in LDS; the
-// M fragments of the next PF k-steps are in flight while the current ones are
-// multiplied.  CB and PF are chosen per factor and column count by timing
-// (bcr_solve).
+// V + z*comp_rows*ld.  Each op (one output block, described by a BcrOpDesc
+// so that a workgroup finds everything it needs in one load) computes
+// out <- [B_out] + sum_t coef_t M_t V_t, where V_t is block t of B or of the
+// solution X and the output goes to B (in place; no op of the pass reads a
+// block the pass writes) or to X.  Every op spreads its row groups (rows
+// [64 g, 64 g + 64), grid z) over workgroups and CB combined columns per
+// workgroup (component-major: combined column j is column j % ncols of
+// component j / ncols).  The products run on the FP64 matrix cores: wave w
+// owns row tile 4g + w times CB/16 column tiles (v_mfma_f64_16x16x4: lane l
+// supplies M[row l%16][k l/16] and V[k l/16][col l%16]; accumulator item v
+// is row 4v + l/16); input tiles are staged in LDS.  Each block M_t is stored
+// in that fragment order: row tile g, k-step q at off + (g*nq + q)*64 + l
+// (nq = ceil(cols/4), zero-padded), so a wave reads one contiguous 512-byte
+// run per k-step; the data array ends with BCR_DATA_PAD doubles of padding.
+//
+// Streaming variant, any block up to BCR_MAXBS rows: the M fragments of the
+// next PF k-steps are in flight while the current ones are multiplied.
 template <int CB, int PF>
-__global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict__ start, const int* __restrict__ op_out,
-                                                  const int* __restrict__ op_self, const int* __restrict__ op_nterm,
-                                                  const int* __restrict__ op_in, const long* __restrict__ op_off,
-                                                  const double* __restrict__ op_coef, const double* __restrict__ data,
-                                                  double* __restrict__ B, long ldb, double* __restrict__ X, long ldx,
-                                                  int mode, int ncols, int ncomp, long comp_rows) {
+__global__ __launch_bounds__(256) void k_bcr_stream(const BcrOpDesc* __restrict__ ops, int op0,
+                                                    const double* __restrict__ data, double* __restrict__ B, long ldb,
+                                                    double* __restrict__ X, long ldx, int ncols, int ncomp,
+                                                    long comp_rows) {
   __shared__ double xs[BCR_MAXBS + 4][CB + 1];
-  const int o = op0 + blockIdx.x;
+  const BcrOpDesc& d = ops[op0 + blockIdx.x];
   const int j0 = blockIdx.y * CB;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int lr = lane % 16, lk = lane / 16;
-  const int ob = op_out[o];
-  const int r0 = start[ob], bo = start[ob + 1] - r0;
+  const int r0 = d.r0, bo = d.bo;
   if ((int)blockIdx.z * 64 >= bo) return;   // uniform per workgroup
   const int rt = blockIdx.z * 4 + wave;
   const bool active = rt * 16 < bo;
@@ -925,13 +1103,14 @@ __global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict
     const int comp = j / ncols, c = j - comp * ncols;
     return ((long)comp * comp_rows + row) * ld + c;
   };
-  double* out = (mode == 1 || mode == 2) ? X : B;
-  const long ldo = (mode == 1 || mode == 2) ? ldx : ldb;
+  const bool to_x = d.flags & 2;
+  double* out = to_x ? X : B;
+  const long ldo = to_x ? ldx : ldb;
   constexpr int NCT = CB / 16;
   dbl4 acc[NCT];
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct) acc[ct] = dbl4{0.0, 0.0, 0.0, 0.0};
-  if (active && op_self[o]) {
+  if (active && (d.flags & 1)) {
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
@@ -940,15 +1119,14 @@ __global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict
         if (r < bo && j < ctot) acc[ct][v] = B[addr(r0 + r, j, ldb)];
       }
   }
-  const int nterm = op_nterm[o];
-  const int ra = rt * 16 + lr;
+  const int nterm = d.nterm;
+  const int rtc = min(rt, (bo - 1) / 16);   // idle waves read a valid tile
   for (int t = 0; t < nterm; ++t) {
-    const int ib = op_in[BCR_NT * o + t];
-    const int i0 = start[ib], bi = start[ib + 1] - i0;
+    const int i0 = d.in_r0[t], bi = d.in_bi[t];
     const int bi4 = (bi + 3) & ~3;
-    const double* M = data + op_off[BCR_NT * o + t];
-    const double coef = op_coef[BCR_NT * o + t];
-    const bool from_x = (mode == 1 && ib != ob) || mode == 3;
+    const double* M = data + d.off[t] + (long)rtc * (bi4 / 4) * 64 + lane;   // fragment order
+    const double coef = d.coef[t];
+    const bool from_x = (d.in_x >> t) & 1;
     const double* src = from_x ? X : B;
     const long lds = from_x ? ldx : ldb;
     __syncthreads();
@@ -958,29 +1136,24 @@ __global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict
     }
     __syncthreads();
     if (!active) continue;
-    // M fragments stream from memory: PF k-steps are kept in flight
+    // fragments past the block's end read the padding behind the data
+    // array or the next block: in bounds, never multiplied
     double an[PF];
 #pragma unroll
-    for (int d = 0; d < PF; ++d) {
-      const int kk = 4 * d + lk;
-      an[d] = (ra < bo && kk < bi) ? M[(long)kk * bo + ra] : 0.0;
-    }
+    for (int q = 0; q < PF; ++q) an[q] = M[q * 64];
     for (int k = 0; k < bi4; k += 4 * PF) {
       double a[PF];
 #pragma unroll
-      for (int d = 0; d < PF; ++d) a[d] = coef * an[d];
+      for (int q = 0; q < PF; ++q) a[q] = coef * an[q];
 #pragma unroll
-      for (int d = 0; d < PF; ++d) {
-        const int kk = k + 4 * (PF + d) + lk;
-        an[d] = (ra < bo && kk < bi) ? M[(long)kk * bo + ra] : 0.0;
-      }
+      for (int q = 0; q < PF; ++q) an[q] = M[(k / 4 + PF + q) * 64];
 #pragma unroll
-      for (int d = 0; d < PF; ++d) {
-        const int kr = k + 4 * d;
+      for (int q = 0; q < PF; ++q) {
+        const int kr = k + 4 * q;
         if (kr >= bi4) break;
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct)
-          acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[d], xs[kr + lk][ct * 16 + lr], acc[ct], 0, 0, 0);
+          acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], xs[kr + lk][ct * 16 + lr], acc[ct], 0, 0, 0);
       }
     }
   }
@@ -991,6 +1164,130 @@ __global__ __launch_bounds__(256) void k_bcr_pass(int op0, const int* __restrict
     for (int v = 0; v < 4; ++v) {
       const int r = rt * 16 + 4 * v + lk, j = j0 + ct * 16 + lr;
       if (r < bo && j < ctot) out[addr(r0 + r, j, ldo)] = acc[ct][v];
+    }
+}
+
+// Latency variant for blocks of at most 4*KM rows: a term's whole M fragment
+// (KM k-steps) and its input tile are loaded in one round trip.  With DB the
+// next term's loads are in flight while the current term runs on the matrix
+// cores (input tiles double-buffered in LDS, twice the registers); without,
+// the registers are halved for occupancy on passes with many ops.
+template <int CB, int KM, bool DB>
+__global__ __launch_bounds__(256) void k_bcr_tile(const BcrOpDesc* __restrict__ ops, int op0,
+                                                  const double* __restrict__ data, double* __restrict__ B, long ldb,
+                                                  double* __restrict__ X, long ldx, int ncols, int ncomp,
+                                                  long comp_rows) {
+  constexpr int KR = 4 * KM;              // rows of the largest input block
+  constexpr int XPT = KR * CB / 256;      // staged input values per thread
+  constexpr int NCT = CB / 16;
+  constexpr int NBUF = DB ? 2 : 1;
+  static_assert(KR * CB % 256 == 0, "tile must split evenly over the workgroup");
+  __shared__ double xs[NBUF][KR][CB + 1];
+  const BcrOpDesc& d = ops[op0 + blockIdx.x];
+  const int j0 = blockIdx.y * CB;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int lr = lane % 16, lk = lane / 16;
+  const int r0 = d.r0, bo = d.bo;
+  if ((int)blockIdx.z * 64 >= bo) return;   // uniform per workgroup
+  const int rt = blockIdx.z * 4 + wave;
+  const bool active = rt * 16 < bo;
+  const int ctot = ncomp * ncols;
+  const int rtc = min(rt, (bo - 1) / 16);   // idle waves read a valid tile
+  // the combined columns this thread stages: component offset and column
+  int xcomp[XPT], xcol[XPT];
+#pragma unroll
+  for (int q = 0; q < XPT; ++q) {
+    const int j = j0 + (tid + 256 * q) % CB;
+    xcomp[q] = j < ctot ? j / ncols : -1;
+    xcol[q] = j < ctot ? j - xcomp[q] * ncols : 0;
+  }
+  const bool to_x = d.flags & 2;
+  double* out = to_x ? X : B;
+  const long ldo = to_x ? ldx : ldb;
+  const int nterm = d.nterm;
+  double mf[KM], xr[XPT];
+  double mn[DB ? KM : 1];
+  // fragment order: k-step q of row tile rtc is 64 contiguous doubles;
+  // k-steps past the block's end read the padding behind the data array or
+  // the next block (in bounds, never multiplied)
+  auto load_m = [&](int t, double* m) {
+    const double* M = data + d.off[t] + (long)rtc * ((d.in_bi[t] + 3) / 4) * 64 + lane;
+#pragma unroll
+    for (int q = 0; q < KM; ++q) m[q] = M[q * 64];
+  };
+  auto load_x = [&](int t) {
+    const int i0 = d.in_r0[t], bi = d.in_bi[t];
+    const bool from_x = (d.in_x >> t) & 1;
+    const double* src = from_x ? X : B;
+    const long lds = from_x ? ldx : ldb;
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int k = (tid + 256 * q) / CB;
+      xr[q] = (k < bi && xcomp[q] >= 0) ? src[((long)xcomp[q] * comp_rows + i0 + k) * lds + xcol[q]] : 0.0;
+    }
+  };
+  if (nterm > 0) {
+    load_m(0, mf);
+    load_x(0);
+  }
+  dbl4 acc[NCT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) acc[ct] = dbl4{0.0, 0.0, 0.0, 0.0};
+  if (active && (d.flags & 1)) {
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rt * 16 + 4 * v + lk, j = j0 + ct * 16 + lr;
+        if (r < bo && j < ctot) {
+          const int comp = j / ncols;
+          acc[ct][v] = B[((long)comp * comp_rows + r0 + r) * ldb + (j - comp * ncols)];
+        }
+      }
+  }
+  for (int t = 0; t < nterm; ++t) {
+    double(*xb)[CB + 1] = xs[DB ? (t & 1) : 0];
+    if (!DB && t > 0) __syncthreads();   // the single buffer is free again
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int e = tid + 256 * q;
+      xb[e / CB][e % CB] = xr[q];
+    }
+    __syncthreads();
+    const int bi4 = (d.in_bi[t] + 3) & ~3;
+    const double coef = d.coef[t];
+    if (DB && t + 1 < nterm) {
+      load_m(t + 1, mn);
+      load_x(t + 1);
+    }
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < KM; ++q) {
+        if (4 * q >= bi4) break;
+        const double a = coef * mf[q];
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+          acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb[4 * q + lk][ct * 16 + lr], acc[ct], 0, 0, 0);
+      }
+    }
+    if (DB) {
+#pragma unroll
+      for (int q = 0; q < KM; ++q) mf[q] = mn[DB ? q : 0];
+    } else if (t + 1 < nterm) {
+      load_m(t + 1, mf);
+      load_x(t + 1);
+    }
+  }
+  if (!active) return;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = rt * 16 + 4 * v + lk, j = j0 + ct * 16 + lr;
+      if (r < bo && j < ctot) {
+        const int comp = j / ncols;
+        out[((long)comp * comp_rows + r0 + r) * ldo + (j - comp * ncols)] = acc[ct][v];
+      }
     }
 }
 
@@ -1351,17 +1648,45 @@ void copy2d(hipStream_t s, int rows, int cols, const double* src, long lds, doub
   hipLaunchKernelGGL(k_copy2d, dim3(nb), dim3(256), 0, s, rows, cols, src, lds, dst, ldd, alpha, dscale, inv);
 }
 
+void transpose_copy_batched(hipStream_t s, int batch, int rows, int cols, const double* src, long sbatch, long lds,
+                            double* dst, long dbatch, long ldd) {
+  if (batch <= 0 || rows <= 0 || cols <= 0) return;
+  if (batch > 65535) throw std::runtime_error("transpose_copy_batched: batch too large");
+  const unsigned gx = (unsigned)cdiv(cols, 32);
+  const unsigned gy = (unsigned)std::min<long>(cdiv(rows, 32), std::max<long>(1, 65536 / ((long)gx * batch)));
+  hipLaunchKernelGGL(k_transpose_copy, dim3(gx, std::max(1u, std::min(gy, 65535u)), batch), dim3(32, 8), 0, s, rows,
+                     cols, src, lds, sbatch, dst, ldd, dbatch);
+}
+
 void transpose_copy(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst, long ldd) {
-  long total = (long)rows * cols;
-  if (total <= 0) return;
-  unsigned nb = std::min<unsigned>(cdiv(total, 256), 8192);
-  hipLaunchKernelGGL(k_transpose_copy, dim3(nb), dim3(256), 0, s, rows, cols, src, lds, dst, ldd);
+  transpose_copy_batched(s, 1, rows, cols, src, 0, lds, dst, 0, ldd);
+}
+
+void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const double* eval,
+              const double* x, int ldx, int xcol0, int ncols, double* y, int ldy, int ycol0, double alpha,
+              double beta) {
+  if (nrows <= 0 || ncols <= 0 || ncomp <= 0) return;
+  const double by = 12.0 * ELL_WIDTH * nrows + 8.0 * ncomp * ((double)nrows * ncols) +
+                    8.0 * ncomp * (double)nrows * ncols * (beta != 0.0 ? 2.0 : 1.0);
+  ProfScope ps(KC_SPMM, s, by, 2.0 * ELL_WIDTH * (double)nrows * ncomp * ncols);
+  const unsigned nb = 8 * cdiv(cdiv(nrows, 4), 8);
+  hipLaunchKernelGGL(k_ell_spmm<ELL_WIDTH>, dim3(nb, ncomp), dim3(256), 0, s, nrows, ics, ocs, ecol, eval, x, ldx,
+                     xcol0, ncols, y, ldy, ycol0, alpha, beta);
 }
 
 void spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* rowptr, const int* col, const double* vals,
           int nv, long vstride, const double* x, int ldx, int xcol0, int ncols, double* y, int ldy, int ycol0,
-          int yvstep, double alpha, double beta) {
+          int yvstep, double alpha, double beta, int max_row_nnz) {
   if (nrows <= 0 || ncols <= 0 || nv <= 0) return;
+  if (nv == 1 && max_row_nnz > 0 && max_row_nnz <= 32) {
+    const double nnz = (double)vstride > 0 ? (double)vstride : 0.0;
+    const double by = 4.0 * (nrows + 1) + nnz * 12.0 + 8.0 * ncomp * ((double)std::max(ics, nrows) * ncols) +
+                      8.0 * ncomp * (double)nrows * ncols * (beta != 0.0 ? 2.0 : 1.0);
+    ProfScope ps(KC_SPMM, s, by, 2.0 * nnz * ncomp * ncols);
+    hipLaunchKernelGGL(k_spmm_short<32>, dim3(cdiv(nrows, 4), ncomp), dim3(256), 0, s, nrows, ics, ocs, rowptr, col,
+                       vals, x, ldx, xcol0, ncols, y, ldy, ycol0, alpha, beta);
+    return;
+  }
   for (int v0 = 0; v0 < nv; v0 += NVMAX) {
     int nvb = std::min(NVMAX, nv - v0);
     dim3 grid(cdiv(nrows, 4), ncomp);
@@ -1458,27 +1783,38 @@ namespace {
 // the (CB, PF) variants of k_bcr_pass that the tuner chooses from
 struct BcrVariant {
   int cb;
-  decltype(&k_bcr_pass<32, 8>) fn;
+  int max_rows;   // largest block the variant takes
+  decltype(&k_bcr_stream<32, 8>) fn;
 };
-const BcrVariant kBcrVariants[] = {{32, k_bcr_pass<32, 8>}, {32, k_bcr_pass<32, 16>}, {16, k_bcr_pass<16, 8>},
-                                   {16, k_bcr_pass<16, 16>}, {64, k_bcr_pass<64, 8>}, {32, k_bcr_pass<32, 4>}};
+const BcrVariant kBcrVariants[] = {
+    {32, BCR_MAXBS, k_bcr_stream<32, 8>},     {16, BCR_MAXBS, k_bcr_stream<16, 8>},
+    {32, BCR_MAXBS, k_bcr_stream<32, 16>},    {16, 128, k_bcr_tile<16, 32, true>},
+    {32, 128, k_bcr_tile<32, 32, true>},      {16, 128, k_bcr_tile<16, 32, false>},
+    {32, 128, k_bcr_tile<32, 32, false>},     {16, 64, k_bcr_tile<16, 16, true>},
+    {32, 64, k_bcr_tile<32, 16, true>}};
 constexpr int kNumBcrVariants = sizeof(kBcrVariants) / sizeof(kBcrVariants[0]);
 std::mutex g_bcr_mu;
-std::map<std::tuple<const double*, int, int>, int> g_bcr_choice;   // (factor, ncols, ncomp) -> variant
+std::map<std::tuple<const double*, int, int>, std::vector<int>> g_bcr_choice;   // (factor, ncols, ncomp) -> variant per pass
 
-void bcr_run(hipStream_t s, const BcrDev& f, int var, int ncomp, double* B, long ldb, double* X, long ldx, int ncols) {
-  const BcrVariant& v = kBcrVariants[var];
+// ev (npass + 1 events, optional) brackets every pass
+void bcr_run(hipStream_t s, const BcrDev& f, const int* vars, int ncomp, double* B, long ldb, double* X, long ldx,
+             int ncols, hipEvent_t* ev = nullptr) {
   for (int p = 0; p < f.npass; ++p) {
+    if (ev) (void)hipEventRecord(ev[p], s);
     const int o0 = f.pass_begin[p], no = f.pass_begin[p + 1] - o0;
     if (no <= 0) continue;
-    hipLaunchKernelGGL(v.fn, dim3(no, cdiv((long)ncomp * ncols, v.cb), cdiv(f.maxbs, 64)), dim3(256), 0, s, o0, f.start,
-                       f.op_out, f.op_self, f.op_nterm, f.op_in, f.op_off, f.op_coef, f.data, B, ldb, X, ldx,
-                       f.pass_mode[p], ncols, ncomp, (long)f.n);
+    const BcrVariant& v = kBcrVariants[vars[p]];
+    hipLaunchKernelGGL(v.fn, dim3(no, cdiv((long)ncomp * ncols, v.cb), cdiv(f.maxbs, 64)), dim3(256), 0, s, f.ops, o0,
+                       f.data, B, ldb, X, ldx, ncols, ncomp, (long)f.n);
   }
+  if (ev) (void)hipEventRecord(ev[f.npass], s);
 }
 
-// time every variant on scratch copies of the right-hand side; keep the fastest
-int bcr_tune(hipStream_t s, const BcrDev& f, int ncomp, const double* B, long ldb, int ncols) {
+// time every variant on scratch copies of the right-hand side, pass by pass;
+// keep the fastest variant of each pass
+std::vector<int> bcr_tune(hipStream_t s, const BcrDev& f, int ncomp, const double* B, long ldb, int ncols) {
+  const int np = f.npass;
+  std::vector<int> best(np, 0);
   const long rows = (long)ncomp * f.n;
   double *b0 = nullptr, *bw = nullptr, *xw = nullptr;
   if (hipMalloc(&b0, sizeof(double) * rows * ncols) != hipSuccess ||
@@ -1487,34 +1823,35 @@ int bcr_tune(hipStream_t s, const BcrDev& f, int ncomp, const double* B, long ld
     (void)hipGetLastError();
     for (double* p : {b0, bw, xw})
       if (p) (void)hipFree(p);
-    return 0;
+    return best;
   }
   copy2d(s, (int)rows, ncols, B, ldb, b0, ncols, 1.0, nullptr, 0);
   copy2d(s, (int)rows, ncols, b0, ncols, xw, ncols, 1.0, nullptr, 0);   // finite inputs for product passes
-  hipEvent_t e0, e1;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
-  int best = 0;
-  float best_ms = 1e30f;
+  std::vector<hipEvent_t> ev(np + 1);
+  for (auto& e : ev) (void)hipEventCreate(&e);
+  std::vector<float> best_ms(np, 1e30f);
   for (int v = 0; v < kNumBcrVariants; ++v) {
-    float tot = 0.f;
+    if (f.maxbs > kBcrVariants[v].max_rows) continue;
+    const std::vector<int> vv(np, v);
+    std::vector<float> tot(np, 0.f);
     for (int rep = 0; rep < 3; ++rep) {
       copy2d(s, (int)rows, ncols, b0, ncols, bw, ncols, 1.0, nullptr, 0);
-      (void)hipEventRecord(e0, s);
-      bcr_run(s, f, v, ncomp, bw, ncols, xw, ncols, ncols);
-      (void)hipEventRecord(e1, s);
-      (void)hipEventSynchronize(e1);
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (rep > 0) tot += ms;   // the first run warms the caches
+      bcr_run(s, f, vv.data(), ncomp, bw, ncols, xw, ncols, ncols, ev.data());
+      (void)hipEventSynchronize(ev[np]);
+      if (rep == 0) continue;   // the first run warms the caches
+      for (int p = 0; p < np; ++p) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[p], ev[p + 1]);
+        tot[p] += ms;
+      }
     }
-    if (tot < best_ms) {
-      best_ms = tot;
-      best = v;
-    }
+    for (int p = 0; p < np; ++p)
+      if (tot[p] < best_ms[p]) {
+        best_ms[p] = tot[p];
+        best[p] = v;
+      }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  for (auto& e : ev) (void)hipEventDestroy(e);
   (void)hipStreamSynchronize(s);
   for (double* p : {b0, bw, xw}) (void)hipFree(p);
   return best;
@@ -1524,25 +1861,25 @@ int bcr_tune(hipStream_t s, const BcrDev& f, int ncomp, const double* B, long ld
 void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols) {
   if (ncols <= 0 || f.npass == 0) return;
   if (f.maxbs > BCR_MAXBS) throw std::runtime_error("block cyclic reduction: block larger than 256");
-  int var = 0;
+  std::vector<int> vars;
   {
     const auto key = std::make_tuple((const double*)f.data, ncols, ncomp);
     std::unique_lock<std::mutex> lk(g_bcr_mu);
     auto it = g_bcr_choice.find(key);
     if (it != g_bcr_choice.end()) {
-      var = it->second;
+      vars = it->second;
     } else {
       lk.unlock();
       const bool was = prof_enabled();
       prof_enable(false);
-      var = bcr_tune(s, f, ncomp, B, ldb, ncols);
+      vars = bcr_tune(s, f, ncomp, B, ldb, ncols);
       prof_enable(was);
       lk.lock();
-      g_bcr_choice[key] = var;
+      g_bcr_choice[key] = vars;
     }
   }
   ProfScope ps(KC_BCR, s, 8.0 * (f.ndata + 3.0 * ncomp * (double)f.n * ncols), 2.0 * f.ndata * ncols * ncomp);
-  bcr_run(s, f, var, ncomp, B, ldb, X, ldx, ncols);
+  bcr_run(s, f, vars.data(), ncomp, B, ldb, X, ldx, ncols);
 }
 
 int bcr_choice_count() {

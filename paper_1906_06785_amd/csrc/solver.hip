@@ -10,6 +10,7 @@
 #include <memory>
 #include <string>
 #include <thread>
+#include <map>
 #include <vector>
 
 #include "../../include/sgtt.h"
@@ -45,6 +46,7 @@ T* dev_upload(Ctx& c, const std::vector<T>& h) {
 
 struct DevCsr {
   int nrows = 0, ncols = 0, nnz = 0, nv = 0;
+  int max_row = 0;          // most entries in one row
   int *rowptr = nullptr, *col = nullptr;
   double* vals = nullptr;   // nv value arrays of nnz each
   void free_all() {
@@ -62,6 +64,7 @@ DevCsr upload_csr(Ctx& c, const Csr& pat, const std::vector<const double*>& vals
   d.ncols = pat.ncols;
   d.nnz = pat.nnz();
   d.nv = (int)valsets.size();
+  for (int r = 0; r < pat.nrows; ++r) d.max_row = std::max(d.max_row, pat.rowptr[r + 1] - pat.rowptr[r]);
   d.rowptr = dev_upload(c, pat.rowptr);
   d.col = dev_upload(c, pat.col);
   std::vector<double> all((size_t)d.nnz * std::max(d.nv, 1));
@@ -71,32 +74,65 @@ DevCsr upload_csr(Ctx& c, const Csr& pat, const std::vector<const double*>& vals
 }
 
 void free_bcr(BcrDev& d) {
-  for (void* p : {(void*)d.start, (void*)d.op_out, (void*)d.op_self, (void*)d.op_nterm, (void*)d.op_in,
-                  (void*)d.op_off, (void*)d.op_coef, (void*)d.data})
+  for (void* p : {(void*)d.ops, (void*)d.data})
     if (p) (void)hipFree(p);
   d = BcrDev();
 }
 
+// device form of a factor: one descriptor per op.  Pass modes: 0 forward
+// reduction (inputs from B, output to B), 2 top system (inputs from B,
+// output to X), 1 back substitution (own block from B, neighbours from X,
+// output to X).
 BcrDev upload_bcr(Ctx& c, const BcrFactor& f) {
   if (f.maxbs > 256) throw SgttError(-6, "block cyclic reduction: block larger than 256");
+  if (BcrFactor::NT != BCR_NT) throw SgttError(-6, "block cyclic reduction: op layout mismatch");
   BcrDev d;
   d.n = f.n;
   d.nblk = f.nblk;
   d.maxbs = f.maxbs;
   d.npass = (int)f.pass_begin.size() - 1;
-  d.pass_mode = f.pass_mode;
-  if (BcrFactor::NT != 8) throw SgttError(-6, "block cyclic reduction: op layout mismatch");
   d.pass_begin = f.pass_begin;
   d.ndata = (double)f.data.size();
-  d.start = dev_upload(c, f.start);
-  d.op_out = dev_upload(c, f.op_out);
-  d.op_self = dev_upload(c, f.op_self);
-  d.op_nterm = dev_upload(c, f.op_nterm);
-  d.op_in = dev_upload(c, f.op_in);
-  std::vector<long> off(f.op_off.begin(), f.op_off.end());
-  d.op_off = dev_upload(c, off);
-  d.op_coef = dev_upload(c, f.op_coef);
-  d.data = dev_upload(c, f.data);
+  std::vector<BcrOpDesc> ops(f.op_out.size());
+  std::vector<double> frag;                       // blocks in fragment order
+  std::map<std::tuple<long, int, int>, long> placed;
+  auto place = [&](long off, int rows, int cols) -> long {
+    const auto key = std::make_tuple(off, rows, cols);
+    auto it = placed.find(key);
+    if (it != placed.end()) return it->second;
+    const long at = (long)frag.size();
+    frag.resize(frag.size() + bcr_fragment_size(rows, cols), 0.0);
+    for (int k = 0; k < cols; ++k)
+      for (int i = 0; i < rows; ++i) frag[at + bcr_fragment_index(i, k, cols)] = f.data[off + (long)k * rows + i];
+    placed[key] = at;
+    return at;
+  };
+  for (int p = 0; p < d.npass; ++p) {
+    const int mode = f.pass_mode[p];
+    if (mode < 0 || mode > 2) throw SgttError(-6, "block cyclic reduction: unknown pass mode");
+    for (int o = f.pass_begin[p]; o < f.pass_begin[p + 1]; ++o) {
+      BcrOpDesc& q = ops[o];
+      q = BcrOpDesc();
+      const int ob = f.op_out[o];
+      q.r0 = f.start[ob];
+      q.bo = f.start[ob + 1] - q.r0;
+      q.nterm = f.op_nterm[o];
+      if (q.nterm > BCR_NT) throw SgttError(-6, "block cyclic reduction: too many terms");
+      q.flags = (f.op_self[o] ? 1 : 0) | (mode != 0 ? 2 : 0);
+      for (int t = 0; t < q.nterm; ++t) {
+        const int ib = f.op_in[BCR_NT * o + t];
+        q.in_r0[t] = f.start[ib];
+        q.in_bi[t] = f.start[ib + 1] - f.start[ib];
+        q.off[t] = place(f.op_off[BCR_NT * o + t], q.bo, q.in_bi[t]);
+        q.coef[t] = f.op_coef[BCR_NT * o + t];
+        if (mode == 1 && ib != ob) q.in_x |= 1 << t;
+      }
+    }
+  }
+  frag.resize(frag.size() + BCR_DATA_PAD, 0.0);
+  d.ndata = (double)frag.size();
+  d.ops = dev_upload(c, ops);
+  d.data = dev_upload(c, frag);
   return d;
 }
 
@@ -137,7 +173,8 @@ struct sgtt_system {
   double* Hw = nullptr;    // k1 x k2 x nxi x nxi
   double* omega = nullptr; // nt x k2 (mean-mode time factors)
   BcrDev Fbt, Xbt;         // F_avg and X = B M*^-1 B^T (block cyclic reduction)
-  BcrDev Mblk;             // tau^-1 M as dense slab blocks (time coupling of the mean solve)
+  int* Me_col = nullptr;   // M in padded-row form (time coupling of the mean solve)
+  double* Me_val = nullptr;
   TT bu, bp;               // right-hand side
   double* Dinv = nullptr;  // 1 / diag(F_avg) on free scalar nodes
   sgtt::Mlp* mlp_collect = nullptr;   // records (r, F_avg^-1 r) pairs from mean solves
@@ -155,7 +192,8 @@ struct sgtt_system {
     Xmid.free_all();
     free_bcr(Fbt);
     free_bcr(Xbt);
-    free_bcr(Mblk);
+    for (void* p : {(void*)Me_col, (void*)Me_val})
+      if (p) (void)hipFree(p);
     for (double* p : {Gnu, w1, Hw, omega, dsc, Dinv}) (void)hipFree(p);
   }
 };
@@ -184,7 +222,7 @@ TT apply_velocity(sgtt_system& S, const TT& u, const TT& p) {
   spmm(c.s, S.ns, 2, S.ns, S.ns, S.Kop.rowptr, S.Kop.col, S.Kop.vals, 2 + k2, S.Kop.nnz, u.c3, r2u, 0, r2u, o.c3,
        R2, 0, r2u, 1.0);
   spmm(c.s, S.nu, 1, 0, 0, S.Btd.rowptr, S.Btd.col, S.Btd.vals, 1, 0, p.c3, r2p, 0, r2p, o.c3, R2,
-       2 * r2u + k2 * r2u, 0, 1.0);
+       2 * r2u + k2 * r2u, 0, 1.0, 0.0, S.Btd.max_row);
   return o;
 }
 
@@ -555,21 +593,23 @@ struct PrecOpts {
 TT exact_mean_solve(sgtt_system& S, const TT& y, double eps) {
   Ctx& c = S.ctx->c;
   const int nt = S.nt, nxi = S.nxi, nu = S.nu;
-  const long ldw = (long)nt * nxi;
-  double* Z = c.pool.get((size_t)ldw * y.r2);   // G1 x_1 G2: (nt nxi) x r2
+  const long slab = (long)nu * nxi;              // one time step: node-major, nxi columns, contiguous
+  double* Z = c.pool.get((size_t)nt * nxi * y.r2);   // G1 x_1 G2: (nt nxi) x r2
   gemm(c.s, 1, nt, nxi * y.r2, y.r1, 1.0, y.c1, 0, y.r1, 1, y.c2, 0, (long)nxi * y.r2, 1, 0.0, Z, 0,
        (long)nxi * y.r2, 1);
-  double* W = c.pool.get((size_t)nu * ldw);     // node-major full tensor: W[x][t nxi + i]
-  gemm(c.s, 1, nu, (int)ldw, y.r2, 1.0, y.c3, 0, y.r2, 1, Z, 0, 1, y.r2, 0.0, W, 0, ldw, 1);
+  double* W = c.pool.get((size_t)nt * slab);   // W[t][x][xi] = sum_b G3[x][b] Z[t xi][b]
+  gemm(c.s, nt, nu, nxi, y.r2, 1.0, y.c3, 0, y.r2, 1, Z, (long)nxi * y.r2, 1, y.r2, 0.0, W, slab, nxi, 1);
   c.pool.put(Z);
-  double* Vn = c.pool.get((size_t)nu * ldw);    // solution, same layout
+  double* Vn = c.pool.get((size_t)nt * slab);  // solution, same layout
   for (int t = 0; t < nt; ++t) {
-    if (t > 0)   // y_t + tau^-1 M v_{t-1}: M as dense slab blocks, one pass on the matrix cores
-      bcr_solve(c.s, S.Mblk, 2, W + (long)t * nxi, ldw, Vn + (long)(t - 1) * nxi, ldw, nxi);
-    bcr_solve(c.s, S.Fbt, 2, W + (long)t * nxi, ldw, Vn + (long)t * nxi, ldw, nxi);
+    double* Wt = W + t * slab;
+    if (t > 0)   // y_t + tau^-1 M v_{t-1}
+      ell_spmm(c.s, S.ns, 2, S.ns, S.ns, S.Me_col, S.Me_val, Vn + (t - 1) * slab, nxi, 0, nxi, Wt, nxi, 0,
+               1.0 / S.tau, 1.0);
+    bcr_solve(c.s, S.Fbt, 2, Wt, nxi, Vn + t * slab, nxi, nxi);
   }
   double* V = W;                                 // C order (t, xi, x), reusing the consumed right-hand side
-  transpose_copy(c.s, nu, (int)ldw, Vn, ldw, V, nu);
+  transpose_copy_batched(c.s, nt, nu, nxi, Vn, slab, nxi, V, slab, nu);
   c.pool.put(Vn);
   TT out = tt_from_full(c, V, nt, nxi, nu, eps, nullptr);
   c.pool.put(W);
@@ -590,7 +630,7 @@ Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCoun
   copy2d(c.s, S.nt, ph.r1, ph.c1, ph.r1, bph.c1, ph.r1, -1.0, nullptr, 0);
   SGTT_HIP(hipMemcpyAsync(bph.c2, ph.c2, sizeof(double) * ph.n_c2(), hipMemcpyDeviceToDevice, c.s));
   spmm(c.s, S.nu, 1, 0, 0, S.Btd.rowptr, S.Btd.col, S.Btd.vals, 1, 0, ph.c3, ph.r2, 0, ph.r2, bph.c3, ph.r2, 0, 0,
-       1.0);
+       1.0, 0.0, S.Btd.max_row);
   Vec rhs;
   rhs.nc = 1;
   rhs.c[0] = tt_concat(c, {&yu, &bph}, nullptr, {});
@@ -913,11 +953,20 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
   S->Btd = upload_csr(c, hp.Bt, {hp.Bt.val.data()});
   S->Xbt = factor_bcr(c, hp.Xp, hp.Xp.val.data(), hp.p_blocks);
   {
-    BcrFactor mf;
-    std::string err;
-    block_tridiag_matvec_ops(hp.Kff, hp.Mff.data(), 1.0 / prm.tau, hp.vel_blocks, mf, err);
-    if (!err.empty()) throw SgttError(-6, err);
-    S->Mblk = upload_bcr(c, mf);
+    const Csr& K = hp.Kff;
+    std::vector<int> ec((size_t)K.nrows * ELL_WIDTH);
+    std::vector<double> ev((size_t)K.nrows * ELL_WIDTH, 0.0);
+    for (int r = 0; r < K.nrows; ++r) {
+      const int n = K.rowptr[r + 1] - K.rowptr[r];
+      if (n > ELL_WIDTH) throw SgttError(-6, "mass matrix row longer than the padded width");
+      for (int q = 0; q < ELL_WIDTH; ++q) {
+        const int t = K.rowptr[r] + q;
+        ec[(size_t)r * ELL_WIDTH + q] = q < n ? K.col[t] : r;
+        ev[(size_t)r * ELL_WIDTH + q] = q < n ? hp.Mff[t] : 0.0;
+      }
+    }
+    S->Me_col = dev_upload(c, ec);
+    S->Me_val = dev_upload(c, ev);
   }
   const int nt = S->nt, nxi = S->nxi, nall = S->nall, ns = S->ns;
   // Dirichlet lift TT over all nodes: ramp (x) e_1 (x) g_all
@@ -1029,7 +1078,7 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
       spmm(c.s, ns, 2, nall, ns, Kfa.rowptr, Kfa.col, Kfa.vals, 2, Kfa.nnz, w.c3, r2u, 0, r2u, ru.c3, R2, 0, r2u,
            1.0);
       spmm(c.s, hp.n_u, 1, 0, 0, S->Btd.rowptr, S->Btd.col, S->Btd.vals, 1, 0, p.c3, r2p, 0, r2p, ru.c3, R2,
-           2 * r2u, 0, 1.0);
+           2 * r2u, 0, 1.0, 0.0, S->Btd.max_row);
       TT rp = tt_new(c, nt, nxi, hp.n_p, r1u, r2u);
       copy2d(c.s, nt, r1u, w.c1, r1u, rp.c1, r1u, -1.0, nullptr, 0);
       SGTT_HIP(hipMemcpyAsync(rp.c2, w.c2, sizeof(double) * w.n_c2(), hipMemcpyDeviceToDevice, c.s));
