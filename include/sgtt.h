@@ -317,6 +317,10 @@ int sgtt_mlp_attach(sgtt_system* sys, sgtt_mlp* mlp);
  * context stream (process-wide switch; enabling clears earlier records).
  * Adds two event records per launch while enabled. */
 int sgtt_profile_enable(sgtt_context* ctx, int enable);
+/* The same switch restricted to the kernel classes whose bit is set in
+ * class_mask (bit c = class id c; 0 turns profiling off), so that a timed
+ * run pays the event records of the classes it reports only. */
+int sgtt_profile_enable_classes(sgtt_context* ctx, unsigned class_mask);
 /* Sums since enabling, per kernel class (index = class id, see
  * sgtt_profile_class_name): event seconds, algorithmic bytes and flops (what
  * each launch's operation must read/write and compute, from its arguments),

@@ -17,6 +17,7 @@ enum KernelClass {
 };
 const char* kernel_class_name(int cls);
 void prof_enable(bool on);
+void prof_enable_mask(unsigned class_mask);   // bit c records class c; 0 = off
 bool prof_enabled();
 // sums since the last reset: seconds (from events), bytes, flops, launches
 void prof_read(double* seconds, double* bytes, double* flops, long* launches);
@@ -129,22 +130,46 @@ void core1_diag(hipStream_t s, int n1, int r, int k, const double* w, int ldw, c
 void core2_block(hipStream_t s, int r1, int n2, int r2, const double* in, const double* X, int k1, int k2,
                  double* out, int R1, int R2, int row0, int col0);
 
-// One-workgroup truncated eigen-decomposition of a symmetric PSD Gram
-// matrix S (N x N row-major, overwritten), following the TT-SVD rank rule:
-// pivoted Cholesky until the remaining trace is <= frac*delta^2, Jacobi
-// eigen-decomposition of the small factor, rank k = smallest r >= 1 with
-// tail + residual <= delta^2, U (N x k, ldU = kmax) orthonormal leading
-// eigenvectors.  delta^2 = eps^2 * normsq / 2 where normsq = *normsq_in if
-// given, else trace(S) (written to *normsq_out).  Writes k to *k_out and
-// the kept eigenvalue sum to *kept_out.  L: scratch N x kmax (+ N).
-// *info = 1 when kmax pivots were not enough and kmax < rank_bound (the
-// largest rank the matrix can have), i.e. the rank capacity is exceeded;
-// *info = 2 when more than 96 pivots are needed and large_ok is set (the
-// caller then runs the blocked path); without large_ok the pivoted Cholesky
-// subspace (orthonormalized) is the truncation, up to 512 columns.
-void trunc_eig(hipStream_t s, int N, double* S, double eps, const double* normsq_in, double* normsq_out,
-               double* U, int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound,
-               int large_ok = 0);
+// Truncated eigen-decomposition of a symmetric PSD Gram matrix S (N x N
+// row-major), following the TT-SVD rank rule, in stages (the full routine
+// is trunc_sym in tt_core):
+//  trunc_pc: one-workgroup pivoted Cholesky S ~ L L^T (L column-major, ld N)
+//    until the remaining trace is <= delta^2 / 16.  delta^2 = eps^2 normsq / 2
+//    where normsq = *normsq_in if given, else trace(S) (written to
+//    *normsq_out).  *info = 1 when kmax pivots were not enough and kmax <
+//    rank_bound (rank capacity exceeded); *info = 2 when more than 96 pivots
+//    are needed and large_ok is set (the caller runs the blocked path);
+//    without large_ok the pivoted Cholesky subspace (orthonormalized) is the
+//    truncation, up to 512 columns, written to U (N x k, ld kmax) with *k_out
+//    and the kept trace *kept_out.  A zero matrix gives k = 1, U = e_1.
+//    Otherwise *kp_out = kp > 0 pivots and state[0..3] = {trace, delta^2,
+//    zero threshold, residual trace} for the next stage; *kp_out = 0 when
+//    the stage finished the truncation (or *info = 2).  L: scratch N x kmax
+//    (+ N).
+//    In mode 0 the columns kp .. km-1 of L are zeroed (km = min(96, kmax)).
+//  The later stages read kp (and k) from device memory and do nothing when
+//  the first stage finished, so the whole chain is queued without a host
+//  round trip:
+//  trunc_jacobi: for T = L^T L (km x km, ld 96), cyclic Jacobi on its
+//    leading kp x kp block, rank k = smallest r >= 1 with discarded
+//    eigenvalues + residual <= delta^2, writes *k_out, the kept eigenvalue
+//    sum *kept_out and W = V_k diag(lambda^-1/2) (km x km, zero outside
+//    kp x k, ld 96), so that L W has orthonormal columns.
+//  chol_inv_upper: R = C^-T (km x km, zero outside k x k, ld 96) for the
+//    Cholesky factor C of the leading k x k block of G (ld 96): U R has
+//    orthonormal columns when G = U^T U; *info = 3 when G is not
+//    numerically positive definite.
+//  take_basis: U[i][c] = X[i][c] (ld ldx) for c < k when the eigen stage ran.
+constexpr int TRUNC_KSMALL = 96;
+void trunc_pc(hipStream_t s, int N, double* S, double eps, const double* normsq_in, double* normsq_out, double* U,
+              int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound, int large_ok,
+              int* kp_out, double* state);
+void trunc_jacobi(hipStream_t s, int km, const int* kp_dev, const double* T, const double* state, double* W,
+                  int* k_out, double* kept_out);
+void chol_inv_upper(hipStream_t s, int km, const int* kp_dev, const int* k_dev, const double* G, double* R,
+                    int* info);
+void take_basis(hipStream_t s, const int* kp_dev, const int* k_dev, int N, const double* X, int ldx, double* U,
+                int kmax);
 
 // Blocked pivoted Cholesky of a symmetric PSD Gram matrix S (N x N),
 // used when more than 96 pivots are needed.  pc_init: d = diag(S),
@@ -203,6 +228,10 @@ struct BcrDev {
   int n = 0, nblk = 0, maxbs = 0, npass = 0;
   double ndata = 0;                 // doubles of block data (for the profiler)
   std::vector<int> pass_begin;      // host: ops of pass p are [pass_begin[p], pass_begin[p + 1])
+  // host, per pass, for the profiler: sum over ops and terms of rows x cols
+  // (flops = 2 * that * columns), doubles of block data, and rows of the
+  // right-hand side read or written (times columns)
+  std::vector<double> pass_mk, pass_data, pass_rows;
   BcrOpDesc* ops = nullptr;
   double* data = nullptr;
 };

@@ -24,9 +24,11 @@ struct ProfRec {
   int cls, region;
   hipEvent_t a, b;
   double bytes, flops;
+  long launches;
 };
 struct Profiler {
   bool on = false;
+  unsigned mask = ~0u;   // kernel classes recorded while on
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
@@ -43,29 +45,39 @@ Profiler g_prof;
 std::mutex g_prof_mu;
 thread_local int g_region = 0;   // per host thread (workers of batched solves)
 
+// Brackets launches of one kernel class with HIP events on their stream.
+// A scope may cover several dependent launches of the class (launches > 1);
+// its time then includes the dispatch gaps between them.
 struct ProfScope {
   int cls;
   hipStream_t s;
   hipEvent_t a = nullptr;
   double bytes, flops;
-  ProfScope(int c, hipStream_t st, double by, double fl) : cls(c), s(st), bytes(by), flops(fl) {
-    if (!g_prof.on) return;
+  long launches;
+  ProfScope(int c, hipStream_t st, double by, double fl, long nl = 1)
+      : cls(c), s(st), bytes(by), flops(fl), launches(nl) {
+    if (!g_prof.on || !((g_prof.mask >> c) & 1u)) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     a = g_prof.ev();
     (void)hipEventRecord(a, s);
+  }
+  void add(double by, double fl, long nl) {
+    bytes += by;
+    flops += fl;
+    launches += nl;
   }
   ~ProfScope() {
     if (!a) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     hipEvent_t b = g_prof.ev();
     (void)hipEventRecord(b, s);
-    g_prof.recs.push_back(ProfRec{cls, g_region, a, b, bytes, flops});
+    g_prof.recs.push_back(ProfRec{cls, g_region, a, b, bytes, flops, launches});
   }
 };
 }  // namespace
 
 const char* kernel_class_name(int cls) {
-  static const char* names[] = {"k_gemm", "k_gemm_ptr", "k_spmm", "k_bcr_pass", "k_trunc_eig",
+  static const char* names[] = {"k_gemm", "k_gemm_ptr", "k_spmm", "k_bcr", "k_trunc_eig",
                                 "k_reduce_partials", "other", "k_gemm_lowp"};
   return (cls >= 0 && cls < KC_COUNT) ? names[cls] : "?";
 }
@@ -90,7 +102,23 @@ void prof_read_regions(double* seconds) {
     seconds[r.region * KC_COUNT + r.cls] += ms * 1e-3;
   }
 }
-void prof_enable(bool on) { g_prof.on = on; }
+void prof_enable(bool on) { prof_enable_mask(on ? ~0u : 0u); }
+void prof_enable_mask(unsigned mask) {
+  const bool on = mask != 0;
+  if (on) {
+    // create the events before the profiled region: creating them while
+    // kernels are queued would add host time to what is measured
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    constexpr size_t kReserve = 1 << 17;
+    while (g_prof.pool.size() < kReserve) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) break;
+      g_prof.pool.push_back(e);
+    }
+  }
+  g_prof.mask = mask;
+  g_prof.on = on;
+}
 
 namespace {
 thread_local int g_gemm_prec = GP_F64;
@@ -119,7 +147,7 @@ void prof_read(double* seconds, double* bytes, double* flops, long* launches) {
     seconds[r.cls] += ms * 1e-3;
     bytes[r.cls] += r.bytes;
     flops[r.cls] += r.flops;
-    launches[r.cls] += 1;
+    launches[r.cls] += r.launches;
   }
 }
 
@@ -700,22 +728,56 @@ __device__ inline void block_argmax_sum(double v, int idx, double sm, double* sh
   }
 }
 
-__global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restrict__ S, double eps,
-                                                          const double* normsq_in, double* normsq_out,
-                                                          double* __restrict__ U, int kmax, double* __restrict__ L,
-                                                          double* __restrict__ dwork, int* k_out, double* kept_out,
-                                                          int* info, int rank_bound, int large_ok) {
-  __shared__ double T[KSMALL * KLD];
-  __shared__ double V[KSMALL * KLD];
+// Two-pass classical Gram-Schmidt of the k columns of X (column-major, ld
+// N, overwritten), one wave per coefficient; U (N x k, ld kmax) receives the
+// orthonormal columns.  Whole workgroup; lp holds >= k doubles of LDS.
+__device__ void gs2_block(int N, int k, double* __restrict__ X, double* __restrict__ U, int kmax, double* lp,
+                          double* shv) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int wv = tid / WAVE, ln = tid % WAVE, nwv = nth / WAVE;
+  for (int c = 0; c < k; ++c) {
+    double* xc = X + (long)c * N;
+    for (int pass = 0; pass < 2 && c > 0; ++pass) {
+      for (int d = wv; d < c; d += nwv) {
+        const double sv = wave_dot(X + (long)d * N, xc, N);
+        if (ln == 0) lp[d] = sv;
+      }
+      __syncthreads();
+      for (int i = tid; i < N; i += nth) xc[i] -= col_combo(X, N, i, lp, 1, c);
+      __syncthreads();
+    }
+    double s = 0.0;
+    for (int i = tid; i < N; i += nth) s = fma(xc[i], xc[i], s);
+    s = block_sum(s, shv);
+    double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    for (int i = tid; i < N; i += nth) xc[i] *= inv;
+    __syncthreads();
+  }
+  for (long e = tid; e < (long)N * k; e += nth) {
+    int i = e / k, c = e % k;
+    U[(long)i * kmax + c] = X[(long)c * N + i];
+  }
+}
+
+
+// Symmetric truncation of a Gram matrix S (N x N), first stage, one
+// workgroup.  Pivoted Cholesky S ~ L L^T (L column-major, ld N).  Outcomes:
+// info = 2 (more than KSMALL pivots needed and large_ok: the caller runs the
+// blocked path); a zero matrix (rank 1, U = e_1); mode 1 (more than KSMALL
+// pivots, bond without a large path: U = orthonormal basis of the pivoted
+// columns, by two-pass Gram-Schmidt here); or mode 0: *kp_out = kp > 0 and
+// state = {trace, delta^2, zero threshold, residual trace} for the
+// eigen-decomposition stage (k_trunc_jacobi), else *kp_out = 0.
+__global__ __launch_bounds__(TE_THREADS) void k_trunc_pc(int N, double* __restrict__ S, double eps,
+                                                         const double* normsq_in, double* normsq_out,
+                                                         double* __restrict__ U, int kmax, double* __restrict__ L,
+                                                         double* __restrict__ dwork, int* k_out, double* kept_out,
+                                                         int* info, int rank_bound, int large_ok, int* kp_out,
+                                                         double* state) {
   __shared__ double shv[32];
   __shared__ int shi[32];
   __shared__ double shs[32];
   __shared__ double lp[KCAP];
-  __shared__ double rc[KSMALL / 2 + 1], rs[KSMALL / 2 + 1];
-  __shared__ int rp[KSMALL / 2 + 1], rq[KSMALL / 2 + 1];
-  __shared__ double lam[KSMALL];
-  __shared__ int order[KSMALL];
-  __shared__ int s_flag;
   const int tid = threadIdx.x, nth = blockDim.x;
   if (kmax > KCAP) kmax = KCAP;
   // --- trace and tolerance
@@ -781,6 +843,7 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
     kp = j + 1;
   }
   __syncthreads();
+  if (tid == 0) *kp_out = 0;
   if (mode == 1 && large_ok) {
     if (tid == 0) *info = 2;
     return;
@@ -806,28 +869,51 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
     }
     __syncthreads();
   }
-  const int n = kp;
   if (mode == 0) {
-  // --- T = L^T L (kp x kp), one wavefront per entry; V = I
-  {
-    const int wv = tid / WAVE, ln = tid % WAVE, nwv = nth / WAVE;
-    const int ntri = kp * (kp + 1) / 2;
-    for (int e = wv; e < ntri; e += nwv) {
-      // e -> (a, b) with a <= b, row-major over the upper triangle
-      int a = (int)((2.0 * kp + 1.0 - sqrt((2.0 * kp + 1.0) * (2.0 * kp + 1.0) - 8.0 * e)) / 2.0);
-      while (a > 0 && a * kp - a * (a - 1) / 2 > e) --a;
-      while ((a + 1) * kp - (a + 1) * a / 2 <= e) ++a;
-      const int b = a + (e - (a * kp - a * (a - 1) / 2));
-      const double s = wave_dot(L + (long)a * N, L + (long)b * N, N);
-      if (ln == 0) {
-        T[a * KLD + b] = s;
-        T[b * KLD + a] = s;
-      }
+    // columns kp .. min(KSMALL, kmax) - 1 of L are zero for the fixed-size
+    // products of the next stages
+    const int km = min(KSMALL, kmax);
+    for (long e = tid; e < (long)N * (km - kp); e += nth) L[(long)kp * N + e] = 0.0;
+    if (tid == 0) {
+      *kp_out = kp;
+      state[0] = tr;
+      state[1] = delta2;
+      state[2] = zero_thr;
+      state[3] = resid;
     }
-    for (int e = tid; e < kp * kp; e += nth) {
-      int a = e / kp, b = e % kp;
-      V[a * KLD + b] = (a == b) ? 1.0 : 0.0;
-    }
+    return;
+  }
+  const int k = shi[0];
+  __syncthreads();
+  gs2_block(N, k, L, U, kmax, lp, shv);
+}
+
+// Second stage: eigen-decomposition of T = L^T L (kp x kp of a km x km
+// product, ld KSMALL; kp read from the first stage, nothing to do when 0) by
+// cyclic Jacobi in LDS, rank cut k (smallest k with discarded eigenvalues +
+// residual trace <= delta^2, or every numerically nonzero direction when
+// delta = 0), and W = V_k diag(lambda^-1/2) (km x km, zero outside kp x k,
+// ld KSMALL) so that L W spans the kept subspace with orthonormal columns.
+__global__ __launch_bounds__(TE_THREADS) void k_trunc_jacobi(int km, const int* __restrict__ kp_dev,
+                                                             const double* __restrict__ Tg,
+                                                             const double* __restrict__ state, double* __restrict__ W,
+                                                             int* k_out, double* kept_out) {
+  __shared__ double T[KSMALL * KLD];
+  __shared__ double V[KSMALL * KLD];
+  __shared__ int shi[32];
+  __shared__ double rc[KSMALL / 2 + 1], rs[KSMALL / 2 + 1];
+  __shared__ int rp[KSMALL / 2 + 1], rq[KSMALL / 2 + 1];
+  __shared__ double lam[KSMALL];
+  __shared__ int order[KSMALL];
+  __shared__ int s_flag;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int n = *kp_dev;
+  if (n <= 0) return;   // the first stage finished the truncation
+  const double delta2 = state[1], zero_thr = state[2], resid = state[3];
+  for (int e = tid; e < n * n; e += nth) {
+    const int a = e / n, b = e - a * n;
+    T[a * KLD + b] = 0.5 * (Tg[a * KSMALL + b] + Tg[b * KSMALL + a]);
+    V[a * KLD + b] = (a == b) ? 1.0 : 0.0;
   }
   __syncthreads();
   // --- cyclic Jacobi (round-robin pairs)
@@ -936,46 +1022,92 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_eig(int N, double* __restr
   __syncthreads();
   const int kc = shi[0];
   __syncthreads();
-  // --- U = L V_k diag(lambda^-1/2), column-major into the U buffer
-  for (long e = tid; e < (long)N * kc; e += nth) {
-    const int c = e / N, i = e % N;
-    const int oc = order[c];
-    const double sv = col_combo(L, N, i, V + oc, KLD, n);
-    const double l = lam[oc];
-    U[(long)c * N + i] = l > 0.0 ? sv / sqrt(l) : 0.0;
+  // --- W = V_k diag(lambda^-1/2), zero outside kp x k (km x km written)
+  for (int e = tid; e < km * km; e += nth) {
+    const int a = e / km, c = e - a * km;
+    double w = 0.0;
+    if (a < n && c < kc) {
+      const int oc = order[c];
+      const double l = lam[oc];
+      w = l > 0.0 ? V[a * KLD + oc] / sqrt(l) : 0.0;
+    }
+    W[a * KSMALL + c] = w;
+  }
+}
+
+// R = C^-T (upper triangular, km x km, zero outside k x k, ld KSMALL) for
+// the Cholesky factor C of the leading k x k block of the symmetric positive
+// definite G (ld KSMALL), so that U R has orthonormal columns when
+// G = U^T U (Cholesky QR); k read from the eigen stage, nothing to do when
+// the first stage finished.  *info = 3 if G is not numerically positive
+// definite.
+__global__ __launch_bounds__(256) void k_chol_inv(int km, const int* __restrict__ kp_dev, const int* __restrict__ k_dev,
+                                                  const double* __restrict__ G, double* __restrict__ R, int* info) {
+  __shared__ double C[KSMALL * KLD];
+  __shared__ double X[KSMALL * KLD];
+  __shared__ int bad;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if (*kp_dev <= 0) return;   // the first stage finished the truncation
+  const int k = *k_dev;
+  for (int e = tid; e < km * km; e += nth) R[(e / km) * KSMALL + e % km] = 0.0;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < k * k; e += nth) {
+    const int a = e / k, b = e - a * k;
+    C[a * KLD + b] = a >= b ? 0.5 * (G[a * KSMALL + b] + G[b * KSMALL + a]) : 0.0;
   }
   __syncthreads();
-  // move to L (column-major work area for Gram-Schmidt)
-  for (long e = tid; e < (long)N * kc; e += nth) L[e] = U[e];
-  __syncthreads();
-  }  // mode == 0
-  const int k = shi[0];
-  __syncthreads();
-  // --- orthonormalize the k columns of L (column-major) by classical
-  // Gram-Schmidt with two passes, one wave per coefficient; write U (N x k,
-  // row-major, ld kmax)
-  const int wv = tid / WAVE, ln = tid % WAVE, nwv = nth / WAVE;
-  for (int c = 0; c < k; ++c) {
-    double* xc = L + (long)c * N;
-    for (int pass = 0; pass < 2 && c > 0; ++pass) {
-      for (int d = wv; d < c; d += nwv) {
-        const double sv = wave_dot(L + (long)d * N, xc, N);
-        if (ln == 0) lp[d] = sv;
-      }
-      __syncthreads();
-      for (int i = tid; i < N; i += nth) xc[i] -= col_combo(L, N, i, lp, 1, c);
-      __syncthreads();
+  // right-looking Cholesky, lower triangle
+  for (int j = 0; j < k; ++j) {
+    const double d = C[j * KLD + j];
+    if (d <= 0.0) {
+      if (tid == 0) bad = 1;
+      break;
     }
-    double s = 0.0;
-    for (int i = tid; i < N; i += nth) s = fma(xc[i], xc[i], s);
-    s = block_sum(s, shv);
-    double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-    for (int i = tid; i < N; i += nth) xc[i] *= inv;
+    const double r = sqrt(d);
+    __syncthreads();
+    if (tid == 0) C[j * KLD + j] = r;
+    for (int i = j + 1 + tid; i < k; i += nth) C[i * KLD + j] /= r;
+    __syncthreads();
+    const int m = k - j - 1;
+    for (int e = tid; e < m * m; e += nth) {
+      const int a = e / m, b = e - a * m;
+      if (b > a) continue;
+      const int i = j + 1 + a, l = j + 1 + b;
+      C[i * KLD + l] -= C[i * KLD + j] * C[l * KLD + j];
+    }
     __syncthreads();
   }
-  for (long e = tid; e < (long)N * k; e += nth) {
-    int i = e / k, c = e % k;
-    U[(long)i * kmax + c] = L[(long)c * N + i];
+  if (bad) {
+    if (tid == 0) *info = 3;
+    return;
+  }
+  // X = C^-1 by columns (thread j owns column j), then R = X^T
+  for (int j = tid; j < k; j += nth) {
+    for (int i = 0; i < j; ++i) X[i * KLD + j] = 0.0;
+    X[j * KLD + j] = 1.0 / C[j * KLD + j];
+    for (int i = j + 1; i < k; ++i) {
+      double sm = 0.0;
+      for (int l = j; l < i; ++l) sm = fma(C[i * KLD + l], X[l * KLD + j], sm);
+      X[i * KLD + j] = -sm / C[i * KLD + i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += nth) {
+    const int a = e / k, b = e - a * k;
+    R[a * KSMALL + b] = X[b * KLD + a];
+  }
+}
+
+// U[i][c] = X[i][c] (X row-major, ld ldx) for c < *k_dev, when the eigen
+// stage ran (*kp_dev > 0)
+__global__ void k_take_basis(const int* __restrict__ kp_dev, const int* __restrict__ k_dev, int N,
+                             const double* __restrict__ X, int ldx, double* __restrict__ U, int kmax) {
+  if (*kp_dev <= 0) return;
+  const int k = *k_dev;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < (long)N * k; e += (long)gridDim.x * blockDim.x) {
+    const long i = e / k;
+    const int c = (int)(e - i * k);
+    U[i * kmax + c] = X[i * ldx + c];
   }
 }
 
@@ -1722,14 +1854,37 @@ void core2_block(hipStream_t s, int r1, int n2, int r2, const double* in, const 
                      row0, col0);
 }
 
-void trunc_eig(hipStream_t s, int N, double* S, double eps, const double* normsq_in, double* normsq_out, double* U,
-               int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound, int large_ok) {
+void trunc_pc(hipStream_t s, int N, double* S, double eps, const double* normsq_in, double* normsq_out, double* U,
+              int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound, int large_ok,
+              int* kp_out, double* state) {
+  static_assert(TRUNC_KSMALL == KSMALL, "truncation stage sizes");
   // dwork: N doubles placed after L (caller sizes L as N*kmax + N)
   double* dwork = L + (long)N * kmax;
   ProfScope ps(KC_TRUNC, s, 8.0 * (double)N * N, 0.0);
-  hipLaunchKernelGGL(k_trunc_eig, dim3(1), dim3(TE_THREADS), 0, s, N, S, eps, normsq_in, normsq_out, U, kmax, L, dwork,
-                     k_out, kept_out, info, rank_bound, large_ok);
+  hipLaunchKernelGGL(k_trunc_pc, dim3(1), dim3(TE_THREADS), 0, s, N, S, eps, normsq_in, normsq_out, U, kmax, L, dwork,
+                     k_out, kept_out, info, rank_bound, large_ok, kp_out, state);
 }
+
+void trunc_jacobi(hipStream_t s, int km, const int* kp_dev, const double* T, const double* state, double* W,
+                  int* k_out, double* kept_out) {
+  if (km < 1 || km > KSMALL) throw std::runtime_error("trunc_jacobi: size out of range");
+  ProfScope ps(KC_TRUNC, s, 8.0 * 2.0 * km * km, 0.0);
+  hipLaunchKernelGGL(k_trunc_jacobi, dim3(1), dim3(TE_THREADS), 0, s, km, kp_dev, T, state, W, k_out, kept_out);
+}
+
+void chol_inv_upper(hipStream_t s, int km, const int* kp_dev, const int* k_dev, const double* G, double* R,
+                    int* info) {
+  if (km < 1 || km > KSMALL) throw std::runtime_error("chol_inv_upper: size out of range");
+  ProfScope ps(KC_TRUNC, s, 8.0 * 2.0 * km * km, (double)km * km * km / 2.0);
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, s, km, kp_dev, k_dev, G, R, info);
+}
+
+void take_basis(hipStream_t s, const int* kp_dev, const int* k_dev, int N, const double* X, int ldx, double* U,
+                int kmax) {
+  const unsigned nb = std::min<unsigned>(cdiv((long)N * ldx, 256), 1024);
+  hipLaunchKernelGGL(k_take_basis, dim3(std::max(1u, nb)), dim3(256), 0, s, kp_dev, k_dev, N, X, ldx, U, kmax);
+}
+
 
 
 void pc_init(hipStream_t s, int N, const double* S, double eps, const double* normsq_in, double* normsq_out, double* d,
@@ -1796,14 +1951,20 @@ constexpr int kNumBcrVariants = sizeof(kBcrVariants) / sizeof(kBcrVariants[0]);
 std::mutex g_bcr_mu;
 std::map<std::tuple<const double*, int, int>, std::vector<int>> g_bcr_choice;   // (factor, ncols, ncomp) -> variant per pass
 
-// ev (npass + 1 events, optional) brackets every pass
+// ev (npass + 1 events, optional) brackets every pass.  The profiler sees
+// one scope per solve that counts every pass as a launch (algorithmic bytes
+// of a pass: its block data once, the right-hand side rows it reads and
+// writes).
 void bcr_run(hipStream_t s, const BcrDev& f, const int* vars, int ncomp, double* B, long ldb, double* X, long ldx,
              int ncols, hipEvent_t* ev = nullptr) {
+  const double cols = (double)ncomp * ncols;
+  ProfScope ps(KC_BCR, s, 0.0, 0.0, 0);
   for (int p = 0; p < f.npass; ++p) {
     if (ev) (void)hipEventRecord(ev[p], s);
     const int o0 = f.pass_begin[p], no = f.pass_begin[p + 1] - o0;
     if (no <= 0) continue;
     const BcrVariant& v = kBcrVariants[vars[p]];
+    ps.add(8.0 * (f.pass_data[p] + f.pass_rows[p] * cols), 2.0 * f.pass_mk[p] * cols, 1);
     hipLaunchKernelGGL(v.fn, dim3(no, cdiv((long)ncomp * ncols, v.cb), cdiv(f.maxbs, 64)), dim3(256), 0, s, f.ops, o0,
                        f.data, B, ldb, X, ldx, ncols, ncomp, (long)f.n);
   }
@@ -1878,7 +2039,6 @@ void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, d
       g_bcr_choice[key] = vars;
     }
   }
-  ProfScope ps(KC_BCR, s, 8.0 * (f.ndata + 3.0 * ncomp * (double)f.n * ncols), 2.0 * f.ndata * ncols * ncomp);
   bcr_run(s, f, vars.data(), ncomp, B, ldb, X, ldx, ncols);
 }
 

@@ -129,6 +129,22 @@ BcrDev upload_bcr(Ctx& c, const BcrFactor& f) {
       }
     }
   }
+  d.pass_mk.assign(d.npass, 0.0);
+  d.pass_data.assign(d.npass, 0.0);
+  d.pass_rows.assign(d.npass, 0.0);
+  for (int p = 0; p < d.npass; ++p) {
+    std::map<long, long> blocks;   // distinct blocks of the pass
+    for (int o = f.pass_begin[p]; o < f.pass_begin[p + 1]; ++o) {
+      const BcrOpDesc& q = ops[o];
+      d.pass_rows[p] += q.bo * ((q.flags & 1) ? 2.0 : 1.0);
+      for (int t = 0; t < q.nterm; ++t) {
+        d.pass_mk[p] += (double)q.bo * q.in_bi[t];
+        d.pass_rows[p] += q.in_bi[t];
+        blocks[q.off[t]] = bcr_fragment_size(q.bo, q.in_bi[t]);
+      }
+    }
+    for (const auto& b : blocks) d.pass_data[p] += (double)b.second;
+  }
   frag.resize(frag.size() + BCR_DATA_PAD, 0.0);
   d.ndata = (double)frag.size();
   d.ops = dev_upload(c, ops);
@@ -1611,6 +1627,14 @@ int sgtt_profile_enable(sgtt_context* ctx, int enable) {
   (void)hipStreamSynchronize(ctx->c.s);
   prof_reset();
   prof_enable(enable != 0);
+  return SGTT_OK;
+}
+
+int sgtt_profile_enable_classes(sgtt_context* ctx, unsigned class_mask) {
+  if (!ctx) return SGTT_E_INVALID;
+  (void)hipStreamSynchronize(ctx->c.s);
+  prof_reset();
+  prof_enable_mask(class_mask);
   return SGTT_OK;
 }
 

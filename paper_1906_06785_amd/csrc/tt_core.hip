@@ -240,6 +240,43 @@ static Skeleton trunc_skeleton(Ctx& c, int N, double* S, double eps, const doubl
 }
 
 namespace {
+// Truncated eigen-decomposition of a Gram matrix S (N x N): the staged
+// routine behind every TT truncation (same contract as the stages in
+// kernels.h).  The pivoted Cholesky and the small Jacobi eigen-solver run
+// in one workgroup each; the products with L and the re-orthonormalization
+// (Cholesky QR, twice) are GEMMs over the whole device, at the fixed width
+// km = min(96, kmax) so that nothing waits for the host: the stages read the
+// pivot count and the rank from device memory.  *info = 3 reports a failed
+// Cholesky QR.
+void trunc_sym(Ctx& c, int N, double* S, double eps, const double* normsq_in, double* normsq_out, double* U, int kmax,
+               double* Lw, int* k_out, double* kept_out, int* info, int rank_bound, int large_ok = 0) {
+  GemmPrecisionScope gp(GP_F64);
+  constexpr int KS = TRUNC_KSMALL;
+  const int km = std::min(KS, kmax);
+  int* kp_dev = c.dint + 32;
+  double* state = c.dscal + 240;
+  trunc_pc(c.s, N, S, eps, normsq_in, normsq_out, U, kmax, Lw, k_out, kept_out, info, rank_bound, large_ok, kp_dev,
+           state);
+  double* small = c.pool.get((size_t)4 * KS * KS);
+  double *T = small, *W = small + KS * KS, *G = small + 2 * KS * KS, *R = small + 3 * KS * KS;
+  double* U0 = c.pool.get((size_t)N * km);
+  double* U1 = c.pool.get((size_t)N * km);
+  gemm(c.s, 1, km, km, N, 1.0, Lw, 0, N, 1, Lw, 0, 1, N, 0.0, T, 0, KS, 1);   // T = L^T L
+  trunc_jacobi(c.s, km, kp_dev, T, state, W, k_out, kept_out);
+  gemm(c.s, 1, N, km, km, 1.0, Lw, 0, 1, N, W, 0, KS, 1, 0.0, U0, 0, 1, N);   // U0 = L W (column-major)
+  // Cholesky QR twice: U1 = U0 R0 (column-major), U0 <- U1 R1 (row-major, ld km)
+  gemm(c.s, 1, km, km, N, 1.0, U0, 0, N, 1, U0, 0, 1, N, 0.0, G, 0, KS, 1);
+  chol_inv_upper(c.s, km, kp_dev, k_out, G, R, info);
+  gemm(c.s, 1, N, km, km, 1.0, U0, 0, 1, N, R, 0, KS, 1, 0.0, U1, 0, 1, N);
+  gemm(c.s, 1, km, km, N, 1.0, U1, 0, N, 1, U1, 0, 1, N, 0.0, G, 0, KS, 1);
+  chol_inv_upper(c.s, km, kp_dev, k_out, G, R, info);
+  gemm(c.s, 1, N, km, km, 1.0, U1, 0, 1, N, R, 0, KS, 1, 0.0, U0, 0, km, 1);
+  take_basis(c.s, kp_dev, k_out, N, U0, km, U, kmax);
+  c.pool.put(U0);
+  c.pool.put(U1);
+  c.pool.put(small);
+}
+
 double* upload_descs(Ctx& c, const std::vector<GemmDesc>& d) {
   size_t nd = (d.size() * sizeof(GemmDesc) + sizeof(double) - 1) / sizeof(double);
   double* buf = c.pool.get(nd);
@@ -331,13 +368,14 @@ TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_no
   double* U1 = c.pool.get((size_t)n1 * kmax1);
   {
     double* Lw = c.scratch2((size_t)n1 * kmax1 + n1 + 64);
-    trunc_eig(c.s, n1, S1, eps, nullptr, dnorm, U1, kmax1, Lw, dk, dkept1, dk + 1, std::min(n1, R1));
+    trunc_sym(c, n1, S1, eps, nullptr, dnorm, U1, kmax1, Lw, dk, dkept1, dk + 1, std::min(n1, R1));
   }
   int h[4];
   SGTT_HIP(hipMemcpyAsync(c.hint, dk, 2 * sizeof(int), hipMemcpyDeviceToHost, c.s));
   c.sync();
   h[0] = c.hint[0];
   h[1] = c.hint[1];
+  if (h[1] == 3) throw SgttError(-1, "TT truncation: orthonormalization failed (bond 1)");
   if (h[1] != 0) throw SgttError(-4, "TT rank capacity exceeded (bond 1)");
   const int k1 = h[0];
   gemm_precision(amb);
@@ -370,12 +408,13 @@ TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_no
   double* U2 = c.pool.get((size_t)N2 * kmax2);
   {
     double* Lw = c.scratch2((size_t)N2 * kmax2 + N2 + 64);
-    trunc_eig(c.s, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw, dk + 2, dkept2, dk + 3, std::min(N2, R2), 1);
+    trunc_sym(c, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw, dk + 2, dkept2, dk + 3, std::min(N2, R2), 1);
     SGTT_HIP(hipMemcpyAsync(c.hint, dk + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, c.s));
     c.sync();
     h[2] = c.hint[0];
     h[3] = c.hint[1];
   }
+  if (h[3] == 3) throw SgttError(-1, "TT truncation: orthonormalization failed (bond 2)");
   if (h[3] == 1) throw SgttError(-4, "TT rank capacity exceeded (bond 2)");
   Skeleton sk;
   if (h[3] == 2)
@@ -419,9 +458,10 @@ TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, dou
   const int kmax1 = std::min({n1, maxrank, RANK_CAP});
   double* U1 = c.pool.get((size_t)n1 * kmax1);
   double* Lw = c.scratch2((size_t)n1 * kmax1 + n1 + 64);
-  trunc_eig(c.s, n1, S1, eps, nullptr, dnorm, U1, kmax1, Lw, dk, dkept, dk + 1, n1);
+  trunc_sym(c, n1, S1, eps, nullptr, dnorm, U1, kmax1, Lw, dk, dkept, dk + 1, n1);
   int h[4];
   read_ints(c, dk, 2, h);
+  if (h[1] == 3) throw SgttError(-1, "TT truncation: orthonormalization failed (full bond 1)");
   if (h[1] != 0) throw SgttError(-4, "TT rank capacity exceeded (full bond 1)");
   const int k1 = h[0];
   const int N2 = k1 * n2;
@@ -433,8 +473,9 @@ TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, dou
   const int kmax2 = std::min({N2, maxrank, RANK_CAP});
   double* U2 = c.pool.get((size_t)N2 * kmax2);
   double* Lw2 = c.scratch2((size_t)N2 * kmax2 + N2 + 64);
-  trunc_eig(c.s, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw2, dk + 2, dkept, dk + 3, std::min(N2, n3), 1);
+  trunc_sym(c, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw2, dk + 2, dkept, dk + 3, std::min(N2, n3), 1);
   read_ints(c, dk + 2, 2, h + 2);
+  if (h[3] == 3) throw SgttError(-1, "TT truncation: orthonormalization failed (full bond 2)");
   if (h[3] == 1) throw SgttError(-4, "TT rank capacity exceeded (full bond 2)");
   Skeleton sk;
   if (h[3] == 2)

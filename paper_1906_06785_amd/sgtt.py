@@ -117,6 +117,7 @@ _sig = {
     "sgtt_hessenberg_lsq": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int, C.c_double, C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]),
     "sgtt_profile_enable": (C.c_int, [_P, C.c_int]),
+    "sgtt_profile_enable_classes": (C.c_int, [_P, C.c_uint]),
     "sgtt_profile_read": (C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), C.POINTER(C.c_long), C.POINTER(C.c_int)]),
     "sgtt_profile_class_name": (C.c_char_p, [C.c_int]),
@@ -340,8 +341,17 @@ class Context:
         self.check(_lib.sgtt_expand(self._c, C.byref(s), out.data_ptr()))
         return out.reshape(buf.n1, buf.n2, buf.n3)
 
-    def profile(self, enable: bool):
-        self.check(_lib.sgtt_profile_enable(self._c, int(enable)))
+    def profile(self, enable: bool, classes=None):
+        """Switch the event profiler; classes (iterable of class names) limits
+        it to those kernel classes."""
+        if classes is None:
+            self.check(_lib.sgtt_profile_enable(self._c, int(enable)))
+            return
+        names = [_lib.sgtt_profile_class_name(i).decode() for i in range(16)]
+        mask = 0
+        for cname in classes:
+            mask |= 1 << names.index(cname)
+        self.check(_lib.sgtt_profile_enable_classes(self._c, mask if enable else 0))
 
     def profile_read(self):
         n = 16
