@@ -1694,9 +1694,10 @@ void gemm(hipStream_t s, int batch, int m, int n, int k, double alpha, const dou
           int kstep, long klimit) {
   if (m <= 0 || n <= 0 || batch <= 0) return;
   const long tiles = (long)cdiv(m, TM) * cdiv(n, TN);
-  if (batch == 1 && klimit == 0 && tiles <= 16 && k >= 2048) {
-    // small output, long reduction: split K over workgroups, then reduce
-    long nch = std::min<long>(k / 512, 256 / tiles);
+  if (batch == 1 && klimit == 0 && tiles <= 16 && k >= 384) {
+    // small output, long reduction: split K over workgroups (chunks of at
+    // least 128), then reduce
+    long nch = std::min<long>(k / 128, 256 / tiles);
     long ne = (long)m * n;
     double* ws = nch > 1 ? splitk_ws(s, (size_t)(nch * ne)) : nullptr;
     if (ws) {

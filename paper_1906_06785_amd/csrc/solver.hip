@@ -609,23 +609,23 @@ struct PrecOpts {
 TT exact_mean_solve(sgtt_system& S, const TT& y, double eps) {
   Ctx& c = S.ctx->c;
   const int nt = S.nt, nxi = S.nxi, nu = S.nu;
-  const long slab = (long)nu * nxi;              // one time step: node-major, nxi columns, contiguous
-  double* Z = c.pool.get((size_t)nt * nxi * y.r2);   // G1 x_1 G2: (nt nxi) x r2
+  const long ldw = (long)nt * nxi;
+  double* Z = c.pool.get((size_t)ldw * y.r2);   // G1 x_1 G2: (nt nxi) x r2
   gemm(c.s, 1, nt, nxi * y.r2, y.r1, 1.0, y.c1, 0, y.r1, 1, y.c2, 0, (long)nxi * y.r2, 1, 0.0, Z, 0,
        (long)nxi * y.r2, 1);
-  double* W = c.pool.get((size_t)nt * slab);   // W[t][x][xi] = sum_b G3[x][b] Z[t xi][b]
-  gemm(c.s, nt, nu, nxi, y.r2, 1.0, y.c3, 0, y.r2, 1, Z, (long)nxi * y.r2, 1, y.r2, 0.0, W, slab, nxi, 1);
+  double* W = c.pool.get((size_t)nu * ldw);     // node-major full tensor: W[x][t nxi + xi]
+  gemm(c.s, 1, nu, (int)ldw, y.r2, 1.0, y.c3, 0, y.r2, 1, Z, 0, 1, y.r2, 0.0, W, 0, ldw, 1);
   c.pool.put(Z);
-  double* Vn = c.pool.get((size_t)nt * slab);  // solution, same layout
+  double* Vn = c.pool.get((size_t)nu * ldw);    // solution, same layout
   for (int t = 0; t < nt; ++t) {
-    double* Wt = W + t * slab;
+    double* Wt = W + (long)t * nxi;
     if (t > 0)   // y_t + tau^-1 M v_{t-1}
-      ell_spmm(c.s, S.ns, 2, S.ns, S.ns, S.Me_col, S.Me_val, Vn + (t - 1) * slab, nxi, 0, nxi, Wt, nxi, 0,
-               1.0 / S.tau, 1.0);
-    bcr_solve(c.s, S.Fbt, 2, Wt, nxi, Vn + t * slab, nxi, nxi);
+      ell_spmm(c.s, S.ns, 2, S.ns, S.ns, S.Me_col, S.Me_val, Vn + (long)(t - 1) * nxi, (int)ldw, 0, nxi, Wt,
+               (int)ldw, 0, 1.0 / S.tau, 1.0);
+    bcr_solve(c.s, S.Fbt, 2, Wt, ldw, Vn + (long)t * nxi, ldw, nxi);
   }
   double* V = W;                                 // C order (t, xi, x), reusing the consumed right-hand side
-  transpose_copy_batched(c.s, nt, nu, nxi, Vn, slab, nxi, V, slab, nu);
+  transpose_copy(c.s, nu, (int)ldw, Vn, ldw, V, nu);
   c.pool.put(Vn);
   TT out = tt_from_full(c, V, nt, nxi, nu, eps, nullptr);
   c.pool.put(W);
