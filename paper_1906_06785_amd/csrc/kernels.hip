@@ -933,7 +933,7 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_jacobi(int km, const int* 
         double c = 1.0, s = 0.0;
         if (q < n) {
           double apq = T[p * KLD + q], app = T[p * KLD + p], aqq = T[q * KLD + q];
-          if (fabs(apq) > fmax(1e-15 * sqrt(fabs(app * aqq)), 1e-17 * ttr) && apq != 0.0) {
+          if (fabs(apq) > fmax(1e-13 * sqrt(fabs(app * aqq)), 1e-16 * ttr) && apq != 0.0) {
             double th = (aqq - app) / (2.0 * apq);
             double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
@@ -1056,27 +1056,40 @@ __global__ __launch_bounds__(256) void k_chol_inv(int km, const int* __restrict_
     C[a * KLD + b] = a >= b ? 0.5 * (G[a * KSMALL + b] + G[b * KSMALL + a]) : 0.0;
   }
   __syncthreads();
-  // right-looking Cholesky, lower triangle
+  // right-looking Cholesky on the unscaled Schur complement: step j takes
+  // d_j = S[j][j] and updates S[i][l] -= S[i][j] S[l][j] / d_j for
+  // j < l <= i; column j is final after step j, so the scaling by sqrt(d_j)
+  // waits until the end and each step needs one barrier
+  __shared__ double rdiag[KSMALL];
   for (int j = 0; j < k; ++j) {
-    const double d = C[j * KLD + j];
+    __syncthreads();
+    const double d = C[j * KLD + j];   // same value on every thread
     if (d <= 0.0) {
       if (tid == 0) bad = 1;
       break;
     }
-    const double r = sqrt(d);
-    __syncthreads();
-    if (tid == 0) C[j * KLD + j] = r;
-    for (int i = j + 1 + tid; i < k; i += nth) C[i * KLD + j] /= r;
-    __syncthreads();
+    if (tid == 0) rdiag[j] = sqrt(d);
+    const double inv_d = 1.0 / d;
     const int m = k - j - 1;
-    for (int e = tid; e < m * m; e += nth) {
-      const int a = e / m, b = e - a * m;
-      if (b > a) continue;
+    for (int e = tid; e < m * (m + 1) / 2; e += nth) {
+      // e -> (a, b), b <= a, row-major over the lower triangle
+      int a = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+      while (a * (a + 1) / 2 > e) --a;
+      while ((a + 1) * (a + 2) / 2 <= e) ++a;
+      const int b = e - a * (a + 1) / 2;
       const int i = j + 1 + a, l = j + 1 + b;
-      C[i * KLD + l] -= C[i * KLD + j] * C[l * KLD + j];
+      C[i * KLD + l] -= C[i * KLD + j] * C[l * KLD + j] * inv_d;
     }
-    __syncthreads();
   }
+  __syncthreads();
+  if (!bad) {
+    for (int e = tid; e < k * k; e += nth) {
+      const int i = e / k, j = e - i * k;
+      if (i > j) C[i * KLD + j] /= rdiag[j];
+    }
+    for (int j = tid; j < k; j += nth) C[j * KLD + j] = rdiag[j];
+  }
+  __syncthreads();
   if (bad) {
     if (tid == 0) *info = 3;
     return;
@@ -1086,9 +1099,16 @@ __global__ __launch_bounds__(256) void k_chol_inv(int km, const int* __restrict_
     for (int i = 0; i < j; ++i) X[i * KLD + j] = 0.0;
     X[j * KLD + j] = 1.0 / C[j * KLD + j];
     for (int i = j + 1; i < k; ++i) {
-      double sm = 0.0;
-      for (int l = j; l < i; ++l) sm = fma(C[i * KLD + l], X[l * KLD + j], sm);
-      X[i * KLD + j] = -sm / C[i * KLD + i];
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int l = j;
+      for (; l + 4 <= i; l += 4) {
+        s0 = fma(C[i * KLD + l], X[l * KLD + j], s0);
+        s1 = fma(C[i * KLD + l + 1], X[(l + 1) * KLD + j], s1);
+        s2 = fma(C[i * KLD + l + 2], X[(l + 2) * KLD + j], s2);
+        s3 = fma(C[i * KLD + l + 3], X[(l + 3) * KLD + j], s3);
+      }
+      for (; l < i; ++l) s0 = fma(C[i * KLD + l], X[l * KLD + j], s0);
+      X[i * KLD + j] = -((s0 + s1) + (s2 + s3)) / C[i * KLD + i];
     }
   }
   __syncthreads();
@@ -1526,8 +1546,8 @@ __global__ __launch_bounds__(1024) void k_pc_panel(int N, const double* __restri
     for (int q = 0; q < PC_Q; ++q) {
       const int i = tid + q * nth;
       if (i >= N) continue;
-      double v = S[(long)p * N + i];   // S is symmetric: row p read coalesced
-      for (int u = 0; u < t; ++u) v -= Lp[(long)u * N + i] * lp[u];
+      // S is symmetric: row p read coalesced
+      const double v = S[(long)p * N + i] - col_combo(Lp, N, i, lp, 1, t);
       // rows already eliminated (zero Schur diagonal) have a zero Schur row
       const double li = (i == p) ? l : (dl[q] > 0.0 ? v / l : 0.0);
       Lp[(long)t * N + i] = li;
