@@ -1333,7 +1333,10 @@ __global__ __launch_bounds__(256) void k_bcr_tile(const BcrOpDesc* __restrict__ 
   constexpr int XPT = KR * CB / 256;      // staged input values per thread
   constexpr int NCT = CB / 16;
   constexpr int NBUF = DB ? 2 : 1;
+  // the column a thread stages repeats with period CB / gcd(256, CB) in q
+  constexpr int PER = CB / (CB % 256 == 0 ? 256 : (CB & -CB) < 256 ? (CB & -CB) : 256);
   static_assert(KR * CB % 256 == 0, "tile must split evenly over the workgroup");
+  static_assert(CB % 16 == 0 && (256 * PER) % CB == 0, "column period");
   __shared__ double xs[NBUF][KR][CB + 1];
   const BcrOpDesc& d = ops[op0 + blockIdx.x];
   const int j0 = blockIdx.y * CB;
@@ -1346,9 +1349,9 @@ __global__ __launch_bounds__(256) void k_bcr_tile(const BcrOpDesc* __restrict__ 
   const int ctot = ncomp * ncols;
   const int rtc = min(rt, (bo - 1) / 16);   // idle waves read a valid tile
   // the combined columns this thread stages: component offset and column
-  int xcomp[XPT], xcol[XPT];
+  int xcomp[PER], xcol[PER];
 #pragma unroll
-  for (int q = 0; q < XPT; ++q) {
+  for (int q = 0; q < PER; ++q) {
     const int j = j0 + (tid + 256 * q) % CB;
     xcomp[q] = j < ctot ? j / ncols : -1;
     xcol[q] = j < ctot ? j - xcomp[q] * ncols : 0;
@@ -1374,8 +1377,8 @@ __global__ __launch_bounds__(256) void k_bcr_tile(const BcrOpDesc* __restrict__ 
     const long lds = from_x ? ldx : ldb;
 #pragma unroll
     for (int q = 0; q < XPT; ++q) {
-      const int k = (tid + 256 * q) / CB;
-      xr[q] = (k < bi && xcomp[q] >= 0) ? src[((long)xcomp[q] * comp_rows + i0 + k) * lds + xcol[q]] : 0.0;
+      const int k = (tid + 256 * q) / CB, qc = q % PER;
+      xr[q] = (k < bi && xcomp[qc] >= 0) ? src[((long)xcomp[qc] * comp_rows + i0 + k) * lds + xcol[qc]] : 0.0;
     }
   };
   if (nterm > 0) {
@@ -1967,7 +1970,8 @@ const BcrVariant kBcrVariants[] = {
     {32, BCR_MAXBS, k_bcr_stream<32, 16>},    {16, 128, k_bcr_tile<16, 32, true>},
     {32, 128, k_bcr_tile<32, 32, true>},      {16, 128, k_bcr_tile<16, 32, false>},
     {32, 128, k_bcr_tile<32, 32, false>},     {16, 64, k_bcr_tile<16, 16, true>},
-    {32, 64, k_bcr_tile<32, 16, true>}};
+    {32, 64, k_bcr_tile<32, 16, true>},       {48, 128, k_bcr_tile<48, 32, true>},
+    {48, 128, k_bcr_tile<48, 32, false>},     {80, 128, k_bcr_tile<80, 32, false>}};
 constexpr int kNumBcrVariants = sizeof(kBcrVariants) / sizeof(kBcrVariants[0]);
 std::mutex g_bcr_mu;
 std::map<std::tuple<const double*, int, int>, std::vector<int>> g_bcr_choice;   // (factor, ncols, ncomp) -> variant per pass
