@@ -105,13 +105,13 @@ void lsc_middle_values(const HostProblem& hp, const double* Svals, double* out);
 // right-hand sides b in place from their odd neighbours' b; then the top
 // solve and the backward passes (top level down) write the solution x of the
 // odd positions from their own b and their neighbours' x.  The reduction stops
-// at 8 blocks or fewer; their system is solved with a dense inverse (one op
+// at 16 blocks or fewer; their system is solved with a dense inverse (one op
 // per block, one term per block of the top system).
 struct BcrFactor {
   int n = 0, nblk = 0, maxbs = 0;
   std::vector<int> start;              // nblk + 1
   std::vector<int> op_out, op_self;    // per op: output block, 1 = add v_out
-  static constexpr int NT = 8;          // terms per op (at most)
+  static constexpr int NT = 16;         // terms per op (at most)
   std::vector<int> op_nterm;           // per op: number of terms
   std::vector<int> op_in;              // NT per op
   std::vector<int64_t> op_off;         // NT per op: matrix offsets in data

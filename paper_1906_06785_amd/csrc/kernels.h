@@ -207,7 +207,7 @@ void sg_convection_full(hipStream_t s, int nt, int nxi, int n_u, int ns, int nal
 // [in_r0[t], in_r0[t] + in_bi[t]) of X if bit t of in_x, else of B), with
 // the bo x in_bi[t] block M_t at data + off[t] in matrix-core fragment order
 // (bcr_fragment_order); the output goes to X if flags & 2, else to B.
-constexpr int BCR_NT = 8;
+constexpr int BCR_NT = 16;
 constexpr int BCR_DATA_PAD = 64 * 64;   // doubles of padding behind the block data
 // Element (i, k) of a rows x cols block in fragment order: row tile i / 16,
 // k-step k / 4, lane (i % 16) + 16 (k % 4), at ((i/16) nq + k/4) 64 + lane

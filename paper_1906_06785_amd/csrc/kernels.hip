@@ -1319,6 +1319,34 @@ __global__ __launch_bounds__(256) void k_bcr_stream(const BcrOpDesc* __restrict_
     }
 }
 
+// A term's matrix-core fragments: k-step q of the wave's row tile is 64
+// contiguous doubles (fragment order); k-steps past the block's end read the
+// padding behind the data array or the next block (in bounds, never
+// multiplied).  Inlined by force, with the arrays by reference, so that they
+// stay in registers.
+template <int KM>
+__device__ __forceinline__ void bcr_load_frag(const double* __restrict__ M, double (&m)[KM]) {
+#pragma unroll
+  for (int q = 0; q < KM; ++q) m[q] = M[q * 64];
+}
+
+// A term's input tile (rows of its block x CB combined columns) into
+// registers, XPT values per thread, from X or B per the op's bits.
+template <int CB, int XPT, int PER>
+__device__ __forceinline__ void bcr_load_tile(const BcrOpDesc& d, int t, const double* B, long ldb, const double* X,
+                                              long ldx, long comp_rows, int tid, const int (&xcomp)[PER],
+                                              const int (&xcol)[PER], double (&xr)[XPT]) {
+  const int i0 = d.in_r0[t], bi = d.in_bi[t];
+  const bool from_x = (d.in_x >> t) & 1;
+  const double* src = from_x ? X : B;
+  const long lds = from_x ? ldx : ldb;
+#pragma unroll
+  for (int q = 0; q < XPT; ++q) {
+    const int k = (tid + 256 * q) / CB, qc = q % PER;
+    xr[q] = (k < bi && xcomp[qc] >= 0) ? src[((long)xcomp[qc] * comp_rows + i0 + k) * lds + xcol[qc]] : 0.0;
+  }
+}
+
 // Latency variant for blocks of at most 4*KM rows: a term's whole M fragment
 // (KM k-steps) and its input tile are loaded in one round trip.  With DB the
 // next term's loads are in flight while the current term runs on the matrix
@@ -1362,28 +1390,9 @@ __global__ __launch_bounds__(256) void k_bcr_tile(const BcrOpDesc* __restrict__ 
   const int nterm = d.nterm;
   double mf[KM], xr[XPT];
   double mn[DB ? KM : 1];
-  // fragment order: k-step q of row tile rtc is 64 contiguous doubles;
-  // k-steps past the block's end read the padding behind the data array or
-  // the next block (in bounds, never multiplied)
-  auto load_m = [&](int t, double* m) {
-    const double* M = data + d.off[t] + (long)rtc * ((d.in_bi[t] + 3) / 4) * 64 + lane;
-#pragma unroll
-    for (int q = 0; q < KM; ++q) m[q] = M[q * 64];
-  };
-  auto load_x = [&](int t) {
-    const int i0 = d.in_r0[t], bi = d.in_bi[t];
-    const bool from_x = (d.in_x >> t) & 1;
-    const double* src = from_x ? X : B;
-    const long lds = from_x ? ldx : ldb;
-#pragma unroll
-    for (int q = 0; q < XPT; ++q) {
-      const int k = (tid + 256 * q) / CB, qc = q % PER;
-      xr[q] = (k < bi && xcomp[qc] >= 0) ? src[((long)xcomp[qc] * comp_rows + i0 + k) * lds + xcol[qc]] : 0.0;
-    }
-  };
   if (nterm > 0) {
-    load_m(0, mf);
-    load_x(0);
+    bcr_load_frag<KM>(data + d.off[0] + (long)rtc * ((d.in_bi[0] + 3) / 4) * 64 + lane, mf);
+    bcr_load_tile<CB, XPT, PER>(d, 0, B, ldb, X, ldx, comp_rows, tid, xcomp, xcol, xr);
   }
   dbl4 acc[NCT];
 #pragma unroll
@@ -1412,8 +1421,8 @@ __global__ __launch_bounds__(256) void k_bcr_tile(const BcrOpDesc* __restrict__ 
     const int bi4 = (d.in_bi[t] + 3) & ~3;
     const double coef = d.coef[t];
     if (DB && t + 1 < nterm) {
-      load_m(t + 1, mn);
-      load_x(t + 1);
+      bcr_load_frag<DB ? KM : 1>(data + d.off[t + 1] + (long)rtc * ((d.in_bi[t + 1] + 3) / 4) * 64 + lane, mn);
+      bcr_load_tile<CB, XPT, PER>(d, t + 1, B, ldb, X, ldx, comp_rows, tid, xcomp, xcol, xr);
     }
     if (active) {
 #pragma unroll
@@ -1429,8 +1438,8 @@ __global__ __launch_bounds__(256) void k_bcr_tile(const BcrOpDesc* __restrict__ 
 #pragma unroll
       for (int q = 0; q < KM; ++q) mf[q] = mn[DB ? q : 0];
     } else if (t + 1 < nterm) {
-      load_m(t + 1, mf);
-      load_x(t + 1);
+      bcr_load_frag<KM>(data + d.off[t + 1] + (long)rtc * ((d.in_bi[t + 1] + 3) / 4) * 64 + lane, mf);
+      bcr_load_tile<CB, XPT, PER>(d, t + 1, B, ldb, X, ldx, comp_rows, tid, xcomp, xcol, xr);
     }
   }
   if (!active) return;
