@@ -56,6 +56,10 @@ def parse(argv=None):
                     help="N > 0: instead, time N independent problems (batch_configs) on --contexts streams")
     ap.add_argument("--contexts", type=int, default=8)
     ap.add_argument("--batch-small", action="store_true", help="coarse grids / short horizons for the batch")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="M > 0: before the timed solves, one device-to-device copy of M MiB (a plain copy kernel "
+                         "of known size for scaling memory counters)")
+    ap.add_argument("--progress", action="store_true", help="one line on stderr per solve")
     return ap.parse_args(argv)
 
 
@@ -65,6 +69,30 @@ def solve_options(args=None):
         args = parse([])
     return dict(restart=args.restart, outer_explicit=args.outer_explicit, verbose=args.verbose, relax=args.relax,
                 precision=args.precision, inner_mode=args.inner_mode, inner_rhs_eps=args.inner_rhs_eps)
+
+
+# HBM traffic of the dominant kernel, measured with rocprofv3 counters
+# (FETCH_SIZE and WRITE_SIZE runs, scaled by the same counters on a device copy
+# of known size): bytes per launch, valid while the kernel source it was
+# measured on is unchanged (digest of the block cyclic reduction section of
+# kernels.hip).  None until measured.
+TRAFFIC_RECORD = None
+
+
+def bcr_source_digest():
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1906_06785_amd", "csrc", "kernels.hip")).read()
+    head = "// " + "-" * 66 + " block cyclic reduction"
+    i0 = src.index(head)
+    i1 = src.index("// " + "-" * 66, i0 + len(head))
+    return hashlib.sha256(src[i0:i1].encode()).hexdigest()
+
+
+def recorded_traffic(dom_name):
+    rec = TRAFFIC_RECORD
+    if dom_name != "k_bcr" or not rec or rec.get("kernel_src_sha256") != bcr_source_digest():
+        return None
+    return rec["bytes_per_launch"]
 
 
 # kernel classes of the profiler -> the kernels they stand for
@@ -163,17 +191,33 @@ def main():
     setup_s = time.perf_counter() - t_setup
     opts = solve_options(args)
     out = S.pair(*OUT_CAPS)
+    def progress(what):
+        if args.progress:
+            print(f"[bench] {what} done at {time.perf_counter() - t_setup:.1f} s", file=sys.stderr, flush=True)
+
     for _ in range(args.warmup):
         S.solve(b, out, **opts)
+        progress("warm-up solve")
     torch.cuda.synchronize()
     # breakdown solve (outside the timed region): every kernel class and
     # phase, and the dominant class by event time
     ctx.profile(True)
     S.solve(b, out, **opts)
+    progress("breakdown solve")
     breakdown = ctx.profile_read()
     phases = ctx.profile_regions()
     ctx.profile(False)
     dom_name = max(breakdown.items(), key=lambda kv: kv[1]["seconds"])[0]
+    if args.copy_calibration_mb > 0:
+        # a plain copy of known size just before the timed region (also marks
+        # where the timed solves begin in a kernel trace)
+        n = args.copy_calibration_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     # timed region: events on the dominant class only
     ctx.profile(True, classes=[dom_name])
     torch.cuda.synchronize()
@@ -185,6 +229,7 @@ def main():
     for _ in range(args.steps):
         _, st, rc = S.solve(b, out, **opts)
         stats.append(st)
+        progress("timed solve")
     ev1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -204,7 +249,9 @@ def main():
                 "frac": ach / PEAK_FP64_TFLOPS}
     roof.update({"kernel": KERNEL_LABELS.get(dom_name, dom_name), "launches": nl,
                  "avg_launch_us": sec / max(nl, 1) * 1e6,
-                 "share_of_timed_region": sec / ev_s if ev_s > 0 else None, "traffic": None})
+                 "algorithmic_bytes_per_launch": by / max(nl, 1), "algorithmic_flops_per_launch": fl / max(nl, 1),
+                 "share_of_timed_region": sec / ev_s if ev_s > 0 else None,
+                 "traffic": recorded_traffic(dom_name)})
     outer = int(round(sum(s["outer_iters"] for s in stats) / len(stats)))
     worst = max(s["rel_residual"] for s in stats)
     res = {

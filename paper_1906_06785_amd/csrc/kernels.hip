@@ -1237,11 +1237,12 @@ static_assert(sizeof(BcrOpDesc) % 8 == 0, "descriptor layout");
 // Streaming variant, any block up to BCR_MAXBS rows: the M fragments of the
 // next PF k-steps are in flight while the current ones are multiplied.
 template <int CB, int PF>
-__global__ __launch_bounds__(256) void k_bcr_stream(const BcrOpDesc* __restrict__ ops, int op0,
+__global__ __launch_bounds__(256) void k_bcr_stream(const BcrOpDesc* __restrict__ ops, int op0, int nops,
                                                     const double* __restrict__ data, double* __restrict__ B, long ldb,
                                                     double* __restrict__ X, long ldx, int ncols, int ncomp,
                                                     long comp_rows) {
   __shared__ double xs[BCR_MAXBS + 4][CB + 1];
+  if ((int)blockIdx.x >= nops) return;   // grid padding (uniform per workgroup)
   const BcrOpDesc& d = ops[op0 + blockIdx.x];
   const int j0 = blockIdx.y * CB;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
@@ -1353,7 +1354,7 @@ __device__ __forceinline__ void bcr_load_tile(const BcrOpDesc& d, int t, const d
 // cores (input tiles double-buffered in LDS, twice the registers); without,
 // the registers are halved for occupancy on passes with many ops.
 template <int CB, int KM, bool DB>
-__global__ __launch_bounds__(256) void k_bcr_tile(const BcrOpDesc* __restrict__ ops, int op0,
+__global__ __launch_bounds__(256) void k_bcr_tile(const BcrOpDesc* __restrict__ ops, int op0, int nops,
                                                   const double* __restrict__ data, double* __restrict__ B, long ldb,
                                                   double* __restrict__ X, long ldx, int ncols, int ncomp,
                                                   long comp_rows) {
@@ -1366,6 +1367,7 @@ __global__ __launch_bounds__(256) void k_bcr_tile(const BcrOpDesc* __restrict__ 
   static_assert(KR * CB % 256 == 0, "tile must split evenly over the workgroup");
   static_assert(CB % 16 == 0 && (256 * PER) % CB == 0, "column period");
   __shared__ double xs[NBUF][KR][CB + 1];
+  if ((int)blockIdx.x >= nops) return;   // grid padding (uniform per workgroup)
   const BcrOpDesc& d = ops[op0 + blockIdx.x];
   const int j0 = blockIdx.y * CB;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
@@ -1999,8 +2001,12 @@ void bcr_run(hipStream_t s, const BcrDev& f, const int* vars, int ncomp, double*
     if (no <= 0) continue;
     const BcrVariant& v = kBcrVariants[vars[p]];
     ps.add(8.0 * (f.pass_data[p] + f.pass_rows[p] * cols), 2.0 * f.pass_mk[p] * cols, 1);
-    hipLaunchKernelGGL(v.fn, dim3(no, cdiv((long)ncomp * ncols, v.cb), cdiv(f.maxbs, 64)), dim3(256), 0, s, f.ops, o0,
-                       f.data, B, ldb, X, ldx, ncols, ncomp, (long)f.n);
+    // workgroup ids are dealt round-robin over the 8 XCDs; with the op index
+    // padded to a multiple of 8, every column chunk and row group of an op
+    // runs on the same XCD and shares its blocks through that XCD's L2
+    const unsigned gx = 8 * cdiv(no, 8);
+    hipLaunchKernelGGL(v.fn, dim3(gx, cdiv((long)ncomp * ncols, v.cb), cdiv(f.maxbs, 64)), dim3(256), 0, s, f.ops, o0,
+                       no, f.data, B, ldb, X, ldx, ncols, ncomp, (long)f.n);
   }
   if (ev) (void)hipEventRecord(ev[f.npass], s);
 }
