@@ -43,7 +43,8 @@ def parse(argv=None):
     ap.add_argument("--restart", type=int, default=20)
     ap.add_argument("--relax", type=int, default=1,
                     help="1: relaxed truncation of late Krylov vectors (inexact Krylov); 0: fixed eps of Alg. 4.2")
-    ap.add_argument("--cpu-seconds", type=float, default=25.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="CPU baseline budget: the oracle stops after the first outer iteration that ends past it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", type=int, default=0)
     ap.add_argument("--precision", type=int, default=0, help="inner-solve products: 0 FP64, 1 FP32, 2 BF16")
