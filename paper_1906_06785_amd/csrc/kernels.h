@@ -142,10 +142,12 @@ void core2_block(hipStream_t s, int r1, int n2, int r2, const double* in, const 
 //    without large_ok the pivoted Cholesky subspace (orthonormalized) is the
 //    truncation, up to 512 columns, written to U (N x k, ld kmax) with *k_out
 //    and the kept trace *kept_out.  A zero matrix gives k = 1, U = e_1.
-//    Otherwise *kp_out = kp > 0 pivots and state[0..3] = {trace, delta^2,
-//    zero threshold, residual trace} for the next stage; *kp_out = 0 when
-//    the stage finished the truncation (or *info = 2).  L: scratch N x kmax
-//    (+ N).
+//    Otherwise *kp_out = kp > 0 pivots for the next stage; *kp_out = 0 when
+//    the stage finished the truncation (or *info = 2).  Always state[0..3] =
+//    {residual trace, delta^2, zero threshold, trace} (the layout pc_panel
+//    uses) and piv_out[j] = the j-th pivot (j < 96), so that after *info = 2
+//    the blocked path can resume from the 96 pivots in L and the remaining
+//    Schur diagonal in the N doubles after L.  L: scratch N x kmax (+ N).
 //    In mode 0 the columns kp .. km-1 of L are zeroed (km = min(96, kmax)).
 //  The later stages read kp (and k) from device memory and do nothing when
 //  the first stage finished, so the whole chain is queued without a host
@@ -163,7 +165,7 @@ void core2_block(hipStream_t s, int r1, int n2, int r2, const double* in, const 
 constexpr int TRUNC_KSMALL = 96;
 void trunc_pc(hipStream_t s, int N, double* S, double eps, const double* normsq_in, double* normsq_out, double* U,
               int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound, int large_ok,
-              int* kp_out, double* state);
+              int* kp_out, double* state, int* piv_out);
 void trunc_jacobi(hipStream_t s, int km, const int* kp_dev, const double* T, const double* state, double* W,
                   int* k_out, double* kept_out);
 void chol_inv_upper(hipStream_t s, int km, const int* kp_dev, const int* k_dev, const double* G, double* R,

@@ -773,7 +773,7 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_pc(int N, double* __restri
                                                          double* __restrict__ U, int kmax, double* __restrict__ L,
                                                          double* __restrict__ dwork, int* k_out, double* kept_out,
                                                          int* info, int rank_bound, int large_ok, int* kp_out,
-                                                         double* state) {
+                                                         double* state, int* piv_out) {
   __shared__ double shv[32];
   __shared__ int shi[32];
   __shared__ double shs[32];
@@ -823,6 +823,7 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_pc(int N, double* __restri
     }
     if (bv <= zero_thr || bv <= 0.0) break;
     const int p = bi;
+    if (tid == 0 && j < KSMALL) piv_out[j] = p;
     for (int t = tid; t < j; t += nth) lp[t] = L[(long)t * N + p];
     __syncthreads();
     const double ljj = sqrt(bv);
@@ -843,7 +844,15 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_pc(int N, double* __restri
     kp = j + 1;
   }
   __syncthreads();
-  if (tid == 0) *kp_out = 0;
+  if (tid == 0) {
+    *kp_out = 0;
+    // residual trace, target, zero threshold, trace: the layout of the
+    // blocked path's state, which resumes from these pivots
+    state[0] = resid;
+    state[1] = delta2;
+    state[2] = zero_thr;
+    state[3] = tr;
+  }
   if (mode == 1 && large_ok) {
     if (tid == 0) *info = 2;
     return;
@@ -874,13 +883,7 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_pc(int N, double* __restri
     // products of the next stages
     const int km = min(KSMALL, kmax);
     for (long e = tid; e < (long)N * (km - kp); e += nth) L[(long)kp * N + e] = 0.0;
-    if (tid == 0) {
-      *kp_out = kp;
-      state[0] = tr;
-      state[1] = delta2;
-      state[2] = zero_thr;
-      state[3] = resid;
-    }
+    if (tid == 0) *kp_out = kp;
     return;
   }
   const int k = shi[0];
@@ -909,7 +912,7 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_jacobi(int km, const int* 
   const int tid = threadIdx.x, nth = blockDim.x;
   const int n = *kp_dev;
   if (n <= 0) return;   // the first stage finished the truncation
-  const double delta2 = state[1], zero_thr = state[2], resid = state[3];
+  const double resid = state[0], delta2 = state[1], zero_thr = state[2];
   for (int e = tid; e < n * n; e += nth) {
     const int a = e / n, b = e - a * n;
     T[a * KLD + b] = 0.5 * (Tg[a * KSMALL + b] + Tg[b * KSMALL + a]);
@@ -1891,13 +1894,13 @@ void core2_block(hipStream_t s, int r1, int n2, int r2, const double* in, const 
 
 void trunc_pc(hipStream_t s, int N, double* S, double eps, const double* normsq_in, double* normsq_out, double* U,
               int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound, int large_ok,
-              int* kp_out, double* state) {
+              int* kp_out, double* state, int* piv_out) {
   static_assert(TRUNC_KSMALL == KSMALL, "truncation stage sizes");
   // dwork: N doubles placed after L (caller sizes L as N*kmax + N)
   double* dwork = L + (long)N * kmax;
   ProfScope ps(KC_TRUNC, s, 8.0 * (double)N * N, 0.0);
   hipLaunchKernelGGL(k_trunc_pc, dim3(1), dim3(TE_THREADS), 0, s, N, S, eps, normsq_in, normsq_out, U, kmax, L, dwork,
-                     k_out, kept_out, info, rank_bound, large_ok, kp_out, state);
+                     k_out, kept_out, info, rank_bound, large_ok, kp_out, state, piv_out);
 }
 
 void trunc_jacobi(hipStream_t s, int km, const int* kp_dev, const double* T, const double* state, double* W,

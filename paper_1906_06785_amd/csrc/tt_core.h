@@ -71,6 +71,7 @@ struct Ctx {
   double* ws2 = nullptr;
   size_t ws2_n = 0;
   int* dint = nullptr;         // small device int scratch (64)
+  int* dpiv = nullptr;         // pivots of the last truncation's first stage (96)
   double* dscal = nullptr;     // small device double scratch (256)
   int* hint = nullptr;         // pinned host mirror (64)
   double* hdbl = nullptr;      // pinned host mirror (256)

@@ -196,8 +196,13 @@ struct Skeleton {
   }
 };
 
+// Blocked pivoted Cholesky with a skeleton factor.  With k0 > 0 it resumes
+// from the first stage of trunc_sym: k0 pivots in L0 (column-major, ld N),
+// their indices in c.dpiv, the remaining Schur diagonal d0 and the stage
+// state (residual trace, target, zero threshold, trace) at c.dscal + 240.
 static Skeleton trunc_skeleton(Ctx& c, int N, double* S, double eps, const double* dnorm_in, double* d_kept,
-                               int kcap, int rank_bound, const char* what) {
+                               int kcap, int rank_bound, const char* what, const double* L0 = nullptr,
+                               const double* d0 = nullptr, int k0 = 0) {
   GemmPrecisionScope f64(GP_F64);
   double* L = c.pool.get((size_t)N * kcap);
   double* d = c.pool.get((size_t)N + 8);
@@ -206,8 +211,18 @@ static Skeleton trunc_skeleton(Ctx& c, int N, double* S, double eps, const doubl
   sk.pivbuf = c.pool.get((size_t)kcap / 2 + 1);
   int* piv = (int*)sk.pivbuf;
   int* out = c.dint + 16;
-  pc_init(c.s, N, S, eps, dnorm_in, nullptr, d, state);
   int k = 0;
+  if (k0 > 0 && k0 <= kcap) {
+    copy2d(c.s, k0, N, L0, N, L, N, 1.0, nullptr, 0);
+    copy2d(c.s, 1, N, d0, N, d, N, 1.0, nullptr, 0);
+    copy2d(c.s, 1, 4, c.dscal + 240, 4, state, 4, 1.0, nullptr, 0);
+    SGTT_HIP(hipMemcpyAsync(piv, c.dpiv, sizeof(int) * k0, hipMemcpyDeviceToDevice, c.s));
+    // Schur complement after those pivots
+    gemm(c.s, 1, N, N, k0, -1.0, L, 0, 1, N, L, 0, N, 1, 1.0, S, 0, N, 1);
+    k = k0;
+  } else {
+    pc_init(c.s, N, S, eps, dnorm_in, nullptr, d, state);
+  }
   for (;;) {
     const int ns = std::min(64, kcap - k);
     if (ns <= 0) {
@@ -255,8 +270,9 @@ void trunc_sym(Ctx& c, int N, double* S, double eps, const double* normsq_in, do
   const int km = std::min(KS, kmax);
   int* kp_dev = c.dint + 32;
   double* state = c.dscal + 240;
+  if (!c.dpiv) c.dpiv = (int*)c.pool.get(KS / 2);
   trunc_pc(c.s, N, S, eps, normsq_in, normsq_out, U, kmax, Lw, k_out, kept_out, info, rank_bound, large_ok, kp_dev,
-           state);
+           state, c.dpiv);
   double* small = c.pool.get((size_t)4 * KS * KS);
   double *T = small, *W = small + KS * KS, *G = small + 2 * KS * KS, *R = small + 3 * KS * KS;
   double* U0 = c.pool.get((size_t)N * km);
@@ -406,20 +422,18 @@ TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_no
   gemm(c.s, 1, N2, N2, R2, 1.0, T2, 0, R2, 1, Cm, 0, 1, R2, 0.0, S2, 0, N2, 1);
   const int kmax2 = std::min({N2, R2, maxrank, RANK_CAP});
   double* U2 = c.pool.get((size_t)N2 * kmax2);
-  {
-    double* Lw = c.scratch2((size_t)N2 * kmax2 + N2 + 64);
-    trunc_sym(c, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw, dk + 2, dkept2, dk + 3, std::min(N2, R2), 1);
-    SGTT_HIP(hipMemcpyAsync(c.hint, dk + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, c.s));
-    c.sync();
-    h[2] = c.hint[0];
-    h[3] = c.hint[1];
-  }
+  double* Lw = c.scratch2((size_t)N2 * kmax2 + N2 + 64);   // first-stage pivots, kept for the blocked path
+  trunc_sym(c, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw, dk + 2, dkept2, dk + 3, std::min(N2, R2), 1);
+  SGTT_HIP(hipMemcpyAsync(c.hint, dk + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  h[2] = c.hint[0];
+  h[3] = c.hint[1];
   if (h[3] == 3) throw SgttError(-1, "TT truncation: orthonormalization failed (bond 2)");
   if (h[3] == 1) throw SgttError(-4, "TT rank capacity exceeded (bond 2)");
   Skeleton sk;
   if (h[3] == 2)
     sk = trunc_skeleton(c, N2, S2, eps, dnorm, dkept2, std::min({N2, R2, maxrank, RANK_CAP_LARGE}),
-                        std::min(N2, R2), "bond 2");
+                        std::min(N2, R2), "bond 2", Lw, Lw + (size_t)N2 * kmax2, TRUNC_KSMALL);
   const int k2 = h[3] == 2 ? sk.k : h[2];
   gemm_precision(amb);
   // ---- W (k2 x R2) = U2^T C, or the skeleton rows C[P, :]; new G3 = sum_j C_j W_j^T
@@ -480,7 +494,7 @@ TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, dou
   Skeleton sk;
   if (h[3] == 2)
     sk = trunc_skeleton(c, N2, S2, eps, dnorm, dkept, std::min({N2, n3, maxrank, RANK_CAP_LARGE}), std::min(N2, n3),
-                        "full bond 2");
+                        "full bond 2", Lw2, Lw2 + (size_t)N2 * kmax2, TRUNC_KSMALL);
   const int k2 = h[3] == 2 ? sk.k : h[2];
   TT t = tt_new(c, n1, n2, n3, k1, k2);
   copy2d(c.s, n1, k1, U1, kmax1, t.c1, k1, 1.0, nullptr, 0);
