@@ -556,8 +556,13 @@ __global__ __launch_bounds__(256) void k_ell_spmm(int nrows, int ics, int ocs,
   const long r = (long)lb * (blockDim.x / WAVE) + wave;
   const int c = blockIdx.y;
   if (r >= nrows) return;
+  static_assert(EW == 32, "entry groups of 16, 9 and 7");
   const int my_col = lane < EW ? ecol[r * EW + lane] : 0;
   const double my_val = lane < EW ? eval[r * EW + lane] : 0.0;
+  // entries past the row's last one are padding (column r, value 0); the
+  // row length decides, uniformly per wave, how many entry groups load
+  const unsigned long long real = __ballot(lane < EW && !(my_col == (int)r && my_val == 0.0));
+  const int n = real ? 64 - __clzll(real) : 0;
   const double* xb = x + (long)c * ics * ldx + xcol0;
   double* yb = y + ((long)c * ocs + r) * ldy + ycol0;
   for (int j0 = 0; j0 < ncols; j0 += WAVE) {
@@ -565,14 +570,30 @@ __global__ __launch_bounds__(256) void k_ell_spmm(int nrows, int ics, int ocs,
     const bool act = j < ncols;
     const int jc = act ? j : ncols - 1;   // idle lanes read a valid column
     const double yo = (act && beta != 0.0) ? yb[j] : 0.0;
-    double xv[EW];
-    // padded entries (q >= n) point at row r with value 0: every load is
-    // valid, so none is predicated and all are issued back to back
-#pragma unroll
-    for (int q = 0; q < EW; ++q) xv[q] = xb[(long)__builtin_amdgcn_readlane(my_col, q) * ldx + jc];
+    // within a group every load is valid (padding points at row r), so none
+    // is predicated and the group's loads are issued back to back
     double acc = 0.0;
+    {
+      double xv[16];
 #pragma unroll
-    for (int q = 0; q < EW; ++q) acc = fma(readlane_f64(my_val, q), xv[q], acc);
+      for (int q = 0; q < 16; ++q) xv[q] = xb[(long)__builtin_amdgcn_readlane(my_col, q) * ldx + jc];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc = fma(readlane_f64(my_val, q), xv[q], acc);
+    }
+    if (n > 16) {
+      double xv[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) xv[q] = xb[(long)__builtin_amdgcn_readlane(my_col, 16 + q) * ldx + jc];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) acc = fma(readlane_f64(my_val, 16 + q), xv[q], acc);
+    }
+    if (n > 25) {
+      double xv[7];
+#pragma unroll
+      for (int q = 0; q < 7; ++q) xv[q] = xb[(long)__builtin_amdgcn_readlane(my_col, 25 + q) * ldx + jc];
+#pragma unroll
+      for (int q = 0; q < 7; ++q) acc = fma(readlane_f64(my_val, 25 + q), xv[q], acc);
+    }
     if (act) yb[j] = alpha * acc + beta * yo;
   }
 }
