@@ -18,6 +18,7 @@ enum KernelClass {
 const char* kernel_class_name(int cls);
 void prof_enable(bool on);
 void prof_enable_mask(unsigned class_mask);   // bit c records class c; 0 = off
+unsigned prof_mask();                          // classes recorded now (0 when off)
 bool prof_enabled();
 // sums since the last reset: seconds (from events), bytes, flops, launches
 void prof_read(double* seconds, double* bytes, double* flops, long* launches);

@@ -129,6 +129,7 @@ int gemm_precision(int p) {
   return old;
 }
 bool prof_enabled() { return g_prof.on; }
+unsigned prof_mask() { return g_prof.on ? g_prof.mask : 0u; }
 void prof_reset() {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof.recs.clear();
@@ -2088,17 +2089,21 @@ void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, d
   if (f.maxbs > BCR_MAXBS) throw std::runtime_error("block cyclic reduction: block larger than 256");
   std::vector<int> vars;
   {
-    const auto key = std::make_tuple((const double*)f.data, ncols, ncomp);
+    // column counts share a choice per power-of-two bucket (ranks vary from
+    // call to call; the variants' ranking follows the column count slowly)
+    int bucket = 16;
+    while (bucket < ncols) bucket *= 2;
+    const auto key = std::make_tuple((const double*)f.data, bucket, ncomp);
     std::unique_lock<std::mutex> lk(g_bcr_mu);
     auto it = g_bcr_choice.find(key);
     if (it != g_bcr_choice.end()) {
       vars = it->second;
     } else {
       lk.unlock();
-      const bool was = prof_enabled();
-      prof_enable(false);
+      const unsigned was = prof_mask();   // tuning runs are not profiled
+      prof_enable_mask(0u);
       vars = bcr_tune(s, f, ncomp, B, ldb, ncols);
-      prof_enable(was);
+      prof_enable_mask(was);
       lk.lock();
       g_bcr_choice[key] = vars;
     }
