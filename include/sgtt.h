@@ -358,6 +358,16 @@ int sgtt_host_gpc(const sgtt_host_problem* hp, int which, double* out);
 /* Dirichlet lift g over all velocity nodes (2 n_all) and node coordinates
  * (n_all x 2), free node list (n_s) */
 int sgtt_host_mesh(const sgtt_host_problem* hp, double* coords, int* free_nodes, double* g_all);
+/* Host check of the block cyclic reduction that the spatial solves run on the
+ * device (the F_avg solve of eq. 5.23 and the X solve of eq. 5.19): factor
+ * which = 0: F = M / tau + nu A on the velocity slabs (n_s rows), or
+ * which = 1: X = B M*^-1 B^T on the pressure slabs (n_p rows), and apply its
+ * op lists on the host to ncols right-hand sides b (row-major, n x ncols),
+ * x = A^-1 b (same layout).  *npass gets the number of passes.  Host memory
+ * only; the caller owns b and x.  SGTT_E_INVALID on bad arguments, -6 on a
+ * singular block. */
+int sgtt_host_bcr_solve(const sgtt_host_problem* hp, int which, double tau, double nu, int ncols, const double* b,
+                        double* x, int* npass);
 
 #ifdef __cplusplus
 }

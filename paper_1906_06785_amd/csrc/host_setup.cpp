@@ -854,4 +854,33 @@ void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& bloc
 }
 
 
+void bcr_apply_host(const BcrFactor& f, int ncols, const double* b, double* x) {
+  constexpr int NT = BcrFactor::NT;
+  const size_t nv = (size_t)f.n * ncols;
+  std::vector<double> B(b, b + nv), X(nv, 0.0);
+  for (size_t p = 0; p + 1 < f.pass_begin.size(); ++p) {
+    const int mode = f.pass_mode[p];
+    std::vector<double>& out = mode != 0 ? X : B;
+    std::vector<double> res = out;   // ops of a pass read the state before the pass
+    parallel_for(f.pass_begin[p + 1] - f.pass_begin[p], [&](int q) {
+      const int o = f.pass_begin[p] + q, ob = f.op_out[o], r0 = f.start[ob], bo = f.start[ob + 1] - r0;
+      for (int r = 0; r < bo; ++r)
+        for (int c = 0; c < ncols; ++c) {
+          double acc = f.op_self[o] ? B[(size_t)(r0 + r) * ncols + c] : 0.0;
+          for (int t = 0; t < f.op_nterm[o]; ++t) {
+            const int ib = f.op_in[NT * o + t], i0 = f.start[ib], bi = f.start[ib + 1] - i0;
+            const std::vector<double>& src = (mode == 1 && ib != ob) ? X : B;
+            const double* m = f.data.data() + f.op_off[NT * o + t];
+            double sum = 0.0;
+            for (int k = 0; k < bi; ++k) sum += m[(size_t)k * bo + r] * src[(size_t)(i0 + k) * ncols + c];
+            acc += f.op_coef[NT * o + t] * sum;
+          }
+          res[(size_t)(r0 + r) * ncols + c] = acc;
+        }
+    });
+    out.swap(res);
+  }
+  std::copy(X.begin(), X.end(), x);
+}
+
 }  // namespace sgtt

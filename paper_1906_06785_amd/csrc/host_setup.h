@@ -125,6 +125,9 @@ struct BcrFactor {
 };
 void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& blocks, BcrFactor& f,
                 std::string& err);
+// The factor's op lists applied on the host (reference of the device
+// passes): x = A^-1 b for ncols columns, row-major (row r at r * ncols).
+void bcr_apply_host(const BcrFactor& f, int ncols, const double* b, double* x);
 
 
 

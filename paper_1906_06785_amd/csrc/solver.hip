@@ -1739,6 +1739,30 @@ int sgtt_host_csr(const sgtt_host_problem* h, int which, int* nrows, int* ncols,
   return SGTT_OK;
 }
 
+int sgtt_host_bcr_solve(const sgtt_host_problem* h, int which, double tau, double nu, int ncols, const double* b,
+                        double* x, int* npass) {
+  if (!h || !b || !x || ncols <= 0 || (which != 0 && which != 1) || (which == 0 && !(tau > 0.0)))
+    return SGTT_E_INVALID;
+  try {
+    const HostProblem& hp = h->hp;
+    BcrFactor f;
+    std::string err;
+    if (which == 0) {
+      std::vector<double> F(hp.Kff.nnz());
+      for (int t = 0; t < hp.Kff.nnz(); ++t) F[t] = hp.Mff[t] / tau + nu * hp.Aff[t];
+      bcr_factor(hp.Kff, F.data(), hp.vel_blocks, f, err);
+    } else {
+      bcr_factor(hp.Xp, hp.Xp.val.data(), hp.p_blocks, f, err);
+    }
+    if (!err.empty()) return -6;
+    bcr_apply_host(f, ncols, b, x);
+    if (npass) *npass = (int)f.pass_begin.size() - 1;
+    return SGTT_OK;
+  } catch (...) {
+    return -6;
+  }
+}
+
 int sgtt_host_gpc(const sgtt_host_problem* h, int which, double* out) {
   if (!h || !out) return SGTT_E_INVALID;
   const HostProblem& hp = h->hp;

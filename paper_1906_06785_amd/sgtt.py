@@ -150,6 +150,8 @@ _sig = {
                                 C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "sgtt_host_gpc": (C.c_int, [_P, C.c_int, C.POINTER(C.c_double)]),
     "sgtt_host_mesh": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "sgtt_host_bcr_solve": (C.c_int, [_P, C.c_int, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double), C.POINTER(C.c_int)]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -207,6 +209,23 @@ class HostProblem:
         _lib.sgtt_host_csr(self._h, which, None, None, None, rp.ctypes.data_as(C.POINTER(C.c_int)),
                            col.ctypes.data_as(C.POINTER(C.c_int)), val.ctypes.data_as(C.POINTER(C.c_double)))
         return sp.csr_matrix((val, col, rp), shape=(nr.value, nc.value))
+
+    def bcr_solve(self, which: int, b, tau: float = 0.0, nu: float = 0.0):
+        """Host application of the block cyclic reduction factor (which 0:
+        M/tau + nu A on the velocity slabs, 1: B M*^-1 B^T on the pressure
+        slabs) to the columns of b (n x ncols); returns (x, number of passes)."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        if b.ndim == 1:
+            b = b[:, None]
+        if which in (0, 1) and (b.ndim != 2 or b.shape[0] != (self.n_s if which == 0 else self.n_p)):
+            raise ValueError(f"b has shape {b.shape}; expected {self.n_s if which == 0 else self.n_p} rows")
+        x = np.zeros_like(b)
+        npass = C.c_int()
+        rc = _lib.sgtt_host_bcr_solve(self._h, which, tau, nu, b.shape[1], b.ctypes.data_as(C.POINTER(C.c_double)),
+                                      x.ctypes.data_as(C.POINTER(C.c_double)), C.byref(npass))
+        if rc != 0:
+            raise SgttError(rc, "host block cyclic reduction failed")
+        return x, npass.value
 
     def gpc(self, which: int):
         n = self.n_xi

@@ -1,0 +1,51 @@
+"""CPU checks of bench.py's host logic: the one-GPU guard and the rule that a
+recorded traffic figure is reported only for the kernel source it was
+measured on."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_exits_with_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+def test_recorded_traffic_only_for_measured_source(monkeypatch):
+    digest = bench.bcr_source_digest()
+    assert len(digest) == 64
+    rec = dict(kernel_src_sha256=digest, bytes_per_launch=123, fetch_bytes_per_launch=100,
+               write_bytes_per_launch=23, summary="x")
+    monkeypatch.setattr(bench, "TRAFFIC_RECORD", rec)
+    assert bench.recorded_traffic("k_bcr") == 123
+    assert bench.recorded_traffic("k_gemm") is None
+    monkeypatch.setattr(bench, "TRAFFIC_RECORD", dict(rec, kernel_src_sha256="0" * 64))
+    assert bench.recorded_traffic("k_bcr") is None
+    monkeypatch.setattr(bench, "TRAFFIC_RECORD", None)
+    assert bench.recorded_traffic("k_bcr") is None
+
+
+def test_recorded_summary_exists():
+    rec = bench.TRAFFIC_RECORD
+    if rec:
+        assert os.path.exists(os.path.join(ROOT, rec["summary"]))
+        assert rec["bytes_per_launch"] == rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+@pytest.mark.parametrize("argv", [[], ["--steps", "5", "--warmup", "2"]])
+def test_default_solve_options(argv):
+    a = bench.parse(argv)
+    assert a.gpus == 1 and a.config == "C2"
+    o = bench.solve_options(a)
+    assert o["inner_mode"] == 1 and o["precision"] == 0

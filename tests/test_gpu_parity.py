@@ -115,6 +115,46 @@ def test_round_sum_cancellation(sg, ctx):
     assert np.linalg.norm(Y - tt.full(G)) <= 1e-7 * np.linalg.norm(tt.full(G))
 
 
+def test_round_zero_tt(sg, ctx):
+    # the zero vector rounds to ranks (1, 1) and stays exactly zero
+    _flush("round zero")
+    G = [np.zeros_like(g) for g in random_tt_cores(10, 6, 500, 4, 6, 5)]
+    buf = sg.TTBuf(10, 6, 500, 32, 32).set_cores(*G)
+    ctx.round(buf, 1e-6)
+    assert (buf.r1, buf.r2) == (1, 1)
+    assert not np.any(ctx.expand(buf).cpu().numpy())
+
+
+def test_round_difference_cancels(sg, ctx):
+    # x - x: every direction cancels up to the rounding of the Gram matrices
+    _flush("round x - x")
+    G = random_tt_cores(10, 6, 500, 4, 6, 5)
+    buf = sg.TTBuf(10, 6, 500, 32, 32).set_cores(*tt.concat([G, G], [1.0, -1.0]))
+    ctx.round(buf, 1e-8)
+    assert buf.r1 <= 8 and buf.r2 <= 12
+    Y = ctx.expand(buf).cpu().numpy()
+    assert np.linalg.norm(Y) <= 1e-6 * np.linalg.norm(tt.full(G))
+
+
+def test_profiler_class_mask(sg, ctx, tiny):
+    # events only for the selected kernel classes; all classes otherwise
+    P, S = tiny
+    _flush("profiler class mask")
+    b = S.rhs()
+    try:
+        ctx.profile(True, classes=["k_bcr"])
+        S.solve(b, restart=10, relax=1)
+        got = ctx.profile_read()
+        assert got["k_bcr"]["launches"] > 0 and got["k_bcr"]["seconds"] > 0
+        assert all(v["launches"] == 0 and v["seconds"] == 0 for k, v in got.items() if k != "k_bcr")
+        ctx.profile(True)
+        S.solve(b, restart=10, relax=1)
+        got = ctx.profile_read()
+        assert got["k_bcr"]["launches"] > 0 and got["k_gemm"]["launches"] > 0
+    finally:
+        ctx.profile(False)
+
+
 @pytest.mark.parametrize("which", ["tiny", "c1"])
 def test_apply_matches_oracle(sg, ctx, tiny, c1, which):
     P, S = tiny if which == "tiny" else c1

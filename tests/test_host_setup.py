@@ -69,3 +69,35 @@ def test_host_setup_full_size_counts():
     sg = _lib()
     hp = sg.HostProblem(CONFIGS["C2"])
     assert (hp.n_u, hp.n_p, hp.n_xi, hp.nt) == (50368, 6641, 35, 128)
+
+
+@pytest.mark.parametrize("name", ["tiny", "C1", "C2"])
+def test_host_block_cyclic_reduction_solves_spatial_systems(name):
+    """The op lists of the block cyclic reduction (the device passes' program)
+    applied on the host solve the velocity matrix M/tau + nu A (eq. 5.23) and
+    the pressure Laplacian B M*^-1 B^T (eq. 5.19) as a sparse direct solve of
+    the oracle's own assembly does."""
+    import scipy.sparse.linalg as spl
+    sg = _lib()
+    cfg = CONFIGS[name]
+    hp = sg.HostProblem(cfg)
+    P = Problem(cfg)
+    rng = np.random.default_rng(7)
+    tau, nu = 0.1, 1.0 / 50
+    Msi = sp.diags(1.0 / P.Mstar)
+    for which, A in ((0, (P.M / tau + nu * P.A).tocsc()), (1, (P.B @ Msi @ P.Bt).tocsc())):
+        b = rng.standard_normal((A.shape[0], 5))
+        x, npass = hp.bcr_solve(which, b, tau, nu)
+        assert npass >= 1
+        ref = spl.splu(A).solve(b)
+        assert np.abs(x - ref).max() <= 1e-9 * np.abs(ref).max()
+        assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_host_block_cyclic_reduction_rejects_bad_arguments():
+    sg = _lib()
+    hp = sg.HostProblem(CONFIGS["tiny"])
+    with pytest.raises(sg.SgttError):
+        hp.bcr_solve(2, np.ones((hp.n_p, 1)))
+    with pytest.raises(sg.SgttError):
+        hp.bcr_solve(0, np.ones((hp.n_s, 1)), tau=0.0)
