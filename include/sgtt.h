@@ -176,6 +176,18 @@ int sgtt_apply(sgtt_system* sys, const sgtt_tt_pair* x, sgtt_tt_pair* y, double 
 int sgtt_precondition(sgtt_system* sys, const sgtt_tt_pair* r, sgtt_tt_pair* z,
                       const sgtt_solve_opts* opts);
 
+/* Spatial solves of the preconditioner on the device, by block cyclic
+ * reduction: which = 0 solves F_avg v = b (eq. 5.23; both velocity
+ * components, 2 n_s rows, component 2 after component 1), which = 1 solves
+ * X q = b with X = B M*^-1 B^T (eq. 5.19; n_p rows).  b and x are device
+ * buffers owned by the caller, row-major with ncols columns (ld = ncols);
+ * b is not modified.  variant = -1 uses the tuned kernel choice of every
+ * pass; 0 <= variant < sgtt_bcr_variant_count() runs every pass with that
+ * kernel variant (SGTT_E_INVALID if it does not take the factor's block
+ * size).  Runs on the context's stream and waits for it. */
+int sgtt_bcr_apply(sgtt_system* sys, int which, int variant, int ncols, const double* b, double* x);
+int sgtt_bcr_variant_count(void);
+
 /* In-place truncation T_eps (eq. 4.5-4.7): ||round(x) - x|| <= eps ||x||
  * (up to the accuracy of FP64 Gram matrices, about 1e-8 relative).  If a
  * rank would exceed max_rank (> 0; 0 means 4096) or the capacity of x, the

@@ -242,6 +242,12 @@ struct BcrDev {
 // component z of B at B + z * n * ldb, of X at X + z * n * ldx).  B is
 // overwritten (reduced right-hand sides); X must not overlap B.
 void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols);
+// The same solve with one kernel variant for every pass (0 .. count - 1);
+// throws when the variant does not take the factor's block size.
+int bcr_variant_count();
+bool bcr_variant_takes(const BcrDev& f, int variant);
+void bcr_solve_variant(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols,
+                       int variant);
 
 
 

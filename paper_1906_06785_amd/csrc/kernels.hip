@@ -1482,6 +1482,120 @@ __global__ __launch_bounds__(256) void k_bcr_tile(const BcrOpDesc* __restrict__ 
     }
 }
 
+// Operands of term t for one wave of the split-k variant: k-step q = wave +
+// 4 s (s < KQ) of row tile rt, the M fragment (fragment order; k-steps past
+// the term's end read the padding behind the data array or the next block, in
+// bounds, never multiplied) and the input rows 4 q + lane / 16 in the B
+// layout (rows past the block's end read its last row).
+template <int KQ, int NCT>
+__device__ __forceinline__ void bcr_split_load(const BcrOpDesc& d, int t, const double* __restrict__ data, int rt,
+                                               int wave, int lk, int lane, const double* B, long ldb, const double* X,
+                                               long ldx, const long (&cb_off)[NCT], const int (&cb_col)[NCT],
+                                               double (&fa)[KQ], double (&fx)[KQ][NCT]) {
+  const int i0 = d.in_r0[t], bi = d.in_bi[t];
+  const int nq = (bi + 3) / 4;
+  const double* M = data + d.off[t] + ((long)rt * nq + wave) * 64 + lane;
+  const bool from_x = (d.in_x >> t) & 1;
+  const double* src = from_x ? X : B;
+  const long ld = from_x ? ldx : ldb;
+#pragma unroll
+  for (int s = 0; s < KQ; ++s) {
+    fa[s] = M[(long)s * 256];
+    const int k = min(4 * (wave + 4 * s) + lk, bi - 1);
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) fx[s][ct] = src[(cb_off[ct] + i0 + k) * ld + cb_col[ct]];
+  }
+}
+
+// Split-k variant (the default for blocks of up to 16 KQ rows): a workgroup
+// computes one 16-row tile of an op (grid z) for CB combined columns, and its
+// four waves share the k-steps of every term (wave w takes k-steps w, w + 4,
+// ..., at most KQ per term).  Each wave loads its operands straight from
+// memory (M fragments, input rows in the matrix-core B layout), TP terms per
+// round trip, and the four partial products are added in LDS.  A wave's
+// chain of dependent products is a quarter of the row-tile variants', and a
+// small workgroup keeps many of them in flight per compute unit.  Input rows
+// past a block's end are read at its last row (finite, multiplied by the zero
+// padding of the fragment); k-steps past a term's end, and the last term
+// loaded again where the last round of terms runs short, are multiplied by
+// an exact zero.
+template <int CB, int KQ, int TP>
+__global__ __launch_bounds__(256) void k_bcr_split(const BcrOpDesc* __restrict__ ops, int op0, int nops,
+                                                   const double* __restrict__ data, double* __restrict__ B, long ldb,
+                                                   double* __restrict__ X, long ldx, int ncols, int ncomp,
+                                                   long comp_rows) {
+  constexpr int NCT = CB / 16;
+  static_assert(CB % 16 == 0, "column tiles of 16");
+  __shared__ double red[4][NCT * 256];
+  if ((int)blockIdx.x >= nops) return;   // grid padding (uniform per workgroup)
+  const BcrOpDesc& d = ops[op0 + blockIdx.x];
+  const int rt = blockIdx.z;
+  const int r0 = d.r0, bo = d.bo;
+  if (rt * 16 >= bo) return;   // uniform per workgroup
+  const int j0 = blockIdx.y * CB;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int lr = lane % 16, lk = lane / 16;
+  const int ctot = ncomp * ncols;
+  // this lane's B-operand columns, clamped to a valid one
+  long cb_off[NCT];
+  int cb_col[NCT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    const int j = min(j0 + ct * 16 + lr, ctot - 1);
+    const int comp = j / ncols;
+    cb_off[ct] = (long)comp * comp_rows;
+    cb_col[ct] = j - comp * ncols;
+  }
+  const int nterm = d.nterm;
+  double a[TP][KQ], x[TP][KQ][NCT];
+  dbl4 acc[NCT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) acc[ct] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int t0 = 0; t0 < nterm; t0 += TP) {
+#pragma unroll
+    for (int u = 0; u < TP; ++u)
+      bcr_split_load<KQ, NCT>(d, min(t0 + u, nterm - 1), data, rt, wave, lk, lane, B, ldb, X, ldx, cb_off, cb_col,
+                              a[u], x[u]);
+    __builtin_amdgcn_sched_barrier(0);   // keeps the round's loads ahead of its products
+    // no branches between the loads and their use, so that every load of
+    // the round is issued before the first product waits: k-steps past a
+    // term's end and terms past the last one multiply an exact zero
+#pragma unroll
+    for (int u = 0; u < TP; ++u) {
+      const int t = min(t0 + u, nterm - 1);
+      const int nq = (d.in_bi[t] + 3) / 4;
+      const double coef = (t0 + u < nterm) ? d.coef[t] : 0.0;
+#pragma unroll
+      for (int s = 0; s < KQ; ++s) {
+        const double av = (wave + 4 * s < nq) ? coef * a[u][s] : 0.0;
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+          acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, x[u][s][ct], acc[ct], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave][(ct * 4 + v) * 64 + lane] = acc[ct][v];
+  __syncthreads();
+  const bool to_x = d.flags & 2;
+  double* out = to_x ? X : B;
+  const long ldo = to_x ? ldx : ldb;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    // thread tid sums accumulator item (ct, v = tid / 64, lane tid % 64)
+    const int e = ct * 256 + tid, v = tid / 64, l = tid % 64;
+    const int r = rt * 16 + 4 * v + l / 16, j = j0 + ct * 16 + l % 16;
+    if (r < bo && j < ctot) {
+      double sum = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+      const int comp = j / ncols, c = j - comp * ncols;
+      if (d.flags & 1) sum += B[((long)comp * comp_rows + r0 + r) * ldb + c];
+      out[((long)comp * comp_rows + r0 + r) * ldo + c] = sum;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ blocked pivoted Cholesky
 // state[0] = residual trace, [1] = target (delta^2), [2] = zero threshold,
 // [3] = trace
@@ -1999,15 +2113,19 @@ namespace {
 struct BcrVariant {
   int cb;
   int max_rows;   // largest block the variant takes
+  int wg_rows;    // output rows per workgroup (grid z covers the largest block)
   decltype(&k_bcr_stream<32, 8>) fn;
 };
 const BcrVariant kBcrVariants[] = {
-    {32, BCR_MAXBS, k_bcr_stream<32, 8>},     {16, BCR_MAXBS, k_bcr_stream<16, 8>},
-    {32, BCR_MAXBS, k_bcr_stream<32, 16>},    {16, 128, k_bcr_tile<16, 32, true>},
-    {32, 128, k_bcr_tile<32, 32, true>},      {16, 128, k_bcr_tile<16, 32, false>},
-    {32, 128, k_bcr_tile<32, 32, false>},     {16, 64, k_bcr_tile<16, 16, true>},
-    {32, 64, k_bcr_tile<32, 16, true>},       {48, 128, k_bcr_tile<48, 32, true>},
-    {48, 128, k_bcr_tile<48, 32, false>},     {80, 128, k_bcr_tile<80, 32, false>}};
+    {32, BCR_MAXBS, 64, k_bcr_stream<32, 8>},  {16, BCR_MAXBS, 64, k_bcr_stream<16, 8>},
+    {32, BCR_MAXBS, 64, k_bcr_stream<32, 16>}, {16, 128, 64, k_bcr_tile<16, 32, true>},
+    {32, 128, 64, k_bcr_tile<32, 32, true>},   {16, 128, 64, k_bcr_tile<16, 32, false>},
+    {32, 128, 64, k_bcr_tile<32, 32, false>},  {16, 64, 64, k_bcr_tile<16, 16, true>},
+    {32, 64, 64, k_bcr_tile<32, 16, true>},    {48, 128, 64, k_bcr_tile<48, 32, true>},
+    {48, 128, 64, k_bcr_tile<48, 32, false>},  {80, 128, 64, k_bcr_tile<80, 32, false>},
+    {16, 128, 16, k_bcr_split<16, 8, 1>},      {16, 128, 16, k_bcr_split<16, 8, 2>},
+    {16, 128, 16, k_bcr_split<16, 8, 4>},      {32, 128, 16, k_bcr_split<32, 8, 1>},
+    {32, 128, 16, k_bcr_split<32, 8, 2>},      {16, 256, 16, k_bcr_split<16, 16, 1>}};
 constexpr int kNumBcrVariants = sizeof(kBcrVariants) / sizeof(kBcrVariants[0]);
 std::mutex g_bcr_mu;
 std::map<std::tuple<const double*, int, int>, std::vector<int>> g_bcr_choice;   // (factor, ncols, ncomp) -> variant per pass
@@ -2030,8 +2148,8 @@ void bcr_run(hipStream_t s, const BcrDev& f, const int* vars, int ncomp, double*
     // padded to a multiple of 8, every column chunk and row group of an op
     // runs on the same XCD and shares its blocks through that XCD's L2
     const unsigned gx = 8 * cdiv(no, 8);
-    hipLaunchKernelGGL(v.fn, dim3(gx, cdiv((long)ncomp * ncols, v.cb), cdiv(f.maxbs, 64)), dim3(256), 0, s, f.ops, o0,
-                       no, f.data, B, ldb, X, ldx, ncols, ncomp, (long)f.n);
+    hipLaunchKernelGGL(v.fn, dim3(gx, cdiv((long)ncomp * ncols, v.cb), cdiv(f.maxbs, v.wg_rows)), dim3(256), 0, s,
+                       f.ops, o0, no, f.data, B, ldb, X, ldx, ncols, ncomp, (long)f.n);
   }
   if (ev) (void)hipEventRecord(ev[f.npass], s);
 }
@@ -2109,6 +2227,22 @@ void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, d
     }
   }
   bcr_run(s, f, vars.data(), ncomp, B, ldb, X, ldx, ncols);
+}
+
+int bcr_variant_count() { return kNumBcrVariants; }
+
+bool bcr_variant_takes(const BcrDev& f, int variant) {
+  return variant >= 0 && variant < kNumBcrVariants && f.maxbs <= kBcrVariants[variant].max_rows;
+}
+
+void bcr_solve_variant(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols,
+                       int variant) {
+  if (variant < 0 || variant >= kNumBcrVariants) throw std::runtime_error("block cyclic reduction: no such variant");
+  if (f.maxbs > kBcrVariants[variant].max_rows)
+    throw std::runtime_error("block cyclic reduction: blocks too large for the variant");
+  if (ncols <= 0 || f.npass == 0) return;
+  const std::vector<int> vv(f.npass, variant);
+  bcr_run(s, f, vv.data(), ncomp, B, ldb, X, ldx, ncols);
 }
 
 int bcr_choice_count() {

@@ -1234,6 +1234,31 @@ int sgtt_precondition(sgtt_system* S, const sgtt_tt_pair* r, sgtt_tt_pair* z, co
   });
 }
 
+int sgtt_bcr_variant_count(void) { return bcr_variant_count(); }
+
+int sgtt_bcr_apply(sgtt_system* S, int which, int variant, int ncols, const double* b, double* x) {
+  if (!S || !b || !x || ncols <= 0 || (which != 0 && which != 1) || variant < -1 ||
+      variant >= bcr_variant_count())
+    return SGTT_E_INVALID;
+  sgtt_context* ctx = S->ctx;
+  return guarded(ctx, [&]() {
+    Ctx& c = ctx->c;
+    const BcrDev& f = which == 0 ? S->Fbt : S->Xbt;
+    const int ncomp = which == 0 ? 2 : 1;
+    if (variant >= 0 && !bcr_variant_takes(f, variant))
+      throw SgttError(SGTT_E_INVALID, "block cyclic reduction: blocks too large for the variant");
+    const size_t n = (size_t)ncomp * f.n * ncols;
+    double* w = c.pool.get(n);   // the reduction overwrites its right-hand side
+    SGTT_HIP(hipMemcpyAsync(w, b, sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
+    if (variant < 0)
+      bcr_solve(c.s, f, ncomp, w, ncols, x, ncols, ncols);
+    else
+      bcr_solve_variant(c.s, f, ncomp, w, ncols, x, ncols, ncols, variant);
+    c.sync();
+    c.pool.put(w);
+  });
+}
+
 int sgtt_round(sgtt_context* ctx, sgtt_tt* x, double eps, int max_rank) {
   if (!ctx || !x) return SGTT_E_INVALID;
   return guarded(ctx, [&]() {

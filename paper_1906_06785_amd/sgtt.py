@@ -150,6 +150,8 @@ _sig = {
                                 C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "sgtt_host_gpc": (C.c_int, [_P, C.c_int, C.POINTER(C.c_double)]),
     "sgtt_host_mesh": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "sgtt_bcr_apply": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
+    "sgtt_bcr_variant_count": (C.c_int, []),
     "sgtt_host_bcr_solve": (C.c_int, [_P, C.c_int, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_double),
                                       C.POINTER(C.c_double), C.POINTER(C.c_int)]),
 }
@@ -415,6 +417,10 @@ class Context:
             self._c = None
 
 
+def bcr_variant_count() -> int:
+    return _lib.sgtt_bcr_variant_count()
+
+
 class System:
     def __init__(self, ctx: Context, cfg: dict, prior: PairBuf | None = None, eps_conv=1e-3, eps_rhs=1e-6):
         self.ctx = ctx
@@ -446,6 +452,23 @@ class System:
         self.ctx.check(_lib.sgtt_apply(self._s, C.byref(sx), C.byref(so), eps))
         out.update(so)
         return out
+
+    def bcr_apply(self, which: int, b, variant: int = -1):
+        """Device block cyclic reduction solve (which 0: F_avg on both
+        velocity components, 2 n_s rows; 1: B M*^-1 B^T, n_p rows) of the
+        columns of b (a 2-D float64 tensor on the context's device); returns x
+        (new tensor).  variant -1: tuned choice; else that kernel variant for
+        every pass."""
+        import torch
+        rows = 2 * (self.nu // 2) if which == 0 else self.np
+        if b.dim() != 2 or b.shape[0] != rows or b.dtype != torch.float64 or b.device.type != "cuda":
+            raise ValueError(f"b must be a float64 device tensor with {rows} rows")
+        b = b.contiguous()
+        x = torch.empty_like(b)
+        torch.cuda.synchronize(b.device)   # b is ready before the library's stream reads it
+        self.ctx.check(_lib.sgtt_bcr_apply(self._s, which, variant, b.shape[1], C.c_void_p(b.data_ptr()),
+                                           C.c_void_p(x.data_ptr())))
+        return x
 
     def precondition(self, r: PairBuf, out: PairBuf | None = None, **opts):
         out = out or self.pair()
