@@ -100,8 +100,9 @@ def recorded_traffic(dom_name):
 
 # kernel classes of the profiler -> the kernels they stand for
 KERNEL_LABELS = {
-    "k_bcr": "k_bcr_stream<*> + k_bcr_tile<*> (block cyclic reduction passes; one event pair per spatial "
-             "solve, so the average includes the dispatch gaps between its passes)",
+    "k_bcr": "k_bcr_split<*> + k_bcr_tile<*> + k_bcr_stream<*> (block cyclic reduction passes, kernel variant "
+             "tuned per pass; one event pair per spatial solve, so the average includes the dispatch gaps between "
+             "its passes)",
 }
 
 OUT_CAPS = (128, 4096)   # output TT capacity (core-1 rank, core-2 rank) of the solution

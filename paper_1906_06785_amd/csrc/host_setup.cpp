@@ -851,6 +851,121 @@ void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& bloc
     emit(bwd[l]);
     f.pass_mode.push_back(1);
   }
+  // Columns of a term matrix that are exactly zero at either end are left
+  // out: the input rows they multiply are not read.  In the back
+  // substitution D^-1 L couples only the neighbour's rows that the original
+  // off-diagonal block touches (one node column of the slab).  A term whose
+  // matrix is zero altogether is dropped.
+  const size_t nops = f.op_out.size();
+  f.op_k0.assign(nops * NT, 0);
+  f.op_kn.assign(nops * NT, 0);
+  for (size_t o = 0; o < nops; ++o) {
+    const int bo = f.start[f.op_out[o] + 1] - f.start[f.op_out[o]];
+    int w = 0;
+    for (int t = 0; t < f.op_nterm[o]; ++t) {
+      const size_t q = NT * o + t;
+      const int ib = f.op_in[q], bi = f.start[ib + 1] - f.start[ib];
+      const double* m = f.data.data() + f.op_off[q];
+      auto zero_col = [&](int k) {
+        for (int r = 0; r < bo; ++r)
+          if (m[(size_t)k * bo + r] != 0.0) return false;
+        return true;
+      };
+      int k0 = 0, k1 = bi;
+      while (k0 < k1 && zero_col(k0)) ++k0;
+      while (k1 > k0 && zero_col(k1 - 1)) --k1;
+      if (k1 == k0) continue;
+      const size_t qw = NT * o + w++;
+      f.op_in[qw] = ib;
+      f.op_off[qw] = f.op_off[q];
+      f.op_coef[qw] = f.op_coef[q];
+      f.op_k0[qw] = k0;
+      f.op_kn[qw] = k1 - k0;
+    }
+    f.op_nterm[o] = w;
+  }
+  // An op whose terms are zero on whole row ranges of the output block is
+  // split in two at the row where that saves most (when it saves at least a
+  // tenth of the op's matrix data): each half keeps the terms that touch it.
+  // In the forward passes U D^-1 is zero on the rows of the slab's first node
+  // column.  A forward op left with nothing to add is dropped.
+  BcrFactor g;
+  g.op_out.reserve(nops);
+  g.pass_begin.push_back(0);
+  for (size_t p = 0; p + 1 < f.pass_begin.size(); ++p) {
+    for (int o = f.pass_begin[p]; o < f.pass_begin[p + 1]; ++o) {
+      const int bo = f.start[f.op_out[o] + 1] - f.start[f.op_out[o]];
+      const int nt = f.op_nterm[o];
+      std::vector<int> lo(nt), hi(nt);
+      double total = 0.0;
+      for (int t = 0; t < nt; ++t) {
+        const size_t q = NT * o + t;
+        const double* m = f.data.data() + f.op_off[q] + (size_t)f.op_k0[q] * bo;
+        const int kn = f.op_kn[q];
+        auto zero_row = [&](int r) {
+          for (int k = 0; k < kn; ++k)
+            if (m[(size_t)k * bo + r] != 0.0) return false;
+          return true;
+        };
+        lo[t] = 0;
+        hi[t] = bo;
+        while (lo[t] < hi[t] && zero_row(lo[t])) ++lo[t];
+        while (hi[t] > lo[t] && zero_row(hi[t] - 1)) --hi[t];
+        total += (double)bo * kn;
+      }
+      int best = 0;
+      double best_save = 0.0;
+      for (int t = 0; t < nt; ++t)
+        for (int rb : {lo[t], hi[t]}) {
+          if (rb <= 0 || rb >= bo) continue;
+          double save = 0.0;
+          for (int u = 0; u < nt; ++u) {
+            // rows [0, rb) need term u only if it starts there, [rb, bo) only
+            // if it ends there
+            if (lo[u] >= rb || lo[u] >= hi[u]) save += (double)rb * f.op_kn[NT * o + u];
+            if (hi[u] <= rb || lo[u] >= hi[u]) save += (double)(bo - rb) * f.op_kn[NT * o + u];
+          }
+          if (save > best_save) {
+            best_save = save;
+            best = rb;
+          }
+        }
+      const bool split = best > 0 && best_save >= 0.1 * total;
+      for (int half = 0; half < (split ? 2 : 1); ++half) {
+        const int a = split && half == 1 ? best : 0, b = split && half == 0 ? best : bo;
+        std::vector<int> keep;
+        for (int t = 0; t < nt; ++t)
+          if (!split || (lo[t] < b && hi[t] > a)) keep.push_back(t);
+        if (keep.empty() && f.pass_mode[p] == 0 && f.op_self[o]) continue;   // b stays as it is
+        g.op_out.push_back(f.op_out[o]);
+        g.op_self.push_back(f.op_self[o]);
+        g.op_row0.push_back(a);
+        g.op_rows.push_back(b - a);
+        g.op_nterm.push_back((int)keep.size());
+        for (int t = 0; t < NT; ++t) {
+          const size_t q = t < (int)keep.size() ? NT * o + keep[t] : 0;
+          const bool on = t < (int)keep.size();
+          g.op_in.push_back(on ? f.op_in[q] : 0);
+          g.op_off.push_back(on ? f.op_off[q] : 0);
+          g.op_coef.push_back(on ? f.op_coef[q] : 0.0);
+          g.op_k0.push_back(on ? f.op_k0[q] : 0);
+          g.op_kn.push_back(on ? f.op_kn[q] : 0);
+        }
+      }
+    }
+    g.pass_begin.push_back((int)g.op_out.size());
+  }
+  f.op_out.swap(g.op_out);
+  f.op_self.swap(g.op_self);
+  f.op_row0.swap(g.op_row0);
+  f.op_rows.swap(g.op_rows);
+  f.op_nterm.swap(g.op_nterm);
+  f.op_in.swap(g.op_in);
+  f.op_off.swap(g.op_off);
+  f.op_coef.swap(g.op_coef);
+  f.op_k0.swap(g.op_k0);
+  f.op_kn.swap(g.op_kn);
+  f.pass_begin.swap(g.pass_begin);
 }
 
 
@@ -863,16 +978,18 @@ void bcr_apply_host(const BcrFactor& f, int ncols, const double* b, double* x) {
     std::vector<double>& out = mode != 0 ? X : B;
     std::vector<double> res = out;   // ops of a pass read the state before the pass
     parallel_for(f.pass_begin[p + 1] - f.pass_begin[p], [&](int q) {
-      const int o = f.pass_begin[p] + q, ob = f.op_out[o], r0 = f.start[ob], bo = f.start[ob + 1] - r0;
-      for (int r = 0; r < bo; ++r)
+      const int o = f.pass_begin[p] + q, ob = f.op_out[o];
+      const int ld = f.start[ob + 1] - f.start[ob], row0 = f.op_row0[o], r0 = f.start[ob] + row0;
+      for (int r = 0; r < f.op_rows[o]; ++r)
         for (int c = 0; c < ncols; ++c) {
           double acc = f.op_self[o] ? B[(size_t)(r0 + r) * ncols + c] : 0.0;
           for (int t = 0; t < f.op_nterm[o]; ++t) {
-            const int ib = f.op_in[NT * o + t], i0 = f.start[ib], bi = f.start[ib + 1] - i0;
+            const int ib = f.op_in[NT * o + t], k0 = f.op_k0[NT * o + t], kn = f.op_kn[NT * o + t];
+            const int i0 = f.start[ib] + k0;
             const std::vector<double>& src = (mode == 1 && ib != ob) ? X : B;
-            const double* m = f.data.data() + f.op_off[NT * o + t];
+            const double* m = f.data.data() + f.op_off[NT * o + t] + (size_t)k0 * ld + row0;
             double sum = 0.0;
-            for (int k = 0; k < bi; ++k) sum += m[(size_t)k * bo + r] * src[(size_t)(i0 + k) * ncols + c];
+            for (int k = 0; k < kn; ++k) sum += m[(size_t)k * ld + r] * src[(size_t)(i0 + k) * ncols + c];
             acc += f.op_coef[NT * o + t] * sum;
           }
           res[(size_t)(r0 + r) * ncols + c] = acc;

@@ -111,11 +111,19 @@ struct BcrFactor {
   int n = 0, nblk = 0, maxbs = 0;
   std::vector<int> start;              // nblk + 1
   std::vector<int> op_out, op_self;    // per op: output block, 1 = add v_out
+  // per op: the rows [row0, row0 + rows) of the output block it writes; its
+  // term matrices are stored for the whole block (rows of the block, column-
+  // major) and the op uses their rows row0 ..
+  std::vector<int> op_row0, op_rows;
   static constexpr int NT = 16;         // terms per op (at most)
   std::vector<int> op_nterm;           // per op: number of terms
   std::vector<int> op_in;              // NT per op
   std::vector<int64_t> op_off;         // NT per op: matrix offsets in data
   std::vector<double> op_coef;         // NT per op
+  // NT per op: the term reads rows [k0, k0 + kn) of its input block and
+  // multiplies them by columns [k0, k0 + kn) of its matrix (the others are
+  // exactly zero)
+  std::vector<int> op_k0, op_kn;
   std::vector<int> pass_begin;         // op ranges of the passes (npass + 1)
   // per pass: 0 reduce the right-hand side in place (inputs from b);
   // 2 solve the top system (inputs from b, output x); 1 back substitution

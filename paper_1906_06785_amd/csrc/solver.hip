@@ -96,14 +96,15 @@ BcrDev upload_bcr(Ctx& c, const BcrFactor& f) {
   std::vector<BcrOpDesc> ops(f.op_out.size());
   std::vector<double> frag;                       // blocks in fragment order
   std::map<std::tuple<long, int, int>, long> placed;
-  auto place = [&](long off, int rows, int cols) -> long {
+  // rows x cols of a column-major matrix with ld rows starting at off
+  auto place = [&](long off, int ld, int rows, int cols) -> long {
     const auto key = std::make_tuple(off, rows, cols);
     auto it = placed.find(key);
     if (it != placed.end()) return it->second;
     const long at = (long)frag.size();
     frag.resize(frag.size() + bcr_fragment_size(rows, cols), 0.0);
     for (int k = 0; k < cols; ++k)
-      for (int i = 0; i < rows; ++i) frag[at + bcr_fragment_index(i, k, cols)] = f.data[off + (long)k * rows + i];
+      for (int i = 0; i < rows; ++i) frag[at + bcr_fragment_index(i, k, cols)] = f.data[off + (long)k * ld + i];
     placed[key] = at;
     return at;
   };
@@ -113,17 +114,17 @@ BcrDev upload_bcr(Ctx& c, const BcrFactor& f) {
     for (int o = f.pass_begin[p]; o < f.pass_begin[p + 1]; ++o) {
       BcrOpDesc& q = ops[o];
       q = BcrOpDesc();
-      const int ob = f.op_out[o];
-      q.r0 = f.start[ob];
-      q.bo = f.start[ob + 1] - q.r0;
+      const int ob = f.op_out[o], ld = f.start[ob + 1] - f.start[ob];
+      q.r0 = f.start[ob] + f.op_row0[o];
+      q.bo = f.op_rows[o];
       q.nterm = f.op_nterm[o];
       if (q.nterm > BCR_NT) throw SgttError(-6, "block cyclic reduction: too many terms");
       q.flags = (f.op_self[o] ? 1 : 0) | (mode != 0 ? 2 : 0);
       for (int t = 0; t < q.nterm; ++t) {
-        const int ib = f.op_in[BCR_NT * o + t];
-        q.in_r0[t] = f.start[ib];
-        q.in_bi[t] = f.start[ib + 1] - f.start[ib];
-        q.off[t] = place(f.op_off[BCR_NT * o + t], q.bo, q.in_bi[t]);
+        const int ib = f.op_in[BCR_NT * o + t], k0 = f.op_k0[BCR_NT * o + t];
+        q.in_r0[t] = f.start[ib] + k0;
+        q.in_bi[t] = f.op_kn[BCR_NT * o + t];
+        q.off[t] = place(f.op_off[BCR_NT * o + t] + (long)k0 * ld + f.op_row0[o], ld, q.bo, q.in_bi[t]);
         q.coef[t] = f.op_coef[BCR_NT * o + t];
         if (mode == 1 && ib != ob) q.in_x |= 1 << t;
       }
