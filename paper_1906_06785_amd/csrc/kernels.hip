@@ -946,14 +946,25 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_jacobi(int km, const int* 
   for (int i = 0; i < n; ++i) ttr += fabs(T[i * KLD + i]);
   const int np2 = n + (n & 1);
   const int npairs = np2 / 2;
+  static_assert(KSMALL <= 128, "item grids of the rotation updates");
+  int tsh = 0, vsh = 0;   // log2 of the item grid widths (>= npairs, >= n)
+  while ((1 << tsh) < npairs) ++tsh;
+  while ((1 << vsh) < n) ++vsh;
   for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
     if (tid == 0) s_flag = 0;
     __syncthreads();
     for (int rnd = 0; rnd < np2 - 1; ++rnd) {
       if (tid < npairs) {
         int a, b;
-        if (tid == 0) { a = np2 - 1; b = rnd; }
-        else { a = (rnd + tid) % (np2 - 1); b = (rnd - tid + (np2 - 1)) % (np2 - 1); }
+        if (tid == 0) {
+          a = np2 - 1;
+          b = rnd;
+        } else {   // (rnd + tid) and (rnd - tid) modulo np2 - 1, both in range after one step
+          a = rnd + tid;
+          if (a >= np2 - 1) a -= np2 - 1;
+          b = rnd - tid;
+          if (b < 0) b += np2 - 1;
+        }
         int p = a < b ? a : b, q = a < b ? b : a;
         double c = 1.0, s = 0.0;
         if (q < n) {
@@ -977,8 +988,10 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_jacobi(int km, const int* 
       // T <- J^T T J in one pass: the pairs are disjoint, so every 2 x 2
       // block (rows of pair a, columns of pair b) is updated on its own by
       // the two rotations; V <- V J alongside
-      for (int e = tid; e < npairs * npairs; e += nth) {
-        const int a = e / npairs, b = e - a * npairs;
+      // (item grids a power of two wide: no integer division by a count)
+      for (int e = tid; e < (npairs << tsh); e += nth) {
+        const int a = e >> tsh, b = e & ((1 << tsh) - 1);
+        if (b >= npairs) continue;
         const double sa = rs[a], sb = rs[b];
         if (sa == 0.0 && sb == 0.0) continue;
         const double ca = rc[a], cb = rc[b];
@@ -995,8 +1008,9 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_jacobi(int km, const int* 
         if (ra) T[qa * KLD + pb] = cb * xqp - sb * xqq;
         if (ra && rb) T[qa * KLD + qb] = sb * xqp + cb * xqq;
       }
-      for (int e = tid; e < npairs * n; e += nth) {
-        const int pr = e / n, i = e - pr * n;
+      for (int e = tid; e < (npairs << vsh); e += nth) {
+        const int pr = e >> vsh, i = e & ((1 << vsh) - 1);
+        if (i >= n) continue;
         const int p = rp[pr], q = rq[pr];
         if (p == q || rs[pr] == 0.0) continue;
         const double c = rc[pr], s = rs[pr];

@@ -423,17 +423,24 @@ TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_no
   const int kmax2 = std::min({N2, R2, maxrank, RANK_CAP});
   double* U2 = c.pool.get((size_t)N2 * kmax2);
   double* Lw = c.scratch2((size_t)N2 * kmax2 + N2 + 64);   // first-stage pivots, kept for the blocked path
-  trunc_sym(c, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw, dk + 2, dkept2, dk + 3, std::min(N2, R2), 1);
-  SGTT_HIP(hipMemcpyAsync(c.hint, dk + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, c.s));
-  c.sync();
-  h[2] = c.hint[0];
-  h[3] = c.hint[1];
+  const bool direct = N2 >= TRUNC_BLOCKED_N;
+  if (direct) {
+    h[2] = 0;
+    h[3] = 2;
+  } else {
+    trunc_sym(c, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw, dk + 2, dkept2, dk + 3, std::min(N2, R2), 1);
+    SGTT_HIP(hipMemcpyAsync(c.hint, dk + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, c.s));
+    c.sync();
+    h[2] = c.hint[0];
+    h[3] = c.hint[1];
+  }
   if (h[3] == 3) throw SgttError(-1, "TT truncation: orthonormalization failed (bond 2)");
   if (h[3] == 1) throw SgttError(-4, "TT rank capacity exceeded (bond 2)");
   Skeleton sk;
   if (h[3] == 2)
     sk = trunc_skeleton(c, N2, S2, eps, dnorm, dkept2, std::min({N2, R2, maxrank, RANK_CAP_LARGE}),
-                        std::min(N2, R2), "bond 2", Lw, Lw + (size_t)N2 * kmax2, TRUNC_KSMALL);
+                        std::min(N2, R2), "bond 2", direct ? nullptr : Lw,
+                        direct ? nullptr : Lw + (size_t)N2 * kmax2, direct ? 0 : TRUNC_KSMALL);
   const int k2 = h[3] == 2 ? sk.k : h[2];
   gemm_precision(amb);
   // ---- W (k2 x R2) = U2^T C, or the skeleton rows C[P, :]; new G3 = sum_j C_j W_j^T
@@ -487,14 +494,21 @@ TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, dou
   const int kmax2 = std::min({N2, maxrank, RANK_CAP});
   double* U2 = c.pool.get((size_t)N2 * kmax2);
   double* Lw2 = c.scratch2((size_t)N2 * kmax2 + N2 + 64);
-  trunc_sym(c, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw2, dk + 2, dkept, dk + 3, std::min(N2, n3), 1);
-  read_ints(c, dk + 2, 2, h + 2);
+  const bool direct = N2 >= TRUNC_BLOCKED_N;
+  if (direct) {
+    h[2] = 0;
+    h[3] = 2;
+  } else {
+    trunc_sym(c, N2, S2, eps, dnorm, nullptr, U2, kmax2, Lw2, dk + 2, dkept, dk + 3, std::min(N2, n3), 1);
+    read_ints(c, dk + 2, 2, h + 2);
+  }
   if (h[3] == 3) throw SgttError(-1, "TT truncation: orthonormalization failed (full bond 2)");
   if (h[3] == 1) throw SgttError(-4, "TT rank capacity exceeded (full bond 2)");
   Skeleton sk;
   if (h[3] == 2)
     sk = trunc_skeleton(c, N2, S2, eps, dnorm, dkept, std::min({N2, n3, maxrank, RANK_CAP_LARGE}), std::min(N2, n3),
-                        "full bond 2", Lw2, Lw2 + (size_t)N2 * kmax2, TRUNC_KSMALL);
+                        "full bond 2", direct ? nullptr : Lw2, direct ? nullptr : Lw2 + (size_t)N2 * kmax2,
+                        direct ? 0 : TRUNC_KSMALL);
   const int k2 = h[3] == 2 ? sk.k : h[2];
   TT t = tt_new(c, n1, n2, n3, k1, k2);
   copy2d(c.s, n1, k1, U1, kmax1, t.c1, k1, 1.0, nullptr, 0);
