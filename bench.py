@@ -76,19 +76,26 @@ def solve_options(args=None):
 # (FETCH_SIZE and WRITE_SIZE runs, scaled by the same counters on a device copy
 # of known size): bytes per launch, valid while the kernel source it was
 # measured on is unchanged (digest of the block cyclic reduction section of
-# kernels.hip).  None until measured.
-TRAFFIC_RECORD = {"kernel_src_sha256": "5d6446216e79e2098af5c8fbb7bc25afdc0703f94bebfd85502a4c061185b314",
-                  "bytes_per_launch": 34931225, "fetch_bytes_per_launch": 31545528, "write_bytes_per_launch": 3385697,
+# kernels.hip and of the host factorization).  None until measured.
+TRAFFIC_RECORD = {"kernel_src_sha256": "12eb2c4c70deb575f017698bb4d7b98b56ab3dc6b5ed67aab8c86a749f5e63ac",
+                  "bytes_per_launch": 32953178, "fetch_bytes_per_launch": 30163588, "write_bytes_per_launch": 2789590,
                   "summary": "profiles/k_bcr_c2_stokes_traffic.md"}
 
 
 def bcr_source_digest():
+    """Digest of what the pass traffic depends on: the block cyclic reduction
+    section of kernels.hip (the pass kernels) and the host factorization
+    (bcr_factor in host_setup.cpp: block sizes, levels, dropped zeros)."""
     import hashlib
-    src = open(os.path.join(ROOT, "paper_1906_06785_amd", "csrc", "kernels.hip")).read()
+    csrc = os.path.join(ROOT, "paper_1906_06785_amd", "csrc")
+    src = open(os.path.join(csrc, "kernels.hip")).read()
     head = "// " + "-" * 66 + " block cyclic reduction"
     i0 = src.index(head)
     i1 = src.index("// " + "-" * 66, i0 + len(head))
-    return hashlib.sha256(src[i0:i1].encode()).hexdigest()
+    host = open(os.path.join(csrc, "host_setup.cpp")).read()
+    j0 = host.index("void bcr_factor(")
+    j1 = host.index("void bcr_apply_host(")
+    return hashlib.sha256((src[i0:i1] + host[j0:j1]).encode()).hexdigest()
 
 
 def recorded_traffic(dom_name):
