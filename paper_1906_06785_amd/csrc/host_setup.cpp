@@ -682,7 +682,7 @@ void bcr_factor(const Csr& pat, const double* vals, const std::vector<int>& bloc
     f.data.insert(f.data.end(), m.begin(), m.end());
     return off;
   };
-  constexpr int NT = BcrFactor::NT, NTOP = 16;
+  constexpr int NT = BcrFactor::NT, NTOP = 8;
   struct Op {
     int out, self, nterm, in[NT];
     int64_t off[NT];

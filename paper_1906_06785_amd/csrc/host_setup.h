@@ -105,7 +105,7 @@ void lsc_middle_values(const HostProblem& hp, const double* Svals, double* out);
 // right-hand sides b in place from their odd neighbours' b; then the top
 // solve and the backward passes (top level down) write the solution x of the
 // odd positions from their own b and their neighbours' x.  The reduction stops
-// at 16 blocks or fewer; their system is solved with a dense inverse (one op
+// at 8 blocks or fewer; their system is solved with a dense inverse (one op
 // per block, one term per block of the top system).
 struct BcrFactor {
   int n = 0, nblk = 0, maxbs = 0;

@@ -165,10 +165,11 @@ void core2_block(hipStream_t s, int r1, int n2, int r2, const double* in, const 
 //  take_basis: U[i][c] = X[i][c] (ld ldx) for c < k when the eigen stage ran.
 constexpr int TRUNC_KSMALL = 96;
 // Second-bond Grams of at least this order go straight to the blocked
-// pivoted Cholesky (64-pivot panels, device-wide Schur updates): their ranks
-// nearly always exceed TRUNC_KSMALL, and the panels' products are shorter
-// than the one-workgroup stage's.
-constexpr int TRUNC_BLOCKED_N = 768;
+// pivoted Cholesky (32-pivot panels, device-wide Schur updates): their ranks
+// mostly exceed TRUNC_KSMALL, and the panels' products are shorter than the
+// one-workgroup stage's.
+constexpr int TRUNC_BLOCKED_N = 512;
+constexpr int TRUNC_PANEL = 32;   // pivots per panel of the blocked path (<= 64)
 void trunc_pc(hipStream_t s, int N, double* S, double eps, const double* normsq_in, double* normsq_out, double* U,
               int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound, int large_ok,
               int* kp_out, double* state, int* piv_out);
