@@ -165,11 +165,10 @@ void core2_block(hipStream_t s, int r1, int n2, int r2, const double* in, const 
 //  take_basis: U[i][c] = X[i][c] (ld ldx) for c < k when the eigen stage ran.
 constexpr int TRUNC_KSMALL = 96;
 // Second-bond Grams of at least this order go straight to the blocked
-// pivoted Cholesky (32-pivot panels, device-wide Schur updates): their ranks
-// mostly exceed TRUNC_KSMALL, and the panels' products are shorter than the
-// one-workgroup stage's.
+// pivoted Cholesky (panels of pc_panel_width pivots, device-wide Schur
+// updates): their ranks mostly exceed TRUNC_KSMALL, and the panels' products
+// are shorter than the one-workgroup stage's.
 constexpr int TRUNC_BLOCKED_N = 512;
-constexpr int TRUNC_PANEL = 32;   // pivots per panel of the blocked path (<= 64)
 void trunc_pc(hipStream_t s, int N, double* S, double eps, const double* normsq_in, double* normsq_out, double* U,
               int kmax, double* L, int* k_out, double* kept_out, int* info, int rank_bound, int large_ok,
               int* kp_out, double* state, int* piv_out);
@@ -188,6 +187,10 @@ void take_basis(hipStream_t s, const int* kp_dev, const int* k_dev, int N, const
 // subtracts Lp Lp^T from S between panels (GEMM).
 void pc_init(hipStream_t s, int N, const double* S, double eps, const double* normsq_in, double* normsq_out,
              double* d, double* state);
+// Panel width of pc_panel for Grams of order N: up to order 4096 the panel
+// lives in registers (24 pivots up to 1024, 16 up to 2048, 8 up to 4096);
+// beyond, 32-pivot panels run from global memory.
+int pc_panel_width(int N);
 void pc_panel(hipStream_t s, int N, const double* S, double* d, double* Lp, int* piv, int nsteps, double* state,
               int* out, double* kept);
 // Skeleton (interpolative) factor F = L L_P^{-1} of the pivoted Cholesky

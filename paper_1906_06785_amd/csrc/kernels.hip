@@ -1735,6 +1735,156 @@ __global__ __launch_bounds__(1024) void k_pc_panel(int N, const double* __restri
   }
 }
 
+// (argmax of the Schur diagonal with the smallest index on ties, its sum)
+// over a 1024-thread workgroup whose threads hold RQ diagonal entries each;
+// two barriers, the result broadcast to every thread.
+template <int RQ>
+__device__ __forceinline__ void pc_reg_reduce(int N, const double (&dl)[RQ], double* shv, int* shi, double* shs,
+                                              double* s_bv, int* s_p, double* s_res, double& bv, int& p,
+                                              double& sum) {
+  const int tid = threadIdx.x, wv = tid / WAVE, ln = tid % WAVE, nwv = blockDim.x / WAVE;
+  double mv = -1.0, sm = 0.0;
+  int mi = 0;
+#pragma unroll
+  for (int q = 0; q < RQ; ++q) {
+    const int i = tid + q * 1024;
+    if (i < N) {
+      sm += dl[q];
+      if (dl[q] > mv) {
+        mv = dl[q];
+        mi = i;
+      }
+    }
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const double ov = __shfl_down(mv, o, WAVE);
+    const int oi = __shfl_down(mi, o, WAVE);
+    sm += __shfl_down(sm, o, WAVE);
+    if (ov > mv || (ov == mv && oi < mi)) {
+      mv = ov;
+      mi = oi;
+    }
+  }
+  if (ln == 0) {
+    shv[wv] = mv;
+    shi[wv] = mi;
+    shs[wv] = sm;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double b = shv[0], tot = shs[0];
+    int bi = shi[0];
+    for (int q = 1; q < nwv; ++q) {
+      tot += shs[q];
+      if (shv[q] > b || (shv[q] == b && shi[q] < bi)) {
+        b = shv[q];
+        bi = shi[q];
+      }
+    }
+    *s_bv = b;
+    *s_p = bi;
+    *s_res = tot;
+  }
+  __syncthreads();
+  bv = *s_bv;
+  p = *s_p;
+  sum = *s_res;
+}
+
+// Register-resident form of k_pc_panel (same contract, panels of at most PW
+// pivots, N <= 1024 RQ): thread tid owns rows i = tid + 1024 q (q < RQ) and
+// keeps their Schur diagonal and panel entries in registers, so a pivot
+// column is its S row minus register dot products with the pivot row's
+// panel entries, which the owner publishes in LDS.  The pivot loop is
+// unrolled so that every register index is static.
+template <int RQ, int PW>
+__global__ __launch_bounds__(1024) void k_pc_panel_reg(int N, const double* __restrict__ S, double* __restrict__ d,
+                                                       double* __restrict__ Lp, int* __restrict__ piv, int nsteps,
+                                                       double* state, int* out, double* kept) {
+  __shared__ double shv[16], shs[16];
+  __shared__ int shi[16];
+  __shared__ double lp[PW];
+  __shared__ double s_bv, s_res;
+  __shared__ int s_p;
+  const int tid = threadIdx.x;
+  double dl[RQ], lr[RQ][PW];
+#pragma unroll
+  for (int q = 0; q < RQ; ++q) {
+    const int i = tid + q * 1024;
+    dl[q] = (i < N) ? d[i] : 0.0;
+#pragma unroll
+    for (int c = 0; c < PW; ++c) lr[q][c] = 0.0;
+  }
+  const double target = state[1], zero_thr = state[2];
+  double resid = state[0];
+  int t_end = PW, done = 0;
+  bool stopped = false;
+#pragma unroll
+  for (int t = 0; t < PW; ++t) {
+    double bv, sum;
+    int p;
+    pc_reg_reduce<RQ>(N, dl, shv, shi, shs, &s_bv, &s_p, &s_res, bv, p, sum);
+    if (t > 0) resid = sum;   // the first pass keeps the trace handed in
+    if (resid <= target || t == nsteps || bv <= zero_thr || bv <= 0.0) {
+      done = (t != nsteps || resid <= target) ? 1 : 0;
+      t_end = t;
+      stopped = true;
+      break;
+    }
+    // the owner of row p publishes that row's panel entries
+    if ((p & 1023) == tid) {
+#pragma unroll
+      for (int q = 0; q < RQ; ++q)
+        if (q == (p >> 10)) {
+#pragma unroll
+          for (int c = 0; c < t; ++c) lp[c] = lr[q][c];
+        }
+    }
+    if (tid == 0) piv[t] = p;
+    __syncthreads();
+    const double l = sqrt(bv);
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+      const int i = tid + q * 1024;
+      if (i < N) {
+        // S is symmetric: row p read coalesced
+        double v = S[(long)p * N + i];
+#pragma unroll
+        for (int c = 0; c < t; ++c) v = fma(-lr[q][c], lp[c], v);
+        // rows already eliminated (zero Schur diagonal) have a zero Schur row
+        const double li = (i == p) ? l : (dl[q] > 0.0 ? v / l : 0.0);
+        lr[q][t] = li;
+        const double dd = dl[q] - li * li;
+        dl[q] = (i == p || dd < 0.0) ? 0.0 : dd;
+      }
+    }
+  }
+  if (!stopped) {
+    // all PW pivots taken: the residual trace after the last one
+    double bv, sum;
+    int p;
+    pc_reg_reduce<RQ>(N, dl, shv, shi, shs, &s_bv, &s_p, &s_res, bv, p, sum);
+    resid = sum;
+    done = resid <= target ? 1 : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < RQ; ++q) {
+    const int i = tid + q * 1024;
+    if (i < N) {
+      d[i] = dl[q];
+#pragma unroll
+      for (int c = 0; c < PW; ++c)
+        if (c < t_end) Lp[(long)c * N + i] = lr[q][c];
+    }
+  }
+  if (tid == 0) {
+    state[0] = resid;
+    out[0] = t_end;
+    out[1] = done;
+    if (kept) *kept = state[3] - resid;
+  }
+}
+
 // LP[a*k + c] = L[c*N + piv[a]]: the pivot rows of L (row-major k x k,
 // lower triangular up to rounding)
 __global__ void k_gather_pivot_rows(int N, int k, const double* __restrict__ L, const int* __restrict__ piv,
@@ -2080,10 +2230,18 @@ void pc_init(hipStream_t s, int N, const double* S, double eps, const double* no
   hipLaunchKernelGGL(k_pc_init, dim3(1), dim3(1024), 0, s, N, S, eps, normsq_in, normsq_out, d, state);
 }
 
+int pc_panel_width(int N) { return N <= 1024 ? 24 : N <= 2048 ? 16 : N <= 4096 ? 8 : 32; }
+
 void pc_panel(hipStream_t s, int N, const double* S, double* d, double* Lp, int* piv, int nsteps, double* state,
               int* out, double* kept) {
   if (N > PC_Q * 1024 || nsteps > 64) throw std::runtime_error("pivoted Cholesky panel: size out of range");
   ProfScope ps(KC_TRUNC, s, 8.0 * (double)N * nsteps * 2, (double)N * nsteps * nsteps);
+  if (N <= 4096 && nsteps <= pc_panel_width(N)) {
+    // register-resident panel
+    auto kern = N <= 1024 ? k_pc_panel_reg<1, 24> : N <= 2048 ? k_pc_panel_reg<2, 16> : k_pc_panel_reg<4, 8>;
+    hipLaunchKernelGGL(kern, dim3(1), dim3(1024), 0, s, N, S, d, Lp, piv, nsteps, state, out, kept);
+    return;
+  }
   hipLaunchKernelGGL(k_pc_panel, dim3(1), dim3(1024), 0, s, N, S, d, Lp, piv, nsteps, state, out, kept);
 }
 

@@ -224,7 +224,7 @@ static Skeleton trunc_skeleton(Ctx& c, int N, double* S, double eps, const doubl
     pc_init(c.s, N, S, eps, dnorm_in, nullptr, d, state);
   }
   for (;;) {
-    const int ns = std::min(TRUNC_PANEL, kcap - k);
+    const int ns = std::min(pc_panel_width(N), kcap - k);
     if (ns <= 0) {
       if (kcap < rank_bound) {
         c.pool.put(L);
