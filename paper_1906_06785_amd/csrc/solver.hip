@@ -1249,14 +1249,19 @@ int sgtt_bcr_apply(sgtt_system* S, int which, int variant, int ncols, const doub
     if (variant >= 0 && !bcr_variant_takes(f, variant))
       throw SgttError(SGTT_E_INVALID, "block cyclic reduction: blocks too large for the variant");
     const size_t n = (size_t)ncomp * f.n * ncols;
-    double* w = c.pool.get(n);   // the reduction overwrites its right-hand side
-    SGTT_HIP(hipMemcpyAsync(w, b, sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
+    // the reduction overwrites its right-hand side: it works on a copy, which
+    // goes back to the pool on every way out
+    struct Held {
+      Pool& pool;
+      double* p;
+      ~Held() { pool.put(p); }
+    } w{c.pool, c.pool.get(n)};
+    SGTT_HIP(hipMemcpyAsync(w.p, b, sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
     if (variant < 0)
-      bcr_solve(c.s, f, ncomp, w, ncols, x, ncols, ncols);
+      bcr_solve(c.s, f, ncomp, w.p, ncols, x, ncols, ncols);
     else
-      bcr_solve_variant(c.s, f, ncomp, w, ncols, x, ncols, ncols, variant);
+      bcr_solve_variant(c.s, f, ncomp, w.p, ncols, x, ncols, ncols, variant);
     c.sync();
-    c.pool.put(w);
   });
 }
 
