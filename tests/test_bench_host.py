@@ -49,3 +49,34 @@ def test_default_solve_options(argv):
     assert a.gpus == 1 and a.config == "C2"
     o = bench.solve_options(a)
     assert o["inner_mode"] == 1 and o["precision"] == 0
+
+
+def test_traffic_digest_follows_the_pass_kernels_and_the_factorization(tmp_path, monkeypatch):
+    # the recorded traffic stays valid exactly while the pass kernels and the
+    # host factorization are unchanged
+    import shutil
+    src = os.path.join(ROOT, "paper_1906_06785_amd", "csrc")
+    dst = tmp_path / "paper_1906_06785_amd" / "csrc"
+    dst.mkdir(parents=True)
+    for f in ("kernels.hip", "host_setup.cpp"):
+        shutil.copy(os.path.join(src, f), dst / f)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    d0 = bench.bcr_source_digest()
+
+    def edit(name, anchor, extra):
+        p = dst / name
+        text = p.read_text()
+        i = text.index(anchor)
+        p.write_text(text[:i] + extra + text[i:])
+
+    # outside both sections: same digest
+    edit("kernels.hip", "// ------------------------------------------------------------------ truncation", "// note\n")
+    edit("host_setup.cpp", "void bcr_factor(", "// note\n")
+    assert bench.bcr_source_digest() == d0
+    # inside the pass kernels
+    edit("kernels.hip", "constexpr int BCR_MAXBS", "// note\n")
+    d1 = bench.bcr_source_digest()
+    assert d1 != d0
+    # inside the factorization
+    edit("host_setup.cpp", "  constexpr int NT = BcrFactor::NT, NTOP", "  // note\n")
+    assert bench.bcr_source_digest() != d1
