@@ -104,6 +104,24 @@ def test_round_large_rank_second_bond(sg, ctx, n1, r2, eps):
     assert abs(buf.r1 - r_ref[0]) <= 1
 
 
+@pytest.mark.parametrize("n1,r1", [(40, 40), (80, 80), (128, 128)])
+def test_round_blocked_panel_sizes(sg, ctx, n1, r1):
+    # second-bond Grams of order 35 r1 = 1400, 2800 and 4480: the register
+    # panels of 16 and 8 pivots and, above order 4096, the 32-pivot panels in
+    # global memory; the bound of eq. 4.6 holds on each
+    _flush(f"round blocked panels n1={n1}")
+    n2, n3, r2, eps = 35, 3000, 160, 1e-3
+    G = random_tt_cores(n1, n2, n3, r1, r2, seed=13)
+    G = (G[0], G[1], G[2] * np.exp(-0.03 * np.arange(r2))[:, None])
+    X = tt.full(G)
+    buf = sg.TTBuf(n1, n2, n3, r1 + 4, r2 + 8).set_cores(*G)
+    ctx.round(buf, eps)
+    Y = ctx.expand(buf).cpu().numpy()
+    nrm = np.linalg.norm(X)
+    assert np.linalg.norm(Y - X) <= eps * nrm * (1 + 1e-6) + 1e-8 * nrm
+    assert 1 <= buf.r2 <= r2
+
+
 def test_round_sum_cancellation(sg, ctx):
     # x + x - x rounds back to x's ranks and values
     _flush("round cancellation")
