@@ -172,9 +172,11 @@ int sgtt_apply(sgtt_system* sys, const sgtt_tt_pair* x, sgtt_tt_pair* y, double 
 
 /* z = P^-1 r for the mean-based LSC block-triangular preconditioner
  * (eq. 5.2, 5.19, 5.22-5.23).  opts supplies eps_krylov and the inner solve
- * parameters; NULL uses defaults. */
+ * parameters; NULL uses defaults.  stats (may be NULL) gets the inner
+ * iteration count (inner_iters) of this application; its other fields are
+ * zero. */
 int sgtt_precondition(sgtt_system* sys, const sgtt_tt_pair* r, sgtt_tt_pair* z,
-                      const sgtt_solve_opts* opts);
+                      const sgtt_solve_opts* opts, sgtt_solve_stats* stats);
 
 /* Spatial solves of the preconditioner on the device, by block cyclic
  * reduction: which = 0 solves F_avg v = b (eq. 5.23; both velocity
@@ -297,7 +299,7 @@ typedef struct sgtt_mlp sgtt_mlp;
 /* n = spatial size of one component (n_s of the system), capacity = pairs
  * that can be recorded (2 per velocity column of a mean solve). */
 int sgtt_mlp_create(sgtt_context* ctx, int n, int width, long capacity, unsigned seed, sgtt_mlp** out);
-int sgtt_mlp_destroy(sgtt_mlp* mlp);
+int sgtt_mlp_destroy(sgtt_mlp* mlp);   /* SGTT_E_INVALID while a system refers to it */
 /* number of parameters (W1 w x n, b1 w, W2 w x w, b2 w, W3 n x w, b3 n, in
  * this order, row-major) and of recorded pairs */
 int sgtt_mlp_size(const sgtt_mlp* mlp, long* nparam, long* npairs);
@@ -321,7 +323,11 @@ int sgtt_mlp_train(sgtt_mlp* mlp, int steps, int batch, double lr, unsigned seed
  * later solves (NULL stops recording); network and system must share the
  * context and the spatial size */
 int sgtt_mlp_collect(sgtt_system* sys, sgtt_mlp* mlp);
-/* use the network for the mean solves of this system (NULL: exact solve) */
+/* use the network for the mean solves of this system (NULL: exact solve)
+ * Ownership: a system refers to the network it collects for or uses; it does
+ * not own it.  sgtt_mlp_destroy fails with SGTT_E_INVALID (network kept)
+ * while any system still refers to it; detaching (NULL) or destroying the
+ * system releases the reference. */
 int sgtt_mlp_attach(sgtt_system* sys, sgtt_mlp* mlp);
 
 /* ------------------------------------------------------------- profiling */

@@ -20,10 +20,16 @@ the truncation, sec. 6.2): run Alg. 4.2 cycles on L d = r_j, accumulate the
 solution as the exact sum of the cycle results, and recompute the residual
 b - L z exactly in full format; stop when ||b - L z|| <= tol ||b||.
 
-Parity: the LSC preconditioner has no closed form -- "parity unpinned" beyond
-(i) the full-tensor vs TT (eps -> 0) agreement of this same code, and (ii) the
-ideal block-triangular preconditioner converging in two GMRES iterations
-(eq. 5.3), which pins block order and signs of P.
+Parity: the mean-based LSC preconditioner has no closed form in general.
+Its pins (tests/test_oracle_system.py): (i) driven through MeanLSC's own block
+code with the exact Schur complement and exact (F + C)^-1 (hooks), flexible
+GMRES converges in two iterations (eq. 5.3), which pins the block structure
+and the orientation of its pieces (the sign of p^ follows eq. 5.2 and is not
+pinned: +S and -S give the same two-step convergence);
+(ii) for a velocity operator equal to a multiple of M* the LSC approximation
+of eq. 5.19 is the exact Schur complement, which pins its composition;
+(iii) the TT form equals the full-tensor form (eps -> 0).  Beyond these, the
+approximation quality itself is parity unpinned.
 """
 from __future__ import annotations
 
@@ -152,9 +158,20 @@ def lowrank_fgmres(ops, apply_op, precond, b, tol, eps, maxit, record=None, dead
 # mean-based LSC preconditioner
 # --------------------------------------------------------------------------
 class MeanLSC:
+    """Mean-based block-triangular preconditioner (eq. 5.2) with the LSC Schur
+    approximation (eq. 5.19).  Optional hooks replace one piece of it in the
+    full-tensor forms (apply_full_exact), so that tests can drive this class's
+    own block code with pieces whose result is known:
+      schur_inv(Yp)     -> S^-1 Yp  in place of the LSC approximation,
+      velocity_inv(Y)   -> (F + C)^-1 Y  in place of the mean solve,
+      mean_apply(U)     -> the velocity operator inside eq. 5.19 in place of
+                           F_0 + C (eq. 5.20-5.21).
+    Tensors are (n_t, n_xi, n) arrays."""
+
     def __init__(self, prob, conv=None, mode="tt", inner_tol=1e-1, inner_eps=1e-3,
-                 inner_maxit=20, eps=1e-6):
+                 inner_maxit=20, eps=1e-6, schur_inv=None, velocity_inv=None, mean_apply=None):
         P = self.prob = prob
+        self.hook_schur, self.hook_vel, self.hook_mean = schur_inv, velocity_inv, mean_apply
         self.conv, self.mode = conv, mode
         self.inner_tol, self.inner_eps, self.inner_maxit, self.eps = inner_tol, inner_eps, inner_maxit, eps
         Msi = sp.diags(1.0 / P.Mstar)
@@ -244,29 +261,38 @@ class MeanLSC:
             V[k] = self._Finv(rhs)
         return V
 
-    def apply_full_exact(self, yu, yp):
-        """P^-1 [yu; yp] (eq. 5.2) with the LSC Schur approximation (eq. 5.19)
-        and the velocity block (F_0 + C)^-1 applied exactly."""
+    def schur_inv_full(self, yp):
+        """S_LSC,0^-1 yp = X^-1 [B M*^-1 (F_0 + C) M*^-1 B^T] X^-1 yp
+        (eq. 5.19) on a full pressure tensor, or the schur_inv hook."""
+        if self.hook_schur is not None:
+            return self.hook_schur(yp)
         P = self.prob
         nt, nx = P.nt, P.n_xi
         sh = (nt * nx, -1)
         t1 = self._Xinv(yp.reshape(sh))
         t2 = np.asarray(self.MsBt @ t1.T).T.reshape(nt, nx, -1)
-        t3 = self._mean_apply_full(t2)
+        t3 = self.hook_mean(t2) if self.hook_mean is not None else self._mean_apply_full(t2)
         t4 = np.asarray(self.BMs @ t3.reshape(sh).T).T
-        ph = -self._Xinv(t4).reshape(nt, nx, -1)
+        return self._Xinv(t4).reshape(nt, nx, -1)
+
+    def apply_full_exact(self, yu, yp):
+        """P^-1 [yu; yp] (eq. 5.2): p^ = -S^-1 yp with the LSC Schur
+        approximation (eq. 5.19), then the velocity block (F_0 + C)^-1 applied
+        exactly to yu - B^T p^ (each piece replaceable by its hook)."""
+        P = self.prob
+        nt, nx = P.nt, P.n_xi
+        sh = (nt * nx, -1)
+        ph = -self.schur_inv_full(yp)
         rhs = yu - np.asarray(P.Bt @ ph.reshape(sh).T).T.reshape(nt, nx, -1)
+        if self.hook_vel is not None:
+            return self.hook_vel(rhs), ph
         return self.mean_solve_exact_full(rhs), ph
 
     def apply_full(self, yu, yp):
         P = self.prob
         nt, nx = P.nt, P.n_xi
         sh = (nt * nx, -1)
-        t1 = self._Xinv(yp.reshape(sh))
-        t2 = np.asarray(self.MsBt @ t1.T).T.reshape(nt, nx, -1)
-        t3 = self._mean_apply_full(t2)
-        t4 = np.asarray(self.BMs @ t3.reshape(sh).T).T
-        ph = -self._Xinv(t4).reshape(nt, nx, -1)
+        ph = -self.schur_inv_full(yp)
         rhs = yu - np.asarray(P.Bt @ ph.reshape(sh).T).T.reshape(nt, nx, -1)
         sub = _FlatOps(rhs.shape)
         v, its, _, _ = lowrank_fgmres(sub, lambda x: self._mean_apply_full(x.reshape(rhs.shape)).ravel(),

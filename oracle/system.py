@@ -180,9 +180,8 @@ class Problem:
         from the TT cores: each sparse operator row touches only the core-3
         columns of its nonzeros.  which = "u" (velocity rows, free dofs) or
         "p" (pressure rows).  No full tensor is formed, so this works at any
-        size.  Convection is not supported here (Stokes systems)."""
-        if conv is not None:
-            raise NotImplementedError("residual_entries: Stokes systems only")
+        size.  With conv, the velocity rows include N(w~) u in the form of
+        eq. 4.12: sum_{a,b} w1[t,a] sum_k Hw[a,b][i,k] (N_b u_{t,k})_j."""
         u, pp = x
         t = np.asarray(t, dtype=np.int64)
         i = np.asarray(i, dtype=np.int64)
@@ -215,6 +214,11 @@ class Problem:
                     mu = mu - row_vals(u, self.Mb, tk - 1, jk)
                 au = row_vals(u, self.Ab, tk, jk)
                 lx = mu[ik] / self.tau + self.Gnu[ik] @ au + entry_of(pp, tk, ik, jk, self.Bt)
+                if conv is not None:
+                    for bb in range(conv.k2):
+                        nv = row_vals(u, conv.Nb_ff[bb], tk, jk)          # over chaos index k
+                        for a in range(conv.k1):
+                            lx += conv.w1[tk, a] * (conv.Hw[a, bb][ik] @ nv)
                 out[k] = entry_of(b[0], tk, ik, jk, Iu) - lx
         else:
             Ip = sp.identity(self.n_p, format="csr")

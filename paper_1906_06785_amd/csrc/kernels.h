@@ -4,6 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 namespace sgtt {
@@ -236,6 +240,13 @@ struct BcrOpDesc {
   long off[BCR_NT];
   double coef[BCR_NT];
 };
+// Tuned kernel variant per pass, per (column bucket, components), of one
+// factor.  Owned by the factor (shared between copies of its BcrDev), so a
+// choice never outlives the factor it was timed on.
+struct BcrChoices {
+  std::mutex mu;
+  std::map<std::pair<int, int>, std::vector<int>> by_key;
+};
 struct BcrDev {
   int n = 0, nblk = 0, maxbs = 0, npass = 0;
   double ndata = 0;                 // doubles of block data (for the profiler)
@@ -246,6 +257,7 @@ struct BcrDev {
   std::vector<double> pass_mk, pass_data, pass_rows;
   BcrOpDesc* ops = nullptr;
   double* data = nullptr;
+  std::shared_ptr<BcrChoices> choices = std::make_shared<BcrChoices>();
 };
 // X <- A^-1 B for ncols columns of ncomp components (rows of one component;
 // component z of B at B + z * n * ldb, of X at X + z * n * ldx).  B is

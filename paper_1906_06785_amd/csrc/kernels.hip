@@ -2299,15 +2299,18 @@ const BcrVariant kBcrVariants[] = {
     {16, 128, 16, k_bcr_split<16, 8, 4>},      {32, 128, 16, k_bcr_split<32, 8, 1>},
     {32, 128, 16, k_bcr_split<32, 8, 2>},      {16, 256, 16, k_bcr_split<16, 16, 1>}};
 constexpr int kNumBcrVariants = sizeof(kBcrVariants) / sizeof(kBcrVariants[0]);
-std::mutex g_bcr_mu;
-std::map<std::tuple<const double*, int, int>, std::vector<int>> g_bcr_choice;   // (factor, ncols, ncomp) -> variant per pass
 
 // ev (npass + 1 events, optional) brackets every pass.  The profiler sees
 // one scope per solve that counts every pass as a launch (algorithmic bytes
 // of a pass: its block data once, the right-hand side rows it reads and
 // writes).
-void bcr_run(hipStream_t s, const BcrDev& f, const int* vars, int ncomp, double* B, long ldb, double* X, long ldx,
-             int ncols, hipEvent_t* ev = nullptr) {
+void bcr_run(hipStream_t s, const BcrDev& f, const std::vector<int>& vars, int ncomp, double* B, long ldb, double* X,
+             long ldx, int ncols, hipEvent_t* ev = nullptr) {
+  // every pass needs a variant that takes the factor's largest block
+  if ((int)vars.size() != f.npass) throw std::runtime_error("block cyclic reduction: variant list does not match");
+  for (int v : vars)
+    if (v < 0 || v >= kNumBcrVariants || f.maxbs > kBcrVariants[v].max_rows)
+      throw std::runtime_error("block cyclic reduction: variant does not take the factor's blocks");
   const double cols = (double)ncomp * ncols;
   ProfScope ps(KC_BCR, s, 0.0, 0.0, 0);
   for (int p = 0; p < f.npass; ++p) {
@@ -2352,7 +2355,7 @@ std::vector<int> bcr_tune(hipStream_t s, const BcrDev& f, int ncomp, const doubl
     std::vector<float> tot(np, 0.f);
     for (int rep = 0; rep < 3; ++rep) {
       copy2d(s, (int)rows, ncols, b0, ncols, bw, ncols, 1.0, nullptr, 0);
-      bcr_run(s, f, vv.data(), ncomp, bw, ncols, xw, ncols, ncols, ev.data());
+      bcr_run(s, f, vv, ncomp, bw, ncols, xw, ncols, ncols, ev.data());
       (void)hipEventSynchronize(ev[np]);
       if (rep == 0) continue;   // the first run warms the caches
       for (int p = 0; p < np; ++p) {
@@ -2383,10 +2386,12 @@ void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, d
     // call to call; the variants' ranking follows the column count slowly)
     int bucket = 16;
     while (bucket < ncols) bucket *= 2;
-    const auto key = std::make_tuple((const double*)f.data, bucket, ncomp);
-    std::unique_lock<std::mutex> lk(g_bcr_mu);
-    auto it = g_bcr_choice.find(key);
-    if (it != g_bcr_choice.end()) {
+    if (!f.choices) throw std::runtime_error("block cyclic reduction: factor without a choice table");
+    BcrChoices& ch = *f.choices;
+    const auto key = std::make_pair(bucket, ncomp);
+    std::unique_lock<std::mutex> lk(ch.mu);
+    auto it = ch.by_key.find(key);
+    if (it != ch.by_key.end()) {
       vars = it->second;
     } else {
       lk.unlock();
@@ -2395,10 +2400,10 @@ void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, d
       vars = bcr_tune(s, f, ncomp, B, ldb, ncols);
       prof_enable_mask(was);
       lk.lock();
-      g_bcr_choice[key] = vars;
+      ch.by_key[key] = vars;
     }
   }
-  bcr_run(s, f, vars.data(), ncomp, B, ldb, X, ldx, ncols);
+  bcr_run(s, f, vars, ncomp, B, ldb, X, ldx, ncols);
 }
 
 int bcr_variant_count() { return kNumBcrVariants; }
@@ -2414,13 +2419,9 @@ void bcr_solve_variant(hipStream_t s, const BcrDev& f, int ncomp, double* B, lon
     throw std::runtime_error("block cyclic reduction: blocks too large for the variant");
   if (ncols <= 0 || f.npass == 0) return;
   const std::vector<int> vv(f.npass, variant);
-  bcr_run(s, f, vv.data(), ncomp, B, ldb, X, ldx, ncols);
+  bcr_run(s, f, vv, ncomp, B, ldb, X, ldx, ncols);
 }
 
-int bcr_choice_count() {
-  std::lock_guard<std::mutex> lk(g_bcr_mu);
-  return (int)g_bcr_choice.size();
-}
 
 void hessenberg_lsq(hipStream_t s, const double* H, int ld, int k, const double* beta, double* y, double* resid) {
   size_t shm = sizeof(double) * ((size_t)(k + 1) * k + (k + 1) + 2 * k);

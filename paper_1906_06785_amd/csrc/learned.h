@@ -31,6 +31,7 @@ struct Mlp {
   float* act = nullptr;
   size_t act_n = 0;
   double* dscal = nullptr;         // device loss accumulator
+  int uses = 0;                    // systems holding it (attached or collecting)
   ~Mlp();
 };
 

@@ -203,6 +203,8 @@ struct sgtt_system {
   // solve scratch (device scalars)
   double* dsc = nullptr;   // 32768 doubles: outer GMRES [0,16384), inner [16384,30000), residual [30000,)
   ~sgtt_system() {
+    if (mlp_collect) --mlp_collect->uses;
+    if (mlp_apply) --mlp_apply->uses;
     Kop.free_all();
     Bd.free_all();
     Btd.free_all();
@@ -1221,7 +1223,8 @@ int sgtt_apply(sgtt_system* S, const sgtt_tt_pair* x, sgtt_tt_pair* y, double ep
   });
 }
 
-int sgtt_precondition(sgtt_system* S, const sgtt_tt_pair* r, sgtt_tt_pair* z, const sgtt_solve_opts* opts) {
+int sgtt_precondition(sgtt_system* S, const sgtt_tt_pair* r, sgtt_tt_pair* z, const sgtt_solve_opts* opts,
+                      sgtt_solve_stats* stats) {
   if (!S || !r || !z) return SGTT_E_INVALID;
   sgtt_context* ctx = S->ctx;
   return guarded(ctx, [&]() {
@@ -1229,9 +1232,14 @@ int sgtt_precondition(sgtt_system* S, const sgtt_tt_pair* r, sgtt_tt_pair* z, co
     check_tt(r->p, S->nt, S->nxi, S->np);
     sgtt_solve_opts o = opts ? *opts : default_opts();
     Vec rv = vec_from_pair(r);
-    Vec zv = lsc_precondition(*S, rv, prec_opts(&o), nullptr);
+    SolveCounters cnt;
+    Vec zv = lsc_precondition(*S, rv, prec_opts(&o), &cnt);
     write_pair(ctx->c, zv, z);
     ctx->c.sync();
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->inner_iters = cnt.inner;
+    }
   });
 }
 
@@ -1585,7 +1593,13 @@ int sgtt_mlp_create(sgtt_context* ctx, int n, int width, long capacity, unsigned
 }
 
 int sgtt_mlp_destroy(sgtt_mlp* m) {
-  if (m && m->ctx) (void)hipStreamSynchronize(m->ctx->c.s);
+  if (!m) return SGTT_OK;
+  if (m->m && m->m->uses > 0) {
+    // a system still holds the network: detach it first (attach / collect NULL)
+    if (m->ctx) m->ctx->err = "network still attached to (or collecting for) a system";
+    return SGTT_E_INVALID;
+  }
+  if (m->ctx) (void)hipStreamSynchronize(m->ctx->c.s);
   delete m;
   return SGTT_OK;
 }
@@ -1639,7 +1653,9 @@ int sgtt_mlp_collect(sgtt_system* S, sgtt_mlp* m) {
     S->ctx->err = "network and system do not match (context or spatial size)";
     return SGTT_E_INVALID;
   }
+  if (S->mlp_collect) --S->mlp_collect->uses;
   S->mlp_collect = m ? m->m.get() : nullptr;
+  if (S->mlp_collect) ++S->mlp_collect->uses;
   return SGTT_OK;
 }
 
@@ -1649,7 +1665,9 @@ int sgtt_mlp_attach(sgtt_system* S, sgtt_mlp* m) {
     S->ctx->err = "network and system do not match (context or spatial size)";
     return SGTT_E_INVALID;
   }
+  if (S->mlp_apply) --S->mlp_apply->uses;
   S->mlp_apply = m ? m->m.get() : nullptr;
+  if (S->mlp_apply) ++S->mlp_apply->uses;
   return SGTT_OK;
 }
 

@@ -106,7 +106,8 @@ _sig = {
     "sgtt_system_info_get": (C.c_int, [_P, C.POINTER(SystemInfo)]),
     "sgtt_rhs": (C.c_int, [_P, C.POINTER(SgttPair)]),
     "sgtt_apply": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), C.c_double]),
-    "sgtt_precondition": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), C.POINTER(SolveOpts)]),
+    "sgtt_precondition": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), C.POINTER(SolveOpts),
+                                    C.POINTER(SolveStats)]),
     "sgtt_round": (C.c_int, [_P, C.POINTER(SgttTT), C.c_double, C.c_int]),
     "sgtt_dot": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), C.POINTER(C.c_double)]),
     "sgtt_axpby": (C.c_int, [_P, C.c_double, C.POINTER(SgttPair), C.c_double, C.POINTER(SgttPair)]),
@@ -470,13 +471,15 @@ class System:
                                            C.c_void_p(x.data_ptr())))
         return x
 
-    def precondition(self, r: PairBuf, out: PairBuf | None = None, **opts):
+    def precondition(self, r: PairBuf, out: PairBuf | None = None, with_stats: bool = False, **opts):
+        """z = P^-1 r; with_stats=True returns (z, inner iteration count)."""
         out = out or self.pair()
         o = make_opts(**opts)
+        st = SolveStats()
         sr, so = r.struct(), out.struct()
-        self.ctx.check(_lib.sgtt_precondition(self._s, C.byref(sr), C.byref(so), C.byref(o)))
+        self.ctx.check(_lib.sgtt_precondition(self._s, C.byref(sr), C.byref(so), C.byref(o), C.byref(st)))
         out.update(so)
-        return out
+        return (out, st.inner_iters) if with_stats else out
 
     def solve(self, b: PairBuf, out: PairBuf | None = None, **opts):
         out = out or self.pair(96, 512)
@@ -584,9 +587,12 @@ class Mlp:
 
     def collect(self, system, on=True):
         self.ctx.check(_lib.sgtt_mlp_collect(system._s, self._m if on else None))
+        # the system keeps the network alive while it refers to it
+        system._mlp_collect = self if on else None
 
     def attach(self, system, on=True):
         self.ctx.check(_lib.sgtt_mlp_attach(system._s, self._m if on else None))
+        system._mlp_apply = self if on else None
 
     def __del__(self):
         if getattr(self, "_m", None) and _lib is not None:

@@ -76,3 +76,28 @@ def test_bcr_rejects_bad_arguments(sg, ctx):
         S.bcr_apply(1, b, sg.bcr_variant_count())
     with pytest.raises(ValueError):
         S.bcr_apply(0, b, -1)
+
+
+def test_bcr_choice_follows_its_factor_across_systems(sg, ctx):
+    # the tuned kernel choice belongs to the factor it was timed on: systems
+    # destroyed and assembled again (a C1 factor, then the larger C1b and C2
+    # factors, then C1 again) each solve correctly with the tuned choice,
+    # whatever device addresses the allocator hands out
+    import gc
+    import torch
+    rng = np.random.default_rng(77)
+    for name in ("C1", "C1b", "C2", "C1"):
+        cfg = CONFIGS[name]
+        P = Problem(cfg)
+        F = (P.M / cfg["tau"] + cfg["nu0"] * P.A).tocsc()
+        lu = spl.splu(F)
+        for rep in range(2):
+            S = sg.System(ctx, cfg)
+            n = lu.shape[0]
+            b = rng.standard_normal((2 * n, 35))
+            ref = np.concatenate([lu.solve(b[z * n:(z + 1) * n]) for z in range(2)])
+            _flush(f"bcr tuned choice {name} rep {rep}")
+            x = S.bcr_apply(0, torch.from_numpy(b).cuda(), -1).cpu().numpy()
+            assert np.abs(x - ref).max() <= 1e-10 * np.abs(ref).max(), name
+            del S
+            gc.collect()

@@ -211,19 +211,25 @@ def test_hessenberg_lsq(sg, ctx):
         assert abs(res - np.linalg.norm(H @ yr - e1)) <= 1e-11
 
 
-def test_preconditioner_matches_oracle(sg, ctx, tiny):
+@pytest.mark.parametrize("which", ["tiny", "c1"])
+def test_preconditioner_matches_oracle(sg, ctx, tiny, c1, which):
     # with truncation switched (almost) off, P^-1 r of the library equals the
-    # oracle's full-rank TT preconditioner (same inner iteration count)
-    P, S = tiny
-    _flush("precondition tiny")
+    # oracle's full-rank TT preconditioner, with the same inner iteration count
+    P, S = tiny if which == "tiny" else c1
+    _flush(f"precondition {which}")
     r = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 4), (2, 3), 9)
-    br = _pair_buf(S, r)
-    out = S.precondition(br, eps_krylov=1e-13, inner_eps=1e-13, inner_tol=1e-1)
+    br = _pair_buf(S, r, 32, 256)
+    out, its = S.precondition(br, with_stats=True, eps_krylov=1e-13, inner_eps=1e-13, inner_tol=1e-1)
     prec = MeanLSC(P, None, "tt", 1e-1, 1e-13, 20, 1e-13)
     ref = prec.apply_tt(r)
     got = tt.pair_full(out.cores())
     want = tt.pair_full(ref)
-    assert np.linalg.norm(got - want) <= 1e-6 * np.linalg.norm(want)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    _flush(f"inner iterations gpu {its} oracle {prec.inner_iters[-1]}, rel difference {err:.2e}")
+    assert its == prec.inner_iters[-1]
+    # Gram-based rounding resolves singular values down to about sqrt(u)
+    # relative, so the inner iterates agree to about 1e-8 per step
+    assert err <= 1e-6
 
 
 def test_preconditioner_exact_inner_matches_oracle(sg, ctx, c1):
@@ -257,6 +263,19 @@ def test_preconditioner_exact_inner_long_horizon(sg, ctx):
         assert np.linalg.norm(got - want) <= 3e-8 * np.linalg.norm(want)
 
 
+# Solution-error checks refine past the 1e-8 residual target (exact residual
+# 1e-10), so that the error against the exact solution is measured rather than
+# bounded by cond(L) * 1e-8, and then require ||x - x*|| <= 1e-8 ||x*||.
+TIGHT = dict(tol=1e-10, max_cycles=12)
+
+
+def _solution_error(P, x, conv=None, b=None):
+    bo = P.rhs() if b is None else b
+    u, p = P.solve_direct(tt.full(bo[0]), tt.full(bo[1]), conv)
+    zd = np.concatenate([u.ravel(), p.ravel()])
+    return np.linalg.norm(tt.pair_full(x.cores()) - zd) / np.linalg.norm(zd)
+
+
 def test_solve_c1_stokes_to_1e8(sg, ctx, c1):
     P, S = c1
     _flush("solve C1 Stokes")
@@ -271,23 +290,43 @@ def test_solve_c1_stokes_to_1e8(sg, ctx, c1):
     yu, yp = P.apply_full(xu, xp)
     rel = np.sqrt(np.sum((bu - yu) ** 2) + np.sum((bp - yp) ** 2)) / np.sqrt(np.sum(bu ** 2) + np.sum(bp ** 2))
     assert rel <= 1e-8
-    # and the error against the exact (time-stepping) solution
-    u, p = P.solve_direct(bu, bp)
-    zd = np.concatenate([u.ravel(), p.ravel()])
-    zg = np.concatenate([xu.ravel(), xp.ravel()])
-    assert np.linalg.norm(zg - zd) <= 1e-7 * np.linalg.norm(zd)
     assert abs(S.residual(b, x) - rel) <= 1e-3 * rel + 1e-14
+    # refined past the target: the error against the exact (time-stepping)
+    # solution of the oracle
+    x2, st2, rc2 = S.solve(b, S.pair(96, 1024), **TIGHT)
+    err = _solution_error(P, x2)
+    _flush(f"refined: rel residual {st2['rel_residual']:.2e}, solution error {err:.2e}")
+    assert rc2 == 0 and st2["rel_residual"] <= 1e-10
+    assert err <= 1e-8
+
+
+def test_solve_c1_outer_iterations_match_oracle(sg, ctx, c1):
+    # the same method on both sides (Alg. 4.2 cycles with the mean-based LSC
+    # preconditioner and the inner GMRES of eq. 5.22-5.23, restart 30, fixed
+    # truncation 1e-6, refinement right-hand sides compressed at 1e-6): the
+    # outer iteration counts agree within 2 (ranks may differ by one at a
+    # threshold, which can shift an iteration)
+    from oracle.solver import solve_tt
+    P, S = c1
+    _flush("solve c1: outer iterations against the oracle")
+    b = S.rhs()
+    x, st, rc = S.solve(b, S.pair(96, 1024), restart=30, relax=0, outer_explicit=1, inner_mode=0,
+                        cycle_rhs_factor=1e-30)
+    _, ost = solve_tt(P, P.rhs())
+    _flush(f"outer iterations gpu {st['outer_iters']} ({st['cycles']} cycles), oracle {ost['outer']} "
+           f"({ost['cycles']} cycles); inner gpu {st['inner_iters']} oracle {sum(ost['inner'])}")
+    assert rc == 0 and st["rel_residual"] <= 1e-8 and ost["rel"][-1] <= 1e-8
+    assert abs(st["outer_iters"] - ost["outer"]) <= 2
 
 
 def test_solve_c1_exact_inner_to_1e8(sg, ctx, c1):
     P, S = c1
     _flush("solve c1 exact inner")
-    x, st, rc = S.solve(S.rhs(), S.pair(64, 1024), restart=20, relax=1, inner_mode=1)
-    assert rc == 0 and st["rel_residual"] <= 1e-8
-    bo = P.rhs()
-    u, p = P.solve_direct(tt.full(bo[0]), tt.full(bo[1]))
-    zd = np.concatenate([u.ravel(), p.ravel()])
-    assert np.linalg.norm(tt.pair_full(x.cores()) - zd) <= 1e-7 * np.linalg.norm(zd)
+    x, st, rc = S.solve(S.rhs(), S.pair(64, 1024), restart=20, relax=1, inner_mode=1, **TIGHT)
+    err = _solution_error(P, x)
+    _flush(f"rel residual {st['rel_residual']:.2e}, solution error {err:.2e}")
+    assert rc == 0 and st["rel_residual"] <= 1e-10
+    assert err <= 1e-8
 
 
 @pytest.mark.parametrize("precision", [1, 2])
@@ -297,22 +336,31 @@ def test_solve_c1_mixed_precision_to_1e8(sg, ctx, c1, precision):
     P, S = c1
     _flush(f"solve c1 precision={precision}")
     b = S.rhs()
-    x, st, rc = S.solve(b, S.pair(64, 1024), restart=20, relax=1, precision=precision)
-    assert rc == 0 and st["rel_residual"] <= 1e-8
-    bo = P.rhs()
-    u, p = P.solve_direct(tt.full(bo[0]), tt.full(bo[1]))
-    zd = np.concatenate([u.ravel(), p.ravel()])
-    assert np.linalg.norm(tt.pair_full(x.cores()) - zd) <= 1e-7 * np.linalg.norm(zd)
+    x, st, rc = S.solve(b, S.pair(64, 1024), restart=20, relax=1, precision=precision, **TIGHT)
+    err = _solution_error(P, x)
+    _flush(f"rel residual {st['rel_residual']:.2e}, solution error {err:.2e}")
+    assert rc == 0 and st["rel_residual"] <= 1e-10
+    assert err <= 1e-8
 
 
-@pytest.mark.parametrize("precision,bound", [(1, 1e-3), (2, 1e-1)])
-def test_preconditioner_reduced_precision_close(sg, ctx, tiny, precision, bound):
-    # the reduced-precision inner solve stays close to the FP64 one (it is a
-    # preconditioner: its error only costs iterations, not accuracy)
-    P, S = tiny
-    _flush(f"precondition tiny precision={precision}")
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_preconditioner_reduced_precision_meets_inner_tolerance(sg, ctx, c1, precision):
+    # In every precision the preconditioner does what eq. 5.2 with eq. 5.22
+    # asks, checked with the oracle's operators on full tensors: the pressure
+    # part is p^ = -S_LSC^-1 y_p (FP64 in every mode), and the velocity part
+    # solves (F_0 + C) v = y_u - B^T p^ to the inner tolerance 1e-1 (plus the
+    # inner truncation 1e-3).  Reduced precision only changes which
+    # approximate solution the inner GMRES returns.
+    P, S = c1
+    _flush(f"precondition c1 precision={precision}")
     r = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 4), (2, 3), 9)
-    br = _pair_buf(S, r)
-    ref = tt.pair_full(S.precondition(br, inner_eps=1e-3).cores())
-    got = tt.pair_full(S.precondition(br, inner_eps=1e-3, precision=precision).cores())
-    assert np.linalg.norm(got - ref) <= bound * np.linalg.norm(ref)
+    out = S.precondition(_pair_buf(S, r, 32, 256), inner_eps=1e-3, precision=precision)
+    zu, zp = [tt.full(c) for c in out.cores()]
+    prec = MeanLSC(P, None, "full")
+    ph = -prec.schur_inv_full(tt.full(r[1]))
+    assert np.linalg.norm(zp - ph) <= 1e-5 * np.linalg.norm(ph)
+    sh = (P.nt * P.n_xi, -1)
+    rhs = tt.full(r[0]) - np.asarray(P.Bt @ ph.reshape(sh).T).T.reshape(zu.shape)
+    res = np.linalg.norm(prec._mean_apply_full(zu) - rhs) / np.linalg.norm(rhs)
+    _flush(f"inner relative residual {res:.3e}")
+    assert res <= 0.15

@@ -86,3 +86,36 @@ def test_convection_skew_up_to_boundary():
     # boundary mass on that edge, whose total is the edge length 2
     out = np.abs(x1 - 2.0) < 1e-12
     assert abs(S[np.ix_(out, out)].sum() - 2.0) < 1e-12
+
+
+def test_convection_orientation_constant_wind():
+    # eq. 3.7: [N(w)]_ij = (w . grad phi_j, phi_i), so N(w) applied to the
+    # nodal values of a Q2 function v gives the moments (w . grad v, phi_i).
+    # For constant w and v = x1 (or x2) that is w1 (1, phi_i) = w1 (M 1)_i on
+    # EVERY row; the transposed matrix gives (w . grad phi_i, x1) instead,
+    # which differs on every row.
+    m = fem.build_mesh(0.5, 2.0)
+    M, A, B1, B2, Mp = fem.assemble(m)
+    one = np.ones(m.n_all)
+    x1, x2 = m.coords[:, 0], m.coords[:, 1]
+    w1, w2 = 0.7, -0.4
+    N = fem.convection(m, np.full(m.n_all, w1), np.full(m.n_all, w2))
+    assert np.abs(N @ x1 - w1 * (M @ one)).max() < 1e-14
+    assert np.abs(N @ x2 - w2 * (M @ one)).max() < 1e-14
+    assert np.abs(N.T @ x1 - w1 * (M @ one)).max() > 1e-3
+    # quadratic v = x1^2: w . grad v = 2 w1 x1, a Q2 function
+    assert np.abs(N @ (x1 * x1) - 2 * w1 * (M @ x1)).max() < 1e-13
+
+
+def test_convection_orientation_solenoidal_wind():
+    # non-constant divergence-free wind w = (x2, x1): w . grad x1 = x2 and
+    # w . grad x2 = x1, so N x1 = M x2 and N x2 = M x1 row by row; the Q2
+    # wind is exact and 3x3 Gauss integrates the products exactly.
+    m = fem.build_mesh(0.25, 2.0)
+    M, A, B1, B2, Mp = fem.assemble(m)
+    x1, x2 = m.coords[:, 0], m.coords[:, 1]
+    N = fem.convection(m, x2.copy(), x1.copy())
+    assert np.abs(N @ x1 - M @ x2).max() < 1e-13
+    assert np.abs(N @ x2 - M @ x1).max() < 1e-13
+    # and for v = x1 x2: w . grad v = x2^2 + x1^2
+    assert np.abs(N @ (x1 * x2) - M @ (x1 * x1 + x2 * x2)).max() < 1e-13

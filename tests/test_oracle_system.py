@@ -256,6 +256,16 @@ def test_residual_entries_match_full_residual():
         t, i, j = g.integers(0, P.nt, 60), g.integers(0, P.n_xi, 60), g.integers(0, n, 60)
         e = P.residual_entries(b, x, which, t, i, j)
         assert np.abs(e - full[t, i, j]).max() <= 1e-13 * np.abs(full).max()
+    # a Picard system: the convection term of eq. 4.12 entry by entry
+    prior = _prior(P)
+    conv = P.convection(prior, 1e-3)
+    b2 = P.rhs(prior)
+    yu, yp = P.apply_full(tt.full(x[0]), tt.full(x[1]), conv)
+    ru, rp = tt.full(b2[0]) - yu, tt.full(b2[1]) - yp
+    for which, full, n in (("u", ru, P.n_u), ("p", rp, P.n_p)):
+        t, i, j = g.integers(0, P.nt, 60), g.integers(0, P.n_xi, 60), g.integers(0, n, 60)
+        e = P.residual_entries(b2, x, which, t, i, j, conv=conv)
+        assert np.abs(e - full[t, i, j]).max() <= 1e-13 * np.abs(full).max()
 
 
 def test_picard_direct_contracts(tiny):
@@ -277,3 +287,116 @@ def test_exact_mean_solve_inverts_mean_matrix(tiny):
     V = prec.mean_solve_exact_full(Y)
     back = prec._mean_apply_full(V)
     assert np.linalg.norm(back - Y) <= 1e-12 * np.linalg.norm(Y)
+
+
+def _psi_multi(idx, xi):
+    # orthonormal multivariate Legendre polynomial for U[-1,1]^m (scipy's
+    # Legendre evaluation, independent of oracle.gpc)
+    from scipy.special import eval_legendre
+    v = 1.0
+    for k, n in enumerate(idx):
+        v = v * np.sqrt(2 * n + 1) * eval_legendre(n, xi[k])
+    return v
+
+
+def test_sg_convection_matches_quadrature():
+    # eq. 4.12: the stochastic Galerkin convection of a wind w(t, xi, x) =
+    # sum_l w_l(t, x) psi_l(xi) is the Galerkin projection
+    #     out_r(t) = E[ psi_r(xi) N(w(t, xi)) u(t, xi) ],  u = sum_s u_s psi_s,
+    # evaluated here by tensor Gauss-Legendre quadrature of deterministic
+    # convection matrices assembled at each quadrature point (m = 2, p = 2).
+    from scipy.special import roots_legendre
+    from oracle import mesh as fem
+    cfg = dict(CONFIGS["tiny"], m=2, p=2, nt=2)
+    P = Problem(cfg)
+    g = np.random.default_rng(21)
+    na, f = P.n_all, P.mesh.free
+    # an all-node wind TT of ranks (2, 3) and a free-dof velocity tensor
+    W1 = g.standard_normal((P.nt, 2))
+    W2 = g.standard_normal((2, P.n_xi, 3))
+    W3 = g.standard_normal((3, 2 * na))
+    conv = __import__("oracle.system", fromlist=["Convection"]).Convection(P, (W1, W2, W3))
+    U = g.standard_normal((P.nt, P.n_xi, P.n_u))
+    got = conv.full_apply(U)
+    Wfull = np.einsum("ta,alb,bx->tlx", W1, W2, W3)          # (nt, n_xi, 2 n_all)
+    xq, wq = roots_legendre(5)                               # exact for degree <= 9 per variable
+    want = np.zeros_like(U)
+    for q1, w1q in zip(xq, wq):
+        for q2, w2q in zip(xq, wq):
+            xi = (q1, q2)
+            wt = 0.25 * w1q * w2q                            # U[-1,1]^2 density
+            psi = np.array([_psi_multi(ix, xi) for ix in P.idx])
+            for t in range(P.nt):
+                w = psi @ Wfull[t]                           # wind at this xi
+                N = fem.convection(P.mesh, w[:na], w[na:])[f][:, f]
+                u = psi @ U[t]
+                Nu = np.concatenate([N @ u[:P.n_s], N @ u[P.n_s:]])
+                want[t] += wt * psi[:, None] * Nu[None, :]
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    # the mean convection of eq. 5.21 (psi_1 mode of the wind, identity in
+    # the chaos mode) is N(E[w]) applied to every chaos coefficient
+    got0 = conv.full_apply(U, mean=True)
+    want0 = np.zeros_like(U)
+    for t in range(P.nt):
+        N = fem.convection(P.mesh, Wfull[t, 0, :na], Wfull[t, 0, na:])[f][:, f]
+        for r in range(P.n_xi):
+            want0[t, r] = np.concatenate([N @ U[t, r, :P.n_s], N @ U[t, r, P.n_s:]])
+    assert np.abs(got0 - want0).max() <= 1e-12 * np.abs(want0).max()
+
+
+def test_meanlsc_block_code_with_exact_pieces_converges_in_two(tiny):
+    # eq. 5.2-5.3 through MeanLSC's own block code: with the exact Schur
+    # complement S = B (F + C)^-1 B^T and the exact (F + C)^-1 swapped in by
+    # its hooks, flexible GMRES converges in two iterations.  A dropped
+    # coupling B^T p^ or a transposed piece breaks this (S is not symmetric:
+    # F + C is block lower-bidiagonal in time).  The sign and scale of the
+    # Schur block are not fixed by it (block-triangular forms with +S or
+    # -S both give two iterations).
+    from oracle.solver import MeanLSC
+    P = tiny
+    K = P.explicit().toarray()
+    nu_tot = P.nt * P.n_xi * P.n_u
+    F, Bt, Bm = K[:nu_tot, :nu_tot], K[:nu_tot, nu_tot:], K[nu_tot:, :nu_tot]
+    Finv = np.linalg.inv(F)
+    Sinv = np.linalg.inv(Bm @ Finv @ Bt)
+    shp_u, shp_p = (P.nt, P.n_xi, P.n_u), (P.nt, P.n_xi, P.n_p)
+    prec = MeanLSC(P, None, "full", schur_inv=lambda Y: (Sinv @ Y.ravel()).reshape(shp_p),
+                   velocity_inv=lambda Y: (Finv @ Y.ravel()).reshape(shp_u))
+    ops = FullOps(P)
+
+    def pc(v):
+        u, p = ops.split(v)
+        return ops.join(*prec.apply_full_exact(u, p))
+
+    b = tt.pair_full(P.rhs())
+    z, k, res, bn = lowrank_fgmres(ops, lambda x: K @ x, pc, b, 1e-10, 0.0, 10)
+    assert k == 2
+    assert np.linalg.norm(K @ z - b) <= 1e-10 * bn
+    # a transposed Schur inverse loses the two-step convergence
+    bad = MeanLSC(P, None, "full", schur_inv=lambda Y: (Sinv.T @ Y.ravel()).reshape(shp_p),
+                  velocity_inv=lambda Y: (Finv @ Y.ravel()).reshape(shp_u))
+
+    def pc_bad(v):
+        u, p = ops.split(v)
+        return ops.join(*bad.apply_full_exact(u, p))
+
+    _, k_bad, _, _ = lowrank_fgmres(ops, lambda x: K @ x, pc_bad, b, 1e-10, 0.0, 10)
+    assert k_bad > 2
+
+
+def test_lsc_is_exact_for_a_diagonal_velocity_operator(tiny):
+    # eq. 5.19: when the velocity operator is alpha M* (a multiple of the
+    # diagonal mass used inside the LSC formula), X (B M*^-1 F M*^-1 B^T)^-1 X
+    # with X = B M*^-1 B^T equals the exact Schur complement B F^-1 B^T =
+    # X / alpha.  Pins the composition and placement of M*^-1 in MeanLSC.
+    from oracle.solver import MeanLSC
+    P = tiny
+    alpha = 3.7
+    Ms = P.Mstar
+    prec = MeanLSC(P, None, "full", mean_apply=lambda U: alpha * Ms[None, None, :] * U)
+    g = np.random.default_rng(5)
+    Yp = g.standard_normal((P.nt, P.n_xi, P.n_p))
+    got = prec.schur_inv_full(Yp)
+    S = (P.B @ sp.diags(1.0 / (alpha * Ms)) @ P.Bt).toarray()
+    want = np.linalg.solve(S, Yp.reshape(-1, P.n_p).T).T.reshape(Yp.shape)
+    assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
