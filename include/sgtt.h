@@ -163,7 +163,12 @@ int sgtt_assemble(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_t
 int sgtt_system_destroy(sgtt_system* sys);
 int sgtt_system_info_get(const sgtt_system* sys, sgtt_system_info* info);
 
-/* Write the right-hand side into caller buffers b (capacities checked). */
+/* Write the right-hand side of the system into caller buffers b: for the
+ * Stokes system the lifted Dirichlet data f (sec. 3.2 with the inflow of
+ * eq. 6.1; exact TT of ranks <= 2), for a Picard step the nonlinear residual
+ * r = f - L(w)[w; p_w] of eq. 3.15 (the untruncated prior, sec. 4.3),
+ * truncated with desc->eps_rhs.  Capacities of b are checked
+ * (SGTT_E_RANK_CAP, b unchanged); ranks are written to b. */
 int sgtt_rhs(sgtt_system* sys, sgtt_tt_pair* b);
 
 /* y = L x (eq. 3.11-3.12 with eq. 4.4 and eq. 4.12), exact when eps == 0,
@@ -190,6 +195,7 @@ int sgtt_precondition(sgtt_system* sys, const sgtt_tt_pair* r, sgtt_tt_pair* z,
 int sgtt_bcr_apply(sgtt_system* sys, int which, int variant, int ncols, const double* b, double* x);
 int sgtt_bcr_variant_count(void);
 
+
 /* In-place truncation T_eps (eq. 4.5-4.7): ||round(x) - x|| <= eps ||x||
  * (up to the accuracy of FP64 Gram matrices, about 1e-8 relative).  If a
  * rank would exceed max_rank (> 0; 0 means 4096) or the capacity of x, the
@@ -199,10 +205,22 @@ int sgtt_bcr_variant_count(void);
  * holds, core 2 is then not orthonormal. */
 int sgtt_round(sgtt_context* ctx, sgtt_tt* x, double eps, int max_rank);
 
-/* <x, y> = <x.u, y.u> + <x.p, y.p>; result to host memory (synchronizes). */
+/* Euclidean inner product of two all-at-once vectors over all free (time,
+ * chaos, space) coefficients, <x, y> = <x.u, y.u> + <x.p, y.p> (the norm of
+ * the residual and the Gram-Schmidt products of Alg. 4.2), computed from the
+ * cores by contraction over the TT modes (sec. 4.1, eq. 4.4 applied to the
+ * identity), never expanding the tensors.  x and y must have the same mode
+ * sizes (SGTT_E_INVALID otherwise); ranks may differ.  Result to host memory
+ * (synchronizes the context stream); SGTT_E_NONFINITE for a NaN/Inf result. */
 int sgtt_dot(sgtt_context* ctx, const sgtt_tt_pair* x, const sgtt_tt_pair* y, double* out);
 
-/* y = alpha x + beta y as an exact TT (ranks add; capacity checked). */
+/* y = alpha x + beta y as an exact TT by core concatenation (sec. 4.1: the
+ * ranks of a sum add, and the sum is not truncated; Alg. 4.2 rounds such
+ * sums with sgtt_round).  Core 1 of the result is [alpha X1, beta Y1], core 2
+ * is block diagonal, core 3 is [X3, Y3] (in the layout of sgtt_tt).  The
+ * result ranks (x.r1 + y.r1, x.r2 + y.r2) must fit y's capacities, else
+ * SGTT_E_RANK_CAP with y unchanged; mode sizes must match (SGTT_E_INVALID).
+ * y is overwritten on success (its ranks updated). */
 int sgtt_axpby(sgtt_context* ctx, double alpha, const sgtt_tt_pair* x, double beta, sgtt_tt_pair* y);
 
 /* Solve L x = b (Alg. 4.2 with refinement to an exact relative residual).
