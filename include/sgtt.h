@@ -195,6 +195,24 @@ int sgtt_precondition(sgtt_system* sys, const sgtt_tt_pair* r, sgtt_tt_pair* z,
 int sgtt_bcr_apply(sgtt_system* sys, int which, int variant, int ncols, const double* b, double* x);
 int sgtt_bcr_variant_count(void);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * spatial solve as sgtt_bcr_apply, allocating nothing.  The reduction's
+ * working copy of b lives in a fixed device array that the library holds on
+ * every GPU it runs on until the process ends, of
+ * SGTT_NOALLOC_SCRATCH_DOUBLES doubles (32 MiB): it takes
+ * ncomp * rows * ncols <= SGTT_NOALLOC_SCRATCH_DOUBLES (ncomp = 2 for
+ * which = 0, else 1; rows = n_s or n_p), else SGTT_E_INVALID with nothing
+ * launched.  variant >= 0 runs that kernel variant in every pass; -1 takes
+ * the choice an earlier sgtt_bcr_apply or solve tuned for this column count
+ * (power-of-two bucket), else the first variant that takes the blocks: no
+ * timing runs.  Stream-ordered on the context's stream and does NOT wait for
+ * it (the caller synchronizes before reading x).  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other contexts or
+ * streams, other threads) race.  Each call overwrites the part of the array
+ * it uses before reading it. */
+#define SGTT_NOALLOC_SCRATCH_DOUBLES (4 * 1024 * 1024)
+int sgtt_bcr_apply_noalloc(sgtt_system* sys, int which, int variant, int ncols, const double* b, double* x);
 
 /* In-place truncation T_eps (eq. 4.5-4.7): ||round(x) - x|| <= eps ||x||
  * (up to the accuracy of FP64 Gram matrices, about 1e-8 relative).  If a

@@ -269,6 +269,11 @@ int bcr_variant_count();
 bool bcr_variant_takes(const BcrDev& f, int variant);
 void bcr_solve_variant(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols,
                        int variant);
+// The same solve without timing variants: variant >= 0 for every pass, or
+// -1 for the choice an earlier bcr_solve tuned for this column bucket, else
+// the first variant that takes the blocks.  Launches only (no allocation).
+void bcr_solve_untuned(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols,
+                       int variant);
 
 
 

@@ -2377,18 +2377,24 @@ std::vector<int> bcr_tune(hipStream_t s, const BcrDev& f, int ncomp, const doubl
 }
 }  // namespace
 
+namespace {
+// column counts share a choice per power-of-two bucket (ranks vary from call
+// to call; the variants' ranking follows the column count slowly)
+std::pair<int, int> bcr_choice_key(int ncomp, int ncols) {
+  int bucket = 16;
+  while (bucket < ncols) bucket *= 2;
+  return std::make_pair(bucket, ncomp);
+}
+}  // namespace
+
 void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols) {
   if (ncols <= 0 || f.npass == 0) return;
   if (f.maxbs > BCR_MAXBS) throw std::runtime_error("block cyclic reduction: block larger than 256");
   std::vector<int> vars;
   {
-    // column counts share a choice per power-of-two bucket (ranks vary from
-    // call to call; the variants' ranking follows the column count slowly)
-    int bucket = 16;
-    while (bucket < ncols) bucket *= 2;
     if (!f.choices) throw std::runtime_error("block cyclic reduction: factor without a choice table");
     BcrChoices& ch = *f.choices;
-    const auto key = std::make_pair(bucket, ncomp);
+    const auto key = bcr_choice_key(ncomp, ncols);
     std::unique_lock<std::mutex> lk(ch.mu);
     auto it = ch.by_key.find(key);
     if (it != ch.by_key.end()) {
@@ -2401,6 +2407,31 @@ void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, d
       prof_enable_mask(was);
       lk.lock();
       ch.by_key[key] = vars;
+    }
+  }
+  bcr_run(s, f, vars, ncomp, B, ldb, X, ldx, ncols);
+}
+
+void bcr_solve_untuned(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols,
+                       int variant) {
+  if (ncols <= 0 || f.npass == 0) return;
+  if (f.maxbs > BCR_MAXBS) throw std::runtime_error("block cyclic reduction: block larger than 256");
+  std::vector<int> vars;
+  if (variant >= 0) {
+    if (!bcr_variant_takes(f, variant))
+      throw std::runtime_error("block cyclic reduction: blocks too large for the variant");
+    vars.assign(f.npass, variant);
+  } else {
+    if (f.choices) {
+      std::lock_guard<std::mutex> lk(f.choices->mu);
+      auto it = f.choices->by_key.find(bcr_choice_key(ncomp, ncols));
+      if (it != f.choices->by_key.end()) vars = it->second;
+    }
+    if (vars.empty()) {
+      int v = 0;
+      while (v < kNumBcrVariants && !bcr_variant_takes(f, v)) ++v;
+      if (v == kNumBcrVariants) throw std::runtime_error("block cyclic reduction: no variant takes the blocks");
+      vars.assign(f.npass, v);
     }
   }
   bcr_run(s, f, vars, ncomp, B, ldb, X, ldx, ncols);

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <map>
@@ -25,6 +26,7 @@ using namespace sgtt;
 struct sgtt_context {
   int device = 0;
   bool own_stream = false;
+  double* scratch = nullptr;   // this device's allocation-free scratch (device address)
   std::string err;
   Ctx c;
 };
@@ -892,6 +894,33 @@ int guarded(sgtt_context* ctx, F&& f) {
 }
 }  // namespace
 
+// Device scratch of the allocation-free spatial solve (sgtt_bcr_apply_noalloc):
+// the working copy of the right-hand side that the reduction overwrites.
+// Every GPU the library runs on holds its own copy until the process ends.
+// Host code never uses the array's name as an address: it takes the
+// per-device address that hipGetSymbolAddress returns (noalloc_scratch).
+static __device__ __align__(256) double scratch[SGTT_NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's scratch; resolved once per device, with that
+// device current (the caller has made it current).
+double* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) throw SgttError(SGTT_E_INVALID, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    SGTT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw SgttError(SGTT_E_HIP, "scratch symbol has no device address");
+    g_scratch_ptr[device] = (double*)p;
+  }
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
 extern "C" {
 
 const char* sgtt_version(void) { return "sgtt 0.1 gfx950 fp64"; }
@@ -910,6 +939,7 @@ int sgtt_context_create(int device, void* stream, sgtt_context** out) {
       SGTT_HIP(hipStreamCreate(&ctx->c.s));   // blocking: ordered after the legacy default stream
       ctx->own_stream = true;
     }
+    ctx->scratch = noalloc_scratch(device);
     SGTT_HIP(hipHostMalloc((void**)&ctx->c.hint, 64 * sizeof(int), hipHostMallocDefault));
     SGTT_HIP(hipHostMalloc((void**)&ctx->c.hdbl, 256 * sizeof(double), hipHostMallocDefault));
     ctx->c.dint = (int*)ctx->c.pool.get(64);
@@ -1270,6 +1300,29 @@ int sgtt_bcr_apply(sgtt_system* S, int which, int variant, int ncols, const doub
     else
       bcr_solve_variant(c.s, f, ncomp, w.p, ncols, x, ncols, ncols, variant);
     c.sync();
+  });
+}
+
+int sgtt_bcr_apply_noalloc(sgtt_system* S, int which, int variant, int ncols, const double* b, double* x) {
+  if (!S || !b || !x || ncols <= 0 || (which != 0 && which != 1) || variant < -1 ||
+      variant >= bcr_variant_count())
+    return SGTT_E_INVALID;
+  sgtt_context* ctx = S->ctx;
+  return guarded(ctx, [&]() {
+    Ctx& c = ctx->c;
+    const BcrDev& f = which == 0 ? S->Fbt : S->Xbt;
+    const int ncomp = which == 0 ? 2 : 1;
+    const size_t n = (size_t)ncomp * f.n * ncols;
+    if (n > (size_t)SGTT_NOALLOC_SCRATCH_DOUBLES)
+      throw SgttError(SGTT_E_INVALID, "sgtt_bcr_apply_noalloc: " + std::to_string(n) +
+                                          " right-hand-side values exceed the scratch of " +
+                                          std::to_string((long)SGTT_NOALLOC_SCRATCH_DOUBLES) + " doubles");
+    if (!ctx->scratch) throw SgttError(SGTT_E_INVALID, "context has no scratch address");
+    // the whole working copy is overwritten before the reduction reads it,
+    // so what an earlier call left in the scratch is never seen
+    SGTT_HIP(hipMemcpyAsync(ctx->scratch, b, sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
+    bcr_solve_untuned(c.s, f, ncomp, ctx->scratch, ncols, x, ncols, ncols, variant);
+    SGTT_HIP(hipGetLastError());
   });
 }
 

@@ -153,6 +153,7 @@ _sig = {
     "sgtt_host_mesh": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "sgtt_bcr_apply": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
     "sgtt_bcr_variant_count": (C.c_int, []),
+    "sgtt_bcr_apply_noalloc": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
     "sgtt_host_bcr_solve": (C.c_int, [_P, C.c_int, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_double),
                                       C.POINTER(C.c_double), C.POINTER(C.c_int)]),
 }
@@ -469,6 +470,24 @@ class System:
         torch.cuda.synchronize(b.device)   # b is ready before the library's stream reads it
         self.ctx.check(_lib.sgtt_bcr_apply(self._s, which, variant, b.shape[1], C.c_void_p(b.data_ptr()),
                                            C.c_void_p(x.data_ptr())))
+        return x
+
+    def bcr_apply_noalloc(self, which: int, b, x, variant: int = -1):
+        """The same solve through the allocation-free entry point, into the
+        caller's x (a float64 device tensor shaped like b); waits for the
+        context's stream before returning."""
+        import torch
+        rows = 2 * (self.nu // 2) if which == 0 else self.np
+        for t in (b, x):
+            if t.dim() != 2 or t.shape[0] != rows or t.dtype != torch.float64 or t.device.type != "cuda" \
+                    or not t.is_contiguous():
+                raise ValueError(f"b and x must be contiguous float64 device tensors with {rows} rows")
+        if x.shape != b.shape:
+            raise ValueError("x must have the shape of b")
+        torch.cuda.synchronize(b.device)
+        self.ctx.check(_lib.sgtt_bcr_apply_noalloc(self._s, which, variant, b.shape[1], C.c_void_p(b.data_ptr()),
+                                                   C.c_void_p(x.data_ptr())))
+        torch.cuda.synchronize(b.device)   # the call does not wait for its stream
         return x
 
     def precondition(self, r: PairBuf, out: PairBuf | None = None, with_stats: bool = False, **opts):
