@@ -109,6 +109,27 @@ def build_mesh(h: float, L: float = 12.0) -> StepMesh:
     return StepMesh(h, L, coords, conn, pcoords, pconn, free, dirichlet, g1)
 
 
+def _q1_1d_d(t):
+    return np.array([-0.5, 0.5])
+
+
+def _ref_tables_q1():
+    """Q1 basis derivatives at the 9 Gauss points: dpsi[g, k, d]."""
+    dpsi = np.zeros((9, 4, 2))
+    g = 0
+    for jb in range(3):
+        for ia in range(3):
+            xi, eta = _GP[ia], _GP[jb]
+            px, py = _q1_1d(xi), _q1_1d(eta)
+            dx, dy = _q1_1d_d(xi), _q1_1d_d(eta)
+            for b in range(2):
+                for a in range(2):
+                    dpsi[g, a + 2 * b, 0] = dx[a] * py[b]
+                    dpsi[g, a + 2 * b, 1] = px[a] * dy[b]
+            g += 1
+    return dpsi
+
+
 def _ref_tables():
     """Basis values / derivatives at the 9 Gauss points of the reference square."""
     phi = np.zeros((9, 9))      # [gauss point g, local node k]
@@ -179,3 +200,29 @@ def convection(mesh: StepMesh, w1: np.ndarray, w2: np.ndarray):
         + np.einsum("g,eg,gi,gj->eij", wq, W2, phi, dphi[:, :, 1])
     Ne *= h / 2.0
     return _assemble(mesh.conn, mesh.conn, Ne, mesh.n_all, mesh.n_all)
+
+
+def pressure_stiffness(mesh: StepMesh):
+    """Unit-viscosity Q1 stiffness on the pressure space, [A_p]_ij =
+    (grad psi_j, grad psi_i) over the whole domain with no boundary condition
+    imposed (the pressure convection-diffusion operator of sec. 5.1 is only
+    multiplied with, never inverted, so its boundary treatment is a reading:
+    natural conditions everywhere)."""
+    _, _, _, wq = _ref_tables()
+    dpsi = _ref_tables_q1()
+    Ape = np.einsum("g,gid,gjd->ij", wq, dpsi, dpsi)   # (2/h)^2 * jac = 1
+    return _assemble(mesh.pconn, mesh.pconn, Ape, mesh.n_p, mesh.n_p)
+
+
+def pressure_convection(mesh: StepMesh, w1: np.ndarray, w2: np.ndarray):
+    """[N_p(w)]_ij = (w . grad psi_j, psi_i) on the Q1 pressure space for a Q2
+    wind (w1, w2) given at all velocity nodes (sec. 5.1, F_p)."""
+    phi, _, psi, wq = _ref_tables()
+    dpsi = _ref_tables_q1()
+    h = mesh.h
+    W1 = w1[mesh.conn] @ phi.T
+    W2 = w2[mesh.conn] @ phi.T
+    Ne = np.einsum("g,eg,gi,gj->eij", wq, W1, psi, dpsi[:, :, 0]) \
+        + np.einsum("g,eg,gi,gj->eij", wq, W2, psi, dpsi[:, :, 1])
+    Ne *= h / 2.0
+    return _assemble(mesh.pconn, mesh.pconn, Ne, mesh.n_p, mesh.n_p)

@@ -159,7 +159,11 @@ def lowrank_fgmres(ops, apply_op, precond, b, tol, eps, maxit, record=None, dead
 # --------------------------------------------------------------------------
 class MeanLSC:
     """Mean-based block-triangular preconditioner (eq. 5.2) with the LSC Schur
-    approximation (eq. 5.19).  Optional hooks replace one piece of it in the
+    approximation (eq. 5.19), or with schur="pcd" the PCD approximation
+    (eq. 5.17): p^ = -X^-1 (F_p,0 + C_p) M_p*^-1 y_p, X = B M*^-1 B^T, with
+    the Q1 pressure-space mass, stiffness and mean convection of sec. 5.1
+    (assembled with natural boundary conditions, a reading: the paper leaves
+    them open, and F_p is only multiplied with).  Optional hooks replace one piece of it in the
     full-tensor forms (apply_full_exact), so that tests can drive this class's
     own block code with pieces whose result is known:
       schur_inv(Yp)     -> S^-1 Yp  in place of the LSC approximation,
@@ -169,8 +173,21 @@ class MeanLSC:
     Tensors are (n_t, n_xi, n) arrays."""
 
     def __init__(self, prob, conv=None, mode="tt", inner_tol=1e-1, inner_eps=1e-3,
-                 inner_maxit=20, eps=1e-6, schur_inv=None, velocity_inv=None, mean_apply=None):
+                 inner_maxit=20, eps=1e-6, schur_inv=None, velocity_inv=None, mean_apply=None,
+                 velocity="inner", schur="lsc"):
         P = self.prob = prob
+        # Schur complement approximation: "lsc" = eq. 5.19, "pcd" = eq. 5.17
+        if schur not in ("lsc", "pcd"):
+            raise ValueError(f"unknown Schur approximation {schur!r}")
+        self.schur = schur
+        # velocity block of eq. 5.2 in the TT form: "inner" = low-rank GMRES
+        # on (F_0 + C) preconditioned by M (eq. 5.22-5.23); "minv" = M^-1 of
+        # eq. 5.23 applied once; "exact" = (F_0 + C)^-1 by time stepping
+        # (systems without convection).  Each result is truncated at inner_eps
+        # except the inner GMRES iterate, which its own loop truncates.
+        if velocity not in ("inner", "minv", "exact"):
+            raise ValueError(f"unknown velocity block {velocity!r}")
+        self.velocity = velocity
         self.hook_schur, self.hook_vel, self.hook_mean = schur_inv, velocity_inv, mean_apply
         self.conv, self.mode = conv, mode
         self.inner_tol, self.inner_eps, self.inner_maxit, self.eps = inner_tol, inner_eps, inner_maxit, eps
@@ -184,6 +201,16 @@ class MeanLSC:
                 Favg = Favg + conv.avg_coef[b] * conv.N_ff[b]
         self.Flu = spla.splu(Favg.tocsc())
         self.inner_iters = []
+        if schur == "pcd":
+            # F_p,0 + C_p = tau^-1 (I - C) (x) I (x) M_p + I (x) I (x) nu_0 A_p + N_p,0
+            # (sec. 5.1, eq. 5.17), M_p* = diag(M_p)
+            from . import mesh as fem
+            self.Mp = P.Mp.tocsr()
+            self.Ap = (P.c[0] * fem.pressure_stiffness(P.mesh)).tocsr()
+            self.Mpstar = P.Mp.diagonal()
+            na = P.mesh.n_all
+            self.Np = [] if conv is None else \
+                [fem.pressure_convection(P.mesh, conv.w3[b, :na], conv.w3[b, na:]).tocsr() for b in range(conv.k2)]
 
     # spatial solves applied along the space mode
     def _Xinv(self, G3):          # G3: (r, n_p)
@@ -212,15 +239,55 @@ class MeanLSC:
         G1, G2, G3 = u
         return np.cumsum(G1, axis=0), G2, self._Finv(G3)
 
+    def _pressure_mean_apply_tt(self, q):
+        """(F_p,0 + C_p) q on the pressure space (eq. 5.17) as an exact TT."""
+        P = self.prob
+        parts = [tt.mode_apply(q, (P.It - P.Ct) / P.tau, None, self.Mp),
+                 tt.mode_apply(q, None, None, self.Ap)]
+        if self.conv is not None:
+            c = self.conv
+            G1, G2, G3 = q
+            r1, n2, r2 = G2.shape
+            O1 = (c.w1[:, :, None] * G1[:, None, :]).reshape(G1.shape[0], c.k1 * r1)
+            Hw = np.einsum("ab,ij->abij", c.w2[:, 0, :], np.eye(n2))
+            O2 = np.einsum("abij,cjd->acibd", Hw, G2).reshape(c.k1 * r1, n2, c.k2 * r2)
+            O3 = np.concatenate([np.asarray(self.Np[b] @ G3.T).T for b in range(c.k2)], axis=0)
+            parts.append((O1, O2, O3))
+        return tt.concat(parts)
+
+    def _pressure_mean_apply_full(self, Q):
+        P = self.prob
+        nt, nx = P.nt, P.n_xi
+        sh = (nt * nx, -1)
+        MQ = np.asarray(self.Mp @ Q.reshape(sh).T).T.reshape(nt, nx, -1)
+        out = MQ.copy()
+        out[1:] -= MQ[:-1]
+        out /= P.tau
+        out += np.asarray(self.Ap @ Q.reshape(sh).T).T.reshape(nt, nx, -1)
+        if self.conv is not None:
+            for b in range(self.conv.k2):
+                Z = np.asarray(self.Np[b] @ Q.reshape(sh).T).T.reshape(nt, nx, -1)
+                out += self.conv.omega[:, b][:, None, None] * Z
+        return out
+
     def apply_tt(self, y):
         yu, yp = y
         P = self.prob
-        t1 = (yp[0], yp[1], self._Xinv(yp[2]))
-        t2 = tt.mode_apply(t1, None, None, self.MsBt)           # velocity space
-        t3 = self._mean_apply_tt(t2)
-        t4 = tt.tt_round(tt.mode_apply(t3, None, None, self.BMs), self.eps)
+        if self.schur == "pcd":
+            # p^ = -X^-1 (F_p,0 + C_p) M_p*^-1 y_p   (eq. 5.17)
+            t1 = (yp[0], yp[1], yp[2] / self.Mpstar[None, :])
+            t4 = tt.tt_round(self._pressure_mean_apply_tt(t1), self.eps)
+        else:
+            t1 = (yp[0], yp[1], self._Xinv(yp[2]))
+            t2 = tt.mode_apply(t1, None, None, self.MsBt)           # velocity space
+            t3 = self._mean_apply_tt(t2)
+            t4 = tt.tt_round(tt.mode_apply(t3, None, None, self.BMs), self.eps)
         ph = (-t4[0], t4[1], self._Xinv(t4[2]))
         rhs = tt.concat([yu, tt.mode_apply(ph, None, None, P.Bt)], [1.0, -1.0])
+        if self.velocity == "minv":
+            return tt.tt_round(self._Minv_tt(rhs), self.inner_eps), ph
+        if self.velocity == "exact":
+            return tt.tt_svd(self.mean_solve_exact_full(tt.full(rhs)), self.inner_eps), ph
         sub = _SingleTT((P.nt, P.n_xi, P.n_u))
         v, its, _, _ = lowrank_fgmres(sub, self._mean_apply_tt, self._Minv_tt, rhs,
                                       self.inner_tol, self.inner_eps, self.inner_maxit)
@@ -269,6 +336,9 @@ class MeanLSC:
         P = self.prob
         nt, nx = P.nt, P.n_xi
         sh = (nt * nx, -1)
+        if self.schur == "pcd":
+            t2 = self._pressure_mean_apply_full(yp / self.Mpstar[None, None, :])
+            return self._Xinv(t2.reshape(sh)).reshape(nt, nx, -1)
         t1 = self._Xinv(yp.reshape(sh))
         t2 = np.asarray(self.MsBt @ t1.T).T.reshape(nt, nx, -1)
         t3 = self.hook_mean(t2) if self.hook_mean is not None else self._mean_apply_full(t2)
@@ -349,14 +419,18 @@ class _FlatOps:
 # driver: one Picard-step linear solve to an exact relative residual
 # --------------------------------------------------------------------------
 def solve_tt(prob, b, conv=None, tol=1e-8, eps_krylov=1e-6, tol_cycle=1e-4, restart=30,
-             max_cycles=8, inner_tol=1e-1, inner_eps=1e-3, inner_maxit=20, record=None, max_seconds=None):
+             max_cycles=8, inner_tol=1e-1, inner_eps=1e-3, inner_maxit=20, record=None, max_seconds=None,
+             velocity="inner", schur="lsc"):
     """Low-rank FGMRES cycles + exact-residual refinement; returns (z, stats),
     z an exact TT sum of the cycle corrections.  max_seconds bounds a timing
-    sample: the outer loop stops once it is exceeded (stats["sampled"])."""
+    sample: the outer loop stops once it is exceeded (stats["sampled"]).
+    velocity and schur select the preconditioner's velocity block and Schur
+    complement approximation (see MeanLSC)."""
     t0 = time.perf_counter()
     deadline = None if max_seconds is None else t0 + max_seconds
     ops = TTOps(prob, conv)
-    prec = MeanLSC(prob, conv, "tt", inner_tol, inner_eps, inner_maxit, eps_krylov)
+    prec = MeanLSC(prob, conv, "tt", inner_tol, inner_eps, inner_maxit, eps_krylov, velocity=velocity,
+                   schur=schur)
     bu_f, bp_f = tt.full(b[0]), tt.full(b[1])
     bnorm = np.sqrt(np.sum(bu_f ** 2) + np.sum(bp_f ** 2))
     terms = []

@@ -47,6 +47,7 @@ class Convection:
         self.Hw = np.einsum("alb,lij->abij", G2, prob.H)
         na = prob.mesh.n_all
         f = prob.mesh.free
+        self.w3 = G3
         self.Nall = [fem.convection(prob.mesh, G3[b, :na], G3[b, na:]) for b in range(self.k2)]
         self.N_ff = [N[f][:, f].tocsr() for N in self.Nall]
         # bold (two-component) free-row restrictions

@@ -119,3 +119,37 @@ def test_convection_orientation_solenoidal_wind():
     assert np.abs(N @ x2 - M @ x1).max() < 1e-13
     # and for v = x1 x2: w . grad v = x2^2 + x1^2
     assert np.abs(N @ (x1 * x2) - M @ (x1 * x1 + x2 * x2)).max() < 1e-13
+
+
+def test_pressure_stiffness_kills_constants_and_integrates_gradients():
+    # Q1 stiffness on the pressure space (sec. 5.1): A_p 1 = 0, and for the Q1
+    # fields x1 and x2, (grad x_k, grad x_k) = area = 25 and the cross term 0
+    m = fem.build_mesh(0.25, 12.0)
+    Ap = fem.pressure_stiffness(m)
+    assert np.abs(Ap @ np.ones(m.n_p)).max() < 1e-13
+    x1, x2 = m.pcoords[:, 0], m.pcoords[:, 1]
+    assert abs(x1 @ Ap @ x1 - 25.0) < 1e-11
+    assert abs(x2 @ Ap @ x2 - 25.0) < 1e-11
+    assert abs(x1 @ Ap @ x2) < 1e-11
+
+
+def test_pressure_convection_orientation_and_skew():
+    # [N_p(w)]_ij = (w . grad psi_j, psi_i): for w = (1, 0) the pressure field
+    # x1 has w . grad x1 = 1, so N_p(w) x1 = M_p 1 on every row (a transposed
+    # N_p fails this); and N_p + N_p^T = boundary terms of the divergence-free
+    # w, zero on rows of nodes off the faces where w . n != 0 (inflow x1 = -1,
+    # outflow x1 = 12 and the step faces x1 = 0, |x2| >= 1/2)
+    m = fem.build_mesh(0.25, 12.0)
+    _, _, _, _, Mp = fem.assemble(m)
+    one = np.ones(m.n_all)
+    Np = fem.pressure_convection(m, one, 0.0 * one)
+    x1 = m.pcoords[:, 0]
+    assert np.abs(Np @ x1 - Mp @ np.ones(m.n_p)).max() < 1e-13
+    S = (Np + Np.T).tocsr()
+    px1, px2 = m.pcoords[:, 0], m.pcoords[:, 1]
+    step_face = (np.abs(px1) < 1e-12) & (np.abs(px2) >= 0.5 - 1e-12)
+    interior = (np.abs(px1 + 1.0) > 1e-12) & (np.abs(px1 - 12.0) > 1e-12) & ~step_face
+    assert np.abs(S[interior].toarray()).max() < 1e-13
+    # a wind (0, 1): w . grad x2 = 1
+    Np2 = fem.pressure_convection(m, 0.0 * one, one)
+    assert np.abs(Np2 @ m.pcoords[:, 1] - Mp @ np.ones(m.n_p)).max() < 1e-13

@@ -289,6 +289,90 @@ def test_exact_mean_solve_inverts_mean_matrix(tiny):
     assert np.linalg.norm(back - Y) <= 1e-12 * np.linalg.norm(Y)
 
 
+def test_minv_inverts_the_mean_based_matrix(tiny):
+    # eq. 5.23: M = (I - C) (x) I (x) F_avg with F_avg = tau^-1 M + nu_0 A +
+    # N(w_avg) on both velocity components; the prefix-sum / spatial-solve
+    # form of M^-1 must invert the explicit Kronecker matrix, with and
+    # without convection (w_avg = time mean of the psi_1 mode of w~)
+    from oracle.solver import MeanLSC
+    P = tiny
+    prior = _prior(P)
+    for conv in (None, P.convection(prior, 1e-12)):
+        Fs = P.M / P.tau + P.cfg["nu0"] * P.A
+        if conv is not None:
+            w_avg = (conv.w1 @ conv.w2[:, 0, :]).mean(axis=0)
+            for b in range(conv.k2):
+                Fs = Fs + w_avg[b] * conv.N_ff[b]
+        Mexp = sp.kron(sp.kron(P.It - P.Ct, sp.identity(P.n_xi)), sp.block_diag([Fs, Fs])).tocsr()
+        prec = MeanLSC(P, conv, "tt", velocity="minv")
+        y = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (3, 4), (1, 1), 9)[0]
+        v = tt.full(prec._Minv_tt(y)).ravel()
+        Y = tt.full(y).ravel()
+        assert np.linalg.norm(Mexp @ v - Y) <= 1e-12 * np.linalg.norm(Y)
+
+
+def test_minv_velocity_block_solves_to_target(tiny):
+    # FGMRES with M^-1 applied once as the velocity block (a varying, inexact
+    # preconditioner is admitted by the flexible method, sec. 4.2) still
+    # reaches the exact solution through the refinement cycles
+    P = tiny
+    b = P.rhs()
+    z, st = solve_tt(P, b, velocity="minv")
+    assert st["rel"][-1] <= 1e-8
+    u, p = P.solve_direct(tt.full(b[0]), tt.full(b[1]))
+    zd = np.concatenate([u.ravel(), p.ravel()])
+    assert np.linalg.norm(tt.pair_full(z) - zd) <= 1e-7 * np.linalg.norm(zd)
+
+
+def test_pcd_pressure_operator_matches_explicit_kron(tiny):
+    # eq. 5.17: F_p,0 + C_p = tau^-1 (I - C) (x) I (x) M_p + I (x) I (x) nu_0 A_p
+    # + sum_b diag(omega_b) (x) I (x) N_p(w3_b), omega_b(t) the psi_1 mode of
+    # the wind's time factor (the mean convection of sec. 5.1); the TT form
+    # of the preconditioner must equal this Kronecker matrix
+    from oracle import mesh as fem
+    from oracle.solver import MeanLSC
+    P = tiny
+    prior = _prior(P)
+    conv = P.convection(prior, 1e-12)
+    prec = MeanLSC(P, conv, "tt", schur="pcd")
+    na = P.mesh.n_all
+    Ap = fem.pressure_stiffness(P.mesh)
+    K = sp.kron(sp.kron((P.It - P.Ct) / P.tau, sp.identity(P.n_xi)), P.Mp) \
+        + sp.kron(sp.identity(P.nt * P.n_xi), P.cfg["nu0"] * Ap)
+    omega = conv.w1 @ conv.w2[:, 0, :]
+    for b in range(conv.k2):
+        Npb = fem.pressure_convection(P.mesh, conv.w3[b, :na], conv.w3[b, na:])
+        K = K + sp.kron(sp.kron(sp.diags(omega[:, b]), sp.identity(P.n_xi)), Npb)
+    q = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (1, 1), (2, 3), 4)[1]
+    got = tt.full(prec._pressure_mean_apply_tt(q)).ravel()
+    want = K @ tt.full(q).ravel()
+    assert np.linalg.norm(got - want) <= 1e-13 * np.linalg.norm(want)
+    # the full-tensor form is the same operator
+    full = prec._pressure_mean_apply_full(tt.full(q)).ravel()
+    assert np.linalg.norm(full - want) <= 1e-13 * np.linalg.norm(want)
+
+
+def test_pcd_preconditioner_tt_equals_full_and_solves(tiny):
+    # the TT form of the PCD preconditioner equals its full-tensor form
+    # (eps -> 0), and FGMRES with it reaches the exact solution
+    from oracle.solver import MeanLSC
+    P = tiny
+    prior = _prior(P)
+    conv = P.convection(prior, 1e-3)
+    y = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 3), (2, 2), 5)
+    tt_prec = MeanLSC(P, conv, "tt", inner_tol=1e-13, inner_eps=1e-14, inner_maxit=60, eps=1e-14, schur="pcd")
+    _, ph_tt = tt_prec.apply_tt(y)
+    full_prec = MeanLSC(P, conv, "full", schur="pcd")
+    ph_full = -full_prec.schur_inv_full(tt.full(y[1]))
+    assert np.linalg.norm(tt.full(ph_tt) - ph_full) <= 1e-10 * np.linalg.norm(ph_full)
+    b = P.rhs(prior)
+    z, st = solve_tt(P, b, conv, schur="pcd")
+    assert st["rel"][-1] <= 1e-8
+    u, p = P.solve_direct(tt.full(b[0]), tt.full(b[1]), conv)
+    zd = np.concatenate([u.ravel(), p.ravel()])
+    assert np.linalg.norm(tt.pair_full(z) - zd) <= 1e-7 * np.linalg.norm(zd)
+
+
 def _psi_multi(idx, xi):
     # orthonormal multivariate Legendre polynomial for U[-1,1]^m (scipy's
     # Legendre evaluation, independent of oracle.gpc)
