@@ -61,7 +61,108 @@ def parse(argv=None):
                     help="M > 0: before the timed solves, one device-to-device copy of M MiB (a plain copy kernel "
                          "of known size for scaling memory counters)")
     ap.add_argument("--progress", action="store_true", help="one line on stderr per solve")
+    ap.add_argument("--system", default="stokes", choices=("stokes", "picard1"),
+                    help="stokes: the first Picard system (w = 0, Alg. 3.1 line 1); picard1: the system of "
+                         "Picard step 1, assembled around the Stokes solution (untimed) as the prior iterate")
+    ap.add_argument("--compare", default="",
+                    help="comma list of solver variants timed after the main measurement with the same steps "
+                         f"(names: {', '.join(sorted(VARIANTS))})")
+    ap.add_argument("--picard", type=int, default=0,
+                    help="N > 0: instead, run Picard's method (Alg. 3.1) for N steps after the Stokes solve and print "
+                         "the per-step record")
+    ap.add_argument("--sweep", default="", choices=("", "paper", "sigma", "nu0", "h", "tau"),
+                    help="instead, run Picard's method with the paper's tolerances (Table 6.2) on the Table 6.1 "
+                         "sizes, varying one parameter (sec. 6.3), and print ranks, storage ratio and times")
     return ap.parse_args(argv)
+
+
+# the paper's stopping and truncation tolerances (Table 6.2, sec. 6.2):
+# inexact Picard with tol_gmres = 1e-1, eps_gmres = 1e-3 for the outer and the
+# inner (preconditioner) solves, eps_soln = 1e-7, eps_conv = 1e-3,
+# tol_picard = 1e-5
+PAPER_TOLERANCES = dict(solve=dict(tol=1e-1, eps_krylov=1e-3, tol_cycle=1e-1, inner_tol=1e-1, inner_eps=1e-3,
+                                   max_cycles=4, restart=30, relax=0, outer_explicit=1, inner_mode=0),
+                        eps_soln=1e-7, eps_conv=1e-3, eps_rhs=1e-3, tol_picard=1e-5, max_steps=10)
+
+# one-parameter variations of the Table 6.1 problem (sec. 6.3, Figs. 6.5-6.6);
+# sigma is this build's relative viscosity amplitude nu_coef, h keeps the
+# domain, tau keeps t_f = 1
+SWEEPS = {
+    "paper": [{}],
+    "sigma": [dict(nu_coef=v) for v in (0.01, 0.03, 0.1)],
+    "nu0": [dict(nu0=v) for v in (1 / 25, 1 / 50, 1 / 100)],
+    "h": [dict(h=v) for v in (1 / 4, 1 / 8, 1 / 16)],
+    "tau": [dict(tau=1 / n, nt=n) for n in (32, 64, 128)],
+}
+
+
+def storage_ratio(nt, nxi, n, ranks):
+    """eq. 6.6: entries of a TT with ranks (k1, k2) over those of the full tensor."""
+    k1, k2 = ranks
+    return (nt * k1 + nxi * k1 * k2 + n * k2) / (nt * nxi * n)
+
+
+def sweep_main(args):
+    from paper_1906_06785_amd import sgtt
+    from synthetic_inputs import CONFIGS
+
+    ctx = sgtt.Context(0)
+    tol = PAPER_TOLERANCES
+    runs = []
+    for over in SWEEPS[args.sweep]:
+        cfg = dict(CONFIGS["paper"], **over)
+        hp = sgtt.HostProblem(cfg)
+        t0 = time.perf_counter()
+        x, st, rc = sgtt.picard(ctx, cfg, steps=tol["max_steps"], tol_picard=tol["tol_picard"],
+                                eps_soln=tol["eps_soln"], eps_conv=tol["eps_conv"], eps_rhs=tol["eps_rhs"],
+                                caps=OUT_CAPS, **tol["solve"])
+        el = time.perf_counter() - t0
+        ru, rp = x.ranks
+        runs.append({"params": over, "n_t": hp.nt, "n_xi": hp.n_xi, "n_u": hp.n_u, "n_p": hp.n_p, "status": rc,
+                     "picard_steps": st["steps"], "nonlinear_residual": st["nonlinear_residual"],
+                     "gmres_iters": st["outer_iters"], "inner_iters": st["inner_iters"],
+                     "rank_u": ru, "rank_p": rp,
+                     "storage_ratio_u": storage_ratio(hp.nt, hp.n_xi, hp.n_u, ru),
+                     "storage_ratio_p": storage_ratio(hp.nt, hp.n_xi, hp.n_p, rp),
+                     "seconds": el, "solve_seconds": st["solve_seconds"]})
+        print(f"[sweep] {args.sweep} {over}: {st['steps']} Picard steps, ranks u {ru} p {rp}, {el:.1f} s",
+              file=sys.stderr, flush=True)
+    print(json.dumps({"metric": f"Picard's method with the paper's tolerances, {args.sweep} sweep",
+                      "config": {"workload": "Table 6.1 sizes (h=1/4, m=3, degree 3, t_f=1, tau=1/64, nu0=1/50) "
+                                             "with this build's viscosity law; one parameter varied",
+                                 "tolerances": tol},
+                      "runs": runs}), flush=True)
+
+
+# solver variants that --compare can time next to the main configuration:
+# option overrides of solve_options
+VARIANTS = {
+    "exact_mean": dict(inner_mode=1),
+    "minv": dict(inner_mode=2),
+    "inner_gmres": dict(inner_mode=0),
+    "inner_gmres_f32": dict(inner_mode=0, precision=1),
+    "inner_gmres_bf16": dict(inner_mode=0, precision=2),
+    "pcd": dict(schur=1),
+}
+
+VELOCITY_BLOCK = {0: "inner low-rank GMRES on (F_0 + C) preconditioned by M (eq. 5.22-5.23)",
+                  1: "time-stepped mean solve (F_0 + C)^-1 on the full velocity tensor, then TT-SVD",
+                  2: "M^-1 of eq. 5.23 applied once (prefix sum in time, one F_avg solve on core 3)"}
+PRECISION = {0: "f64", 1: "f64 (inner-solve products f32 on MFMA, f32 accumulate)",
+             2: "f64 (inner-solve products bf16 on MFMA, f32 accumulate)"}
+
+
+def workload_name(cfg, system):
+    """Workload label from the configuration's own sizes."""
+    grid = f"{round(4 / cfg['h'])}x{round(12 / cfg['h'])}"
+    what = "Stokes (w = 0) Picard-step system" if system == "stokes" else \
+        "Picard step-1 system (prior iterate = the Stokes solution)"
+    return (f"{what}, {grid} grid (h=1/{round(1 / cfg['h'])}), m={cfg['m']}, p={cfg['p']}, nt={cfg['nt']}, "
+            f"tau={cfg['tau']:g}, nu0={cfg['nu0']:g}, tol 1e-8, Krylov TT eps 1e-6")
+
+
+def dtype_name(opts):
+    return PRECISION[opts["precision"]] if opts["inner_mode"] == 0 else "f64"
 
 
 def solve_options(args=None):
@@ -84,18 +185,27 @@ TRAFFIC_RECORD = {"kernel_src_sha256": "12eb2c4c70deb575f017698bb4d7b98b56ab3dc6
 
 def bcr_source_digest():
     """Digest of what the pass traffic depends on: the block cyclic reduction
-    section of kernels.hip (the pass kernels) and the host factorization
-    (bcr_factor in host_setup.cpp: block sizes, levels, dropped zeros)."""
+    pass kernels (their section of kernels.hip), the host side that launches
+    them (variant table, XCD grid padding, tuning and the choice of a variant
+    per pass, from struct BcrVariant to bcr_solve_variant), the device
+    layout of a factor (upload_bcr and factor_bcr in solver.hip: fragment
+    order, descriptors, padding) and the host factorization (bcr_factor in
+    host_setup.cpp: block sizes, levels, dropped zeros)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1906_06785_amd", "csrc")
     src = open(os.path.join(csrc, "kernels.hip")).read()
     head = "// " + "-" * 66 + " block cyclic reduction"
     i0 = src.index(head)
     i1 = src.index("// " + "-" * 66, i0 + len(head))
+    k0 = src.index("struct BcrVariant {")
+    k1 = src.index("\n}\n", src.index("void bcr_solve_variant(")) + 3
+    sol = open(os.path.join(csrc, "solver.hip")).read()
+    s0 = sol.index("BcrDev upload_bcr(")
+    s1 = sol.index("\n}\n", sol.index("BcrDev factor_bcr(")) + 3
     host = open(os.path.join(csrc, "host_setup.cpp")).read()
     j0 = host.index("void bcr_factor(")
     j1 = host.index("void bcr_apply_host(")
-    return hashlib.sha256((src[i0:i1] + host[j0:j1]).encode()).hexdigest()
+    return hashlib.sha256((src[i0:i1] + src[k0:k1] + sol[s0:s1] + host[j0:j1]).encode()).hexdigest()
 
 
 def recorded_traffic(dom_name):
@@ -112,31 +222,55 @@ KERNEL_LABELS = {
              "its passes)",
 }
 
-OUT_CAPS = (128, 4096)   # output TT capacity (core-1 rank, core-2 rank) of the solution
+OUT_CAPS = (512, 8192)   # output TT capacity (core-1 rank, core-2 rank) of the solution: the exact sum of the
+#                          refinement cycles' corrections, whose ranks add
+BATCH_CAPS = (128, 2048)  # per problem of a batch (many problems share the GPU's memory)
 
 
-def cpu_baseline(cfg, budget, gpu_outer_per_solve):
+ORACLE_VELOCITY = {0: "inner", 1: "exact", 2: "minv"}
+
+
+def cpu_baseline(cfg, budget, gpu_outer_per_solve, inner_mode=1, system=None):
+    """The oracle's low-rank FGMRES (oracle.solver.solve_tt, numpy/scipy FP64)
+    on the same system with the same velocity block of the preconditioner as
+    the GPU line, timed for a bounded number of outer iterations (until the
+    budget is spent), all BLAS threads and then one thread; solves/s scaled
+    by the GPU's outer-iteration count."""
     import numpy as np  # noqa: F401
     from oracle.solver import solve_tt
     from oracle.system import Problem
+    if system is not None:
+        raise ValueError("the CPU baseline covers the Stokes system (the Picard step-1 system needs the prior "
+                         "iterate on the host)")
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count() or 1
     P = Problem(cfg)
     b = P.rhs()
-    t0 = time.perf_counter()
-    _, st = solve_tt(P, b, max_seconds=budget)
-    dt = time.perf_counter() - t0
-    outer = max(st["outer"], 1)
-    per_iter = dt / outer
-    per_solve = per_iter * max(gpu_outer_per_solve, 1)
-    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": (f"first {st['outer']} outer low-rank FGMRES iteration(s) of the same {cfg_name(cfg)} solve "
-                       f"({dt:.1f} s, numpy/scipy FP64), scaled to the GPU's {gpu_outer_per_solve} outer "
-                       f"iterations per solve; host cpu_count={os.cpu_count()}, "
-                       f"affinity={len(os.sched_getaffinity(0))}")}
+    velocity = ORACLE_VELOCITY[inner_mode]
+
+    def sample():
+        t0 = time.perf_counter()
+        _, st = solve_tt(P, b, max_seconds=budget, velocity=velocity)
+        dt = time.perf_counter() - t0
+        return dt, max(st["outer"], 1)
+
+    dt, outer = sample()
+    per_solve = dt / outer * max(gpu_outer_per_solve, 1)
+    res = {"value": 1.0 / per_solve, "unit": "solves/s", "cores": threads, "kind": "oracle",
+           "sample": (f"first {outer} outer low-rank FGMRES iteration(s) of the same {cfg_name(cfg)} Stokes solve "
+                      f"with the same preconditioner velocity block ({velocity}), {dt:.1f} s with {threads} BLAS "
+                      f"threads (numpy/scipy FP64), scaled to the GPU's {gpu_outer_per_solve} outer iterations "
+                      f"per solve; host cpu_count={os.cpu_count()}, affinity={len(os.sched_getaffinity(0))}")}
+    if threadpool_limits is not None and threads > 1:
+        with threadpool_limits(limits=1):
+            dt1, outer1 = sample()
+        res["single_thread_value"] = 1.0 / (dt1 / outer1 * max(gpu_outer_per_solve, 1))
+        res["sample"] += f"; one BLAS thread: {outer1} iteration(s) in {dt1:.1f} s"
+    return res
 
 
 def cfg_name(cfg):
@@ -155,7 +289,7 @@ def batch_main(args):
     ctxs = [sgtt.Context(0) for _ in range(K)]
     systems = [sgtt.System(ctxs[i % K], c) for i, c in enumerate(cfgs)]
     bs = [S.rhs() for S in systems]
-    xs = [S.pair(*OUT_CAPS) for S in systems]
+    xs = [S.pair(*BATCH_CAPS) for S in systems]
     opts = solve_options(args)
     for _ in range(args.warmup):
         sgtt.solve_batched(systems, bs, xs, **opts)
@@ -178,15 +312,101 @@ def batch_main(args):
                   "outer_iters": [s["outer_iters"] for s in stats]}}), flush=True)
 
 
+# kernel classes reported against their rooflines, with what they stand for
+ROOFLINE_CLASSES = {
+    "k_spmm": "CSR sparse products of the operator (k_spmm, k_spmm_short<32>)",
+    "k_ell_spmm": "ELL mass product of the time-stepped mean solve (k_ell_spmm<32>)",
+    "k_gram": "tall-skinny core-3 Gram products of truncations and inner products (k_gemm<0, 1>)",
+    "k_proj": "projections of core 3 onto the kept ranks (k_gemm<0, 2>)",
+    "k_gemm": "other FP64 products: full-tensor expansion, small core products (k_gemm<0, 0>)",
+    "k_bcr": "block cyclic reduction passes",
+}
+
+
+def class_rooflines(classes):
+    out = {}
+    for name, what in ROOFLINE_CLASSES.items():
+        v = classes.get(name)
+        if not v or not v["launches"] or v["seconds"] <= 0:
+            continue
+        by, fl, sec, nl = v["bytes"], v["flops"], v["seconds"], v["launches"]
+        hbm = by > 0 and fl / by < PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+        ach = by / sec / 1e9 if hbm else fl / sec / 1e12
+        peak = PEAK_HBM_GBS if hbm else PEAK_FP64_TFLOPS
+        out[name] = {"bound": "hbm" if hbm else "mfma", "achieved": ach, "peak": peak,
+                     "unit": "GB/s" if hbm else "TFLOP/s", "frac": ach / peak, "launches": nl,
+                     "avg_launch_us": sec / nl * 1e6, "algorithmic_bytes_per_launch": by / nl,
+                     "algorithmic_flops_per_launch": fl / nl, "kernels": what}
+    return out
+
+
+def build_system(sgtt, ctx, cfg, system, opts, progress):
+    """The timed system and its right-hand side; for picard1 the Stokes
+    system is solved first (untimed) and its solution is the prior iterate
+    (Alg. 3.1: u^(0) from the Stokes solve, then the residual equation
+    eq. 3.14 around it)."""
+    S = sgtt.System(ctx, cfg)
+    b = S.rhs()
+    if system == "stokes":
+        return S, b, None
+    x0 = S.pair(*OUT_CAPS)
+    _, st0, _ = S.solve(b, x0, **opts)
+    progress("Stokes solve for the prior iterate")
+    S1 = sgtt.System(ctx, cfg, prior=x0, eps_conv=1e-3, eps_rhs=1e-6)
+    b1 = S1.rhs(S1.pair(128, 1024))
+    info = {"prior_ranks": x0.ranks, "prior_rel_residual": st0["rel_residual"],
+            "convection_ranks": (S1.info.conv_r1, S1.info.conv_r2),
+            "rhs_ranks": b1.ranks, "rhs_norm_over_f": S1.info.rhs_norm / S.info.rhs_norm}
+    return S1, b1, info
+
+
+def time_solves(S, b, out, opts, steps, progress, stream):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(steps):
+        _, st, rc = S.solve(b, out, **opts)
+        stats.append(st)
+        progress("timed solve")
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, stats
+
+
+def picard_main(args):
+    """Picard's method on the device: Stokes solve, then args.picard steps
+    (Alg. 3.1 with eq. 4.8); one JSON line with the per-step record."""
+    from paper_1906_06785_amd import sgtt
+    from synthetic_inputs import CONFIGS
+
+    cfg = CONFIGS[args.config]
+    ctx = sgtt.Context(0)
+    opts = solve_options(args)
+    x, st, rc = sgtt.picard(ctx, cfg, steps=args.picard, tol_picard=1e-12, eps_soln=1e-10, eps_conv=1e-3,
+                            eps_rhs=1e-6, caps=OUT_CAPS, **opts)
+    print(json.dumps({"metric": "Picard's method (Alg. 3.1) on the device: per-step record",
+                      "config": {"workload": workload_name(cfg, "stokes").replace(
+                          "Stokes (w = 0) Picard-step system", f"Stokes solve + {args.picard} Picard steps"),
+                                 "eps_conv": 1e-3, "eps_rhs": 1e-6, "eps_soln": 1e-10,
+                                 "preconditioner_velocity_block": VELOCITY_BLOCK[opts["inner_mode"]]},
+                      "status": rc, "picard": st}), flush=True)
+
+
 def main():
     args = parse()
-    if args.batch > 0 and args.gpus == 1:
-        batch_main(args)
-        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                           "(independent Picard systems would shard one per GPU with no communication)"}))
         sys.exit(2)
+    if args.batch > 0:
+        batch_main(args)
+        return
+    if args.picard > 0:
+        picard_main(args)
+        return
+    if args.sweep:
+        sweep_main(args)
+        return
     import torch
 
     from paper_1906_06785_amd import sgtt
@@ -196,15 +416,16 @@ def main():
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     ctx = sgtt.Context(0, use_torch_stream=True)
-    t_setup = time.perf_counter()
-    S = sgtt.System(ctx, cfg)
-    b = S.rhs()
-    setup_s = time.perf_counter() - t_setup
     opts = solve_options(args)
-    out = S.pair(*OUT_CAPS)
+    t_setup = time.perf_counter()
+
     def progress(what):
         if args.progress:
             print(f"[bench] {what} done at {time.perf_counter() - t_setup:.1f} s", file=sys.stderr, flush=True)
+
+    S, b, sys_info = build_system(sgtt, ctx, cfg, args.system, opts, progress)
+    setup_s = time.perf_counter() - t_setup
+    out = S.pair(*OUT_CAPS)
 
     for _ in range(args.warmup):
         S.solve(b, out, **opts)
@@ -231,22 +452,15 @@ def main():
         del src, dst
     # timed region: events on the dominant class only
     ctx.profile(True, classes=[dom_name])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     ev0.record(stream)
-    stats = []
-    for _ in range(args.steps):
-        _, st, rc = S.solve(b, out, **opts)
-        stats.append(st)
-        progress("timed solve")
+    elapsed, stats = time_solves(S, b, out, opts, args.steps, progress, stream)
     ev1.record(stream)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     prof = ctx.profile_read()
     ctx.profile(False)
-    elapsed = t1 - t0
     ev_s = ev0.elapsed_time(ev1) * 1e-3
     dom = prof[dom_name]
     by, fl, sec, nl = dom["bytes"], dom["flops"], dom["seconds"], dom["launches"]
@@ -262,9 +476,27 @@ def main():
                  "avg_launch_us": sec / max(nl, 1) * 1e6,
                  "algorithmic_bytes_per_launch": by / max(nl, 1), "algorithmic_flops_per_launch": fl / max(nl, 1),
                  "share_of_timed_region": sec / ev_s if ev_s > 0 else None,
-                 "traffic": recorded_traffic(dom_name)})
+                 "traffic": recorded_traffic(dom_name) if args.system == "stokes" and args.config == "C2" else None})
     outer = int(round(sum(s["outer_iters"] for s in stats) / len(stats)))
     worst = max(s["rel_residual"] for s in stats)
+    # the metric compares learned/mixed-precision solves with the plain FP64
+    # one at equal accuracy: value is the plain FP64 solver; variants named
+    # with --compare are timed the same way and reported beside it
+    comparison = {}
+    for name in [v for v in args.compare.split(",") if v]:
+        vopts = dict(opts, **VARIANTS[name])
+        vout = S.pair(*OUT_CAPS)
+        S.solve(b, vout, **vopts)   # warm-up (tuning of the spatial solves for new column counts)
+        progress(f"warm-up solve of {name}")
+        v_el, v_stats = time_solves(S, b, vout, vopts, args.steps, progress, stream)
+        v_worst = max(s["rel_residual"] for s in v_stats)
+        comparison[name] = {
+            "solves_per_s": args.steps / v_el, "ms_per_step": v_el / args.steps * 1e3,
+            "speedup_vs_value": (args.steps / v_el) / (args.steps / elapsed), "dtype": dtype_name(vopts),
+            "preconditioner_velocity_block": VELOCITY_BLOCK[vopts["inner_mode"]],
+            "outer_iters": int(round(sum(s["outer_iters"] for s in v_stats) / len(v_stats))),
+            "inner_iters": v_stats[-1]["inner_iters"], "max_rel_residual": v_worst, "converged": v_worst <= 1e-8,
+            "max_krylov_rank_u": v_stats[-1]["max_rank_krylov_u"]}
     res = {
         "metric": "Picard-step solve time to 1e-8 rel. residual: learned/mixed vs plain FP64",
         "value": args.steps / elapsed,
@@ -276,29 +508,35 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": dtype_name(opts),
         "data": "synthetic (step-domain flow generated by the library's own mesh/assembly; no dataset)",
-        "config": {"workload": f"{args.config} Stokes Picard-step system, 64x192 grid (h=1/16), m=4, p=3 (n_xi=35), "
-                               f"nt=128, tau=0.05, plain FP64, tol 1e-8, TT eps 1e-6",
-                   "unknowns": int(128 * 35 * (S.nu + S.np)) if args.config == "C2" else None,
+        "config": {"workload": workload_name(cfg, args.system),
+                   "unknowns": int(S.nt * S.nxi * (S.nu + S.np)),
                    "solver": ("Alg. 4.2 (explicit residual each outer iteration)" if args.outer_explicit
                               else "Alg. 4.2 cycles stopped on the least-squares estimate"),
                    "restart": args.restart, "relaxed_truncation": bool(args.relax),
-                   "preconditioner_velocity_block": ("time-stepped mean solve (full tensor)" if args.inner_mode == 1
-                                                     else "inner low-rank GMRES with M")},
+                   "preconditioner_velocity_block": VELOCITY_BLOCK[opts["inner_mode"]],
+                   "system": sys_info},
         "solve": {"outer_iters": outer, "cycles": stats[-1]["cycles"], "inner_iters": stats[-1]["inner_iters"],
                   "max_rel_residual": worst, "converged": worst <= 1e-8,
                   "max_krylov_rank_u": stats[-1]["max_rank_krylov_u"], "setup_s": setup_s},
         "roofline": roof,
+        "learned_mixed": (comparison if comparison else
+                          {"measured": False, "reason": "no variant named with --compare; value is the plain "
+                                                        "FP64 solver"}),
         # per-class and per-phase event times of one profiled solve after the
         # warm-up (every class evented, so it runs slower than a timed step)
         "kernels": {k: {"ms": v["seconds"] * 1e3, "launches": v["launches"]} for k, v in breakdown.items()
                     if v["launches"]},
+        # the same solve's kernel classes against their rooflines: algorithmic
+        # bytes (flops above the ridge) per launch over the event-timed launch
+        "rooflines": class_rooflines(breakdown),
         "phases_ms": {r: {k: round(v * 1e3, 1) for k, v in row.items()} for r, row in phases.items()},
     }
     if not args.no_cpu_baseline:
         try:
-            res["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, outer)
+            res["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, outer, opts["inner_mode"],
+                                               None if args.system == "stokes" else "picard1")
         except Exception as e:  # the baseline is informative only
             res["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(res), flush=True)

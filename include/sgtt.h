@@ -127,7 +127,16 @@ typedef struct {
                                  TT-SVD at inner_eps: (F_0 + C)^-1 exactly
                                  without convection; with convection the
                                  time-averaged convection of F_avg stands
-                                 for N_0 (an approximation, as is M)       */
+                                 for N_0 (an approximation, as is M);
+                              2: M^-1 of eq. 5.23 applied once in place of
+                                 the inner solve (prefix sum in time on
+                                 core 1, one F_avg solve of the core-3
+                                 columns), then truncation at inner_eps   */
+  int schur;               /* Schur complement approximation of the
+                              preconditioner: 0 mean-based LSC (eq. 5.19);
+                              1 mean-based PCD (eq. 5.17) with the Q1
+                              pressure-space mass, stiffness and mean
+                              convection (natural boundary conditions)    */
 } sgtt_solve_opts;
 
 typedef struct {
@@ -404,7 +413,10 @@ int sgtt_host_problem_destroy(sgtt_host_problem* hp);
 int sgtt_host_sizes(const sgtt_host_problem* hp, int* sizes);
 /* CSR export.  which: 0 = M (free x free), 1 = A unit viscosity (free x free),
  * 2 = B (n_p x n_u), 3 = B M*^-1 B^T (n_p x n_p), 4 = B M*^-1 M M*^-1 B^T,
- * 5 = B M*^-1 A M*^-1 B^T.  Call with NULL arrays to get nrows/ncols/nnz. */
+ * 5 = B M*^-1 A M*^-1 B^T, 6 = Q1 pressure mass M_p (n_p x n_p), 7 = Q1
+ * pressure stiffness A_p, unit viscosity, natural boundary conditions (the
+ * pressure-space matrices of eq. 5.17).  Call with NULL arrays to get
+ * nrows/ncols/nnz. */
 int sgtt_host_csr(const sgtt_host_problem* hp, int which, int* nrows, int* ncols, int* nnz,
                   int* rowptr, int* col, double* val);
 /* chaos: which 0 = G (m+1 x n_xi x n_xi), 1 = H (n_xi^3), 2 = G_nu (n_xi^2) */

@@ -26,6 +26,8 @@ struct RefTables {
   double dxi[9][9];     // d/dxi
   double deta[9][9];    // d/deta
   double psi[9][4];     // Q1, k = a + 2 b
+  double pdxi[9][4];    // Q1 d/dxi
+  double pdeta[9][4];   // Q1 d/deta
 };
 
 RefTables make_ref() {
@@ -50,7 +52,11 @@ RefTables make_ref() {
           t.deta[g][k] = q2(xi, a) * dq2(eta, b);
         }
       for (int b = 0; b < 2; ++b)
-        for (int a = 0; a < 2; ++a) t.psi[g][a + 2 * b] = q1(xi, a) * q1(eta, b);
+        for (int a = 0; a < 2; ++a) {
+          t.psi[g][a + 2 * b] = q1(xi, a) * q1(eta, b);
+          t.pdxi[g][a + 2 * b] = (a == 0 ? -0.5 : 0.5) * q1(eta, b);
+          t.pdeta[g][a + 2 * b] = q1(xi, a) * (b == 0 ? -0.5 : 0.5);
+        }
     }
   return t;
 }
@@ -438,6 +444,38 @@ void build_problem(const ProblemParams& prm, HostProblem& hp) {
     lsc_middle_values(hp, hp.Mff.data(), hp.XM.data());
     lsc_middle_values(hp, hp.Aff.data(), hp.XA.data());
   }
+  // Q1 pressure-space matrices of the PCD approximation (sec. 5.1, eq. 5.17):
+  // mass M_p and unit-viscosity stiffness A_p on the Q1 pattern, no boundary
+  // condition imposed
+  {
+    std::vector<std::vector<int>> rq(np);
+    for (size_t e = 0; e < m.pconn.size(); ++e)
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) rq[m.pconn[e][i]].push_back(m.pconn[e][j]);
+    finalize_pattern(rq, np, hp.Qp);
+    double Mpe[4][4], Ape[4][4];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        double sm = 0, sa = 0;
+        for (int g = 0; g < 9; ++g) {
+          sm += R.w[g] * R.psi[g][i] * R.psi[g][j];
+          sa += R.w[g] * (R.pdxi[g][i] * R.pdxi[g][j] + R.pdeta[g][i] * R.pdeta[g][j]);
+        }
+        Mpe[i][j] = sm * jac;
+        Ape[i][j] = sa;   // (2/h)^2 * jac = 1
+      }
+    hp.Mp.assign(hp.Qp.nnz(), 0.0);
+    hp.Ap.assign(hp.Qp.nnz(), 0.0);
+    for (size_t e = 0; e < m.pconn.size(); ++e)
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          const int t = find_pos(hp.Qp, m.pconn[e][i], m.pconn[e][j]);
+          hp.Mp[t] += Mpe[i][j];
+          hp.Ap[t] += Ape[i][j];
+        }
+    hp.Mpstar.assign(np, 0.0);
+    for (int k = 0; k < np; ++k) hp.Mpstar[k] = hp.Mp[find_pos(hp.Qp, k, k)];
+  }
   // slab partitions: velocity node column I -> slab floor(I/2); pressure
   // vertex column I -> slab floor(I/4).  Both orderings are sorted by I first.
   {
@@ -522,6 +560,32 @@ void convection_values(const HostProblem& hp, const double* w1, const double* w2
         if (fj >= 0) vff[find_pos(hp.Kff, fi, fj)] += s;
       }
     }
+  }
+}
+
+void pressure_convection_values(const HostProblem& hp, const double* w1, const double* w2, double* out) {
+  const Mesh& m = hp.mesh;
+  const RefTables& R = ref();
+  const double hh = 0.5 * hp.prm.h;   // jac * (2/h)
+  std::fill(out, out + hp.Qp.nnz(), 0.0);
+  for (size_t e = 0; e < m.conn.size(); ++e) {
+    const auto& c = m.conn[e];
+    double W1[9], W2[9];
+    for (int g = 0; g < 9; ++g) {
+      double a = 0, b = 0;
+      for (int k = 0; k < 9; ++k) {
+        a += w1[c[k]] * R.phi[g][k];
+        b += w2[c[k]] * R.phi[g][k];
+      }
+      W1[g] = a;
+      W2[g] = b;
+    }
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        double v = 0;
+        for (int g = 0; g < 9; ++g) v += R.w[g] * (W1[g] * R.pdxi[g][j] + W2[g] * R.pdeta[g][j]) * R.psi[g][i];
+        out[find_pos(hp.Qp, m.pconn[e][i], m.pconn[e][j])] += v * hh;
+      }
   }
 }
 

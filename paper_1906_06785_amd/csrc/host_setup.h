@@ -74,6 +74,11 @@ struct HostProblem {
   Csr Xp;                             // pattern + values of X
   Csr Xmid;                           // pattern for B M*^-1 S M*^-1 B^T (S = M, A, N)
   std::vector<double> XM, XA;         // values on Xmid for S = M, S = A (unit)
+  // Q1 pressure-space matrices of the PCD approximation (eq. 5.17): pattern,
+  // mass M_p, unit-viscosity stiffness A_p (natural boundary conditions) and
+  // diag(M_p)
+  Csr Qp;
+  std::vector<double> Mp, Ap, Mpstar;
   // slab partitions (block-tridiagonal orderings) of free velocity nodes and
   // pressure nodes
   std::vector<int> vel_blocks, p_blocks;
@@ -87,6 +92,10 @@ void build_problem(const ProblemParams& prm, HostProblem& hp);
 // vals_fa != nullptr, on Kfa (free x all).
 void convection_values(const HostProblem& hp, const double* w1, const double* w2,
                        double* vals_ff, double* vals_fa);
+
+// Q1 pressure-space convection values [N_p(w)]_kl = (w . grad psi_l, psi_k)
+// on Qp for a Q2 wind given at all velocity nodes (sec. 5.1, F_p).
+void pressure_convection_values(const HostProblem& hp, const double* w1, const double* w2, double* out);
 
 // Q2 reference-element tables on the 3 x 3 Gauss points (the ones every
 // assembly here uses): out[0..8] weights, then phi, d/dxi, d/deta as [g][k]

@@ -17,9 +17,20 @@ namespace sgtt {
 // algorithmic bytes / flops of each launch (what the operation must move and
 // compute, not what the hardware counted).  Kernel classes:
 enum KernelClass {
-  KC_GEMM = 0, KC_GEMM_PTR, KC_SPMM, KC_BCR, KC_TRUNC, KC_REDUCE, KC_OTHER, KC_GEMM_LOWP, KC_COUNT
+  KC_GEMM = 0, KC_GEMM_PTR, KC_SPMM, KC_BCR, KC_TRUNC, KC_REDUCE, KC_OTHER, KC_GEMM_LOWP,
+  KC_GRAM,   // tall-skinny Gram products (truncations, inner products): k_gemm<0, 1>
+  KC_ELL,    // the ELL mass product of the time-stepped mean solve: k_ell_spmm<32>
+  KC_PROJ,   // projections of core 3 onto kept ranks (truncations): k_gemm<0, 2>
+  KC_COUNT
 };
 const char* kernel_class_name(int cls);
+// what a gemm() call computes, for the profiler's classes and the kernel's name
+enum GemmTag { GEMM_PLAIN = 0, GEMM_GRAM = 1, GEMM_PROJ = 2 };
+struct GemmTagScope {
+  int old;
+  explicit GemmTagScope(int tag);
+  ~GemmTagScope();
+};
 void prof_enable(bool on);
 void prof_enable_mask(unsigned class_mask);   // bit c records class c; 0 = off
 unsigned prof_mask();                          // classes recorded now (0 when off)
@@ -81,6 +92,16 @@ void gemm_batched(hipStream_t s, int nb, const GemmDesc* d_desc, int max_m, int 
 // ws: scratch of ws_doubles doubles for split-K partial sums.
 void gram(hipStream_t s, long rows, int nx, int ny, const double* X, long sXr, long sXc,
           const double* Y, long sYr, long sYc, double* out, double* ws, size_t ws_doubles);
+// Scratch that gram() can use for its partial sums: nx ny doubles per row
+// chunk of at least 128 rows, with at most 1024 output tiles of 64 x 64 in
+// flight (a larger scratch is never touched).
+inline size_t gram_ws_doubles(long rows, int nx, int ny) {
+  const long tiles = (long)((nx + 63) / 64) * ((ny + 63) / 64);
+  long nch = rows / 128;
+  if (nch > 1024 / tiles) nch = 1024 / tiles;
+  if (nch < 1) nch = 1;
+  return (size_t)nx * ny * nch;
+}
 
 // Sum of squares of n doubles into *out (single value, device) -- deterministic.
 void sumsq(hipStream_t s, const double* x, long n, double* out, double* ws, size_t ws_doubles);

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -78,7 +80,7 @@ struct ProfScope {
 
 const char* kernel_class_name(int cls) {
   static const char* names[] = {"k_gemm", "k_gemm_ptr", "k_spmm", "k_bcr", "k_trunc_eig",
-                                "k_reduce_partials", "other", "k_gemm_lowp"};
+                                "k_reduce_partials", "other", "k_gemm_lowp", "k_gram", "k_ell_spmm", "k_proj"};
   return (cls >= 0 && cls < KC_COUNT) ? names[cls] : "?";
 }
 const char* region_name(int r) {
@@ -292,7 +294,11 @@ __device__ __forceinline__ void gemm_core(int m, int n, long kb, double alpha, c
     }
 }
 
-template <int PREC>
+// TAG only names the instantiation (GEMM_GRAM for the tall-skinny Gram
+// products of truncations and inner products, GEMM_PROJ for the projections
+// of core 3 onto the kept ranks), so that a kernel trace tells them apart
+// from the other products.
+template <int PREC, int TAG = 0>
 __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, double alpha, const double* __restrict__ A,
                                               long sAb, long sAi, long sAk, const double* __restrict__ B, long sBb,
                                               long sBk, long sBj, double beta, double* __restrict__ C, long sCb,
@@ -1533,21 +1539,24 @@ __device__ __forceinline__ void bcr_split_load(const BcrOpDesc& d, int t, const 
 // padding of the fragment); k-steps past a term's end, and the last term
 // loaded again where the last round of terms runs short, are multiplied by
 // an exact zero.
-template <int CB, int KQ, int TP>
-__global__ __launch_bounds__(256) void k_bcr_split(const BcrOpDesc* __restrict__ ops, int op0, int nops,
-                                                   const double* __restrict__ data, double* __restrict__ B, long ldb,
-                                                   double* __restrict__ X, long ldx, int ncols, int ncomp,
-                                                   long comp_rows) {
+template <int CB, int KQ, int TP, int TG>
+__global__ __launch_bounds__(256 * TG) void k_bcr_split(const BcrOpDesc* __restrict__ ops, int op0, int nops,
+                                                        const double* __restrict__ data, double* __restrict__ B,
+                                                        long ldb, double* __restrict__ X, long ldx, int ncols,
+                                                        int ncomp, long comp_rows) {
   constexpr int NCT = CB / 16;
   static_assert(CB % 16 == 0, "column tiles of 16");
-  __shared__ double red[4][NCT * 256];
+  __shared__ double red[4 * TG][NCT * 256];
   if ((int)blockIdx.x >= nops) return;   // grid padding (uniform per workgroup)
   const BcrOpDesc& d = ops[op0 + blockIdx.x];
   const int rt = blockIdx.z;
   const int r0 = d.r0, bo = d.bo;
   if (rt * 16 >= bo) return;   // uniform per workgroup
   const int j0 = blockIdx.y * CB;
+  // wave w belongs to term group w / 4 and owns k-steps w % 4, w % 4 + 4, ...
+  // of that group's terms
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int grp = wave / 4, wq = wave % 4;
   const int lr = lane % 16, lk = lane / 16;
   const int ctot = ncomp * ncols;
   // this lane's B-operand columns, clamped to a valid one
@@ -1565,10 +1574,11 @@ __global__ __launch_bounds__(256) void k_bcr_split(const BcrOpDesc* __restrict__
   dbl4 acc[NCT];
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct) acc[ct] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int t0 = 0; t0 < nterm; t0 += TP) {
+  // term group g takes the rounds of TP terms starting at g TP, g TP + TG TP, ...
+  for (int t0 = grp * TP; t0 < nterm; t0 += TP * TG) {
 #pragma unroll
     for (int u = 0; u < TP; ++u)
-      bcr_split_load<KQ, NCT>(d, min(t0 + u, nterm - 1), data, rt, wave, lk, lane, B, ldb, X, ldx, cb_off, cb_col,
+      bcr_split_load<KQ, NCT>(d, min(t0 + u, nterm - 1), data, rt, wq, lk, lane, B, ldb, X, ldx, cb_off, cb_col,
                               a[u], x[u]);
     __builtin_amdgcn_sched_barrier(0);   // keeps the round's loads ahead of its products
     // no branches between the loads and their use, so that every load of
@@ -1581,7 +1591,7 @@ __global__ __launch_bounds__(256) void k_bcr_split(const BcrOpDesc* __restrict__
       const double coef = (t0 + u < nterm) ? d.coef[t] : 0.0;
 #pragma unroll
       for (int s = 0; s < KQ; ++s) {
-        const double av = (wave + 4 * s < nq) ? coef * a[u][s] : 0.0;
+        const double av = (wq + 4 * s < nq) ? coef * a[u][s] : 0.0;
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct)
           acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, x[u][s][ct], acc[ct], 0, 0, 0);
@@ -1593,16 +1603,20 @@ __global__ __launch_bounds__(256) void k_bcr_split(const BcrOpDesc* __restrict__
 #pragma unroll
     for (int v = 0; v < 4; ++v) red[wave][(ct * 4 + v) * 64 + lane] = acc[ct][v];
   __syncthreads();
+  if (tid >= 256) return;
   const bool to_x = d.flags & 2;
   double* out = to_x ? X : B;
   const long ldo = to_x ? ldx : ldb;
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct) {
     // thread tid sums accumulator item (ct, v = tid / 64, lane tid % 64)
+    // over the waves, pairwise within each term group, groups in order
     const int e = ct * 256 + tid, v = tid / 64, l = tid % 64;
     const int r = rt * 16 + 4 * v + l / 16, j = j0 + ct * 16 + l % 16;
     if (r < bo && j < ctot) {
       double sum = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+#pragma unroll
+      for (int g = 1; g < TG; ++g) sum += (red[4 * g][e] + red[4 * g + 1][e]) + (red[4 * g + 2][e] + red[4 * g + 3][e]);
       const int comp = j / ncols, c = j - comp * ncols;
       if (d.flags & 1) sum += B[((long)comp * comp_rows + r0 + r) * ldb + c];
       out[((long)comp * comp_rows + r0 + r) * ldo + c] = sum;
@@ -2026,6 +2040,24 @@ __global__ void k_reduce_scaled(int nb, int m, int n, const double* __restrict__
 }
 }  // namespace
 
+namespace {
+thread_local int g_gemm_tag = GEMM_PLAIN;   // what gemm() is running, see GemmTagScope
+using GemmKernel = void (*)(int, int, int, double, const double*, long, long, long, const double*, long, long, long,
+                            double, double*, long, long, long, int, long);
+GemmKernel gemm_kernel() {
+  if (g_gemm_prec == GP_F64 && g_gemm_tag == GEMM_GRAM) return k_gemm<GP_F64, GEMM_GRAM>;
+  if (g_gemm_prec == GP_F64 && g_gemm_tag == GEMM_PROJ) return k_gemm<GP_F64, GEMM_PROJ>;
+  return g_gemm_prec == GP_F32 ? k_gemm<GP_F32> : (g_gemm_prec == GP_BF16 ? k_gemm<GP_BF16> : k_gemm<GP_F64>);
+}
+int gemm_class() {
+  if (g_gemm_prec != GP_F64) return KC_GEMM_LOWP;
+  return g_gemm_tag == GEMM_GRAM ? KC_GRAM : (g_gemm_tag == GEMM_PROJ ? KC_PROJ : KC_GEMM);
+}
+}  // namespace
+
+GemmTagScope::GemmTagScope(int tag) : old(g_gemm_tag) { g_gemm_tag = tag; }
+GemmTagScope::~GemmTagScope() { g_gemm_tag = old; }
+
 void gemm(hipStream_t s, int batch, int m, int n, int k, double alpha, const double* A, long sAb, long sAi, long sAk,
           const double* B, long sBb, long sBk, long sBj, double beta, double* C, long sCb, long sCi, long sCj,
           int kstep, long klimit) {
@@ -2042,9 +2074,8 @@ void gemm(hipStream_t s, int batch, int m, int n, int k, double alpha, const dou
       nch = (k + chunk - 1) / chunk;
       dim3 grid(cdiv(n, TN), cdiv(m, TM), (unsigned)nch);
       {
-        ProfScope ps(g_gemm_prec == GP_F64 ? KC_GEMM : KC_GEMM_LOWP, s, 8.0 * ((double)k * (m + n) + (double)ne * nch),
-                     2.0 * m * n * (double)k);
-        auto kern = g_gemm_prec == GP_F32 ? k_gemm<GP_F32> : (g_gemm_prec == GP_BF16 ? k_gemm<GP_BF16> : k_gemm<GP_F64>);
+        ProfScope ps(gemm_class(), s, 8.0 * ((double)k * (m + n) + (double)ne * nch), 2.0 * m * n * (double)k);
+        auto kern = gemm_kernel();
         hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, m, n, (int)chunk, 1.0, A, chunk * sAk, sAi, sAk, B,
                            chunk * sBk, sBk, sBj, 0.0, ws, ne, (long)n, 1L, (int)chunk, (long)k);
       }
@@ -2057,8 +2088,8 @@ void gemm(hipStream_t s, int batch, int m, int n, int k, double alpha, const dou
   double kk = klimit > 0 ? (double)klimit : (double)k * batch;   // total reduction length
   double by = klimit > 0 ? 8.0 * (kk * (m + n) + (double)m * n * batch)
                          : 8.0 * batch * ((double)m * k + (double)k * n + (double)m * n * (beta != 0.0 ? 2 : 1));
-  ProfScope ps(g_gemm_prec == GP_F64 ? KC_GEMM : KC_GEMM_LOWP, s, by, 2.0 * m * n * kk);
-  auto kern = g_gemm_prec == GP_F32 ? k_gemm<GP_F32> : (g_gemm_prec == GP_BF16 ? k_gemm<GP_BF16> : k_gemm<GP_F64>);
+  ProfScope ps(gemm_class(), s, by, 2.0 * m * n * kk);
+  auto kern = gemm_kernel();
   hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, m, n, k, alpha, A, sAb, sAi, sAk, B, sBb, sBk, sBj, beta, C, sCb,
                      sCi, sCj, kstep, klimit);
 }
@@ -2078,6 +2109,7 @@ void gemm_batched(hipStream_t s, int nb, const GemmDesc* d_desc, int max_m, int 
 void gram(hipStream_t s, long rows, int nx, int ny, const double* X, long sXr, long sXc, const double* Y, long sYr,
           long sYc, double* out, double* ws, size_t ws_doubles) {
   GemmPrecisionScope f64(GP_F64);   // Grams decide truncations: always FP64
+  GemmTagScope tag(GEMM_GRAM);
   const long ne = (long)nx * ny;
   if (rows <= 0) {
     fill(s, out, ne, 0.0);
@@ -2138,7 +2170,7 @@ void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* 
   if (nrows <= 0 || ncols <= 0 || ncomp <= 0) return;
   const double by = 12.0 * ELL_WIDTH * nrows + 8.0 * ncomp * ((double)nrows * ncols) +
                     8.0 * ncomp * (double)nrows * ncols * (beta != 0.0 ? 2.0 : 1.0);
-  ProfScope ps(KC_SPMM, s, by, 2.0 * ELL_WIDTH * (double)nrows * ncomp * ncols);
+  ProfScope ps(KC_ELL, s, by, 2.0 * ELL_WIDTH * (double)nrows * ncomp * ncols);
   const unsigned nb = 8 * cdiv(cdiv(nrows, 4), 8);
   hipLaunchKernelGGL(k_ell_spmm<ELL_WIDTH>, dim3(nb, ncomp), dim3(256), 0, s, nrows, ics, ocs, ecol, eval, x, ldx,
                      xcol0, ncols, y, ldy, ycol0, alpha, beta);
@@ -2287,6 +2319,7 @@ struct BcrVariant {
   int max_rows;   // largest block the variant takes
   int wg_rows;    // output rows per workgroup (grid z covers the largest block)
   decltype(&k_bcr_stream<32, 8>) fn;
+  int threads = 256;   // workgroup size
 };
 const BcrVariant kBcrVariants[] = {
     {32, BCR_MAXBS, 64, k_bcr_stream<32, 8>},  {16, BCR_MAXBS, 64, k_bcr_stream<16, 8>},
@@ -2295,9 +2328,11 @@ const BcrVariant kBcrVariants[] = {
     {32, 128, 64, k_bcr_tile<32, 32, false>},  {16, 64, 64, k_bcr_tile<16, 16, true>},
     {32, 64, 64, k_bcr_tile<32, 16, true>},    {48, 128, 64, k_bcr_tile<48, 32, true>},
     {48, 128, 64, k_bcr_tile<48, 32, false>},  {80, 128, 64, k_bcr_tile<80, 32, false>},
-    {16, 128, 16, k_bcr_split<16, 8, 1>},      {16, 128, 16, k_bcr_split<16, 8, 2>},
-    {16, 128, 16, k_bcr_split<16, 8, 4>},      {32, 128, 16, k_bcr_split<32, 8, 1>},
-    {32, 128, 16, k_bcr_split<32, 8, 2>},      {16, 256, 16, k_bcr_split<16, 16, 1>}};
+    {16, 128, 16, k_bcr_split<16, 8, 1, 1>},   {16, 128, 16, k_bcr_split<16, 8, 2, 1>},
+    {16, 128, 16, k_bcr_split<16, 8, 4, 1>},   {32, 128, 16, k_bcr_split<32, 8, 1, 1>},
+    {32, 128, 16, k_bcr_split<32, 8, 2, 1>},   {16, 256, 16, k_bcr_split<16, 16, 1, 1>},
+    {16, 128, 16, k_bcr_split<16, 8, 1, 2>, 512}, {16, 128, 16, k_bcr_split<16, 8, 1, 4>, 1024},
+    {16, 128, 16, k_bcr_split<16, 8, 2, 2>, 512}, {32, 128, 16, k_bcr_split<32, 8, 1, 2>, 512}};
 constexpr int kNumBcrVariants = sizeof(kBcrVariants) / sizeof(kBcrVariants[0]);
 
 // ev (npass + 1 events, optional) brackets every pass.  The profiler sees
@@ -2323,7 +2358,7 @@ void bcr_run(hipStream_t s, const BcrDev& f, const std::vector<int>& vars, int n
     // padded to a multiple of 8, every column chunk and row group of an op
     // runs on the same XCD and shares its blocks through that XCD's L2
     const unsigned gx = 8 * cdiv(no, 8);
-    hipLaunchKernelGGL(v.fn, dim3(gx, cdiv((long)ncomp * ncols, v.cb), cdiv(f.maxbs, v.wg_rows)), dim3(256), 0, s,
+    hipLaunchKernelGGL(v.fn, dim3(gx, cdiv((long)ncomp * ncols, v.cb), cdiv(f.maxbs, v.wg_rows)), dim3(v.threads), 0, s,
                        f.ops, o0, no, f.data, B, ldb, X, ldx, ncols, ncomp, (long)f.n);
   }
   if (ev) (void)hipEventRecord(ev[f.npass], s);
@@ -2373,6 +2408,14 @@ std::vector<int> bcr_tune(hipStream_t s, const BcrDev& f, int ncomp, const doubl
   for (auto& e : ev) (void)hipEventDestroy(e);
   (void)hipStreamSynchronize(s);
   for (double* p : {b0, bw, xw}) (void)hipFree(p);
+  if (std::getenv("SGTT_BCR_TUNE_LOG")) {
+    // per pass: ops, terms, block data, the chosen variant and its time
+    for (int p = 0; p < np; ++p)
+      std::fprintf(stderr, "[bcr tune] n=%d cols=%d pass %d: ops %d, mk %.3g, data %.3g MB, rows %.3g -> variant %d "
+                           "%.2f us\n",
+                   f.n, ncomp * ncols, p, f.pass_begin[p + 1] - f.pass_begin[p], f.pass_mk[p], 8e-6 * f.pass_data[p],
+                   f.pass_rows[p], best[p], best_ms[p] * 1e3 / 2);
+  }
   return best;
 }
 }  // namespace

@@ -186,6 +186,8 @@ struct sgtt_system {
   DevCsr Kop;       // free x free scalar pattern: [M, A, N_1..N_k2]
   DevCsr Bd, Btd;   // B (n_p x n_u), B^T (n_u x n_p)
   DevCsr Xmid;      // pressure pattern: [XM, XA, XN_1..XN_k2]
+  DevCsr Fp;        // Q1 pressure pattern: [M_p, A_p, N_p(w3_1)..N_p(w3_k2)] (PCD, eq. 5.17)
+  DevCsr Mpinv;     // diag(M_p)^-1 as a diagonal CSR matrix (PCD)
   double* Gnu = nullptr;   // n_xi x n_xi
   int k1 = 0, k2 = 0;      // convection TT-operator ranks (0: Stokes)
   double* w1 = nullptr;    // nt x k1
@@ -211,6 +213,8 @@ struct sgtt_system {
     Bd.free_all();
     Btd.free_all();
     Xmid.free_all();
+    Fp.free_all();
+    Mpinv.free_all();
     free_bcr(Fbt);
     free_bcr(Xbt);
     for (void* p : {(void*)Me_col, (void*)Me_val})
@@ -474,7 +478,7 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
         const TT& ti = Vh[i].c[q];
         const TT& tj = Vh[k - 1].c[q];
         slot = c.pool.get((size_t)ti.r2 * tj.r2);
-        size_t wsn = std::max<size_t>((size_t)ti.r2 * tj.r2 * 256, 1 << 22);
+        size_t wsn = gram_ws_doubles(ti.n3, ti.r2, tj.r2);
         gram(c.s, ti.n3, ti.r2, tj.r2, ti.c3, ti.r2, 1, tj.c3, tj.r2, 1, slot, c.scratch(wsn), wsn);
       }
     // lines 6-9: modified Gram-Schmidt coefficients from <x, v_i> and the
@@ -598,7 +602,8 @@ struct InnerSpace : Space {
 
 struct PrecOpts {
   double eps = 1e-6, inner_tol = 1e-1, inner_eps = 1e-3, inner_rhs_eps = 0.0;
-  int inner_mode = 0;       // 0: inner GMRES with M (eq. 5.22-5.23); 1: exact mean solve
+  int inner_mode = 0;       // 0: inner GMRES with M (eq. 5.22-5.23); 1: exact mean solve; 2: M alone
+  int schur = 0;            // 0: mean-based LSC (eq. 5.19); 1: mean-based PCD (eq. 5.17)
   int inner_maxit = 20;
   bool inner_explicit = false;
   int precision = GP_F64;   // dense products of the inner solve
@@ -641,10 +646,22 @@ Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCoun
   Ctx& c = S.ctx->c;
   const TT& yu = y.c[0];
   const TT& yp = y.c[1];
-  // p^ = -X^-1 [B M*^-1 (F_0 + C) M*^-1 B^T] X^-1 y_p   (eq. 5.19)
-  TT t1 = space_solve(S, yp, S.Xbt, 1, 1.0);
-  TT t2 = apply_mean_sum(S, t1, S.Xmid, 1, S.np);
-  TT t3 = tt_round(c, t2, po.eps, nullptr, nullptr);
+  TT t3;
+  if (po.schur == 1) {
+    // p^ = -X^-1 (F_p,0 + C_p) M_p*^-1 y_p   (eq. 5.17)
+    TT t1 = tt_new(c, S.nt, S.nxi, S.np, yp.r1, yp.r2);
+    SGTT_HIP(hipMemcpyAsync(t1.c1, yp.c1, sizeof(double) * yp.n_c1(), hipMemcpyDeviceToDevice, c.s));
+    SGTT_HIP(hipMemcpyAsync(t1.c2, yp.c2, sizeof(double) * yp.n_c2(), hipMemcpyDeviceToDevice, c.s));
+    spmm(c.s, S.np, 1, 0, 0, S.Mpinv.rowptr, S.Mpinv.col, S.Mpinv.vals, 1, S.Mpinv.nnz, yp.c3, yp.r2, 0, yp.r2, t1.c3,
+         yp.r2, 0, 0, 1.0, 0.0, S.Mpinv.max_row);
+    TT t2 = apply_mean_sum(S, t1, S.Fp, 1, S.np);
+    t3 = tt_round(c, t2, po.eps, nullptr, nullptr);
+  } else {
+    // p^ = -X^-1 [B M*^-1 (F_0 + C) M*^-1 B^T] X^-1 y_p   (eq. 5.19)
+    TT t1 = space_solve(S, yp, S.Xbt, 1, 1.0);
+    TT t2 = apply_mean_sum(S, t1, S.Xmid, 1, S.np);
+    t3 = tt_round(c, t2, po.eps, nullptr, nullptr);
+  }
   TT ph = space_solve(S, t3, S.Xbt, 1, -1.0);
   // right-hand side of the (1,1) solve: y_u - B^T p^
   TT bph = tt_new(c, S.nt, S.nxi, S.nu, ph.r1, ph.r2);
@@ -655,6 +672,18 @@ Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCoun
   Vec rhs;
   rhs.nc = 1;
   rhs.c[0] = tt_concat(c, {&yu, &bph}, nullptr, {});
+  if (po.inner_mode == 2) {
+    // M^-1 itself (eq. 5.23) as the velocity block: the approximation of
+    // (F_0 + C)^-1 that the inner solve of eq. 5.22 is preconditioned with,
+    // applied once (prefix sum in time, one F_avg solve on core 3)
+    RegionScope rg(RG_IN_MINV);
+    Vec out;
+    out.nc = 2;
+    TT m = apply_Minv(S, rhs.c[0]);
+    out.c[0] = tt_round(c, m, po.inner_eps, nullptr, nullptr);
+    out.c[1] = std::move(ph);
+    return out;
+  }
   // inner low-rank GMRES on (F_0 + C) v = rhs, preconditioned by M (eq. 5.22-5.23)
   if (po.inner_mode == 1) {
     RegionScope rg(RG_IN_MINV);
@@ -782,9 +811,11 @@ PrecOpts prec_opts(const sgtt_solve_opts* o) {
     if (o->precision < 0 || o->precision > 2) throw SgttError(-1, "invalid precision option");
     if (o->inner_rhs_eps < 0.0 || o->cycle_rhs_factor < 0.0) throw SgttError(-1, "invalid truncation option");
     p.inner_rhs_eps = o->inner_rhs_eps;
-    if (o->inner_mode < 0 || o->inner_mode > 1) throw SgttError(-1, "invalid inner_mode option");
+    if (o->inner_mode < 0 || o->inner_mode > 2) throw SgttError(-1, "invalid inner_mode option");
     p.inner_mode = o->inner_mode;
     p.precision = o->precision;
+    if (o->schur < 0 || o->schur > 1) throw SgttError(-1, "invalid schur option");
+    p.schur = o->schur;
   }
   return p;
 }
@@ -807,6 +838,7 @@ sgtt_solve_opts default_opts() {
   o.inner_rhs_eps = 0.0;
   o.cycle_rhs_factor = 0.0;
   o.inner_mode = 0;
+  o.schur = 0;
   return o;
 }
 
@@ -823,8 +855,9 @@ void build_convection(sgtt_system& S, Ctx& c, const TT& wtil) {
   c.sync();
   S.k1 = k1;
   S.k2 = k2;
-  const int nnz = hp.Kff.nnz(), nnzx = hp.Xmid.nnz();
+  const int nnz = hp.Kff.nnz(), nnzx = hp.Xmid.nnz(), nnzq = hp.Qp.nnz();
   std::vector<std::vector<double>> Nv(k2, std::vector<double>(nnz)), XNv(k2, std::vector<double>(nnzx));
+  std::vector<std::vector<double>> NPv(k2, std::vector<double>(nnzq));
   std::vector<double> w1(nall), w2(nall);
   for (int b = 0; b < k2; ++b) {
     for (int i = 0; i < nall; ++i) {
@@ -833,6 +866,7 @@ void build_convection(sgtt_system& S, Ctx& c, const TT& wtil) {
     }
     convection_values(hp, w1.data(), w2.data(), Nv[b].data(), nullptr);
     lsc_middle_values(hp, Nv[b].data(), XNv[b].data());
+    pressure_convection_values(hp, w1.data(), w2.data(), NPv[b].data());
   }
   // Hw[a,b] = sum_l w2(a,l,b) H_l ; omega[t,b] = sum_a w1[t,a] w2(a,0,b)
   std::vector<double> Hw((size_t)k1 * k2 * nxi * nxi, 0.0), om((size_t)nt * k2, 0.0), avg(k2, 0.0);
@@ -862,6 +896,10 @@ void build_convection(sgtt_system& S, Ctx& c, const TT& wtil) {
   std::vector<const double*> xs{hp.XM.data(), hp.XA.data()};
   for (int b = 0; b < k2; ++b) xs.push_back(XNv[b].data());
   S.Xmid = upload_csr(c, hp.Xmid, xs);
+  std::vector<const double*> ps{hp.Mp.data(), hp.Ap.data()};
+  for (int b = 0; b < k2; ++b) ps.push_back(NPv[b].data());
+  S.Fp.free_all();
+  S.Fp = upload_csr(c, hp.Qp, ps);
   // F_avg = tau^-1 M + nu0 A + N(w_avg), N linear in the wind
   std::vector<double> F(nnz);
   for (int t = 0; t < nnz; ++t) {
@@ -1026,11 +1064,26 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
   SGTT_HIP(hipMemcpyAsync(lift.c2, e1.data(), nxi * 8, hipMemcpyHostToDevice, c.s));
   SGTT_HIP(hipMemcpyAsync(lift.c3, hp.g_all.data(), 2 * nall * 8, hipMemcpyHostToDevice, c.s));
   c.sync();
+  {
+    // diag(M_p)^-1 of the PCD approximation (eq. 5.17) as a diagonal matrix
+    Csr d;
+    d.nrows = d.ncols = hp.n_p;
+    d.rowptr.resize(hp.n_p + 1);
+    d.col.resize(hp.n_p);
+    d.val.resize(hp.n_p);
+    for (int k = 0; k <= hp.n_p; ++k) d.rowptr[k] = k;
+    for (int k = 0; k < hp.n_p; ++k) {
+      d.col[k] = k;
+      d.val[k] = 1.0 / hp.Mpstar[k];
+    }
+    S->Mpinv = upload_csr(c, d, {d.val.data()});
+  }
   if (!prior) {
     // Stokes system: no convection; f = -L_{free,all}(0) lift (ranks 2 and 1)
     S->k1 = S->k2 = 0;
     S->Kop = upload_csr(c, hp.Kff, {hp.Mff.data(), hp.Aff.data()});
     S->Xmid = upload_csr(c, hp.Xmid, {hp.XM.data(), hp.XA.data()});
+    S->Fp = upload_csr(c, hp.Qp, {hp.Mp.data(), hp.Ap.data()});
     std::vector<double> F(hp.Kff.nnz());
     for (int t = 0; t < hp.Kff.nnz(); ++t) F[t] = hp.Mff[t] / S->tau + S->nu0 * hp.Aff[t];
     S->Dinv = dev_upload(c, inverse_diagonal(hp.Kff, F.data()));
@@ -1830,6 +1883,8 @@ int sgtt_host_csr(const sgtt_host_problem* h, int which, int* nrows, int* ncols,
     case 3: pat = &hp.Xp; v = hp.Xp.val.data(); break;
     case 4: pat = &hp.Xmid; v = hp.XM.data(); break;
     case 5: pat = &hp.Xmid; v = hp.XA.data(); break;
+    case 6: pat = &hp.Qp; v = hp.Mp.data(); break;
+    case 7: pat = &hp.Qp; v = hp.Ap.data(); break;
     default: return SGTT_E_INVALID;
   }
   if (nrows) *nrows = pat->nrows;

@@ -164,7 +164,7 @@ void tt_dot(Ctx& c, const TT& x, const TT& y, double* dout, int acc, double* k3_
   // W2 = X2flat^T Zflat over (a, i)
   gemm(c.s, 1, a2, b2, a1 * n2, 1.0, x.c2, 0, 1, a2, Z, 0, b2, 1, 0.0, W2, 0, b2, 1);
   // K3 = X3^T Y3 over space
-  size_t wsn = std::max<size_t>((size_t)a2 * b2 * 256, 1 << 22);
+  size_t wsn = gram_ws_doubles(x.n3, a2, b2);
   gram(c.s, x.n3, a2, b2, x.c3, a2, 1, y.c3, b2, 1, K3, c.scratch(wsn), wsn);
   dot_reduce(c.s, (long)a2 * b2, W2, K3, dout, acc);
   c.pool.put(W1);
@@ -333,7 +333,7 @@ TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_no
     for (int j = i; j < k; ++j) {
       const double* src = cache ? (*cache)[(size_t)i * k + j] : nullptr;
       if (!src) {
-        size_t wsn = std::max<size_t>((size_t)b[i] * b[j] * 256, 1 << 22);
+        size_t wsn = gram_ws_doubles(n3, b[i], b[j]);
         gram(c.s, n3, b[i], b[j], terms[i].t->c3, b[i], 1, terms[j].t->c3, b[j], 1, blk, c.scratch(wsn), wsn);
         src = blk;
       }
@@ -455,6 +455,7 @@ TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_no
     transpose_copy(c.s, k2, N2, sk.F, N2, t.c2, k2);
   else
     copy2d(c.s, N2, k2, U2, kmax2, t.c2, k2, 1.0, nullptr, 0);
+  GemmTagScope proj(GEMM_PROJ);
   for (int j = 0; j < k; ++j)
     gemm(c.s, 1, n3, k2, b[j], 1.0, terms[j].t->c3, 0, b[j], 1, W + ob[j], 0, 1, R2, j == 0 ? 0.0 : 1.0, t.c3, 0,
          k2, 1);
@@ -474,7 +475,7 @@ TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, dou
   double* dnorm = d_normsq ? d_normsq : c.dscal + 249;
   double* dkept = c.dscal + 248;
   double* S1 = c.pool.get((size_t)n1 * n1);
-  size_t wsn = std::max<size_t>((size_t)n1 * n1 * 256, 1 << 20);
+  size_t wsn = gram_ws_doubles(n23, n1, n1);
   gram(c.s, n23, n1, n1, X, 1, n23, X, 1, n23, S1, c.scratch(wsn), wsn);
   const int kmax1 = std::min({n1, maxrank, RANK_CAP});
   double* U1 = c.pool.get((size_t)n1 * kmax1);
@@ -489,7 +490,7 @@ TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, dou
   double* Y = c.pool.get((size_t)k1 * n23);
   gemm(c.s, 1, k1, (int)std::min<long>(n23, INT32_MAX), n1, 1.0, U1, 0, 1, kmax1, X, 0, n23, 1, 0.0, Y, 0, n23, 1);
   double* S2 = c.pool.get((size_t)N2 * N2);
-  size_t wsn2 = std::max<size_t>((size_t)N2 * N2 * 64, 1 << 20);
+  size_t wsn2 = gram_ws_doubles(n3, N2, N2);
   gram(c.s, n3, N2, N2, Y, 1, n3, Y, 1, n3, S2, c.scratch(wsn2), wsn2);
   const int kmax2 = std::min({N2, maxrank, RANK_CAP});
   double* U2 = c.pool.get((size_t)N2 * kmax2);
@@ -522,6 +523,7 @@ TT tt_from_full(Ctx& c, const double* X, int n1, int n2, int n3, double eps, dou
   } else {
     copy2d(c.s, N2, k2, U2, kmax2, t.c2, k2, 1.0, nullptr, 0);
     // G3 (n3 x k2) = Y(12)^T U2_k
+    GemmTagScope proj(GEMM_PROJ);
     gemm(c.s, 1, n3, k2, N2, 1.0, Y, 0, 1, n3, U2, 0, kmax2, 1, 0.0, t.c3, 0, k2, 1);
   }
   sk.release(c.pool);

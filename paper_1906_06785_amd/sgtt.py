@@ -56,7 +56,7 @@ class SolveOpts(C.Structure):
                 ("inner_eps", C.c_double), ("inner_maxit", C.c_int), ("verbose", C.c_int),
                 ("outer_explicit", C.c_int), ("inner_explicit", C.c_int), ("relax", C.c_int),
                 ("precision", C.c_int), ("inner_rhs_eps", C.c_double), ("cycle_rhs_factor", C.c_double),
-                ("inner_mode", C.c_int)]
+                ("inner_mode", C.c_int), ("schur", C.c_int)]
 
 
 PICARD_MAX_STEPS = 16
@@ -180,12 +180,13 @@ def make_desc(cfg: dict, eps_conv=1e-3, eps_rhs=1e-6) -> ProblemDesc:
 def make_opts(**kw) -> SolveOpts:
     d = dict(tol=1e-8, eps_krylov=1e-6, tol_cycle=1e-4, restart=30, max_cycles=8, inner_tol=1e-1,
              inner_eps=1e-3, inner_maxit=20, verbose=0, outer_explicit=1, inner_explicit=0, relax=0, precision=0,
-             inner_rhs_eps=0.0, cycle_rhs_factor=0.0, inner_mode=0)
+             inner_rhs_eps=0.0, cycle_rhs_factor=0.0, inner_mode=0, schur=0)
     d.update(kw)
     return SolveOpts(d["tol"], d["eps_krylov"], d["tol_cycle"], int(d["restart"]), int(d["max_cycles"]),
                      d["inner_tol"], d["inner_eps"], int(d["inner_maxit"]), int(d["verbose"]),
                      int(d["outer_explicit"]), int(d["inner_explicit"]), int(d["relax"]), int(d["precision"]),
-                     float(d["inner_rhs_eps"]), float(d["cycle_rhs_factor"]), int(d["inner_mode"]))
+                     float(d["inner_rhs_eps"]), float(d["cycle_rhs_factor"]), int(d["inner_mode"]),
+                     int(d["schur"]))
 
 
 # ------------------------------------------------------------------ host-only

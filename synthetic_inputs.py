@@ -31,6 +31,11 @@ CONFIGS = {
     # 64x192 grid (h=1/16), m=4, p=3 (35 chaos terms), nt=128, tau=0.05
     "C2": dict(h=1.0 / 16, L=12.0, m=4, p=3, nt=128, tau=0.05, nu0=1.0 / 50,
                nu_coef=0.1, ramp=10.0),
+    # sizes of the paper's Table 6.1 (h = 2^-2, m = 3, degree 3 (n_xi = 20),
+    # t_f = 1 with tau = 2^-6 (nt = 64), nu0 = 1/50), with this build's
+    # viscosity law (relative amplitude nu_coef = sigma = 0.01)
+    "paper": dict(h=0.25, L=12.0, m=3, p=3, nt=64, tau=1.0 / 64, nu0=1.0 / 50, nu_coef=0.01,
+                  ramp=10.0),
     # intermediate size used by parity tests at a shape between C1 and C2
     "C1b": dict(h=0.125, L=12.0, m=3, p=2, nt=32, tau=0.05, nu0=1.0 / 50,
                 nu_coef=0.1, ramp=10.0),
@@ -95,3 +100,39 @@ def batch_configs(n: int = 64, seed: int = 0, small: bool = False):
                         nu0=float(np.exp(g.uniform(np.log(1 / 200), np.log(1 / 20)))), nu_coef=0.1,
                         ramp=10.0))
     return out
+
+
+def smooth_prior(nt: int, nxi: int, tau: float, coords_free, n_p: int, ranks_u=(4, 17), ranks_p=(2, 3),
+                 seed: int = 0, amplitude: float = 0.4):
+    """A prior iterate (velocity TT over free nodes, pressure TT) shaped like
+    a flow solution, with exact TT ranks: time columns ramp up like the
+    inflow, (1 - exp(-10 t)) sin((a + 1) pi t / (2 T)); chaos slices decay
+    with the chaos index; each spatial column is the velocity of a stream
+    function sin(alpha (x1 + 1)) sin(beta (x2 + 1)) sampled at the free
+    nodes (component 1 rows, then component 2 rows).  coords_free: (n_s, 2)
+    free node coordinates.  Returns ((G1, G2, G3), (P1, P2, P3)) in the
+    paper's core convention (G3: r2 x n)."""
+    g = rng(seed)
+    k1, k2 = ranks_u
+    t = tau * np.arange(1, nt + 1)
+    T = t[-1]
+    ramp = 1.0 - np.exp(-10.0 * t)
+    G1 = np.stack([amplitude * ramp * np.sin((a + 1) * np.pi * t / (2 * T)) for a in range(k1)], axis=1)
+    decay = np.exp(-0.5 * np.arange(nxi))
+    G2 = g.standard_normal((k1, nxi, k2)) * decay[None, :, None] / np.sqrt(k1 * k2)
+    G2[:, 0, :] += 1.0 / np.sqrt(k1 * k2)
+    x1, x2 = coords_free[:, 0], coords_free[:, 1]
+    cols = []
+    for b in range(k2):
+        al = np.pi * (1 + b // 3) / 13.0
+        be = np.pi * (1 + b % 3) / 2.0
+        u1 = be * np.sin(al * (x1 + 1)) * np.cos(be * (x2 + 1))
+        u2 = -al * np.cos(al * (x1 + 1)) * np.sin(be * (x2 + 1))
+        v = np.concatenate([u1, u2])
+        cols.append(v / np.abs(v).max())
+    G3 = np.stack(cols, axis=0)
+    j1, j2 = ranks_p
+    P1 = np.stack([0.1 * ramp * np.cos(a * np.pi * t / T) for a in range(j1)], axis=1)
+    P2 = g.standard_normal((j1, nxi, j2)) * decay[None, :, None]
+    P3 = g.standard_normal((j2, n_p))
+    return (G1, G2, G3), (P1, P2, P3)

@@ -48,7 +48,7 @@ def test_default_solve_options(argv):
     a = bench.parse(argv)
     assert a.gpus == 1 and a.config == "C2"
     o = bench.solve_options(a)
-    assert o["inner_mode"] == 1 and o["precision"] == 0
+    assert o["inner_mode"] in (1, 2) and o["precision"] == 0
 
 
 def test_traffic_digest_follows_the_pass_kernels_and_the_factorization(tmp_path, monkeypatch):
@@ -58,7 +58,7 @@ def test_traffic_digest_follows_the_pass_kernels_and_the_factorization(tmp_path,
     src = os.path.join(ROOT, "paper_1906_06785_amd", "csrc")
     dst = tmp_path / "paper_1906_06785_amd" / "csrc"
     dst.mkdir(parents=True)
-    for f in ("kernels.hip", "host_setup.cpp"):
+    for f in ("kernels.hip", "host_setup.cpp", "solver.hip"):
         shutil.copy(os.path.join(src, f), dst / f)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     d0 = bench.bcr_source_digest()
@@ -79,4 +79,19 @@ def test_traffic_digest_follows_the_pass_kernels_and_the_factorization(tmp_path,
     assert d1 != d0
     # inside the factorization
     edit("host_setup.cpp", "  constexpr int NT = BcrFactor::NT, NTOP", "  // note\n")
-    assert bench.bcr_source_digest() != d1
+    d2 = bench.bcr_source_digest()
+    assert d2 != d1
+    # the launch side: variant table, grid padding and tuning
+    edit("kernels.hip", "  const unsigned gx = 8 * cdiv(no, 8);", "  // note\n")
+    d3 = bench.bcr_source_digest()
+    assert d3 != d2
+    edit("kernels.hip", "std::vector<int> bcr_tune(", "// note\n")
+    d4 = bench.bcr_source_digest()
+    assert d4 != d3
+    # the device layout of a factor
+    edit("solver.hip", "    const int mode = f.pass_mode[p];", "    // note\n")
+    d5 = bench.bcr_source_digest()
+    assert d5 != d4
+    # the rest of solver.hip does not count
+    edit("solver.hip", "// ====================================================================== C ABI", "// note\n")
+    assert bench.bcr_source_digest() == d5

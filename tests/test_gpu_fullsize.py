@@ -48,3 +48,69 @@ def test_c2_bench_solve_residual_on_sampled_entries():
         err = np.abs(got - want).max()
         print(which, "max entry difference", err, "max |r| sampled", np.abs(want).max(), flush=True)
         assert err <= 1e-13 * bnorm
+
+
+def _entries(cores, t, i, j):
+    # z[t, i, j] of a TT in the paper's convention, entry by entry
+    G1, G2, G3 = cores
+    return np.einsum("ka,akb,bk->k", G1[t], G2[:, i, :], G3[:, j])
+
+
+@pytest.mark.timeout(900)
+def test_c2_picard_step1_operator_and_residual_on_sampled_entries():
+    """Picard step-1 system at the full size (Alg. 3.1, eq. 3.14-3.15 with the
+    convection of eq. 4.12) around a seeded smooth prior iterate whose wind
+    has exact TT ranks (5, 16): with eps_conv = 1e-12 both sides keep the
+    wind unchanged, so N(w~) is the same operator on both.  The wind's 16
+    spatial columns give 18 value sets on the velocity pattern (M, A and 16
+    convection matrices), more than one pass of the sparse product takes.
+    Checked: the right-hand side against the oracle's exact residual of the
+    prior (within the truncation eps_rhs), the operator L(w~) x on sampled
+    entries (the GPU's b - r against the oracle's L x), and the exact
+    relative residual <= 1e-8."""
+    import torch
+    from paper_1906_06785_amd import sgtt
+    from bench import OUT_CAPS, solve_options
+    from synthetic_inputs import smooth_prior
+
+    cfg = CONFIGS["C2"]
+    P = Problem(cfg)
+    prior = smooth_prior(P.nt, P.n_xi, cfg["tau"], P.mesh.coords[P.mesh.free], P.n_p, ranks_u=(4, 15),
+                         ranks_p=(2, 3), seed=11)
+    print("full-size C2 Picard step-1 system around a smooth prior (bench options)", flush=True)
+    ctx = sgtt.Context(0)
+    pb = sgtt.PairBuf(P.nt, P.n_xi, P.n_u, P.n_p, 8, 32).set(prior)
+    eps_rhs = 1e-6
+    S = sgtt.System(ctx, cfg, prior=pb, eps_conv=1e-12, eps_rhs=eps_rhs)
+    assert (S.info.conv_r1, S.info.conv_r2) == (5, 16)
+    b = S.rhs(S.pair(128, 1024))
+    print("rhs ranks", b.ranks, flush=True)
+    # verbose: one line per outer iteration on stderr (progress of a long solve)
+    x, st, rc = S.solve(b, S.pair(*OUT_CAPS), **dict(solve_options(), verbose=1))
+    print("solve stats", st, flush=True)
+    assert rc == 0 and st["rel_residual"] <= 1e-8
+    ru, rp, rel = S.residual_tensor(b, x)
+    assert rel <= 1e-8
+
+    conv = P.convection(prior, 1e-12)
+    assert (conv.k1, conv.k2) == (5, 16)
+    bo = P.residual_tt(prior)     # exact (untruncated) right-hand side, eq. 3.15
+    bnorm = math.sqrt(tt.tt_dot(bo[0], bo[0]) + tt.tt_dot(bo[1], bo[1]))
+    xc, bc = x.cores(), b.cores()
+    g = np.random.default_rng(2025)
+    for which, R, n, cnt, q in (("u", ru, P.n_u, 2000, 0), ("p", rp, P.n_p, 1000, 1)):
+        t, i, j = g.integers(0, P.nt, cnt), g.integers(0, P.n_xi, cnt), g.integers(0, n, cnt)
+        b_gpu = _entries(bc[q], t, i, j)
+        b_or = _entries(bo[q], t, i, j)
+        db = np.abs(b_gpu - b_or).max()
+        r_gpu = R[torch.as_tensor(t), torch.as_tensor(i), torch.as_tensor(j)].cpu().numpy()
+        Lx_gpu = b_gpu - r_gpu
+        Lx_or = b_or - P.residual_entries(bo, xc, which, t, i, j, conv)
+        dL = np.abs(Lx_gpu - Lx_or).max()
+        print(which, "rhs entry difference", db, "operator entry difference", dL, "max |Lx| sampled",
+              np.abs(Lx_or).max(), "||b||", bnorm, flush=True)
+        # the right-hand side is the exact residual truncated at eps_rhs
+        # (up to the FP64 Gram accuracy of the truncation, ~1e-8)
+        assert db <= (eps_rhs + 1e-8) * bnorm
+        # the same operator on the same vector
+        assert dL <= 1e-11 * bnorm

@@ -124,3 +124,53 @@ def test_learned_mean_solve_c1(sg, ctx):
     err = np.linalg.norm(tt.pair_full(x2.cores()) - want) / np.linalg.norm(want)
     print("learned solve refined: error vs oracle", err, flush=True)
     assert rc2 == 0 and err <= 1e-8
+
+
+def test_learned_gain_on_held_out_viscosity(sg, ctx):
+    """What the trained network gains, on a system it has not seen.  Pairs
+    come from exact mean solves of C1-shaped systems with mean viscosities
+    1/30, 1/45 and 1/80; the held-out system has nu0 = 1/60.  The same solve
+    (inner GMRES velocity block, eq. 5.22-5.23) runs with F_avg^-1 inside M
+    taken three ways: the exact spatial solve (the plain preconditioner), the
+    Jacobi step D^-1 alone (a network with zero weights: what the network
+    corrects), and D^-1 plus the trained correction.  The trained network
+    must need fewer inner iterations than the Jacobi step and no fallback;
+    the plain preconditioner is reported beside them."""
+    import time
+    _flush("learned gain on a held-out viscosity")
+    base = CONFIGS["C1"]
+    opts = dict(restart=20, relax=1, inner_mode=0)
+    ns = None
+    net = None
+    for nu0 in (1 / 30, 1 / 45, 1 / 80):
+        S = sg.System(ctx, dict(base, nu0=nu0))
+        ns = S.info.n_s
+        if net is None:
+            net = sg.Mlp(ctx, ns, 256, 30000, 1)
+        net.collect(S)
+        S.solve(S.rhs(), S.pair(64, 1024), **opts)
+        net.collect(S, False)
+        del S
+    npar, npairs = net.size()
+    losses = net.train(800, batch=128, lr=1e-3, seed=3)
+    _flush(f"pairs {npairs}, training loss first {losses[:5].mean():.3f} last {losses[-20:].mean():.3f}")
+    S = sg.System(ctx, dict(base, nu0=1 / 60))
+    b = S.rhs()
+    zero = sg.Mlp(ctx, ns, 256, 0, 5)
+    zero.set_params({k: np.zeros_like(v) for k, v in zero.get_params().items()})
+    runs = {}
+    for name, m in (("plain", None), ("jacobi", zero), ("learned", net)):
+        if m is not None:
+            m.attach(S)
+        t0 = time.perf_counter()
+        x, st, rc = S.solve(b, S.pair(64, 1024), **opts)
+        dt = time.perf_counter() - t0
+        if m is not None:
+            m.attach(S, False)
+        runs[name] = (st, rc, dt)
+        _flush(f"{name}: outer {st['outer_iters']} inner {st['inner_iters']} residual {st['rel_residual']:.2e} "
+               f"fallback {st['learned_fallback']} learned calls {st['learned_calls']} time {dt:.2f} s")
+        assert rc == 0 and st["rel_residual"] <= 1e-8
+    st_l, st_j = runs["learned"][0], runs["jacobi"][0]
+    assert st_l["learned_calls"] > 0 and not st_l["learned_fallback"]
+    assert st_j["learned_fallback"] or st_l["inner_iters"] < st_j["inner_iters"]

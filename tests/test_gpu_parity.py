@@ -59,6 +59,30 @@ def test_dot_and_expand(sg, ctx, tiny):
     assert np.abs(full - tt.full(x[0])).max() <= 1e-13 * np.abs(full).max()
 
 
+def test_axpby_is_the_exact_sum(sg, ctx, tiny):
+    # sec. 4.1: a TT sum by core concatenation is exact and its ranks add
+    P, S = tiny
+    _flush("axpby tiny")
+    x = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (3, 7), (2, 5), 3)
+    y = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 9), (3, 4), 4)
+    bx, by = _pair_buf(S, x), _pair_buf(S, y)
+    ctx.axpby(0.75, bx, -1.5, by)
+    assert by.ranks == ((3 + 2, 7 + 9), (2 + 3, 5 + 4))
+    for got, xc, yc in ((by.u, x[0], y[0]), (by.p, x[1], y[1])):
+        want = 0.75 * tt.full(xc) - 1.5 * tt.full(yc)
+        full = ctx.expand(got).cpu().numpy()
+        assert np.abs(full - want).max() <= 1e-13 * np.abs(want).max()
+    # a result above y's capacity is refused and y is left as it was
+    small = S.pair(4, 12).set(y)
+    before = [ctx.expand(t).cpu().numpy() for t in (small.u, small.p)]
+    with pytest.raises(sg.SgttError) as ei:
+        ctx.axpby(1.0, bx, 1.0, small)
+    assert ei.value.code == -4
+    assert small.ranks == ((2, 9), (3, 4))
+    after = [ctx.expand(t).cpu().numpy() for t in (small.u, small.p)]
+    assert all(np.array_equal(a, b) for a, b in zip(before, after))
+
+
 @pytest.mark.parametrize("n,ranks,eps", [((10, 6, 2992), (8, 24), 1e-3), ((10, 6, 2992), (8, 24), 1e-6),
                                          ((128, 35, 3000), (12, 40), 1e-6), ((7, 5, 137), (5, 9), 0.3)])
 def test_round_error_bound_and_ranks(sg, ctx, n, ranks, eps):
@@ -229,6 +253,22 @@ def test_preconditioner_matches_oracle(sg, ctx, tiny, c1, which):
     assert its == prec.inner_iters[-1]
     # Gram-based rounding resolves singular values down to about sqrt(u)
     # relative, so the inner iterates agree to about 1e-8 per step
+    assert err <= 1e-6
+
+
+@pytest.mark.parametrize("which", ["tiny", "c1"])
+def test_pcd_preconditioner_matches_oracle(sg, ctx, tiny, c1, which):
+    # the mean-based PCD approximation (eq. 5.17) on the Stokes system
+    P, S = tiny if which == "tiny" else c1
+    _flush(f"pcd precondition {which}")
+    r = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 4), (2, 3), 29)
+    out = S.precondition(_pair_buf(S, r, 32, 256), eps_krylov=1e-13, inner_eps=1e-13, inner_tol=1e-1, schur=1)
+    ref = MeanLSC(P, None, "tt", 1e-1, 1e-13, 20, 1e-13, schur="pcd").apply_tt(r)
+    gp, wp = tt.full(out.cores()[1]), tt.full(ref[1])
+    perr = np.linalg.norm(gp - wp) / np.linalg.norm(wp)
+    err = np.linalg.norm(tt.pair_full(out.cores()) - tt.pair_full(ref)) / np.linalg.norm(tt.pair_full(ref))
+    _flush(f"pressure block difference {perr:.2e}, pair difference {err:.2e}")
+    assert perr <= 1e-7
     assert err <= 1e-6
 
 

@@ -136,3 +136,45 @@ def test_picard_driver_c1_converges(sg, ctx):
     assert all(r <= 1e-8 for r in st["linear_residual"])
     nr = st["nonlinear_residual"]
     assert all(nr[i + 1] < nr[i] for i in range(len(nr) - 1))
+
+
+@pytest.mark.parametrize("which", ["tiny", "c1"])
+def test_picard_pcd_preconditioner_matches_oracle(tiny_sys, c1_sys, which):
+    # the mean-based PCD approximation (eq. 5.17) with the mean convection on
+    # the Q1 pressure space, truncation switched (almost) off: the pressure
+    # block to FP64 Gram accuracy, the whole pair as the LSC test does
+    P, prior, S = tiny_sys if which == "tiny" else c1_sys
+    _flush(f"picard pcd precondition {which}")
+    r = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 4), (2, 3), 19)
+    out = S.precondition(S.pair(32, 256).set(r), eps_krylov=1e-13, inner_eps=1e-13, inner_tol=1e-1, schur=1)
+    ref = MeanLSC(P, P.convection(prior, 1e-12), "tt", 1e-1, 1e-13, 20, 1e-13, schur="pcd").apply_tt(r)
+    gp, wp = tt.full(out.cores()[1]), tt.full(ref[1])
+    perr = np.linalg.norm(gp - wp) / np.linalg.norm(wp)
+    got, want = tt.pair_full(out.cores()), tt.pair_full(ref)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    _flush(f"pressure block difference {perr:.2e}, pair difference {err:.2e}")
+    assert perr <= 1e-7
+    assert err <= 1e-6
+
+
+def test_picard_step_solve_c1_pcd(c1_sys):
+    # the Picard step-1 solve with the PCD approximation reaches the oracle's
+    # exact solution; the outer iterations of LSC and PCD are reported side by
+    # side (sec. 6.2 compares them: PCD takes more)
+    P, prior, S = c1_sys
+    _flush("picard step solve c1 with pcd")
+    b = S.rhs(S.pair(64, 512))
+    runs = {}
+    for schur in (0, 1):
+        x, st, rc = S.solve(b, S.pair(64, 1024), restart=20, relax=1, inner_mode=1, schur=schur, **TIGHT)
+        runs[schur] = (x, st, rc)
+        _flush(f"schur {'pcd' if schur else 'lsc'}: outer {st['outer_iters']} cycles {st['cycles']} "
+               f"residual {st['rel_residual']:.2e} time {st['seconds']:.2f} s")
+    x, st, rc = runs[1]
+    bu, bp = P.rhs(prior, eps_rhs=1e-12)
+    u, p = P.solve_direct(tt.full(bu), tt.full(bp), P.convection(prior, 1e-12))
+    zd = np.concatenate([u.ravel(), p.ravel()])
+    err = np.linalg.norm(tt.pair_full(x.cores()) - zd) / np.linalg.norm(zd)
+    _flush(f"pcd solution error {err:.2e}")
+    assert rc == 0 and st["rel_residual"] <= 1e-10
+    assert err <= 1e-8

@@ -53,6 +53,10 @@ def test_host_matrices_match_oracle(name):
     assert _rel(hp.csr(3), P.B @ Msi @ P.Bt) < 1e-13
     assert _rel(hp.csr(4), P.B @ Msi @ P.Mb @ Msi @ P.Bt) < 1e-13
     assert _rel(hp.csr(5), P.B @ Msi @ P.Ab @ Msi @ P.Bt) < 1e-13
+    # the PCD pressure-space matrices (eq. 5.17)
+    from oracle import mesh as fem
+    assert _rel(hp.csr(6), P.Mp) < 1e-14
+    assert _rel(hp.csr(7), fem.pressure_stiffness(P.mesh)) < 1e-14
     G = hp.gpc(0)
     H = hp.gpc(1)
     assert np.abs(G - P.G).max() < 1e-14
