@@ -23,6 +23,8 @@
 #ifndef SGTT_H
 #define SGTT_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -106,12 +108,18 @@ typedef struct {
   int relax;           /* 0: fixed eps_krylov (Alg. 4.2); 1: truncate the
                           k-th Krylov vectors with eps_krylov ||b||/||r_k-1||
                           (capped at 1e-2), an inexact-Krylov relaxation    */
-  int precision;       /* dense products of the inner mean-matrix solve
-                          (eq. 5.22-5.23): 0 FP64; 1 FP32 and 2 BF16 operands
-                          on the matrix cores with FP32 accumulation.  The
-                          outer iteration, truncation eigen-solves, Hessenberg
-                          least squares and the exact residual stay FP64, so
-                          the refinement still reaches tol                   */
+  int precision;       /* arithmetic of the velocity block of the
+                          preconditioner: 0 FP64.  inner_mode 0: 1 FP32 and 2
+                          BF16 operands on the matrix cores with FP32
+                          accumulation for the dense products of the inner
+                          solve (eq. 5.22-5.23).  inner_mode 1: 1 or 2 run
+                          the time-stepped mean solve in FP32 (full tensor,
+                          mass products and block cyclic reduction passes in
+                          FP32 on the matrix cores, FP32 accumulation; its
+                          TT-SVD in FP64).  The outer iteration, operator,
+                          truncation eigen-solves, Hessenberg least squares
+                          and the exact residual stay FP64, so the flexible
+                          outer solve and the refinement still reach tol    */
   double inner_rhs_eps;    /* truncation of the inner solve's right-hand side
                               (0: inner_eps); the inner solve only has to
                               reach inner_tol                              */
@@ -148,6 +156,11 @@ typedef struct {
   double t_apply, t_round, t_precond, t_residual;   /* seconds by phase     */
   int learned_calls;         /* mean solves done by an attached network      */
   int learned_fallback;      /* 1 if the solve switched back to the exact one */
+  long device_allocs;        /* device allocations (hipMalloc) made during the
+                                solve: 0 once the context's reservation
+                                (sgtt_context_reserve) covers its working set
+                                and the spatial-solve kernel choices for its
+                                column counts are tuned                     */
 } sgtt_solve_stats;
 
 /* ------------------------------------------------------------- context */
@@ -155,6 +168,23 @@ typedef struct {
  * default-priority stream) or an existing hipStream_t (e.g. torch's). */
 int sgtt_context_create(int device, void* hip_stream, sgtt_context** out);
 int sgtt_context_destroy(sgtt_context* ctx);
+/* Device memory of a context.  The library takes temporaries from a
+ * stream-ordered caching pool.  sgtt_context_reserve allocates an arena of
+ * `bytes` up front (and the largest split-K workspace of the context's
+ * stream): later temporaries are carved out of it while it suffices, so a
+ * solve whose working set fits allocates no device memory (what callers
+ * that must not allocate inside a solve need; the peak of an earlier solve
+ * of the same system, from sgtt_context_memory, is a size that fits).
+ * Fails with SGTT_E_INVALID while temporaries of an earlier arena are in use,
+ * SGTT_E_OOM if the arena cannot be allocated; bytes = 0 drops the arena. */
+typedef struct {
+  size_t arena_bytes;       /* reserved arena                                 */
+  size_t arena_peak_bytes;  /* most of it in use at once since the reserve    */
+  size_t cached_bytes;      /* blocks allocated outside the arena (cached)    */
+  long device_allocs;       /* hipMalloc calls of the context's pool so far   */
+} sgtt_memory_info;
+int sgtt_context_reserve(sgtt_context* ctx, size_t bytes);
+int sgtt_context_memory(const sgtt_context* ctx, sgtt_memory_info* out);
 /* last error of the context; with ctx == NULL, the last failed context creation */
 const char* sgtt_last_error(const sgtt_context* ctx);
 /* build identification string (static storage) */

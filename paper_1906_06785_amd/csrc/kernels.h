@@ -24,6 +24,11 @@ enum KernelClass {
   KC_COUNT
 };
 const char* kernel_class_name(int cls);
+// hipMalloc calls made by this file's launchers (split-K workspaces, tuning
+// copies of the block cyclic reduction) since the process started
+long kernel_device_allocs();
+// grow the stream's split-K workspace to the largest any launch uses
+void splitk_reserve(hipStream_t s);
 // what a gemm() call computes, for the profiler's classes and the kernel's name
 enum GemmTag { GEMM_PLAIN = 0, GEMM_GRAM = 1, GEMM_PROJ = 2 };
 struct GemmTagScope {
@@ -113,6 +118,8 @@ void copy2d(hipStream_t s, int rows, int cols, const double* src, long lds, doub
 
 // dst[j*ldd + i] = src[i*lds + j] for i < rows, j < cols
 void transpose_copy(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst, long ldd);
+// the same transpose from FP32 to FP64
+void transpose_widen(hipStream_t s, int rows, int cols, const float* src, long lds, double* dst, long ldd);
 // batch transposes: source b at src + b*sbatch, destination at dst + b*dbatch
 void transpose_copy_batched(hipStream_t s, int batch, int rows, int cols, const double* src, long sbatch, long lds,
                             double* dst, long dbatch, long ldd);
@@ -138,6 +145,13 @@ constexpr int ELL_WIDTH = 32;
 void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const double* eval,
               const double* x, int ldx, int xcol0, int ncols, double* y, int ldy, int ycol0, double alpha,
               double beta);
+// the same product in FP32 (values, input and output)
+void ell_spmm32(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const float* eval,
+                const float* x, int ldx, int xcol0, int ncols, float* y, int ldy, int ycol0, float alpha, float beta);
+// C (float, m x n) = A B from FP64 operands rounded to FP32, FP32
+// accumulation on the matrix cores (strides as for gemm, batch 1)
+void gemm_f32out(hipStream_t s, int m, int n, int k, const double* A, long sAi, long sAk, const double* B, long sBk,
+                 long sBj, float* C, long sCi, long sCj);
 
 // core1 block ops on row-major n1 x r matrices
 // out[t, col0 + a] = scale*(in[t,a] - in[t-1,a])          (kind 0: (I - C)/tau)
@@ -278,6 +292,7 @@ struct BcrDev {
   std::vector<double> pass_mk, pass_data, pass_rows;
   BcrOpDesc* ops = nullptr;
   double* data = nullptr;
+  float* data32 = nullptr;          // the same blocks in FP32 (reduced-precision mean solve)
   std::shared_ptr<BcrChoices> choices = std::make_shared<BcrChoices>();
 };
 // X <- A^-1 B for ncols columns of ncomp components (rows of one component;
@@ -290,6 +305,9 @@ int bcr_variant_count();
 bool bcr_variant_takes(const BcrDev& f, int variant);
 void bcr_solve_variant(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols,
                        int variant);
+// The same solve in FP32 (blocks data32, right-hand sides and solutions in
+// FP32, FP32 accumulation on the matrix cores), kernel variant tuned per pass.
+void bcr_solve32(hipStream_t s, const BcrDev& f, int ncomp, float* B, long ldb, float* X, long ldx, int ncols);
 // The same solve without timing variants: variant >= 0 for every pass, or
 // -1 for the choice an earlier bcr_solve tuned for this column bucket, else
 // the first variant that takes the blocks.  Launches only (no allocation).

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstdio>
 #include <cstdlib>
@@ -203,10 +204,10 @@ __device__ __forceinline__ short to_bf16(float x) {
 // round the FP64 operands when they are staged and accumulate in FP32.
 // K is staged through LDS in slices of 16, the next slice prefetched into
 // registers while the current one is consumed.
-template <int PREC>
+template <int PREC, typename CT = double>
 __device__ __forceinline__ void gemm_core(int m, int n, long kb, double alpha, const double* __restrict__ A, long sAi,
                                           long sAk, const double* __restrict__ B, long sBk, long sBj, double beta,
-                                          double* __restrict__ C, long sCi, long sCj, int i0, int j0) {
+                                          CT* __restrict__ C, long sCi, long sCj, int i0, int j0) {
   typedef typename std::conditional<PREC == GP_F64, double, float>::type st_t;
   typedef typename std::conditional<PREC == GP_F64, dbl4, flt4>::type acc_t;
   __shared__ st_t As[TK][TM + 1];
@@ -286,10 +287,10 @@ __device__ __forceinline__ void gemm_core(int m, int n, long kb, double alpha, c
       for (int tc = 0; tc < 2; ++tc) {
         const long gj = j0 + wc + tc * 16 + lr;
         if (gj >= n) continue;
-        double* cp = C + gi * sCi + gj * sCj;
+        CT* cp = C + gi * sCi + gj * sCj;
         double val = alpha * (double)acc[tr][tc][v];
-        if (beta != 0.0) val += beta * (*cp);
-        *cp = val;
+        if (beta != 0.0) val += beta * (double)(*cp);
+        *cp = (CT)val;
       }
     }
 }
@@ -311,6 +312,14 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, double alpha,
   }
   gemm_core<PREC>(m, n, kb, alpha, A + b * sAb, sAi, sAk, B + b * sBb, sBk, sBj, beta, C + b * sCb, sCi, sCj,
                   blockIdx.y * TM, blockIdx.x * TN);
+}
+
+// C (float) = A B with FP32 operands (rounded from FP64) and FP32
+// accumulation: the full-tensor expansion of the reduced-precision mean solve
+__global__ __launch_bounds__(256) void k_gemm_f32out(int m, int n, int k, const double* __restrict__ A, long sAi,
+                                                     long sAk, const double* __restrict__ B, long sBk, long sBj,
+                                                     float* __restrict__ C, long sCi, long sCj) {
+  gemm_core<GP_F32, float>(m, n, k, 1.0, A, sAi, sAk, B, sBk, sBj, 0.0, C, sCi, sCj, blockIdx.y * TM, blockIdx.x * TN);
 }
 
 template <int PREC>
@@ -405,9 +414,10 @@ __global__ void k_copy2d(int rows, int cols, const double* __restrict__ src, lon
 // dst[j][i] = src[i][j] through a 32 x 32 LDS tile: both the reads (along j)
 // and the writes (along i) are coalesced.  blockDim (32, 8); tiles walk the
 // rows with a grid stride so any row count fits the grid.
-__global__ __launch_bounds__(256) void k_transpose_copy(int rows, int cols, const double* __restrict__ src, long lds,
-                                                        long sbatch, double* __restrict__ dst, long ldd, long dbatch) {
-  __shared__ double tile[32][33];
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_transpose_copy(int rows, int cols, const TI* __restrict__ src, long lds,
+                                                        long sbatch, TO* __restrict__ dst, long ldd, long dbatch) {
+  __shared__ TO tile[32][33];
   src += blockIdx.z * sbatch;   // batch of independent transposes along grid z
   dst += blockIdx.z * dbatch;
   const int tx = threadIdx.x, ty = threadIdx.y;
@@ -417,7 +427,7 @@ __global__ __launch_bounds__(256) void k_transpose_copy(int rows, int cols, cons
     for (int q = 0; q < 4; ++q) {
       const long i = i0 + ty + 8 * q;
       const int j = j0 + tx;
-      if (i < rows && j < cols) tile[ty + 8 * q][tx] = src[i * lds + j];
+      if (i < rows && j < cols) tile[ty + 8 * q][tx] = (TO)src[i * lds + j];
     }
     __syncthreads();
 #pragma unroll
@@ -500,6 +510,10 @@ __device__ inline double readlane_f64(double v, int l) {
   const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
+__device__ inline double readlane_val(double v, int l) { return readlane_f64(v, l); }
+__device__ inline float readlane_val(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
 
 // One value array, rows of at most NZ entries: each lane holds one entry of
 // its wave's row, broadcast across the wave, so all the row's input loads
@@ -550,12 +564,11 @@ __global__ __launch_bounds__(256) void k_spmm_short(int nrows, int ics, int ocs,
 // are dealt round-robin over the 8 XCDs) takes a contiguous range of rows:
 // neighbouring rows share most of their inputs, which then stay in that
 // XCD's L2.  The grid is a multiple of 8 workgroups.
-template <int EW>
+template <int EW, typename T>
 __global__ __launch_bounds__(256) void k_ell_spmm(int nrows, int ics, int ocs,
-                                                  const int* __restrict__ ecol, const double* __restrict__ eval,
-                                                  const double* __restrict__ x, int ldx, int xcol0, int ncols,
-                                                  double* __restrict__ y, int ldy, int ycol0, double alpha,
-                                                  double beta) {
+                                                  const int* __restrict__ ecol, const T* __restrict__ eval,
+                                                  const T* __restrict__ x, int ldx, int xcol0, int ncols,
+                                                  T* __restrict__ y, int ldy, int ycol0, T alpha, T beta) {
   static_assert(EW <= WAVE, "one entry per lane");
   const unsigned per = gridDim.x / 8;
   const unsigned lb = (blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -565,41 +578,41 @@ __global__ __launch_bounds__(256) void k_ell_spmm(int nrows, int ics, int ocs,
   if (r >= nrows) return;
   static_assert(EW == 32, "entry groups of 16, 9 and 7");
   const int my_col = lane < EW ? ecol[r * EW + lane] : 0;
-  const double my_val = lane < EW ? eval[r * EW + lane] : 0.0;
+  const T my_val = lane < EW ? eval[r * EW + lane] : (T)0;
   // entries past the row's last one are padding (column r, value 0); the
   // row length decides, uniformly per wave, how many entry groups load
-  const unsigned long long real = __ballot(lane < EW && !(my_col == (int)r && my_val == 0.0));
+  const unsigned long long real = __ballot(lane < EW && !(my_col == (int)r && my_val == (T)0));
   const int n = real ? 64 - __clzll(real) : 0;
-  const double* xb = x + (long)c * ics * ldx + xcol0;
-  double* yb = y + ((long)c * ocs + r) * ldy + ycol0;
+  const T* xb = x + (long)c * ics * ldx + xcol0;
+  T* yb = y + ((long)c * ocs + r) * ldy + ycol0;
   for (int j0 = 0; j0 < ncols; j0 += WAVE) {
     const int j = j0 + lane;
     const bool act = j < ncols;
     const int jc = act ? j : ncols - 1;   // idle lanes read a valid column
-    const double yo = (act && beta != 0.0) ? yb[j] : 0.0;
+    const T yo = (act && beta != (T)0) ? yb[j] : (T)0;
     // within a group every load is valid (padding points at row r), so none
     // is predicated and the group's loads are issued back to back
-    double acc = 0.0;
+    T acc = 0;
     {
-      double xv[16];
+      T xv[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) xv[q] = xb[(long)__builtin_amdgcn_readlane(my_col, q) * ldx + jc];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) acc = fma(readlane_f64(my_val, q), xv[q], acc);
+      for (int q = 0; q < 16; ++q) acc = fma(readlane_val(my_val, q), xv[q], acc);
     }
     if (n > 16) {
-      double xv[9];
+      T xv[9];
 #pragma unroll
       for (int q = 0; q < 9; ++q) xv[q] = xb[(long)__builtin_amdgcn_readlane(my_col, 16 + q) * ldx + jc];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) acc = fma(readlane_f64(my_val, 16 + q), xv[q], acc);
+      for (int q = 0; q < 9; ++q) acc = fma(readlane_val(my_val, 16 + q), xv[q], acc);
     }
     if (n > 25) {
-      double xv[7];
+      T xv[7];
 #pragma unroll
       for (int q = 0; q < 7; ++q) xv[q] = xb[(long)__builtin_amdgcn_readlane(my_col, 25 + q) * ldx + jc];
 #pragma unroll
-      for (int q = 0; q < 7; ++q) acc = fma(readlane_f64(my_val, 25 + q), xv[q], acc);
+      for (int q = 0; q < 7; ++q) acc = fma(readlane_val(my_val, 25 + q), xv[q], acc);
     }
     if (act) yb[j] = alpha * acc + beta * yo;
   }
@@ -1539,24 +1552,21 @@ __device__ __forceinline__ void bcr_split_load(const BcrOpDesc& d, int t, const 
 // padding of the fragment); k-steps past a term's end, and the last term
 // loaded again where the last round of terms runs short, are multiplied by
 // an exact zero.
-template <int CB, int KQ, int TP, int TG>
-__global__ __launch_bounds__(256 * TG) void k_bcr_split(const BcrOpDesc* __restrict__ ops, int op0, int nops,
-                                                        const double* __restrict__ data, double* __restrict__ B,
-                                                        long ldb, double* __restrict__ X, long ldx, int ncols,
-                                                        int ncomp, long comp_rows) {
+template <int CB, int KQ, int TP>
+__global__ __launch_bounds__(256) void k_bcr_split(const BcrOpDesc* __restrict__ ops, int op0, int nops,
+                                                   const double* __restrict__ data, double* __restrict__ B, long ldb,
+                                                   double* __restrict__ X, long ldx, int ncols, int ncomp,
+                                                   long comp_rows) {
   constexpr int NCT = CB / 16;
   static_assert(CB % 16 == 0, "column tiles of 16");
-  __shared__ double red[4 * TG][NCT * 256];
+  __shared__ double red[4][NCT * 256];
   if ((int)blockIdx.x >= nops) return;   // grid padding (uniform per workgroup)
   const BcrOpDesc& d = ops[op0 + blockIdx.x];
   const int rt = blockIdx.z;
   const int r0 = d.r0, bo = d.bo;
   if (rt * 16 >= bo) return;   // uniform per workgroup
   const int j0 = blockIdx.y * CB;
-  // wave w belongs to term group w / 4 and owns k-steps w % 4, w % 4 + 4, ...
-  // of that group's terms
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-  const int grp = wave / 4, wq = wave % 4;
   const int lr = lane % 16, lk = lane / 16;
   const int ctot = ncomp * ncols;
   // this lane's B-operand columns, clamped to a valid one
@@ -1574,11 +1584,10 @@ __global__ __launch_bounds__(256 * TG) void k_bcr_split(const BcrOpDesc* __restr
   dbl4 acc[NCT];
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct) acc[ct] = dbl4{0.0, 0.0, 0.0, 0.0};
-  // term group g takes the rounds of TP terms starting at g TP, g TP + TG TP, ...
-  for (int t0 = grp * TP; t0 < nterm; t0 += TP * TG) {
+  for (int t0 = 0; t0 < nterm; t0 += TP) {
 #pragma unroll
     for (int u = 0; u < TP; ++u)
-      bcr_split_load<KQ, NCT>(d, min(t0 + u, nterm - 1), data, rt, wq, lk, lane, B, ldb, X, ldx, cb_off, cb_col,
+      bcr_split_load<KQ, NCT>(d, min(t0 + u, nterm - 1), data, rt, wave, lk, lane, B, ldb, X, ldx, cb_off, cb_col,
                               a[u], x[u]);
     __builtin_amdgcn_sched_barrier(0);   // keeps the round's loads ahead of its products
     // no branches between the loads and their use, so that every load of
@@ -1591,7 +1600,7 @@ __global__ __launch_bounds__(256 * TG) void k_bcr_split(const BcrOpDesc* __restr
       const double coef = (t0 + u < nterm) ? d.coef[t] : 0.0;
 #pragma unroll
       for (int s = 0; s < KQ; ++s) {
-        const double av = (wq + 4 * s < nq) ? coef * a[u][s] : 0.0;
+        const double av = (wave + 4 * s < nq) ? coef * a[u][s] : 0.0;
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct)
           acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, x[u][s][ct], acc[ct], 0, 0, 0);
@@ -1603,20 +1612,115 @@ __global__ __launch_bounds__(256 * TG) void k_bcr_split(const BcrOpDesc* __restr
 #pragma unroll
     for (int v = 0; v < 4; ++v) red[wave][(ct * 4 + v) * 64 + lane] = acc[ct][v];
   __syncthreads();
-  if (tid >= 256) return;
   const bool to_x = d.flags & 2;
   double* out = to_x ? X : B;
   const long ldo = to_x ? ldx : ldb;
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct) {
     // thread tid sums accumulator item (ct, v = tid / 64, lane tid % 64)
-    // over the waves, pairwise within each term group, groups in order
     const int e = ct * 256 + tid, v = tid / 64, l = tid % 64;
     const int r = rt * 16 + 4 * v + l / 16, j = j0 + ct * 16 + l % 16;
     if (r < bo && j < ctot) {
       double sum = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+      const int comp = j / ncols, c = j - comp * ncols;
+      if (d.flags & 1) sum += B[((long)comp * comp_rows + r0 + r) * ldb + c];
+      out[((long)comp * comp_rows + r0 + r) * ldo + c] = sum;
+    }
+  }
+}
+
+
+// FP32 form of the split-k pass for the reduced-precision mean solve: blocks
+// in the same fragment order as FP32 values, right-hand sides and solutions
+// in FP32, products on v_mfma_f32_16x16x4f32 with FP32 accumulation (lane l
+// supplies M[l%16][l/16] and V[l/16][l%16] as in FP64; accumulator item v is
+// D[4(l/16) + v][l%16]).
+template <int KQ, int NCT>
+__device__ __forceinline__ void bcr_split_load32(const BcrOpDesc& d, int t, const float* __restrict__ data, int rt,
+                                                 int wave, int lk, int lane, const float* B, long ldb, const float* X,
+                                                 long ldx, const long (&cb_off)[NCT], const int (&cb_col)[NCT],
+                                                 float (&fa)[KQ], float (&fx)[KQ][NCT]) {
+  const int i0 = d.in_r0[t], bi = d.in_bi[t];
+  const int nq = (bi + 3) / 4;
+  const float* M = data + d.off[t] + ((long)rt * nq + wave) * 64 + lane;
+  const bool from_x = (d.in_x >> t) & 1;
+  const float* src = from_x ? X : B;
+  const long ld = from_x ? ldx : ldb;
 #pragma unroll
-      for (int g = 1; g < TG; ++g) sum += (red[4 * g][e] + red[4 * g + 1][e]) + (red[4 * g + 2][e] + red[4 * g + 3][e]);
+  for (int s = 0; s < KQ; ++s) {
+    fa[s] = M[(long)s * 256];
+    const int k = min(4 * (wave + 4 * s) + lk, bi - 1);
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) fx[s][ct] = src[(cb_off[ct] + i0 + k) * ld + cb_col[ct]];
+  }
+}
+
+template <int CB, int KQ, int TP>
+__global__ __launch_bounds__(256) void k_bcr_split32(const BcrOpDesc* __restrict__ ops, int op0, int nops,
+                                                     const float* __restrict__ data, float* __restrict__ B, long ldb,
+                                                     float* __restrict__ X, long ldx, int ncols, int ncomp,
+                                                     long comp_rows) {
+  constexpr int NCT = CB / 16;
+  static_assert(CB % 16 == 0, "column tiles of 16");
+  __shared__ float red[4][NCT * 256];
+  if ((int)blockIdx.x >= nops) return;   // grid padding (uniform per workgroup)
+  const BcrOpDesc& d = ops[op0 + blockIdx.x];
+  const int rt = blockIdx.z;
+  const int r0 = d.r0, bo = d.bo;
+  if (rt * 16 >= bo) return;   // uniform per workgroup
+  const int j0 = blockIdx.y * CB;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int lr = lane % 16, lk = lane / 16;
+  const int ctot = ncomp * ncols;
+  long cb_off[NCT];
+  int cb_col[NCT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    const int j = min(j0 + ct * 16 + lr, ctot - 1);
+    const int comp = j / ncols;
+    cb_off[ct] = (long)comp * comp_rows;
+    cb_col[ct] = j - comp * ncols;
+  }
+  const int nterm = d.nterm;
+  float a[TP][KQ], x[TP][KQ][NCT];
+  flt4 acc[NCT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) acc[ct] = flt4{0.f, 0.f, 0.f, 0.f};
+  for (int t0 = 0; t0 < nterm; t0 += TP) {
+#pragma unroll
+    for (int u = 0; u < TP; ++u)
+      bcr_split_load32<KQ, NCT>(d, min(t0 + u, nterm - 1), data, rt, wave, lk, lane, B, ldb, X, ldx, cb_off, cb_col,
+                                a[u], x[u]);
+    __builtin_amdgcn_sched_barrier(0);   // keeps the round's loads ahead of its products
+#pragma unroll
+    for (int u = 0; u < TP; ++u) {
+      const int t = min(t0 + u, nterm - 1);
+      const int nq = (d.in_bi[t] + 3) / 4;
+      const float coef = (t0 + u < nterm) ? (float)d.coef[t] : 0.f;
+#pragma unroll
+      for (int s = 0; s < KQ; ++s) {
+        const float av = (wave + 4 * s < nq) ? coef * a[u][s] : 0.f;
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+          acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, x[u][s][ct], acc[ct], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave][(ct * 4 + v) * 64 + lane] = acc[ct][v];
+  __syncthreads();
+  const bool to_x = d.flags & 2;
+  float* out = to_x ? X : B;
+  const long ldo = to_x ? ldx : ldb;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    // thread tid sums accumulator item (ct, v = tid / 64, lane tid % 64)
+    const int e = ct * 256 + tid, v = tid / 64, l = tid % 64;
+    const int r = rt * 16 + 4 * (l / 16) + v, j = j0 + ct * 16 + l % 16;
+    if (r < bo && j < ctot) {
+      float sum = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
       const int comp = j / ncols, c = j - comp * ncols;
       if (d.flags & 1) sum += B[((long)comp * comp_rows + r0 + r) * ldb + c];
       out[((long)comp * comp_rows + r0 + r) * ldo + c] = sum;
@@ -2005,6 +2109,7 @@ namespace {
 // on one stream is ordered, so the buffer is reused safely); grown on demand
 std::mutex g_splitk_mu;
 std::unordered_map<hipStream_t, std::pair<double*, size_t>> g_splitk;
+std::atomic<long> g_kernel_allocs{0};   // hipMalloc calls made here (workspaces, tuning copies)
 double* splitk_ws(hipStream_t s, size_t n) {
   std::lock_guard<std::mutex> lk(g_splitk_mu);
   auto& e = g_splitk[s];
@@ -2015,6 +2120,7 @@ double* splitk_ws(hipStream_t s, size_t n) {
     }
     e.first = nullptr;
     e.second = 0;
+    ++g_kernel_allocs;
     if (hipMalloc(&e.first, n * sizeof(double)) != hipSuccess) {
       (void)hipGetLastError();
       e.first = nullptr;
@@ -2054,6 +2160,14 @@ int gemm_class() {
   return g_gemm_tag == GEMM_GRAM ? KC_GRAM : (g_gemm_tag == GEMM_PROJ ? KC_PROJ : KC_GEMM);
 }
 }  // namespace
+
+long kernel_device_allocs() { return g_kernel_allocs.load(); }
+
+// the split-K partial sums of one launch never exceed 256 chunks of at
+// most 256 / chunks output tiles of 64 x 64
+void splitk_reserve(hipStream_t s) {
+  if (!splitk_ws(s, (size_t)256 * 64 * 64)) throw std::runtime_error("split-K workspace: device allocation failed");
+}
 
 GemmTagScope::GemmTagScope(int tag) : old(g_gemm_tag) { g_gemm_tag = tag; }
 GemmTagScope::~GemmTagScope() { g_gemm_tag = old; }
@@ -2106,6 +2220,14 @@ void gemm_batched(hipStream_t s, int nb, const GemmDesc* d_desc, int max_m, int 
   }
 }
 
+void gemm_f32out(hipStream_t s, int m, int n, int k, const double* A, long sAi, long sAk, const double* B, long sBk,
+                 long sBj, float* C, long sCi, long sCj) {
+  if (m <= 0 || n <= 0) return;
+  ProfScope ps(KC_GEMM_LOWP, s, 8.0 * ((double)m * k + (double)k * n) + 4.0 * m * (double)n, 2.0 * m * n * (double)k);
+  hipLaunchKernelGGL(k_gemm_f32out, dim3(cdiv(n, TN), cdiv(m, TM)), dim3(256), 0, s, m, n, k, A, sAi, sAk, B, sBk, sBj,
+                     C, sCi, sCj);
+}
+
 void gram(hipStream_t s, long rows, int nx, int ny, const double* X, long sXr, long sXc, const double* Y, long sYr,
           long sYc, double* out, double* ws, size_t ws_doubles) {
   GemmPrecisionScope f64(GP_F64);   // Grams decide truncations: always FP64
@@ -2156,12 +2278,20 @@ void transpose_copy_batched(hipStream_t s, int batch, int rows, int cols, const 
   if (batch > 65535) throw std::runtime_error("transpose_copy_batched: batch too large");
   const unsigned gx = (unsigned)cdiv(cols, 32);
   const unsigned gy = (unsigned)std::min<long>(cdiv(rows, 32), std::max<long>(1, 65536 / ((long)gx * batch)));
-  hipLaunchKernelGGL(k_transpose_copy, dim3(gx, std::max(1u, std::min(gy, 65535u)), batch), dim3(32, 8), 0, s, rows,
+  hipLaunchKernelGGL((k_transpose_copy<double, double>), dim3(gx, std::max(1u, std::min(gy, 65535u)), batch), dim3(32, 8), 0, s, rows,
                      cols, src, lds, sbatch, dst, ldd, dbatch);
 }
 
 void transpose_copy(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst, long ldd) {
   transpose_copy_batched(s, 1, rows, cols, src, 0, lds, dst, 0, ldd);
+}
+
+void transpose_widen(hipStream_t s, int rows, int cols, const float* src, long lds, double* dst, long ldd) {
+  if (rows <= 0 || cols <= 0) return;
+  const unsigned gx = (unsigned)cdiv(cols, 32);
+  const unsigned gy = (unsigned)std::min<long>(cdiv(rows, 32), std::max<long>(1, 65536 / (long)gx));
+  hipLaunchKernelGGL((k_transpose_copy<float, double>), dim3(gx, std::max(1u, std::min(gy, 65535u)), 1), dim3(32, 8),
+                     0, s, rows, cols, src, lds, 0L, dst, ldd, 0L);
 }
 
 void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const double* eval,
@@ -2172,8 +2302,19 @@ void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* 
                     8.0 * ncomp * (double)nrows * ncols * (beta != 0.0 ? 2.0 : 1.0);
   ProfScope ps(KC_ELL, s, by, 2.0 * ELL_WIDTH * (double)nrows * ncomp * ncols);
   const unsigned nb = 8 * cdiv(cdiv(nrows, 4), 8);
-  hipLaunchKernelGGL(k_ell_spmm<ELL_WIDTH>, dim3(nb, ncomp), dim3(256), 0, s, nrows, ics, ocs, ecol, eval, x, ldx,
-                     xcol0, ncols, y, ldy, ycol0, alpha, beta);
+  hipLaunchKernelGGL((k_ell_spmm<ELL_WIDTH, double>), dim3(nb, ncomp), dim3(256), 0, s, nrows, ics, ocs, ecol, eval, x,
+                     ldx, xcol0, ncols, y, ldy, ycol0, alpha, beta);
+}
+
+void ell_spmm32(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const float* eval,
+                const float* x, int ldx, int xcol0, int ncols, float* y, int ldy, int ycol0, float alpha, float beta) {
+  if (nrows <= 0 || ncols <= 0 || ncomp <= 0) return;
+  const double by = 8.0 * ELL_WIDTH * nrows + 4.0 * ncomp * ((double)nrows * ncols) +
+                    4.0 * ncomp * (double)nrows * ncols * (beta != 0.0f ? 2.0 : 1.0);
+  ProfScope ps(KC_ELL, s, by, 2.0 * ELL_WIDTH * (double)nrows * ncomp * ncols);
+  const unsigned nb = 8 * cdiv(cdiv(nrows, 4), 8);
+  hipLaunchKernelGGL((k_ell_spmm<ELL_WIDTH, float>), dim3(nb, ncomp), dim3(256), 0, s, nrows, ics, ocs, ecol, eval, x,
+                     ldx, xcol0, ncols, y, ldy, ycol0, alpha, beta);
 }
 
 void spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* rowptr, const int* col, const double* vals,
@@ -2319,7 +2460,6 @@ struct BcrVariant {
   int max_rows;   // largest block the variant takes
   int wg_rows;    // output rows per workgroup (grid z covers the largest block)
   decltype(&k_bcr_stream<32, 8>) fn;
-  int threads = 256;   // workgroup size
 };
 const BcrVariant kBcrVariants[] = {
     {32, BCR_MAXBS, 64, k_bcr_stream<32, 8>},  {16, BCR_MAXBS, 64, k_bcr_stream<16, 8>},
@@ -2328,11 +2468,9 @@ const BcrVariant kBcrVariants[] = {
     {32, 128, 64, k_bcr_tile<32, 32, false>},  {16, 64, 64, k_bcr_tile<16, 16, true>},
     {32, 64, 64, k_bcr_tile<32, 16, true>},    {48, 128, 64, k_bcr_tile<48, 32, true>},
     {48, 128, 64, k_bcr_tile<48, 32, false>},  {80, 128, 64, k_bcr_tile<80, 32, false>},
-    {16, 128, 16, k_bcr_split<16, 8, 1, 1>},   {16, 128, 16, k_bcr_split<16, 8, 2, 1>},
-    {16, 128, 16, k_bcr_split<16, 8, 4, 1>},   {32, 128, 16, k_bcr_split<32, 8, 1, 1>},
-    {32, 128, 16, k_bcr_split<32, 8, 2, 1>},   {16, 256, 16, k_bcr_split<16, 16, 1, 1>},
-    {16, 128, 16, k_bcr_split<16, 8, 1, 2>, 512}, {16, 128, 16, k_bcr_split<16, 8, 1, 4>, 1024},
-    {16, 128, 16, k_bcr_split<16, 8, 2, 2>, 512}, {32, 128, 16, k_bcr_split<32, 8, 1, 2>, 512}};
+    {16, 128, 16, k_bcr_split<16, 8, 1>},      {16, 128, 16, k_bcr_split<16, 8, 2>},
+    {16, 128, 16, k_bcr_split<16, 8, 4>},      {32, 128, 16, k_bcr_split<32, 8, 1>},
+    {32, 128, 16, k_bcr_split<32, 8, 2>},      {16, 256, 16, k_bcr_split<16, 16, 1>}};
 constexpr int kNumBcrVariants = sizeof(kBcrVariants) / sizeof(kBcrVariants[0]);
 
 // ev (npass + 1 events, optional) brackets every pass.  The profiler sees
@@ -2358,7 +2496,7 @@ void bcr_run(hipStream_t s, const BcrDev& f, const std::vector<int>& vars, int n
     // padded to a multiple of 8, every column chunk and row group of an op
     // runs on the same XCD and shares its blocks through that XCD's L2
     const unsigned gx = 8 * cdiv(no, 8);
-    hipLaunchKernelGGL(v.fn, dim3(gx, cdiv((long)ncomp * ncols, v.cb), cdiv(f.maxbs, v.wg_rows)), dim3(v.threads), 0, s,
+    hipLaunchKernelGGL(v.fn, dim3(gx, cdiv((long)ncomp * ncols, v.cb), cdiv(f.maxbs, v.wg_rows)), dim3(256), 0, s,
                        f.ops, o0, no, f.data, B, ldb, X, ldx, ncols, ncomp, (long)f.n);
   }
   if (ev) (void)hipEventRecord(ev[f.npass], s);
@@ -2371,6 +2509,7 @@ std::vector<int> bcr_tune(hipStream_t s, const BcrDev& f, int ncomp, const doubl
   std::vector<int> best(np, 0);
   const long rows = (long)ncomp * f.n;
   double *b0 = nullptr, *bw = nullptr, *xw = nullptr;
+  g_kernel_allocs += 3;
   if (hipMalloc(&b0, sizeof(double) * rows * ncols) != hipSuccess ||
       hipMalloc(&bw, sizeof(double) * rows * ncols) != hipSuccess ||
       hipMalloc(&xw, sizeof(double) * rows * ncols) != hipSuccess) {
@@ -2478,6 +2617,113 @@ void bcr_solve_untuned(hipStream_t s, const BcrDev& f, int ncomp, double* B, lon
     }
   }
   bcr_run(s, f, vars, ncomp, B, ldb, X, ldx, ncols);
+}
+
+// ---- FP32 passes of the reduced-precision mean solve
+namespace {
+struct BcrVariant32 {
+  int cb;
+  int max_rows;
+  decltype(&k_bcr_split32<16, 8, 1>) fn;
+};
+const BcrVariant32 kBcrVariants32[] = {{16, 128, k_bcr_split32<16, 8, 1>},
+                                       {16, 128, k_bcr_split32<16, 8, 2>},
+                                       {32, 128, k_bcr_split32<32, 8, 1>},
+                                       {16, 256, k_bcr_split32<16, 16, 1>}};
+constexpr int kNumBcrVariants32 = sizeof(kBcrVariants32) / sizeof(kBcrVariants32[0]);
+
+void bcr_run32(hipStream_t s, const BcrDev& f, const std::vector<int>& vars, int ncomp, float* B, long ldb, float* X,
+               long ldx, int ncols, hipEvent_t* ev = nullptr) {
+  if (!f.data32) throw std::runtime_error("block cyclic reduction: factor without FP32 blocks");
+  if ((int)vars.size() != f.npass) throw std::runtime_error("block cyclic reduction: variant list does not match");
+  for (int v : vars)
+    if (v < 0 || v >= kNumBcrVariants32 || f.maxbs > kBcrVariants32[v].max_rows)
+      throw std::runtime_error("block cyclic reduction: variant does not take the factor's blocks");
+  const double cols = (double)ncomp * ncols;
+  ProfScope ps(KC_BCR, s, 0.0, 0.0, 0);
+  for (int p = 0; p < f.npass; ++p) {
+    if (ev) (void)hipEventRecord(ev[p], s);
+    const int o0 = f.pass_begin[p], no = f.pass_begin[p + 1] - o0;
+    if (no <= 0) continue;
+    const BcrVariant32& v = kBcrVariants32[vars[p]];
+    ps.add(4.0 * (f.pass_data[p] + f.pass_rows[p] * cols), 2.0 * f.pass_mk[p] * cols, 1);
+    const unsigned gx = 8 * cdiv(no, 8);   // op index padded to a multiple of 8 (XCD-aware, as in FP64)
+    hipLaunchKernelGGL(v.fn, dim3(gx, cdiv((long)ncomp * ncols, v.cb), cdiv(f.maxbs, 16)), dim3(256), 0, s, f.ops, o0,
+                       no, f.data32, B, ldb, X, ldx, ncols, ncomp, (long)f.n);
+  }
+  if (ev) (void)hipEventRecord(ev[f.npass], s);
+}
+
+std::vector<int> bcr_tune32(hipStream_t s, const BcrDev& f, int ncomp, const float* B, long ldb, int ncols) {
+  const int np = f.npass;
+  std::vector<int> best(np, 0);
+  const long rows = (long)ncomp * f.n;
+  float *b0 = nullptr, *bw = nullptr, *xw = nullptr;
+  g_kernel_allocs += 3;
+  if (hipMalloc(&b0, sizeof(float) * rows * ncols) != hipSuccess ||
+      hipMalloc(&bw, sizeof(float) * rows * ncols) != hipSuccess ||
+      hipMalloc(&xw, sizeof(float) * rows * ncols) != hipSuccess) {
+    (void)hipGetLastError();
+    for (float* p : {b0, bw, xw})
+      if (p) (void)hipFree(p);
+    return best;
+  }
+  (void)hipMemcpy2DAsync(b0, sizeof(float) * ncols, B, sizeof(float) * ldb, sizeof(float) * ncols, rows,
+                         hipMemcpyDeviceToDevice, s);
+  (void)hipMemcpyAsync(xw, b0, sizeof(float) * rows * ncols, hipMemcpyDeviceToDevice, s);
+  std::vector<hipEvent_t> ev(np + 1);
+  for (auto& e : ev) (void)hipEventCreate(&e);
+  std::vector<float> best_ms(np, 1e30f);
+  for (int v = 0; v < kNumBcrVariants32; ++v) {
+    if (f.maxbs > kBcrVariants32[v].max_rows) continue;
+    const std::vector<int> vv(np, v);
+    std::vector<float> tot(np, 0.f);
+    for (int rep = 0; rep < 3; ++rep) {
+      (void)hipMemcpyAsync(bw, b0, sizeof(float) * rows * ncols, hipMemcpyDeviceToDevice, s);
+      bcr_run32(s, f, vv, ncomp, bw, ncols, xw, ncols, ncols, ev.data());
+      (void)hipEventSynchronize(ev[np]);
+      if (rep == 0) continue;
+      for (int p = 0; p < np; ++p) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[p], ev[p + 1]);
+        tot[p] += ms;
+      }
+    }
+    for (int p = 0; p < np; ++p)
+      if (tot[p] < best_ms[p]) {
+        best_ms[p] = tot[p];
+        best[p] = v;
+      }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  (void)hipStreamSynchronize(s);
+  for (float* p : {b0, bw, xw}) (void)hipFree(p);
+  return best;
+}
+}  // namespace
+
+void bcr_solve32(hipStream_t s, const BcrDev& f, int ncomp, float* B, long ldb, float* X, long ldx, int ncols) {
+  if (ncols <= 0 || f.npass == 0) return;
+  if (!f.choices) throw std::runtime_error("block cyclic reduction: factor without a choice table");
+  std::vector<int> vars;
+  BcrChoices& ch = *f.choices;
+  auto key = bcr_choice_key(ncomp, ncols);
+  key.second += 64;   // FP32 choices are kept apart from the FP64 ones
+  std::unique_lock<std::mutex> lk(ch.mu);
+  auto it = ch.by_key.find(key);
+  if (it != ch.by_key.end()) {
+    vars = it->second;
+  } else {
+    lk.unlock();
+    const unsigned was = prof_mask();
+    prof_enable_mask(0u);
+    vars = bcr_tune32(s, f, ncomp, B, ldb, ncols);
+    prof_enable_mask(was);
+    lk.lock();
+    ch.by_key[key] = vars;
+  }
+  lk.unlock();
+  bcr_run32(s, f, vars, ncomp, B, ldb, X, ldx, ncols);
 }
 
 int bcr_variant_count() { return kNumBcrVariants; }

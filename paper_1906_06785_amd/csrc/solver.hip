@@ -76,7 +76,7 @@ DevCsr upload_csr(Ctx& c, const Csr& pat, const std::vector<const double*>& vals
 }
 
 void free_bcr(BcrDev& d) {
-  for (void* p : {(void*)d.ops, (void*)d.data})
+  for (void* p : {(void*)d.ops, (void*)d.data, (void*)d.data32})
     if (p) (void)hipFree(p);
   d = BcrDev();
 }
@@ -152,6 +152,9 @@ BcrDev upload_bcr(Ctx& c, const BcrFactor& f) {
   d.ndata = (double)frag.size();
   d.ops = dev_upload(c, ops);
   d.data = dev_upload(c, frag);
+  // the blocks once more in FP32 for the reduced-precision mean solve
+  std::vector<float> frag32(frag.begin(), frag.end());
+  d.data32 = dev_upload(c, frag32);
   return d;
 }
 
@@ -196,6 +199,7 @@ struct sgtt_system {
   BcrDev Fbt, Xbt;         // F_avg and X = B M*^-1 B^T (block cyclic reduction)
   int* Me_col = nullptr;   // M in padded-row form (time coupling of the mean solve)
   double* Me_val = nullptr;
+  float* Me_val32 = nullptr;   // the same values in FP32 (reduced-precision mean solve)
   TT bu, bp;               // right-hand side
   double* Dinv = nullptr;  // 1 / diag(F_avg) on free scalar nodes
   sgtt::Mlp* mlp_collect = nullptr;   // records (r, F_avg^-1 r) pairs from mean solves
@@ -217,7 +221,7 @@ struct sgtt_system {
     Mpinv.free_all();
     free_bcr(Fbt);
     free_bcr(Xbt);
-    for (void* p : {(void*)Me_col, (void*)Me_val})
+    for (void* p : {(void*)Me_col, (void*)Me_val, (void*)Me_val32})
       if (p) (void)hipFree(p);
     for (double* p : {Gnu, w1, Hw, omega, dsc, Dinv}) (void)hipFree(p);
   }
@@ -616,6 +620,42 @@ struct PrecOpts {
 // F_avg on the diagonal and -tau^-1 M below, identity in the chaos mode:
 // block forward substitution in time on the full-format velocity (node-major,
 // columns (t, xi)), then TT-SVD (Alg. 4.1) at eps.
+// The same solve in FP32 (precision option 1): the expansion writes the full
+// velocity tensor in FP32 (FP32 operands, FP32 accumulation), the time steps
+// run the FP32 ELL mass product and FP32 block cyclic reduction passes, and
+// the transpose widens the result to FP64 for the TT-SVD, whose Grams, rank
+// decisions and projections stay FP64.  The result is accurate to FP32
+// rounding relative to the exact one, far below the inner truncation eps.
+TT exact_mean_solve32(sgtt_system& S, const TT& y, double eps) {
+  Ctx& c = S.ctx->c;
+  const int nt = S.nt, nxi = S.nxi, nu = S.nu;
+  const long ldw = (long)nt * nxi;
+  double* Z = c.pool.get((size_t)ldw * y.r2);   // G1 x_1 G2: (nt nxi) x r2
+  gemm(c.s, 1, nt, nxi * y.r2, y.r1, 1.0, y.c1, 0, y.r1, 1, y.c2, 0, (long)nxi * y.r2, 1, 0.0, Z, 0,
+       (long)nxi * y.r2, 1);
+  const size_t nfull = (size_t)nu * ldw;
+  double* Wd = c.pool.get((nfull + 1) / 2);      // node-major FP32 tensor W[x][t nxi + xi]
+  float* W = reinterpret_cast<float*>(Wd);
+  gemm_f32out(c.s, nu, (int)ldw, y.r2, y.c3, y.r2, 1, Z, 1, y.r2, W, ldw, 1);
+  c.pool.put(Z);
+  double* Vd = c.pool.get((nfull + 1) / 2);      // FP32 solution, same layout
+  float* Vn = reinterpret_cast<float*>(Vd);
+  for (int t = 0; t < nt; ++t) {
+    float* Wt = W + (long)t * nxi;
+    if (t > 0)   // y_t + tau^-1 M v_{t-1}
+      ell_spmm32(c.s, S.ns, 2, S.ns, S.ns, S.Me_col, S.Me_val32, Vn + (long)(t - 1) * nxi, (int)ldw, 0, nxi, Wt,
+                 (int)ldw, 0, (float)(1.0 / S.tau), 1.0f);
+    bcr_solve32(c.s, S.Fbt, 2, Wt, ldw, Vn + (long)t * nxi, ldw, nxi);
+  }
+  c.pool.put(Wd);
+  double* V = c.pool.get(nfull);                 // C order (t, xi, x), FP64
+  transpose_widen(c.s, nu, (int)ldw, Vn, ldw, V, nu);
+  c.pool.put(Vd);
+  TT out = tt_from_full(c, V, nt, nxi, nu, eps, nullptr);
+  c.pool.put(V);
+  return out;
+}
+
 TT exact_mean_solve(sgtt_system& S, const TT& y, double eps) {
   Ctx& c = S.ctx->c;
   const int nt = S.nt, nxi = S.nxi, nu = S.nu;
@@ -689,7 +729,8 @@ Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCoun
     RegionScope rg(RG_IN_MINV);
     Vec out;
     out.nc = 2;
-    out.c[0] = exact_mean_solve(S, rhs.c[0], po.inner_eps);
+    out.c[0] = po.precision != GP_F64 ? exact_mean_solve32(S, rhs.c[0], po.inner_eps)
+                                      : exact_mean_solve(S, rhs.c[0], po.inner_eps);
     out.c[1] = std::move(ph);
     return out;
   }
@@ -991,6 +1032,25 @@ int sgtt_context_create(int device, void* stream, sgtt_context** out) {
   return SGTT_OK;
 }
 
+int sgtt_context_reserve(sgtt_context* ctx, size_t bytes) {
+  if (!ctx) return SGTT_E_INVALID;
+  return guarded(ctx, [&]() {
+    ctx->c.sync();
+    ctx->c.pool.reserve(bytes / sizeof(double));
+    splitk_reserve(ctx->c.s);
+  });
+}
+
+int sgtt_context_memory(const sgtt_context* ctx, sgtt_memory_info* out) {
+  if (!ctx || !out) return SGTT_E_INVALID;
+  const Pool& p = ctx->c.pool;
+  out->arena_bytes = p.arena_bytes();
+  out->arena_peak_bytes = p.arena_peak_bytes();
+  out->cached_bytes = p.bytes_held();
+  out->device_allocs = p.device_allocs();
+  return SGTT_OK;
+}
+
 int sgtt_context_destroy(sgtt_context* ctx) {
   if (!ctx) return SGTT_E_INVALID;
   (void)hipStreamSynchronize(ctx->c.s);
@@ -1053,6 +1113,7 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
       }
     }
     S->Me_col = dev_upload(c, ec);
+    S->Me_val32 = dev_upload(c, std::vector<float>(ev.begin(), ev.end()));
     S->Me_val = dev_upload(c, ev);
   }
   const int nt = S->nt, nxi = S->nxi, nall = S->nall, ns = S->ns;
@@ -1474,6 +1535,7 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
     throw SgttError(-1, "invalid solve options");
   double t0 = now_s();
   long r0 = c.roundings;
+  const long a0 = c.pool.device_allocs() + kernel_device_allocs();
   SolveCounters cnt;
   cnt.verbose = o.verbose;
   OuterSpace sp(*S, prec_opts(&o), &cnt);
@@ -1527,6 +1589,7 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
     stats->t_residual = 0;
     stats->learned_calls = S->mlp_calls;
     stats->learned_fallback = S->mlp_off ? 1 : 0;
+    stats->device_allocs = c.pool.device_allocs() + kernel_device_allocs() - a0;
   }
   return rel > o.tol ? SGTT_W_NOT_CONVERGED : SGTT_OK;
 }

@@ -26,17 +26,35 @@ struct SgttError : std::runtime_error {
   } while (0)
 
 // Caching device allocator: blocks are reused stream-ordered on one stream.
+// With a reservation (reserve), blocks are first carved out of one arena
+// allocated up front (first fit, freed blocks coalesce), so that work done
+// after the reservation allocates no device memory while the arena suffices;
+// blocks beyond it come from hipMalloc and are cached as before.
 class Pool {
  public:
   ~Pool();
   double* get(size_t ndoubles);
   void put(double* p);
+  // allocate an arena of ndoubles (replaces an empty earlier one; fails if
+  // blocks of the old arena are in use)
+  void reserve(size_t ndoubles);
   size_t bytes_held() const { return held_; }
+  size_t arena_bytes() const { return arena_n_ * sizeof(double); }
+  size_t arena_peak_bytes() const { return arena_peak_ * sizeof(double); }
+  long device_allocs() const { return device_allocs_; }   // hipMalloc calls so far
 
  private:
   std::unordered_map<double*, size_t> size_;
   std::multimap<size_t, double*> free_;
   size_t held_ = 0;
+  long device_allocs_ = 0;
+  // arena: [arena_, arena_ + arena_n_), free ranges by offset (doubles)
+  double* arena_ = nullptr;
+  size_t arena_n_ = 0, arena_used_ = 0, arena_peak_ = 0;
+  std::map<size_t, size_t> arena_free_;
+  std::unordered_map<double*, size_t> arena_size_;
+  double* arena_get(size_t n);
+  bool arena_put(double* p);
 };
 
 // Device TT: core1 n1 x r1 (ld r1), core2 r1 x n2 x r2, core3 n3 x r2 (ld r2).

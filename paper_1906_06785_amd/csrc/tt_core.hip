@@ -19,11 +19,77 @@ namespace sgtt {
 // ------------------------------------------------------------------ pool
 Pool::~Pool() {
   for (auto& kv : size_) (void)hipFree(kv.first);
+  if (arena_) (void)hipFree(arena_);
+}
+
+void Pool::reserve(size_t n) {
+  if (!arena_size_.empty()) throw SgttError(-1, "reserve: blocks of the current arena are in use");
+  if (arena_) {
+    (void)hipFree(arena_);
+    arena_ = nullptr;
+    arena_n_ = 0;
+    arena_free_.clear();
+  }
+  if (n == 0) return;
+  n = (n + 255) / 256 * 256;
+  double* p = nullptr;
+  if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw SgttError(-3, "reserve: device allocation of the arena failed");
+  }
+  ++device_allocs_;
+  arena_ = p;
+  arena_n_ = n;
+  arena_used_ = 0;
+  arena_peak_ = 0;
+  arena_free_[0] = n;
+}
+
+double* Pool::arena_get(size_t want) {
+  for (auto it = arena_free_.begin(); it != arena_free_.end(); ++it) {
+    if (it->second < want) continue;
+    const size_t off = it->first, len = it->second;
+    arena_free_.erase(it);
+    if (len > want) arena_free_[off + want] = len - want;
+    double* p = arena_ + off;
+    arena_size_[p] = want;
+    arena_used_ += want;
+    arena_peak_ = std::max(arena_peak_, arena_used_);
+    return p;
+  }
+  return nullptr;
+}
+
+bool Pool::arena_put(double* p) {
+  auto it = arena_size_.find(p);
+  if (it == arena_size_.end()) return false;
+  size_t off = (size_t)(p - arena_), len = it->second;
+  arena_size_.erase(it);
+  arena_used_ -= len;
+  // coalesce with the free neighbours
+  auto next = arena_free_.lower_bound(off);
+  if (next != arena_free_.end() && next->first == off + len) {
+    len += next->second;
+    next = arena_free_.erase(next);
+  }
+  if (next != arena_free_.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      prev->second += len;
+      return true;
+    }
+  }
+  arena_free_[off] = len;
+  return true;
 }
 
 double* Pool::get(size_t n) {
   if (n == 0) n = 1;
   size_t want = (n + 255) / 256 * 256;
+  if (arena_) {
+    double* p = arena_get(want);
+    if (p) return p;
+  }
   auto it = free_.lower_bound(want);
   if (it != free_.end() && it->first <= 2 * want + (1u << 20)) {
     double* p = it->second;
@@ -31,6 +97,7 @@ double* Pool::get(size_t n) {
     return p;
   }
   double* p = nullptr;
+  ++device_allocs_;
   hipError_t e = hipMalloc(&p, want * sizeof(double));
   if (e != hipSuccess) {
     // release cached blocks and retry once
@@ -51,6 +118,7 @@ double* Pool::get(size_t n) {
 
 void Pool::put(double* p) {
   if (!p) return;
+  if (arena_ && arena_put(p)) return;
   auto it = size_.find(p);
   if (it == size_.end()) return;
   free_.insert({it->second, p});

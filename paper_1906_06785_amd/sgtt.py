@@ -84,12 +84,17 @@ class PicardStats(C.Structure):
                 "seconds": self.seconds}
 
 
+class MemoryInfo(C.Structure):
+    _fields_ = [("arena_bytes", C.c_size_t), ("arena_peak_bytes", C.c_size_t), ("cached_bytes", C.c_size_t),
+                ("device_allocs", C.c_long)]
+
+
 class SolveStats(C.Structure):
     _fields_ = [("cycles", C.c_int), ("outer_iters", C.c_int), ("inner_iters", C.c_int),
                 ("rel_residual", C.c_double), ("seconds", C.c_double), ("max_rank_krylov_u", C.c_int),
                 ("max_rank_krylov_p", C.c_int), ("roundings", C.c_int), ("t_apply", C.c_double),
                 ("t_round", C.c_double), ("t_precond", C.c_double), ("t_residual", C.c_double),
-                ("learned_calls", C.c_int), ("learned_fallback", C.c_int)]
+                ("learned_calls", C.c_int), ("learned_fallback", C.c_int), ("device_allocs", C.c_long)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -100,6 +105,8 @@ _sig = {
     "sgtt_version": (C.c_char_p, []),
     "sgtt_context_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
     "sgtt_context_destroy": (C.c_int, [_P]),
+    "sgtt_context_reserve": (C.c_int, [_P, C.c_size_t]),
+    "sgtt_context_memory": (C.c_int, [_P, C.POINTER(MemoryInfo)]),
     "sgtt_last_error": (C.c_char_p, [_P]),
     "sgtt_assemble": (C.c_int, [_P, C.POINTER(ProblemDesc), C.POINTER(SgttPair), C.POINTER(_P)]),
     "sgtt_system_destroy": (C.c_int, [_P]),
@@ -339,6 +346,15 @@ class Context:
         if rc < 0:
             raise SgttError(rc, _lib.sgtt_last_error(self._c).decode())
         return rc
+
+    def reserve(self, nbytes: int):
+        """Allocate the context's device arena up front (sgtt_context_reserve)."""
+        self.check(_lib.sgtt_context_reserve(self._c, int(nbytes)))
+
+    def memory(self) -> dict:
+        m = MemoryInfo()
+        self.check(_lib.sgtt_context_memory(self._c, C.byref(m)))
+        return {k: getattr(m, k) for k, _ in m._fields_}
 
     def round(self, buf: TTBuf, eps: float, max_rank: int = 0):
         s = buf.struct()

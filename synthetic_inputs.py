@@ -103,11 +103,12 @@ def batch_configs(n: int = 64, seed: int = 0, small: bool = False):
 
 
 def smooth_prior(nt: int, nxi: int, tau: float, coords_free, n_p: int, ranks_u=(4, 17), ranks_p=(2, 3),
-                 seed: int = 0, amplitude: float = 0.4):
+                 seed: int = 0, amplitude: float = 0.4, mean_only: bool = False):
     """A prior iterate (velocity TT over free nodes, pressure TT) shaped like
     a flow solution, with exact TT ranks: time columns ramp up like the
     inflow, (1 - exp(-10 t)) sin((a + 1) pi t / (2 T)); chaos slices decay
-    with the chaos index; each spatial column is the velocity of a stream
+    with the chaos index (mean_only: only the first chaos mode, a
+    deterministic prior); each spatial column is the velocity of a stream
     function sin(alpha (x1 + 1)) sin(beta (x2 + 1)) sampled at the free
     nodes (component 1 rows, then component 2 rows).  coords_free: (n_s, 2)
     free node coordinates.  Returns ((G1, G2, G3), (P1, P2, P3)) in the
@@ -121,6 +122,8 @@ def smooth_prior(nt: int, nxi: int, tau: float, coords_free, n_p: int, ranks_u=(
     decay = np.exp(-0.5 * np.arange(nxi))
     G2 = g.standard_normal((k1, nxi, k2)) * decay[None, :, None] / np.sqrt(k1 * k2)
     G2[:, 0, :] += 1.0 / np.sqrt(k1 * k2)
+    if mean_only:
+        G2[:, 1:, :] = 0.0
     x1, x2 = coords_free[:, 0], coords_free[:, 1]
     cols = []
     for b in range(k2):
@@ -134,5 +137,7 @@ def smooth_prior(nt: int, nxi: int, tau: float, coords_free, n_p: int, ranks_u=(
     j1, j2 = ranks_p
     P1 = np.stack([0.1 * ramp * np.cos(a * np.pi * t / T) for a in range(j1)], axis=1)
     P2 = g.standard_normal((j1, nxi, j2)) * decay[None, :, None]
+    if mean_only:
+        P2[:, 1:, :] = 0.0
     P3 = g.standard_normal((j2, n_p))
     return (G1, G2, G3), (P1, P2, P3)

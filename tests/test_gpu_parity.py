@@ -404,3 +404,55 @@ def test_preconditioner_reduced_precision_meets_inner_tolerance(sg, ctx, c1, pre
     res = np.linalg.norm(prec._mean_apply_full(zu) - rhs) / np.linalg.norm(rhs)
     _flush(f"inner relative residual {res:.3e}")
     assert res <= 0.15
+
+
+def test_reserved_context_solves_without_allocating(sg):
+    # with an arena reserved up front, a solve whose working set fits makes
+    # no device allocation (after a first solve has tuned the spatial-solve
+    # kernels for its column counts); the answer is the same
+    ctx = sg.Context(0)
+    _flush("reserved context: C1 solves")
+    ctx.reserve(8 << 30)
+    S = sg.System(ctx, CONFIGS["C1"])
+    b = S.rhs()
+    x1, st1, rc1 = S.solve(b, S.pair(96, 1024), restart=20, relax=1, inner_mode=1)
+    x2, st2, rc2 = S.solve(b, S.pair(96, 1024), restart=20, relax=1, inner_mode=1)
+    mem = ctx.memory()
+    _flush(f"allocations: first solve {st1['device_allocs']}, second {st2['device_allocs']}; memory {mem}")
+    assert rc1 == 0 and rc2 == 0 and st2["rel_residual"] <= 1e-8
+    assert st2["device_allocs"] == 0
+    assert 0 < mem["arena_peak_bytes"] <= mem["arena_bytes"] == 8 << 30
+    d = tt.pair_full(x1.cores()) - tt.pair_full(x2.cores())
+    assert np.linalg.norm(d) <= 1e-12 * np.linalg.norm(tt.pair_full(x1.cores()))
+
+
+def test_preconditioner_fp32_mean_solve_matches_oracle(sg, ctx, c1):
+    # the time-stepped mean solve in FP32 (precision 1) against the oracle's
+    # FP64 full-format preconditioner: agreement to FP32 rounding, far below
+    # the 1e-3 truncation the mean solve is compressed with
+    P, S = c1
+    _flush("precondition c1, FP32 time-stepped mean solve")
+    r = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 4), (2, 3), 31)
+    out = S.precondition(_pair_buf(S, r, 32, 256), eps_krylov=1e-13, inner_eps=1e-13, inner_mode=1, precision=1)
+    prec = MeanLSC(P, None, "full")
+    yu, yp = tt.full(r[0]), tt.full(r[1])
+    vu, vp = prec.apply_full_exact(yu, yp)
+    want = np.concatenate([vu.ravel(), vp.ravel()])
+    got = tt.pair_full(out.cores())
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    _flush(f"FP32 mean solve vs oracle: {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_solve_c1_fp32_mean_solve_to_1e8(sg, ctx, c1):
+    # the flexible outer solve with the FP32 mean solve in the preconditioner
+    # still reaches the oracle's exact solution (FP64 outer iteration and
+    # refinement, sec. 4.2)
+    P, S = c1
+    _flush("solve c1 with the FP32 mean solve")
+    b = S.rhs()
+    x, st, rc = S.solve(b, S.pair(96, 1024), restart=20, relax=1, inner_mode=1, precision=1, **TIGHT)
+    err = _solution_error(P, x)
+    _flush(f"outer {st['outer_iters']} residual {st['rel_residual']:.2e} solution error {err:.2e}")
+    assert rc == 0 and st["rel_residual"] <= 1e-10
+    assert err <= 1e-8

@@ -178,3 +178,31 @@ def test_picard_step_solve_c1_pcd(c1_sys):
     _flush(f"pcd solution error {err:.2e}")
     assert rc == 0 and st["rel_residual"] <= 1e-10
     assert err <= 1e-8
+
+
+def test_picard_apply_and_preconditioner_with_many_value_sets(sg, ctx):
+    # a wind of spatial rank 18 gives 20 value sets on the velocity pattern
+    # (M, A and 18 convection matrices) and on the pressure patterns of the
+    # LSC and PCD approximations: more than one pass of the sparse product
+    # takes (16).  Operator (eq. 4.12) and both preconditioners (eq. 5.17,
+    # 5.19) against the oracle.
+    _flush("picard c1 wind of rank 18")
+    P = Problem(CONFIGS["C1"])
+    u, p = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (3, 17), (1, 1), 13)
+    prior = (tt.scale(u, 0.3 / tt.tt_norm(u)), tt.scale(p, 0.1 / tt.tt_norm(p)))
+    S0 = sg.System(ctx, CONFIGS["C1"])
+    S = sg.System(ctx, CONFIGS["C1"], prior=S0.pair(8, 32).set(prior), **EXACT)
+    conv = P.convection(prior, 1e-12)
+    assert (S.info.conv_r1, S.info.conv_r2) == (conv.k1, conv.k2) == (4, 18)
+    x = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 3), (2, 2), 14)
+    got = tt.pair_full(S.apply(S.pair(64, 512).set(x)).cores())
+    want = tt.pair_full(P.apply(x, conv))
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    r = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 3), (2, 3), 15)
+    for schur, name in ((0, "lsc"), (1, "pcd")):
+        out = S.precondition(S.pair(32, 256).set(r), eps_krylov=1e-13, inner_eps=1e-13, inner_tol=1e-1, schur=schur)
+        ref = MeanLSC(P, conv, "tt", 1e-1, 1e-13, 20, 1e-13, schur=name).apply_tt(r)
+        gp, wp = tt.full(out.cores()[1]), tt.full(ref[1])
+        perr = np.linalg.norm(gp - wp) / np.linalg.norm(wp)
+        _flush(f"{name}: pressure block difference {perr:.2e}")
+        assert perr <= 1e-7
