@@ -226,3 +226,14 @@ def pressure_convection(mesh: StepMesh, w1: np.ndarray, w2: np.ndarray):
         + np.einsum("g,eg,gi,gj->eij", wq, W2, psi, dpsi[:, :, 1])
     Ne *= h / 2.0
     return _assemble(mesh.pconn, mesh.pconn, Ne, mesh.n_p, mesh.n_p)
+
+
+def stiffness_weighted(mesh: StepMesh, a_vertex: np.ndarray):
+    """[A(a)]_ij = (a grad phi_j, grad phi_i) over all velocity nodes for a
+    coefficient field a given by its values at the Q1 (pressure) vertices
+    and interpolated bilinearly to the Gauss points (eq. 3.7 with a
+    spatially varying viscosity)."""
+    phi, dphi, psi, wq = _ref_tables()
+    Ag = a_vertex[mesh.pconn] @ psi.T                 # (ne, 9) coefficient at the Gauss points
+    Ae = np.einsum("g,eg,gid,gjd->eij", wq, Ag, dphi, dphi)   # (2/h)^2 * jac = 1
+    return _assemble(mesh.conn, mesh.conn, Ae, mesh.n_all, mesh.n_all)

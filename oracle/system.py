@@ -108,6 +108,25 @@ class Problem:
         self.n_xi = len(self.idx)
         self.c = gpc.viscosity_coefficients(cfg["m"], cfg["nu0"], cfg["nu_coef"])
         self.Gnu = np.einsum("l,lij->ij", self.c, self.G)
+        # viscous terms sum_l G_l (x) A_l of eq. 3.6 as (chaos matrix, free x
+        # free, free x all scalar stiffness): one term G_nu (x) A for the law
+        # nu0 (1 + sigma sum xi_k / k^2) (A_l proportional to A); m + 1 terms
+        # for the KL law of sec. 6.1, xi_k ~ U[-sqrt 3, sqrt 3] (G_l scaled by
+        # sqrt 3) and A_l = nu0 sigma sqrt(beta_l) A(a_l)
+        if cfg.get("viscosity", "power") == "kl":
+            from . import kl
+            self.kl_beta, self.kl_modes = kl.viscosity_fields(self.mesh, cfg["corr_length"], cfg["m"])
+            terms = [(cfg["nu0"] * self.G[0], A)]
+            for l in range(cfg["m"]):
+                Al = fem.stiffness_weighted(self.mesh, self.kl_modes[l])
+                terms.append((np.sqrt(3.0) * self.G[l + 1],
+                              cfg["nu0"] * cfg["nu_coef"] * np.sqrt(self.kl_beta[l]) * Al))
+        else:
+            terms = [(self.Gnu, A)]
+        self.visc = []
+        for Gl, Al in terms:
+            Af, Afa = Al[f][:, f].tocsr(), Al[f]
+            self.visc.append((Gl, sp.block_diag([Af, Af]).tocsr(), sp.block_diag([Afa, Afa]).tocsr()))
         self.nt, self.tau = cfg["nt"], cfg["tau"]
         self.Ct = sp.diags([np.ones(self.nt - 1)], [-1], shape=(self.nt, self.nt)).tocsr()
         self.It = sp.identity(self.nt, format="csr")
@@ -151,9 +170,9 @@ class Problem:
         """L x as an exact TT pair (no truncation)."""
         u, p = x
         It_C = (self.It - self.Ct) / self.tau
-        parts = [tt.mode_apply(u, It_C, None, self.Mb),
-                 tt.mode_apply(u, None, self.Gnu, self.Ab),
-                 tt.mode_apply(p, None, None, self.Bt)]
+        parts = [tt.mode_apply(u, It_C, None, self.Mb)]
+        parts += [tt.mode_apply(u, None, Gl, Ab) for Gl, Ab, _ in self.visc]
+        parts.append(tt.mode_apply(p, None, None, self.Bt))
         if conv is not None:
             parts.append(conv.ttm_apply(u))
         yu = tt.concat(parts)
@@ -165,11 +184,12 @@ class Problem:
         nt, nx = self.nt, self.n_xi
         U = xu.reshape(nt * nx, self.n_u)
         MU = np.asarray(self.Mb @ U.T).T.reshape(nt, nx, -1)
-        AU = np.asarray(self.Ab @ U.T).T.reshape(nt, nx, -1)
         yu = MU.copy()
         yu[1:] -= MU[:-1]
         yu /= self.tau
-        yu += np.einsum("ij,tjx->tix", self.Gnu, AU)
+        for Gl, Ab, _ in self.visc:
+            AU = np.asarray(Ab @ U.T).T.reshape(nt, nx, -1)
+            yu += np.einsum("ij,tjx->tix", Gl, AU)
         yu += np.asarray(self.Bt @ xp.reshape(nt * nx, -1).T).T.reshape(nt, nx, -1)
         if conv is not None:
             yu += conv.full_apply(xu)
@@ -213,8 +233,9 @@ class Problem:
                 mu = row_vals(u, self.Mb, tk, jk)
                 if tk > 0:
                     mu = mu - row_vals(u, self.Mb, tk - 1, jk)
-                au = row_vals(u, self.Ab, tk, jk)
-                lx = mu[ik] / self.tau + self.Gnu[ik] @ au + entry_of(pp, tk, ik, jk, self.Bt)
+                lx = mu[ik] / self.tau + entry_of(pp, tk, ik, jk, self.Bt)
+                for Gl, Ab, _ in self.visc:
+                    lx += Gl[ik] @ row_vals(u, Ab, tk, jk)
                 if conv is not None:
                     for bb in range(conv.k2):
                         nv = row_vals(u, conv.Nb_ff[bb], tk, jk)          # over chaos index k
@@ -231,8 +252,9 @@ class Problem:
     def explicit(self, conv=None):
         """Explicit sparse all-at-once matrix (scipy.sparse.kron), small sizes."""
         kron = sp.kron
-        Kuu = kron(kron((self.It - self.Ct) / self.tau, sp.identity(self.n_xi)), self.Mb) \
-            + kron(kron(self.It, sp.csr_matrix(self.Gnu)), self.Ab)
+        Kuu = kron(kron((self.It - self.Ct) / self.tau, sp.identity(self.n_xi)), self.Mb)
+        for Gl, Ab, _ in self.visc:
+            Kuu = Kuu + kron(kron(self.It, sp.csr_matrix(Gl)), Ab)
         if conv is not None:
             for a in range(conv.k1):
                 for b in range(conv.k2):
@@ -249,8 +271,8 @@ class Problem:
         (Stokes: prior=None gives f).  Velocity rows are free rows only."""
         wall = self.wind(prior)
         It_C = (self.It - self.Ct) / self.tau
-        parts = [tt.mode_apply(wall, It_C, None, self.Mb_fall),
-                 tt.mode_apply(wall, None, self.Gnu, self.Ab_fall)]
+        parts = [tt.mode_apply(wall, It_C, None, self.Mb_fall)]
+        parts += [tt.mode_apply(wall, None, Gl, Abfa) for Gl, _, Abfa in self.visc]
         if prior is not None:
             conv = Convection(self, wall)
             parts.append(conv.ttm_apply(wall, which="fall"))
@@ -273,7 +295,9 @@ class Problem:
         each step solve the SG saddle-point block with scipy's sparse LU."""
         nt, nx, nu, npp = self.nt, self.n_xi, self.n_u, self.n_p
         Ix = sp.identity(nx)
-        base = sp.kron(Ix, self.Mb) / self.tau + sp.kron(sp.csr_matrix(self.Gnu), self.Ab)
+        base = sp.kron(Ix, self.Mb) / self.tau
+        for Gl, Ab, _ in self.visc:
+            base = base + sp.kron(sp.csr_matrix(Gl), Ab)
         Kup = sp.kron(Ix, self.Bt)
         Kpu = sp.kron(Ix, self.B)
         u = np.zeros((nt, nx, nu))

@@ -36,6 +36,17 @@ CONFIGS = {
     # viscosity law (relative amplitude nu_coef = sigma = 0.01)
     "paper": dict(h=0.25, L=12.0, m=3, p=3, nt=64, tau=1.0 / 64, nu0=1.0 / 50, nu_coef=0.01,
                   ramp=10.0),
+    # the Table 6.1 problem with the paper's own viscosity: truncated KL
+    # expansion of an exponential covariance (correlation length b = 4,
+    # sigma = 0.01, m = 3 modes), xi_k ~ U[-sqrt 3, sqrt 3]
+    "paper_kl": dict(h=0.25, L=12.0, m=3, p=3, nt=64, tau=1.0 / 64, nu0=1.0 / 50, nu_coef=0.01,
+                     ramp=10.0, viscosity="kl", corr_length=4.0),
+    # small KL problem for the oracle's pins and GPU parity (sigma raised so
+    # that the random part is visible at FP64 tolerances)
+    "tinykl": dict(h=0.5, L=2.0, m=2, p=2, nt=3, tau=0.1, nu0=1.0 / 50, nu_coef=0.3,
+                   ramp=10.0, viscosity="kl", corr_length=4.0),
+    "C1kl": dict(h=0.25, L=12.0, m=2, p=2, nt=10, tau=0.1, nu0=1.0 / 50, nu_coef=0.3,
+                 ramp=10.0, viscosity="kl", corr_length=4.0),
     # intermediate size used by parity tests at a shape between C1 and C2
     "C1b": dict(h=0.125, L=12.0, m=3, p=2, nt=32, tau=0.05, nu0=1.0 / 50,
                 nu_coef=0.1, ramp=10.0),

@@ -456,3 +456,39 @@ def test_solve_c1_fp32_mean_solve_to_1e8(sg, ctx, c1):
     _flush(f"outer {st['outer_iters']} residual {st['rel_residual']:.2e} solution error {err:.2e}")
     assert rc == 0 and st["rel_residual"] <= 1e-10
     assert err <= 1e-8
+
+
+@pytest.fixture(scope="module")
+def kl_systems(sg, ctx):
+    out = {}
+    for name in ("tinykl", "C1kl"):
+        out[name] = (Problem(CONFIGS[name]), sg.System(ctx, CONFIGS[name]))
+    return out
+
+
+@pytest.mark.parametrize("name", ["tinykl", "C1kl"])
+def test_kl_apply_and_rhs_match_oracle(sg, ctx, kl_systems, name):
+    # the paper's KL viscosity (sec. 6.1): m + 1 viscous terms
+    # sum_l G_l (x) A_l in the operator (eq. 3.6, 3.11-3.12) and in the
+    # right-hand side, each side with its own KL expansion
+    P, S = kl_systems[name]
+    _flush(f"KL apply and rhs {name}")
+    x = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (3, 5), (2, 4), 41)
+    out = S.apply(_pair_buf(S, x, 32, 128))
+    want = tt.pair_full(P.apply(x))
+    got = tt.pair_full(out.cores())
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    b = S.rhs()
+    bo = tt.pair_full(P.rhs())
+    assert np.abs(tt.pair_full(b.cores()) - bo).max() <= 1e-12 * np.abs(bo).max()
+
+
+def test_kl_solve_c1_reaches_oracle_solution(sg, ctx, kl_systems):
+    P, S = kl_systems["C1kl"]
+    _flush("KL solve C1")
+    b = S.rhs()
+    x, st, rc = S.solve(b, S.pair(96, 1024), restart=20, relax=1, inner_mode=1, **TIGHT)
+    err = _solution_error(P, x)
+    _flush(f"outer {st['outer_iters']} residual {st['rel_residual']:.2e} solution error {err:.2e}")
+    assert rc == 0 and st["rel_residual"] <= 1e-10
+    assert err <= 1e-8

@@ -206,3 +206,18 @@ def test_picard_apply_and_preconditioner_with_many_value_sets(sg, ctx):
         perr = np.linalg.norm(gp - wp) / np.linalg.norm(wp)
         _flush(f"{name}: pressure block difference {perr:.2e}")
         assert perr <= 1e-7
+
+
+def test_kl_picard_system_matches_oracle(sg, ctx):
+    # a Picard step-1 system with the KL viscosity: operator and nonlinear
+    # residual right-hand side (eq. 3.15) with the m + 1 viscous terms
+    _flush("KL picard system tiny")
+    P, prior, S = _system(sg, ctx, "tinykl", **EXACT)
+    conv = P.convection(prior, 1e-12)
+    x = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (3, 5), (2, 4), 43)
+    got = tt.pair_full(S.apply(S.pair(64, 512).set(x)).cores())
+    want = tt.pair_full(P.apply(x, conv))
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    rhs = tt.pair_full(S.rhs(S.pair(64, 512)).cores())
+    r = tt.pair_full(P.residual_tt(prior))
+    assert np.linalg.norm(rhs - r) <= 1e-10 * np.linalg.norm(r)

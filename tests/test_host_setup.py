@@ -105,3 +105,27 @@ def test_host_block_cyclic_reduction_rejects_bad_arguments():
         hp.bcr_solve(2, np.ones((hp.n_p, 1)))
     with pytest.raises(sg.SgttError):
         hp.bcr_solve(0, np.ones((hp.n_s, 1)), tau=0.0)
+
+
+def test_host_kl_expansion_and_viscous_terms_match_oracle():
+    # KL law (sec. 6.1): eigenpairs of the covariance, the sqrt 3 scaled chaos
+    # matrices and the m + 1 stiffness matrices against the oracle's
+    # independent assembly
+    sg = _lib()
+    from synthetic_inputs import CONFIGS
+    cfg = CONFIGS["paper_kl"]
+    hp = sg.HostProblem(cfg)
+    P = Problem(cfg)
+    beta, modes, nv = hp.kl()
+    assert nv == cfg["m"] + 1 and len(beta) == cfg["m"]
+    assert np.allclose(beta, P.kl_beta, rtol=1e-10)
+    assert np.abs(modes - P.kl_modes).max() <= 1e-8 * np.abs(P.kl_modes).max()
+    Gv = hp.gpc(3)
+    for t, (Gl, Ab, _) in enumerate(P.visc):
+        assert np.abs(Gv[t] - Gl).max() < 1e-14
+        n = P.n_s
+        assert _rel(hp.csr(8 + t), Ab[:n, :n]) < 1e-12
+    # the other law has one viscous term, G_nu (x) A
+    hp0 = sg.HostProblem(CONFIGS["C1"])
+    assert hp0.kl()[2] == 1
+    assert np.abs(hp0.gpc(3)[0] - hp0.gpc(2)).max() == 0.0

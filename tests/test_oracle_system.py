@@ -24,8 +24,9 @@ def _prior(P, seed=3):
     return tt.scale(u, 0.3 / tt.tt_norm(u)), tt.scale(p, 0.1 / tt.tt_norm(p))
 
 
-def test_apply_matches_explicit_kron(tiny):
-    P = tiny
+@pytest.mark.parametrize("name", ["tiny", "tinykl"])
+def test_apply_matches_explicit_kron(name):
+    P = Problem(CONFIGS[name])
     x = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 3), (2, 2), 0)
     K = P.explicit()
     ref = K @ tt.pair_full(x)
@@ -46,8 +47,9 @@ def test_apply_with_convection_matches_explicit(tiny):
     assert np.abs(np.concatenate([yu.ravel(), yp.ravel()]) - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-def test_time_stepping_equals_dense_solve(tiny):
-    P = tiny
+@pytest.mark.parametrize("name", ["tiny", "tinykl"])
+def test_time_stepping_equals_dense_solve(name):
+    P = Problem(CONFIGS[name])
     b = P.rhs()
     K = P.explicit()
     zd = spla.spsolve(K, tt.pair_full(b))
@@ -237,6 +239,36 @@ def test_stochastic_galerkin_mean_matches_quadrature():
     mean = np.zeros(P.n_u)
     for x, w in zip(xq, wq):
         Pd = Problem(dict(cfg, m=1, p=0, nu0=nu0 * (1 + c * x), nu_coef=0.0))
+        bd = Pd.rhs()
+        ud, _ = Pd.solve_direct(tt.full(bd[0]), tt.full(bd[1]))
+        mean += 0.5 * w * ud[-1, 0]
+    assert np.linalg.norm(u[-1, 0] - mean) <= 1e-9 * np.linalg.norm(mean)
+
+
+def test_kl_stochastic_galerkin_mean_matches_quadrature():
+    # One KL mode, high chaos degree: the Galerkin mean of the final time step
+    # equals the expectation over xi ~ U[-sqrt 3, sqrt 3] of deterministic
+    # solves with nu(x, xi) = nu0 (1 + sigma sqrt(beta_1) a_1(x) xi)
+    # (Gauss-Legendre quadrature in xi / sqrt 3).  Pins the sqrt 3 scaling of
+    # G_1 and the assembly of A_1 = nu0 sigma sqrt(beta_1) A(a_1).
+    from scipy.special import roots_legendre
+    from oracle import mesh as fem
+    nu0, sigma = 0.5, 0.2     # nu(x, xi) stays within about 30 % of nu0
+    cfg = dict(CONFIGS["tinykl"], m=1, p=10, nu0=nu0, nu_coef=sigma, nt=3, tau=0.2)
+    P = Problem(cfg)
+    b = P.rhs()
+    u, p = P.solve_direct(tt.full(b[0]), tt.full(b[1]))
+    _, A, _, _, _ = fem.assemble(P.mesh)
+    A1 = fem.stiffness_weighted(P.mesh, P.kl_modes[0])
+    f = P.mesh.free
+    xq, wq = roots_legendre(16)
+    mean = np.zeros(P.n_u)
+    for x, w in zip(xq, wq):
+        xi = np.sqrt(3.0) * x
+        Pd = Problem(dict(cfg, m=1, p=0, viscosity="power", nu_coef=0.0))
+        Ad = nu0 * A + nu0 * sigma * np.sqrt(P.kl_beta[0]) * xi * A1
+        Af, Afa = Ad[f][:, f].tocsr(), Ad[f]
+        Pd.visc = [(np.eye(1), sp.block_diag([Af, Af]).tocsr(), sp.block_diag([Afa, Afa]).tocsr())]
         bd = Pd.rhs()
         ud, _ = Pd.solve_direct(tt.full(bd[0]), tt.full(bd[1]))
         mean += 0.5 * w * ud[-1, 0]
