@@ -70,7 +70,7 @@ def parse(argv=None):
     ap.add_argument("--picard", type=int, default=0,
                     help="N > 0: instead, run Picard's method (Alg. 3.1) for N steps after the Stokes solve and print "
                          "the per-step record")
-    ap.add_argument("--sweep", default="", choices=("", "paper", "sigma", "nu0", "h", "tau"),
+    ap.add_argument("--sweep", default="", choices=("", "paper", "sigma", "nu0", "h", "tau", "kl", "kl_tol"),
                     help="instead, run Picard's method with the paper's tolerances (Table 6.2) on the Table 6.1 "
                          "sizes, varying one parameter (sec. 6.3), and print ranks, storage ratio and times")
     return ap.parse_args(argv)
@@ -93,6 +93,11 @@ SWEEPS = {
     "nu0": [dict(nu0=v) for v in (1 / 25, 1 / 50, 1 / 100)],
     "h": [dict(h=v) for v in (1 / 4, 1 / 8, 1 / 16)],
     "tau": [dict(tau=1 / n, nt=n) for n in (32, 64, 128)],
+    # the paper's own problem: KL viscosity (sec. 6.1), Table 6.1 and 6.2
+    "kl": [dict(base="paper_kl")],
+    # Table 6.3: tighter GMRES tolerances with eps_gmres = 1e-2 tol_gmres
+    "kl_tol": [dict(base="paper_kl", solve=dict(tol=t, tol_cycle=t, eps_krylov=1e-2 * t, inner_eps=1e-2 * t),
+                    eps_rhs=1e-2 * t) for t in (1e-1, 1e-2, 1e-3)],
 }
 
 
@@ -110,12 +115,17 @@ def sweep_main(args):
     tol = PAPER_TOLERANCES
     runs = []
     for over in SWEEPS[args.sweep]:
-        cfg = dict(CONFIGS["paper"], **over)
+        over = dict(over)
+        base = over.pop("base", "paper")
+        solve = dict(tol["solve"], **over.pop("solve", {}))
+        eps_rhs = over.pop("eps_rhs", tol["eps_rhs"])
+        cfg = dict(CONFIGS[base], **over)
         hp = sgtt.HostProblem(cfg)
         t0 = time.perf_counter()
         x, st, rc = sgtt.picard(ctx, cfg, steps=tol["max_steps"], tol_picard=tol["tol_picard"],
-                                eps_soln=tol["eps_soln"], eps_conv=tol["eps_conv"], eps_rhs=tol["eps_rhs"],
-                                caps=OUT_CAPS, **tol["solve"])
+                                eps_soln=tol["eps_soln"], eps_conv=tol["eps_conv"], eps_rhs=eps_rhs,
+                                caps=OUT_CAPS, **solve)
+        over.update(base=base, solve=solve, eps_rhs=eps_rhs)
         el = time.perf_counter() - t0
         ru, rp = x.ranks
         runs.append({"params": over, "n_t": hp.nt, "n_xi": hp.n_xi, "n_u": hp.n_u, "n_p": hp.n_p, "status": rc,
@@ -128,8 +138,9 @@ def sweep_main(args):
         print(f"[sweep] {args.sweep} {over}: {st['steps']} Picard steps, ranks u {ru} p {rp}, {el:.1f} s",
               file=sys.stderr, flush=True)
     print(json.dumps({"metric": f"Picard's method with the paper's tolerances, {args.sweep} sweep",
-                      "config": {"workload": "Table 6.1 sizes (h=1/4, m=3, degree 3, t_f=1, tau=1/64, nu0=1/50) "
-                                             "with this build's viscosity law; one parameter varied",
+                      "config": {"workload": "Table 6.1 sizes (h=1/4, m=3, degree 3, t_f=1, tau=1/64, nu0=1/50); "
+                                             "base 'paper': this build's viscosity law, 'paper_kl': the KL "
+                                             "viscosity of sec. 6.1 (b=4, sigma=0.01); one parameter varied",
                                  "tolerances": tol},
                       "runs": runs}), flush=True)
 
@@ -500,13 +511,19 @@ def main():
         progress(f"warm-up solve of {name}")
         v_el, v_stats = time_solves(S, b, vout, vopts, args.steps, progress, stream)
         v_worst = max(s["rel_residual"] for s in v_stats)
+        ctx.profile(True)   # one profiled solve of the variant for its breakdown
+        _, vp_st, _ = S.solve(b, vout, **vopts)
+        v_breakdown = ctx.profile_read()
+        ctx.profile(False)
         comparison[name] = {
             "solves_per_s": args.steps / v_el, "ms_per_step": v_el / args.steps * 1e3,
             "speedup_vs_value": (args.steps / v_el) / (args.steps / elapsed), "dtype": dtype_name(vopts),
             "preconditioner_velocity_block": VELOCITY_BLOCK[vopts["inner_mode"]],
             "outer_iters": int(round(sum(s["outer_iters"] for s in v_stats) / len(v_stats))),
             "inner_iters": v_stats[-1]["inner_iters"], "max_rel_residual": v_worst, "converged": v_worst <= 1e-8,
-            "max_krylov_rank_u": v_stats[-1]["max_rank_krylov_u"]}
+            "max_krylov_rank_u": v_stats[-1]["max_rank_krylov_u"],
+            "kernels": {k: {"ms": v["seconds"] * 1e3, "launches": v["launches"]} for k, v in v_breakdown.items()
+                        if v["launches"]}}
     res = {
         "metric": "Picard-step solve time to 1e-8 rel. residual: learned/mixed vs plain FP64",
         "value": args.steps / elapsed,

@@ -66,8 +66,12 @@ typedef struct {
   sgtt_tt p;
 } sgtt_tt_pair;
 
-/* Problem description (sec. 6.1; viscosity nu0 (1 + nu_coef sum_k xi_k/k^2),
- * xi_k ~ U[-1,1], Legendre chaos of total degree <= p in m variables). */
+/* Problem description (sec. 6.1).  Viscosity law 0: nu0 (1 + nu_coef
+ * sum_k xi_k/k^2), xi_k ~ U[-1,1]; law 1: the paper's truncated KL expansion
+ * nu0 (1 + nu_coef sum_k sqrt(beta_k) a_k(x) xi_k) of the covariance
+ * exp(-||x - y||_1 / corr_length), xi_k ~ U[-sqrt 3, sqrt 3] (sec. 6.1, its
+ * m + 1 distinct stiffness matrices in eq. 3.6; meshes up to h = 1/8).
+ * Legendre chaos of total degree <= p in m variables. */
 typedef struct {
   double h;          /* mesh size: 1/h even integer                         */
   double L;          /* channel length (12 in the paper)                    */
@@ -80,6 +84,8 @@ typedef struct {
   double ramp;       /* inflow ramp rate: u_D = (1-4 x2^2)(1-exp(-ramp t))  */
   double eps_conv;   /* truncation of the convection field (eq. 4.13)       */
   double eps_rhs;    /* truncation of a Picard residual right-hand side     */
+  int viscosity_law; /* 0 or 1, see above                                   */
+  double corr_length;/* KL correlation length b (law 1)                     */
 } sgtt_problem_desc;
 
 typedef struct {
@@ -445,12 +451,20 @@ int sgtt_host_sizes(const sgtt_host_problem* hp, int* sizes);
  * 2 = B (n_p x n_u), 3 = B M*^-1 B^T (n_p x n_p), 4 = B M*^-1 M M*^-1 B^T,
  * 5 = B M*^-1 A M*^-1 B^T, 6 = Q1 pressure mass M_p (n_p x n_p), 7 = Q1
  * pressure stiffness A_p, unit viscosity, natural boundary conditions (the
- * pressure-space matrices of eq. 5.17).  Call with NULL arrays to get
- * nrows/ncols/nnz. */
+ * pressure-space matrices of eq. 5.17), 8 + t = the stiffness A_t of the
+ * t-th viscous term of eq. 3.6 on the free x free pattern (t < nvisc, see
+ * sgtt_host_kl; t = 0 is the unit-viscosity A).  Call with NULL arrays to
+ * get nrows/ncols/nnz. */
 int sgtt_host_csr(const sgtt_host_problem* hp, int which, int* nrows, int* ncols, int* nnz,
                   int* rowptr, int* col, double* val);
-/* chaos: which 0 = G (m+1 x n_xi x n_xi), 1 = H (n_xi^3), 2 = G_nu (n_xi^2) */
+/* chaos: which 0 = G (m+1 x n_xi x n_xi), 1 = H (n_xi^3), 2 = G_nu (n_xi^2),
+ * 3 = the chaos matrices of the viscous terms (nvisc x n_xi x n_xi) */
 int sgtt_host_gpc(const sgtt_host_problem* hp, int which, double* out);
+/* Viscous terms and KL expansion (sec. 6.1): *nvisc gets the number of
+ * viscous terms sum_t Gv_t (x) A_t of eq. 3.6 (1 for law 0, m + 1 for the
+ * KL law), *nmodes the KL modes (0 for law 0); beta (nmodes) and modes
+ * (nmodes x n_p, values at the pressure vertices, int a^2 = 1) may be NULL. */
+int sgtt_host_kl(const sgtt_host_problem* hp, int* nmodes, int* nvisc, double* beta, double* modes);
 /* Dirichlet lift g over all velocity nodes (2 n_all) and node coordinates
  * (n_all x 2), free node list (n_s) */
 int sgtt_host_mesh(const sgtt_host_problem* hp, double* coords, int* free_nodes, double* g_all);

@@ -476,6 +476,35 @@ void build_problem(const ProblemParams& prm, HostProblem& hp) {
     hp.Mpstar.assign(np, 0.0);
     for (int k = 0; k < np; ++k) hp.Mpstar[k] = hp.Mp[find_pos(hp.Qp, k, k)];
   }
+  // viscous terms (eq. 3.6): one for the law nu0 (1 + sigma sum xi_k/k^2),
+  // m + 1 for the KL law (sec. 6.1)
+  {
+    const int nx = hp.n_xi, nnz = hp.Kff.nnz(), nnzfa = hp.Kfa.nnz();
+    hp.Aff_visc.assign(1, hp.Aff);
+    hp.Afa_visc.assign(1, hp.Afa);
+    if (prm.visc_law == 1) {
+      kl_expansion(hp, prm.corr_length, prm.m, hp.kl_beta, hp.kl_modes);
+      hp.nvisc = prm.m + 1;
+      hp.Gvisc.assign((size_t)hp.nvisc * nx * nx, 0.0);
+      for (int i = 0; i < nx; ++i) hp.Gvisc[(size_t)i * nx + i] = prm.nu0;
+      for (int l = 1; l <= prm.m; ++l) {
+        for (int i = 0; i < nx * nx; ++i)
+          hp.Gvisc[(size_t)l * nx * nx + i] = std::sqrt(3.0) * hp.G[(size_t)l * nx * nx + i];
+        std::vector<double> vff(nnz), vfa(nnzfa);
+        weighted_stiffness_values(hp, &hp.kl_modes[(size_t)(l - 1) * np], vff.data(), vfa.data());
+        const double cl = prm.nu0 * prm.nu_coef * std::sqrt(hp.kl_beta[l - 1]);
+        for (auto& v : vff) v *= cl;
+        for (auto& v : vfa) v *= cl;
+        hp.Aff_visc.push_back(std::move(vff));
+        hp.Afa_visc.push_back(std::move(vfa));
+      }
+    } else if (prm.visc_law == 0) {
+      hp.nvisc = 1;
+      hp.Gvisc = hp.Gnu;
+    } else {
+      throw std::runtime_error("unknown viscosity law");
+    }
+  }
   // slab partitions: velocity node column I -> slab floor(I/2); pressure
   // vertex column I -> slab floor(I/4).  Both orderings are sorted by I first.
   {
@@ -560,6 +589,251 @@ void convection_values(const HostProblem& hp, const double* w1, const double* w2
         if (fj >= 0) vff[find_pos(hp.Kff, fi, fj)] += s;
       }
     }
+  }
+}
+
+void weighted_stiffness_values(const HostProblem& hp, const double* a, double* vff, double* vfa) {
+  const Mesh& m = hp.mesh;
+  const RefTables& R = ref();
+  std::fill(vff, vff + hp.Kff.nnz(), 0.0);
+  if (vfa) std::fill(vfa, vfa + hp.Kfa.nnz(), 0.0);
+  for (size_t e = 0; e < m.conn.size(); ++e) {
+    const auto& c = m.conn[e];
+    double ag[9];
+    for (int g = 0; g < 9; ++g) {
+      double v = 0;
+      for (int k = 0; k < 4; ++k) v += a[m.pconn[e][k]] * R.psi[g][k];
+      ag[g] = v;
+    }
+    for (int i = 0; i < 9; ++i) {
+      const int fi = m.free_id[c[i]];
+      if (fi < 0) continue;
+      for (int j = 0; j < 9; ++j) {
+        double v = 0;   // (2/h)^2 * jac = 1
+        for (int g = 0; g < 9; ++g) v += R.w[g] * ag[g] * (R.dxi[g][i] * R.dxi[g][j] + R.deta[g][i] * R.deta[g][j]);
+        if (vfa) vfa[find_pos(hp.Kfa, fi, c[j])] += v;
+        const int fj = m.free_id[c[j]];
+        if (fj >= 0) vff[find_pos(hp.Kff, fi, fj)] += v;
+      }
+    }
+  }
+}
+
+namespace {
+// eigen-decomposition of a small symmetric q x q matrix (row-major) by
+// cyclic Jacobi rotations: w eigenvalues, V columns eigenvectors
+void sym_eigen_small(int q, std::vector<double> A, std::vector<double>& w, std::vector<double>& V) {
+  V.assign((size_t)q * q, 0.0);
+  for (int i = 0; i < q; ++i) V[(size_t)i * q + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0, tot = 0;
+    for (int i = 0; i < q; ++i)
+      for (int j = 0; j < q; ++j) {
+        const double x = A[(size_t)i * q + j] * A[(size_t)i * q + j];
+        tot += x;
+        if (i != j) off += x;
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < q; ++p)
+      for (int r = p + 1; r < q; ++r) {
+        const double apr = A[(size_t)p * q + r];
+        if (apr == 0.0) continue;
+        const double app = A[(size_t)p * q + p], arr = A[(size_t)r * q + r];
+        const double th = 0.5 * (arr - app) / apr;
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < q; ++k) {   // rows p, r
+          const double a1 = A[(size_t)p * q + k], a2 = A[(size_t)r * q + k];
+          A[(size_t)p * q + k] = cs * a1 - sn * a2;
+          A[(size_t)r * q + k] = sn * a1 + cs * a2;
+        }
+        for (int k = 0; k < q; ++k) {   // columns p, r
+          const double a1 = A[(size_t)k * q + p], a2 = A[(size_t)k * q + r];
+          A[(size_t)k * q + p] = cs * a1 - sn * a2;
+          A[(size_t)k * q + r] = sn * a1 + cs * a2;
+        }
+        for (int k = 0; k < q; ++k) {
+          const double v1 = V[(size_t)k * q + p], v2 = V[(size_t)k * q + r];
+          V[(size_t)k * q + p] = cs * v1 - sn * v2;
+          V[(size_t)k * q + r] = sn * v1 + cs * v2;
+        }
+      }
+  }
+  w.resize(q);
+  for (int i = 0; i < q; ++i) w[i] = A[(size_t)i * q + i];
+}
+}  // namespace
+
+void kl_expansion(const HostProblem& hp, double b, int m, std::vector<double>& beta, std::vector<double>& modes) {
+  const Mesh& M = hp.mesh;
+  const RefTables& R = ref();
+  const int n = hp.n_p, ne = (int)M.pconn.size(), ng = 9 * ne;
+  if (ng > 16000) throw std::runtime_error("KL expansion: mesh too fine for the dense covariance quadrature");
+  if (m < 1 || m > n) throw std::runtime_error("KL expansion: bad number of modes");
+  const double h = hp.prm.h, jw = 0.25 * h * h;
+  const double gp[3] = {-std::sqrt(0.6), 0.0, std::sqrt(0.6)};
+  std::vector<double> X((size_t)ng), Y((size_t)ng), W((size_t)ng);
+  for (int e = 0; e < ne; ++e) {
+    const int v0 = M.pconn[e][0];
+    const double x0 = M.pI[v0] * h / 2.0, y0 = M.pJ[v0] * h / 2.0;
+    for (int g = 0; g < 9; ++g) {
+      X[(size_t)e * 9 + g] = x0 + (gp[g % 3] + 1.0) * h / 2.0;
+      Y[(size_t)e * 9 + g] = y0 + (gp[g / 3] + 1.0) * h / 2.0;
+      W[(size_t)e * 9 + g] = R.w[g] * jw;
+    }
+  }
+  // T = K W Psi (ng x n), then C = Psi^T W T (n x n)
+  std::vector<double> T((size_t)ng * n, 0.0);
+  for (int gq = 0; gq < ng; ++gq) {
+    double* Tg = &T[(size_t)gq * n];
+    for (int e = 0; e < ne; ++e)
+      for (int g = 0; g < 9; ++g) {
+        const int hq = e * 9 + g;
+        const double kv = std::exp(-(std::fabs(X[gq] - X[hq]) + std::fabs(Y[gq] - Y[hq])) / b) * W[hq];
+        for (int k = 0; k < 4; ++k) Tg[M.pconn[e][k]] += kv * R.psi[g][k];
+      }
+  }
+  std::vector<double> C((size_t)n * n, 0.0);
+  for (int e = 0; e < ne; ++e)
+    for (int g = 0; g < 9; ++g) {
+      const int gq = e * 9 + g;
+      for (int k = 0; k < 4; ++k) {
+        const double f = W[gq] * R.psi[g][k];
+        double* Ck = &C[(size_t)M.pconn[e][k] * n];
+        const double* Tg = &T[(size_t)gq * n];
+        for (int l = 0; l < n; ++l) Ck[l] += f * Tg[l];
+      }
+    }
+  T.clear();
+  T.shrink_to_fit();
+  // M_p = L L^T (dense Cholesky), B = L^-1 C L^-T
+  std::vector<double> L((size_t)n * n, 0.0);
+  for (int k = 0; k < n; ++k)
+    for (int t = hp.Qp.rowptr[k]; t < hp.Qp.rowptr[k + 1]; ++t) L[(size_t)k * n + hp.Qp.col[t]] = hp.Mp[t];
+  for (int j = 0; j < n; ++j) {
+    double d = L[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(d > 0)) throw std::runtime_error("KL expansion: mass matrix not positive definite");
+    d = std::sqrt(d);
+    L[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double v = L[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) v -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = v / d;
+    }
+    for (int i = 0; i < j; ++i) L[(size_t)i * n + j] = 0.0;
+  }
+  auto lower_solve = [&](double* x) {   // x <- L^-1 x
+    for (int i = 0; i < n; ++i) {
+      double v = x[i];
+      for (int k = 0; k < i; ++k) v -= L[(size_t)i * n + k] * x[k];
+      x[i] = v / L[(size_t)i * n + i];
+    }
+  };
+  auto upper_solve = [&](double* x) {   // x <- L^-T x
+    for (int i = n - 1; i >= 0; --i) {
+      double v = x[i];
+      for (int k = i + 1; k < n; ++k) v -= L[(size_t)k * n + i] * x[k];
+      x[i] = v / L[(size_t)i * n + i];
+    }
+  };
+  // B = L^-1 C L^-T: columns of C solved, then rows (C symmetric)
+  std::vector<double> Bm(C);
+  std::vector<double> col(n);
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) col[i] = Bm[(size_t)i * n + j];
+    lower_solve(col.data());
+    for (int i = 0; i < n; ++i) Bm[(size_t)i * n + j] = col[i];
+  }
+  for (int i = 0; i < n; ++i) lower_solve(&Bm[(size_t)i * n]);
+  // subspace iteration for the m largest eigenpairs of B (symmetric)
+  const int q = std::min(n, m + 8);
+  std::vector<double> Xs((size_t)n * q), Z((size_t)n * q);
+  uint64_t st = 0x9e3779b97f4a7c15ull;
+  for (auto& v : Xs) {
+    st ^= st << 13; st ^= st >> 7; st ^= st << 17;
+    v = (double)(st >> 11) / 9007199254740992.0 - 0.5;
+  }
+  std::vector<double> w, V, prev(m, 0.0);
+  auto orthonormalize = [&](std::vector<double>& Q) {   // columns, modified Gram-Schmidt twice
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = 0; j < q; ++j) {
+        for (int k = 0; k < j; ++k) {
+          double d = 0;
+          for (int i = 0; i < n; ++i) d += Q[(size_t)i * q + k] * Q[(size_t)i * q + j];
+          for (int i = 0; i < n; ++i) Q[(size_t)i * q + j] -= d * Q[(size_t)i * q + k];
+        }
+        double nr = 0;
+        for (int i = 0; i < n; ++i) nr += Q[(size_t)i * q + j] * Q[(size_t)i * q + j];
+        nr = std::sqrt(nr);
+        for (int i = 0; i < n; ++i) Q[(size_t)i * q + j] /= nr;
+      }
+  };
+  orthonormalize(Xs);
+  bool done = false;
+  for (int it = 0; it < 5000 && !done; ++it) {
+    // Z = B Xs
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < q; ++j) {
+        double v = 0;
+        for (int k = 0; k < n; ++k) v += Bm[(size_t)i * n + k] * Xs[(size_t)k * q + j];
+        Z[(size_t)i * q + j] = v;
+      }
+    orthonormalize(Z);
+    // Rayleigh-Ritz: H = Z^T B Z
+    std::vector<double> BZ((size_t)n * q), H((size_t)q * q, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < q; ++j) {
+        double v = 0;
+        for (int k = 0; k < n; ++k) v += Bm[(size_t)i * n + k] * Z[(size_t)k * q + j];
+        BZ[(size_t)i * q + j] = v;
+      }
+    for (int a = 0; a < q; ++a)
+      for (int c = 0; c < q; ++c) {
+        double v = 0;
+        for (int i = 0; i < n; ++i) v += Z[(size_t)i * q + a] * BZ[(size_t)i * q + c];
+        H[(size_t)a * q + c] = v;
+      }
+    for (int a = 0; a < q; ++a)
+      for (int c = a + 1; c < q; ++c) H[(size_t)a * q + c] = H[(size_t)c * q + a] = 0.5 * (H[(size_t)a * q + c] + H[(size_t)c * q + a]);
+    sym_eigen_small(q, H, w, V);
+    std::vector<int> ord(q);
+    for (int i = 0; i < q; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int x, int y) { return w[x] > w[y]; });
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < q; ++j) {
+        double v = 0;
+        for (int k = 0; k < q; ++k) v += Z[(size_t)i * q + k] * V[(size_t)k * q + ord[j]];
+        Xs[(size_t)i * q + j] = v;
+      }
+    // converged when the m leading Ritz pairs have residuals ||B x - th x|| <= 1e-13 th_1
+    double worst = 0;
+    for (int j = 0; j < m; ++j) {
+      const double th = w[ord[j]];
+      double r2 = 0;
+      for (int i = 0; i < n; ++i) {
+        double v = 0;
+        for (int k = 0; k < n; ++k) v += Bm[(size_t)i * n + k] * Xs[(size_t)k * q + j];
+        v -= th * Xs[(size_t)i * q + j];
+        r2 += v * v;
+      }
+      worst = std::max(worst, std::sqrt(r2));
+      prev[j] = th;
+    }
+    done = worst <= 1e-13 * std::fabs(w[ord[0]]);
+  }
+  if (!done) throw std::runtime_error("KL expansion: subspace iteration did not converge");
+  beta.assign(prev.begin(), prev.end());
+  modes.assign((size_t)m * n, 0.0);
+  for (int j = 0; j < m; ++j) {
+    for (int i = 0; i < n; ++i) col[i] = Xs[(size_t)i * q + j];
+    upper_solve(col.data());
+    double amax = 0;
+    for (int i = 0; i < n; ++i) amax = std::max(amax, std::fabs(col[i]));
+    int first = 0;
+    while (std::fabs(col[first]) < 0.5 * amax) ++first;
+    const double sgn = col[first] < 0 ? -1.0 : 1.0;
+    for (int i = 0; i < n; ++i) modes[(size_t)j * n + i] = sgn * col[i];
   }
 }
 

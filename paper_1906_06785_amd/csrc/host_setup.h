@@ -25,6 +25,11 @@ struct ProblemParams {
   double h = 0.25, L = 12.0;
   int m = 2, p = 2, nt = 10;
   double tau = 0.1, nu0 = 1.0 / 50, nu_coef = 0.1, ramp = 10.0;
+  // 0: nu0 (1 + nu_coef sum_k xi_k / k^2), xi_k ~ U[-1,1]; 1: truncated KL
+  // expansion of exp(-||x - y||_1 / corr_length) (sec. 6.1), sigma = nu_coef,
+  // xi_k ~ U[-sqrt 3, sqrt 3]
+  int visc_law = 0;
+  double corr_length = 4.0;
 };
 
 struct Mesh {
@@ -64,6 +69,17 @@ struct HostProblem {
   std::vector<double> H;              // n_xi x n_xi x n_xi  (H[0] = I)
   std::vector<double> visc;           // c_0..c_m
   std::vector<double> Gnu;            // n_xi x n_xi
+  // viscous terms sum_t Gv_t (x) A_t of eq. 3.6: nvisc chaos matrices
+  // (n_xi x n_xi each) and stiffness value sets on Kff and Kfa.  Law 0: one
+  // term G_nu (x) A (unit A); law 1: nu0 I (x) A and sqrt 3 G_l (x)
+  // nu0 sigma sqrt(beta_l) A(a_l), l = 1..m.  Value set 0 is always the
+  // unit-viscosity A (the mean operator uses nu0 times it).
+  int nvisc = 1;
+  std::vector<double> Gvisc;
+  std::vector<std::vector<double>> Aff_visc, Afa_visc;
+  // KL expansion (law 1): eigenvalues beta_l and modes a_l at the Q1
+  // vertices (m x n_p, int a_l^2 = 1)
+  std::vector<double> kl_beta, kl_modes;
   // time
   std::vector<double> ramp;           // a_k = 1 - exp(-ramp t_k), k = 1..nt
   // Dirichlet lift over all velocity nodes: g_all (2 n_all)
@@ -92,6 +108,18 @@ void build_problem(const ProblemParams& prm, HostProblem& hp);
 // vals_fa != nullptr, on Kfa (free x all).
 void convection_values(const HostProblem& hp, const double* w1, const double* w2,
                        double* vals_ff, double* vals_fa);
+
+// Truncated Karhunen-Loeve expansion of exp(-||x - y||_1 / b) on the mesh
+// (sec. 6.1): Galerkin on the Q1 vertex space, C a = beta M_p a with
+// C_kl = int int c(x, y) psi_k(x) psi_l(y) by 3 x 3 Gauss quadrature in both
+// integrals; the m largest eigenpairs by subspace iteration, modes
+// M_p-orthonormal, signed so that the first vertex with |a| >= max|a| / 2
+// has a > 0.  Throws when the quadrature would not fit (meshes finer than
+// h = 1/8).
+void kl_expansion(const HostProblem& hp, double b, int m, std::vector<double>& beta, std::vector<double>& modes);
+// Values of the stiffness with coefficient field a (Q1 vertex values,
+// interpolated to the Gauss points) on Kff and, if vals_fa != nullptr, Kfa.
+void weighted_stiffness_values(const HostProblem& hp, const double* a_vertex, double* vals_ff, double* vals_fa);
 
 // Q1 pressure-space convection values [N_p(w)]_kl = (w . grad psi_l, psi_k)
 // on Qp for a Q2 wind given at all velocity nodes (sec. 5.1, F_p).

@@ -148,8 +148,8 @@ void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* 
 // the same product in FP32 (values, input and output)
 void ell_spmm32(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const float* eval,
                 const float* x, int ldx, int xcol0, int ncols, float* y, int ldy, int ycol0, float alpha, float beta);
-// C (float, m x n) = A B from FP64 operands rounded to FP32, FP32
-// accumulation on the matrix cores (strides as for gemm, batch 1)
+// C (float, m x n) = A B computed in FP64 on the matrix cores and rounded
+// to FP32 on the store (strides as for gemm, batch 1)
 void gemm_f32out(hipStream_t s, int m, int n, int k, const double* A, long sAi, long sAk, const double* B, long sBk,
                  long sBj, float* C, long sCi, long sCj);
 

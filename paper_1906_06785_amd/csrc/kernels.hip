@@ -314,12 +314,13 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, double alpha,
                   blockIdx.y * TM, blockIdx.x * TN);
 }
 
-// C (float) = A B with FP32 operands (rounded from FP64) and FP32
-// accumulation: the full-tensor expansion of the reduced-precision mean solve
+// C (float) = A B computed in FP64 and rounded once on the store: the
+// full-tensor expansion of the reduced-precision mean solve (the TT cores of
+// a sum can cancel in the product, so the product itself stays FP64)
 __global__ __launch_bounds__(256) void k_gemm_f32out(int m, int n, int k, const double* __restrict__ A, long sAi,
                                                      long sAk, const double* __restrict__ B, long sBk, long sBj,
                                                      float* __restrict__ C, long sCi, long sCj) {
-  gemm_core<GP_F32, float>(m, n, k, 1.0, A, sAi, sAk, B, sBk, sBj, 0.0, C, sCi, sCj, blockIdx.y * TM, blockIdx.x * TN);
+  gemm_core<GP_F64, float>(m, n, k, 1.0, A, sAi, sAk, B, sBk, sBj, 0.0, C, sCi, sCj, blockIdx.y * TM, blockIdx.x * TN);
 }
 
 template <int PREC>
@@ -2223,7 +2224,7 @@ void gemm_batched(hipStream_t s, int nb, const GemmDesc* d_desc, int max_m, int 
 void gemm_f32out(hipStream_t s, int m, int n, int k, const double* A, long sAi, long sAk, const double* B, long sBk,
                  long sBj, float* C, long sCi, long sCj) {
   if (m <= 0 || n <= 0) return;
-  ProfScope ps(KC_GEMM_LOWP, s, 8.0 * ((double)m * k + (double)k * n) + 4.0 * m * (double)n, 2.0 * m * n * (double)k);
+  ProfScope ps(KC_GEMM, s, 8.0 * ((double)m * k + (double)k * n) + 4.0 * m * (double)n, 2.0 * m * n * (double)k);
   hipLaunchKernelGGL(k_gemm_f32out, dim3(cdiv(n, TN), cdiv(m, TM)), dim3(256), 0, s, m, n, k, A, sAi, sAk, B, sBk, sBj,
                      C, sCi, sCj);
 }

@@ -186,12 +186,14 @@ struct sgtt_system {
   int nt = 0, nxi = 0, ns = 0, nu = 0, np = 0, nall = 0;
   double tau = 0, nu0 = 0;
   // operator data
-  DevCsr Kop;       // free x free scalar pattern: [M, A, N_1..N_k2]
+  DevCsr Kop;       // free x free scalar pattern: [M, A_0..A_{nvisc-1}, N_1..N_k2] (operator)
+  DevCsr Kmean;     // the same pattern: [M, A (unit), N_1..N_k2] (mean matrix, eq. 5.20-5.21)
   DevCsr Bd, Btd;   // B (n_p x n_u), B^T (n_u x n_p)
   DevCsr Xmid;      // pressure pattern: [XM, XA, XN_1..XN_k2]
   DevCsr Fp;        // Q1 pressure pattern: [M_p, A_p, N_p(w3_1)..N_p(w3_k2)] (PCD, eq. 5.17)
   DevCsr Mpinv;     // diag(M_p)^-1 as a diagonal CSR matrix (PCD)
-  double* Gnu = nullptr;   // n_xi x n_xi
+  double* Gvisc = nullptr; // nvisc chaos matrices (n_xi x n_xi) of the viscous terms (eq. 3.6)
+  int nvisc = 1;
   int k1 = 0, k2 = 0;      // convection TT-operator ranks (0: Stokes)
   double* w1 = nullptr;    // nt x k1
   double* Hw = nullptr;    // k1 x k2 x nxi x nxi
@@ -214,6 +216,7 @@ struct sgtt_system {
     if (mlp_collect) --mlp_collect->uses;
     if (mlp_apply) --mlp_apply->uses;
     Kop.free_all();
+    Kmean.free_all();
     Bd.free_all();
     Btd.free_all();
     Xmid.free_all();
@@ -223,7 +226,7 @@ struct sgtt_system {
     free_bcr(Xbt);
     for (void* p : {(void*)Me_col, (void*)Me_val, (void*)Me_val32})
       if (p) (void)hipFree(p);
-    for (double* p : {Gnu, w1, Hw, omega, dsc, Dinv}) (void)hipFree(p);
+    for (double* p : {Gvisc, w1, Hw, omega, dsc, Dinv}) (void)hipFree(p);
   }
 };
 
@@ -233,25 +236,27 @@ namespace {
 // L applied to (u, p): velocity part (eq. 3.12 with eq. 4.4 and eq. 4.12)
 TT apply_velocity(sgtt_system& S, const TT& u, const TT& p) {
   Ctx& c = S.ctx->c;
-  const int r1u = u.r1, r2u = u.r2, r1p = p.r1, r2p = p.r2, k1 = S.k1, k2 = S.k2;
-  const int R1 = 2 * r1u + k1 * r1u + r1p, R2 = 2 * r2u + k2 * r2u + r2p;
+  const int r1u = u.r1, r2u = u.r2, r1p = p.r1, r2p = p.r2, k1 = S.k1, k2 = S.k2, nv = S.nvisc;
+  const int R1 = 2 * r1u + k1 * r1u + r1p, R2 = (1 + nv) * r2u + k2 * r2u + r2p;
   TT o = tt_new(c, S.nt, S.nxi, S.nu, R1, R2);
   // core 1: [(I - C)/tau u1 | u1 | diag(w1_a) u1 | p1]
   core1_op(c.s, 0, S.nt, r1u, u.c1, r1u, o.c1, R1, 0, 1.0 / S.tau);
   core1_op(c.s, 1, S.nt, r1u, u.c1, r1u, o.c1, R1, r1u, 1.0);
   if (k1) core1_diag(c.s, S.nt, r1u, k1, S.w1, k1, u.c1, r1u, o.c1, R1, 2 * r1u);
   core1_op(c.s, 1, S.nt, r1p, p.c1, r1p, o.c1, R1, 2 * r1u + k1 * r1u, 1.0);
-  // core 2: blocks [u2 ; G_nu u2 ; (sum_l w2(a,l,b) H_l) u2 ; p2]
+  // core 2: blocks [u2 ; (Gv_0 u2 | .. | Gv_{nv-1} u2) ; (sum_l w2(a,l,b) H_l) u2 ; p2]
+  // (the viscous terms share the time factor u1 of core 1)
   fill(c.s, o.c2, o.n_c2(), 0.0);
   core2_block(c.s, r1u, S.nxi, r2u, u.c2, nullptr, 1, 1, o.c2, R1, R2, 0, 0);
-  core2_block(c.s, r1u, S.nxi, r2u, u.c2, S.Gnu, 1, 1, o.c2, R1, R2, r1u, r2u);
-  if (k1) core2_block(c.s, r1u, S.nxi, r2u, u.c2, S.Hw, k1, k2, o.c2, R1, R2, 2 * r1u, 2 * r2u);
-  core2_block(c.s, r1p, S.nxi, r2p, p.c2, nullptr, 1, 1, o.c2, R1, R2, 2 * r1u + k1 * r1u, 2 * r2u + k2 * r2u);
-  // core 3: [M u3 | A u3 | N_b u3 | B^T p3]
-  spmm(c.s, S.ns, 2, S.ns, S.ns, S.Kop.rowptr, S.Kop.col, S.Kop.vals, 2 + k2, S.Kop.nnz, u.c3, r2u, 0, r2u, o.c3,
-       R2, 0, r2u, 1.0);
+  core2_block(c.s, r1u, S.nxi, r2u, u.c2, S.Gvisc, 1, nv, o.c2, R1, R2, r1u, r2u);
+  if (k1) core2_block(c.s, r1u, S.nxi, r2u, u.c2, S.Hw, k1, k2, o.c2, R1, R2, 2 * r1u, (1 + nv) * r2u);
+  core2_block(c.s, r1p, S.nxi, r2p, p.c2, nullptr, 1, 1, o.c2, R1, R2, 2 * r1u + k1 * r1u,
+              (1 + nv) * r2u + k2 * r2u);
+  // core 3: [M u3 | A_0 u3 .. A_{nv-1} u3 | N_b u3 | B^T p3]
+  spmm(c.s, S.ns, 2, S.ns, S.ns, S.Kop.rowptr, S.Kop.col, S.Kop.vals, 1 + nv + k2, S.Kop.nnz, u.c3, r2u, 0, r2u,
+       o.c3, R2, 0, r2u, 1.0);
   spmm(c.s, S.nu, 1, 0, 0, S.Btd.rowptr, S.Btd.col, S.Btd.vals, 1, 0, p.c3, r2p, 0, r2p, o.c3, R2,
-       2 * r2u + k2 * r2u, 0, 1.0, 0.0, S.Btd.max_row);
+       (1 + nv) * r2u + k2 * r2u, 0, 1.0, 0.0, S.Btd.max_row);
   return o;
 }
 
@@ -593,7 +598,7 @@ struct InnerSpace : Space {
   Vec apply(const Vec& x) override {
     Vec y;
     y.nc = 1;
-    y.c[0] = apply_mean_sum(S, x.c[0], S.Kop, 2, S.ns);
+    y.c[0] = apply_mean_sum(S, x.c[0], S.Kmean, 2, S.ns);
     return y;
   }
   Vec precond(const Vec& x) override {
@@ -621,7 +626,7 @@ struct PrecOpts {
 // block forward substitution in time on the full-format velocity (node-major,
 // columns (t, xi)), then TT-SVD (Alg. 4.1) at eps.
 // The same solve in FP32 (precision option 1): the expansion writes the full
-// velocity tensor in FP32 (FP32 operands, FP32 accumulation), the time steps
+// velocity tensor in FP32 (computed in FP64, rounded on the store), the time steps
 // run the FP32 ELL mass product and FP32 block cyclic reduction passes, and
 // the transpose widens the result to FP64 for the TT-SVD, whose Grams, rank
 // decisions and projections stay FP64.  The result is accurate to FP32
@@ -931,9 +936,16 @@ void build_convection(sgtt_system& S, Ctx& c, const TT& wtil) {
   S.Hw = dev_upload(c, Hw);
   S.omega = dev_upload(c, om);
   // operator value sets
-  std::vector<const double*> vs{hp.Mff.data(), hp.Aff.data()};
-  for (int b = 0; b < k2; ++b) vs.push_back(Nv[b].data());
+  std::vector<const double*> vs{hp.Mff.data()}, vm{hp.Mff.data(), hp.Aff.data()};
+  for (const auto& a : hp.Aff_visc) vs.push_back(a.data());
+  for (int b = 0; b < k2; ++b) {
+    vs.push_back(Nv[b].data());
+    vm.push_back(Nv[b].data());
+  }
+  S.Kop.free_all();
+  S.Kmean.free_all();
   S.Kop = upload_csr(c, hp.Kff, vs);
+  S.Kmean = upload_csr(c, hp.Kff, vm);
   std::vector<const double*> xs{hp.XM.data(), hp.XA.data()};
   for (int b = 0; b < k2; ++b) xs.push_back(XNv[b].data());
   S.Xmid = upload_csr(c, hp.Xmid, xs);
@@ -1080,6 +1092,8 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
   prm.nu0 = desc->nu0;
   prm.nu_coef = desc->nu_coef;
   prm.ramp = desc->ramp;
+  prm.visc_law = desc->viscosity_law;
+  prm.corr_length = desc->corr_length;
   try {
     build_problem(prm, S->hp);
   } catch (const std::exception& e) {
@@ -1095,7 +1109,8 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
   S->tau = prm.tau;
   S->nu0 = prm.nu0;
   SGTT_HIP(hipMalloc(&S->dsc, 32768 * sizeof(double)));
-  S->Gnu = dev_upload(c, hp.Gnu);
+  S->nvisc = hp.nvisc;
+  S->Gvisc = dev_upload(c, hp.Gvisc);
   S->Bd = upload_csr(c, hp.B, {hp.B.val.data()});
   S->Btd = upload_csr(c, hp.Bt, {hp.Bt.val.data()});
   S->Xbt = factor_bcr(c, hp.Xp, hp.Xp.val.data(), hp.p_blocks);
@@ -1142,41 +1157,51 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
   if (!prior) {
     // Stokes system: no convection; f = -L_{free,all}(0) lift (ranks 2 and 1)
     S->k1 = S->k2 = 0;
-    S->Kop = upload_csr(c, hp.Kff, {hp.Mff.data(), hp.Aff.data()});
+    {
+      std::vector<const double*> vs{hp.Mff.data()};
+      for (const auto& a : hp.Aff_visc) vs.push_back(a.data());
+      S->Kop = upload_csr(c, hp.Kff, vs);
+      S->Kmean = upload_csr(c, hp.Kff, {hp.Mff.data(), hp.Aff.data()});
+    }
     S->Xmid = upload_csr(c, hp.Xmid, {hp.XM.data(), hp.XA.data()});
     S->Fp = upload_csr(c, hp.Qp, {hp.Mp.data(), hp.Ap.data()});
     std::vector<double> F(hp.Kff.nnz());
     for (int t = 0; t < hp.Kff.nnz(); ++t) F[t] = hp.Mff[t] / S->tau + S->nu0 * hp.Aff[t];
     S->Dinv = dev_upload(c, inverse_diagonal(hp.Kff, F.data()));
     S->Fbt = factor_bcr(c, hp.Kff, F.data(), hp.vel_blocks);
-    // f^u: core1 [(I-C)a/tau | a], core2 [e1 ; G_nu e1], core3 -[M_fa g | A_fa g]
-    std::vector<double> Ca(nt), c1((size_t)nt * 2), c2((size_t)2 * nxi * 2, 0.0);
+    // f^u: core1 [(I-C)a/tau | a], core2 [e1 ; (Gv_0 e1 | .. | Gv_{nv-1} e1)],
+    // core3 -[M_fa g | A_0,fa g | .. | A_{nv-1},fa g]
+    const int nv = hp.nvisc, rb = 1 + nv;
+    std::vector<double> Ca(nt), c1((size_t)nt * 2), c2((size_t)2 * nxi * rb, 0.0);
     for (int k = 0; k < nt; ++k) {
       c1[(size_t)k * 2 + 0] = (hp.ramp[k] - (k > 0 ? hp.ramp[k - 1] : 0.0)) / S->tau;
       c1[(size_t)k * 2 + 1] = hp.ramp[k];
     }
     for (int i = 0; i < nxi; ++i) {
-      c2[((size_t)0 * nxi + i) * 2 + 0] = e1[i];
-      c2[((size_t)1 * nxi + i) * 2 + 1] = hp.Gnu[(size_t)i * nxi + 0];
+      c2[((size_t)0 * nxi + i) * rb + 0] = e1[i];
+      for (int v = 0; v < nv; ++v)
+        c2[((size_t)1 * nxi + i) * rb + 1 + v] = hp.Gvisc[((size_t)v * nxi + i) * nxi + 0];
     }
-    std::vector<double> c3((size_t)2 * ns * 2, 0.0), pc3(hp.n_p, 0.0);
+    std::vector<double> c3((size_t)2 * ns * rb, 0.0), pc3(hp.n_p, 0.0);
     for (int comp = 0; comp < 2; ++comp)
       for (int i = 0; i < ns; ++i) {
-        double sm = 0, sa = 0;
-        for (int t = hp.Kfa.rowptr[i]; t < hp.Kfa.rowptr[i + 1]; ++t) {
-          double g = hp.g_all[(size_t)comp * nall + hp.Kfa.col[t]];
-          sm += hp.Mfa[t] * g;
-          sa += hp.Afa[t] * g;
+        double sm = 0;
+        for (int t = hp.Kfa.rowptr[i]; t < hp.Kfa.rowptr[i + 1]; ++t)
+          sm += hp.Mfa[t] * hp.g_all[(size_t)comp * nall + hp.Kfa.col[t]];
+        c3[((size_t)comp * ns + i) * rb + 0] = -sm;
+        for (int v = 0; v < nv; ++v) {
+          double sa = 0;
+          for (int t = hp.Kfa.rowptr[i]; t < hp.Kfa.rowptr[i + 1]; ++t)
+            sa += hp.Afa_visc[v][t] * hp.g_all[(size_t)comp * nall + hp.Kfa.col[t]];
+          c3[((size_t)comp * ns + i) * rb + 1 + v] = -sa;
         }
-        c3[((size_t)comp * ns + i) * 2 + 0] = -sm;
-        c3[((size_t)comp * ns + i) * 2 + 1] = -sa;
       }
     for (int k = 0; k < hp.n_p; ++k) {
       double s = 0;
       for (int t = hp.Ball.rowptr[k]; t < hp.Ball.rowptr[k + 1]; ++t) s += hp.Ball.val[t] * hp.g_all[hp.Ball.col[t]];
       pc3[k] = -s;
     }
-    S->bu = tt_new(c, nt, nxi, hp.n_u, 2, 2);
+    S->bu = tt_new(c, nt, nxi, hp.n_u, 2, rb);
     SGTT_HIP(hipMemcpyAsync(S->bu.c1, c1.data(), c1.size() * 8, hipMemcpyHostToDevice, c.s));
     SGTT_HIP(hipMemcpyAsync(S->bu.c2, c2.data(), c2.size() * 8, hipMemcpyHostToDevice, c.s));
     SGTT_HIP(hipMemcpyAsync(S->bu.c3, c3.data(), c3.size() * 8, hipMemcpyHostToDevice, c.s));
@@ -1220,7 +1245,10 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
     // element (its TT ranks would be the squares of the iterate's)
     {
       if (nxi > 64) throw SgttError(-1, "Picard residual: n_xi > 64 not supported");
-      DevCsr Kfa = upload_csr(c, hp.Kfa, {hp.Mfa.data(), hp.Afa.data()});
+      std::vector<const double*> fa{hp.Mfa.data()};
+      for (const auto& a : hp.Afa_visc) fa.push_back(a.data());
+      DevCsr Kfa = upload_csr(c, hp.Kfa, fa);
+      const int nv = hp.nvisc;
       DevCsr Ball = upload_csr(c, hp.Ball, {hp.Ball.val.data()});
       const TT& w = wall;
       TT pview = tt_view(prior->p.n1, prior->p.n2, prior->p.n3, prior->p.r1, prior->p.r2, prior->p.core1,
@@ -1228,7 +1256,7 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
       TT uview = tt_view(pu.n1, pu.n2, pu.n3, pu.r1, pu.r2, pu.core1, pu.core2, pu.core3);
       const TT& p = pview;
       const int r1u = w.r1, r2u = w.r2, r1p = p.r1, r2p = p.r2;
-      const int R1 = 2 * r1u + r1p, R2 = 2 * r2u + r2p;
+      const int R1 = 2 * r1u + r1p, R2 = (1 + nv) * r2u + r2p;
       TT ru = tt_new(c, nt, nxi, hp.n_u, R1, R2);
       core1_op(c.s, 0, nt, r1u, w.c1, r1u, ru.c1, R1, 0, 1.0 / S->tau);
       core1_op(c.s, 1, nt, r1u, w.c1, r1u, ru.c1, R1, r1u, 1.0);
@@ -1236,12 +1264,12 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
       copy2d(c.s, nt, R1, ru.c1, R1, ru.c1, R1, -1.0, nullptr, 0);   // r = -(...)
       fill(c.s, ru.c2, ru.n_c2(), 0.0);
       core2_block(c.s, r1u, nxi, r2u, w.c2, nullptr, 1, 1, ru.c2, R1, R2, 0, 0);
-      core2_block(c.s, r1u, nxi, r2u, w.c2, S->Gnu, 1, 1, ru.c2, R1, R2, r1u, r2u);
-      core2_block(c.s, r1p, nxi, r2p, p.c2, nullptr, 1, 1, ru.c2, R1, R2, 2 * r1u, 2 * r2u);
-      spmm(c.s, ns, 2, nall, ns, Kfa.rowptr, Kfa.col, Kfa.vals, 2, Kfa.nnz, w.c3, r2u, 0, r2u, ru.c3, R2, 0, r2u,
-           1.0);
+      core2_block(c.s, r1u, nxi, r2u, w.c2, S->Gvisc, 1, nv, ru.c2, R1, R2, r1u, r2u);
+      core2_block(c.s, r1p, nxi, r2p, p.c2, nullptr, 1, 1, ru.c2, R1, R2, 2 * r1u, (1 + nv) * r2u);
+      spmm(c.s, ns, 2, nall, ns, Kfa.rowptr, Kfa.col, Kfa.vals, 1 + nv, Kfa.nnz, w.c3, r2u, 0, r2u, ru.c3, R2, 0,
+           r2u, 1.0);
       spmm(c.s, hp.n_u, 1, 0, 0, S->Btd.rowptr, S->Btd.col, S->Btd.vals, 1, 0, p.c3, r2p, 0, r2p, ru.c3, R2,
-           2 * r2u, 0, 1.0, 0.0, S->Btd.max_row);
+           (1 + nv) * r2u, 0, 1.0, 0.0, S->Btd.max_row);
       TT rp = tt_new(c, nt, nxi, hp.n_p, r1u, r2u);
       copy2d(c.s, nt, r1u, w.c1, r1u, rp.c1, r1u, -1.0, nullptr, 0);
       SGTT_HIP(hipMemcpyAsync(rp.c2, w.c2, sizeof(double) * w.n_c2(), hipMemcpyDeviceToDevice, c.s));
@@ -1909,6 +1937,8 @@ int sgtt_host_problem_create(const sgtt_problem_desc* desc, sgtt_host_problem** 
     prm.nu0 = desc->nu0;
     prm.nu_coef = desc->nu_coef;
     prm.ramp = desc->ramp;
+    prm.visc_law = desc->viscosity_law;
+    prm.corr_length = desc->corr_length;
     build_problem(prm, h->hp);
     *out = h.release();
   } catch (...) {
@@ -1948,7 +1978,13 @@ int sgtt_host_csr(const sgtt_host_problem* h, int which, int* nrows, int* ncols,
     case 5: pat = &hp.Xmid; v = hp.XA.data(); break;
     case 6: pat = &hp.Qp; v = hp.Mp.data(); break;
     case 7: pat = &hp.Qp; v = hp.Ap.data(); break;
-    default: return SGTT_E_INVALID;
+    default:
+      if (which >= 8 && which < 8 + hp.nvisc) {
+        pat = &hp.Kff;
+        v = hp.Aff_visc[which - 8].data();
+        break;
+      }
+      return SGTT_E_INVALID;
   }
   if (nrows) *nrows = pat->nrows;
   if (ncols) *ncols = pat->ncols;
@@ -1956,6 +1992,17 @@ int sgtt_host_csr(const sgtt_host_problem* h, int which, int* nrows, int* ncols,
   if (rowptr) std::copy(pat->rowptr.begin(), pat->rowptr.end(), rowptr);
   if (col) std::copy(pat->col.begin(), pat->col.end(), col);
   if (val) std::copy(v, v + pat->nnz(), val);
+  return SGTT_OK;
+}
+
+int sgtt_host_kl(const sgtt_host_problem* h, int* nmodes, int* nvisc, double* beta, double* modes) {
+  if (!h) return SGTT_E_INVALID;
+  const HostProblem& hp = h->hp;
+  const int m = (int)hp.kl_beta.size();
+  if (nmodes) *nmodes = m;
+  if (nvisc) *nvisc = hp.nvisc;
+  if (beta) std::copy(hp.kl_beta.begin(), hp.kl_beta.end(), beta);
+  if (modes) std::copy(hp.kl_modes.begin(), hp.kl_modes.end(), modes);
   return SGTT_OK;
 }
 
@@ -1986,7 +2033,8 @@ int sgtt_host_bcr_solve(const sgtt_host_problem* h, int which, double tau, doubl
 int sgtt_host_gpc(const sgtt_host_problem* h, int which, double* out) {
   if (!h || !out) return SGTT_E_INVALID;
   const HostProblem& hp = h->hp;
-  const std::vector<double>* src = which == 0 ? &hp.G : which == 1 ? &hp.H : which == 2 ? &hp.Gnu : nullptr;
+  const std::vector<double>* src = which == 0 ? &hp.G : which == 1 ? &hp.H : which == 2 ? &hp.Gnu
+                                  : which == 3 ? &hp.Gvisc : nullptr;
   if (!src) return SGTT_E_INVALID;
   std::copy(src->begin(), src->end(), out);
   return SGTT_OK;

@@ -40,7 +40,8 @@ class SgttPair(C.Structure):
 class ProblemDesc(C.Structure):
     _fields_ = [("h", C.c_double), ("L", C.c_double), ("m", C.c_int), ("p", C.c_int), ("nt", C.c_int),
                 ("tau", C.c_double), ("nu0", C.c_double), ("nu_coef", C.c_double), ("ramp", C.c_double),
-                ("eps_conv", C.c_double), ("eps_rhs", C.c_double)]
+                ("eps_conv", C.c_double), ("eps_rhs", C.c_double), ("viscosity_law", C.c_int),
+                ("corr_length", C.c_double)]
 
 
 class SystemInfo(C.Structure):
@@ -157,6 +158,8 @@ _sig = {
     "sgtt_host_csr": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                 C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "sgtt_host_gpc": (C.c_int, [_P, C.c_int, C.POINTER(C.c_double)]),
+    "sgtt_host_kl": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double),
+                               C.POINTER(C.c_double)]),
     "sgtt_host_mesh": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "sgtt_bcr_apply": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
     "sgtt_bcr_variant_count": (C.c_int, []),
@@ -181,7 +184,8 @@ class SgttError(RuntimeError):
 def make_desc(cfg: dict, eps_conv=1e-3, eps_rhs=1e-6) -> ProblemDesc:
     return ProblemDesc(float(cfg["h"]), float(cfg.get("L", 12.0)), int(cfg["m"]), int(cfg["p"]), int(cfg["nt"]),
                        float(cfg["tau"]), float(cfg["nu0"]), float(cfg["nu_coef"]), float(cfg.get("ramp", 10.0)),
-                       float(cfg.get("eps_conv", eps_conv)), float(cfg.get("eps_rhs", eps_rhs)))
+                       float(cfg.get("eps_conv", eps_conv)), float(cfg.get("eps_rhs", eps_rhs)),
+                       1 if cfg.get("viscosity", "power") == "kl" else 0, float(cfg.get("corr_length", 4.0)))
 
 
 def make_opts(**kw) -> SolveOpts:
@@ -241,11 +245,23 @@ class HostProblem:
 
     def gpc(self, which: int):
         n = self.n_xi
-        size = {0: (self.m + 1) * n * n, 1: n ** 3, 2: n * n}[which]
+        nv = self.kl()[2] if which == 3 else 0
+        size = {0: (self.m + 1) * n * n, 1: n ** 3, 2: n * n, 3: nv * n * n}[which]
         out = np.zeros(size)
         _lib.sgtt_host_gpc(self._h, which, out.ctypes.data_as(C.POINTER(C.c_double)))
-        shape = {0: (self.m + 1, n, n), 1: (n, n, n), 2: (n, n)}[which]
+        shape = {0: (self.m + 1, n, n), 1: (n, n, n), 2: (n, n), 3: (nv, n, n)}[which]
         return out.reshape(shape)
+
+    def kl(self):
+        """(beta, modes (m x n_p), number of viscous terms) of the KL law;
+        empty arrays for the other law."""
+        nm, nv = C.c_int(), C.c_int()
+        _lib.sgtt_host_kl(self._h, C.byref(nm), C.byref(nv), None, None)
+        beta = np.zeros(nm.value)
+        modes = np.zeros((nm.value, self.n_p))
+        _lib.sgtt_host_kl(self._h, None, None, beta.ctypes.data_as(C.POINTER(C.c_double)),
+                          modes.ctypes.data_as(C.POINTER(C.c_double)))
+        return beta, modes, nv.value
 
     def mesh(self):
         coords = np.zeros(2 * self.n_all)
