@@ -196,8 +196,8 @@ def solve_options(args=None):
 # of known size): bytes per launch, valid while the kernel source it was
 # measured on is unchanged (digest of the block cyclic reduction section of
 # kernels.hip and of the host factorization).  None until measured.
-TRAFFIC_RECORD = {"kernel_src_sha256": "12eb2c4c70deb575f017698bb4d7b98b56ab3dc6b5ed67aab8c86a749f5e63ac",
-                  "bytes_per_launch": 32953178, "fetch_bytes_per_launch": 30163588, "write_bytes_per_launch": 2789590,
+TRAFFIC_RECORD = {"kernel_src_sha256": "64d19edf8066ca1089c329bbe08a9a22b9037d3708e31f06ad274193367a0f78",
+                  "bytes_per_launch": 33188862, "fetch_bytes_per_launch": 30331157, "write_bytes_per_launch": 2857705,
                   "summary": "profiles/k_bcr_c2_stokes_traffic.md"}
 
 
