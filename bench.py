@@ -57,6 +57,9 @@ def parse(argv=None):
                     help="N > 0: instead, time N independent problems (batch_configs) on --contexts streams")
     ap.add_argument("--contexts", type=int, default=8)
     ap.add_argument("--batch-small", action="store_true", help="coarse grids / short horizons for the batch")
+    ap.add_argument("--event-sample", type=int, default=8,
+                    help="in the timed region, bracket one scope of the dominant kernel class in every N with "
+                         "HIP events (a scope is one launch, or one spatial solve's passes)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="M > 0: before the timed solves, one device-to-device copy of M MiB (a plain copy kernel "
                          "of known size for scaling memory counters)")
@@ -70,7 +73,7 @@ def parse(argv=None):
     ap.add_argument("--picard", type=int, default=0,
                     help="N > 0: instead, run Picard's method (Alg. 3.1) for N steps after the Stokes solve and print "
                          "the per-step record")
-    ap.add_argument("--sweep", default="", choices=("", "paper", "sigma", "nu0", "h", "tau", "kl", "kl_tol"),
+    ap.add_argument("--sweep", default="", choices=("",) + tuple(SWEEPS),
                     help="instead, run Picard's method with the paper's tolerances (Table 6.2) on the Table 6.1 "
                          "sizes, varying one parameter (sec. 6.3), and print ranks, storage ratio and times")
     return ap.parse_args(argv)
@@ -82,7 +85,11 @@ def parse(argv=None):
 # tol_picard = 1e-5
 PAPER_TOLERANCES = dict(solve=dict(tol=1e-1, eps_krylov=1e-3, tol_cycle=1e-1, inner_tol=1e-1, inner_eps=1e-3,
                                    max_cycles=4, restart=30, relax=0, outer_explicit=1, inner_mode=0),
-                        eps_soln=1e-7, eps_conv=1e-3, eps_rhs=1e-3, tol_picard=1e-5, max_steps=10)
+                        eps_soln=1e-7, eps_conv=1e-3, eps_rhs=1e-3, tol_picard=1e-5, max_steps=10,
+                        # the update truncated, the sum kept exact: the Gram-based rounding of the sum
+                        # itself (update_mode 0, eq. 4.8 as written) leaves the nonlinear residual
+                        # level at about 1.1e-5, just above tol_picard (the "floor" sweep)
+                        update_mode=1)
 
 # one-parameter variations of the Table 6.1 problem (sec. 6.3, Figs. 6.5-6.6);
 # sigma is this build's relative viscosity amplitude nu_coef, h keeps the
@@ -98,6 +105,11 @@ SWEEPS = {
     # Table 6.3: tighter GMRES tolerances with eps_gmres = 1e-2 tol_gmres
     "kl_tol": [dict(base="paper_kl", solve=dict(tol=t, tol_cycle=t, eps_krylov=1e-2 * t, inner_eps=1e-2 * t),
                     eps_rhs=1e-2 * t) for t in (1e-1, 1e-2, 1e-3)],
+    # eq. 4.8 as written (the updated iterate rounded, update_mode 0): the
+    # nonlinear residual levels off near 1.1e-5 whatever the truncation of
+    # the iterate or of the convection field
+    "floor": [dict(base="paper_kl", update_mode=0, eps_soln=e) for e in (1e-7, 1e-9)]
+             + [dict(base="paper_kl", update_mode=0, eps_conv=1e-5)],
 }
 
 
@@ -119,19 +131,26 @@ def sweep_main(args):
         base = over.pop("base", "paper")
         solve = dict(tol["solve"], **over.pop("solve", {}))
         eps_rhs = over.pop("eps_rhs", tol["eps_rhs"])
+        eps_soln = over.pop("eps_soln", tol["eps_soln"])
+        eps_conv = over.pop("eps_conv", tol["eps_conv"])
+        update_mode = over.pop("update_mode", tol["update_mode"])
         cfg = dict(CONFIGS[base], **over)
         hp = sgtt.HostProblem(cfg)
         t0 = time.perf_counter()
         x, st, rc = sgtt.picard(ctx, cfg, steps=tol["max_steps"], tol_picard=tol["tol_picard"],
-                                eps_soln=tol["eps_soln"], eps_conv=tol["eps_conv"], eps_rhs=eps_rhs,
-                                caps=OUT_CAPS, **solve)
-        over.update(base=base, solve=solve, eps_rhs=eps_rhs)
+                                eps_soln=eps_soln, eps_conv=eps_conv, eps_rhs=eps_rhs,
+                                caps=OUT_CAPS, update_mode=update_mode, **solve)
+        over.update(base=base, solve=solve, eps_rhs=eps_rhs, eps_soln=eps_soln, eps_conv=eps_conv,
+                    update_mode=update_mode)
         el = time.perf_counter() - t0
-        ru, rp = x.ranks
+        # ranks of the final iterate rounded at eps_soln (eq. 4.8); with
+        # update_mode 1 the stored exact sum has the larger stored ranks
+        ru, rp = tuple(st["rank_u"][-1]), tuple(st["rank_p"][-1])
         runs.append({"params": over, "n_t": hp.nt, "n_xi": hp.n_xi, "n_u": hp.n_u, "n_p": hp.n_p, "status": rc,
                      "picard_steps": st["steps"], "nonlinear_residual": st["nonlinear_residual"],
                      "gmres_iters": st["outer_iters"], "inner_iters": st["inner_iters"],
-                     "rank_u": ru, "rank_p": rp,
+                     "rank_u": ru, "rank_p": rp, "rank_u_per_step": st["rank_u"], "rank_p_per_step": st["rank_p"],
+                     "stored_rank_u": tuple(x.ranks[0]), "stored_rank_p": tuple(x.ranks[1]),
                      "storage_ratio_u": storage_ratio(hp.nt, hp.n_xi, hp.n_u, ru),
                      "storage_ratio_p": storage_ratio(hp.nt, hp.n_xi, hp.n_p, rp),
                      "seconds": el, "solve_seconds": st["solve_seconds"]})
@@ -471,8 +490,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    # timed region: events on the dominant class only
+    # timed region: events on the dominant class only, on one of its scopes
+    # in every --event-sample (evenly spread over the timed solves)
     ctx.profile(True, classes=[dom_name])
+    ctx.profile_sample(args.event_sample)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -482,6 +503,7 @@ def main():
     torch.cuda.synchronize()
     prof = ctx.profile_read()
     ctx.profile(False)
+    ctx.profile_sample(1)
     ev_s = ev0.elapsed_time(ev1) * 1e-3
     dom = prof[dom_name]
     by, fl, sec, nl = dom["bytes"], dom["flops"], dom["seconds"], dom["launches"]
@@ -496,7 +518,11 @@ def main():
     roof.update({"kernel": KERNEL_LABELS.get(dom_name, dom_name), "launches": nl,
                  "avg_launch_us": sec / max(nl, 1) * 1e6,
                  "algorithmic_bytes_per_launch": by / max(nl, 1), "algorithmic_flops_per_launch": fl / max(nl, 1),
-                 "share_of_timed_region": sec / ev_s if ev_s > 0 else None,
+                 # launches and seconds cover the sampled scopes: one in every
+                 # event_sample_period, so the class's share of the timed
+                 # region is about period times the sampled seconds
+                 "event_sample_period": args.event_sample,
+                 "share_of_timed_region": sec * args.event_sample / ev_s if ev_s > 0 else None,
                  "traffic": recorded_traffic(dom_name) if args.system == "stokes" and args.config == "C2" else None})
     outer = int(round(sum(s["outer_iters"] for s in stats) / len(stats)))
     worst = max(s["rel_residual"] for s in stats)

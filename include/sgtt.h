@@ -195,6 +195,12 @@ int sgtt_context_memory(const sgtt_context* ctx, sgtt_memory_info* out);
 const char* sgtt_last_error(const sgtt_context* ctx);
 /* build identification string (static storage) */
 const char* sgtt_version(void);
+/* sizeof of the public structs, in this order: sgtt_tt, sgtt_tt_pair,
+ * sgtt_problem_desc, sgtt_system_info, sgtt_solve_opts, sgtt_solve_stats,
+ * sgtt_memory_info, sgtt_picard_opts, sgtt_picard_stats; the first
+ * min(n, 9) go to sizes.  Returns the number of structs (9).  For bindings
+ * that mirror the structs (host only, no device call). */
+int sgtt_abi_sizes(long* sizes, int n);
 
 /* ------------------------------------------------------------- system */
 /* Assemble the Picard-step system eq. 3.14: operator L(w~) with
@@ -309,8 +315,13 @@ int sgtt_solve_batched(sgtt_system* const* systems, int n, const sgtt_tt_pair* c
 typedef struct {
   int max_steps;          /* Picard steps after the Stokes solve (Alg. 3.1, maxit) */
   double tol_picard;      /* stop when ||r^(i)|| <= tol_picard ||f|| (Alg. 3.1)    */
-  double eps_soln;        /* truncation of the updated iterates (eq. 4.8)          */
+  double eps_soln;        /* truncation of the updated iterates (eq. 4.8); 0 keeps  */
+                          /* u^(i-1) + du as the exact sum (ranks add)            */
   sgtt_solve_opts solve;  /* options of every linear solve                        */
+  int update_mode;        /* 0: u^(i) = T_eps_soln(u^(i-1) + du) (eq. 4.8);        */
+                          /* 1: u^(i) = u^(i-1) + T_eps_soln(du), the update       */
+                          /* truncated relative to its own norm and the sum kept   */
+                          /* exact (ranks add; see sgtt_picard)                    */
 } sgtt_picard_opts;
 
 typedef struct {
@@ -324,6 +335,11 @@ typedef struct {
   int rank_u[SGTT_PICARD_MAX_STEPS + 1][2];             /* iterate ranks after    */
   int rank_p[SGTT_PICARD_MAX_STEPS + 1][2];             /* solve i and eq. 4.8    */
   double seconds;
+  /* ranks of the iterate as stored: equal to rank_u / rank_p with
+   * update_mode 0; with update_mode 1 the exact sum's ranks, while rank_u /
+   * rank_p give the ranks of that sum rounded at eps_soln */
+  int stored_rank_u[SGTT_PICARD_MAX_STEPS + 1][2];
+  int stored_rank_p[SGTT_PICARD_MAX_STEPS + 1][2];
 } sgtt_picard_stats;
 
 /* Picard's method (Alg. 3.1) with the low-rank variant of sec. 4.3: the
@@ -332,7 +348,12 @@ typedef struct {
  * residual r^(i-1) = f - L(u^(i-1)) [u^(i-1); p^(i-1)] of the untruncated
  * iterate (truncated at desc->eps_rhs for the right-hand side), solves for
  * (du, dp) with opts->solve, and sets u^(i) = T_eps_soln(u^(i-1) + du),
- * p^(i) likewise (eq. 4.8).  Stops when ||r^(i)|| <= tol_picard ||f|| or
+ * p^(i) likewise (eq. 4.8).  The rounding is Gram-based, so its result is
+ * accurate to about sqrt(machine epsilon) ||u|| whatever eps_soln asks; the
+ * residual of such an error stalls the nonlinear residual near 1e-5 ||f||
+ * on the step-domain problems.  update_mode 1 truncates the update alone
+ * (error eps_soln ||du||) and keeps the sum exact, so the iterate's ranks
+ * grow by the update's at every step.  Stops when ||r^(i)|| <= tol_picard ||f|| or
  * after max_steps (<= SGTT_PICARD_MAX_STEPS) steps; the residual of the
  * returned iterate is always evaluated (nonlinear_residual[steps]).  x:
  * caller buffers for the last iterate (capacity checked).  Returns
@@ -420,6 +441,16 @@ int sgtt_profile_enable(sgtt_context* ctx, int enable);
  * class_mask (bit c = class id c; 0 turns profiling off), so that a timed
  * run pays the event records of the classes it reports only. */
 int sgtt_profile_enable_classes(sgtt_context* ctx, unsigned class_mask);
+/* Sampling of the event scopes: of the scopes of each class opened since
+ * this call (or since profiling was last enabled), the 1st, (period+1)th,
+ * (2 period+1)th ... are recorded; the others run without events.  A scope
+ * brackets one launch, or one spatial solve's passes for the block cyclic
+ * reduction.  period 1 (the default) records every scope; period < 1 is
+ * SGTT_E_INVALID.  The sums of sgtt_profile_read then cover the sampled
+ * scopes only, so their ratios (bytes or flops per second, seconds per
+ * launch) stay averages over the run while the event records cost 1/period
+ * of what they cost unsampled.  Synchronizes the context stream. */
+int sgtt_profile_sample(sgtt_context* ctx, int period);
 /* Sums since enabling, per kernel class (index = class id, see
  * sgtt_profile_class_name): event seconds, algorithmic bytes and flops (what
  * each launch's operation must read/write and compute, from its arguments),

@@ -39,6 +39,7 @@ struct GemmTagScope {
 void prof_enable(bool on);
 void prof_enable_mask(unsigned class_mask);   // bit c records class c; 0 = off
 unsigned prof_mask();                          // classes recorded now (0 when off)
+void prof_sample_period(int period);          // record one scope in every `period` per class
 bool prof_enabled();
 // sums since the last reset: seconds (from events), bytes, flops, launches
 void prof_read(double* seconds, double* bytes, double* flops, long* launches);
@@ -142,11 +143,11 @@ void spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* rowp
 // (c*ics + col)*ldx + xcol0, of y at (c*ocs + r)*ldy + ycol0.
 // y = alpha * A x + beta * y.
 constexpr int ELL_WIDTH = 32;
-void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const double* eval,
+void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const double* eval, long nnz,
               const double* x, int ldx, int xcol0, int ncols, double* y, int ldy, int ycol0, double alpha,
               double beta);
 // the same product in FP32 (values, input and output)
-void ell_spmm32(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const float* eval,
+void ell_spmm32(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const float* eval, long nnz,
                 const float* x, int ldx, int xcol0, int ncols, float* y, int ldy, int ycol0, float alpha, float beta);
 // C (float, m x n) = A B computed in FP64 on the matrix cores and rounded
 // to FP32 on the store (strides as for gemm, batch 1)

@@ -32,6 +32,8 @@ struct ProfRec {
 struct Profiler {
   bool on = false;
   unsigned mask = ~0u;   // kernel classes recorded while on
+  int period = 1;        // one scope in every `period` of a class is recorded
+  long seen[KC_COUNT] = {};
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
@@ -61,6 +63,7 @@ struct ProfScope {
       : cls(c), s(st), bytes(by), flops(fl), launches(nl) {
     if (!g_prof.on || !((g_prof.mask >> c) & 1u)) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (g_prof.seen[c]++ % g_prof.period != 0) return;
     a = g_prof.ev();
     (void)hipEventRecord(a, s);
   }
@@ -121,6 +124,12 @@ void prof_enable_mask(unsigned mask) {
   }
   g_prof.mask = mask;
   g_prof.on = on;
+  for (long& n : g_prof.seen) n = 0;
+}
+void prof_sample_period(int period) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.period = period < 1 ? 1 : period;
+  for (long& n : g_prof.seen) n = 0;
 }
 
 namespace {
@@ -2295,24 +2304,26 @@ void transpose_widen(hipStream_t s, int rows, int cols, const float* src, long l
                      0, s, rows, cols, src, lds, 0L, dst, ldd, 0L);
 }
 
-void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const double* eval,
+void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const double* eval, long nnz,
               const double* x, int ldx, int xcol0, int ncols, double* y, int ldy, int ycol0, double alpha,
               double beta) {
   if (nrows <= 0 || ncols <= 0 || ncomp <= 0) return;
-  const double by = 12.0 * ELL_WIDTH * nrows + 8.0 * ncomp * ((double)nrows * ncols) +
+  // algorithmic: the matrix's nonzeros (column index and value) once, the
+  // inputs once, the outputs written (and read when accumulated)
+  const double by = 12.0 * nnz + 8.0 * ncomp * ((double)nrows * ncols) +
                     8.0 * ncomp * (double)nrows * ncols * (beta != 0.0 ? 2.0 : 1.0);
-  ProfScope ps(KC_ELL, s, by, 2.0 * ELL_WIDTH * (double)nrows * ncomp * ncols);
+  ProfScope ps(KC_ELL, s, by, 2.0 * (double)nnz * ncomp * ncols);
   const unsigned nb = 8 * cdiv(cdiv(nrows, 4), 8);
   hipLaunchKernelGGL((k_ell_spmm<ELL_WIDTH, double>), dim3(nb, ncomp), dim3(256), 0, s, nrows, ics, ocs, ecol, eval, x,
                      ldx, xcol0, ncols, y, ldy, ycol0, alpha, beta);
 }
 
-void ell_spmm32(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const float* eval,
+void ell_spmm32(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const float* eval, long nnz,
                 const float* x, int ldx, int xcol0, int ncols, float* y, int ldy, int ycol0, float alpha, float beta) {
   if (nrows <= 0 || ncols <= 0 || ncomp <= 0) return;
-  const double by = 8.0 * ELL_WIDTH * nrows + 4.0 * ncomp * ((double)nrows * ncols) +
+  const double by = 8.0 * nnz + 4.0 * ncomp * ((double)nrows * ncols) +
                     4.0 * ncomp * (double)nrows * ncols * (beta != 0.0f ? 2.0 : 1.0);
-  ProfScope ps(KC_ELL, s, by, 2.0 * ELL_WIDTH * (double)nrows * ncomp * ncols);
+  ProfScope ps(KC_ELL, s, by, 2.0 * (double)nnz * ncomp * ncols);
   const unsigned nb = 8 * cdiv(cdiv(nrows, 4), 8);
   hipLaunchKernelGGL((k_ell_spmm<ELL_WIDTH, float>), dim3(nb, ncomp), dim3(256), 0, s, nrows, ics, ocs, ecol, eval, x,
                      ldx, xcol0, ncols, y, ldy, ycol0, alpha, beta);

@@ -201,6 +201,7 @@ struct sgtt_system {
   BcrDev Fbt, Xbt;         // F_avg and X = B M*^-1 B^T (block cyclic reduction)
   int* Me_col = nullptr;   // M in padded-row form (time coupling of the mean solve)
   double* Me_val = nullptr;
+  long Me_nnz = 0;         // nonzeros of M (its padded rows hold 32)
   float* Me_val32 = nullptr;   // the same values in FP32 (reduced-precision mean solve)
   TT bu, bp;               // right-hand side
   double* Dinv = nullptr;  // 1 / diag(F_avg) on free scalar nodes
@@ -648,7 +649,7 @@ TT exact_mean_solve32(sgtt_system& S, const TT& y, double eps) {
   for (int t = 0; t < nt; ++t) {
     float* Wt = W + (long)t * nxi;
     if (t > 0)   // y_t + tau^-1 M v_{t-1}
-      ell_spmm32(c.s, S.ns, 2, S.ns, S.ns, S.Me_col, S.Me_val32, Vn + (long)(t - 1) * nxi, (int)ldw, 0, nxi, Wt,
+      ell_spmm32(c.s, S.ns, 2, S.ns, S.ns, S.Me_col, S.Me_val32, S.Me_nnz, Vn + (long)(t - 1) * nxi, (int)ldw, 0, nxi, Wt,
                  (int)ldw, 0, (float)(1.0 / S.tau), 1.0f);
     bcr_solve32(c.s, S.Fbt, 2, Wt, ldw, Vn + (long)t * nxi, ldw, nxi);
   }
@@ -675,7 +676,7 @@ TT exact_mean_solve(sgtt_system& S, const TT& y, double eps) {
   for (int t = 0; t < nt; ++t) {
     double* Wt = W + (long)t * nxi;
     if (t > 0)   // y_t + tau^-1 M v_{t-1}
-      ell_spmm(c.s, S.ns, 2, S.ns, S.ns, S.Me_col, S.Me_val, Vn + (long)(t - 1) * nxi, (int)ldw, 0, nxi, Wt,
+      ell_spmm(c.s, S.ns, 2, S.ns, S.ns, S.Me_col, S.Me_val, S.Me_nnz, Vn + (long)(t - 1) * nxi, (int)ldw, 0, nxi, Wt,
                (int)ldw, 0, 1.0 / S.tau, 1.0);
     bcr_solve(c.s, S.Fbt, 2, Wt, ldw, Vn + (long)t * nxi, ldw, nxi);
   }
@@ -1016,6 +1017,15 @@ extern "C" {
 
 const char* sgtt_version(void) { return "sgtt 0.1 gfx950 fp64"; }
 
+int sgtt_abi_sizes(long* sizes, int n) {
+  const long all[] = {(long)sizeof(sgtt_tt),          (long)sizeof(sgtt_tt_pair),     (long)sizeof(sgtt_problem_desc),
+                      (long)sizeof(sgtt_system_info), (long)sizeof(sgtt_solve_opts),  (long)sizeof(sgtt_solve_stats),
+                      (long)sizeof(sgtt_memory_info), (long)sizeof(sgtt_picard_opts), (long)sizeof(sgtt_picard_stats)};
+  const int total = (int)(sizeof(all) / sizeof(all[0]));
+  for (int i = 0; sizes && i < n && i < total; ++i) sizes[i] = all[i];
+  return total;
+}
+
 static thread_local std::string g_create_err;
 
 int sgtt_context_create(int device, void* stream, sgtt_context** out) {
@@ -1128,6 +1138,7 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
       }
     }
     S->Me_col = dev_upload(c, ec);
+    S->Me_nnz = K.rowptr[K.nrows];
     S->Me_val32 = dev_upload(c, std::vector<float>(ev.begin(), ev.end()));
     S->Me_val = dev_upload(c, ev);
   }
@@ -1688,6 +1699,7 @@ int sgtt_picard(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_pic
                 sgtt_picard_stats* stats) {
   if (!ctx || !desc || !opts || !x) return SGTT_E_INVALID;
   if (opts->max_steps < 0 || opts->max_steps > SGTT_PICARD_MAX_STEPS) return SGTT_E_INVALID;
+  if (opts->update_mode != 0 && opts->update_mode != 1) return SGTT_E_INVALID;
   int status = SGTT_OK;
   try {
     Ctx& c = ctx->c;
@@ -1704,10 +1716,23 @@ int sgtt_picard(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_pic
       st.outer_iters[i] = ls.outer_iters;
       st.inner_iters[i] = ls.inner_iters;
       st.solve_seconds[i] = ls.seconds;
-      st.rank_u[i][0] = it.c[0].r1;
-      st.rank_u[i][1] = it.c[0].r2;
-      st.rank_p[i][0] = it.c[1].r1;
-      st.rank_p[i][1] = it.c[1].r2;
+      st.stored_rank_u[i][0] = it.c[0].r1;
+      st.stored_rank_u[i][1] = it.c[0].r2;
+      st.stored_rank_p[i][0] = it.c[1].r1;
+      st.stored_rank_p[i][1] = it.c[1].r2;
+      if (opts->update_mode == 1 && opts->eps_soln > 0 && i > 0) {
+        // the ranks eq. 4.8 would give: the stored sum rounded at eps_soln
+        Vec r = vec_round(c, it, opts->eps_soln, nullptr, nullptr);
+        st.rank_u[i][0] = r.c[0].r1;
+        st.rank_u[i][1] = r.c[0].r2;
+        st.rank_p[i][0] = r.c[1].r1;
+        st.rank_p[i][1] = r.c[1].r2;
+      } else {
+        st.rank_u[i][0] = it.c[0].r1;
+        st.rank_u[i][1] = it.c[0].r2;
+        st.rank_p[i][0] = it.c[1].r1;
+        st.rank_p[i][1] = it.c[1].r2;
+      }
     };
     Vec cur;
     {
@@ -1717,7 +1742,7 @@ int sgtt_picard(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_pic
       Vec z;
       sgtt_solve_stats ls{};
       if (solve_internal(S.get(), b, opts->solve, z, &ls) != SGTT_OK) status = SGTT_W_NOT_CONVERGED;
-      cur = vec_round(c, z, opts->eps_soln, nullptr, nullptr);
+      cur = opts->eps_soln > 0 ? vec_round(c, z, opts->eps_soln, nullptr, nullptr) : std::move(z);
       record(0, ls, cur);
     }
     S.reset();
@@ -1753,8 +1778,17 @@ int sgtt_picard(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_pic
       Vec d;
       sgtt_solve_stats ls{};
       if (solve_internal(S.get(), b, opts->solve, d, &ls) != SGTT_OK) status = SGTT_W_NOT_CONVERGED;
-      Vec next = vec_concat(c, {&cur, &d}, nullptr, {});
-      cur = vec_round(c, next, opts->eps_soln, nullptr, nullptr);
+      if (opts->update_mode == 1) {
+        // u^(i) = u^(i-1) + T(du): the update is truncated relative to its
+        // own norm and the sum is kept exact, so the iterate carries no
+        // rounding error of the size of the Gram-based rounding's floor
+        // (about sqrt(machine epsilon) of ||u||)
+        Vec dr = opts->eps_soln > 0 ? vec_round(c, d, opts->eps_soln, nullptr, nullptr) : std::move(d);
+        cur = vec_concat(c, {&cur, &dr}, nullptr, {});
+      } else {
+        Vec next = vec_concat(c, {&cur, &d}, nullptr, {});
+        cur = opts->eps_soln > 0 ? vec_round(c, next, opts->eps_soln, nullptr, nullptr) : std::move(next);
+      }
       record(i, ls, cur);
     }
     S.reset();
@@ -1881,6 +1915,13 @@ int sgtt_profile_enable_classes(sgtt_context* ctx, unsigned class_mask) {
   (void)hipStreamSynchronize(ctx->c.s);
   prof_reset();
   prof_enable_mask(class_mask);
+  return SGTT_OK;
+}
+
+int sgtt_profile_sample(sgtt_context* ctx, int period) {
+  if (!ctx || period < 1) return SGTT_E_INVALID;
+  (void)hipStreamSynchronize(ctx->c.s);
+  prof_sample_period(period);
   return SGTT_OK;
 }
 

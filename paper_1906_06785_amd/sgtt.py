@@ -65,7 +65,7 @@ PICARD_MAX_STEPS = 16
 
 class PicardOpts(C.Structure):
     _fields_ = [("max_steps", C.c_int), ("tol_picard", C.c_double), ("eps_soln", C.c_double),
-                ("solve", SolveOpts)]
+                ("solve", SolveOpts), ("update_mode", C.c_int)]
 
 
 class PicardStats(C.Structure):
@@ -73,7 +73,8 @@ class PicardStats(C.Structure):
     _fields_ = [("steps", C.c_int), ("nonlinear_residual", C.c_double * _n), ("linear_residual", C.c_double * _n),
                 ("outer_iters", C.c_int * _n), ("inner_iters", C.c_int * _n), ("solve_seconds", C.c_double * _n),
                 ("assemble_seconds", C.c_double * (_n + 1)), ("rank_u", (C.c_int * 2) * _n),
-                ("rank_p", (C.c_int * 2) * _n), ("seconds", C.c_double)]
+                ("rank_p", (C.c_int * 2) * _n), ("seconds", C.c_double),
+                ("stored_rank_u", (C.c_int * 2) * _n), ("stored_rank_p", (C.c_int * 2) * _n)]
 
     def as_dict(self):
         n = self.steps + 1
@@ -82,6 +83,8 @@ class PicardStats(C.Structure):
                 "inner_iters": list(self.inner_iters[:n]), "solve_seconds": list(self.solve_seconds[:n]),
                 "assemble_seconds": list(self.assemble_seconds[:n + 1]),
                 "rank_u": [tuple(r) for r in self.rank_u[:n]], "rank_p": [tuple(r) for r in self.rank_p[:n]],
+                "stored_rank_u": [tuple(r) for r in self.stored_rank_u[:n]],
+                "stored_rank_p": [tuple(r) for r in self.stored_rank_p[:n]],
                 "seconds": self.seconds}
 
 
@@ -127,6 +130,8 @@ _sig = {
                                       C.POINTER(C.c_double)]),
     "sgtt_profile_enable": (C.c_int, [_P, C.c_int]),
     "sgtt_profile_enable_classes": (C.c_int, [_P, C.c_uint]),
+    "sgtt_profile_sample": (C.c_int, [_P, C.c_int]),
+    "sgtt_abi_sizes": (C.c_int, [C.POINTER(C.c_long), C.c_int]),
     "sgtt_profile_read": (C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), C.POINTER(C.c_long), C.POINTER(C.c_int)]),
     "sgtt_profile_class_name": (C.c_char_p, [C.c_int]),
@@ -409,6 +414,10 @@ class Context:
             mask |= 1 << names.index(cname)
         self.check(_lib.sgtt_profile_enable_classes(self._c, mask if enable else 0))
 
+    def profile_sample(self, period: int):
+        """Record one event scope in every `period` of each kernel class."""
+        self.check(_lib.sgtt_profile_sample(self._c, int(period)))
+
     def profile_read(self):
         n = 16
         sec = (C.c_double * n)()
@@ -675,10 +684,12 @@ def solve_batched(systems, bs, xs, **opts):
 
 
 def picard(ctx: Context, cfg: dict, steps: int = 5, tol_picard: float = 1e-5, eps_soln: float = 1e-10,
-           eps_conv: float = 1e-3, eps_rhs: float = 1e-6, out: PairBuf | None = None, caps=(128, 2048), **solve_opts):
-    """Picard's method (Alg. 3.1, eq. 4.8) on the device: returns (iterate, stats dict, status)."""
+           eps_conv: float = 1e-3, eps_rhs: float = 1e-6, out: PairBuf | None = None, caps=(128, 2048),
+           update_mode: int = 0, **solve_opts):
+    """Picard's method (Alg. 3.1, eq. 4.8) on the device: returns (iterate, stats dict, status).
+    update_mode 0 truncates the updated iterate, 1 the update alone (the sum kept exact)."""
     d = make_desc(cfg, eps_conv, eps_rhs)
-    o = PicardOpts(int(steps), float(tol_picard), float(eps_soln), make_opts(**solve_opts))
+    o = PicardOpts(int(steps), float(tol_picard), float(eps_soln), make_opts(**solve_opts), int(update_mode))
     if out is None:
         hp = HostProblem(cfg)
         out = PairBuf(hp.nt, hp.n_xi, hp.n_u, hp.n_p, caps[0], caps[1], device=f"cuda:{ctx.device}")
@@ -687,6 +698,19 @@ def picard(ctx: Context, cfg: dict, steps: int = 5, tol_picard: float = 1e-5, ep
     rc = ctx.check(_lib.sgtt_picard(ctx._c, C.byref(d), C.byref(o), C.byref(so), C.byref(st)))
     out.update(so)
     return out, st.as_dict(), rc
+
+
+ABI_STRUCTS = ("SgttTT", "SgttPair", "ProblemDesc", "SystemInfo", "SolveOpts", "SolveStats", "MemoryInfo",
+               "PicardOpts", "PicardStats")
+
+
+def abi_sizes() -> dict:
+    """sizeof of each public struct as the library was compiled, keyed by
+    the name of its ctypes mirror here."""
+    n = len(ABI_STRUCTS)
+    buf = (C.c_long * n)()
+    _lib.sgtt_abi_sizes(buf, n)
+    return dict(zip(ABI_STRUCTS, list(buf)))
 
 
 def version() -> str:

@@ -268,8 +268,8 @@ def test_pcd_preconditioner_matches_oracle(sg, ctx, tiny, c1, which):
     perr = np.linalg.norm(gp - wp) / np.linalg.norm(wp)
     err = np.linalg.norm(tt.pair_full(out.cores()) - tt.pair_full(ref)) / np.linalg.norm(tt.pair_full(ref))
     _flush(f"pressure block difference {perr:.2e}, pair difference {err:.2e}")
-    assert perr <= 1e-7
-    assert err <= 1e-6
+    assert perr <= 1e-10
+    assert err <= 1e-7
 
 
 def test_preconditioner_exact_inner_matches_oracle(sg, ctx, c1):

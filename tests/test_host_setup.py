@@ -32,6 +32,17 @@ def test_library_exports_every_declared_symbol():
     assert set(sg.EXPORTED) == declared
 
 
+def test_binding_structs_match_the_compiled_layout():
+    # every ctypes mirror of a public struct has the size the library was
+    # compiled with (a field added on one side only shows here)
+    import ctypes
+    sg = _lib()
+    sizes = sg.abi_sizes()
+    assert set(sizes) == set(sg.ABI_STRUCTS)
+    for name, n in sizes.items():
+        assert ctypes.sizeof(getattr(sg, name)) == n, name
+
+
 def _rel(a, b):
     a = sp.csr_matrix(a)
     b = sp.csr_matrix(b)
