@@ -122,6 +122,19 @@ void transpose_copy(hipStream_t s, int rows, int cols, const double* src, long l
 // the same transpose from FP32 to FP64
 void transpose_widen(hipStream_t s, int rows, int cols, const float* src, long lds, double* dst, long ldd);
 // batch transposes: source b at src + b*sbatch, destination at dst + b*dbatch
+// Many independent 2-D block copies in one launch: block z copies a
+// rows x cols row-major block, dst[i][j] = a src[i][j] (transpose 0) or
+// dst[j][i] = a src[i][j] (transpose 1), with a = alpha, times *dalpha when
+// dalpha is set.  The descriptors live in device memory (n of them).
+struct BlockCopy {
+  const double* src;
+  double* dst;
+  const double* dalpha;
+  long lds, ldd;
+  int rows, cols, transpose, pad_;
+  double alpha;
+};
+void block_copy_batched(hipStream_t s, const BlockCopy* d_descs, int n, int max_rows, int max_cols);
 void transpose_copy_batched(hipStream_t s, int batch, int rows, int cols, const double* src, long sbatch, long lds,
                             double* dst, long dbatch, long ldd);
 

@@ -421,6 +421,37 @@ __global__ void k_copy2d(int rows, int cols, const double* __restrict__ src, lon
   }
 }
 
+// Batched block copies (BlockCopy): grid (column tiles, row tiles, block),
+// 32 x 32 tiles through LDS so that a transposed block is read and written
+// along its rows; tiles past a block's extent leave at once.
+__global__ __launch_bounds__(256) void k_block_copy(const BlockCopy* __restrict__ descs) {
+  __shared__ double tile[32][33];
+  const BlockCopy d = descs[blockIdx.z];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  if (i0 >= d.rows || j0 >= d.cols) return;   // uniform per workgroup
+  const double a = d.dalpha ? d.alpha * (*d.dalpha) : d.alpha;
+  if (!d.transpose) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + ty + 8 * q, j = j0 + tx;
+      if (i < d.rows && j < d.cols) d.dst[(long)i * d.ldd + j] = a * d.src[(long)i * d.lds + j];
+    }
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = i0 + ty + 8 * q, j = j0 + tx;
+    if (i < d.rows && j < d.cols) tile[ty + 8 * q][tx] = d.src[(long)i * d.lds + j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = j0 + ty + 8 * q, i = i0 + tx;
+    if (i < d.rows && j < d.cols) d.dst[(long)j * d.ldd + i] = a * tile[tx][ty + 8 * q];
+  }
+}
+
 // dst[j][i] = src[i][j] through a 32 x 32 LDS tile: both the reads (along j)
 // and the writes (along i) are coalesced.  blockDim (32, 8); tiles walk the
 // rows with a grid stride so any row count fits the grid.
@@ -2290,6 +2321,13 @@ void transpose_copy_batched(hipStream_t s, int batch, int rows, int cols, const 
   const unsigned gy = (unsigned)std::min<long>(cdiv(rows, 32), std::max<long>(1, 65536 / ((long)gx * batch)));
   hipLaunchKernelGGL((k_transpose_copy<double, double>), dim3(gx, std::max(1u, std::min(gy, 65535u)), batch), dim3(32, 8), 0, s, rows,
                      cols, src, lds, sbatch, dst, ldd, dbatch);
+}
+
+void block_copy_batched(hipStream_t s, const BlockCopy* d_descs, int n, int max_rows, int max_cols) {
+  if (n <= 0 || max_rows <= 0 || max_cols <= 0) return;
+  if (n > 65535 || cdiv(max_rows, 32) > 65535) throw std::runtime_error("block_copy_batched: grid too large");
+  hipLaunchKernelGGL(k_block_copy, dim3((unsigned)cdiv(max_cols, 32), (unsigned)cdiv(max_rows, 32), n), dim3(32, 8), 0,
+                     s, d_descs);
 }
 
 void transpose_copy(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst, long ldd) {

@@ -198,6 +198,22 @@ TT tt_copy(Ctx& c, const TT& x) {
   return t;
 }
 
+// Block-copy descriptors to device memory (pool) and one launch for all of
+// them; the pool returns the descriptor memory in stream order.
+static void run_block_copies(Ctx& c, const std::vector<BlockCopy>& d) {
+  if (d.empty()) return;
+  int mr = 0, mc = 0;
+  for (const auto& b : d) {
+    mr = std::max(mr, b.rows);
+    mc = std::max(mc, b.cols);
+  }
+  size_t nd = (d.size() * sizeof(BlockCopy) + sizeof(double) - 1) / sizeof(double);
+  double* buf = c.pool.get(nd);
+  SGTT_HIP(hipMemcpyAsync(buf, d.data(), d.size() * sizeof(BlockCopy), hipMemcpyHostToDevice, c.s));
+  block_copy_batched(c.s, (const BlockCopy*)buf, (int)d.size(), mr, mc);
+  c.pool.put(buf);
+}
+
 TT tt_concat(Ctx& c, const std::vector<const TT*>& xs, const double* dcoef, const std::vector<double>& hcoef) {
   const TT& x0 = *xs[0];
   int R1 = 0, R2 = 0;
@@ -205,15 +221,17 @@ TT tt_concat(Ctx& c, const std::vector<const TT*>& xs, const double* dcoef, cons
   TT t = tt_new(c, x0.n1, x0.n2, x0.n3, R1, R2);
   fill(c.s, t.c2, t.n_c2(), 0.0);
   int o1 = 0, o2 = 0;
+  std::vector<BlockCopy> place;
   for (size_t i = 0; i < xs.size(); ++i) {
     const TT& x = *xs[i];
     double hc = hcoef.empty() ? 1.0 : hcoef[i];
-    copy2d(c.s, x.n1, x.r1, x.c1, x.r1, t.c1 + o1, R1, hc, dcoef ? dcoef + i : nullptr, 0);
+    place.push_back(BlockCopy{x.c1, t.c1 + o1, dcoef ? dcoef + i : nullptr, x.r1, R1, x.n1, x.r1, 0, 0, hc});
     core2_block(c.s, x.r1, x.n2, x.r2, x.c2, nullptr, 1, 1, t.c2, R1, R2, o1, o2);
-    copy2d(c.s, x.n3, x.r2, x.c3, x.r2, t.c3 + o2, R2, 1.0, nullptr, 0);
+    place.push_back(BlockCopy{x.c3, t.c3 + o2, nullptr, x.r2, R2, x.n3, x.r2, 0, 0, 1.0});
     o1 += x.r1;
     o2 += x.r2;
   }
+  run_block_copies(c, place);
   return t;
 }
 
@@ -392,27 +410,43 @@ TT tt_round_sum(Ctx& c, const std::vector<Term>& terms, double eps, double* d_no
   // Gram-forming products (K3, K2, S1, S2) run in FP64 whatever the ambient
   // precision; the projections (D, C, W, new core 3) use the ambient one.
   const int amb = gemm_precision(GP_F64);
-  // ---- K3 = G3^T G3 (R2 x R2) assembled from blocks (cached or computed)
+  // ---- K3 = G3^T G3 (R2 x R2) assembled from blocks (cached or computed),
+  // and G1 = [c_i A_i] (n1 x R1): every block placed by one batched copy
   double* K3 = c.pool.get((size_t)R2 * R2);
-  int maxb = 0;
-  for (int i = 0; i < k; ++i) maxb = std::max(maxb, b[i]);
-  double* blk = c.pool.get((size_t)maxb * maxb);
-  for (int i = 0; i < k; ++i)
-    for (int j = i; j < k; ++j) {
-      const double* src = cache ? (*cache)[(size_t)i * k + j] : nullptr;
-      if (!src) {
-        size_t wsn = gram_ws_doubles(n3, b[i], b[j]);
-        gram(c.s, n3, b[i], b[j], terms[i].t->c3, b[i], 1, terms[j].t->c3, b[j], 1, blk, c.scratch(wsn), wsn);
-        src = blk;
-      }
-      copy2d(c.s, b[i], b[j], src, b[j], K3 + (size_t)ob[i] * R2 + ob[j], R2, 1.0, nullptr, 0);
-      if (j != i) transpose_copy(c.s, b[i], b[j], src, b[j], K3 + (size_t)ob[j] * R2 + ob[i], R2);
-    }
-  c.pool.put(blk);
-  // ---- G1 = [c_i A_i] (n1 x R1)
   double* G1 = c.pool.get((size_t)n1 * R1);
+  std::vector<BlockCopy> place;
+  double* gbuf = nullptr;
+  if (k == 1 && !(cache && (*cache)[0])) {
+    size_t wsn = gram_ws_doubles(n3, b[0], b[0]);
+    gram(c.s, n3, b[0], b[0], terms[0].t->c3, b[0], 1, terms[0].t->c3, b[0], 1, K3, c.scratch(wsn), wsn);
+  } else {
+    size_t need = 0;
+    for (int i = 0; i < k; ++i)
+      for (int j = i; j < k; ++j)
+        if (!(cache && (*cache)[(size_t)i * k + j])) need += (size_t)b[i] * b[j];
+    gbuf = need ? c.pool.get(need) : nullptr;
+    size_t off = 0;
+    for (int i = 0; i < k; ++i)
+      for (int j = i; j < k; ++j) {
+        const double* src = cache ? (*cache)[(size_t)i * k + j] : nullptr;
+        if (!src) {
+          double* g = gbuf + off;
+          off += (size_t)b[i] * b[j];
+          size_t wsn = gram_ws_doubles(n3, b[i], b[j]);
+          gram(c.s, n3, b[i], b[j], terms[i].t->c3, b[i], 1, terms[j].t->c3, b[j], 1, g, c.scratch(wsn), wsn);
+          src = g;
+        }
+        place.push_back(BlockCopy{src, K3 + (size_t)ob[i] * R2 + ob[j], nullptr, b[j], R2, b[i], b[j], 0, 0, 1.0});
+        if (j != i)
+          place.push_back(
+              BlockCopy{src, K3 + (size_t)ob[j] * R2 + ob[i], nullptr, b[j], R2, b[i], b[j], 1, 0, 1.0});
+      }
+  }
   for (int i = 0; i < k; ++i)
-    copy2d(c.s, n1, a[i], terms[i].t->c1, a[i], G1 + oa[i], R1, terms[i].hcoef, terms[i].dcoef, 0);
+    place.push_back(BlockCopy{terms[i].t->c1, G1 + oa[i], terms[i].dcoef, a[i], R1, n1, a[i], 0, 0,
+                              terms[i].hcoef});
+  run_block_copies(c, place);
+  if (gbuf) c.pool.put(gbuf);
   // ---- K2 (R1 x R1): K2_ij = sum_l B_i,l K3_ij B_j,l^T via T_ij = B_i K3_ij
   double* K2 = c.pool.get((size_t)R1 * R1);
   {
