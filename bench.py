@@ -57,6 +57,8 @@ def parse(argv=None):
                     help="N > 0: instead, time N independent problems (batch_configs) on --contexts streams")
     ap.add_argument("--contexts", type=int, default=8)
     ap.add_argument("--batch-small", action="store_true", help="coarse grids / short horizons for the batch")
+    ap.add_argument("--jsonl", default="",
+                    help="append one JSON line per timed solve (stats, residual and rank history) to this file")
     ap.add_argument("--event-sample", type=int, default=8,
                     help="in the timed region, bracket one scope of the dominant kernel class in every N with "
                          "HIP events (a scope is one launch, or one spatial solve's passes)")
@@ -400,14 +402,21 @@ def build_system(sgtt, ctx, cfg, system, opts, progress):
     return S1, b1, info
 
 
-def time_solves(S, b, out, opts, steps, progress, stream):
+def time_solves(S, b, out, opts, steps, progress, stream, jsonl=None, label=""):
+    """Times `steps` solves; with jsonl (an open file) each solve appends one
+    JSON line: its stats and its per-iteration history (residuals and ranks
+    of every outer iteration and refinement cycle; a host-side copy, no
+    device work)."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
-    for _ in range(steps):
+    for i in range(steps):
         _, st, rc = S.solve(b, out, **opts)
         stats.append(st)
+        if jsonl is not None:
+            jsonl.write(json.dumps({"solve": i, "label": label, "status": rc, "stats": st,
+                                    "history": S.history()}) + "\n")
         progress("timed solve")
     torch.cuda.synchronize()
     return time.perf_counter() - t0, stats
@@ -498,7 +507,8 @@ def main():
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
-    elapsed, stats = time_solves(S, b, out, opts, args.steps, progress, stream)
+    jsonl = open(args.jsonl, "a") if args.jsonl else None
+    elapsed, stats = time_solves(S, b, out, opts, args.steps, progress, stream, jsonl, "plain")
     ev1.record(stream)
     torch.cuda.synchronize()
     prof = ctx.profile_read()
@@ -535,7 +545,7 @@ def main():
         vout = S.pair(*OUT_CAPS)
         S.solve(b, vout, **vopts)   # warm-up (tuning of the spatial solves for new column counts)
         progress(f"warm-up solve of {name}")
-        v_el, v_stats = time_solves(S, b, vout, vopts, args.steps, progress, stream)
+        v_el, v_stats = time_solves(S, b, vout, vopts, args.steps, progress, stream, jsonl, name)
         v_worst = max(s["rel_residual"] for s in v_stats)
         ctx.profile(True)   # one profiled solve of the variant for its breakdown
         _, vp_st, _ = S.solve(b, vout, **vopts)
@@ -592,6 +602,8 @@ def main():
                                                None if args.system == "stokes" else "picard1")
         except Exception as e:  # the baseline is informative only
             res["cpu_baseline"] = {"error": repr(e)}
+    if jsonl is not None:
+        jsonl.close()
     print(json.dumps(res), flush=True)
 
 

@@ -39,6 +39,8 @@ extern "C" {
                                      output left unchanged                         */
 #define SGTT_E_NONFINITE -5       /* NaN/Inf met in a reduction                    */
 #define SGTT_E_SETUP -6           /* problem setup failed (mesh / factorization)   */
+#define SGTT_E_IO -7              /* checkpoint file missing, unreadable, of another
+                                     format, or failing its hash                    */
 
 typedef struct sgtt_context sgtt_context;
 typedef struct sgtt_system sgtt_system;
@@ -197,8 +199,9 @@ const char* sgtt_last_error(const sgtt_context* ctx);
 const char* sgtt_version(void);
 /* sizeof of the public structs, in this order: sgtt_tt, sgtt_tt_pair,
  * sgtt_problem_desc, sgtt_system_info, sgtt_solve_opts, sgtt_solve_stats,
- * sgtt_memory_info, sgtt_picard_opts, sgtt_picard_stats; the first
- * min(n, 9) go to sizes.  Returns the number of structs (9).  For bindings
+ * sgtt_memory_info, sgtt_picard_opts, sgtt_picard_stats, sgtt_iter_record;
+ * the first min(n, 10) go to sizes.  Returns the number of structs (10).
+ * For bindings
  * that mirror the structs (host only, no device call). */
 int sgtt_abi_sizes(long* sizes, int n);
 
@@ -360,6 +363,54 @@ typedef struct {
  * SGTT_W_NOT_CONVERGED if a linear solve missed its tolerance. */
 int sgtt_picard(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_picard_opts* opts,
                 sgtt_tt_pair* x, sgtt_picard_stats* stats);
+
+/* ------------------------------------------------------------- solve history */
+/* One record per outer FGMRES iteration of the last sgtt_solve on a system
+ * (iter = 1, 2, ... within refinement cycle `cycle`), and one closing each
+ * refinement cycle (iter = -1).  For an iteration, rel is the relative
+ * residual of the cycle's correction system (the explicit one when
+ * outer_explicit is set, else the Hessenberg estimate of Alg. 4.2), rank_v
+ * the (r1, r2) of the newest Krylov vector of each component, rank_z those
+ * of the cycle's current solution (explicit residuals only, else 0).  For a
+ * cycle's end, rel is the exact ||b - L x|| / ||b|| of the accumulated
+ * solution and rank_z its ranks.  seconds: since the solve began. */
+typedef struct {
+  int cycle, iter;
+  double rel;
+  int rank_v_u[2], rank_v_p[2];
+  int rank_z_u[2], rank_z_p[2];
+  double seconds;
+} sgtt_iter_record;
+/* Copies the first min(max_records, n) records to out; *nrecords gets n. */
+int sgtt_solve_history(const sgtt_system* sys, int max_records, sgtt_iter_record* out, int* nrecords);
+
+/* ------------------------------------------------------------- checkpoints */
+/* The Picard iterate (Alg. 3.1) is the natural restart point of a nonlinear
+ * solve; it is small (eq. 6.6).  A checkpoint file holds one TT pair: a
+ * magic tag, a format version, the sizes and ranks (n1, n2, n3, r1, r2 of
+ * the velocity TT, then of the pressure TT), the six cores in the layout of
+ * sgtt_tt with the live ranks as leading dimensions, as little-endian
+ * float64, and a 64-bit FNV-1a hash of all of it.  Files are written to
+ * "<path>.tmp" and renamed, so a failed write leaves no torn file behind.
+ *
+ * sgtt_pair_save: copies x's live cores to the host (synchronizes the
+ * context stream) and writes them.  SGTT_E_IO if the file cannot be
+ * written.
+ * sgtt_pair_load: reads a file into x's buffers (sizes must match x's n1,
+ * n2, n3: SGTT_E_INVALID; ranks above x's capacities: SGTT_E_RANK_CAP;
+ * missing, damaged or foreign files: SGTT_E_IO) and sets x's ranks; x is
+ * unchanged unless the call returns SGTT_OK.  Synchronizes. */
+int sgtt_pair_save(sgtt_context* ctx, const sgtt_tt_pair* x, const char* path);
+int sgtt_pair_load(sgtt_context* ctx, const char* path, sgtt_tt_pair* x);
+/* Host-only forms (no device call): dims[10] = n1, n2, n3, r1, r2 of the
+ * velocity TT then of the pressure TT; cores[6] = core 1, 2, 3 of each,
+ * compact, in host memory.  sgtt_pair_file_info reads the dims of a file
+ * (header checked, the hash is not); sgtt_pair_file_read_host reads into
+ * host buffers whose sizes caps[10] = n1, n2, n3, cap1, cap2 per TT give,
+ * with the checks of sgtt_pair_load, and writes the file's dims. */
+int sgtt_pair_file_write_host(const char* path, const int* dims, const double* const* cores);
+int sgtt_pair_file_info(const char* path, int* dims);
+int sgtt_pair_file_read_host(const char* path, const int* caps, double* const* cores, int* dims);
 
 /* Exact ||b - L x|| / ||b|| evaluated in full format on the device
  * (synchronizes; result to host). */

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libsgtt.so")
 ARCH = os.environ.get("SGTT_ARCH", "gfx950")
 
 HIP_SOURCES = ["kernels.hip", "tt_core.hip", "learned.hip", "solver.hip"]
-CXX_SOURCES = ["host_setup.cpp"]
+CXX_SOURCES = ["host_setup.cpp", "checkpoint.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/sgtt.h"
+#include "checkpoint.h"
 #include "host_setup.h"
 #include "kernels.h"
 #include "learned.h"
@@ -207,6 +208,7 @@ struct sgtt_system {
   double* Dinv = nullptr;  // 1 / diag(F_avg) on free scalar nodes
   sgtt::Mlp* mlp_collect = nullptr;   // records (r, F_avg^-1 r) pairs from mean solves
   sgtt::Mlp* mlp_apply = nullptr;     // learned mean solve in M^-1 (eq. 5.23)
+  std::vector<sgtt_iter_record> hist;   // the last solve's outer iterations
   bool mlp_off = false;               // fallback taken in the current solve
   int mlp_fails = 0, mlp_calls = 0;
   double rhs_norm = 0;     // ||f|| (Stokes) or ||r|| of the untruncated nonlinear residual (Picard)
@@ -397,7 +399,17 @@ struct SolveCounters {
   int maxr_u = 0, maxr_p = 0;
   double t_apply = 0, t_round = 0, t_prec = 0;
   int verbose = 0;
+  std::vector<sgtt_iter_record>* hist = nullptr;   // outer iterations of the solve
+  int cycle = 0;
+  double t_start = 0;
 };
+
+void hist_ranks(const Vec& v, int* u, int* p) {
+  u[0] = v.c[0].r1;
+  u[1] = v.c[0].r2;
+  p[0] = v.nc > 1 ? v.c[1].r1 : 0;
+  p[1] = v.nc > 1 ? v.c[1].r2 : 0;
+}
 
 // Core-3 Gram blocks of a growing basis, per TT component: blk(c, i, j) for
 // i <= j holds basis_i.core3^T basis_j.core3 (device, pool-owned).
@@ -532,6 +544,15 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
     hessenberg_lsq(c.s, H, ld, k, sc + 5, y, sc + 8);
     if (!explicit_res) {
       res = read_double(c, sc + 8);
+      if (cnt && cnt->hist) {
+        sgtt_iter_record h{};
+        h.cycle = cnt->cycle;
+        h.iter = k;
+        h.rel = res / bnorm;
+        hist_ranks(V.back(), h.rank_v_u, h.rank_v_p);
+        h.seconds = now_s() - cnt->t_start;
+        cnt->hist->push_back(h);
+      }
       if (cnt && cnt->verbose > 1)
         fprintf(stderr, "[sgtt %s] it %d  est %.3e  ranks v=(%d,%d) x=(%d,%d) rhs=(%d,%d)\n", tag, k, res / bnorm,
                 V.back().c[0].r1, V.back().c[0].r2, x.c[0].r1, x.c[0].r2, V[0].c[0].r1, V[0].c[0].r2);
@@ -566,6 +587,16 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
         if (i == 0) cnt->maxr_u = std::max(cnt->maxr_u, r2);
         else cnt->maxr_p = std::max(cnt->maxr_p, r2);
       }
+    }
+    if (cnt && cnt->hist) {
+      sgtt_iter_record h{};
+      h.cycle = cnt->cycle;
+      h.iter = k;
+      h.rel = res / bnorm;
+      hist_ranks(V.back(), h.rank_v_u, h.rank_v_p);
+      hist_ranks(z, h.rank_z_u, h.rank_z_p);
+      h.seconds = now_s() - cnt->t_start;
+      cnt->hist->push_back(h);
     }
     if (cnt && cnt->verbose)
       fprintf(stderr, "[sgtt %s] it %d  rel %.3e  ranks v=(%d,%d) z=(%d,%d) Lz=(%d,%d)\n", tag, k, res / bnorm,
@@ -1020,7 +1051,8 @@ const char* sgtt_version(void) { return "sgtt 0.1 gfx950 fp64"; }
 int sgtt_abi_sizes(long* sizes, int n) {
   const long all[] = {(long)sizeof(sgtt_tt),          (long)sizeof(sgtt_tt_pair),     (long)sizeof(sgtt_problem_desc),
                       (long)sizeof(sgtt_system_info), (long)sizeof(sgtt_solve_opts),  (long)sizeof(sgtt_solve_stats),
-                      (long)sizeof(sgtt_memory_info), (long)sizeof(sgtt_picard_opts), (long)sizeof(sgtt_picard_stats)};
+                      (long)sizeof(sgtt_memory_info), (long)sizeof(sgtt_picard_opts), (long)sizeof(sgtt_picard_stats),
+                      (long)sizeof(sgtt_iter_record)};
   const int total = (int)(sizeof(all) / sizeof(all[0]));
   for (int i = 0; sizes && i < n && i < total; ++i) sizes[i] = all[i];
   return total;
@@ -1539,6 +1571,85 @@ int sgtt_hessenberg_lsq(sgtt_context* ctx, const double* H, int k, double beta, 
   });
 }
 
+int sgtt_solve_history(const sgtt_system* S, int max_records, sgtt_iter_record* out, int* nrecords) {
+  if (!S || !nrecords || max_records < 0 || (max_records > 0 && !out)) return SGTT_E_INVALID;
+  const int n = (int)S->hist.size();
+  *nrecords = n;
+  for (int i = 0; i < n && i < max_records; ++i) out[i] = S->hist[i];
+  return SGTT_OK;
+}
+
+int sgtt_pair_save(sgtt_context* ctx, const sgtt_tt_pair* x, const char* path) {
+  if (!ctx || !x || !path) return SGTT_E_INVALID;
+  int st = SGTT_OK;
+  const int g = guarded(ctx, [&]() {
+    const sgtt_tt* t[2] = {&x->u, &x->p};
+    int dims[10];
+    std::vector<double> host[6];
+    for (int q = 0; q < 2; ++q) {
+      const sgtt_tt& a = *t[q];
+      if (a.r1 < 1 || a.r2 < 1 || a.r1 > a.cap1 || a.r2 > a.cap2 || !a.core1 || !a.core2 || !a.core3)
+        throw SgttError(SGTT_E_INVALID, "checkpoint: invalid TT");
+      const int d[5] = {a.n1, a.n2, a.n3, a.r1, a.r2};
+      std::memcpy(dims + 5 * q, d, sizeof(d));
+      const double* src[3] = {a.core1, a.core2, a.core3};
+      const long len[3] = {(long)a.n1 * a.r1, (long)a.r1 * a.n2 * a.r2, (long)a.n3 * a.r2};
+      for (int w = 0; w < 3; ++w) {
+        host[3 * q + w].resize((size_t)len[w]);
+        SGTT_HIP(hipMemcpyAsync(host[3 * q + w].data(), src[w], sizeof(double) * len[w], hipMemcpyDeviceToHost,
+                                ctx->c.s));
+      }
+    }
+    ctx->c.sync();
+    const double* cores[6];
+    for (int i = 0; i < 6; ++i) cores[i] = host[i].data();
+    st = pair_file_write(path, dims, cores);
+    if (st != SGTT_OK) ctx->err = std::string("checkpoint: cannot write ") + path;
+  });
+  return g != SGTT_OK ? g : st;
+}
+
+int sgtt_pair_load(sgtt_context* ctx, const char* path, sgtt_tt_pair* x) {
+  if (!ctx || !x || !path) return SGTT_E_INVALID;
+  int st = SGTT_OK;
+  const int g = guarded(ctx, [&]() {
+    sgtt_tt* t[2] = {&x->u, &x->p};
+    int caps[10], dims[10];
+    std::vector<double> host[6];
+    double* cores[6];
+    for (int q = 0; q < 2; ++q) {
+      const sgtt_tt& a = *t[q];
+      if (a.cap1 < 1 || a.cap2 < 1 || !a.core1 || !a.core2 || !a.core3)
+        throw SgttError(SGTT_E_INVALID, "checkpoint: invalid destination TT");
+      const int c[5] = {a.n1, a.n2, a.n3, a.cap1, a.cap2};
+      std::memcpy(caps + 5 * q, c, sizeof(c));
+      const long len[3] = {(long)a.n1 * a.cap1, (long)a.cap1 * a.n2 * a.cap2, (long)a.n3 * a.cap2};
+      for (int w = 0; w < 3; ++w) {
+        host[3 * q + w].resize((size_t)len[w]);
+        cores[3 * q + w] = host[3 * q + w].data();
+      }
+    }
+    st = pair_file_read(path, caps, cores, dims);
+    if (st != SGTT_OK) {
+      ctx->err = std::string("checkpoint: cannot load ") + path;
+      return;
+    }
+    for (int q = 0; q < 2; ++q) {
+      sgtt_tt& a = *t[q];
+      const int r1 = dims[5 * q + 3], r2 = dims[5 * q + 4];
+      double* dst[3] = {a.core1, a.core2, a.core3};
+      const long len[3] = {(long)a.n1 * r1, (long)r1 * a.n2 * r2, (long)a.n3 * r2};
+      for (int w = 0; w < 3; ++w)
+        SGTT_HIP(hipMemcpyAsync(dst[w], host[3 * q + w].data(), sizeof(double) * len[w], hipMemcpyHostToDevice,
+                                ctx->c.s));
+      a.r1 = r1;
+      a.r2 = r2;
+    }
+    ctx->c.sync();
+  });
+  return g != SGTT_OK ? g : st;
+}
+
 int sgtt_residual(sgtt_system* S, const sgtt_tt_pair* b, const sgtt_tt_pair* x, double* rel) {
   if (!S || !b || !x || !rel) return SGTT_E_INVALID;
   sgtt_context* ctx = S->ctx;
@@ -1577,6 +1688,9 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
   const long a0 = c.pool.device_allocs() + kernel_device_allocs();
   SolveCounters cnt;
   cnt.verbose = o.verbose;
+  cnt.t_start = t0;
+  S->hist.clear();
+  cnt.hist = &S->hist;
   OuterSpace sp(*S, prec_opts(&o), &cnt);
   S->mlp_off = false;
   S->mlp_fails = 0;
@@ -1588,6 +1702,7 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
   for (int cyc = 0; cyc < o.max_cycles; ++cyc) {
     int its = 0;
     double rr = 0;
+    cnt.cycle = cyc;
     Vec d = lowrank_fgmres(c, sp, r, o.tol_cycle, o.eps_krylov, o.restart, S->dsc, its, rr, &cnt, "outer",
                            o.outer_explicit != 0, o.relax != 0);
     cnt.outer += its;
@@ -1606,6 +1721,17 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
       const double fac = o.cycle_rhs_factor > 0.0 ? o.cycle_rhs_factor : 0.05;
       eps_r = std::max(o.eps_krylov, std::min(1e-3, fac * o.tol / std::max(rel, 1e-300)));
       full_residual(*S, bv, z, nullptr, &rnext, eps_r, &bn2);
+    }
+    {
+      // end of a refinement cycle: the exact residual of the accumulated
+      // solution against b, and that solution's ranks
+      sgtt_iter_record h{};
+      h.cycle = cyc;
+      h.iter = -1;
+      h.rel = rel;
+      hist_ranks(z, h.rank_z_u, h.rank_z_p);
+      h.seconds = now_s() - t0;
+      S->hist.push_back(h);
     }
     if (o.verbose) fprintf(stderr, "[sgtt] cycle %d: outer its %d, exact rel residual %.3e\n", cyc, its, rel);
     if (!std::isfinite(rel)) throw SgttError(-5, "non-finite residual");

@@ -88,6 +88,17 @@ class PicardStats(C.Structure):
                 "seconds": self.seconds}
 
 
+class IterRecord(C.Structure):
+    _fields_ = [("cycle", C.c_int), ("iter", C.c_int), ("rel", C.c_double), ("rank_v_u", C.c_int * 2),
+                ("rank_v_p", C.c_int * 2), ("rank_z_u", C.c_int * 2), ("rank_z_p", C.c_int * 2),
+                ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {"cycle": self.cycle, "iter": self.iter, "rel": self.rel, "rank_v_u": tuple(self.rank_v_u),
+                "rank_v_p": tuple(self.rank_v_p), "rank_z_u": tuple(self.rank_z_u),
+                "rank_z_p": tuple(self.rank_z_p), "seconds": self.seconds}
+
+
 class MemoryInfo(C.Structure):
     _fields_ = [("arena_bytes", C.c_size_t), ("arena_peak_bytes", C.c_size_t), ("cached_bytes", C.c_size_t),
                 ("device_allocs", C.c_long)]
@@ -125,6 +136,13 @@ _sig = {
     "sgtt_solve": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), C.POINTER(SolveOpts),
                              C.POINTER(SolveStats)]),
     "sgtt_residual": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), C.POINTER(C.c_double)]),
+    "sgtt_solve_history": (C.c_int, [_P, C.c_int, C.POINTER(IterRecord), C.POINTER(C.c_int)]),
+    "sgtt_pair_save": (C.c_int, [_P, C.POINTER(SgttPair), C.c_char_p]),
+    "sgtt_pair_load": (C.c_int, [_P, C.c_char_p, C.POINTER(SgttPair)]),
+    "sgtt_pair_file_write_host": (C.c_int, [C.c_char_p, C.POINTER(C.c_int), C.POINTER(C.c_void_p)]),
+    "sgtt_pair_file_info": (C.c_int, [C.c_char_p, C.POINTER(C.c_int)]),
+    "sgtt_pair_file_read_host": (C.c_int, [C.c_char_p, C.POINTER(C.c_int), C.POINTER(C.c_void_p),
+                                           C.POINTER(C.c_int)]),
     "sgtt_expand": (C.c_int, [_P, C.POINTER(SgttTT), _P]),
     "sgtt_hessenberg_lsq": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int, C.c_double, C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]),
@@ -414,6 +432,18 @@ class Context:
             mask |= 1 << names.index(cname)
         self.check(_lib.sgtt_profile_enable_classes(self._c, mask if enable else 0))
 
+    def save_pair(self, buf: "PairBuf", path: str):
+        """Write the TT pair in buf to a checkpoint file."""
+        s = buf.struct()
+        self.check(_lib.sgtt_pair_save(self._c, C.byref(s), os.fsencode(path)))
+
+    def load_pair(self, path: str, buf: "PairBuf"):
+        """Read a checkpoint file into buf (its capacities bound the ranks)."""
+        s = buf.struct()
+        self.check(_lib.sgtt_pair_load(self._c, os.fsencode(path), C.byref(s)))
+        buf.update(s)
+        return buf
+
     def profile_sample(self, period: int):
         """Record one event scope in every `period` of each kernel class."""
         self.check(_lib.sgtt_profile_sample(self._c, int(period)))
@@ -478,6 +508,14 @@ class System:
         _lib.sgtt_system_info_get(self._s, C.byref(info))
         self.info = info
         self.nt, self.nxi, self.nu, self.np = info.nt, info.n_xi, info.n_u, info.n_p
+
+    def history(self):
+        """Outer iterations and refinement-cycle ends of the last solve (list of dicts)."""
+        n = C.c_int()
+        self.ctx.check(_lib.sgtt_solve_history(self._s, 0, None, C.byref(n)))
+        buf = (IterRecord * max(n.value, 1))()
+        self.ctx.check(_lib.sgtt_solve_history(self._s, n.value, buf, C.byref(n)))
+        return [buf[i].as_dict() for i in range(n.value)]
 
     def pair(self, cap1=64, cap2=256, capp1=None, capp2=None):
         return PairBuf(self.nt, self.nxi, self.nu, self.np, cap1, cap2, capp1, capp2,
@@ -700,8 +738,57 @@ def picard(ctx: Context, cfg: dict, steps: int = 5, tol_picard: float = 1e-5, ep
     return out, st.as_dict(), rc
 
 
+def pair_file_info(path: str):
+    """(n1, n2, n3, r1, r2) of the velocity and pressure TTs of a checkpoint
+    file; raises SgttError for a missing or foreign file."""
+    d = (C.c_int * 10)()
+    rc = _lib.sgtt_pair_file_info(os.fsencode(path), d)
+    if rc != 0:
+        raise SgttError(rc, f"checkpoint file {path}")
+    return tuple(d[0:5]), tuple(d[5:10])
+
+
+def write_pair_host(path: str, cores):
+    """Write a checkpoint from host arrays: cores = ((G1, G2, G3), (P1, P2, P3))
+    in the library's layout (core 1 n1 x r1, core 2 r1 x n2 x r2, core 3
+    n3 x r2)."""
+    arrs, dims = [], []
+    for g1, g2, g3 in cores:
+        a = [np.ascontiguousarray(x, dtype=np.float64) for x in (g1, g2, g3)]
+        arrs += a
+        dims += [a[0].shape[0], a[1].shape[1], a[2].shape[0], a[0].shape[1], a[2].shape[1]]
+    d = (C.c_int * 10)(*dims)
+    ptrs = (C.c_void_p * 6)(*[x.ctypes.data for x in arrs])
+    rc = _lib.sgtt_pair_file_write_host(os.fsencode(path), d, ptrs)
+    if rc != 0:
+        raise SgttError(rc, f"checkpoint file {path}")
+
+
+def read_pair_host(path: str, caps=None):
+    """Read a checkpoint into host arrays; caps = ((n1, n2, n3, cap1, cap2),
+    (...)) sizes the buffers (default: the file's own sizes)."""
+    if caps is None:
+        caps = pair_file_info(path)
+    bufs = []
+    for n1, n2, n3, c1, c2 in caps:
+        bufs += [np.zeros(n1 * c1), np.zeros(c1 * n2 * c2), np.zeros(n3 * c2)]
+    cp = (C.c_int * 10)(*[v for c in caps for v in c])
+    ptrs = (C.c_void_p * 6)(*[x.ctypes.data for x in bufs])
+    d = (C.c_int * 10)()
+    rc = _lib.sgtt_pair_file_read_host(os.fsencode(path), cp, ptrs, d)
+    if rc != 0:
+        raise SgttError(rc, f"checkpoint file {path}")
+    out = []
+    for q in range(2):
+        n1, n2, n3, r1, r2 = d[5 * q:5 * q + 5]
+        b = bufs[3 * q:3 * q + 3]
+        out.append((b[0][:n1 * r1].reshape(n1, r1), b[1][:r1 * n2 * r2].reshape(r1, n2, r2),
+                    b[2][:n3 * r2].reshape(n3, r2)))
+    return tuple(out)
+
+
 ABI_STRUCTS = ("SgttTT", "SgttPair", "ProblemDesc", "SystemInfo", "SolveOpts", "SolveStats", "MemoryInfo",
-               "PicardOpts", "PicardStats")
+               "PicardOpts", "PicardStats", "IterRecord")
 
 
 def abi_sizes() -> dict:
