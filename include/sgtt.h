@@ -296,7 +296,10 @@ int sgtt_dot(sgtt_context* ctx, const sgtt_tt_pair* x, const sgtt_tt_pair* y, do
 int sgtt_axpby(sgtt_context* ctx, double alpha, const sgtt_tt_pair* x, double beta, sgtt_tt_pair* y);
 
 /* Solve L x = b (Alg. 4.2 with refinement to an exact relative residual).
- * x is output only (z_0 = 0).  opts = NULL uses defaults. */
+ * x is output only (z_0 = 0).  opts = NULL uses defaults.  Returns
+ * SGTT_W_NOT_CONVERGED with the best iterate in x when max_cycles run out,
+ * SGTT_E_NONFINITE (x untouched) for a right-hand side with a NaN or Inf,
+ * checked before any rounding, or for a non-finite residual later. */
 int sgtt_solve(sgtt_system* sys, const sgtt_tt_pair* b, sgtt_tt_pair* x, const sgtt_solve_opts* opts,
                sgtt_solve_stats* stats);
 

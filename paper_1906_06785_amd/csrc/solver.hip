@@ -1695,6 +1695,13 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
   S->mlp_off = false;
   S->mlp_fails = 0;
   S->mlp_calls = 0;
+  {
+    // a non-finite right-hand side is refused before any rounding sees it
+    // (the inner product is plain products and sums)
+    double* d = S->dsc + 30020;
+    vec_dot(c, bv, bv, d);
+    if (!std::isfinite(read_double(c, d))) throw SgttError(-5, "non-finite right-hand side");
+  }
   std::vector<Vec> terms;
   Vec r = vec_copy(c, bv);
   double bn2 = -1.0, rel = 1.0;
