@@ -463,8 +463,15 @@ int sgtt_mlp_size(const sgtt_mlp* mlp, long* nparam, long* npairs);
  * weights to FP16 and resets the optimizer state) */
 int sgtt_mlp_set_params(sgtt_mlp* mlp, const float* host);
 int sgtt_mlp_get_params(sgtt_mlp* mlp, float* host);
-/* y = MLP(x) for batch host columns (column s at x + s*n) */
+/* y = MLP(x) for batch host columns (column s at x + s*n): FP16 weights
+ * widened to FP32 against FP32 activations on the FP32 matrix cores (the
+ * form training differentiates) */
 int sgtt_mlp_forward(sgtt_mlp* mlp, const float* x, int batch, float* y);
+/* the same with every product on the FP16 matrix cores: inputs and hidden
+ * activations rounded to FP16, FP32 accumulation (the form the correction
+ * takes inside the preconditioner, where each right-hand side column is
+ * scaled to unit norm before rounding) */
+int sgtt_mlp_forward_f16(sgtt_mlp* mlp, const float* x, int batch, float* y);
 /* loss (mean relative squared error) and its gradient (host, nparam floats,
  * may be NULL) for host inputs x and targets t */
 int sgtt_mlp_loss_grad(sgtt_mlp* mlp, const float* x, const float* t, int batch, double* loss, float* grad);

@@ -38,6 +38,22 @@ def forward(p, X):
     return Y, (X, z1, h1, z2, h2)
 
 
+def _to_f16(a):
+    # round as the device does: its FP32 value to the nearest FP16
+    return a.astype(np.float32).astype(np.float16).astype(np.float64)
+
+
+def forward_f16(p, X):
+    """The forward with FP16 operands: the input and each hidden activation
+    rounded to FP16 before the product that consumes it (weights are FP16
+    already), products and sums otherwise exact (FP64 here; the device
+    accumulates in FP32)."""
+    h0 = _to_f16(X)
+    h1 = np.maximum(p["W1"] @ h0 + p["b1"][:, None], 0.0)
+    h2 = np.maximum(p["W2"] @ _to_f16(h1) + p["b2"][:, None], 0.0)
+    return p["W3"] @ _to_f16(h2) + p["b3"][:, None]
+
+
 def loss(p, X, T):
     """Mean relative squared error over the batch columns."""
     Y, _ = forward(p, X)

@@ -38,8 +38,10 @@ struct Mlp {
 Mlp* mlp_create(hipStream_t s, int n, int w, long cap, unsigned seed);
 void mlp_set_params(Mlp& m, const float* host);
 void mlp_get_params(const Mlp& m, float* host);
-// Y (n x B, sample-major: column s at Y + s*n) = MLP(X) for inputs in the same layout
-void mlp_forward_host(Mlp& m, const float* Xh, int B, float* Yh);
+// Y (n x B, sample-major: column s at Y + s*n) = MLP(X) for inputs in the same
+// layout; f16: the products on FP16 matrix cores with FP16 operands (the
+// form the solver's correction uses), else FP32 operands (training's form)
+void mlp_forward_host(Mlp& m, const float* Xh, int B, float* Yh, bool f16);
 // loss and gradients (FP32) for host inputs / targets; grads in parameter order
 double mlp_loss_grad_host(Mlp& m, const float* Xh, const float* Th, int B, float* gh);
 // Adam training on the collected pairs: steps minibatches of B pairs

@@ -102,6 +102,85 @@ __global__ __launch_bounds__(256) void k_mgemm(int m, int n, int k, float alpha,
     }
 }
 
+// The same product with FP16 operands on the FP16 matrix cores
+// (v_mfma_f32_16x16x16f16, FP32 accumulation): A (FP16 weight bits) is exact
+// in FP16; B is scaled by bscale[j] (when given) and rounded to FP16 as it is
+// staged.  Lane l supplies A[l%16][4(l/16) .. 4(l/16)+3] and
+// B[4(l/16) .. 4(l/16)+3][l%16]; accumulator item v is D[4(l/16) + v][l%16].
+// The tiles sit in LDS with k contiguous (rows of MK + 4 halves), so a lane
+// reads its four operands as one 8-byte load.
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+
+template <class TA, class TB, class TC>
+__global__ __launch_bounds__(256) void k_mgemm_h(int m, int n, int k, float alpha, const TA* __restrict__ A, long sAi,
+                                                 long sAk, const TB* __restrict__ B, long sBk, long sBj,
+                                                 const float* __restrict__ bscale, float beta, TC* __restrict__ C,
+                                                 long sCi, long sCj) {
+  constexpr int KP = MK + 4;
+  __shared__ __align__(16) _Float16 Ah[MT * KP];
+  __shared__ __align__(16) _Float16 Bh[MT * KP];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int i0 = blockIdx.y * MT, j0 = blockIdx.x * MT;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int lr = lane % 16, lk = lane / 16;
+  f4v acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
+  const bool a_kfast = (sAk == 1), b_kfast = (sBk == 1);
+  for (int kk = 0; kk < k; kk += MK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      int ii, kx;
+      if (a_kfast) { kx = e % MK; ii = e / MK; } else { ii = e % MT; kx = e / MT; }
+      const long gi = i0 + ii, gk = kk + kx;
+      Ah[ii * KP + kx] = (_Float16)((gi < m && gk < k) ? ldf(A, gi * sAi + gk * sAk) : 0.f);
+      int jj, kx2;
+      if (b_kfast) { kx2 = e % MK; jj = e / MK; } else { jj = e % MT; kx2 = e / MT; }
+      const long gj = j0 + jj, gk2 = kk + kx2;
+      float bv = (gj < n && gk2 < k) ? ldf(B, gk2 * sBk + gj * sBj) : 0.f;
+      if (bscale && gj < n) bv *= bscale[gj];
+      Bh[jj * KP + kx2] = (_Float16)bv;
+    }
+    __syncthreads();
+    const h4v a0 = *reinterpret_cast<const h4v*>(&Ah[(wr + lr) * KP + 4 * lk]);
+    const h4v a1 = *reinterpret_cast<const h4v*>(&Ah[(wr + 16 + lr) * KP + 4 * lk]);
+    const h4v b0 = *reinterpret_cast<const h4v*>(&Bh[(wc + lr) * KP + 4 * lk]);
+    const h4v b1 = *reinterpret_cast<const h4v*>(&Bh[(wc + 16 + lr) * KP + 4 * lk]);
+    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16f16(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16f16(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16f16(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16f16(a1, b1, acc[1][1], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const long gi = i0 + wr + tr * 16 + 4 * lk + v;
+      if (gi >= m) continue;
+#pragma unroll
+      for (int tc = 0; tc < 2; ++tc) {
+        const long gj = j0 + wc + tc * 16 + lr;
+        if (gj >= n) continue;
+        TC* cp = C + gi * sCi + gj * sCj;
+        float val = alpha * acc[tr][tc][v];
+        if (beta != 0.f) val += beta * (float)(*cp);
+        *cp = (TC)val;
+      }
+    }
+}
+
+template <class TA, class TB, class TC>
+void mgemm_h(hipStream_t s, int m, int n, int k, float alpha, const TA* A, long sAi, long sAk, const TB* B, long sBk,
+             long sBj, const float* bscale, float beta, TC* C, long sCi, long sCj) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL((k_mgemm_h<TA, TB, TC>), dim3(cdivu(n, MT), cdivu(m, MT)), dim3(256), 0, s, m, n, k, alpha, A,
+                     sAi, sAk, B, sBk, sBj, bscale, beta, C, sCi, sCj);
+}
+
 template <class TA, class TB, class TC>
 void mgemm(hipStream_t s, int m, int n, int k, float alpha, const TA* A, long sAi, long sAk, const TB* B, long sBk,
            long sBj, float beta, TC* C, long sCi, long sCj) {
@@ -346,13 +425,27 @@ Acts acts(Mlp& m, int B) {
   return r;
 }
 
-// forward on sample-major inputs X (column s at X + s*n) into a.H1, a.H2, a.Y
+// forward on sample-major inputs X (column s at X + s*n) into a.H1, a.H2, a.Y.
+// f16: every product on the FP16 matrix cores (inputs scaled by colscale and
+// rounded to FP16 as they are staged, activations rounded likewise), as the
+// solver's correction runs; otherwise FP16 weights widened to FP32 against
+// FP32 activations (training, whose gradients need the wider operands).
 template <class TX>
-void forward(Mlp& m, const TX* X, long sXk, long sXj, const float* colscale, int B, Acts& a) {
+void forward(Mlp& m, const TX* X, long sXk, long sXj, const float* colscale, int B, Acts& a, bool f16) {
   const int n = m.n, w = m.w;
   const unsigned short* W1 = m.w16 + m.off_W1;
   const unsigned short* W2 = m.w16 + m.off_W2;
   const unsigned short* W3 = m.w16 + m.off_W3;
+  if (f16) {
+    mgemm_h(m.s, w, B, n, 1.f, W1, (long)n, 1L, X, sXk, sXj, colscale, 0.f, a.H1, 1L, (long)w);
+    hipLaunchKernelGGL(k_bias_act, dim3(cdivu((long)w * B, 256)), dim3(256), 0, m.s, w, B, a.H1,
+                       m.master + m.off_b1, nullptr, 1);
+    mgemm_h(m.s, w, B, w, 1.f, W2, (long)w, 1L, a.H1, 1L, (long)w, nullptr, 0.f, a.H2, 1L, (long)w);
+    hipLaunchKernelGGL(k_bias_act, dim3(cdivu((long)w * B, 256)), dim3(256), 0, m.s, w, B, a.H2,
+                       m.master + m.off_b2, nullptr, 1);
+    mgemm_h(m.s, n, B, w, 1.f, W3, (long)w, 1L, a.H2, 1L, (long)w, nullptr, 0.f, a.Y, 1L, (long)n);
+    return;
+  }
   mgemm(m.s, w, B, n, 1.f, W1, (long)n, 1L, X, sXk, sXj, 0.f, a.H1, 1L, (long)w);
   hipLaunchKernelGGL(k_bias_act, dim3(cdivu((long)w * B, 256)), dim3(256), 0, m.s, w, B, a.H1, m.master + m.off_b1,
                      colscale, 1);
@@ -365,7 +458,7 @@ void forward(Mlp& m, const TX* X, long sXk, long sXj, const float* colscale, int
 // loss and gradients for the batch in a.Xb / a.Tb; returns the loss (syncs)
 double loss_grad(Mlp& m, int B, Acts& a) {
   const int n = m.n, w = m.w;
-  forward(m, a.Xb, 1L, (long)n, nullptr, B, a);
+  forward(m, a.Xb, 1L, (long)n, nullptr, B, a, false);
   hipLaunchKernelGGL(k_bias_act, dim3(cdivu((long)n * B, 256)), dim3(256), 0, m.s, n, B, a.Y, m.master + m.off_b3,
                      nullptr, 0);
   MLP_HIP(hipMemsetAsync(m.dscal, 0, sizeof(double), m.s));
@@ -393,11 +486,11 @@ double loss_grad(Mlp& m, int B, Acts& a) {
 }
 }  // namespace
 
-void mlp_forward_host(Mlp& m, const float* Xh, int B, float* Yh) {
+void mlp_forward_host(Mlp& m, const float* Xh, int B, float* Yh, bool f16) {
   if (B < 1) return;
   Acts a = acts(m, B);
   MLP_HIP(hipMemcpyAsync(a.Xb, Xh, (size_t)B * m.n * sizeof(float), hipMemcpyHostToDevice, m.s));
-  forward(m, a.Xb, 1L, (long)m.n, nullptr, B, a);
+  forward(m, a.Xb, 1L, (long)m.n, nullptr, B, a, f16);
   hipLaunchKernelGGL(k_bias_act, dim3(cdivu((long)m.n * B, 256)), dim3(256), 0, m.s, m.n, B, a.Y,
                      m.master + m.off_b3, nullptr, 0);
   MLP_HIP(hipMemcpyAsync(Yh, a.Y, (size_t)B * m.n * sizeof(float), hipMemcpyDeviceToHost, m.s));
@@ -481,7 +574,7 @@ void mlp_apply(Mlp& m, int ns, int ncomp, int ncols, const double* R, double* Z,
     const double* Rc = R + (long)c * ns * ld;
     double* Zc = Z + (long)c * ns * ld;
     hipLaunchKernelGGL(k_colnorm, dim3(ncols), dim3(256), 0, m.s, ns, Rc, ld, nrm, inv);
-    forward(m, Rc, ld, 1L, inv, ncols, a);
+    forward(m, Rc, ld, 1L, inv, ncols, a, true);
     hipLaunchKernelGGL(k_mlp_out, dim3(cdivu((long)ns * ncols, 256)), dim3(256), 0, m.s, ns, ncols, Rc, Zc, ld, Dinv,
                        a.Y, m.master + m.off_b3, nrm);
   }

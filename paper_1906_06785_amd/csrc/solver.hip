@@ -1987,7 +1987,12 @@ int sgtt_mlp_get_params(sgtt_mlp* m, float* host) {
 
 int sgtt_mlp_forward(sgtt_mlp* m, const float* x, int batch, float* y) {
   if (!m || !x || !y || batch < 1) return SGTT_E_INVALID;
-  return guarded(m->ctx, [&]() { mlp_forward_host(*m->m, x, batch, y); });
+  return guarded(m->ctx, [&]() { mlp_forward_host(*m->m, x, batch, y, false); });
+}
+
+int sgtt_mlp_forward_f16(sgtt_mlp* m, const float* x, int batch, float* y) {
+  if (!m || !x || !y || batch < 1) return SGTT_E_INVALID;
+  return guarded(m->ctx, [&]() { mlp_forward_host(*m->m, x, batch, y, true); });
 }
 
 int sgtt_mlp_loss_grad(sgtt_mlp* m, const float* x, const float* t, int batch, double* loss, float* grad) {

@@ -164,6 +164,7 @@ _sig = {
     "sgtt_mlp_set_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
     "sgtt_mlp_get_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
     "sgtt_mlp_forward": (C.c_int, [_P, C.POINTER(C.c_float), C.c_int, C.POINTER(C.c_float)]),
+    "sgtt_mlp_forward_f16": (C.c_int, [_P, C.POINTER(C.c_float), C.c_int, C.POINTER(C.c_float)]),
     "sgtt_mlp_loss_grad": (C.c_int, [_P, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int,
                                      C.POINTER(C.c_double), C.POINTER(C.c_float)]),
     "sgtt_mlp_train": (C.c_int, [_P, C.c_int, C.c_int, C.c_double, C.c_uint, C.POINTER(C.c_double)]),
@@ -650,13 +651,15 @@ class Mlp:
         self.ctx.check(_lib.sgtt_mlp_get_params(self._m, flat.ctypes.data_as(C.POINTER(C.c_float))))
         return self.split(flat)
 
-    def forward(self, X):
-        """X: (n, B) -> (n, B) float32."""
+    def forward(self, X, f16: bool = False):
+        """X: (n, B) -> (n, B) float32; f16 runs the products on FP16
+        operands (the preconditioner's form)."""
         Xc = np.ascontiguousarray(np.asarray(X, dtype=np.float32).T)
         B = Xc.shape[0]
         Y = np.zeros_like(Xc)
-        self.ctx.check(_lib.sgtt_mlp_forward(self._m, Xc.ctypes.data_as(C.POINTER(C.c_float)), B,
-                                             Y.ctypes.data_as(C.POINTER(C.c_float))))
+        fn = _lib.sgtt_mlp_forward_f16 if f16 else _lib.sgtt_mlp_forward
+        self.ctx.check(fn(self._m, Xc.ctypes.data_as(C.POINTER(C.c_float)), B,
+                          Y.ctypes.data_as(C.POINTER(C.c_float))))
         return Y.T
 
     def loss_grad(self, X, T):

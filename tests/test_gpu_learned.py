@@ -51,6 +51,18 @@ def test_mlp_forward_and_gradients_match_oracle(sg, ctx, n, w, B):
     Y = net.forward(X)
     Yo, _ = omlp.forward(p, X)
     assert np.linalg.norm(Y - Yo) <= 1e-5 * np.linalg.norm(Yo)
+    # the preconditioner's form on the FP16 matrix cores: against the oracle
+    # with the same operand rounding (a rounding to FP16 taken from FP32
+    # values that differ in the last bit can land one FP16 step apart, so
+    # the bound is a few FP16 steps of one activation), and against the
+    # exact forward by the FP16 rounding of the operands
+    Y16 = net.forward(X, f16=True)
+    Yo16 = omlp.forward_f16(p, X)
+    e16 = np.linalg.norm(Y16 - Yo16) / np.linalg.norm(Yo16)
+    e64 = np.linalg.norm(Y16 - Yo) / np.linalg.norm(Yo)
+    _flush(f"fp16 operands: vs oracle with fp16 operands {e16:.2e}, vs exact forward {e64:.2e}")
+    assert e16 <= 2e-4
+    assert e64 <= 5e-3
     L, gr = net.loss_grad(X, T)
     Lo, go = omlp.grads(p, X, T)
     assert abs(L - Lo) <= 1e-5 * Lo

@@ -50,3 +50,22 @@ def test_adam_first_step_is_sign_times_lr():
     state = [np.zeros(3), np.zeros(3)]
     new, _ = mlp.adam_step(np.zeros(3), g, state, 0.01, 1)
     assert np.allclose(new, -0.01 * g / (np.abs(g) + 1e-8))
+
+
+def test_forward_f16_rounds_only_the_operands():
+    # with inputs, weights and every activation exact in FP16 (small dyadic
+    # numbers) the FP16-operand forward is the exact forward; with general
+    # inputs it differs by the FP16 rounding of the three operands only
+    g = np.random.default_rng(4)
+    n, w, B = 12, 8, 5
+    p = {"W1": g.integers(-3, 4, (w, n)) / 8.0, "b1": g.integers(-2, 3, w) / 4.0,
+         "W2": g.integers(-3, 4, (w, w)) / 8.0, "b2": g.integers(-2, 3, w) / 4.0,
+         "W3": g.integers(-3, 4, (n, w)) / 8.0, "b3": g.integers(-2, 3, n) / 4.0}
+    X = g.integers(-4, 5, (n, B)) / 4.0
+    Y, _ = mlp.forward(p, X)
+    assert np.array_equal(mlp.forward_f16(p, X), Y)
+    p = mlp.init_params(40, 16, 2)
+    X = g.standard_normal((40, 9)) / np.sqrt(40)
+    Y, _ = mlp.forward(p, X)
+    d = np.linalg.norm(mlp.forward_f16(p, X) - Y) / np.linalg.norm(Y)
+    assert 1e-6 < d < 3 * 2.0 ** -11 * 10
