@@ -23,7 +23,7 @@ def _lib():
 def test_library_exports_every_declared_symbol():
     sg = _lib()
     header = open(os.path.join(ROOT, "include", "sgtt.h")).read()
-    declared = set(re.findall(r"\b(sgtt_[a-z_]+)\s*\(", header))
+    declared = set(re.findall(r"\b(sgtt_[a-z_0-9]+)\s*\(", header))
     assert declared, "no declarations parsed"
     import ctypes
     lib = ctypes.CDLL(sg.LIB_PATH)
