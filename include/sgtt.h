@@ -367,6 +367,16 @@ typedef struct {
 int sgtt_picard(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_picard_opts* opts,
                 sgtt_tt_pair* x, sgtt_picard_stats* stats);
 
+/* ------------------------------------------------------------- dense products */
+/* C = alpha A B + beta C in FP64 with the library's product kernels (the
+ * ones the TT cores, Grams, projections and full-tensor expansions use):
+ * row-major device matrices, A m x k (leading dimension lda >= k), B k x n
+ * (ldb >= n), C m x n (ldc >= n).  m, n >= 1, k >= 0 (A and B may be NULL
+ * for k = 0, which scales C by beta); SGTT_E_INVALID otherwise.  Stream-ordered on the context stream; synchronizes.  For
+ * checks of the kernels against a reference product. */
+int sgtt_gemm(sgtt_context* ctx, int m, int n, int k, double alpha, const double* A, long lda, const double* B,
+              long ldb, double beta, double* C, long ldc);
+
 /* ------------------------------------------------------------- solve history */
 /* One record per outer FGMRES iteration of the last sgtt_solve on a system
  * (iter = 1, 2, ... within refinement cycle `cycle`), and one closing each

@@ -1571,6 +1571,17 @@ int sgtt_hessenberg_lsq(sgtt_context* ctx, const double* H, int k, double beta, 
   });
 }
 
+int sgtt_gemm(sgtt_context* ctx, int m, int n, int k, double alpha, const double* A, long lda, const double* B,
+              long ldb, double beta, double* C, long ldc) {
+  if (!ctx || !C || m < 1 || n < 1 || k < 0 || ldc < n || (k > 0 && (!A || !B || lda < k || ldb < n)))
+    return SGTT_E_INVALID;
+  return guarded(ctx, [&]() {
+    GemmPrecisionScope f64(GP_F64);
+    gemm(ctx->c.s, 1, m, n, k, alpha, A, 0, lda, 1, B, 0, ldb, 1, beta, C, 0, ldc, 1);
+    ctx->c.sync();
+  });
+}
+
 int sgtt_solve_history(const sgtt_system* S, int max_records, sgtt_iter_record* out, int* nrecords) {
   if (!S || !nrecords || max_records < 0 || (max_records > 0 && !out)) return SGTT_E_INVALID;
   const int n = (int)S->hist.size();

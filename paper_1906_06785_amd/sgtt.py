@@ -137,6 +137,8 @@ _sig = {
                              C.POINTER(SolveStats)]),
     "sgtt_residual": (C.c_int, [_P, C.POINTER(SgttPair), C.POINTER(SgttPair), C.POINTER(C.c_double)]),
     "sgtt_solve_history": (C.c_int, [_P, C.c_int, C.POINTER(IterRecord), C.POINTER(C.c_int)]),
+    "sgtt_gemm": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_double, _P, C.c_long, _P, C.c_long, C.c_double,
+                            _P, C.c_long]),
     "sgtt_pair_save": (C.c_int, [_P, C.POINTER(SgttPair), C.c_char_p]),
     "sgtt_pair_load": (C.c_int, [_P, C.c_char_p, C.POINTER(SgttPair)]),
     "sgtt_pair_file_write_host": (C.c_int, [C.c_char_p, C.POINTER(C.c_int), C.POINTER(C.c_void_p)]),
@@ -432,6 +434,18 @@ class Context:
         for cname in classes:
             mask |= 1 << names.index(cname)
         self.check(_lib.sgtt_profile_enable_classes(self._c, mask if enable else 0))
+
+    def gemm(self, A, B, C=None, alpha=1.0, beta=0.0):
+        """C = alpha A B + beta C with the library's FP64 product kernels;
+        A, B, C row-major float64 device tensors (C created when None)."""
+        torch = _torch()
+        m, k = A.shape
+        n = B.shape[1]
+        if C is None:
+            C = torch.zeros((m, n), dtype=torch.float64, device=A.device)
+        self.check(_lib.sgtt_gemm(self._c, m, n, k, float(alpha), A.data_ptr(), A.stride(0), B.data_ptr(),
+                                  B.stride(0), float(beta), C.data_ptr(), C.stride(0)))
+        return C
 
     def save_pair(self, buf: "PairBuf", path: str):
         """Write the TT pair in buf to a checkpoint file."""
