@@ -1011,6 +1011,21 @@ __global__ __launch_bounds__(TE_THREADS) void k_trunc_jacobi(int km, const int* 
   while ((1 << tsh) < npairs) ++tsh;
   while ((1 << vsh) < n) ++vsh;
   for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
+    // a sweep in which no pair would rotate changes nothing: test every
+    // pair against the rotation threshold first and stop without it
+    if (tid == 0) s_flag = 0;
+    __syncthreads();
+    for (int e = tid; e < n * n; e += nth) {
+      const int a = e / n, b = e - a * n;
+      if (a < b) {
+        const double apq = T[a * KLD + b];
+        if (fabs(apq) > fmax(1e-13 * sqrt(fabs(T[a * KLD + a] * T[b * KLD + b])), 1e-16 * ttr) && apq != 0.0)
+          s_flag = 1;
+      }
+    }
+    __syncthreads();
+    if (!s_flag) break;   // uniform: every thread reads the flag after the barrier
+    __syncthreads();
     if (tid == 0) s_flag = 0;
     __syncthreads();
     for (int rnd = 0; rnd < np2 - 1; ++rnd) {
