@@ -173,7 +173,14 @@ typedef struct {
 
 /* ------------------------------------------------------------- context */
 /* One device, one stream.  hip_stream may be NULL (the library creates a
- * default-priority stream) or an existing hipStream_t (e.g. torch's). */
+ * default-priority stream) or an existing hipStream_t (e.g. torch's).
+ * Calls are ordered on that stream.  Inside a solve, the pressure TT of a
+ * vector pair is rounded on a second, default-priority stream driven by a
+ * second host thread of the context (created on first use, with its own
+ * memory pool), forked from and joined back into the context's stream; the
+ * results are the same as rounding both on one stream.  The environment
+ * variable SGTT_SIDE_LANE=0 at context creation keeps both on the calling
+ * thread and stream. */
 int sgtt_context_create(int device, void* hip_stream, sgtt_context** out);
 int sgtt_context_destroy(sgtt_context* ctx);
 /* Device memory of a context.  The library takes temporaries from a

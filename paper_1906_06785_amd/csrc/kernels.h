@@ -29,6 +29,8 @@ const char* kernel_class_name(int cls);
 long kernel_device_allocs();
 // grow the stream's split-K workspace to the largest any launch uses
 void splitk_reserve(hipStream_t s);
+// frees the split-K workspace of a stream that is about to be destroyed
+void splitk_release(hipStream_t s);
 // what a gemm() call computes, for the profiler's classes and the kernel's name
 enum GemmTag { GEMM_PLAIN = 0, GEMM_GRAM = 1, GEMM_PROJ = 2 };
 struct GemmTagScope {

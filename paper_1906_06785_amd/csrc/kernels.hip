@@ -2225,6 +2225,17 @@ void splitk_reserve(hipStream_t s) {
   if (!splitk_ws(s, (size_t)256 * 64 * 64)) throw std::runtime_error("split-K workspace: device allocation failed");
 }
 
+void splitk_release(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_splitk_mu);
+  auto it = g_splitk.find(s);
+  if (it == g_splitk.end()) return;
+  if (it->second.first) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(it->second.first);
+  }
+  g_splitk.erase(it);
+}
+
 GemmTagScope::GemmTagScope(int tag) : old(g_gemm_tag) { g_gemm_tag = tag; }
 GemmTagScope::~GemmTagScope() { g_gemm_tag = old; }
 

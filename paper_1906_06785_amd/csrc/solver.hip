@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -349,6 +350,16 @@ Vec vec_round(Ctx& c, const Vec& x, double eps, double* d_normsq, double* d_kept
   // d_normsq / d_kept: device arrays of 2 (per component), may be null
   Vec y;
   y.nc = x.nc;
+  if (x.nc == 2) {
+    pair_run(
+        c,
+        [&](Ctx& cc) { return tt_round(cc, x.c[0], eps, d_normsq, d_kept); },
+        [&](Ctx& cc) {
+          return tt_round(cc, x.c[1], eps, d_normsq ? d_normsq + 1 : nullptr, d_kept ? d_kept + 1 : nullptr);
+        },
+        y.c[0], y.c[1]);
+    return y;
+  }
   for (int i = 0; i < x.nc; ++i)
     y.c[i] = tt_round(c, x.c[i], eps, d_normsq ? d_normsq + i : nullptr, d_kept ? d_kept + i : nullptr);
   return y;
@@ -478,6 +489,22 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
   Vec z;
   double res = beta;
   int k = 0;
+  // z = T(sum_i y_i vh_i) of line 13, the pair's two components side by side
+  auto solution_round = [&](Vec& zz) {
+    auto one = [&](Ctx& cc, int q) {
+      std::vector<Term> terms;
+      std::vector<const double*> cache((size_t)k * k, nullptr);
+      for (int i = 0; i < k; ++i) {
+        terms.push_back(Term{&Vh[i].c[q], y + i, 1.0});
+        for (int j = i; j < k; ++j) cache[(size_t)i * k + j] = KVh.at(q, i, j);
+      }
+      return tt_round_sum(cc, terms, eps, nullptr, nullptr, &cache);
+    };
+    if (nc == 2)
+      pair_run(c, [&](Ctx& cc) { return one(cc, 0); }, [&](Ctx& cc) { return one(cc, 1); }, zz.c[0], zz.c[1]);
+    else
+      zz.c[0] = one(c, 0);
+  };
   while (res > tol * bnorm && k < maxit) {
     ++k;
     double t0 = now_s();
@@ -517,7 +544,7 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
     // line 10: h_{k+1,k} = ||x - sum h v||, v_{k+1} = T(x / h)
     Vec vn;
     vn.nc = nc;
-    for (int q = 0; q < nc; ++q) {
+    auto mgs_round = [&](Ctx& cc, int q) {
       std::vector<Term> terms{Term{&x.c[q], coef, 1.0}};
       std::vector<const double*> cache((size_t)(k + 1) * (k + 1), nullptr);
       for (int i = 0; i < k; ++i) {
@@ -525,8 +552,13 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
         cache[(size_t)0 * (k + 1) + 1 + i] = KX.at(q, 0, i);
         for (int j = i; j < k; ++j) cache[(size_t)(1 + i) * (k + 1) + 1 + j] = KV.at(q, i, j);
       }
-      vn.c[q] = tt_round_sum(c, terms, eps_k, sc + 6 + q, nullptr, &cache);
-    }
+      return tt_round_sum(cc, terms, eps_k, sc + 6 + q, nullptr, &cache);
+    };
+    if (nc == 2)
+      pair_run(c, [&](Ctx& cc) { return mgs_round(cc, 0); }, [&](Ctx& cc) { return mgs_round(cc, 1); }, vn.c[0],
+               vn.c[1]);
+    else
+      vn.c[0] = mgs_round(c, 0);
     scalar_op(c.s, 0, sc + 6, nc > 1 ? sc + 7 : nullptr, H + (size_t)(k - 1) * ld + k);   // h_{k+1,k}
     double hk = read_double(c, H + (size_t)(k - 1) * ld + k);
     bool breakdown = !(hk > 1e-14 * beta);
@@ -561,23 +593,21 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
     }
     z = Vec();
     z.nc = nc;
-    for (int q = 0; q < nc; ++q) {
-      std::vector<Term> terms;
-      std::vector<const double*> cache((size_t)k * k, nullptr);
-      for (int i = 0; i < k; ++i) {
-        terms.push_back(Term{&Vh[i].c[q], y + i, 1.0});
-        for (int j = i; j < k; ++j) cache[(size_t)i * k + j] = KVh.at(q, i, j);
-      }
-      z.c[q] = tt_round_sum(c, terms, eps, nullptr, nullptr, &cache);
-    }
+    solution_round(z);
     // line 14: s_k = T(b - L z_k)
     double t2 = now_s();
     Vec Lz = sp.apply(z);
     if (cnt) cnt->t_apply += now_s() - t2;
-    for (int q = 0; q < nc; ++q) {
-      std::vector<Term> terms{Term{&b.c[q], nullptr, 1.0}, Term{&Lz.c[q], nullptr, -1.0}};
-      TT sk = tt_round_sum(c, terms, eps, nullptr, sc + 9 + q, nullptr);
-      (void)sk;
+    {
+      auto one = [&](Ctx& cc, int q) {
+        std::vector<Term> terms{Term{&b.c[q], nullptr, 1.0}, Term{&Lz.c[q], nullptr, -1.0}};
+        return tt_round_sum(cc, terms, eps, nullptr, sc + 9 + q, nullptr);
+      };
+      TT sk0, sk1;
+      if (nc == 2)
+        pair_run(c, [&](Ctx& cc) { return one(cc, 0); }, [&](Ctx& cc) { return one(cc, 1); }, sk0, sk1);
+      else
+        sk0 = one(c, 0);
     }
     scalar_op(c.s, 0, sc + 9, nc > 1 ? sc + 10 : nullptr, sc + 11);
     res = read_double(c, sc + 11);
@@ -609,15 +639,7 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
   if (!explicit_res && k > 0) {
     z = Vec();
     z.nc = nc;
-    for (int q = 0; q < nc; ++q) {
-      std::vector<Term> terms;
-      std::vector<const double*> cache((size_t)k * k, nullptr);
-      for (int i = 0; i < k; ++i) {
-        terms.push_back(Term{&Vh[i].c[q], y + i, 1.0});
-        for (int j = i; j < k; ++j) cache[(size_t)i * k + j] = KVh.at(q, i, j);
-      }
-      z.c[q] = tt_round_sum(c, terms, eps, nullptr, nullptr, &cache);
-    }
+    solution_round(z);
   }
   if (k == 0) z = vec_copy(c, V[0]);
   return z;
@@ -1065,6 +1087,13 @@ int sgtt_context_create(int device, void* stream, sgtt_context** out) {
   sgtt_context* ctx = new sgtt_context();
   try {
     ctx->device = device;
+    ctx->c.device = device;
+    {
+      // the pressure TT of a pair is rounded on a second stream beside the
+      // velocity TT (SGTT_SIDE_LANE=0 rounds them one after the other)
+      const char* e = std::getenv("SGTT_SIDE_LANE");
+      ctx->c.side_enabled = !(e && e[0] == '0');
+    }
     SGTT_HIP(hipSetDevice(device));
     if (stream) {
       ctx->c.s = (hipStream_t)stream;
@@ -1111,7 +1140,10 @@ int sgtt_context_destroy(sgtt_context* ctx) {
   hipStream_t s = ctx->c.s;
   bool own = ctx->own_stream;
   delete ctx;
-  if (own) (void)hipStreamDestroy(s);
+  if (own) {
+    splitk_release(s);
+    (void)hipStreamDestroy(s);
+  }
   return SGTT_OK;
 }
 
@@ -1695,8 +1727,8 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
   if (o.restart < 1 || o.restart > 60 || o.max_cycles < 1 || o.inner_maxit < 1 || o.inner_maxit > 60)
     throw SgttError(-1, "invalid solve options");
   double t0 = now_s();
-  long r0 = c.roundings;
-  const long a0 = c.pool.device_allocs() + kernel_device_allocs();
+  long r0 = c.roundings + side_roundings(c);
+  const long a0 = c.pool.device_allocs() + kernel_device_allocs() + side_device_allocs(c);
   SolveCounters cnt;
   cnt.verbose = o.verbose;
   cnt.t_start = t0;
@@ -1765,14 +1797,14 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
     stats->seconds = now_s() - t0;
     stats->max_rank_krylov_u = cnt.maxr_u;
     stats->max_rank_krylov_p = cnt.maxr_p;
-    stats->roundings = (int)(c.roundings - r0);
+    stats->roundings = (int)(c.roundings + side_roundings(c) - r0);
     stats->t_apply = cnt.t_apply;
     stats->t_round = 0;
     stats->t_precond = cnt.t_prec;
     stats->t_residual = 0;
     stats->learned_calls = S->mlp_calls;
     stats->learned_fallback = S->mlp_off ? 1 : 0;
-    stats->device_allocs = c.pool.device_allocs() + kernel_device_allocs() - a0;
+    stats->device_allocs = c.pool.device_allocs() + kernel_device_allocs() + side_device_allocs(c) - a0;
   }
   return rel > o.tol ? SGTT_W_NOT_CONVERGED : SGTT_OK;
 }

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <functional>
 #include <map>
 #include <stdexcept>
 #include <string>
@@ -80,9 +81,16 @@ struct Vec {
   int nc = 2;
 };
 
+struct SideLane;
+
 struct Ctx {
   hipStream_t s = nullptr;
   Pool pool;
+  // second stream and host thread for the pressure TT of a vector pair
+  // (see pair_run); created on first use, owned by this context
+  SideLane* side = nullptr;
+  int device = 0;
+  bool side_enabled = true;
   // scratch (grown on demand)
   double* ws = nullptr;
   size_t ws_n = 0;
@@ -100,6 +108,22 @@ struct Ctx {
   void sync();
   ~Ctx();
 };
+
+// Runs fu on this thread and context (its stream) and fp on the context's
+// side lane (a second stream driven by a second host thread, with its own
+// memory pool and scratch), concurrently: the two TTs of a vector pair are
+// rounded side by side, so that the one-workgroup eigen stages of the
+// velocity and pressure truncations overlap and each waits on its own
+// stream only.  The side stream starts after everything queued on c's
+// stream so far and c's stream resumes after the side work; fp's result is
+// copied into c's pool (its own memory is recycled on the side lane).  The
+// calling thread's product precision and profiler phase carry over.  With
+// c.side_enabled false both run here, one after the other.
+void pair_run(Ctx& c, const std::function<TT(Ctx&)>& fu, const std::function<TT(Ctx&)>& fp, TT& out_u, TT& out_p);
+// device allocations and roundings of the side lane so far (0 without one)
+long side_device_allocs(const Ctx& c);
+long side_roundings(const Ctx& c);
+void side_release(Ctx& c);   // joins the side thread and frees its stream and memory
 
 TT tt_new(Ctx& c, int n1, int n2, int n3, int r1, int r2);
 TT tt_view(int n1, int n2, int n3, int r1, int r2, double* c1, double* c2, double* c3);

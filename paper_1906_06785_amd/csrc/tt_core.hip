@@ -12,6 +12,10 @@
 #include "tt_core.h"
 
 #include <algorithm>
+#include <condition_variable>
+#include <exception>
+#include <mutex>
+#include <thread>
 #include <cstring>
 
 namespace sgtt {
@@ -146,8 +150,139 @@ void TT::release() {
 }
 
 Ctx::~Ctx() {
+  side_release(*this);
   if (hint) (void)hipHostFree(hint);
   if (hdbl) (void)hipHostFree(hdbl);
+}
+
+// ---------------------------------------------------------------- side lane
+struct SideLane {
+  Ctx c;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::function<void()> job;
+  bool has_job = false, done = true, quit = false;
+  std::exception_ptr err;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  TT held;   // the last result, in this lane's pool until the next job
+
+  explicit SideLane(int device) {
+    c.device = device;
+    c.side_enabled = false;
+    SGTT_HIP(hipSetDevice(device));
+    SGTT_HIP(hipStreamCreateWithFlags(&c.s, hipStreamNonBlocking));
+    SGTT_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+    SGTT_HIP(hipEventCreateWithFlags(&join_ev, hipEventDisableTiming));
+    SGTT_HIP(hipHostMalloc((void**)&c.hint, 64 * sizeof(int), hipHostMallocDefault));
+    SGTT_HIP(hipHostMalloc((void**)&c.hdbl, 256 * sizeof(double), hipHostMallocDefault));
+    c.dint = (int*)c.pool.get(64);
+    c.dscal = c.pool.get(256);
+    th = std::thread([this, device]() {
+      (void)hipSetDevice(device);
+      std::unique_lock<std::mutex> lk(mu);
+      for (;;) {
+        cv.wait(lk, [this] { return has_job || quit; });
+        if (quit) return;
+        std::function<void()> f = std::move(job);
+        has_job = false;
+        lk.unlock();
+        std::exception_ptr e;
+        try {
+          f();
+        } catch (...) {
+          e = std::current_exception();
+        }
+        lk.lock();
+        err = e;
+        done = true;
+        cv.notify_all();
+      }
+    });
+  }
+  ~SideLane() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      quit = true;
+    }
+    cv.notify_all();
+    if (th.joinable()) th.join();
+    (void)hipStreamSynchronize(c.s);
+    held.release();
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
+    // the pool and pinned mirrors go with c; the stream last
+    hipStream_t s = c.s;
+    c.s = nullptr;
+    if (s) {
+      splitk_release(s);
+      (void)hipStreamDestroy(s);
+    }
+  }
+  void post(std::function<void()> f) {
+    std::lock_guard<std::mutex> lk(mu);
+    job = std::move(f);
+    has_job = true;
+    done = false;
+    err = nullptr;
+    cv.notify_all();
+  }
+  // waits for the posted job; returns its exception (null if none)
+  std::exception_ptr wait() {
+    std::unique_lock<std::mutex> lk(mu);
+    cv.wait(lk, [this] { return done; });
+    return err;
+  }
+};
+
+void side_release(Ctx& c) {
+  delete c.side;
+  c.side = nullptr;
+}
+
+long side_device_allocs(const Ctx& c) { return c.side ? c.side->c.pool.device_allocs() : 0; }
+long side_roundings(const Ctx& c) { return c.side ? c.side->c.roundings : 0; }
+
+void pair_run(Ctx& c, const std::function<TT(Ctx&)>& fu, const std::function<TT(Ctx&)>& fp, TT& out_u, TT& out_p) {
+  if (!c.side_enabled) {
+    out_u = fu(c);
+    out_p = fp(c);
+    return;
+  }
+  if (!c.side) c.side = new SideLane(c.device);
+  SideLane& L = *c.side;
+  const int prec = gemm_precision(GP_F64);
+  gemm_precision(prec);
+  const int region = prof_region(0);
+  prof_region(region);
+  SGTT_HIP(hipEventRecord(L.fork_ev, c.s));
+  L.post([&L, &fp, prec, region]() {
+    SGTT_HIP(hipStreamWaitEvent(L.c.s, L.fork_ev, 0));
+    // the previous result was copied out on the main stream before this
+    // job's fork point, so its memory may be reused from here on
+    L.held.release();
+    const int p0 = gemm_precision(prec);
+    const int r0 = prof_region(region);
+    try {
+      L.held = fp(L.c);
+    } catch (...) {
+      gemm_precision(p0);
+      prof_region(r0);
+      throw;
+    }
+    gemm_precision(p0);
+    prof_region(r0);
+    SGTT_HIP(hipEventRecord(L.join_ev, L.c.s));
+  });
+  try {
+    out_u = fu(c);
+  } catch (...) {
+    (void)L.wait();   // the side job refers to the caller's data: let it finish
+    throw;
+  }
+  if (std::exception_ptr e = L.wait()) std::rethrow_exception(e);
+  SGTT_HIP(hipStreamWaitEvent(c.s, L.join_ev, 0));
+  out_p = tt_copy(c, L.held);
 }
 
 double* Ctx::scratch(size_t n) {
