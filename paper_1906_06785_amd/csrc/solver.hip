@@ -238,8 +238,7 @@ namespace {
 
 // ---------------------------------------------------------------- operators
 // L applied to (u, p): velocity part (eq. 3.12 with eq. 4.4 and eq. 4.12)
-TT apply_velocity(sgtt_system& S, const TT& u, const TT& p) {
-  Ctx& c = S.ctx->c;
+TT apply_velocity(sgtt_system& S, const TT& u, const TT& p, Ctx& c) {
   const int r1u = u.r1, r2u = u.r2, r1p = p.r1, r2p = p.r2, k1 = S.k1, k2 = S.k2, nv = S.nvisc;
   const int R1 = 2 * r1u + k1 * r1u + r1p, R2 = (1 + nv) * r2u + k2 * r2u + r2p;
   TT o = tt_new(c, S.nt, S.nxi, S.nu, R1, R2);
@@ -264,8 +263,7 @@ TT apply_velocity(sgtt_system& S, const TT& u, const TT& p) {
   return o;
 }
 
-TT apply_pressure(sgtt_system& S, const TT& u) {
-  Ctx& c = S.ctx->c;
+TT apply_pressure(sgtt_system& S, const TT& u, Ctx& c) {
   TT o = tt_new(c, S.nt, S.nxi, S.np, u.r1, u.r2);
   SGTT_HIP(hipMemcpyAsync(o.c1, u.c1, sizeof(double) * u.n_c1(), hipMemcpyDeviceToDevice, c.s));
   SGTT_HIP(hipMemcpyAsync(o.c2, u.c2, sizeof(double) * u.n_c2(), hipMemcpyDeviceToDevice, c.s));
@@ -273,11 +271,13 @@ TT apply_pressure(sgtt_system& S, const TT& u) {
   return o;
 }
 
-Vec apply_L(sgtt_system& S, const Vec& x) {
+// on the context c (its stream and pool); the system's own by default
+Vec apply_L(sgtt_system& S, const Vec& x, Ctx* cp = nullptr) {
+  Ctx& c = cp ? *cp : S.ctx->c;
   Vec y;
   y.nc = 2;
-  y.c[0] = apply_velocity(S, x.c[0], x.c[1]);
-  y.c[1] = apply_pressure(S, x.c[0]);
+  y.c[0] = apply_velocity(S, x.c[0], x.c[1], c);
+  y.c[1] = apply_pressure(S, x.c[0], c);
   return y;
 }
 
@@ -402,6 +402,10 @@ double read_double(Ctx& c, const double* d) {
 struct Space {
   virtual Vec apply(const Vec&) = 0;
   virtual Vec precond(const Vec&) = 0;
+  // the operator on another context (stream and pool); false (and y
+  // untouched) if the space cannot run there
+  virtual bool can_apply_on() const { return false; }
+  virtual bool apply_on(const Vec&, Ctx&, Vec&) { return false; }
   virtual ~Space() = default;
 };
 
@@ -505,11 +509,32 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
     else
       zz.c[0] = one(c, 0);
   };
+  // With explicit residuals (lines 13-14 every iteration) on a pair, z_k,
+  // L z_k and s_k run on the context's solution lane (its own stream, pool
+  // and host thread) while this thread starts the next iteration's
+  // preconditioner, which needs only v_{k+1}; the lane's residual then
+  // decides whether that iteration happens.  Only when the least-squares
+  // estimate is not yet near the tolerance, so that the speculative
+  // preconditioner is rarely thrown away.
+  SideLane* lane = nullptr;
+  if (explicit_res && nc == 2 && c.side_enabled && sp.can_apply_on()) {
+    if (!c.sol) {
+      c.sol = new SideLane(c.device);
+      c.sol->c.side_enabled = true;
+    }
+    lane = c.sol;
+  }
+  Vh.reserve(maxit + 1);   // the lane reads Vh while this thread appends to it
+  Vec vh_pre;
+  bool have_pre = false;
   while (res > tol * bnorm && k < maxit) {
     ++k;
     double t0 = now_s();
     Vec vh;
-    {
+    if (have_pre) {
+      vh = std::move(vh_pre);
+      have_pre = false;
+    } else {
       RegionScope rg(inner ? RG_IN_MINV : RG_LSC);
       vh = sp.precond(V[k - 1]);
     }
@@ -591,26 +616,90 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
       if (breakdown) break;
       continue;
     }
-    z = Vec();
-    z.nc = nc;
-    solution_round(z);
-    // line 14: s_k = T(b - L z_k)
-    double t2 = now_s();
-    Vec Lz = sp.apply(z);
-    if (cnt) cnt->t_apply += now_s() - t2;
-    {
-      auto one = [&](Ctx& cc, int q) {
-        std::vector<Term> terms{Term{&b.c[q], nullptr, 1.0}, Term{&Lz.c[q], nullptr, -1.0}};
-        return tt_round_sum(cc, terms, eps, nullptr, sc + 9 + q, nullptr);
+    // lines 13-14 on the context cc: z_k = T(V^ y), s_k = T(b - L z_k) and
+    // its norm into sc[11]; returns z_k and ||s_k||
+    auto solution_and_residual = [&](Ctx& cc, Vec& zz, Vec& Lzz) {
+      zz = Vec();
+      zz.nc = nc;
+      auto zone = [&](Ctx& c2, int q) {
+        std::vector<Term> terms;
+        std::vector<const double*> cache((size_t)k * k, nullptr);
+        for (int i = 0; i < k; ++i) {
+          terms.push_back(Term{&Vh[i].c[q], y + i, 1.0});
+          for (int j = i; j < k; ++j) cache[(size_t)i * k + j] = KVh.at(q, i, j);
+        }
+        return tt_round_sum(c2, terms, eps, nullptr, nullptr, &cache);
+      };
+      if (nc == 2)
+        pair_run(cc, [&](Ctx& c2) { return zone(c2, 0); }, [&](Ctx& c2) { return zone(c2, 1); }, zz.c[0], zz.c[1]);
+      else
+        zz.c[0] = zone(cc, 0);
+      if (&cc == &c) {
+        Lzz = sp.apply(zz);
+      } else {
+        sp.apply_on(zz, cc, Lzz);
+      }
+      auto one = [&](Ctx& c2, int q) {
+        std::vector<Term> terms{Term{&b.c[q], nullptr, 1.0}, Term{&Lzz.c[q], nullptr, -1.0}};
+        return tt_round_sum(c2, terms, eps, nullptr, sc + 9 + q, nullptr);
       };
       TT sk0, sk1;
       if (nc == 2)
-        pair_run(c, [&](Ctx& cc) { return one(cc, 0); }, [&](Ctx& cc) { return one(cc, 1); }, sk0, sk1);
+        pair_run(cc, [&](Ctx& c2) { return one(c2, 0); }, [&](Ctx& c2) { return one(c2, 1); }, sk0, sk1);
       else
-        sk0 = one(c, 0);
+        sk0 = one(cc, 0);
+      scalar_op(cc.s, 0, sc + 9, nc > 1 ? sc + 10 : nullptr, sc + 11);
+      return read_double(cc, sc + 11);
+    };
+    Vec Lz;
+    if (lane) {
+      // fork: the lane's stream starts after the least-squares solve
+      SGTT_HIP(hipEventRecord(lane->fork_ev, c.s));
+      double res_lane = 0.0;
+      const int prec = gemm_precision(GP_F64);
+      gemm_precision(prec);
+      lane->post([&, prec]() {
+        SGTT_HIP(hipStreamWaitEvent(lane->c.s, lane->fork_ev, 0));
+        lane->keep.clear();   // the previous z_k, copied out before this fork
+        const int p0 = gemm_precision(prec);
+        const int r0 = prof_region(rg_sol);
+        try {
+          Vec zl, Lzl;
+          res_lane = solution_and_residual(lane->c, zl, Lzl);
+          for (int q = 0; q < nc; ++q) lane->keep.push_back(std::move(zl.c[q]));
+        } catch (...) {
+          gemm_precision(p0);
+          prof_region(r0);
+          throw;
+        }
+        gemm_precision(p0);
+        prof_region(r0);
+        SGTT_HIP(hipEventRecord(lane->join_ev, lane->c.s));
+      });
+      // the next iteration's preconditioner meanwhile, unless the estimate
+      // says this may be the last iteration of the cycle
+      try {
+        if (!breakdown && k < maxit && read_double(c, sc + 8) > 2.0 * tol * bnorm) {
+          RegionScope rg(inner ? RG_IN_MINV : RG_LSC);
+          vh_pre = sp.precond(V[k]);
+          have_pre = true;
+        }
+      } catch (...) {
+        (void)lane->wait();
+        throw;
+      }
+      if (std::exception_ptr e = lane->wait()) std::rethrow_exception(e);
+      SGTT_HIP(hipStreamWaitEvent(c.s, lane->join_ev, 0));
+      // z_k into this context's pool (the lane's copy is released by its next job)
+      z = Vec();
+      z.nc = nc;
+      for (int q = 0; q < nc; ++q) z.c[q] = tt_copy(c, lane->keep[q]);
+      res = res_lane;
+    } else {
+      double t2 = now_s();
+      res = solution_and_residual(c, z, Lz);
+      if (cnt) cnt->t_apply += now_s() - t2;
     }
-    scalar_op(c.s, 0, sc + 9, nc > 1 ? sc + 10 : nullptr, sc + 11);
-    res = read_double(c, sc + 11);
     if (cnt) {
       for (int i = 0; i < nc; ++i) {
         int r2 = V.back().c[i].r2;
@@ -629,8 +718,8 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
       cnt->hist->push_back(h);
     }
     if (cnt && cnt->verbose)
-      fprintf(stderr, "[sgtt %s] it %d  rel %.3e  ranks v=(%d,%d) z=(%d,%d) Lz=(%d,%d)\n", tag, k, res / bnorm,
-              V.back().c[0].r1, V.back().c[0].r2, z.c[0].r1, z.c[0].r2, Lz.c[0].r1, Lz.c[0].r2);
+      fprintf(stderr, "[sgtt %s] it %d  rel %.3e  ranks v=(%d,%d) z=(%d,%d)\n", tag, k, res / bnorm,
+              V.back().c[0].r1, V.back().c[0].r2, z.c[0].r1, z.c[0].r2);
     if (breakdown) break;
   }
   iters = k;
@@ -819,6 +908,11 @@ struct OuterSpace : Space {
   OuterSpace(sgtt_system& s, const PrecOpts& p, SolveCounters* c) : S(s), po(p), cnt(c) {}
   Vec apply(const Vec& x) override { return apply_L(S, x); }
   Vec precond(const Vec& x) override { return lsc_precondition(S, x, po, cnt); }
+  bool can_apply_on() const override { return true; }
+  bool apply_on(const Vec& x, Ctx& cc, Vec& y) override {
+    y = apply_L(S, x, &cc);
+    return true;
+  }
 };
 
 // exact ||b - L z|| / ||b|| in full format

@@ -4,6 +4,10 @@
 
 #include <cstddef>
 #include <functional>
+#include <thread>
+#include <mutex>
+#include <exception>
+#include <condition_variable>
 #include <map>
 #include <stdexcept>
 #include <string>
@@ -89,6 +93,9 @@ struct Ctx {
   // second stream and host thread for the pressure TT of a vector pair
   // (see pair_run); created on first use, owned by this context
   SideLane* side = nullptr;
+  // a second lane for the solver's own overlap (the solution and residual of
+  // one outer iteration beside the next iteration's preconditioner)
+  SideLane* sol = nullptr;
   int device = 0;
   bool side_enabled = true;
   // scratch (grown on demand)
@@ -108,6 +115,92 @@ struct Ctx {
   void sync();
   ~Ctx();
 };
+
+// A second context (own stream, pool and scratch) driven by its own host
+// thread: post() hands it one job at a time, wait() joins it and returns
+// the job's exception (null if none).  fork_ev / join_ev order its stream
+// against the caller's; `held` and `keep` hold results that live in its pool
+// until its next job releases them (on its own thread).
+struct SideLane {
+  Ctx c;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::function<void()> job;
+  bool has_job = false, done = true, quit = false;
+  std::exception_ptr err;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  TT held;   // the last result, in this lane's pool until the next job
+  std::vector<TT> keep;   // more results of the last job, released likewise
+
+  explicit SideLane(int device) {
+    c.device = device;
+    c.side_enabled = false;
+    SGTT_HIP(hipSetDevice(device));
+    SGTT_HIP(hipStreamCreateWithFlags(&c.s, hipStreamNonBlocking));
+    SGTT_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+    SGTT_HIP(hipEventCreateWithFlags(&join_ev, hipEventDisableTiming));
+    SGTT_HIP(hipHostMalloc((void**)&c.hint, 64 * sizeof(int), hipHostMallocDefault));
+    SGTT_HIP(hipHostMalloc((void**)&c.hdbl, 256 * sizeof(double), hipHostMallocDefault));
+    c.dint = (int*)c.pool.get(64);
+    c.dscal = c.pool.get(256);
+    th = std::thread([this, device]() {
+      (void)hipSetDevice(device);
+      std::unique_lock<std::mutex> lk(mu);
+      for (;;) {
+        cv.wait(lk, [this] { return has_job || quit; });
+        if (quit) return;
+        std::function<void()> f = std::move(job);
+        has_job = false;
+        lk.unlock();
+        std::exception_ptr e;
+        try {
+          f();
+        } catch (...) {
+          e = std::current_exception();
+        }
+        lk.lock();
+        err = e;
+        done = true;
+        cv.notify_all();
+      }
+    });
+  }
+  ~SideLane() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      quit = true;
+    }
+    cv.notify_all();
+    if (th.joinable()) th.join();
+    (void)hipStreamSynchronize(c.s);
+    held.release();
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
+    // the pool and pinned mirrors go with c; the stream last
+    hipStream_t s = c.s;
+    c.s = nullptr;
+    if (s) {
+      splitk_release(s);
+      (void)hipStreamDestroy(s);
+    }
+  }
+  void post(std::function<void()> f) {
+    std::lock_guard<std::mutex> lk(mu);
+    job = std::move(f);
+    has_job = true;
+    done = false;
+    err = nullptr;
+    cv.notify_all();
+  }
+  // waits for the posted job; returns its exception (null if none)
+  std::exception_ptr wait() {
+    std::unique_lock<std::mutex> lk(mu);
+    cv.wait(lk, [this] { return done; });
+    return err;
+  }
+};
+
 
 // Runs fu on this thread and context (its stream) and fp on the context's
 // side lane (a second stream driven by a second host thread, with its own

@@ -156,92 +156,23 @@ Ctx::~Ctx() {
 }
 
 // ---------------------------------------------------------------- side lane
-struct SideLane {
-  Ctx c;
-  std::thread th;
-  std::mutex mu;
-  std::condition_variable cv;
-  std::function<void()> job;
-  bool has_job = false, done = true, quit = false;
-  std::exception_ptr err;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
-  TT held;   // the last result, in this lane's pool until the next job
-
-  explicit SideLane(int device) {
-    c.device = device;
-    c.side_enabled = false;
-    SGTT_HIP(hipSetDevice(device));
-    SGTT_HIP(hipStreamCreateWithFlags(&c.s, hipStreamNonBlocking));
-    SGTT_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
-    SGTT_HIP(hipEventCreateWithFlags(&join_ev, hipEventDisableTiming));
-    SGTT_HIP(hipHostMalloc((void**)&c.hint, 64 * sizeof(int), hipHostMallocDefault));
-    SGTT_HIP(hipHostMalloc((void**)&c.hdbl, 256 * sizeof(double), hipHostMallocDefault));
-    c.dint = (int*)c.pool.get(64);
-    c.dscal = c.pool.get(256);
-    th = std::thread([this, device]() {
-      (void)hipSetDevice(device);
-      std::unique_lock<std::mutex> lk(mu);
-      for (;;) {
-        cv.wait(lk, [this] { return has_job || quit; });
-        if (quit) return;
-        std::function<void()> f = std::move(job);
-        has_job = false;
-        lk.unlock();
-        std::exception_ptr e;
-        try {
-          f();
-        } catch (...) {
-          e = std::current_exception();
-        }
-        lk.lock();
-        err = e;
-        done = true;
-        cv.notify_all();
-      }
-    });
-  }
-  ~SideLane() {
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      quit = true;
-    }
-    cv.notify_all();
-    if (th.joinable()) th.join();
-    (void)hipStreamSynchronize(c.s);
-    held.release();
-    if (fork_ev) (void)hipEventDestroy(fork_ev);
-    if (join_ev) (void)hipEventDestroy(join_ev);
-    // the pool and pinned mirrors go with c; the stream last
-    hipStream_t s = c.s;
-    c.s = nullptr;
-    if (s) {
-      splitk_release(s);
-      (void)hipStreamDestroy(s);
-    }
-  }
-  void post(std::function<void()> f) {
-    std::lock_guard<std::mutex> lk(mu);
-    job = std::move(f);
-    has_job = true;
-    done = false;
-    err = nullptr;
-    cv.notify_all();
-  }
-  // waits for the posted job; returns its exception (null if none)
-  std::exception_ptr wait() {
-    std::unique_lock<std::mutex> lk(mu);
-    cv.wait(lk, [this] { return done; });
-    return err;
-  }
-};
-
 void side_release(Ctx& c) {
+  delete c.sol;
+  c.sol = nullptr;
   delete c.side;
   c.side = nullptr;
 }
 
-long side_device_allocs(const Ctx& c) { return c.side ? c.side->c.pool.device_allocs() : 0; }
-long side_roundings(const Ctx& c) { return c.side ? c.side->c.roundings : 0; }
+long side_device_allocs(const Ctx& c) {
+  long n = c.side ? c.side->c.pool.device_allocs() : 0;
+  if (c.sol) n += c.sol->c.pool.device_allocs() + side_device_allocs(c.sol->c);
+  return n;
+}
+long side_roundings(const Ctx& c) {
+  long n = c.side ? c.side->c.roundings : 0;
+  if (c.sol) n += c.sol->c.roundings + side_roundings(c.sol->c);
+  return n;
+}
 
 void pair_run(Ctx& c, const std::function<TT(Ctx&)>& fu, const std::function<TT(Ctx&)>& fp, TT& out_u, TT& out_p) {
   if (!c.side_enabled) {
