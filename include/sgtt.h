@@ -182,6 +182,9 @@ typedef struct {
  * variable SGTT_SIDE_LANE=0 at context creation keeps both on the calling
  * thread and stream. */
 int sgtt_context_create(int device, void* hip_stream, sgtt_context** out);
+/* Ends the caller's use of the context.  Systems and networks made on it
+ * keep it alive: when any remain, its memory, threads and (own) stream are
+ * released with the last of them, in any order of destruction. */
 int sgtt_context_destroy(sgtt_context* ctx);
 /* Device memory of a context.  The library takes temporaries from a
  * stream-ordered caching pool.  sgtt_context_reserve allocates an arena of

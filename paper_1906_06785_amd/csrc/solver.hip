@@ -31,6 +31,11 @@ struct sgtt_context {
   double* scratch = nullptr;   // this device's allocation-free scratch (device address)
   std::string err;
   Ctx c;
+  // systems and networks made on this context and not yet destroyed; a
+  // context destroyed before them is released when the last one goes
+  std::mutex life_mu;
+  int children = 0;
+  bool closing = false;
 };
 
 namespace {
@@ -524,7 +529,8 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
     }
     lane = c.sol;
   }
-  Vh.reserve(maxit + 1);   // the lane reads Vh while this thread appends to it
+  Vh.reserve(maxit + 1);   // the lane reads V and Vh: their storage must not move
+  V.reserve(maxit + 2);
   Vec vh_pre;
   bool have_pre = false;
   while (res > tol * bnorm && k < maxit) {
@@ -545,16 +551,22 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
     Vec x = vec_round(c, sp.apply(vh), eps_k, nullptr, nullptr);
     prof_region(rg_mgs);
     Vh.push_back(std::move(vh));
-    // Gram blocks of the preconditioned basis (for the solution sum)
+    // Gram blocks of the preconditioned basis (for the solution sum); with
+    // the solution lane they are computed there, only their memory is taken
+    // here (from this context's pool, before the lane's fork point)
+    auto vh_grams = [&](Ctx& cc) {
+      for (int q = 0; q < nc; ++q)
+        for (int i = 0; i < k; ++i) {
+          const TT& ti = Vh[i].c[q];
+          const TT& tj = Vh[k - 1].c[q];
+          size_t wsn = gram_ws_doubles(ti.n3, ti.r2, tj.r2);
+          gram(cc.s, ti.n3, ti.r2, tj.r2, ti.c3, ti.r2, 1, tj.c3, tj.r2, 1, KVh.at(q, i, k - 1), cc.scratch(wsn), wsn);
+        }
+    };
     for (int q = 0; q < nc; ++q)
-      for (int i = 0; i < k; ++i) {
-        double*& slot = KVh.at(q, i, k - 1);
-        const TT& ti = Vh[i].c[q];
-        const TT& tj = Vh[k - 1].c[q];
-        slot = c.pool.get((size_t)ti.r2 * tj.r2);
-        size_t wsn = gram_ws_doubles(ti.n3, ti.r2, tj.r2);
-        gram(c.s, ti.n3, ti.r2, tj.r2, ti.c3, ti.r2, 1, tj.c3, tj.r2, 1, slot, c.scratch(wsn), wsn);
-      }
+      for (int i = 0; i < k; ++i)
+        KVh.at(q, i, k - 1) = c.pool.get((size_t)Vh[i].c[q].r2 * Vh[k - 1].c[q].r2);
+    if (!lane) vh_grams(c);
     // lines 6-9: modified Gram-Schmidt coefficients from <x, v_i> and the
     // Gram matrix of the basis (exact in exact arithmetic)
     for (int i = 0; i < k; ++i) {
@@ -587,14 +599,26 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
     scalar_op(c.s, 0, sc + 6, nc > 1 ? sc + 7 : nullptr, H + (size_t)(k - 1) * ld + k);   // h_{k+1,k}
     double hk = read_double(c, H + (size_t)(k - 1) * ld + k);
     bool breakdown = !(hk > 1e-14 * beta);
-    if (!breakdown && k < maxit) {
-      V.push_back(vec_scale3(c, std::move(vn), H + (size_t)(k - 1) * ld + k, 1));
+    // Gram entries of the new basis vector (used by the next iteration's
+    // Gram-Schmidt); on the solution lane when there is one
+    const bool grow = !breakdown && k < maxit;
+    auto new_basis_dots = [&](Ctx& cc) {
       for (int i = 0; i <= k; ++i) {
-        dot_cached(V[i], V[k], GV + (size_t)i * ld + k, KV, i, k);
+        for (int q = 0; q < nc; ++q)
+          tt_dot(cc, V[i].c[q], V[k].c[q], GV + (size_t)i * ld + k, q > 0, KV.at(q, i, k));
         if (i < k)
           SGTT_HIP(hipMemcpyAsync(GV + (size_t)k * ld + i, GV + (size_t)i * ld + k, sizeof(double),
-                                  hipMemcpyDeviceToDevice, c.s));
+                                  hipMemcpyDeviceToDevice, cc.s));
       }
+    };
+    if (grow) {
+      V.push_back(vec_scale3(c, std::move(vn), H + (size_t)(k - 1) * ld + k, 1));
+      for (int i = 0; i <= k; ++i)
+        for (int q = 0; q < nc; ++q) {
+          double*& slot = KV.at(q, i, k);
+          if (!slot) slot = c.pool.get((size_t)V[i].c[q].r2 * V[k].c[q].r2);
+        }
+      if (!lane) new_basis_dots(c);
     }
     // lines 12-13: least squares, z_k = T(V^ y)
     prof_region(rg_sol);
@@ -664,6 +688,11 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
         const int p0 = gemm_precision(prec);
         const int r0 = prof_region(rg_sol);
         try {
+          {
+            GemmPrecisionScope f64(GP_F64);   // Gram entries stay FP64
+            vh_grams(lane->c);
+            if (grow) new_basis_dots(lane->c);
+          }
           Vec zl, Lzl;
           res_lane = solution_and_residual(lane->c, zl, Lzl);
           for (int q = 0; q < nc; ++q) lane->keep.push_back(std::move(zl.c[q]));
@@ -1228,8 +1257,8 @@ int sgtt_context_memory(const sgtt_context* ctx, sgtt_memory_info* out) {
   return SGTT_OK;
 }
 
-int sgtt_context_destroy(sgtt_context* ctx) {
-  if (!ctx) return SGTT_E_INVALID;
+namespace {
+void context_finalize(sgtt_context* ctx) {
   (void)hipStreamSynchronize(ctx->c.s);
   hipStream_t s = ctx->c.s;
   bool own = ctx->own_stream;
@@ -1238,6 +1267,34 @@ int sgtt_context_destroy(sgtt_context* ctx) {
     splitk_release(s);
     (void)hipStreamDestroy(s);
   }
+}
+void context_add_child(sgtt_context* ctx) {
+  std::lock_guard<std::mutex> lk(ctx->life_mu);
+  ++ctx->children;
+}
+// a system or network of ctx is gone; releases a closing context with it
+void context_release_child(sgtt_context* ctx) {
+  bool fin;
+  {
+    std::lock_guard<std::mutex> lk(ctx->life_mu);
+    fin = --ctx->children == 0 && ctx->closing;
+  }
+  if (fin) context_finalize(ctx);
+}
+}  // namespace
+
+int sgtt_context_destroy(sgtt_context* ctx) {
+  if (!ctx) return SGTT_E_INVALID;
+  {
+    std::lock_guard<std::mutex> lk(ctx->life_mu);
+    if (ctx->children > 0) {
+      // systems or networks still refer to it: release it with the last one
+      ctx->closing = true;
+      (void)hipStreamSynchronize(ctx->c.s);
+      return SGTT_OK;
+    }
+  }
+  context_finalize(ctx);
   return SGTT_OK;
 }
 
@@ -1508,13 +1565,18 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
 
 int sgtt_assemble(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_tt_pair* prior, sgtt_system** out) {
   if (!ctx || !desc || !out) return SGTT_E_INVALID;
-  return guarded(ctx, [&]() { *out = assemble_internal(ctx, desc, prior); });
+  return guarded(ctx, [&]() {
+    *out = assemble_internal(ctx, desc, prior);
+    context_add_child(ctx);
+  });
 }
 
 int sgtt_system_destroy(sgtt_system* sys) {
   if (!sys) return SGTT_E_INVALID;
-  (void)hipStreamSynchronize(sys->ctx->c.s);
+  sgtt_context* ctx = sys->ctx;
+  (void)hipStreamSynchronize(ctx->c.s);
   delete sys;
+  context_release_child(ctx);
   return SGTT_OK;
 }
 
@@ -2090,6 +2152,7 @@ int sgtt_mlp_create(sgtt_context* ctx, int n, int width, long capacity, unsigned
     h->ctx = ctx;
     h->m.reset(mlp_create(ctx->c.s, n, width, capacity, seed));
     *out = h.release();
+    context_add_child(ctx);
   });
 }
 
@@ -2100,8 +2163,10 @@ int sgtt_mlp_destroy(sgtt_mlp* m) {
     if (m->ctx) m->ctx->err = "network still attached to (or collecting for) a system";
     return SGTT_E_INVALID;
   }
-  if (m->ctx) (void)hipStreamSynchronize(m->ctx->c.s);
+  sgtt_context* ctx = m->ctx;
+  if (ctx) (void)hipStreamSynchronize(ctx->c.s);
   delete m;
+  if (ctx) context_release_child(ctx);
   return SGTT_OK;
 }
 
