@@ -357,7 +357,7 @@ def batch_main(args):
 # kernel classes reported against their rooflines, with what they stand for
 ROOFLINE_CLASSES = {
     "k_spmm": "CSR sparse products of the operator (k_spmm, k_spmm_short<32>)",
-    "k_ell_spmm": "ELL mass product of the time-stepped mean solve (k_ell_spmm<32>)",
+    "k_ell_spmm": "ELL mass product of the time-stepped mean solve (k_ell_grouped: row groups staged in LDS)",
     "k_gram": "tall-skinny core-3 Gram products of truncations and inner products (k_gemm<0, 1>)",
     "k_proj": "projections of core 3 onto the kept ranks (k_gemm<0, 2>)",
     "k_gemm": "other FP64 products: full-tensor expansion, small core products (k_gemm<0, 0>)",

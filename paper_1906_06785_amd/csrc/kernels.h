@@ -19,7 +19,7 @@ namespace sgtt {
 enum KernelClass {
   KC_GEMM = 0, KC_GEMM_PTR, KC_SPMM, KC_BCR, KC_TRUNC, KC_REDUCE, KC_OTHER, KC_GEMM_LOWP,
   KC_GRAM,   // tall-skinny Gram products (truncations, inner products): k_gemm<0, 1>
-  KC_ELL,    // the ELL mass product of the time-stepped mean solve: k_ell_spmm<32>
+  KC_ELL,    // the ELL mass product of the time-stepped mean solve: k_ell_grouped
   KC_PROJ,   // projections of core 3 onto kept ranks (truncations): k_gemm<0, 2>
   KC_COUNT
 };
@@ -139,6 +139,8 @@ struct BlockCopy {
 void block_copy_batched(hipStream_t s, const BlockCopy* d_descs, int n, int max_rows, int max_cols);
 void transpose_copy_batched(hipStream_t s, int batch, int rows, int cols, const double* src, long sbatch, long lds,
                             double* dst, long dbatch, long ldd);
+void transpose_widen_batched(hipStream_t s, int batch, int rows, int cols, const float* src, long sbatch, long lds,
+                             double* dst, long dbatch, long ldd);
 
 // CSR SpMM over the space index with several value arrays sharing a pattern
 // and `ncomp` velocity components:
@@ -153,17 +155,48 @@ void spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* rowp
           double* y, int ldy, int ycol0, int yvstep, double alpha, double beta = 0.0, int max_row_nnz = 0);
 
 // The same product for a square matrix with one value array in padded-row
-// (ELL) form: row r has ELL_WIDTH entries at ecol/eval[r * ELL_WIDTH ...],
-// padded with (column r, value 0); rows of the input x are at
-// (c*ics + col)*ldx + xcol0, of y at (c*ocs + r)*ldy + ycol0.
-// y = alpha * A x + beta * y.
+// (ELL) form: row r has ELL_WIDTH value slots at eval[r * ELL_WIDTH ...], its
+// entries first, zeros after them.  The rows are cut into groups of
+// consecutive rows (ell_groups_build) whose distinct input rows are staged in
+// LDS; rows of the input x are at (c*ics + col)*ldx + xcol0, of y at
+// (c*ocs + r)*ldy + ycol0.  y = alpha * A x + beta * y.
 constexpr int ELL_WIDTH = 32;
-void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const double* eval, long nnz,
+constexpr int ELL_GROUP_ROWS = 16;   // rows per group, at most
+constexpr int ELL_GROUP_UMAX = 96;   // distinct input rows per group, at most
+constexpr int ELL_CHUNK = 16;        // entries read per step
+// Group g covers rows row0[g] .. row0[g+1]-1 and reads input rows
+// ucols[uptr[g] .. uptr[g+1]-1] (ascending); lidx[r * ELL_WIDTH + q] is the
+// position of row r's q-th entry in its group's list (0 past the entries),
+// rlen[r] the row's entry count rounded up to a multiple of ELL_CHUNK.
+struct EllGroups {
+  int ngroups = 0;
+  int umax = 0;                  // largest distinct-row count of a group
+  int* row0 = nullptr;           // device, ngroups + 1
+  int* uptr = nullptr;           // device, ngroups + 1
+  int* ucols = nullptr;          // device
+  int* lidx = nullptr;           // device, nrows * ELL_WIDTH
+  int* rlen = nullptr;           // device, nrows
+};
+// host: greedy groups of a CSR pattern (a row joins the current group while
+// the group has fewer than ELL_GROUP_ROWS rows and at most ELL_GROUP_UMAX
+// distinct columns with it); throws when a row has more than ELL_WIDTH entries
+void ell_groups_build(int nrows, const int* rowptr, const int* col, std::vector<int>& row0, std::vector<int>& uptr,
+                      std::vector<int>& ucols, std::vector<int>& lidx, std::vector<int>& rlen, int& umax);
+void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const EllGroups& G, const double* eval, long nnz,
               const double* x, int ldx, int xcol0, int ncols, double* y, int ldy, int ycol0, double alpha,
               double beta);
 // the same product in FP32 (values, input and output)
-void ell_spmm32(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const float* eval, long nnz,
-                const float* x, int ldx, int xcol0, int ncols, float* y, int ldy, int ycol0, float alpha, float beta);
+void ell_spmm32(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const EllGroups& G, const float* eval,
+                long nnz, const float* x, int ldx, int xcol0, int ncols, float* y, int ldy, int ycol0, float alpha,
+                float beta);
+// C = A B (m x n) with output column j stored at C[i*sCi + (j / csplit)*sCt +
+// j % csplit]: a column index (t, xi) of csplit values of xi written as one
+// block per t.  gemm_csplit computes at the current product precision,
+// gemm_csplit_f32out in FP64 rounded to FP32 on the store.
+void gemm_csplit(hipStream_t s, int m, int n, int k, const double* A, long sAi, long sAk, const double* B, long sBk,
+                 long sBj, double* C, long sCi, int csplit, long sCt);
+void gemm_csplit_f32out(hipStream_t s, int m, int n, int k, const double* A, long sAi, long sAk, const double* B,
+                        long sBk, long sBj, float* C, long sCi, int csplit, long sCt);
 // C (float, m x n) = A B computed in FP64 on the matrix cores and rounded
 // to FP32 on the store (strides as for gemm, batch 1)
 void gemm_f32out(hipStream_t s, int m, int n, int k, const double* A, long sAi, long sAk, const double* B, long sBk,

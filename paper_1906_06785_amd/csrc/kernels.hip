@@ -213,10 +213,13 @@ __device__ __forceinline__ short to_bf16(float x) {
 // round the FP64 operands when they are staged and accumulate in FP32.
 // K is staged through LDS in slices of 16, the next slice prefetched into
 // registers while the current one is consumed.
-template <int PREC, typename CT = double>
+// With CSPLIT the output column j is stored at (j / csplit) * sCt +
+// (j % csplit) * sCj: a column index (t, xi) laid out as blocks per t.
+template <int PREC, typename CT = double, bool CSPLIT = false>
 __device__ __forceinline__ void gemm_core(int m, int n, long kb, double alpha, const double* __restrict__ A, long sAi,
                                           long sAk, const double* __restrict__ B, long sBk, long sBj, double beta,
-                                          CT* __restrict__ C, long sCi, long sCj, int i0, int j0) {
+                                          CT* __restrict__ C, long sCi, long sCj, int i0, int j0, int csplit = 1,
+                                          long sCt = 0) {
   typedef typename std::conditional<PREC == GP_F64, double, float>::type st_t;
   typedef typename std::conditional<PREC == GP_F64, dbl4, flt4>::type acc_t;
   __shared__ st_t As[TK][TM + 1];
@@ -296,7 +299,7 @@ __device__ __forceinline__ void gemm_core(int m, int n, long kb, double alpha, c
       for (int tc = 0; tc < 2; ++tc) {
         const long gj = j0 + wc + tc * 16 + lr;
         if (gj >= n) continue;
-        CT* cp = C + gi * sCi + gj * sCj;
+        CT* cp = C + gi * sCi + (CSPLIT ? (gj / csplit) * sCt + (gj % csplit) * sCj : gj * sCj);
         double val = alpha * (double)acc[tr][tc][v];
         if (beta != 0.0) val += beta * (double)(*cp);
         *cp = (CT)val;
@@ -330,6 +333,16 @@ __global__ __launch_bounds__(256) void k_gemm_f32out(int m, int n, int k, const 
                                                      long sAk, const double* __restrict__ B, long sBk, long sBj,
                                                      float* __restrict__ C, long sCi, long sCj) {
   gemm_core<GP_F64, float>(m, n, k, 1.0, A, sAi, sAk, B, sBk, sBj, 0.0, C, sCi, sCj, blockIdx.y * TM, blockIdx.x * TN);
+}
+
+// C = A B with the output columns split into blocks (see gemm_core): the
+// full-tensor expansion written time-major for the time-stepped mean solve
+template <int PREC, typename CT>
+__global__ __launch_bounds__(256) void k_gemm_csplit(int m, int n, int k, const double* __restrict__ A, long sAi,
+                                                     long sAk, const double* __restrict__ B, long sBk, long sBj,
+                                                     CT* __restrict__ C, long sCi, int csplit, long sCt) {
+  gemm_core<PREC, CT, true>(m, n, k, 1.0, A, sAi, sAk, B, sBk, sBj, 0.0, C, sCi, 1, blockIdx.y * TM, blockIdx.x * TN,
+                            csplit, sCt);
 }
 
 template <int PREC>
@@ -598,64 +611,97 @@ __global__ __launch_bounds__(256) void k_spmm_short(int nrows, int ics, int ocs,
   }
 }
 
-// Padded-row (ELL) SpMM for one value array: row r holds EW entries at
-// ecol/eval[r*EW ...], padded with (column r, value 0).  A wave computes one row for up to 64
-// columns; the row's entries sit one per lane and all of its input loads are
-// issued together.  Workgroups are remapped so that each XCD (workgroup ids
-// are dealt round-robin over the 8 XCDs) takes a contiguous range of rows:
-// neighbouring rows share most of their inputs, which then stay in that
-// XCD's L2.  The grid is a multiple of 8 workgroups.
-template <int EW, typename T>
-__global__ __launch_bounds__(256) void k_ell_spmm(int nrows, int ics, int ocs,
-                                                  const int* __restrict__ ecol, const T* __restrict__ eval,
-                                                  const T* __restrict__ x, int ldx, int xcol0, int ncols,
-                                                  T* __restrict__ y, int ldy, int ycol0, T alpha, T beta) {
-  static_assert(EW <= WAVE, "one entry per lane");
+// Padded-row (ELL) SpMM over row groups.  A workgroup takes one group of
+// consecutive rows (at most ELL_GROUP_ROWS) and first copies the group's
+// distinct input rows (at most ELL_GROUP_UMAX, listed in ascending order) into
+// LDS with coalesced loads: neighbouring rows share most of their inputs, so
+// an input row leaves L2 once per group instead of once per entry that uses
+// it.  Each wave then forms rows wave, wave + 4, ... of the group with one
+// lane per output column.  A row's entries (LDS positions and values) are
+// wave-uniform and read with scalar loads, ELL_CHUNK at a time: the row
+// length is rounded up to whole chunks (the extra slots hold value 0 and a
+// valid position), so a chunk's LDS reads are issued together with no
+// branches between them.  Columns are processed in chunks of cw (the LDS holds
+// umax x cw values).  Workgroups are remapped so that each XCD (ids are dealt
+// round-robin over the 8 XCDs) takes a contiguous range of groups; the grid
+// is a multiple of 8.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ell_grouped(int ngroups, int ics, int ocs, const int* __restrict__ row0,
+                                                     const int* __restrict__ uptr, const int* __restrict__ ucols,
+                                                     const int* __restrict__ lidx, const int* __restrict__ rlen,
+                                                     const T* __restrict__ eval, const T* __restrict__ x, int ldx,
+                                                     int xcol0, int ncols, int cw, T* __restrict__ y, int ldy,
+                                                     int ycol0, T alpha, T beta) {
+  constexpr int RPW = ELL_GROUP_ROWS / 4;   // rows per wave
+  constexpr int UNR = 24;                   // staging loads in flight per thread
+  static_assert(ELL_GROUP_ROWS % 4 == 0 && ELL_WIDTH % ELL_CHUNK == 0, "group shape");
+  extern __shared__ __align__(16) unsigned char ell_smem[];
+  T* xs = reinterpret_cast<T*>(ell_smem);
+  __shared__ int us[ELL_GROUP_UMAX];
   const unsigned per = gridDim.x / 8;
-  const unsigned lb = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  const long r = (long)lb * (blockDim.x / WAVE) + wave;
+  const unsigned g = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (g >= (unsigned)ngroups) return;   // whole workgroup: before any barrier
   const int c = blockIdx.y;
-  if (r >= nrows) return;
-  static_assert(EW == 32, "entry groups of 16, 9 and 7");
-  const int my_col = lane < EW ? ecol[r * EW + lane] : 0;
-  const T my_val = lane < EW ? eval[r * EW + lane] : (T)0;
-  // entries past the row's last one are padding (column r, value 0); the
-  // row length decides, uniformly per wave, how many entry groups load
-  const unsigned long long real = __ballot(lane < EW && !(my_col == (int)r && my_val == (T)0));
-  const int n = real ? 64 - __clzll(real) : 0;
+  const int ra = row0[g], rb = row0[g + 1];
+  const int ua = uptr[g], U = uptr[g + 1] - ua;
+  // the wave index as a scalar, so that row addresses (and the entry loads
+  // through them) are uniform
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x % WAVE;
+  for (int u = threadIdx.x; u < U; u += blockDim.x) us[u] = ucols[ua + u];
+  __syncthreads();
   const T* xb = x + (long)c * ics * ldx + xcol0;
-  T* yb = y + ((long)c * ocs + r) * ldy + ycol0;
-  for (int j0 = 0; j0 < ncols; j0 += WAVE) {
-    const int j = j0 + lane;
-    const bool act = j < ncols;
-    const int jc = act ? j : ncols - 1;   // idle lanes read a valid column
-    const T yo = (act && beta != (T)0) ? yb[j] : (T)0;
-    // within a group every load is valid (padding points at row r), so none
-    // is predicated and the group's loads are issued back to back
-    T acc = 0;
-    {
-      T xv[16];
+  for (int j0 = 0; j0 < ncols; j0 += cw) {
+    const int w = min(cw, ncols - j0);
+    if (j0 > 0) __syncthreads();   // every read of the previous chunk is done
+    const int jc = lane < w ? lane : w - 1;   // idle lanes read a valid value
+    // this chunk's old outputs, loaded now so that their latency overlaps the
+    // staging below
+    T yo[RPW];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) xv[q] = xb[(long)__builtin_amdgcn_readlane(my_col, q) * ldx + jc];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc = fma(readlane_val(my_val, q), xv[q], acc);
+    for (int i = 0; i < RPW; ++i) {
+      const int r = ra + wave + 4 * i;
+      yo[i] = (r < rb && lane < w && beta != (T)0) ? y[((long)c * ocs + r) * ldy + ycol0 + j0 + jc] : (T)0;
     }
-    if (n > 16) {
-      T xv[9];
+    // element i of the U x w chunk is (i / w, i % w); thread t takes
+    // i = t, t + 256, ..., with the quotient and remainder advanced in steps;
+    // up to UNR loads per thread are issued before the first LDS store
+    const int tot = U * w;
+    const int du = 256 / w, dj = 256 - du * w;
+    int u = threadIdx.x / w, j = threadIdx.x - u * w;
+    for (int i0 = threadIdx.x; i0 < tot; i0 += 256 * UNR) {
+      T v[UNR];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) xv[q] = xb[(long)__builtin_amdgcn_readlane(my_col, 16 + q) * ldx + jc];
+      for (int k = 0; k < UNR; ++k) {
+        v[k] = i0 + 256 * k < tot ? xb[(long)us[u] * ldx + j0 + j] : (T)0;
+        j += dj;
+        u += du;
+        if (j >= w) {
+          j -= w;
+          ++u;
+        }
+      }
 #pragma unroll
-      for (int q = 0; q < 9; ++q) acc = fma(readlane_val(my_val, 16 + q), xv[q], acc);
+      for (int k = 0; k < UNR; ++k)
+        if (i0 + 256 * k < tot) xs[i0 + 256 * k] = v[k];
     }
-    if (n > 25) {
-      T xv[7];
+    __syncthreads();
 #pragma unroll
-      for (int q = 0; q < 7; ++q) xv[q] = xb[(long)__builtin_amdgcn_readlane(my_col, 25 + q) * ldx + jc];
+    for (int i = 0; i < RPW; ++i) {
+      const int r = ra + wave + 4 * i;
+      if (r >= rb) break;   // uniform per wave
+      const int n = rlen[r];
+      const int* lr = lidx + (long)r * ELL_WIDTH;
+      const T* vr = eval + (long)r * ELL_WIDTH;
+      T acc = 0;
+      for (int k = 0; k < n; k += ELL_CHUNK) {
+        T xv[ELL_CHUNK];
 #pragma unroll
-      for (int q = 0; q < 7; ++q) acc = fma(readlane_val(my_val, 25 + q), xv[q], acc);
+        for (int q = 0; q < ELL_CHUNK; ++q) xv[q] = xs[lr[k + q] * w + jc];
+#pragma unroll
+        for (int q = 0; q < ELL_CHUNK; ++q) acc = fma(vr[k + q], xv[q], acc);
+      }
+      if (lane < w) y[((long)c * ocs + r) * ldy + ycol0 + j0 + lane] = alpha * acc + beta * yo[i];
     }
-    if (act) yb[j] = alpha * acc + beta * yo;
   }
 }
 
@@ -2295,6 +2341,27 @@ void gemm_f32out(hipStream_t s, int m, int n, int k, const double* A, long sAi, 
                      C, sCi, sCj);
 }
 
+void gemm_csplit(hipStream_t s, int m, int n, int k, const double* A, long sAi, long sAk, const double* B, long sBk,
+                 long sBj, double* C, long sCi, int csplit, long sCt) {
+  if (m <= 0 || n <= 0) return;
+  if (csplit <= 0) throw std::runtime_error("gemm_csplit: column block must be positive");
+  ProfScope ps(gemm_class(), s, 8.0 * ((double)m * k + (double)k * n + (double)m * n), 2.0 * m * n * (double)k);
+  auto kern = g_gemm_prec == GP_F32 ? k_gemm_csplit<GP_F32, double>
+                                    : (g_gemm_prec == GP_BF16 ? k_gemm_csplit<GP_BF16, double>
+                                                              : k_gemm_csplit<GP_F64, double>);
+  hipLaunchKernelGGL(kern, dim3(cdiv(n, TN), cdiv(m, TM)), dim3(256), 0, s, m, n, k, A, sAi, sAk, B, sBk, sBj, C, sCi,
+                     csplit, sCt);
+}
+
+void gemm_csplit_f32out(hipStream_t s, int m, int n, int k, const double* A, long sAi, long sAk, const double* B,
+                        long sBk, long sBj, float* C, long sCi, int csplit, long sCt) {
+  if (m <= 0 || n <= 0) return;
+  if (csplit <= 0) throw std::runtime_error("gemm_csplit: column block must be positive");
+  ProfScope ps(KC_GEMM, s, 8.0 * ((double)m * k + (double)k * n) + 4.0 * m * (double)n, 2.0 * m * n * (double)k);
+  hipLaunchKernelGGL((k_gemm_csplit<GP_F64, float>), dim3(cdiv(n, TN), cdiv(m, TM)), dim3(256), 0, s, m, n, k, A, sAi,
+                     sAk, B, sBk, sBj, C, sCi, csplit, sCt);
+}
+
 void gram(hipStream_t s, long rows, int nx, int ny, const double* X, long sXr, long sXc, const double* Y, long sYr,
           long sYc, double* out, double* ws, size_t ws_doubles) {
   GemmPrecisionScope f64(GP_F64);   // Grams decide truncations: always FP64
@@ -2360,37 +2427,90 @@ void transpose_copy(hipStream_t s, int rows, int cols, const double* src, long l
   transpose_copy_batched(s, 1, rows, cols, src, 0, lds, dst, 0, ldd);
 }
 
-void transpose_widen(hipStream_t s, int rows, int cols, const float* src, long lds, double* dst, long ldd) {
-  if (rows <= 0 || cols <= 0) return;
+void transpose_widen_batched(hipStream_t s, int batch, int rows, int cols, const float* src, long sbatch, long lds,
+                             double* dst, long dbatch, long ldd) {
+  if (batch <= 0 || rows <= 0 || cols <= 0) return;
+  if (batch > 65535) throw std::runtime_error("transpose_widen_batched: batch too large");
   const unsigned gx = (unsigned)cdiv(cols, 32);
-  const unsigned gy = (unsigned)std::min<long>(cdiv(rows, 32), std::max<long>(1, 65536 / (long)gx));
-  hipLaunchKernelGGL((k_transpose_copy<float, double>), dim3(gx, std::max(1u, std::min(gy, 65535u)), 1), dim3(32, 8),
-                     0, s, rows, cols, src, lds, 0L, dst, ldd, 0L);
+  const unsigned gy = (unsigned)std::min<long>(cdiv(rows, 32), std::max<long>(1, 65536 / ((long)gx * batch)));
+  hipLaunchKernelGGL((k_transpose_copy<float, double>), dim3(gx, std::max(1u, std::min(gy, 65535u)), batch),
+                     dim3(32, 8), 0, s, rows, cols, src, lds, sbatch, dst, ldd, dbatch);
 }
 
-void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const double* eval, long nnz,
+void transpose_widen(hipStream_t s, int rows, int cols, const float* src, long lds, double* dst, long ldd) {
+  transpose_widen_batched(s, 1, rows, cols, src, 0, lds, dst, 0, ldd);
+}
+
+void ell_groups_build(int nrows, const int* rowptr, const int* col, std::vector<int>& row0, std::vector<int>& uptr,
+                      std::vector<int>& ucols, std::vector<int>& lidx, std::vector<int>& rlen, int& umax) {
+  row0.assign(1, 0);
+  uptr.assign(1, 0);
+  ucols.clear();
+  lidx.assign((size_t)nrows * ELL_WIDTH, 0);
+  rlen.assign(nrows, 0);
+  umax = 0;
+  std::vector<int> cur, next;
+  int r = 0;
+  while (r < nrows) {
+    const int g0 = r;
+    cur.clear();
+    while (r < nrows && r - g0 < ELL_GROUP_ROWS) {
+      if (rowptr[r + 1] - rowptr[r] > ELL_WIDTH) throw std::runtime_error("row longer than the padded width");
+      next = cur;
+      next.insert(next.end(), col + rowptr[r], col + rowptr[r + 1]);
+      std::sort(next.begin(), next.end());
+      next.erase(std::unique(next.begin(), next.end()), next.end());
+      if ((int)next.size() > ELL_GROUP_UMAX) break;   // a new group starts at r
+      cur.swap(next);
+      ++r;
+    }
+    for (int q = g0; q < r; ++q) {
+      const int n = rowptr[q + 1] - rowptr[q];
+      rlen[q] = (n + ELL_CHUNK - 1) / ELL_CHUNK * ELL_CHUNK;
+      for (int t = 0; t < n; ++t)
+        lidx[(size_t)q * ELL_WIDTH + t] =
+            (int)(std::lower_bound(cur.begin(), cur.end(), col[rowptr[q] + t]) - cur.begin());
+    }
+    ucols.insert(ucols.end(), cur.begin(), cur.end());
+    row0.push_back(r);
+    uptr.push_back((int)ucols.size());
+    umax = std::max(umax, (int)cur.size());
+  }
+}
+
+namespace {
+template <typename T>
+void ell_launch(hipStream_t s, int ncomp, int ics, int ocs, const EllGroups& G, const T* eval, const T* x, int ldx,
+                int xcol0, int ncols, T* y, int ldy, int ycol0, T alpha, T beta) {
+  // the chunk width keeps the staged rows within 64 KB of LDS
+  const int cw = std::max(1, std::min(WAVE, (int)(65536 / (sizeof(T) * std::max(1, G.umax)))));
+  const size_t lds = sizeof(T) * (size_t)std::max(1, G.umax) * std::min(cw, ncols);
+  const unsigned nb = 8 * cdiv(G.ngroups, 8);
+  hipLaunchKernelGGL((k_ell_grouped<T>), dim3(nb, ncomp), dim3(256), lds, s, G.ngroups, ics, ocs, G.row0, G.uptr,
+                     G.ucols, G.lidx, G.rlen, eval, x, ldx, xcol0, ncols, cw, y, ldy, ycol0, alpha, beta);
+}
+}  // namespace
+
+void ell_spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const EllGroups& G, const double* eval, long nnz,
               const double* x, int ldx, int xcol0, int ncols, double* y, int ldy, int ycol0, double alpha,
               double beta) {
-  if (nrows <= 0 || ncols <= 0 || ncomp <= 0) return;
+  if (nrows <= 0 || ncols <= 0 || ncomp <= 0 || G.ngroups <= 0) return;
   // algorithmic: the matrix's nonzeros (column index and value) once, the
   // inputs once, the outputs written (and read when accumulated)
   const double by = 12.0 * nnz + 8.0 * ncomp * ((double)nrows * ncols) +
                     8.0 * ncomp * (double)nrows * ncols * (beta != 0.0 ? 2.0 : 1.0);
   ProfScope ps(KC_ELL, s, by, 2.0 * (double)nnz * ncomp * ncols);
-  const unsigned nb = 8 * cdiv(cdiv(nrows, 4), 8);
-  hipLaunchKernelGGL((k_ell_spmm<ELL_WIDTH, double>), dim3(nb, ncomp), dim3(256), 0, s, nrows, ics, ocs, ecol, eval, x,
-                     ldx, xcol0, ncols, y, ldy, ycol0, alpha, beta);
+  ell_launch<double>(s, ncomp, ics, ocs, G, eval, x, ldx, xcol0, ncols, y, ldy, ycol0, alpha, beta);
 }
 
-void ell_spmm32(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* ecol, const float* eval, long nnz,
-                const float* x, int ldx, int xcol0, int ncols, float* y, int ldy, int ycol0, float alpha, float beta) {
-  if (nrows <= 0 || ncols <= 0 || ncomp <= 0) return;
+void ell_spmm32(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const EllGroups& G, const float* eval,
+                long nnz, const float* x, int ldx, int xcol0, int ncols, float* y, int ldy, int ycol0, float alpha,
+                float beta) {
+  if (nrows <= 0 || ncols <= 0 || ncomp <= 0 || G.ngroups <= 0) return;
   const double by = 8.0 * nnz + 4.0 * ncomp * ((double)nrows * ncols) +
                     4.0 * ncomp * (double)nrows * ncols * (beta != 0.0f ? 2.0 : 1.0);
   ProfScope ps(KC_ELL, s, by, 2.0 * (double)nnz * ncomp * ncols);
-  const unsigned nb = 8 * cdiv(cdiv(nrows, 4), 8);
-  hipLaunchKernelGGL((k_ell_spmm<ELL_WIDTH, float>), dim3(nb, ncomp), dim3(256), 0, s, nrows, ics, ocs, ecol, eval, x,
-                     ldx, xcol0, ncols, y, ldy, ycol0, alpha, beta);
+  ell_launch<float>(s, ncomp, ics, ocs, G, eval, x, ldx, xcol0, ncols, y, ldy, ycol0, alpha, beta);
 }
 
 void spmm(hipStream_t s, int nrows, int ncomp, int ics, int ocs, const int* rowptr, const int* col, const double* vals,

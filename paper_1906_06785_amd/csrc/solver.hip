@@ -206,7 +206,7 @@ struct sgtt_system {
   double* Hw = nullptr;    // k1 x k2 x nxi x nxi
   double* omega = nullptr; // nt x k2 (mean-mode time factors)
   BcrDev Fbt, Xbt;         // F_avg and X = B M*^-1 B^T (block cyclic reduction)
-  int* Me_col = nullptr;   // M in padded-row form (time coupling of the mean solve)
+  EllGroups Me_groups;     // M in padded-row form (time coupling of the mean solve)
   double* Me_val = nullptr;
   long Me_nnz = 0;         // nonzeros of M (its padded rows hold 32)
   float* Me_val32 = nullptr;   // the same values in FP32 (reduced-precision mean solve)
@@ -233,7 +233,8 @@ struct sgtt_system {
     Mpinv.free_all();
     free_bcr(Fbt);
     free_bcr(Xbt);
-    for (void* p : {(void*)Me_col, (void*)Me_val, (void*)Me_val32})
+    for (void* p : {(void*)Me_groups.row0, (void*)Me_groups.uptr, (void*)Me_groups.ucols, (void*)Me_groups.lidx,
+                    (void*)Me_groups.rlen, (void*)Me_val, (void*)Me_val32})
       if (p) (void)hipFree(p);
     for (double* p : {Gvisc, w1, Hw, omega, dsc, Dinv}) (void)hipFree(p);
   }
@@ -795,8 +796,12 @@ struct PrecOpts {
 // time-averaged one inside F_avg (eq. 5.23).  Without convection this is
 // (F_0 + C)^-1 exactly.  The matrix is lower block-bidiagonal in time with
 // F_avg on the diagonal and -tau^-1 M below, identity in the chaos mode:
-// block forward substitution in time on the full-format velocity (node-major,
-// columns (t, xi)), then TT-SVD (Alg. 4.1) at eps.
+// block forward substitution in time on the full-format velocity, then
+// TT-SVD (Alg. 4.1) at eps.  The full tensor is kept time-major, W[t][x][xi]:
+// each time step's right-hand side and solution are one contiguous node-major
+// block (n_u x n_xi), so the mass products and the block cyclic reduction
+// passes of a step stream whole cache lines and DRAM pages instead of short
+// pieces of rows n_t n_xi values apart.
 // The same solve in FP32 (precision option 1): the expansion writes the full
 // velocity tensor in FP32 (computed in FP64, rounded on the store), the time steps
 // run the FP32 ELL mass product and FP32 block cyclic reduction passes, and
@@ -807,26 +812,27 @@ TT exact_mean_solve32(sgtt_system& S, const TT& y, double eps) {
   Ctx& c = S.ctx->c;
   const int nt = S.nt, nxi = S.nxi, nu = S.nu;
   const long ldw = (long)nt * nxi;
+  const long blk = (long)nu * nxi;               // one time step
   double* Z = c.pool.get((size_t)ldw * y.r2);   // G1 x_1 G2: (nt nxi) x r2
   gemm(c.s, 1, nt, nxi * y.r2, y.r1, 1.0, y.c1, 0, y.r1, 1, y.c2, 0, (long)nxi * y.r2, 1, 0.0, Z, 0,
        (long)nxi * y.r2, 1);
-  const size_t nfull = (size_t)nu * ldw;
-  double* Wd = c.pool.get((nfull + 1) / 2);      // node-major FP32 tensor W[x][t nxi + xi]
+  const size_t nfull = (size_t)nt * blk;
+  double* Wd = c.pool.get((nfull + 1) / 2);      // time-major FP32 tensor W[t][x][xi]
   float* W = reinterpret_cast<float*>(Wd);
-  gemm_f32out(c.s, nu, (int)ldw, y.r2, y.c3, y.r2, 1, Z, 1, y.r2, W, ldw, 1);
+  gemm_csplit_f32out(c.s, nu, (int)ldw, y.r2, y.c3, y.r2, 1, Z, 1, y.r2, W, nxi, nxi, blk);
   c.pool.put(Z);
   double* Vd = c.pool.get((nfull + 1) / 2);      // FP32 solution, same layout
   float* Vn = reinterpret_cast<float*>(Vd);
   for (int t = 0; t < nt; ++t) {
-    float* Wt = W + (long)t * nxi;
+    float* Wt = W + (long)t * blk;
     if (t > 0)   // y_t + tau^-1 M v_{t-1}
-      ell_spmm32(c.s, S.ns, 2, S.ns, S.ns, S.Me_col, S.Me_val32, S.Me_nnz, Vn + (long)(t - 1) * nxi, (int)ldw, 0, nxi, Wt,
-                 (int)ldw, 0, (float)(1.0 / S.tau), 1.0f);
-    bcr_solve32(c.s, S.Fbt, 2, Wt, ldw, Vn + (long)t * nxi, ldw, nxi);
+      ell_spmm32(c.s, S.ns, 2, S.ns, S.ns, S.Me_groups, S.Me_val32, S.Me_nnz, Vn + (long)(t - 1) * blk, nxi, 0, nxi,
+                 Wt, nxi, 0, (float)(1.0 / S.tau), 1.0f);
+    bcr_solve32(c.s, S.Fbt, 2, Wt, nxi, Vn + (long)t * blk, nxi, nxi);
   }
   c.pool.put(Wd);
   double* V = c.pool.get(nfull);                 // C order (t, xi, x), FP64
-  transpose_widen(c.s, nu, (int)ldw, Vn, ldw, V, nu);
+  transpose_widen_batched(c.s, nt, nu, nxi, Vn, blk, nxi, V, blk, nu);
   c.pool.put(Vd);
   TT out = tt_from_full(c, V, nt, nxi, nu, eps, nullptr);
   c.pool.put(V);
@@ -837,22 +843,23 @@ TT exact_mean_solve(sgtt_system& S, const TT& y, double eps) {
   Ctx& c = S.ctx->c;
   const int nt = S.nt, nxi = S.nxi, nu = S.nu;
   const long ldw = (long)nt * nxi;
+  const long blk = (long)nu * nxi;               // one time step
   double* Z = c.pool.get((size_t)ldw * y.r2);   // G1 x_1 G2: (nt nxi) x r2
   gemm(c.s, 1, nt, nxi * y.r2, y.r1, 1.0, y.c1, 0, y.r1, 1, y.c2, 0, (long)nxi * y.r2, 1, 0.0, Z, 0,
        (long)nxi * y.r2, 1);
-  double* W = c.pool.get((size_t)nu * ldw);     // node-major full tensor: W[x][t nxi + xi]
-  gemm(c.s, 1, nu, (int)ldw, y.r2, 1.0, y.c3, 0, y.r2, 1, Z, 0, 1, y.r2, 0.0, W, 0, ldw, 1);
+  double* W = c.pool.get((size_t)nt * blk);     // time-major full tensor: W[t][x][xi]
+  gemm_csplit(c.s, nu, (int)ldw, y.r2, y.c3, y.r2, 1, Z, 1, y.r2, W, nxi, nxi, blk);
   c.pool.put(Z);
-  double* Vn = c.pool.get((size_t)nu * ldw);    // solution, same layout
+  double* Vn = c.pool.get((size_t)nt * blk);    // solution, same layout
   for (int t = 0; t < nt; ++t) {
-    double* Wt = W + (long)t * nxi;
+    double* Wt = W + (long)t * blk;
     if (t > 0)   // y_t + tau^-1 M v_{t-1}
-      ell_spmm(c.s, S.ns, 2, S.ns, S.ns, S.Me_col, S.Me_val, S.Me_nnz, Vn + (long)(t - 1) * nxi, (int)ldw, 0, nxi, Wt,
-               (int)ldw, 0, 1.0 / S.tau, 1.0);
-    bcr_solve(c.s, S.Fbt, 2, Wt, ldw, Vn + (long)t * nxi, ldw, nxi);
+      ell_spmm(c.s, S.ns, 2, S.ns, S.ns, S.Me_groups, S.Me_val, S.Me_nnz, Vn + (long)(t - 1) * blk, nxi, 0, nxi, Wt,
+               nxi, 0, 1.0 / S.tau, 1.0);
+    bcr_solve(c.s, S.Fbt, 2, Wt, nxi, Vn + (long)t * blk, nxi, nxi);
   }
   double* V = W;                                 // C order (t, xi, x), reusing the consumed right-hand side
-  transpose_copy(c.s, nu, (int)ldw, Vn, ldw, V, nu);
+  transpose_copy_batched(c.s, nt, nu, nxi, Vn, blk, nxi, V, blk, nu);
   c.pool.put(Vn);
   TT out = tt_from_full(c, V, nt, nxi, nu, eps, nullptr);
   c.pool.put(W);
@@ -1341,18 +1348,20 @@ sgtt_system* assemble_internal(sgtt_context* ctx, const sgtt_problem_desc* desc,
   S->Xbt = factor_bcr(c, hp.Xp, hp.Xp.val.data(), hp.p_blocks);
   {
     const Csr& K = hp.Kff;
-    std::vector<int> ec((size_t)K.nrows * ELL_WIDTH);
     std::vector<double> ev((size_t)K.nrows * ELL_WIDTH, 0.0);
     for (int r = 0; r < K.nrows; ++r) {
       const int n = K.rowptr[r + 1] - K.rowptr[r];
       if (n > ELL_WIDTH) throw SgttError(-6, "mass matrix row longer than the padded width");
-      for (int q = 0; q < ELL_WIDTH; ++q) {
-        const int t = K.rowptr[r] + q;
-        ec[(size_t)r * ELL_WIDTH + q] = q < n ? K.col[t] : r;
-        ev[(size_t)r * ELL_WIDTH + q] = q < n ? hp.Mff[t] : 0.0;
-      }
+      for (int q = 0; q < n; ++q) ev[(size_t)r * ELL_WIDTH + q] = hp.Mff[K.rowptr[r] + q];
     }
-    S->Me_col = dev_upload(c, ec);
+    std::vector<int> row0, uptr, ucols, lidx, rlen;
+    ell_groups_build(K.nrows, K.rowptr.data(), K.col.data(), row0, uptr, ucols, lidx, rlen, S->Me_groups.umax);
+    S->Me_groups.ngroups = (int)row0.size() - 1;
+    S->Me_groups.row0 = dev_upload(c, row0);
+    S->Me_groups.uptr = dev_upload(c, uptr);
+    S->Me_groups.ucols = dev_upload(c, ucols);
+    S->Me_groups.lidx = dev_upload(c, lidx);
+    S->Me_groups.rlen = dev_upload(c, rlen);
     S->Me_nnz = K.rowptr[K.nrows];
     S->Me_val32 = dev_upload(c, std::vector<float>(ev.begin(), ev.end()));
     S->Me_val = dev_upload(c, ev);

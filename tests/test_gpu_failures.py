@@ -1,8 +1,9 @@
 """Failure handling forced from the host, every kernel exiting normally:
 the iteration limit (Alg. 4.2's maxit; status SGTT_W_NOT_CONVERGED with the
 best iterate), a non-finite right-hand side (refused before any rounding,
-the context usable afterwards) and a network whose corrections do not help
-(the learned mean solve falls back to the exact one)."""
+the context usable afterwards), a network whose corrections do not help
+(the learned mean solve falls back to the exact one), and a context
+destroyed before the system and network made on it."""
 import numpy as np
 import pytest
 
@@ -57,3 +58,20 @@ def test_useless_network_falls_back_to_exact_mean_solve(sg, ctx):
     print(st, flush=True)
     assert rc == 0 and st["rel_residual"] <= 1e-8
     assert st["learned_calls"] > 0 and st["learned_fallback"] == 1
+
+
+def test_context_destroyed_before_its_system_and_network(sg):
+    """A garbage-collected cycle finalizes its objects in any order: a
+    context destroyed while a system and a network still use it stays
+    alive until the last of them is destroyed (then it is released)."""
+    print("context destroyed first tiny", flush=True)
+    c2 = sg.Context(0)
+    S = sg.System(c2, CONFIGS["tiny"])
+    net = sg.Mlp(c2, S.info.n_s, 64, 0, 3)
+    x, st, rc = S.solve(S.rhs(), S.pair(16, 64))
+    assert rc == 0 and st["rel_residual"] <= 1e-8
+    c2.__del__()   # context first
+    assert c2._c is None
+    S.__del__()    # the system's TTs go back to the closing context's pool
+    net.__del__()  # the last child: the context is released here
+    assert S._s is None and net._m is None
