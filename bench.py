@@ -217,8 +217,8 @@ def solve_options(args=None):
 # of known size): bytes per launch, valid while the kernel source it was
 # measured on is unchanged (digest of the block cyclic reduction section of
 # kernels.hip and of the host factorization).  None until measured.
-TRAFFIC_RECORD = {"kernel_src_sha256": "64d19edf8066ca1089c329bbe08a9a22b9037d3708e31f06ad274193367a0f78",
-                  "bytes_per_launch": 33188862, "fetch_bytes_per_launch": 30331157, "write_bytes_per_launch": 2857705,
+TRAFFIC_RECORD = {"kernel_src_sha256": "6ec22fb6fbe7aa10092f6f1c0e927da62ce2ebfdcbf1f1435a602031674dbfc1",
+                  "bytes_per_launch": 24415804, "fetch_bytes_per_launch": 21746598, "write_bytes_per_launch": 2669205,
                   "summary": "profiles/k_bcr_c2_stokes_traffic.md"}
 
 
@@ -228,8 +228,10 @@ def bcr_source_digest():
     them (variant table, XCD grid padding, tuning and the choice of a variant
     per pass, from struct BcrVariant to bcr_solve_variant), the device
     layout of a factor (upload_bcr and factor_bcr in solver.hip: fragment
-    order, descriptors, padding) and the host factorization (bcr_factor in
-    host_setup.cpp: block sizes, levels, dropped zeros)."""
+    order, descriptors, padding), the callers that set the layout of the
+    passes' right-hand sides (the time-stepped mean solves in solver.hip) and
+    the host factorization (bcr_factor in host_setup.cpp: block sizes,
+    levels, dropped zeros)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1906_06785_amd", "csrc")
     src = open(os.path.join(csrc, "kernels.hip")).read()
@@ -241,10 +243,12 @@ def bcr_source_digest():
     sol = open(os.path.join(csrc, "solver.hip")).read()
     s0 = sol.index("BcrDev upload_bcr(")
     s1 = sol.index("\n}\n", sol.index("BcrDev factor_bcr(")) + 3
+    m0 = sol.index("TT exact_mean_solve32(")
+    m1 = sol.index("\n}\n", sol.index("TT exact_mean_solve(")) + 3
     host = open(os.path.join(csrc, "host_setup.cpp")).read()
     j0 = host.index("void bcr_factor(")
     j1 = host.index("void bcr_apply_host(")
-    return hashlib.sha256((src[i0:i1] + src[k0:k1] + sol[s0:s1] + host[j0:j1]).encode()).hexdigest()
+    return hashlib.sha256((src[i0:i1] + src[k0:k1] + sol[s0:s1] + sol[m0:m1] + host[j0:j1]).encode()).hexdigest()
 
 
 def recorded_traffic(dom_name):
