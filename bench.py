@@ -218,7 +218,7 @@ def solve_options(args=None):
 # measured on is unchanged (digest of the block cyclic reduction section of
 # kernels.hip and of the host factorization).  None until measured.
 TRAFFIC_RECORD = {"kernel_src_sha256": "6ec22fb6fbe7aa10092f6f1c0e927da62ce2ebfdcbf1f1435a602031674dbfc1",
-                  "bytes_per_launch": 24415804, "fetch_bytes_per_launch": 21746598, "write_bytes_per_launch": 2669205,
+                  "bytes_per_launch": 24415803, "fetch_bytes_per_launch": 21746598, "write_bytes_per_launch": 2669205,
                   "summary": "profiles/k_bcr_c2_stokes_traffic.md"}
 
 
