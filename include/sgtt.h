@@ -127,7 +127,17 @@ typedef struct {
                           TT-SVD in FP64).  The outer iteration, operator,
                           truncation eigen-solves, Hessenberg least squares
                           and the exact residual stay FP64, so the flexible
-                          outer solve and the refinement still reach tol    */
+                          outer solve and the refinement still reach tol.
+                          3 (relaxed): the velocity block runs in FP32 (as
+                          with 1) only in the outer iterations whose
+                          residual, relative to the right-hand side of the
+                          whole solve, is at most 0.05 tol / 1e-5 (1e-5
+                          bounds the FP32 mean solve's relative error), in
+                          FP64 before; so the FP32 error an application adds
+                          to the solution stays below what the refinement
+                          cycle's right-hand side is compressed at, and
+                          does not raise its ranks.  Outside sgtt_solve
+                          (sgtt_precondition) 3 means FP64                   */
   double inner_rhs_eps;    /* truncation of the inner solve's right-hand side
                               (0: inner_eps); the inner solve only has to
                               reach inner_tol                              */
@@ -169,6 +179,8 @@ typedef struct {
                                 (sgtt_context_reserve) covers its working set
                                 and the spatial-solve kernel choices for its
                                 column counts are tuned                     */
+  int f32_applications;      /* precision 3: preconditioner applications whose
+                                velocity block ran in FP32                  */
 } sgtt_solve_stats;
 
 /* ------------------------------------------------------------- context */

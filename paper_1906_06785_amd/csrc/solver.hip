@@ -408,6 +408,9 @@ double read_double(Ctx& c, const double* d) {
 struct Space {
   virtual Vec apply(const Vec&) = 0;
   virtual Vec precond(const Vec&) = 0;
+  // the residual of the iterate the next precond serves, relative to the
+  // right-hand side of the current solve
+  virtual void note_residual(double) {}
   // the operator on another context (stream and pool); false (and y
   // untouched) if the space cannot run there
   virtual bool can_apply_on() const { return false; }
@@ -423,6 +426,7 @@ struct SolveCounters {
   std::vector<sgtt_iter_record>* hist = nullptr;   // outer iterations of the solve
   int cycle = 0;
   double t_start = 0;
+  int f32_applications = 0;   // relaxed precision: applications run in FP32
 };
 
 void hist_ranks(const Vec& v, int* u, int* p) {
@@ -543,6 +547,7 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
       have_pre = false;
     } else {
       RegionScope rg(inner ? RG_IN_MINV : RG_LSC);
+      sp.note_residual(res / bnorm);
       vh = sp.precond(V[k - 1]);
     }
     double t1 = now_s();
@@ -709,8 +714,10 @@ Vec lowrank_fgmres(Ctx& c, Space& sp, const Vec& b, double tol, double eps, int 
       // the next iteration's preconditioner meanwhile, unless the estimate
       // says this may be the last iteration of the cycle
       try {
-        if (!breakdown && k < maxit && read_double(c, sc + 8) > 2.0 * tol * bnorm) {
+        const double est = read_double(c, sc + 8);
+        if (!breakdown && k < maxit && est > 2.0 * tol * bnorm) {
           RegionScope rg(inner ? RG_IN_MINV : RG_LSC);
+          sp.note_residual(est / bnorm);
           vh_pre = sp.precond(V[k]);
           have_pre = true;
         }
@@ -782,13 +789,21 @@ struct InnerSpace : Space {
   }
 };
 
+// precision option 3: the velocity block in FP32 only where the outer
+// iteration's residual allows it (OuterSpace::note_residual)
+constexpr int PREC_RELAXED = 3;
+// relative error of the FP32 time-stepped mean solve against the FP64 one,
+// bounded from above (the GPU tests measure it against the oracle)
+constexpr double kF32MeanSolveError = 1e-5;
+
 struct PrecOpts {
   double eps = 1e-6, inner_tol = 1e-1, inner_eps = 1e-3, inner_rhs_eps = 0.0;
   int inner_mode = 0;       // 0: inner GMRES with M (eq. 5.22-5.23); 1: exact mean solve; 2: M alone
   int schur = 0;            // 0: mean-based LSC (eq. 5.19); 1: mean-based PCD (eq. 5.17)
   int inner_maxit = 20;
   bool inner_explicit = false;
-  int precision = GP_F64;   // dense products of the inner solve
+  int precision = GP_F64;   // dense products of the inner solve, or PREC_RELAXED
+  bool relaxed_f32 = false;  // PREC_RELAXED: this application may run in FP32
 };
 
 // (tau^-1 (I - C) (x) I (x) M + I (x) I (x) (F_avg - tau^-1 M))^-1 y: the mean
@@ -913,8 +928,8 @@ Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCoun
     RegionScope rg(RG_IN_MINV);
     Vec out;
     out.nc = 2;
-    out.c[0] = po.precision != GP_F64 ? exact_mean_solve32(S, rhs.c[0], po.inner_eps)
-                                      : exact_mean_solve(S, rhs.c[0], po.inner_eps);
+    const bool f32 = po.precision == PREC_RELAXED ? po.relaxed_f32 : po.precision != GP_F64;
+    out.c[0] = f32 ? exact_mean_solve32(S, rhs.c[0], po.inner_eps) : exact_mean_solve(S, rhs.c[0], po.inner_eps);
     out.c[1] = std::move(ph);
     return out;
   }
@@ -923,7 +938,7 @@ Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCoun
   double rr = 0;
   SolveCounters icnt;
   icnt.verbose = cnt ? cnt->verbose : 0;
-  GemmPrecisionScope gp(po.precision);
+  GemmPrecisionScope gp(po.precision == PREC_RELAXED ? (po.relaxed_f32 ? GP_F32 : GP_F64) : po.precision);
   Vec v = lowrank_fgmres(c, isp, rhs, po.inner_tol, po.inner_eps, po.inner_maxit, S.dsc + 16384, its, rr, &icnt,
                          "inner", po.inner_explicit, false, 1e-2, po.inner_rhs_eps);
   if (cnt) cnt->inner += its;
@@ -941,9 +956,17 @@ struct OuterSpace : Space {
   sgtt_system& S;
   PrecOpts po;
   SolveCounters* cnt;
+  // PREC_RELAXED: the relative residual of the whole solve at the start of
+  // the current refinement cycle, and the level below which an application
+  // of the preconditioner may run its velocity block in FP32
+  double cycle_rel = 1.0, f32_below = 0.0;
   OuterSpace(sgtt_system& s, const PrecOpts& p, SolveCounters* c) : S(s), po(p), cnt(c) {}
   Vec apply(const Vec& x) override { return apply_L(S, x); }
   Vec precond(const Vec& x) override { return lsc_precondition(S, x, po, cnt); }
+  void note_residual(double rel) override {
+    po.relaxed_f32 = po.precision == PREC_RELAXED && cycle_rel * rel <= f32_below;
+    if (po.relaxed_f32 && cnt) ++cnt->f32_applications;
+  }
   bool can_apply_on() const override { return true; }
   bool apply_on(const Vec& x, Ctx& cc, Vec& y) override {
     y = apply_L(S, x, &cc);
@@ -1038,7 +1061,7 @@ PrecOpts prec_opts(const sgtt_solve_opts* o) {
     p.inner_eps = o->inner_eps;
     p.inner_maxit = o->inner_maxit;
     p.inner_explicit = o->inner_explicit != 0;
-    if (o->precision < 0 || o->precision > 2) throw SgttError(-1, "invalid precision option");
+    if (o->precision < 0 || o->precision > PREC_RELAXED) throw SgttError(-1, "invalid precision option");
     if (o->inner_rhs_eps < 0.0 || o->cycle_rhs_factor < 0.0) throw SgttError(-1, "invalid truncation option");
     p.inner_rhs_eps = o->inner_rhs_eps;
     if (o->inner_mode < 0 || o->inner_mode > 2) throw SgttError(-1, "invalid inner_mode option");
@@ -1900,6 +1923,10 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
   S->hist.clear();
   cnt.hist = &S->hist;
   OuterSpace sp(*S, prec_opts(&o), &cnt);
+  // an FP32 application adds at most kF32MeanSolveError of itself to the
+  // solution, and its size follows the residual it is applied to: below
+  // this level that stays under the refinement cycle's compression
+  sp.f32_below = 0.05 * o.tol / kF32MeanSolveError;
   S->mlp_off = false;
   S->mlp_fails = 0;
   S->mlp_calls = 0;
@@ -1918,6 +1945,7 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
     int its = 0;
     double rr = 0;
     cnt.cycle = cyc;
+    sp.cycle_rel = rel;   // the cycle solves L d = r_j, ||r_j|| = rel ||b||
     Vec d = lowrank_fgmres(c, sp, r, o.tol_cycle, o.eps_krylov, o.restart, S->dsc, its, rr, &cnt, "outer",
                            o.outer_explicit != 0, o.relax != 0);
     cnt.outer += its;
@@ -1969,6 +1997,7 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
     stats->t_residual = 0;
     stats->learned_calls = S->mlp_calls;
     stats->learned_fallback = S->mlp_off ? 1 : 0;
+    stats->f32_applications = cnt.f32_applications;
     stats->device_allocs = c.pool.device_allocs() + kernel_device_allocs() + side_device_allocs(c) - a0;
   }
   return rel > o.tol ? SGTT_W_NOT_CONVERGED : SGTT_OK;

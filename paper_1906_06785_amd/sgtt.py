@@ -109,7 +109,8 @@ class SolveStats(C.Structure):
                 ("rel_residual", C.c_double), ("seconds", C.c_double), ("max_rank_krylov_u", C.c_int),
                 ("max_rank_krylov_p", C.c_int), ("roundings", C.c_int), ("t_apply", C.c_double),
                 ("t_round", C.c_double), ("t_precond", C.c_double), ("t_residual", C.c_double),
-                ("learned_calls", C.c_int), ("learned_fallback", C.c_int), ("device_allocs", C.c_long)]
+                ("learned_calls", C.c_int), ("learned_fallback", C.c_int), ("device_allocs", C.c_long),
+                ("f32_applications", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

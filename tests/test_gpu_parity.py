@@ -458,6 +458,26 @@ def test_solve_c1_fp32_mean_solve_to_1e8(sg, ctx, c1):
     assert err <= 1e-8
 
 
+def test_solve_c1_relaxed_precision_to_1e8(sg, ctx, c1):
+    # precision 3: the FP32 mean solve only once the residual of the whole
+    # solve is below 0.05 tol / 1e-5; the solve still reaches the oracle's
+    # exact solution, with the same outer iterations as in FP64 and some
+    # preconditioner applications in FP32
+    P, S = c1
+    _flush("solve c1 with relaxed precision")
+    b = S.rhs()
+    x64, st64, rc64 = S.solve(b, S.pair(96, 1024), restart=20, relax=1, inner_mode=1, precision=0, **TIGHT)
+    x, st, rc = S.solve(b, S.pair(96, 1024), restart=20, relax=1, inner_mode=1, precision=3, **TIGHT)
+    err = _solution_error(P, x)
+    _flush(f"outer {st['outer_iters']} (FP64 {st64['outer_iters']}) residual {st['rel_residual']:.2e} "
+           f"solution error {err:.2e} FP32 applications {st['f32_applications']}")
+    assert rc == 0 and st["rel_residual"] <= 1e-10
+    assert err <= 1e-8
+    assert st["f32_applications"] > 0
+    assert st["outer_iters"] <= st64["outer_iters"] + 2
+    assert st64["f32_applications"] == 0
+
+
 @pytest.fixture(scope="module")
 def kl_systems(sg, ctx):
     out = {}
