@@ -525,12 +525,18 @@ __global__ void k_scalar(int kind, const double* a, const double* b, double* out
 // ------------------------------------------------------------------ SpMM
 constexpr int NVMAX = 16;
 
+// CSR SpMM with nv value arrays sharing one pattern: one row per wave, one
+// output column per lane.  The row index is made wave-uniform, so the row's
+// pattern and values are read with scalar loads; its input rows are loaded
+// eight entries at a time before their products, so eight loads are in
+// flight per lane instead of one.  Products are accumulated in entry order.
 __global__ __launch_bounds__(256) void k_spmm(int nrows, int ics, int ocs, const int* __restrict__ rowptr,
                                               const int* __restrict__ col, const double* __restrict__ vals, int nv,
                                               long vstride, const double* __restrict__ x, int ldx, int xcol0,
                                               int ncols, double* __restrict__ y, int ldy, int ycol0, int yvstep,
                                               double alpha, double beta) {
-  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  constexpr int EB = 8;   // entries per batch of loads
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x % WAVE;
   const int r = blockIdx.x * (blockDim.x / WAVE) + wave;
   const int c = blockIdx.y;
   if (r >= nrows) return;
@@ -540,11 +546,27 @@ __global__ __launch_bounds__(256) void k_spmm(int nrows, int ics, int ocs, const
   for (int j0 = 0; j0 < ncols; j0 += WAVE) {
     const int j = j0 + lane;
     const bool act = j < ncols;
+    const int jc = act ? j : ncols - 1;   // idle lanes read a valid column
     double acc[NVMAX];
 #pragma unroll
     for (int v = 0; v < NVMAX; ++v) acc[v] = 0.0;
-    for (int t = t0; t < t1; ++t) {
-      const double xv = act ? xb[(long)col[t] * ldx + j] : 0.0;
+    int t = t0;
+    for (; t + EB <= t1; t += EB) {
+      double xv[EB];
+#pragma unroll
+      for (int q = 0; q < EB; ++q) xv[q] = xb[(long)col[t + q] * ldx + jc];
+      // value array outside, entries inside: a value array's EB values are
+      // contiguous (one wide scalar load), and each sum keeps entry order
+#pragma unroll
+      for (int v = 0; v < NVMAX; ++v) {
+        if (v >= nv) break;
+        const double* vv = vals + v * vstride + t;
+#pragma unroll
+        for (int q = 0; q < EB; ++q) acc[v] = fma(vv[q], xv[q], acc[v]);
+      }
+    }
+    for (; t < t1; ++t) {
+      const double xv = xb[(long)col[t] * ldx + jc];
 #pragma unroll
       for (int v = 0; v < NVMAX; ++v)
         if (v < nv) acc[v] = fma(vals[v * vstride + t], xv, acc[v]);
