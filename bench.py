@@ -223,8 +223,8 @@ def solve_options(args=None):
 # of known size): bytes per launch, valid while the kernel source it was
 # measured on is unchanged (digest of the block cyclic reduction section of
 # kernels.hip and of the host factorization).  None until measured.
-TRAFFIC_RECORD = {"kernel_src_sha256": "6ec22fb6fbe7aa10092f6f1c0e927da62ce2ebfdcbf1f1435a602031674dbfc1",
-                  "bytes_per_launch": 24415803, "fetch_bytes_per_launch": 21746598, "write_bytes_per_launch": 2669205,
+TRAFFIC_RECORD = {"kernel_src_sha256": "030b5e26a1b2bebb51c96c049fec94e251b5421c25faf07ae0f233fbfbbfad93",
+                  "bytes_per_launch": 13208483, "fetch_bytes_per_launch": 10661427, "write_bytes_per_launch": 2547056,
                   "summary": "profiles/k_bcr_c2_stokes_traffic.md"}
 
 

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -13,6 +14,7 @@
 #include <string>
 #include <thread>
 #include <map>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/sgtt.h"
@@ -105,15 +107,34 @@ BcrDev upload_bcr(Ctx& c, const BcrFactor& f) {
   std::vector<BcrOpDesc> ops(f.op_out.size());
   std::vector<double> frag;                       // blocks in fragment order
   std::map<std::tuple<long, int, int>, long> placed;
+  // blocks with bitwise equal contents are stored once (slabs of equal
+  // geometry give equal blocks): content hash -> (offset, size) of each
+  std::unordered_map<uint64_t, std::vector<std::pair<long, long>>> by_content;
+  std::vector<double> tmp;
+  long blocks_seen = 0, blocks_kept = 0;
   // rows x cols of a column-major matrix with ld rows starting at off
   auto place = [&](long off, int ld, int rows, int cols) -> long {
     const auto key = std::make_tuple(off, rows, cols);
     auto it = placed.find(key);
     if (it != placed.end()) return it->second;
-    const long at = (long)frag.size();
-    frag.resize(frag.size() + bcr_fragment_size(rows, cols), 0.0);
+    const long size = bcr_fragment_size(rows, cols);
+    tmp.assign(size, 0.0);
     for (int k = 0; k < cols; ++k)
-      for (int i = 0; i < rows; ++i) frag[at + bcr_fragment_index(i, k, cols)] = f.data[off + (long)k * ld + i];
+      for (int i = 0; i < rows; ++i) tmp[bcr_fragment_index(i, k, cols)] = f.data[off + (long)k * ld + i];
+    uint64_t h = 1469598103934665603ull ^ ((uint64_t)rows << 32 | (uint32_t)cols);
+    const unsigned char* by = reinterpret_cast<const unsigned char*>(tmp.data());
+    for (size_t b = 0; b < sizeof(double) * tmp.size(); ++b) h = (h ^ by[b]) * 1099511628211ull;
+    ++blocks_seen;
+    auto& cand = by_content[h];
+    for (const auto& oc : cand)
+      if (oc.second == size && std::memcmp(frag.data() + oc.first, tmp.data(), sizeof(double) * size) == 0) {
+        placed[key] = oc.first;
+        return oc.first;
+      }
+    const long at = (long)frag.size();
+    frag.insert(frag.end(), tmp.begin(), tmp.end());
+    cand.emplace_back(at, size);
+    ++blocks_kept;
     placed[key] = at;
     return at;
   };
@@ -155,6 +176,9 @@ BcrDev upload_bcr(Ctx& c, const BcrFactor& f) {
     }
     for (const auto& b : blocks) d.pass_data[p] += (double)b.second;
   }
+  if (std::getenv("SGTT_BCR_TUNE_LOG"))
+    std::fprintf(stderr, "[bcr upload] n=%d: %ld blocks, %ld distinct, %.3g MB of block data\n", f.n, blocks_seen,
+                 blocks_kept, 8e-6 * (double)frag.size());
   frag.resize(frag.size() + BCR_DATA_PAD, 0.0);
   d.ndata = (double)frag.size();
   d.ops = dev_upload(c, ops);
