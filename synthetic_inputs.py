@@ -50,6 +50,10 @@ CONFIGS = {
     # intermediate size used by parity tests at a shape between C1 and C2
     "C1b": dict(h=0.125, L=12.0, m=3, p=2, nt=32, tau=0.05, nu0=1.0 / 50,
                 nu_coef=0.1, ramp=10.0),
+    # many chaos terms on a small mesh: m = 4, p = 4 gives n_xi = 70, more
+    # columns per time step than one 64-wide pass of the mass product takes
+    "tinyp4": dict(h=0.5, L=2.0, m=4, p=4, nt=3, tau=0.1, nu0=1.0 / 50, nu_coef=0.1,
+                   ramp=10.0),
 }
 
 # Solver defaults (readings of the paper):

@@ -287,6 +287,27 @@ def test_preconditioner_exact_inner_matches_oracle(sg, ctx, c1):
     assert np.linalg.norm(got - want) <= 1e-8 * np.linalg.norm(want)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_preconditioner_exact_inner_many_chaos_terms(sg, ctx, precision):
+    # n_xi = 70 chaos columns per time step: the mass product of the time
+    # stepping forms them in two column chunks (FP64: 64 + 6 with the group's
+    # input rows staged once per chunk); FP64 and FP32 mean solves against the
+    # oracle's exact preconditioner
+    P = Problem(CONFIGS["tinyp4"])
+    S = sg.System(ctx, CONFIGS["tinyp4"])
+    assert P.n_xi == 70 and S.nxi == 70
+    _flush(f"precondition exact inner tinyp4, precision {precision}")
+    r = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 5), (2, 3), 29)
+    out = S.precondition(_pair_buf(S, r, 32, 512), eps_krylov=1e-13, inner_eps=1e-13, inner_mode=1,
+                         precision=precision)
+    ref_u, ref_p = MeanLSC(P, None, "full").apply_full_exact(tt.full(r[0]), tt.full(r[1]))
+    want = np.concatenate([ref_u.ravel(), ref_p.ravel()])
+    got = tt.pair_full(out.cores())
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    _flush(f"error {err:.2e}")
+    assert err <= (1e-8 if precision == 0 else 1e-5)
+
+
 def test_preconditioner_exact_inner_long_horizon(sg, ctx):
     # the same at 32 time steps (C1b), twice: the first call chooses the
     # spatial solve's kernel variants, the second reuses the choice
