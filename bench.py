@@ -179,6 +179,8 @@ VARIANTS = {
     "pcd": dict(schur=1),
     "mixed_f32": dict(precision=1),
     "mixed_relaxed": dict(precision=3),
+    "graph": dict(graph=1),
+    "mixed_relaxed_graph": dict(precision=3, graph=1),
 }
 
 VELOCITY_BLOCK = {0: "inner low-rank GMRES on (F_0 + C) preconditioned by M (eq. 5.22-5.23)",
@@ -235,7 +237,8 @@ def bcr_source_digest():
     per pass, from struct BcrVariant to bcr_solve_variant), the device
     layout of a factor (upload_bcr and factor_bcr in solver.hip: fragment
     order, descriptors, padding), the callers that set the layout of the
-    passes' right-hand sides (the time-stepped mean solves in solver.hip) and
+    passes' right-hand sides (the time loop of the mean solve and the
+    time-stepped mean solves in solver.hip) and
     the host factorization (bcr_factor in host_setup.cpp: block sizes,
     levels, dropped zeros)."""
     import hashlib
@@ -249,7 +252,7 @@ def bcr_source_digest():
     sol = open(os.path.join(csrc, "solver.hip")).read()
     s0 = sol.index("BcrDev upload_bcr(")
     s1 = sol.index("\n}\n", sol.index("BcrDev factor_bcr(")) + 3
-    m0 = sol.index("TT exact_mean_solve32(")
+    m0 = sol.index("void mean_time_loop(")
     m1 = sol.index("\n}\n", sol.index("TT exact_mean_solve(")) + 3
     host = open(os.path.join(csrc, "host_setup.cpp")).read()
     j0 = host.index("void bcr_factor(")
@@ -569,6 +572,7 @@ def main():
             "inner_iters": v_stats[-1]["inner_iters"], "max_rel_residual": v_worst, "converged": v_worst <= 1e-8,
             "max_krylov_rank_u": v_stats[-1]["max_rank_krylov_u"],
             "f32_applications": v_stats[-1]["f32_applications"],
+            "graph_launches": v_stats[-1]["graph_launches"],
             "kernels": {k: {"ms": v["seconds"] * 1e3, "launches": v["launches"]} for k, v in v_breakdown.items()
                         if v["launches"]}}
     res = {

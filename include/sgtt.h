@@ -46,13 +46,26 @@ typedef struct sgtt_context sgtt_context;
 typedef struct sgtt_system sgtt_system;
 typedef struct sgtt_host_problem sgtt_host_problem;
 
+/* element type of the cores of an sgtt_tt */
+#define SGTT_DTYPE_F64 0
+
 /* A tensor train with three cores in device memory (caller-owned buffers).
  *   core1: n1 x r1, row-major, leading dimension r1     (n1 * cap1 doubles)
  *   core2: r1 x n2 x r2, row-major [a][i][b]            (cap1 * n2 * cap2)
  *   core3: n3 x r2, row-major (node-major), ld r2       (n3 * cap2 doubles)
  * core3 is the transpose of the paper's third core (eq. 4.2): row = space
  * index, so that sparse products over space read contiguous rank vectors.
- * r1, r2 are the live ranks: inputs read them, outputs write them. */
+ * r1, r2 are the live ranks: inputs read them, outputs write them.
+ * dtype: element type of the cores.  The boundary exchanges FP64 tensor
+ *   trains only (SGTT_DTYPE_F64); any other value is refused with
+ *   SGTT_E_INVALID.  Reduced-precision copies (precision options of
+ *   sgtt_solve_opts) live inside the library.
+ * d_ranks: optional device pointer to 2 ints (NULL: none), caller-owned.
+ *   Every call that writes this TT as an output also stores (r1, r2) there,
+ *   ordered on the context stream after the cores, so that work queued
+ *   later on that stream can read the live ranks from device memory without
+ *   a host round trip.  Inputs are always read from r1, r2 above, never
+ *   from d_ranks. */
 typedef struct {
   int n1, n2, n3;
   int r1, r2;
@@ -60,6 +73,8 @@ typedef struct {
   double* core1;
   double* core2;
   double* core3;
+  int dtype;
+  int* d_ranks;
 } sgtt_tt;
 
 /* velocity TT (n3 = n_u) and pressure TT (n3 = n_p) of one all-at-once vector */
@@ -163,6 +178,15 @@ typedef struct {
                               1 mean-based PCD (eq. 5.17) with the Q1
                               pressure-space mass, stiffness and mean
                               convection (natural boundary conditions)    */
+  int graph;               /* 1: inner_mode 1 runs the time loop of its mean
+                              solve (a mass product and a block cyclic
+                              reduction solve per time step) as one HIP
+                              graph launch, captured once per system and
+                              arithmetic on two full-tensor buffers the
+                              system allocates on first use and keeps (2 n_t
+                              n_xi n_u doubles); until the spatial solve's
+                              kernel choices are tuned, the loop runs as
+                              plain launches.  0: plain launches          */
 } sgtt_solve_opts;
 
 typedef struct {
@@ -181,6 +205,8 @@ typedef struct {
                                 column counts are tuned                     */
   int f32_applications;      /* precision 3: preconditioner applications whose
                                 velocity block ran in FP32                  */
+  long graph_launches;       /* graph option: mean-solve time loops run as a
+                                graph launch                                */
 } sgtt_solve_stats;
 
 /* ------------------------------------------------------------- context */

@@ -54,6 +54,9 @@ enum Region {
 };
 const char* region_name(int r);
 int prof_region(int r);
+// hold: the calling host thread records no profiler scopes (while it
+// captures a stream into a graph, where event records would be captured too)
+void prof_hold_thread(bool hold);
 // seconds[r * KC_COUNT + c] since the last reset
 void prof_read_regions(double* seconds);
 struct RegionScope {
@@ -115,6 +118,8 @@ inline size_t gram_ws_doubles(long rows, int nx, int ny) {
 void sumsq(hipStream_t s, const double* x, long n, double* out, double* ws, size_t ws_doubles);
 
 void fill(hipStream_t s, double* p, long n, double v);
+// d[0] = r1, d[1] = r2 (device ints), ordered on s
+void store_ranks(hipStream_t s, int* d, int r1, int r2);
 // 2-D strided copy with scale: dst[i*ldd + j] = alpha * (*dscale if dscale) * src[i*lds + j]
 void copy2d(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst, long ldd,
             double alpha, const double* dscale = nullptr, int dscale_inv = 0);
@@ -352,6 +357,9 @@ void bcr_solve(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, d
 // throws when the variant does not take the factor's block size.
 int bcr_variant_count();
 bool bcr_variant_takes(const BcrDev& f, int variant);
+// whether bcr_solve (f32: bcr_solve32) has its pass variants for this
+// component and column count already, so that it launches kernels only
+bool bcr_is_tuned(const BcrDev& f, int ncomp, int ncols, bool f32);
 void bcr_solve_variant(hipStream_t s, const BcrDev& f, int ncomp, double* B, long ldb, double* X, long ldx, int ncols,
                        int variant);
 // The same solve in FP32 (blocks data32, right-hand sides and solutions in

@@ -49,6 +49,7 @@ struct Profiler {
 Profiler g_prof;
 std::mutex g_prof_mu;
 thread_local int g_region = 0;   // per host thread (workers of batched solves)
+thread_local bool g_prof_held = false;   // this thread records no scopes (stream capture)
 
 // Brackets launches of one kernel class with HIP events on their stream.
 // A scope may cover several dependent launches of the class (launches > 1);
@@ -61,7 +62,7 @@ struct ProfScope {
   long launches;
   ProfScope(int c, hipStream_t st, double by, double fl, long nl = 1)
       : cls(c), s(st), bytes(by), flops(fl), launches(nl) {
-    if (!g_prof.on || !((g_prof.mask >> c) & 1u)) return;
+    if (g_prof_held || !g_prof.on || !((g_prof.mask >> c) & 1u)) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (g_prof.seen[c]++ % g_prof.period != 0) return;
     a = g_prof.ev();
@@ -98,6 +99,7 @@ int prof_region(int r) {
   g_region = (r >= 0 && r < RG_COUNT) ? r : 0;
   return old;
 }
+void prof_hold_thread(bool hold) { g_prof_held = hold; }
 void prof_read_regions(double* seconds) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   for (int i = 0; i < RG_COUNT * KC_COUNT; ++i) seconds[i] = 0.0;
@@ -421,6 +423,11 @@ __global__ __launch_bounds__(1024) void k_dot_reduce(long n, const double* __res
 // ------------------------------------------------------------------ elementwise
 __global__ void k_fill(double* p, long n, double v) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_store_ranks(int* d, int r1, int r2) {
+  if (threadIdx.x == 0) d[0] = r1;
+  if (threadIdx.x == 1) d[1] = r2;
 }
 
 __global__ void k_copy2d(int rows, int cols, const double* __restrict__ src, long lds, double* __restrict__ dst,
@@ -2414,6 +2421,10 @@ void sumsq(hipStream_t s, const double* x, long n, double* out, double* ws, size
   hipLaunchKernelGGL(k_sum_stage2, dim3(1), dim3(1024), 0, s, ws, nb, out);
 }
 
+void store_ranks(hipStream_t s, int* d, int r1, int r2) {
+  hipLaunchKernelGGL(k_store_ranks, dim3(1), dim3(64), 0, s, d, r1, r2);
+}
+
 void fill(hipStream_t s, double* p, long n, double v) {
   if (n <= 0) return;
   unsigned nb = std::min<unsigned>(cdiv(n, 256), 8192);
@@ -2945,6 +2956,15 @@ void bcr_solve32(hipStream_t s, const BcrDev& f, int ncomp, float* B, long ldb, 
 }
 
 int bcr_variant_count() { return kNumBcrVariants; }
+
+bool bcr_is_tuned(const BcrDev& f, int ncomp, int ncols, bool f32) {
+  if (ncols <= 0 || f.npass == 0) return true;   // nothing to tune: bcr_solve returns at once
+  if (!f.choices) return false;
+  auto key = bcr_choice_key(ncomp, ncols);
+  if (f32) key.second += 64;
+  std::lock_guard<std::mutex> lk(f.choices->mu);
+  return f.choices->by_key.count(key) != 0;
+}
 
 bool bcr_variant_takes(const BcrDev& f, int variant) {
   return variant >= 0 && variant < kNumBcrVariants && f.maxbs <= kBcrVariants[variant].max_rows;

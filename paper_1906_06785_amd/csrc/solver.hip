@@ -245,7 +245,20 @@ struct sgtt_system {
   double setup_s = 0;
   // solve scratch (device scalars)
   double* dsc = nullptr;   // 32768 doubles: outer GMRES [0,16384), inner [16384,30000), residual [30000,)
+  // graph of the mean solve's time loop (solve option graph = 1): the
+  // full-tensor right-hand side and solution it runs on (FP64-sized, the
+  // FP32 loop uses their first halves), one executable graph per arithmetic
+  // [FP64, FP32], and the device allocations made for them
+  double* mg_W = nullptr;
+  double* mg_V = nullptr;
+  hipGraphExec_t mg_exec[2] = {nullptr, nullptr};
+  long mg_allocs = 0;
+  long mg_launches = 0;
   ~sgtt_system() {
+    for (hipGraphExec_t& e : mg_exec)
+      if (e) (void)hipGraphExecDestroy(e);
+    for (double* p : {mg_W, mg_V})
+      if (p) (void)hipFree(p);
     if (mlp_collect) --mlp_collect->uses;
     if (mlp_apply) --mlp_apply->uses;
     Kop.free_all();
@@ -828,7 +841,91 @@ struct PrecOpts {
   bool inner_explicit = false;
   int precision = GP_F64;   // dense products of the inner solve, or PREC_RELAXED
   bool relaxed_f32 = false;  // PREC_RELAXED: this application may run in FP32
+  bool graph = false;       // the mean solve's time loop as a captured graph
 };
+
+// The time loop of the mean solve below on the time-major full tensors W
+// (right-hand side, consumed) and V (solution): v_t = F_avg^-1 (w_t +
+// tau^-1 M v_{t-1}), one mass product and one block cyclic reduction solve
+// per step; f32 selects the FP32 kernels on the first halves of the buffers.
+void mean_time_loop(sgtt_system& S, hipStream_t s, bool f32, double* Wd, double* Vd) {
+  const int nt = S.nt, nxi = S.nxi;
+  const long blk = (long)S.nu * nxi;
+  if (f32) {
+    float* W = reinterpret_cast<float*>(Wd);
+    float* V = reinterpret_cast<float*>(Vd);
+    for (int t = 0; t < nt; ++t) {
+      float* Wt = W + (long)t * blk;
+      if (t > 0)
+        ell_spmm32(s, S.ns, 2, S.ns, S.ns, S.Me_groups, S.Me_val32, S.Me_nnz, V + (long)(t - 1) * blk, nxi, 0, nxi,
+                   Wt, nxi, 0, (float)(1.0 / S.tau), 1.0f);
+      bcr_solve32(s, S.Fbt, 2, Wt, nxi, V + (long)t * blk, nxi, nxi);
+    }
+    return;
+  }
+  for (int t = 0; t < nt; ++t) {
+    double* Wt = Wd + (long)t * blk;
+    if (t > 0)
+      ell_spmm(s, S.ns, 2, S.ns, S.ns, S.Me_groups, S.Me_val, S.Me_nnz, Vd + (long)(t - 1) * blk, nxi, 0, nxi, Wt,
+               nxi, 0, 1.0 / S.tau, 1.0);
+    bcr_solve(s, S.Fbt, 2, Wt, nxi, Vd + (long)t * blk, nxi, nxi);
+  }
+}
+
+// The system's own full-tensor buffers of the graph form (allocated on first
+// use, kept until the system is destroyed): a captured graph holds their
+// addresses in its kernel arguments.
+bool mean_graph_buffers(sgtt_system& S) {
+  if (S.mg_W && S.mg_V) return true;
+  const size_t n = (size_t)S.nt * S.nu * S.nxi;
+  for (double** p : {&S.mg_W, &S.mg_V}) {
+    if (*p) continue;
+    ++S.mg_allocs;
+    if (hipMalloc(p, n * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      throw SgttError(-3, "graph form of the mean solve: device allocation failed");
+    }
+  }
+  return true;
+}
+
+// The time loop as one graph launch on the context stream: captured (on the
+// system's buffers) the first time it is asked for once the spatial solve's
+// pass variants are tuned for these columns (tuning times kernels on the
+// GPU, which a capture cannot contain), then replayed.  Returns false when
+// the caller has to run the loop itself this time.
+bool mean_loop_graph(sgtt_system& S, bool f32) {
+  Ctx& c = S.ctx->c;
+  hipGraphExec_t& ex = S.mg_exec[f32 ? 1 : 0];
+  if (!ex) {
+    if (!bcr_is_tuned(S.Fbt, 2, S.nxi, f32)) return false;
+    hipGraph_t gr = nullptr;
+    prof_hold_thread(true);
+    SGTT_HIP(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
+    try {
+      mean_time_loop(S, c.s, f32, S.mg_W, S.mg_V);
+    } catch (...) {
+      (void)hipStreamEndCapture(c.s, &gr);
+      if (gr) (void)hipGraphDestroy(gr);
+      (void)hipGetLastError();
+      prof_hold_thread(false);
+      throw;
+    }
+    const hipError_t e = hipStreamEndCapture(c.s, &gr);
+    prof_hold_thread(false);
+    SGTT_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (ei != hipSuccess) {
+      ex = nullptr;
+      SGTT_HIP(ei);
+    }
+  }
+  SGTT_HIP(hipGraphLaunch(ex, c.s));
+  ++S.mg_launches;
+  return true;
+}
 
 // (tau^-1 (I - C) (x) I (x) M + I (x) I (x) (F_avg - tau^-1 M))^-1 y: the mean
 // matrix F_0 + C of eq. 5.21 with its convection N_0 replaced by the
@@ -847,7 +944,7 @@ struct PrecOpts {
 // the transpose widens the result to FP64 for the TT-SVD, whose Grams, rank
 // decisions and projections stay FP64.  The result is accurate to FP32
 // rounding relative to the exact one, far below the inner truncation eps.
-TT exact_mean_solve32(sgtt_system& S, const TT& y, double eps) {
+TT exact_mean_solve32(sgtt_system& S, const TT& y, double eps, bool graph) {
   Ctx& c = S.ctx->c;
   const int nt = S.nt, nxi = S.nxi, nu = S.nu;
   const long ldw = (long)nt * nxi;
@@ -856,29 +953,24 @@ TT exact_mean_solve32(sgtt_system& S, const TT& y, double eps) {
   gemm(c.s, 1, nt, nxi * y.r2, y.r1, 1.0, y.c1, 0, y.r1, 1, y.c2, 0, (long)nxi * y.r2, 1, 0.0, Z, 0,
        (long)nxi * y.r2, 1);
   const size_t nfull = (size_t)nt * blk;
-  double* Wd = c.pool.get((nfull + 1) / 2);      // time-major FP32 tensor W[t][x][xi]
+  const bool g = graph && mean_graph_buffers(S);
+  double* Wd = g ? S.mg_W : c.pool.get((nfull + 1) / 2);   // time-major FP32 tensor W[t][x][xi]
   float* W = reinterpret_cast<float*>(Wd);
   gemm_csplit_f32out(c.s, nu, (int)ldw, y.r2, y.c3, y.r2, 1, Z, 1, y.r2, W, nxi, nxi, blk);
   c.pool.put(Z);
-  double* Vd = c.pool.get((nfull + 1) / 2);      // FP32 solution, same layout
+  double* Vd = g ? S.mg_V : c.pool.get((nfull + 1) / 2);   // FP32 solution, same layout
   float* Vn = reinterpret_cast<float*>(Vd);
-  for (int t = 0; t < nt; ++t) {
-    float* Wt = W + (long)t * blk;
-    if (t > 0)   // y_t + tau^-1 M v_{t-1}
-      ell_spmm32(c.s, S.ns, 2, S.ns, S.ns, S.Me_groups, S.Me_val32, S.Me_nnz, Vn + (long)(t - 1) * blk, nxi, 0, nxi,
-                 Wt, nxi, 0, (float)(1.0 / S.tau), 1.0f);
-    bcr_solve32(c.s, S.Fbt, 2, Wt, nxi, Vn + (long)t * blk, nxi, nxi);
-  }
-  c.pool.put(Wd);
+  if (!(g && mean_loop_graph(S, true))) mean_time_loop(S, c.s, true, Wd, Vd);
+  if (!g) c.pool.put(Wd);
   double* V = c.pool.get(nfull);                 // C order (t, xi, x), FP64
   transpose_widen_batched(c.s, nt, nu, nxi, Vn, blk, nxi, V, blk, nu);
-  c.pool.put(Vd);
+  if (!g) c.pool.put(Vd);
   TT out = tt_from_full(c, V, nt, nxi, nu, eps, nullptr);
   c.pool.put(V);
   return out;
 }
 
-TT exact_mean_solve(sgtt_system& S, const TT& y, double eps) {
+TT exact_mean_solve(sgtt_system& S, const TT& y, double eps, bool graph) {
   Ctx& c = S.ctx->c;
   const int nt = S.nt, nxi = S.nxi, nu = S.nu;
   const long ldw = (long)nt * nxi;
@@ -886,22 +978,17 @@ TT exact_mean_solve(sgtt_system& S, const TT& y, double eps) {
   double* Z = c.pool.get((size_t)ldw * y.r2);   // G1 x_1 G2: (nt nxi) x r2
   gemm(c.s, 1, nt, nxi * y.r2, y.r1, 1.0, y.c1, 0, y.r1, 1, y.c2, 0, (long)nxi * y.r2, 1, 0.0, Z, 0,
        (long)nxi * y.r2, 1);
-  double* W = c.pool.get((size_t)nt * blk);     // time-major full tensor: W[t][x][xi]
+  const bool g = graph && mean_graph_buffers(S);
+  double* W = g ? S.mg_W : c.pool.get((size_t)nt * blk);   // time-major full tensor: W[t][x][xi]
   gemm_csplit(c.s, nu, (int)ldw, y.r2, y.c3, y.r2, 1, Z, 1, y.r2, W, nxi, nxi, blk);
   c.pool.put(Z);
-  double* Vn = c.pool.get((size_t)nt * blk);    // solution, same layout
-  for (int t = 0; t < nt; ++t) {
-    double* Wt = W + (long)t * blk;
-    if (t > 0)   // y_t + tau^-1 M v_{t-1}
-      ell_spmm(c.s, S.ns, 2, S.ns, S.ns, S.Me_groups, S.Me_val, S.Me_nnz, Vn + (long)(t - 1) * blk, nxi, 0, nxi, Wt,
-               nxi, 0, 1.0 / S.tau, 1.0);
-    bcr_solve(c.s, S.Fbt, 2, Wt, nxi, Vn + (long)t * blk, nxi, nxi);
-  }
+  double* Vn = g ? S.mg_V : c.pool.get((size_t)nt * blk);  // solution, same layout
+  if (!(g && mean_loop_graph(S, false))) mean_time_loop(S, c.s, false, W, Vn);
   double* V = W;                                 // C order (t, xi, x), reusing the consumed right-hand side
   transpose_copy_batched(c.s, nt, nu, nxi, Vn, blk, nxi, V, blk, nu);
-  c.pool.put(Vn);
+  if (!g) c.pool.put(Vn);
   TT out = tt_from_full(c, V, nt, nxi, nu, eps, nullptr);
-  c.pool.put(W);
+  if (!g) c.pool.put(W);
   return out;
 }
 
@@ -953,7 +1040,8 @@ Vec lsc_precondition(sgtt_system& S, const Vec& y, const PrecOpts& po, SolveCoun
     Vec out;
     out.nc = 2;
     const bool f32 = po.precision == PREC_RELAXED ? po.relaxed_f32 : po.precision != GP_F64;
-    out.c[0] = f32 ? exact_mean_solve32(S, rhs.c[0], po.inner_eps) : exact_mean_solve(S, rhs.c[0], po.inner_eps);
+    out.c[0] = f32 ? exact_mean_solve32(S, rhs.c[0], po.inner_eps, po.graph)
+                   : exact_mean_solve(S, rhs.c[0], po.inner_eps, po.graph);
     out.c[1] = std::move(ph);
     return out;
   }
@@ -1044,7 +1132,20 @@ double full_residual(sgtt_system& S, const Vec& b, const Vec& z, double* d_out_s
 }
 
 // ---------------------------------------------------------------- helpers for the ABI
+void check_dtype(const sgtt_tt& t) {
+  if (t.dtype != SGTT_DTYPE_F64) throw SgttError(-1, "TT element type other than FP64");
+}
+
+// live ranks of an output TT: host fields, and the caller's device copy
+void set_ranks(Ctx& c, sgtt_tt* out, int r1, int r2) {
+  out->r1 = r1;
+  out->r2 = r2;
+  if (out->d_ranks) store_ranks(c.s, out->d_ranks, r1, r2);
+}
+
 Vec vec_from_pair(const sgtt_tt_pair* p) {
+  check_dtype(p->u);
+  check_dtype(p->p);
   Vec v;
   v.nc = 2;
   v.c[0] = tt_view(p->u.n1, p->u.n2, p->u.n3, p->u.r1, p->u.r2, p->u.core1, p->u.core2, p->u.core3);
@@ -1053,12 +1154,14 @@ Vec vec_from_pair(const sgtt_tt_pair* p) {
 }
 
 void check_tt(const sgtt_tt& t, int n1, int n2, int n3) {
+  check_dtype(t);
   if (t.n1 != n1 || t.n2 != n2 || t.n3 != n3) throw SgttError(-1, "TT dimensions do not match the system");
   if (t.r1 < 1 || t.r2 < 1 || t.r1 > t.cap1 || t.r2 > t.cap2 || !t.core1 || !t.core2 || !t.core3)
     throw SgttError(-1, "invalid TT ranks or buffers");
 }
 
 void write_tt(Ctx& c, const TT& x, sgtt_tt* out) {
+  check_dtype(*out);
   if (x.r1 > out->cap1 || x.r2 > out->cap2)
     throw SgttError(-4, "result rank (" + std::to_string(x.r1) + "," + std::to_string(x.r2) +
                             ") exceeds output capacity (" + std::to_string(out->cap1) + "," +
@@ -1066,8 +1169,7 @@ void write_tt(Ctx& c, const TT& x, sgtt_tt* out) {
   SGTT_HIP(hipMemcpyAsync(out->core1, x.c1, sizeof(double) * x.n_c1(), hipMemcpyDeviceToDevice, c.s));
   SGTT_HIP(hipMemcpyAsync(out->core2, x.c2, sizeof(double) * x.n_c2(), hipMemcpyDeviceToDevice, c.s));
   SGTT_HIP(hipMemcpyAsync(out->core3, x.c3, sizeof(double) * x.n_c3(), hipMemcpyDeviceToDevice, c.s));
-  out->r1 = x.r1;
-  out->r2 = x.r2;
+  set_ranks(c, out, x.r1, x.r2);
 }
 
 void write_pair(Ctx& c, const Vec& v, sgtt_tt_pair* out) {
@@ -1093,6 +1195,8 @@ PrecOpts prec_opts(const sgtt_solve_opts* o) {
     p.precision = o->precision;
     if (o->schur < 0 || o->schur > 1) throw SgttError(-1, "invalid schur option");
     p.schur = o->schur;
+    if (o->graph < 0 || o->graph > 1) throw SgttError(-1, "invalid graph option");
+    p.graph = o->graph == 1;
   }
   return p;
 }
@@ -1116,6 +1220,7 @@ sgtt_solve_opts default_opts() {
   o.cycle_rhs_factor = 0.0;
   o.inner_mode = 0;
   o.schur = 0;
+  o.graph = 0;
   return o;
 }
 
@@ -1758,6 +1863,7 @@ int sgtt_bcr_apply_noalloc(sgtt_system* S, int which, int variant, int ncols, co
 int sgtt_round(sgtt_context* ctx, sgtt_tt* x, double eps, int max_rank) {
   if (!ctx || !x) return SGTT_E_INVALID;
   return guarded(ctx, [&]() {
+    check_dtype(*x);
     if (x->r1 < 1 || x->r2 < 1 || x->r1 > x->cap1 || x->r2 > x->cap2) throw SgttError(-1, "invalid TT");
     TT v = tt_view(x->n1, x->n2, x->n3, x->r1, x->r2, x->core1, x->core2, x->core3);
     TT r = tt_round(ctx->c, v, eps, nullptr, nullptr, max_rank > 0 ? max_rank : RANK_CAP_LARGE);
@@ -1789,6 +1895,7 @@ int sgtt_axpby(sgtt_context* ctx, double alpha, const sgtt_tt_pair* x, double be
 int sgtt_expand(sgtt_context* ctx, const sgtt_tt* x, double* out) {
   if (!ctx || !x || !out) return SGTT_E_INVALID;
   return guarded(ctx, [&]() {
+    check_dtype(*x);
     TT v = tt_view(x->n1, x->n2, x->n3, x->r1, x->r2, x->core1, x->core2, x->core3);
     tt_expand(ctx->c, v, out);
     ctx->c.sync();
@@ -1843,6 +1950,7 @@ int sgtt_pair_save(sgtt_context* ctx, const sgtt_tt_pair* x, const char* path) {
     std::vector<double> host[6];
     for (int q = 0; q < 2; ++q) {
       const sgtt_tt& a = *t[q];
+      check_dtype(a);
       if (a.r1 < 1 || a.r2 < 1 || a.r1 > a.cap1 || a.r2 > a.cap2 || !a.core1 || !a.core2 || !a.core3)
         throw SgttError(SGTT_E_INVALID, "checkpoint: invalid TT");
       const int d[5] = {a.n1, a.n2, a.n3, a.r1, a.r2};
@@ -1874,6 +1982,7 @@ int sgtt_pair_load(sgtt_context* ctx, const char* path, sgtt_tt_pair* x) {
     double* cores[6];
     for (int q = 0; q < 2; ++q) {
       const sgtt_tt& a = *t[q];
+      check_dtype(a);
       if (a.cap1 < 1 || a.cap2 < 1 || !a.core1 || !a.core2 || !a.core3)
         throw SgttError(SGTT_E_INVALID, "checkpoint: invalid destination TT");
       const int c[5] = {a.n1, a.n2, a.n3, a.cap1, a.cap2};
@@ -1897,8 +2006,7 @@ int sgtt_pair_load(sgtt_context* ctx, const char* path, sgtt_tt_pair* x) {
       for (int w = 0; w < 3; ++w)
         SGTT_HIP(hipMemcpyAsync(dst[w], host[3 * q + w].data(), sizeof(double) * len[w], hipMemcpyHostToDevice,
                                 ctx->c.s));
-      a.r1 = r1;
-      a.r2 = r2;
+      set_ranks(ctx->c, &a, r1, r2);
     }
     ctx->c.sync();
   });
@@ -1940,7 +2048,8 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
     throw SgttError(-1, "invalid solve options");
   double t0 = now_s();
   long r0 = c.roundings + side_roundings(c);
-  const long a0 = c.pool.device_allocs() + kernel_device_allocs() + side_device_allocs(c);
+  const long a0 = c.pool.device_allocs() + kernel_device_allocs() + side_device_allocs(c) + S->mg_allocs;
+  const long g0 = S->mg_launches;
   SolveCounters cnt;
   cnt.verbose = o.verbose;
   cnt.t_start = t0;
@@ -2022,7 +2131,9 @@ int solve_internal(sgtt_system* S, const Vec& bv, const sgtt_solve_opts& o, Vec&
     stats->learned_calls = S->mlp_calls;
     stats->learned_fallback = S->mlp_off ? 1 : 0;
     stats->f32_applications = cnt.f32_applications;
-    stats->device_allocs = c.pool.device_allocs() + kernel_device_allocs() + side_device_allocs(c) - a0;
+    stats->device_allocs =
+        c.pool.device_allocs() + kernel_device_allocs() + side_device_allocs(c) + S->mg_allocs - a0;
+    stats->graph_launches = S->mg_launches - g0;
   }
   return rel > o.tol ? SGTT_W_NOT_CONVERGED : SGTT_OK;
 }
@@ -2143,7 +2254,7 @@ int sgtt_picard(sgtt_context* ctx, const sgtt_problem_desc* desc, const sgtt_pic
     int i = 0;
     for (;;) {
       // lines 6-7: convection matrix and nonlinear residual of the current iterate
-      sgtt_tt_pair prior;
+      sgtt_tt_pair prior{};
       for (int q = 0; q < 2; ++q) {
         sgtt_tt& t = q == 0 ? prior.u : prior.p;
         const TT& src = cur.c[q];

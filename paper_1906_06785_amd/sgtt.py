@@ -30,7 +30,10 @@ SGTT_E_RANK_CAP = -4
 class SgttTT(C.Structure):
     _fields_ = [("n1", C.c_int), ("n2", C.c_int), ("n3", C.c_int), ("r1", C.c_int), ("r2", C.c_int),
                 ("cap1", C.c_int), ("cap2", C.c_int), ("core1", C.c_void_p), ("core2", C.c_void_p),
-                ("core3", C.c_void_p)]
+                ("core3", C.c_void_p), ("dtype", C.c_int), ("d_ranks", C.c_void_p)]
+
+
+SGTT_DTYPE_F64 = 0
 
 
 class SgttPair(C.Structure):
@@ -57,7 +60,7 @@ class SolveOpts(C.Structure):
                 ("inner_eps", C.c_double), ("inner_maxit", C.c_int), ("verbose", C.c_int),
                 ("outer_explicit", C.c_int), ("inner_explicit", C.c_int), ("relax", C.c_int),
                 ("precision", C.c_int), ("inner_rhs_eps", C.c_double), ("cycle_rhs_factor", C.c_double),
-                ("inner_mode", C.c_int), ("schur", C.c_int)]
+                ("inner_mode", C.c_int), ("schur", C.c_int), ("graph", C.c_int)]
 
 
 PICARD_MAX_STEPS = 16
@@ -110,7 +113,7 @@ class SolveStats(C.Structure):
                 ("max_rank_krylov_p", C.c_int), ("roundings", C.c_int), ("t_apply", C.c_double),
                 ("t_round", C.c_double), ("t_precond", C.c_double), ("t_residual", C.c_double),
                 ("learned_calls", C.c_int), ("learned_fallback", C.c_int), ("device_allocs", C.c_long),
-                ("f32_applications", C.c_int)]
+                ("f32_applications", C.c_int), ("graph_launches", C.c_long)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -218,13 +221,13 @@ def make_desc(cfg: dict, eps_conv=1e-3, eps_rhs=1e-6) -> ProblemDesc:
 def make_opts(**kw) -> SolveOpts:
     d = dict(tol=1e-8, eps_krylov=1e-6, tol_cycle=1e-4, restart=30, max_cycles=8, inner_tol=1e-1,
              inner_eps=1e-3, inner_maxit=20, verbose=0, outer_explicit=1, inner_explicit=0, relax=0, precision=0,
-             inner_rhs_eps=0.0, cycle_rhs_factor=0.0, inner_mode=0, schur=0)
+             inner_rhs_eps=0.0, cycle_rhs_factor=0.0, inner_mode=0, schur=0, graph=0)
     d.update(kw)
     return SolveOpts(d["tol"], d["eps_krylov"], d["tol_cycle"], int(d["restart"]), int(d["max_cycles"]),
                      d["inner_tol"], d["inner_eps"], int(d["inner_maxit"]), int(d["verbose"]),
                      int(d["outer_explicit"]), int(d["inner_explicit"]), int(d["relax"]), int(d["precision"]),
                      float(d["inner_rhs_eps"]), float(d["cycle_rhs_factor"]), int(d["inner_mode"]),
-                     int(d["schur"]))
+                     int(d["schur"]), int(d["graph"]))
 
 
 # ------------------------------------------------------------------ host-only
@@ -319,11 +322,13 @@ class TTBuf:
         self.c1 = torch.zeros(n1 * cap1, dtype=torch.float64, device=device)
         self.c2 = torch.zeros(cap1 * n2 * cap2, dtype=torch.float64, device=device)
         self.c3 = torch.zeros(n3 * cap2, dtype=torch.float64, device=device)
+        # live ranks mirrored in device memory by every call that writes this TT
+        self.d_ranks = torch.zeros(2, dtype=torch.int32, device=device)
         self.r1 = self.r2 = 1
 
     def struct(self) -> SgttTT:
         return SgttTT(self.n1, self.n2, self.n3, self.r1, self.r2, self.cap1, self.cap2, self.c1.data_ptr(),
-                      self.c2.data_ptr(), self.c3.data_ptr())
+                      self.c2.data_ptr(), self.c3.data_ptr(), SGTT_DTYPE_F64, self.d_ranks.data_ptr())
 
     def update(self, s: SgttTT):
         self.r1, self.r2 = s.r1, s.r2

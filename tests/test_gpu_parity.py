@@ -83,6 +83,47 @@ def test_axpby_is_the_exact_sum(sg, ctx, tiny):
     assert all(np.array_equal(a, b) for a, b in zip(before, after))
 
 
+def test_device_ranks_follow_every_output(sg, ctx, tiny):
+    # sgtt_tt.d_ranks: every call that writes a TT also stores its live ranks
+    # in device memory, ordered on the stream after the cores
+    import ctypes
+    P, S = tiny
+    _flush("device ranks tiny")
+
+    def dev(t):
+        return tuple(t.d_ranks.cpu().tolist())
+
+    x = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (3, 7), (2, 5), 5)
+    y = random_tt_pair(P.nt, P.n_xi, P.n_u, P.n_p, (2, 9), (3, 4), 6)
+    bx, by = _pair_buf(S, x), _pair_buf(S, y)
+    ctx.axpby(1.0, bx, 2.0, by)
+    assert (dev(by.u), dev(by.p)) == ((5, 16), (5, 9)) == by.ranks
+    ctx.round(by.u, 1e-3)
+    assert dev(by.u) == (by.u.r1, by.u.r2)
+    assert by.u.r2 < 16
+    b = S.rhs()
+    assert (dev(b.u), dev(b.p)) == b.ranks
+    z, st, rc = S.solve(b, tol=1e-10)
+    assert rc == 0 and st["rel_residual"] <= 1e-10
+    assert (dev(z.u), dev(z.p)) == z.ranks
+    # without a device copy (NULL) the output is written as before
+    bz = _pair_buf(S, x)
+    s = bz.struct()
+    s.u.d_ranks = None
+    s.p.d_ranks = None
+    ctx.check(sg._lib.sgtt_axpby(ctx._c, 1.0, ctypes.byref(bx.struct()), 1.0, ctypes.byref(s)))
+    assert (s.u.r1, s.u.r2, s.p.r1, s.p.r2) == (6, 14, 4, 10)
+    assert dev(bz.u) == (0, 0)
+    # a TT of another element type is refused and nothing is written
+    s = by.struct()
+    s.u.dtype = 1
+    before = dev(by.u)
+    with pytest.raises(sg.SgttError) as ei:
+        ctx.check(sg._lib.sgtt_axpby(ctx._c, 1.0, ctypes.byref(bx.struct()), 1.0, ctypes.byref(s)))
+    assert ei.value.code == -1
+    assert (s.u.r1, s.u.r2) == (by.u.r1, by.u.r2) and dev(by.u) == before
+
+
 @pytest.mark.parametrize("n,ranks,eps", [((10, 6, 2992), (8, 24), 1e-3), ((10, 6, 2992), (8, 24), 1e-6),
                                          ((128, 35, 3000), (12, 40), 1e-6), ((7, 5, 137), (5, 9), 0.3)])
 def test_round_error_bound_and_ranks(sg, ctx, n, ranks, eps):
