@@ -485,8 +485,10 @@ def picard_direct(prob, steps, eps_conv=None):
     iterate (eq. 3.15), and adds the update.  Returns the full iterates
     [(U_i, P_i)] and the norms ||r^(i)|| / ||f|| of the nonlinear residual
     of each iterate (i = 0..steps).  Glue around pinned pieces (direct
-    solves, exact residual TTs, convection operator); the loop itself is
-    parity unpinned."""
+    solves, exact residual TTs, convection operator); the loop is pinned by
+    the fixed-point identity of Picard's method: every iterate after the
+    first solves the Oseen equations with the previous iterate's wind
+    frozen."""
     f = prob.rhs(None)
     fnorm = np.sqrt(tt.tt_dot(f[0], f[0]) + tt.tt_dot(f[1], f[1]))
     U, Pp = prob.solve_direct(tt.full(f[0]), tt.full(f[1]))

@@ -309,6 +309,33 @@ def test_picard_direct_contracts(tiny):
     assert all(res[i + 1] < 0.2 * res[i] for i in range(3))
 
 
+def test_picard_direct_iterates_solve_the_frozen_wind_equations(tiny):
+    # Alg. 3.1 in residual form (eq. 3.14-3.15) with exact solves is the
+    # fixed-point iteration whose iterate i+1 solves the Oseen equations with
+    # the wind of iterate i frozen: tau^-1 (I - C) M u + A u + N(w_i) u +
+    # B^T p = 0 on the free velocity rows and B u = 0, for u the whole
+    # velocity (Dirichlet lift included).  The nonlinear residual of iterate
+    # i+1 plus N(w_{i+1}) w_{i+1} minus N(w_i) w_{i+1} is that Oseen residual
+    # and must vanish; an update added with the wrong sign, a residual taken
+    # at the wrong iterate or an update solved with the wrong wind fails it.
+    from oracle.solver import picard_direct
+    from oracle.system import Convection
+    P = tiny
+    its, res = picard_direct(P, 2)
+    f = P.rhs(None)
+    fn = np.sqrt(tt.tt_dot(f[0], f[0]) + tt.tt_dot(f[1], f[1]))
+    priors = [(tt.tt_svd(U, 1e-15), tt.tt_svd(Pp, 1e-15)) for U, Pp in its]
+    for i in range(2):
+        wi, wj = P.wind(priors[i]), P.wind(priors[i + 1])
+        ru, rp = P.residual_tt(priors[i + 1])
+        oseen = (tt.full(ru) + tt.full(Convection(P, wj).ttm_apply(wj, which="fall"))
+                 - tt.full(Convection(P, wi).ttm_apply(wj, which="fall")))
+        assert np.linalg.norm(oseen) <= 1e-10 * fn
+        assert np.linalg.norm(tt.full(rp)) <= 1e-10 * fn
+        # the nonlinear residual itself does not vanish before convergence
+        assert np.linalg.norm(tt.full(ru)) >= 1e-6 * fn
+
+
 def test_exact_mean_solve_inverts_mean_matrix(tiny):
     # (F_0 + C) applied to the exact mean solve gives back the right-hand side
     from oracle.solver import MeanLSC
