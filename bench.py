@@ -225,8 +225,8 @@ def solve_options(args=None):
 # of known size): bytes per launch, valid while the kernel source it was
 # measured on is unchanged (digest of the block cyclic reduction section of
 # kernels.hip and of the host factorization).  None until measured.
-TRAFFIC_RECORD = {"kernel_src_sha256": "030b5e26a1b2bebb51c96c049fec94e251b5421c25faf07ae0f233fbfbbfad93",
-                  "bytes_per_launch": 13208483, "fetch_bytes_per_launch": 10661427, "write_bytes_per_launch": 2547056,
+TRAFFIC_RECORD = {"kernel_src_sha256": "cae3f723e8c5094ffe4413c530815acbbf7cf3b324979e96d5504c72d8b5531e",
+                  "bytes_per_launch": 13232081, "fetch_bytes_per_launch": 10681044, "write_bytes_per_launch": 2551037,
                   "summary": "profiles/k_bcr_c2_stokes_traffic.md"}
 
 
