@@ -573,6 +573,9 @@ def main():
             "max_krylov_rank_u": v_stats[-1]["max_rank_krylov_u"],
             "f32_applications": v_stats[-1]["f32_applications"],
             "graph_launches": v_stats[-1]["graph_launches"],
+            "kernels_note": ("the mean solve's time loop ran as graph launches, which the per-class breakdown does "
+                             "not attribute (its mass products and BCR passes are missing below)")
+            if vp_st["graph_launches"] else None,
             "kernels": {k: {"ms": v["seconds"] * 1e3, "launches": v["launches"]} for k, v in v_breakdown.items()
                         if v["launches"]}}
     res = {

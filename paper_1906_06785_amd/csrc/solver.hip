@@ -1173,6 +1173,8 @@ void write_tt(Ctx& c, const TT& x, sgtt_tt* out) {
 }
 
 void write_pair(Ctx& c, const Vec& v, sgtt_tt_pair* out) {
+  check_dtype(out->u);
+  check_dtype(out->p);
   if (v.c[0].r1 > out->u.cap1 || v.c[0].r2 > out->u.cap2 || v.c[1].r1 > out->p.cap1 || v.c[1].r2 > out->p.cap2)
     throw SgttError(-4, "result rank exceeds output capacity");
   write_tt(c, v.c[0], &out->u);

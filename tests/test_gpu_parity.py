@@ -122,6 +122,15 @@ def test_device_ranks_follow_every_output(sg, ctx, tiny):
         ctx.check(sg._lib.sgtt_axpby(ctx._c, 1.0, ctypes.byref(bx.struct()), 1.0, ctypes.byref(s)))
     assert ei.value.code == -1
     assert (s.u.r1, s.u.r2) == (by.u.r1, by.u.r2) and dev(by.u) == before
+    # an output pair whose pressure TT has another element type: neither TT
+    # of the pair is written
+    bo = S.pair(16, 128)
+    s = bo.struct()
+    s.p.dtype = 1
+    with pytest.raises(sg.SgttError) as ei:
+        ctx.check(sg._lib.sgtt_rhs(S._s, ctypes.byref(s)))
+    assert ei.value.code == -1
+    assert (s.u.r1, s.u.r2) == (1, 1) and dev(bo.u) == (0, 0)
 
 
 @pytest.mark.parametrize("n,ranks,eps", [((10, 6, 2992), (8, 24), 1e-3), ((10, 6, 2992), (8, 24), 1e-6),
