@@ -328,6 +328,61 @@ def cpu_baseline(cfg, budget, gpu_outer_per_solve, inner_mode=1, system=None):
     return res
 
 
+def c1_whole_solves(sgtt, ctx, opts, reps=3):
+    """Whole solves of the C1 Stokes system (h = 1/4, 207,180 unknowns), where
+    the oracle finishes in seconds: the oracle's low-rank FGMRES with the same
+    preconditioner velocity block as the GPU line, one warm-up and the median
+    of reps with all BLAS threads, one solve with one thread; the library's
+    solve of the same system with the same options on the GPU, one warm-up and
+    the median of reps (wall time around sgtt_solve, which returns after its
+    stream is done)."""
+    import statistics
+
+    import torch
+
+    from oracle.solver import solve_tt
+    from oracle.system import Problem
+    from synthetic_inputs import CONFIGS
+    cfg = CONFIGS["C1"]
+    velocity = ORACLE_VELOCITY[opts["inner_mode"]]
+    P = Problem(cfg)
+    bo = P.rhs()
+    cpu, outer_cpu = [], 0
+    for i in range(reps + 1):
+        t0 = time.perf_counter()
+        _, st = solve_tt(P, bo, velocity=velocity)
+        if i:
+            cpu.append(time.perf_counter() - t0)
+        outer_cpu = st["outer"]
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            solve_tt(P, bo, velocity=velocity)
+            one = time.perf_counter() - t0
+    except ImportError:
+        pass
+    S1 = sgtt.System(ctx, cfg)
+    b1 = S1.rhs()
+    x1 = S1.pair(*OUT_CAPS)
+    S1.solve(b1, x1, **opts)   # warm-up: tunes the spatial solves of this system
+    gpu, st1 = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st1, _ = S1.solve(b1, x1, **opts)
+        torch.cuda.synchronize()
+        gpu.append(time.perf_counter() - t0)
+    med_cpu, med_gpu = statistics.median(cpu), statistics.median(gpu)
+    return {"workload": f"Stokes system at C1 ({cfg_name(cfg)}, {int(P.nt * P.n_xi * (P.n_u + P.n_p))} "
+                        f"unknowns), tol 1e-8, same preconditioner velocity block ({velocity})",
+            "oracle_seconds_median": med_cpu, "oracle_seconds": cpu, "oracle_single_thread_seconds": one,
+            "oracle_outer_iters": outer_cpu, "gpu_seconds_median": med_gpu, "gpu_seconds": gpu,
+            "gpu_outer_iters": st1["outer_iters"], "gpu_rel_residual": st1["rel_residual"],
+            "gpu_speedup_vs_oracle": med_cpu / med_gpu}
+
+
 def cfg_name(cfg):
     return f"h={cfg['h']:g} m={cfg['m']} p={cfg['p']} nt={cfg['nt']}"
 
@@ -620,6 +675,13 @@ def main():
                                                None if args.system == "stokes" else "picard1")
         except Exception as e:  # the baseline is informative only
             res["cpu_baseline"] = {"error": repr(e)}
+        if args.config == "C2" and args.system == "stokes":
+            # like for like at a size both sides solve whole
+            try:
+                res["cpu_baseline"]["c1_whole_solves"] = c1_whole_solves(sgtt, ctx, opts)
+            except Exception as e:
+                res["cpu_baseline"]["c1_whole_solves"] = {"error": repr(e)}
+            progress("C1 whole solves on both sides")
     if jsonl is not None:
         jsonl.close()
     print(json.dumps(res), flush=True)
