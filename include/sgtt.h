@@ -521,6 +521,21 @@ int sgtt_mlp_size(const sgtt_mlp* mlp, long* nparam, long* npairs);
  * weights to FP16 and resets the optimizer state) */
 int sgtt_mlp_set_params(sgtt_mlp* mlp, const float* host);
 int sgtt_mlp_get_params(sgtt_mlp* mlp, float* host);
+/* Parameter files of a trained network (a learned correction is trained once
+ * and reused): magic tag, version, n, width, nparam, the FP32 parameters in
+ * the order above, an FNV-1a hash; written under a temporary name and
+ * renamed.  sgtt_mlp_load checks the shape (SGTT_E_INVALID for a network of
+ * another n or width) and the hash (SGTT_E_IO, also for a missing, cut or
+ * foreign file) before it changes the network; it then sets the parameters
+ * as sgtt_mlp_set_params does.  Host-only forms need no context:
+ * sgtt_mlp_file_info reads the header (hash not checked),
+ * sgtt_mlp_file_read_host reads the parameters of a network of the given
+ * shape into host memory (unchanged on error). */
+int sgtt_mlp_save(sgtt_mlp* mlp, const char* path);
+int sgtt_mlp_load(sgtt_mlp* mlp, const char* path);
+int sgtt_mlp_file_write_host(const char* path, int n, int width, const float* params);
+int sgtt_mlp_file_info(const char* path, int* n, int* width, long* nparam);
+int sgtt_mlp_file_read_host(const char* path, int n, int width, float* params);
 /* y = MLP(x) for batch host columns (column s at x + s*n): FP16 weights
  * widened to FP32 against FP32 activations on the FP32 matrix cores (the
  * form training differentiates) */

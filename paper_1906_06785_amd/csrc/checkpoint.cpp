@@ -1,5 +1,6 @@
 // Checkpoint files of a TT pair (the Picard iterate of Alg. 3.1 is the
-// natural restart point): host-side format, written and read with stdio.
+// natural restart point) and parameter files of the learned correction's
+// network: host-side formats, written and read with stdio.
 //
 // Layout, little-endian:
 //   8 bytes  "SGTTPAIR"
@@ -162,9 +163,110 @@ int pair_file_read(const char* path, const int* caps, double* const* cores, int*
   return SGTT_OK;
 }
 
+// ---------------------------------------------------------------- networks
+// Parameter files of the learned correction's network, little-endian:
+//   8 bytes  "SGTTMLPN"
+//   uint32   format version (1)
+//   int32    n (input and output length), width (hidden layer width)
+//   int64    nparam = w n + w + w w + w + n w + n
+//   nparam   IEEE float32 parameters [W1, b1, W2, b2, W3, b3], row-major
+//   uint64   FNV-1a hash of every byte above
+namespace {
+constexpr char kNetMagic[8] = {'S', 'G', 'T', 'T', 'M', 'L', 'P', 'N'};
+
+long net_params(long n, long w) { return w * n + w + w * w + w + n * w + n; }
+
+bool net_dims_valid(long n, long w, long np) {
+  return n >= 1 && w >= 1 && n < kMaxDim && w < kMaxDim && np == net_params(n, w) && np < (1L << 40);
+}
+
+int read_net_header(FILE* f, Fnv& h, int* n, int* w, long* np) {
+  char magic[8];
+  uint32_t ver = 0;
+  int32_t d[2];
+  int64_t p = 0;
+  if (!read_all(f, h, magic, 8) || std::memcmp(magic, kNetMagic, 8) != 0) return SGTT_E_IO;
+  if (!read_all(f, h, &ver, 4) || ver != kVersion) return SGTT_E_IO;
+  if (!read_all(f, h, d, sizeof(d)) || !read_all(f, h, &p, 8)) return SGTT_E_IO;
+  if (!net_dims_valid(d[0], d[1], (long)p)) return SGTT_E_IO;
+  *n = d[0];
+  *w = d[1];
+  *np = (long)p;
+  return SGTT_OK;
+}
+}  // namespace
+
+int net_file_write(const char* path, int n, int w, long nparam, const float* params) {
+  if (!path || !params || !net_dims_valid(n, w, nparam)) return SGTT_E_INVALID;
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    File f(std::fopen(tmp.c_str(), "wb"));
+    if (!f) return SGTT_E_IO;
+    Fnv h;
+    const uint32_t ver = kVersion;
+    const int32_t d[2] = {n, w};
+    const int64_t p = nparam;
+    bool ok = write_all(f.get(), h, kNetMagic, 8) && write_all(f.get(), h, &ver, 4) &&
+              write_all(f.get(), h, d, sizeof(d)) && write_all(f.get(), h, &p, 8) &&
+              write_all(f.get(), h, params, sizeof(float) * (size_t)nparam);
+    const uint64_t sum = h.h;
+    ok = ok && std::fwrite(&sum, 1, 8, f.get()) == 8;
+    ok = ok && std::fflush(f.get()) == 0;
+    if (!ok) {
+      f.reset();
+      std::remove(tmp.c_str());
+      return SGTT_E_IO;
+    }
+  }
+  if (std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return SGTT_E_IO;
+  }
+  return SGTT_OK;
+}
+
+int net_file_info(const char* path, int* n, int* w, long* nparam) {
+  if (!path || !n || !w || !nparam) return SGTT_E_INVALID;
+  File f(std::fopen(path, "rb"));
+  if (!f) return SGTT_E_IO;
+  Fnv h;
+  return read_net_header(f.get(), h, n, w, nparam);
+}
+
+int net_file_read(const char* path, int n, int w, float* params) {
+  if (!path || !params || n < 1 || w < 1) return SGTT_E_INVALID;
+  File f(std::fopen(path, "rb"));
+  if (!f) return SGTT_E_IO;
+  Fnv h;
+  int fn = 0, fw = 0;
+  long np = 0;
+  const int st = read_net_header(f.get(), h, &fn, &fw, &np);
+  if (st != SGTT_OK) return st;
+  if (fn != n || fw != w) return SGTT_E_INVALID;   // a network of another shape
+  // staging first: the caller's parameters change only after the hash check
+  std::vector<float> stage((size_t)np);
+  if (!read_all(f.get(), h, stage.data(), sizeof(float) * stage.size())) return SGTT_E_IO;
+  uint64_t sum = 0;
+  if (std::fread(&sum, 1, 8, f.get()) != 8 || sum != h.h) return SGTT_E_IO;
+  std::memcpy(params, stage.data(), sizeof(float) * stage.size());
+  return SGTT_OK;
+}
+
 }  // namespace sgtt
 
 extern "C" {
+
+int sgtt_mlp_file_write_host(const char* path, int n, int width, const float* params) {
+  return sgtt::net_file_write(path, n, width, sgtt::net_params(n, width), params);
+}
+
+int sgtt_mlp_file_info(const char* path, int* n, int* width, long* nparam) {
+  return sgtt::net_file_info(path, n, width, nparam);
+}
+
+int sgtt_mlp_file_read_host(const char* path, int n, int width, float* params) {
+  return sgtt::net_file_read(path, n, width, params);
+}
 
 int sgtt_pair_file_write_host(const char* path, const int* dims, const double* const* cores) {
   return sgtt::pair_file_write(path, dims, cores);

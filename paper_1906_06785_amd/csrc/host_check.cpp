@@ -143,6 +143,23 @@ int main(int argc, char** argv) {
   }
   check(pair_file_read(path.c_str(), dims, rp, got) == SGTT_E_IO, "damaged checkpoint refused");
   std::remove(path.c_str());
+  // network parameter files
+  {
+    const int n = 37, w = 5;
+    const long np = (long)w * n + w + w * w + w + (long)n * w + n;
+    std::vector<float> par(np), bk(np, 0.f);
+    for (float& v : par) v = (float)nd(rng);
+    const std::string npath = dir + "/host_check.sgmlp";
+    check(net_file_write(npath.c_str(), n, w, np, par.data()) == SGTT_OK, "network file written");
+    int fn = 0, fw = 0;
+    long fp = 0;
+    check(net_file_info(npath.c_str(), &fn, &fw, &fp) == SGTT_OK && fn == n && fw == w && fp == np,
+          "network file header");
+    check(net_file_read(npath.c_str(), n, w, bk.data()) == SGTT_OK && bk == par, "network round trip bit-exact");
+    check(net_file_read(npath.c_str(), n + 1, w, bk.data()) == SGTT_E_INVALID, "network of another shape refused");
+    check(net_file_write(npath.c_str(), n, w, np + 1, par.data()) == SGTT_E_INVALID, "inconsistent count refused");
+    std::remove(npath.c_str());
+  }
   std::printf("%d failures\n", failures);
   return failures ? 1 : 0;
 }

@@ -2362,6 +2362,33 @@ int sgtt_mlp_get_params(sgtt_mlp* m, float* host) {
   return guarded(m->ctx, [&]() { mlp_get_params(*m->m, host); });
 }
 
+int sgtt_mlp_save(sgtt_mlp* m, const char* path) {
+  if (!m || !path) return SGTT_E_INVALID;
+  int st = SGTT_OK;
+  const int g = guarded(m->ctx, [&]() {
+    std::vector<float> p(m->m->nparam);
+    mlp_get_params(*m->m, p.data());
+    st = net_file_write(path, m->m->n, m->m->w, (long)m->m->nparam, p.data());
+    if (st != SGTT_OK) m->ctx->err = std::string("network file: cannot write ") + path;
+  });
+  return g != SGTT_OK ? g : st;
+}
+
+int sgtt_mlp_load(sgtt_mlp* m, const char* path) {
+  if (!m || !path) return SGTT_E_INVALID;
+  int st = SGTT_OK;
+  const int g = guarded(m->ctx, [&]() {
+    std::vector<float> p(m->m->nparam);
+    st = net_file_read(path, m->m->n, m->m->w, p.data());
+    if (st != SGTT_OK) {
+      m->ctx->err = std::string("network file: cannot load ") + path;
+      return;
+    }
+    mlp_set_params(*m->m, p.data());
+  });
+  return g != SGTT_OK ? g : st;
+}
+
 int sgtt_mlp_forward(sgtt_mlp* m, const float* x, int batch, float* y) {
   if (!m || !x || !y || batch < 1) return SGTT_E_INVALID;
   return guarded(m->ctx, [&]() { mlp_forward_host(*m->m, x, batch, y, false); });

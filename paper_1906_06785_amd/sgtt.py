@@ -147,6 +147,11 @@ _sig = {
     "sgtt_pair_load": (C.c_int, [_P, C.c_char_p, C.POINTER(SgttPair)]),
     "sgtt_pair_file_write_host": (C.c_int, [C.c_char_p, C.POINTER(C.c_int), C.POINTER(C.c_void_p)]),
     "sgtt_pair_file_info": (C.c_int, [C.c_char_p, C.POINTER(C.c_int)]),
+    "sgtt_mlp_save": (C.c_int, [_P, C.c_char_p]),
+    "sgtt_mlp_load": (C.c_int, [_P, C.c_char_p]),
+    "sgtt_mlp_file_write_host": (C.c_int, [C.c_char_p, C.c_int, C.c_int, _P]),
+    "sgtt_mlp_file_info": (C.c_int, [C.c_char_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_long)]),
+    "sgtt_mlp_file_read_host": (C.c_int, [C.c_char_p, C.c_int, C.c_int, _P]),
     "sgtt_pair_file_read_host": (C.c_int, [C.c_char_p, C.POINTER(C.c_int), C.POINTER(C.c_void_p),
                                            C.POINTER(C.c_int)]),
     "sgtt_expand": (C.c_int, [_P, C.POINTER(SgttTT), _P]),
@@ -671,6 +676,14 @@ class Mlp:
         self.ctx.check(_lib.sgtt_mlp_get_params(self._m, flat.ctypes.data_as(C.POINTER(C.c_float))))
         return self.split(flat)
 
+    def save(self, path: str):
+        """Write the parameters to a network file (sgtt_mlp_save)."""
+        self.ctx.check(_lib.sgtt_mlp_save(self._m, os.fsencode(path)))
+
+    def load(self, path: str):
+        """Set the parameters from a network file of the same shape."""
+        self.ctx.check(_lib.sgtt_mlp_load(self._m, os.fsencode(path)))
+
     def forward(self, X, f16: bool = False):
         """X: (n, B) -> (n, B) float32; f16 runs the products on FP16
         operands (the preconditioner's form)."""
@@ -759,6 +772,35 @@ def picard(ctx: Context, cfg: dict, steps: int = 5, tol_picard: float = 1e-5, ep
     rc = ctx.check(_lib.sgtt_picard(ctx._c, C.byref(d), C.byref(o), C.byref(so), C.byref(st)))
     out.update(so)
     return out, st.as_dict(), rc
+
+
+def mlp_file_info(path: str):
+    """(n, width, nparam) of a network file; raises SgttError for a missing
+    or foreign file."""
+    n, w, npar = C.c_int(), C.c_int(), C.c_long()
+    rc = _lib.sgtt_mlp_file_info(os.fsencode(path), C.byref(n), C.byref(w), C.byref(npar))
+    if rc != 0:
+        raise SgttError(rc, f"network file {path}")
+    return n.value, w.value, npar.value
+
+
+def write_mlp_host(path: str, n: int, width: int, params):
+    """Write a network file from a host FP32 parameter vector."""
+    flat = np.ascontiguousarray(params, dtype=np.float32).ravel()
+    if flat.size != width * n + width + width * width + width + n * width + n:
+        raise ValueError("parameter count does not match the shape")
+    rc = _lib.sgtt_mlp_file_write_host(os.fsencode(path), n, width, flat.ctypes.data)
+    if rc != 0:
+        raise SgttError(rc, f"network file {path}")
+
+
+def read_mlp_host(path: str, n: int, width: int):
+    """FP32 parameters of a network file of the given shape (host)."""
+    flat = np.zeros(width * n + width + width * width + width + n * width + n, dtype=np.float32)
+    rc = _lib.sgtt_mlp_file_read_host(os.fsencode(path), n, width, flat.ctypes.data)
+    if rc != 0:
+        raise SgttError(rc, f"network file {path}")
+    return flat
 
 
 def pair_file_info(path: str):

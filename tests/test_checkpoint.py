@@ -72,3 +72,48 @@ def test_refusals(tmp_path):
     assert e.value.code == -7
     # the header alone is checked by info (the hash needs the whole file)
     assert sg.pair_file_info(str(tmp_path / "flipped")) == ((5, 3, 40, 2, 4), (5, 3, 7, 3, 2))
+
+
+def _net(seed, n=40, w=8):
+    g = np.random.default_rng(seed)
+    return g.standard_normal(w * n + w + w * w + w + n * w + n).astype(np.float32)
+
+
+def test_network_file_round_trip_and_refusals(tmp_path):
+    # parameter files of the learned correction's network
+    sg = _lib()
+    p = _net(3)
+    f = str(tmp_path / "net.sgmlp")
+    sg.write_mlp_host(f, 40, 8, p)
+    assert not os.path.exists(f + ".tmp")
+    assert sg.mlp_file_info(f) == (40, 8, p.size)
+    assert np.array_equal(sg.read_mlp_host(f, 40, 8), p)
+    raw = open(f, "rb").read()
+    assert len(raw) == 8 + 4 + 8 + 8 + 4 * p.size + 8
+    # another shape is refused as an invalid argument
+    for n, w in ((41, 8), (40, 9)):
+        with pytest.raises(sg.SgttError) as e:
+            sg.read_mlp_host(f, n, w)
+        assert e.value.code == -1
+    # a flipped byte fails the hash; a cut, foreign, pair or missing file,
+    # and a header whose parameter count does not fit its shape, are I/O errors
+    bad = bytearray(raw)
+    bad[100] ^= 0x01
+    lie = bytearray(raw)
+    lie[20] ^= 0x01   # the stored parameter count
+    pair = str(tmp_path / "iterate.sgtt")
+    sg.write_pair_host(pair, _pair(4))
+    cases = {"flipped": bytes(bad), "cut": raw[:-5], "foreign": b"not a network" * 30, "count": bytes(lie)}
+    for name, data in cases.items():
+        g = str(tmp_path / f"{name}.sgmlp")
+        open(g, "wb").write(data)
+        with pytest.raises(sg.SgttError) as e:
+            sg.read_mlp_host(g, 40, 8)
+        assert e.value.code == -7, name
+    for g in (pair, str(tmp_path / "missing.sgmlp")):
+        with pytest.raises(sg.SgttError) as e:
+            sg.read_mlp_host(g, 40, 8)
+        assert e.value.code == -7
+    with pytest.raises(sg.SgttError) as e:
+        sg.write_mlp_host(str(tmp_path / "no" / "dir" / "net.sgmlp"), 40, 8, p)
+    assert e.value.code == -7

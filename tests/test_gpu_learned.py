@@ -102,6 +102,39 @@ def test_mlp_adam_steps_match_oracle(sg, ctx):
         assert d.max() <= 6 * lr + 1e-6, k
 
 
+def test_mlp_save_and_load(sg, ctx, tmp_path):
+    # a trained network written to a file and read into another network of
+    # the same shape gives the same parameters and the same forward, on both
+    # matrix-core forms; a network of another shape refuses the file and
+    # keeps its own parameters
+    _flush("mlp save/load")
+    n, w, B = 40, 16, 9
+    net = sg.Mlp(ctx, n, w, B, 0)
+    net.set_params(_params(n, w, 7))
+    g = np.random.default_rng(8)
+    X = g.standard_normal((n, B)).astype(np.float32)
+    T = g.standard_normal((n, B)).astype(np.float32)
+    net.add_pairs(X, T)
+    net.train(2, batch=B, lr=1e-3)
+    f = str(tmp_path / "net.sgmlp")
+    net.save(f)
+    assert sg.mlp_file_info(f) == (n, w, net.size()[0])
+    other = sg.Mlp(ctx, n, w, 0, 11)
+    other.load(f)
+    a, b = net.get_params(), other.get_params()
+    assert all(np.array_equal(a[k], b[k]) for k in a)
+    assert np.array_equal(sg.read_mlp_host(f, n, w), net.flatten(a))
+    for f16 in (False, True):
+        assert np.array_equal(net.forward(X, f16), other.forward(X, f16))
+    wrong = sg.Mlp(ctx, n, w + 1, 0, 12)
+    before = wrong.get_params()
+    with pytest.raises(sg.SgttError) as e:
+        wrong.load(f)
+    assert e.value.code == -1
+    after = wrong.get_params()
+    assert all(np.array_equal(before[k], after[k]) for k in before)
+
+
 def test_learned_mean_solve_c1(sg, ctx):
     _flush("learned mean solve c1")
     cfg = CONFIGS["C1"]
