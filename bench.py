@@ -70,10 +70,11 @@ def parse(argv=None):
     ap.add_argument("--system", default="stokes", choices=("stokes", "picard1"),
                     help="stokes: the first Picard system (w = 0, Alg. 3.1 line 1); picard1: the system of "
                          "Picard step 1, assembled around the Stokes solution (untimed) as the prior iterate")
-    ap.add_argument("--compare", default="mixed_relaxed",
+    ap.add_argument("--compare", default="mixed_relaxed,graph",
                     help="comma list of solver variants timed after the main measurement with the same steps "
                          f"(names: {', '.join(sorted(VARIANTS))}; empty for none); the default times the "
-                         "mixed-precision solve the metric compares with the plain FP64 one")
+                         "mixed-precision solve the metric compares with the plain FP64 one, and the plain "
+                         "solve with the mean solve's time loop as a captured graph")
     ap.add_argument("--picard", type=int, default=0,
                     help="N > 0: instead, run Picard's method (Alg. 3.1) for N steps after the Stokes solve and print "
                          "the per-step record")
