@@ -901,8 +901,8 @@ bool mean_loop_graph(sgtt_system& S, bool f32) {
   if (!ex) {
     if (!bcr_is_tuned(S.Fbt, 2, S.nxi, f32)) return false;
     hipGraph_t gr = nullptr;
-    prof_hold_thread(true);
     SGTT_HIP(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
+    prof_hold_thread(true);
     try {
       mean_time_loop(S, c.s, f32, S.mg_W, S.mg_V);
     } catch (...) {
