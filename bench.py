@@ -238,8 +238,8 @@ def bcr_source_digest():
     per pass, from struct BcrVariant to bcr_solve_variant), the device
     layout of a factor (upload_bcr and factor_bcr in solver.hip: fragment
     order, descriptors, padding), the callers that set the layout of the
-    passes' right-hand sides (the time loop of the mean solve and the
-    time-stepped mean solves in solver.hip) and
+    passes' right-hand sides (the time loop of the mean solve, not the graph
+    capture around it, and the time-stepped mean solves in solver.hip) and
     the host factorization (bcr_factor in host_setup.cpp: block sizes,
     levels, dropped zeros)."""
     import hashlib
@@ -253,12 +253,15 @@ def bcr_source_digest():
     sol = open(os.path.join(csrc, "solver.hip")).read()
     s0 = sol.index("BcrDev upload_bcr(")
     s1 = sol.index("\n}\n", sol.index("BcrDev factor_bcr(")) + 3
-    m0 = sol.index("void mean_time_loop(")
+    l0 = sol.index("void mean_time_loop(")
+    l1 = sol.index("\n}\n", l0) + 3
+    m0 = sol.index("TT exact_mean_solve32(")
     m1 = sol.index("\n}\n", sol.index("TT exact_mean_solve(")) + 3
     host = open(os.path.join(csrc, "host_setup.cpp")).read()
     j0 = host.index("void bcr_factor(")
     j1 = host.index("void bcr_apply_host(")
-    return hashlib.sha256((src[i0:i1] + src[k0:k1] + sol[s0:s1] + sol[m0:m1] + host[j0:j1]).encode()).hexdigest()
+    return hashlib.sha256((src[i0:i1] + src[k0:k1] + sol[s0:s1] + sol[l0:l1] + sol[m0:m1] +
+                           host[j0:j1]).encode()).hexdigest()
 
 
 def recorded_traffic(dom_name):

@@ -95,3 +95,10 @@ def test_traffic_digest_follows_the_pass_kernels_and_the_factorization(tmp_path,
     # the rest of solver.hip does not count
     edit("solver.hip", "// ====================================================================== C ABI", "// note\n")
     assert bench.bcr_source_digest() == d5
+    # the time loop that lays out the passes' right-hand sides counts; the
+    # graph capture around it does not
+    edit("solver.hip", "  const long blk = (long)S.nu * nxi;\n  if (f32) {", "  // note\n")
+    d6 = bench.bcr_source_digest()
+    assert d6 != d5
+    edit("solver.hip", "bool mean_loop_graph(", "// note\n")
+    assert bench.bcr_source_digest() == d6
