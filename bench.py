@@ -226,8 +226,8 @@ def solve_options(args=None):
 # of known size): bytes per launch, valid while the kernel source it was
 # measured on is unchanged (digest of the block cyclic reduction section of
 # kernels.hip and of the host factorization).  None until measured.
-TRAFFIC_RECORD = {"kernel_src_sha256": "cae3f723e8c5094ffe4413c530815acbbf7cf3b324979e96d5504c72d8b5531e",
-                  "bytes_per_launch": 13232081, "fetch_bytes_per_launch": 10681044, "write_bytes_per_launch": 2551037,
+TRAFFIC_RECORD = {"kernel_src_sha256": "ab4b6e22b1a3b4b6ee52d6c7e0cc1ef1bfcd899b158baaafde10bb28332e78bb",
+                  "bytes_per_launch": 14435093, "fetch_bytes_per_launch": 11849973, "write_bytes_per_launch": 2585120,
                   "summary": "profiles/k_bcr_c2_stokes_traffic.md"}
 
 
