@@ -186,7 +186,9 @@ typedef struct {
                               system allocates on first use and keeps (2 n_t
                               n_xi n_u doubles); until the spatial solve's
                               kernel choices are tuned, the loop runs as
-                              plain launches.  0: plain launches          */
+                              plain launches; the results are those of the
+                              plain launches; inner modes 0 and 2 ignore
+                              it.  0: plain launches                      */
 } sgtt_solve_opts;
 
 typedef struct {
