@@ -360,7 +360,10 @@ int sgtt_solve(sgtt_system* sys, const sgtt_tt_pair* b, sgtt_tt_pair* x, const s
  * return code and stats[i] (may be NULL) its statistics.  Returns the worst
  * status, or SGTT_E_INVALID if any solve failed (see status[i] and
  * sgtt_last_error of that system's context).  A context must not be used by
- * other calls while the batch runs. */
+ * other calls while the batch runs.  With more than one context the solves
+ * of the batch run without the contexts' side lanes (second streams and
+ * host threads), whose work would queue behind the other contexts' streams
+ * on the process's few hardware queues; results are the same. */
 int sgtt_solve_batched(sgtt_system* const* systems, int n, const sgtt_tt_pair* const* b,
                        sgtt_tt_pair* const* x, const sgtt_solve_opts* opts, sgtt_solve_stats* stats,
                        int* status);

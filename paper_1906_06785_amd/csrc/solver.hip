@@ -2182,12 +2182,21 @@ int sgtt_solve_batched(sgtt_system* const* systems, int n, const sgtt_tt_pair* c
     }
     work[w].push_back(i);
   }
+  // with several contexts their streams already fill the device, and a
+  // process has few hardware queues (four by default): each context's side
+  // lanes (the pressure rounding and solution lanes) would queue behind the
+  // other contexts' main streams, so they are switched off for the batch
+  const bool lanes = ctxs.size() == 1;
   auto run = [&](size_t w) {
+    Ctx& c = ctxs[w]->c;
+    const bool was = c.side_enabled;
+    c.side_enabled = was && lanes;
     for (int i : work[w]) {
       sgtt_solve_stats st{};
       status[i] = sgtt_solve(systems[i], b[i], x[i], opts, &st);
       if (stats) stats[i] = st;
     }
+    c.side_enabled = was;
   };
   std::vector<std::thread> th;
   for (size_t w = 1; w < ctxs.size(); ++w) th.emplace_back(run, w);
