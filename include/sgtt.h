@@ -60,7 +60,9 @@ typedef struct sgtt_host_problem sgtt_host_problem;
  *   trains only (SGTT_DTYPE_F64); any other value is refused with
  *   SGTT_E_INVALID.  Reduced-precision copies (precision options of
  *   sgtt_solve_opts) live inside the library.
- * d_ranks: optional device pointer to 2 ints (NULL: none), caller-owned.
+ * d_ranks: optional device pointer to 2 ints (NULL: none), caller-owned;
+ *   memory HIP does not know (e.g. plain host memory) is refused with
+ *   SGTT_E_INVALID before anything is written.
  *   Every call that writes this TT as an output also stores (r1, r2) there,
  *   ordered on the context stream after the cores, so that work queued
  *   later on that stream can read the live ranks from device memory without

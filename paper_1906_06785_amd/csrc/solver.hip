@@ -1132,8 +1132,20 @@ double full_residual(sgtt_system& S, const Vec& b, const Vec& z, double* d_out_s
 }
 
 // ---------------------------------------------------------------- helpers for the ABI
+// element type, and the device copy of the ranks: NULL or memory that HIP
+// knows (device or pinned host), so that storing the ranks cannot fault
 void check_dtype(const sgtt_tt& t) {
   if (t.dtype != SGTT_DTYPE_F64) throw SgttError(-1, "TT element type other than FP64");
+  if (t.d_ranks) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, t.d_ranks) != hipSuccess) {
+      (void)hipGetLastError();
+      throw SgttError(-1, "d_ranks is not memory allocated through HIP");
+    }
+    const bool dev = a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+    const bool pinned = a.type == hipMemoryTypeHost && a.devicePointer;
+    if (!dev && !pinned) throw SgttError(-1, "d_ranks is not accessible from the device");
+  }
 }
 
 // live ranks of an output TT: host fields, and the caller's device copy

@@ -131,6 +131,16 @@ def test_device_ranks_follow_every_output(sg, ctx, tiny):
         ctx.check(sg._lib.sgtt_rhs(S._s, ctypes.byref(s)))
     assert ei.value.code == -1
     assert (s.u.r1, s.u.r2) == (1, 1) and dev(bo.u) == (0, 0)
+    # a device copy of the ranks in plain host memory is refused before any
+    # core is written
+    host_ranks = (ctypes.c_int * 2)(-1, -1)
+    s = by.struct()
+    s.u.d_ranks = ctypes.cast(host_ranks, ctypes.c_void_p)
+    r_before = (by.u.r1, by.u.r2)
+    with pytest.raises(sg.SgttError) as ei:
+        ctx.check(sg._lib.sgtt_axpby(ctx._c, 1.0, ctypes.byref(bx.struct()), 1.0, ctypes.byref(s)))
+    assert ei.value.code == -1
+    assert (s.u.r1, s.u.r2) == r_before and list(host_ranks) == [-1, -1]
 
 
 @pytest.mark.parametrize("n,ranks,eps", [((10, 6, 2992), (8, 24), 1e-3), ((10, 6, 2992), (8, 24), 1e-6),
