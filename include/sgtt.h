@@ -56,6 +56,9 @@ typedef struct sgtt_host_problem sgtt_host_problem;
  * core3 is the transpose of the paper's third core (eq. 4.2): row = space
  * index, so that sparse products over space read contiguous rank vectors.
  * r1, r2 are the live ranks: inputs read them, outputs write them.
+ * The cores must be device, managed or pinned host memory (as
+ * hipPointerGetAttributes reports it); any other pointer is refused with
+ * SGTT_E_INVALID before a kernel runs.
  * dtype: element type of the cores.  The boundary exchanges FP64 tensor
  *   trains only (SGTT_DTYPE_F64); any other value is refused with
  *   SGTT_E_INVALID.  Reduced-precision copies (precision options of

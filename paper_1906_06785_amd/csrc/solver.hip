@@ -1132,20 +1132,28 @@ double full_residual(sgtt_system& S, const Vec& b, const Vec& z, double* d_out_s
 }
 
 // ---------------------------------------------------------------- helpers for the ABI
-// element type, and the device copy of the ranks: NULL or memory that HIP
-// knows (device or pinned host), so that storing the ranks cannot fault
+// a caller's buffer that kernels will read or write: device, managed or
+// pinned host memory (a kernel access to memory HIP does not know faults the
+// GPU, so such a buffer is refused before anything runs)
+void check_device_ptr(const void* p, const char* what) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    throw SgttError(-1, std::string(what) + " is not memory allocated through HIP");
+  }
+  const bool dev = a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+  const bool pinned = a.type == hipMemoryTypeHost && a.devicePointer;
+  if (!dev && !pinned) throw SgttError(-1, std::string(what) + " is not accessible from the device");
+}
+
+// element type, cores and the device copy of the ranks (NULL or memory the
+// device can reach) of a caller's TT
 void check_dtype(const sgtt_tt& t) {
   if (t.dtype != SGTT_DTYPE_F64) throw SgttError(-1, "TT element type other than FP64");
-  if (t.d_ranks) {
-    hipPointerAttribute_t a;
-    if (hipPointerGetAttributes(&a, t.d_ranks) != hipSuccess) {
-      (void)hipGetLastError();
-      throw SgttError(-1, "d_ranks is not memory allocated through HIP");
-    }
-    const bool dev = a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
-    const bool pinned = a.type == hipMemoryTypeHost && a.devicePointer;
-    if (!dev && !pinned) throw SgttError(-1, "d_ranks is not accessible from the device");
-  }
+  if (t.core1) check_device_ptr(t.core1, "core 1");
+  if (t.core2) check_device_ptr(t.core2, "core 2");
+  if (t.core3) check_device_ptr(t.core3, "core 3");
+  if (t.d_ranks) check_device_ptr(t.d_ranks, "d_ranks");
 }
 
 // live ranks of an output TT: host fields, and the caller's device copy

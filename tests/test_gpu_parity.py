@@ -141,6 +141,15 @@ def test_device_ranks_follow_every_output(sg, ctx, tiny):
         ctx.check(sg._lib.sgtt_axpby(ctx._c, 1.0, ctypes.byref(bx.struct()), 1.0, ctypes.byref(s)))
     assert ei.value.code == -1
     assert (s.u.r1, s.u.r2) == r_before and list(host_ranks) == [-1, -1]
+    # so is a core in plain host memory, as an input and as an output
+    host_core = np.zeros(by.p.n3 * by.p.cap2)
+    for which in ("x", "y"):
+        sx, sy = bx.struct(), by.struct()
+        (sx if which == "x" else sy).p.core3 = host_core.ctypes.data
+        with pytest.raises(sg.SgttError) as ei:
+            ctx.check(sg._lib.sgtt_axpby(ctx._c, 1.0, ctypes.byref(sx), 1.0, ctypes.byref(sy)))
+        assert ei.value.code == -1
+    assert not host_core.any()
 
 
 @pytest.mark.parametrize("n,ranks,eps", [((10, 6, 2992), (8, 24), 1e-3), ((10, 6, 2992), (8, 24), 1e-6),
